@@ -1,0 +1,222 @@
+/*
+ * fock.h - C ABI of libfock, the MI355X (gfx950) statevector engine for
+ * CV-ADAPT-VQE on truncated-Fock bosonic chains.
+ *
+ * Problem statement followed (arXiv 2606.05297):
+ *   - Fock basis and truncated ladder operators: Sec. II.A.
+ *   - Gates O = exp(theta A), single-parameter form: Sec. II.B, Sec. IV.B.
+ *   - Bose-Hubbard, bosonic Kitaev chain, Kitaev + Kerr Hamiltonians:
+ *     Sec. III, Eqs. (BoseHubbard), (BosonicKitaevChain), (BosonicKitaevChain_Kerr).
+ *   - Energy E = <psi|H|psi>, pool gradient g = <psi|[H,A]|psi>: Sec. IV.B, Eq. (grad).
+ *   - ADAPT loop (score, select, append, re-optimise with BFGS): Sec. IV.B, Sec. V.A.
+ *
+ * Conventions shared by every entry point
+ *   - State: complex64 (interleaved float re, im), d^L amplitudes, basis state
+ *     |n_0 .. n_{L-1}> at flat index sum_r n_r d^r (mode 0 has stride 1).
+ *     State pointers are DEVICE pointers, at least 16-byte aligned.
+ *   - Limits: 2 <= d <= 16, 1 <= L <= 24, d^L <= 2^31.
+ *   - Host scalars are double.  Reductions (energies, norms, gradients) are
+ *     accumulated in double in a fixed order, so repeated calls on the same
+ *     inputs return bit-identical results.
+ *   - Ownership: the caller owns every buffer it passes (inputs, outputs,
+ *     workspace) and the stream.  Entry points other than adapt_* never
+ *     allocate device memory; the library keeps only small internal pinned
+ *     staging buffers and per-(type, d) gate eigendata.
+ *   - Streams: work is enqueued on `stream` (a hipStream_t; NULL means the
+ *     null stream).  Calls that return host scalars synchronise that stream
+ *     before returning.
+ *   - Errors: every function returns FOCK_OK (0) or a negative FOCK_ERR_*
+ *     code; arguments are validated before any device work is enqueued, and
+ *     fock_last_error() describes the most recent failure on the calling
+ *     thread.  No C++ exception crosses the ABI.
+ */
+#ifndef FOCK_H
+#define FOCK_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef void *fock_stream_t; /* hipStream_t */
+
+enum {
+  FOCK_OK = 0,
+  FOCK_ERR_ARG = -1,         /* invalid argument (null pointer, bad mode, ...) */
+  FOCK_ERR_SIZE = -2,        /* d^L too large or workspace too small */
+  FOCK_ERR_UNSUPPORTED = -3, /* d or L outside the supported range */
+  FOCK_ERR_NONFINITE = -4,   /* NaN/Inf angle or energy */
+  FOCK_ERR_HIP = -5,         /* HIP runtime error */
+  FOCK_ERR_LINESEARCH = -6,  /* BFGS line search failed (last good point kept) */
+  FOCK_ERR_STATE = -7        /* call not valid in the object's current state */
+};
+
+/* Lattice Hamiltonian (Sec. III, build sign convention):
+ *   H = sum_bonds [ -J (a_i^+ a_j + a_j^+ a_i) + Delta (a_i a_j + a_i^+ a_j^+) ]
+ *     + sum_r [ (U/2 + K) n_r (n_r - 1) - mu n_r ]
+ * Bonds: (r, r+1) for r = 0..L-2, plus (0, L-1) when periodic and L >= 3.
+ * Bose-Hubbard: Delta = K = 0.  Kitaev + Kerr: U = 0. */
+typedef struct {
+  int32_t L, d, periodic, reserved;
+  double J, U, mu, Delta, K;
+} fock_ham_t;
+
+/* Anti-Hermitian generators A (gate = exp(theta A)), Sec. II.B and Table I:
+ *   FOCK_HR   a_i^+ a_j - a_j^+ a_i              (beam splitter, phi = pi)
+ *   FOCK_HI   i (a_i^+ a_j + a_j^+ a_i)          (beam splitter, phi = pi/2)
+ *   FOCK_DH   i (N_i a_i^+ a_j + a_j^+ a_i N_i)  (density-assisted hop)
+ *   FOCK_PR   a_i a_j - a_i^+ a_j^+              (two-mode squeezer, phi = 0)
+ *   FOCK_PI   i (a_i a_j + a_i^+ a_j^+)          (two-mode squeezer, phi = pi/2)
+ *   FOCK_KERR i N_i^2   (single mode, j = -1)    (Kerr gate)
+ *   FOCK_ROT  i N_i     (single mode, j = -1)    (phase rotation)
+ * Two-mode ops need 0 <= i < j < L. */
+enum { FOCK_HR = 0, FOCK_HI = 1, FOCK_DH = 2, FOCK_PR = 3, FOCK_PI = 4, FOCK_KERR = 5, FOCK_ROT = 6 };
+
+typedef struct {
+  int32_t type, i, j;
+} fock_op_t;
+
+/* Message for the last failure on this thread ("" if none). */
+const char *fock_last_error(void);
+
+/* ABI version (incremented on incompatible changes). */
+int fock_version(void);
+
+/* Workspace bytes large enough for every low-level call below on this
+ * Hamiltonian's state size with a pool of n_pool ops and circuits of up to
+ * n_ops gates.  Returns FOCK_ERR_UNSUPPORTED / FOCK_ERR_SIZE for bad sizes. */
+int fock_workspace_bytes(const fock_ham_t *ham, int n_pool, int n_ops, size_t *bytes);
+
+/* hpsi = H psi (Sec. III).  If E / norm2 are non-NULL they receive
+ * <psi|H|psi> and <psi|psi> (double; the stream is synchronised).
+ * psi and hpsi: device, d^L complex64 each, must not overlap.
+ * ws: device workspace of ws_bytes (see fock_workspace_bytes). */
+int fock_apply_H(const fock_ham_t *ham, const void *psi, void *hpsi, double *E, double *norm2,
+                 void *ws, size_t ws_bytes, fock_stream_t stream);
+
+/* psi <- exp(theta A_op) psi in place (or its adjoint exp(-theta A_op) when
+ * adjoint != 0), Sec. II.B.  The gate is exp of the truncated generator, hence
+ * exactly unitary; its conserved blocks (n_i + n_j for HR/HI/DH, n_i - n_j for
+ * PR/PI, single levels for KERR/ROT) keep boson number or parity leakage at 0. */
+int fock_apply_gate2(int L, int d, fock_op_t op, double theta, int adjoint, void *psi,
+                     void *ws, size_t ws_bytes, fock_stream_t stream);
+
+/* Pool scoring, Eq. (grad): grads[k] = 2 Re <hpsi| A_k psi> = <psi|[H, A_k]|psi>
+ * for k < P, where hpsi = H psi (from fock_apply_H).  grads: host array of P
+ * doubles (stream synchronised).  P <= 4096. */
+int fock_pool_grads(const fock_ham_t *ham, const fock_op_t *pool, int P, const void *psi,
+                    const void *hpsi, double *grads, void *ws, size_t ws_bytes, fock_stream_t stream);
+
+/* Energy of the ansatz psi = O_n(theta_n) ... O_1(theta_1) psi0 (newest gate
+ * acts last, Sec. IV.B) and, when dEdtheta is non-NULL, all dE/dtheta_k by one
+ * reverse sweep: dE/dtheta_k = 2 Re <lambda_k| A_k phi_k> / <psi|psi> with
+ * phi_k = O_k..O_1 psi0 and lambda_k = O_{k+1}^+ .. O_n^+ H psi.
+ * E receives the Rayleigh quotient <psi|H|psi>/<psi|psi>; norm2 (nullable)
+ * receives <psi|psi>.  psi0: device input (unchanged).  psi_work, lam_work:
+ * device d^L complex64 scratch; on return without gradient they hold psi and
+ * H psi.  ops/theta: host arrays of n entries (n <= 4096). */
+int fock_energy_grad_adjoint(const fock_ham_t *ham, const fock_op_t *ops, const double *theta, int n,
+                             const void *psi0, void *psi_work, void *lam_work, double *E,
+                             double *norm2, double *dEdtheta, void *ws, size_t ws_bytes,
+                             fock_stream_t stream);
+
+/* ------------------------------------------------------------------ ADAPT */
+
+typedef struct {
+  int32_t max_iters;      /* iteration cap (ADAPT steps) */
+  int32_t bfgs_maxiter;   /* BFGS iteration cap per step (1000 in Sec. V.A) */
+  double grad_tol;        /* stop when ||g||_2 over the pool < grad_tol */
+  double tie_tau;         /* candidates |g_k| >= (1 - tie_tau) max|g|; lowest index wins */
+  double gtol_floor_rel;  /* BFGS L-inf tolerance max(min(1e-6, 1e-5|g_sel|), floor*max(1,|E|)) */
+  double warm_gtol;       /* BFGS tolerance for the warm-up layer alone */
+  int32_t n_warm;         /* warm-up layer length (0 = none) */
+  int32_t grad_mode;      /* 0 = adjoint sweep, 1 = central finite differences (plain) */
+  const fock_op_t *warm_ops;    /* host, n_warm entries, copied at create */
+  const double *warm_theta0;    /* host, n_warm initial angles, copied at create */
+  double fd_step;         /* finite-difference step for grad_mode 1 */
+  int32_t recycle_hessian;/* 1: seed each BFGS with the previous inverse Hessian (Appendix D) */
+  int32_t reserved;
+} fock_adapt_opts_t;
+
+typedef struct {
+  int32_t iter;        /* ADAPT step index (0 = warm-up layer) */
+  int32_t k_sel;       /* selected pool index, -1 if none */
+  int32_t converged;   /* 1 when ||g||_2 < grad_tol (no op appended) */
+  int32_t status;      /* FOCK_OK or FOCK_ERR_LINESEARCH */
+  int32_t bfgs_iters, bfgs_evals, n_params, capped;
+  double g_sel;        /* |g_k*| at selection */
+  double g_norm2, g_inf;
+  double E;            /* energy after re-optimisation (Rayleigh quotient) */
+  double norm2;        /* <psi|psi> at that point */
+  double E_init;       /* energy at the start of BFGS */
+} fock_adapt_report_t;
+
+typedef struct fock_adapt fock_adapt_t;
+
+/* Default options: max_iters 60, bfgs_maxiter 1000, grad_tol 1e-3,
+ * tie_tau 1e-4, gtol_floor_rel 1e-5, warm_gtol 1e-6, fd_step 1e-3. */
+void adapt_default_opts(fock_adapt_opts_t *opts);
+
+/* Create an ADAPT run on `ham` with `pool` (P ops, host, copied) from the
+ * device state psi0 (copied).  The object owns its device buffers (three
+ * states plus workspace) and uses `stream`.  With a warm-up layer, its angles
+ * are BFGS-optimised here (report via adapt_warm_report). */
+int adapt_create(const fock_ham_t *ham, const fock_op_t *pool, int P, const void *psi0,
+                 const fock_adapt_opts_t *opts, fock_stream_t stream, fock_adapt_t **out);
+
+/* One ADAPT iteration (Sec. IV.B): score the pool on the current state,
+ * test convergence, select (tie band, lowest index), append exp(theta A_k)
+ * with theta = 0 (or the pending proposal, see adapt_propose), re-optimise all
+ * angles by BFGS.  Returns FOCK_ERR_STATE once the run has converged/capped. */
+int adapt_step(fock_adapt_t *st, fock_adapt_report_t *rep);
+
+/* Report of the warm-up optimisation done in adapt_create. */
+int adapt_warm_report(fock_adapt_t *st, fock_adapt_report_t *rep);
+
+/* Current ansatz: ops and angles (warm-up layer first).  cap = array size;
+ * *n receives the full length. */
+int adapt_get_ansatz(fock_adapt_t *st, fock_op_t *ops, double *theta, int cap, int *n);
+
+/* Proposal for the angles used as the BFGS start of the next step (full
+ * vector of length current n_params + 1).  It is used only if its energy is
+ * not above the plain start {theta_prev, 0}; otherwise the plain start is
+ * kept.  *accepted (after the step) via adapt_last_proposal. */
+int adapt_propose(fock_adapt_t *st, const double *theta, int n);
+int adapt_last_proposal(fock_adapt_t *st, int *accepted, double *E_prop, double *E_plain);
+
+int adapt_destroy(fock_adapt_t *st);
+
+/* ------------------------------------------------------------------ BFGS */
+
+/* Objective for fock_bfgs_minimize: f(x) and its gradient g (both host);
+ * return 0, or a negative code to abort the minimisation. */
+typedef int (*fock_objective_fn)(void *ctx, int n, const double *x, double *f, double *g);
+
+/* BFGS with a strong-Wolfe line search (the minimiser used by adapt_step,
+ * Sec. V.A): stops when ||g||_inf < gtol or after maxiter iterations.  x
+ * (host, n) is the start on entry and the result on return.  Hinv (nullable,
+ * host n x n row-major) seeds the inverse Hessian when non-zero and receives
+ * the final one.  *status = FOCK_OK or FOCK_ERR_LINESEARCH (last accepted point
+ * kept). */
+int fock_bfgs_minimize(int n, double *x, fock_objective_fn fn, void *ctx, double gtol, int maxiter, double *Hinv,
+                       int *iters, int *evals, double *fmin, int *status);
+
+/* ------------------------------------------------------------------ profiling */
+
+/* Kernel ids for per-kernel timing by HIP events recorded on the launch stream. */
+enum { FOCK_K_APPLY_H = 0, FOCK_K_POOL = 1, FOCK_K_GATE = 2, FOCK_K_ADJ = 3, FOCK_K_DIAG = 4,
+       FOCK_K_REDUCE = 5, FOCK_K_NUM = 8 };
+
+/* Enable/disable event timing of every launch (off by default). */
+int fock_prof_enable(int on);
+/* Launch count, summed duration (ms) and summed algorithmic bytes of kernel id
+ * since the last reset (completed launches only; call after a synchronise). */
+int fock_prof_query(int kernel_id, int64_t *launches, double *total_ms, double *bytes);
+int fock_prof_reset(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FOCK_H */

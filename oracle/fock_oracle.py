@@ -562,3 +562,52 @@ def adapt(ham: Ham, psi0, pool, max_iters: int, grad_tol: float = 1e-3, warm_ops
         if callback:
             callback(rec)
     return records
+
+
+# --------------------------------------------------------------------------
+# Single matrix rows (sampled checks on states too large for the full oracle)
+# --------------------------------------------------------------------------
+
+
+def ham_column(ham: Ham, occ: Sequence[int]) -> dict:
+    """H |occ> as {flat index: coefficient}, term by term from the ladder
+    matrices acting on the occupied levels.  H is real symmetric, so this is
+    also row `occ` of H: (H psi)[occ] = sum_k coef_k psi[k]."""
+    L, d = ham.L, ham.d
+    a = ladder(d)
+    ad = a.T
+    out: dict = {}
+
+    def add(new_occ, c):
+        if c == 0.0:
+            return
+        idx = sum(int(n) * d**r for r, n in enumerate(new_occ))
+        out[idx] = out.get(idx, 0.0) + c
+
+    occ = list(occ)
+    for (i, j) in bonds(L, ham.periodic):
+        for (mi, mj, c) in ((ad, a, -ham.J), (a, ad, -ham.J), (a, a, ham.Delta), (ad, ad, ham.Delta)):
+            if c == 0.0:
+                continue
+            # single-mode matrices map |n> to column n: entries mi[:, n_i]
+            for ni2 in range(d):
+                vi = mi[ni2, occ[i]]
+                if vi == 0.0:
+                    continue
+                for nj2 in range(d):
+                    vj = mj[nj2, occ[j]]
+                    if vj == 0.0:
+                        continue
+                    new = list(occ)
+                    new[i], new[j] = ni2, nj2
+                    add(new, c * vi * vj)
+    dg = onsite(ham)
+    add(occ, float(sum(dg[n, n] for n in occ)))
+    return out
+
+
+def apply_H_at(ham: Ham, psi: np.ndarray, flat_index: int) -> complex:
+    """(H psi)[flat_index] from one row of H."""
+    L, d = ham.L, ham.d
+    occ = [(flat_index // d**r) % d for r in range(L)]
+    return complex(sum(c * psi[k] for k, c in ham_column(ham, occ).items()))

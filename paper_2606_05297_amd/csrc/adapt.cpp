@@ -1,0 +1,349 @@
+// CV-ADAPT-VQE driver (Sec. IV.B, Sec. V.A) on top of the device pipeline:
+// score the pool on the current state, test ||g||_2, select the largest
+// |g_k| (lowest index inside a relative tie band), append exp(theta A_k) with
+// theta = 0, and re-optimise all angles with BFGS (adjoint or finite-difference
+// gradients).  An optional warm-up layer is optimised first and re-optimised
+// with every later BFGS (Sec. IV.B, Appendix C).
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "bfgs.h"
+#include "pipeline.h"
+
+using namespace fock;
+
+struct fock_adapt {
+  fock_ham_t ham;
+  uint32_t namp = 0;
+  hipStream_t s = nullptr;
+  fock_adapt_opts_t opt;
+  std::vector<fock_op_t> pool;
+  std::vector<fock_op_t> ops;
+  std::vector<double> theta;
+  std::vector<double> Hinv;
+  void *dbuf = nullptr;
+  float2 *psi0 = nullptr, *phi = nullptr, *lam = nullptr;
+  char *ws = nullptr;
+  size_t ws_bytes = 0;
+  Ctx ctx;
+  int iter = 0;
+  bool done = false;
+  fock_adapt_report_t warm{};
+  std::vector<double> proposal;
+  bool has_prop = false;
+  int prop_acc = 0;
+  double prop_E = 0.0, plain_E = 0.0;
+};
+
+namespace {
+
+int eval_energy(fock_adapt *st, const std::vector<double> &th, double *E, double *n2, std::vector<double> *g) {
+  const int n = (int)st->ops.size();
+  if (!g) return run_circuit(st->ctx, st->ops.data(), th.data(), n, st->psi0, st->phi, st->lam, false, E, n2, nullptr);
+  g->assign(n, 0.0);
+  if (st->opt.grad_mode == 0)
+    return run_circuit(st->ctx, st->ops.data(), th.data(), n, st->psi0, st->phi, st->lam, true, E, n2, g->data());
+  // plain method: central finite differences, 2n extra energy evaluations
+  int rc = run_circuit(st->ctx, st->ops.data(), th.data(), n, st->psi0, st->phi, st->lam, false, E, n2, nullptr);
+  if (rc) return rc;
+  const double h = st->opt.fd_step;
+  std::vector<double> t = th;
+  for (int k = 0; k < n; ++k) {
+    double ep = 0, em = 0;
+    t[k] = th[k] + h;
+    rc = run_circuit(st->ctx, st->ops.data(), t.data(), n, st->psi0, st->phi, st->lam, false, &ep, nullptr, nullptr);
+    if (rc) return rc;
+    t[k] = th[k] - h;
+    rc = run_circuit(st->ctx, st->ops.data(), t.data(), n, st->psi0, st->phi, st->lam, false, &em, nullptr, nullptr);
+    if (rc) return rc;
+    t[k] = th[k];
+    (*g)[k] = (ep - em) / (2.0 * h);
+  }
+  return FOCK_OK;
+}
+
+int optimise(fock_adapt *st, double gtol, fock_adapt_report_t *rep) {
+  ObjFn fn = [st](const std::vector<double> &x, double *f, std::vector<double> *g) {
+    return eval_energy(st, x, f, nullptr, g);
+  };
+  const int n = (int)st->theta.size();
+  std::vector<double> *H = nullptr;
+  if (st->opt.recycle_hessian) {
+    // previous inverse Hessian padded with identity for the new angle (Appendix D)
+    const int m = (int)std::lround(std::sqrt((double)st->Hinv.size()));
+    if (m > 0 && m < n) {
+      std::vector<double> Hn((size_t)n * n, 0.0);
+      for (int r = 0; r < n; ++r) Hn[(size_t)r * n + r] = 1.0;
+      for (int r = 0; r < m; ++r)
+        for (int c = 0; c < m; ++c) Hn[(size_t)r * n + c] = st->Hinv[(size_t)r * m + c];
+      st->Hinv.swap(Hn);
+    } else if (m != n) {
+      st->Hinv.clear();
+    }
+    H = &st->Hinv;
+  }
+  BfgsOut bo;
+  int rc = bfgs_minimize(st->theta, fn, gtol, st->opt.bfgs_maxiter, H, &bo);
+  if (rc) return rc;
+  double E = 0.0, n2 = 0.0;
+  rc = eval_energy(st, st->theta, &E, &n2, nullptr);
+  if (rc) return rc;
+  rep->bfgs_iters = bo.iters;
+  rep->bfgs_evals = bo.evals + 1;
+  rep->status = bo.status;
+  rep->E = E;
+  rep->norm2 = n2;
+  rep->E_init = bo.f0;
+  rep->n_params = n;
+  return FOCK_OK;
+}
+
+double gtol_for(const fock_adapt *st, double gsel, double E) {
+  const double paper = std::min(1e-6, 1e-5 * gsel);
+  return std::max(paper, st->opt.gtol_floor_rel * std::max(1.0, std::fabs(E)));
+}
+
+}  // namespace
+
+extern "C" {
+
+void adapt_default_opts(fock_adapt_opts_t *o) {
+  if (!o) return;
+  memset(o, 0, sizeof(*o));
+  o->max_iters = 60;
+  o->bfgs_maxiter = 1000;
+  o->grad_tol = 1e-3;
+  o->tie_tau = 1e-4;
+  o->gtol_floor_rel = 1e-5;
+  o->warm_gtol = 1e-6;
+  o->fd_step = 1e-3;
+}
+
+int adapt_create(const fock_ham_t *ham, const fock_op_t *pool, int P, const void *psi0, const fock_adapt_opts_t *opts,
+                 fock_stream_t stream, fock_adapt_t **out) {
+  if (!out) return set_error(FOCK_ERR_ARG, "out is NULL");
+  *out = nullptr;
+  uint32_t namp = 0;
+  int rc = check_ham(ham, &namp);
+  if (rc) return rc;
+  if (!opts) return set_error(FOCK_ERR_ARG, "opts is NULL");
+  if (P < 1 || P > 4096 || !pool) return set_error(FOCK_ERR_ARG, "pool must hold 1..4096 ops");
+  if ((rc = check_ptr(psi0, "psi0"))) return rc;
+  for (int k = 0; k < P; ++k)
+    if ((rc = check_op(pool[k], ham->L))) return rc;
+  if (opts->n_warm < 0 || (opts->n_warm > 0 && (!opts->warm_ops || !opts->warm_theta0)))
+    return set_error(FOCK_ERR_ARG, "warm-up layer arrays missing");
+  for (int k = 0; k < opts->n_warm; ++k)
+    if ((rc = check_op(opts->warm_ops[k], ham->L))) return rc;
+  if (opts->max_iters < 0 || opts->bfgs_maxiter < 0 || !(opts->grad_tol >= 0.0))
+    return set_error(FOCK_ERR_ARG, "invalid iteration caps or tolerance");
+  if (opts->grad_mode == 1 && !(opts->fd_step > 0.0)) return set_error(FOCK_ERR_ARG, "fd_step must be > 0");
+
+  fock_adapt *st = new fock_adapt();
+  st->ham = *ham;
+  st->namp = namp;
+  st->s = (hipStream_t)stream;
+  st->opt = *opts;
+  st->opt.warm_ops = nullptr;
+  st->opt.warm_theta0 = nullptr;
+  st->pool.assign(pool, pool + P);
+  for (int k = 0; k < opts->n_warm; ++k) {
+    st->ops.push_back(opts->warm_ops[k]);
+    st->theta.push_back(opts->warm_theta0[k]);
+  }
+  const int nmax = opts->n_warm + opts->max_iters + 1;
+  const Layout L = make_layout(namp, ham->d, P, nmax);
+  const size_t sbytes = (sizeof(float2) * (size_t)namp + 255) & ~(size_t)255;
+  st->ws_bytes = L.total;
+  if (hipMalloc(&st->dbuf, 3 * sbytes + st->ws_bytes) != hipSuccess) {
+    delete st;
+    return set_error(FOCK_ERR_HIP, "hipMalloc of %zu bytes failed", 3 * sbytes + L.total);
+  }
+  char *b = (char *)st->dbuf;
+  st->psi0 = (float2 *)b;
+  st->phi = (float2 *)(b + sbytes);
+  st->lam = (float2 *)(b + 2 * sbytes);
+  st->ws = b + 3 * sbytes;
+  rc = make_ctx(*ham, namp, P, nmax, st->ws, st->ws_bytes, st->s, &st->ctx);
+  if (!rc && hipMemcpyAsync(st->psi0, psi0, sizeof(float2) * namp, hipMemcpyDeviceToDevice, st->s) != hipSuccess)
+    rc = set_error(FOCK_ERR_HIP, "copy of psi0 failed");
+  if (!rc) {
+    st->warm.iter = 0;
+    st->warm.k_sel = -1;
+    if (opts->n_warm > 0) {
+      double E0 = 0.0;
+      rc = eval_energy(st, st->theta, &E0, nullptr, nullptr);
+      if (!rc) rc = optimise(st, std::max(opts->warm_gtol, gtol_for(st, 0.0, E0)), &st->warm);
+    } else {
+      double E0 = 0.0, n2 = 0.0;
+      rc = eval_energy(st, st->theta, &E0, &n2, nullptr);
+      st->warm.E = E0;
+      st->warm.E_init = E0;
+      st->warm.norm2 = n2;
+    }
+  }
+  if (rc) {
+    (void)hipStreamSynchronize(st->s);
+    (void)hipFree(st->dbuf);
+    delete st;
+    return rc;
+  }
+  st->Hinv.clear();
+  *out = st;
+  return FOCK_OK;
+}
+
+int adapt_warm_report(fock_adapt_t *st, fock_adapt_report_t *rep) {
+  if (!st || !rep) return set_error(FOCK_ERR_ARG, "NULL argument");
+  *rep = st->warm;
+  return FOCK_OK;
+}
+
+int adapt_step(fock_adapt_t *st, fock_adapt_report_t *rep) {
+  if (!st || !rep) return set_error(FOCK_ERR_ARG, "NULL argument");
+  if (st->done) return set_error(FOCK_ERR_STATE, "ADAPT run already finished");
+  memset(rep, 0, sizeof(*rep));
+  st->iter += 1;
+  rep->iter = st->iter;
+  rep->k_sel = -1;
+  // 1. state and energy at the current optimum
+  double E = 0.0, n2 = 0.0;
+  int rc = eval_energy(st, st->theta, &E, &n2, nullptr);
+  if (rc) return rc;
+  // 2. pool scoring on (phi = psi, lam = H psi)
+  const int P = (int)st->pool.size();
+  std::vector<double> g(P);
+  rc = pool_dev(st->ctx, st->pool.data(), P, st->phi, st->lam, (double *)(st->ctx.ws + st->ctx.L.result));
+  if (rc) return rc;
+  rc = fetch_results(st->ctx, P, g.data());
+  if (rc) return rc;
+  double gn2 = 0.0, ginf = 0.0;
+  for (auto &v : g) {
+    v /= n2;
+    gn2 += v * v;
+    ginf = std::max(ginf, std::fabs(v));
+  }
+  gn2 = std::sqrt(gn2);
+  rep->g_norm2 = gn2;
+  rep->g_inf = ginf;
+  rep->E = E;
+  rep->E_init = E;
+  rep->norm2 = n2;
+  rep->n_params = (int)st->theta.size();
+  if (gn2 < st->opt.grad_tol) {
+    rep->converged = 1;
+    st->done = true;
+    return FOCK_OK;
+  }
+  if (st->iter > st->opt.max_iters) {
+    rep->capped = 1;
+    st->done = true;
+    return FOCK_OK;
+  }
+  // 3. selection: lowest index inside the relative tie band
+  int ks = 0;
+  for (int k = 0; k < P; ++k)
+    if (std::fabs(g[k]) >= (1.0 - st->opt.tie_tau) * ginf) {
+      ks = k;
+      break;
+    }
+  rep->k_sel = ks;
+  rep->g_sel = std::fabs(g[ks]);
+  // 4. append with theta = 0, or a proposal whose energy is not worse
+  st->ops.push_back(st->pool[ks]);
+  st->theta.push_back(0.0);
+  st->prop_acc = 0;
+  st->plain_E = E;
+  if (st->has_prop) {
+    st->has_prop = false;
+    if (st->proposal.size() == st->theta.size()) {
+      double Ep = 0.0;
+      rc = eval_energy(st, st->proposal, &Ep, nullptr, nullptr);
+      if (rc) return rc;
+      st->prop_E = Ep;
+      if (Ep <= E) {
+        st->theta = st->proposal;
+        st->prop_acc = 1;
+      }
+    }
+  }
+  // 5. re-optimise all angles
+  rc = optimise(st, gtol_for(st, rep->g_sel, E), rep);
+  if (rc) return rc;
+  rep->iter = st->iter;
+  rep->k_sel = ks;
+  rep->g_norm2 = gn2;
+  rep->g_inf = ginf;
+  return FOCK_OK;
+}
+
+int adapt_get_ansatz(fock_adapt_t *st, fock_op_t *ops, double *theta, int cap, int *n) {
+  if (!st || !n) return set_error(FOCK_ERR_ARG, "NULL argument");
+  *n = (int)st->ops.size();
+  const int m = std::min(cap, *n);
+  for (int k = 0; k < m; ++k) {
+    if (ops) ops[k] = st->ops[k];
+    if (theta) theta[k] = st->theta[k];
+  }
+  return FOCK_OK;
+}
+
+int adapt_propose(fock_adapt_t *st, const double *theta, int n) {
+  if (!st || (!theta && n > 0)) return set_error(FOCK_ERR_ARG, "NULL argument");
+  if (n != (int)st->theta.size() + 1)
+    return set_error(FOCK_ERR_ARG, "proposal length %d != current parameters + 1 (%d)", n, (int)st->theta.size() + 1);
+  for (int k = 0; k < n; ++k)
+    if (!std::isfinite(theta[k])) return set_error(FOCK_ERR_NONFINITE, "proposal[%d] not finite", k);
+  st->proposal.assign(theta, theta + n);
+  st->has_prop = true;
+  return FOCK_OK;
+}
+
+int adapt_last_proposal(fock_adapt_t *st, int *accepted, double *E_prop, double *E_plain) {
+  if (!st) return set_error(FOCK_ERR_ARG, "NULL argument");
+  if (accepted) *accepted = st->prop_acc;
+  if (E_prop) *E_prop = st->prop_E;
+  if (E_plain) *E_plain = st->plain_E;
+  return FOCK_OK;
+}
+
+int adapt_destroy(fock_adapt_t *st) {
+  if (!st) return FOCK_OK;
+  (void)hipStreamSynchronize(st->s);
+  if (st->dbuf) (void)hipFree(st->dbuf);
+  delete st;
+  return FOCK_OK;
+}
+
+// Generic BFGS on a host objective (same minimiser the ADAPT driver uses).
+int fock_bfgs_minimize(int n, double *x, fock_objective_fn fn, void *ctx, double gtol, int maxiter, double *Hinv,
+                       int *iters, int *evals, double *fmin, int *status) {
+  if (n < 1 || !x || !fn) return set_error(FOCK_ERR_ARG, "invalid BFGS arguments");
+  std::vector<double> xv(x, x + n);
+  ObjFn f = [fn, ctx](const std::vector<double> &xx, double *fx, std::vector<double> *gx) {
+    gx->resize(xx.size());
+    const int r = fn(ctx, (int)xx.size(), xx.data(), fx, gx->data());
+    if (r) return set_error(r, "objective returned %d", r);
+    return 0;
+  };
+  std::vector<double> H;
+  if (Hinv) H.assign(Hinv, Hinv + (size_t)n * n);
+  // an all-zero matrix means "no seed"
+  bool seeded = false;
+  for (double v : H) seeded |= v != 0.0;
+  if (!seeded) H.clear();
+  BfgsOut o;
+  int rc = bfgs_minimize(xv, f, gtol, maxiter, Hinv ? &H : nullptr, &o);
+  if (rc) return rc;
+  std::copy(xv.begin(), xv.end(), x);
+  if (Hinv) std::copy(H.begin(), H.end(), Hinv);
+  if (iters) *iters = o.iters;
+  if (evals) *evals = o.evals;
+  if (fmin) *fmin = o.f;
+  if (status) *status = o.status;
+  return FOCK_OK;
+}
+
+}  // extern "C"

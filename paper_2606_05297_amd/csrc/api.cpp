@@ -1,0 +1,428 @@
+// C ABI of libfock: argument validation, workspace layout, the energy /
+// adjoint-gradient pipeline, pool scoring, and the ADAPT state machine.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <vector>
+
+#include "bfgs.h"
+#include "pipeline.h"
+
+namespace fock {
+
+// ---------------------------------------------------------------- validation
+int check_geometry(int L, int d, uint32_t *namp) {
+  if (L < 1 || L > kMaxL) return set_error(FOCK_ERR_UNSUPPORTED, "L=%d outside [1, %d]", L, kMaxL);
+  if (d < 2 || d > kMaxD) return set_error(FOCK_ERR_UNSUPPORTED, "d=%d outside [2, %d]", d, kMaxD);
+  uint64_t n = 1;
+  for (int r = 0; r < L; ++r) {
+    n *= (uint64_t)d;
+    if (n > (1ull << 31)) return set_error(FOCK_ERR_SIZE, "d^L = %d^%d exceeds 2^31 amplitudes", d, L);
+  }
+  *namp = (uint32_t)n;
+  return FOCK_OK;
+}
+
+int check_ham(const fock_ham_t *h, uint32_t *namp) {
+  if (!h) return set_error(FOCK_ERR_ARG, "ham is NULL");
+  int rc = check_geometry(h->L, h->d, namp);
+  if (rc) return rc;
+  const double v[5] = {h->J, h->U, h->mu, h->Delta, h->K};
+  for (double x : v)
+    if (!std::isfinite(x)) return set_error(FOCK_ERR_NONFINITE, "non-finite Hamiltonian parameter");
+  return FOCK_OK;
+}
+
+int check_op(const fock_op_t &op, int L) {
+  if (op.type < FOCK_HR || op.type > FOCK_ROT) return set_error(FOCK_ERR_ARG, "unknown op type %d", op.type);
+  if (is_single_mode(op.type)) {
+    if (op.i < 0 || op.i >= L) return set_error(FOCK_ERR_ARG, "mode %d out of range for L=%d", op.i, L);
+    return FOCK_OK;
+  }
+  if (op.i < 0 || op.j < 0 || op.i >= L || op.j >= L)
+    return set_error(FOCK_ERR_ARG, "mode pair (%d,%d) out of range for L=%d", op.i, op.j, L);
+  if (op.i >= op.j) return set_error(FOCK_ERR_ARG, "mode pair (%d,%d) needs i < j", op.i, op.j);
+  return FOCK_OK;
+}
+
+int check_ptr(const void *p, const char *name) {
+  if (!p) return set_error(FOCK_ERR_ARG, "%s is NULL", name);
+  if (((uintptr_t)p) & 15) return set_error(FOCK_ERR_ARG, "%s is not 16-byte aligned", name);
+  return FOCK_OK;
+}
+
+HamArgs make_ham_args(const fock_ham_t &h) {
+  HamArgs a;
+  memset(&a, 0, sizeof(a));
+  a.L = h.L;
+  a.d = h.d;
+  int nr = 1;
+  for (int r = 1; r < h.L; ++r) nr *= h.d;
+  a.nrows = nr;
+  a.periodic_wrap = (h.periodic && h.L >= 3) ? 1 : 0;
+  a.J = (float)h.J;
+  a.Delta = (float)h.Delta;
+  a.c2 = (float)(0.5 * h.U + h.K);
+  a.mu = (float)h.mu;
+  int s = 1;
+  for (int r = 1; r < h.L; ++r) {
+    a.srow[r] = s;
+    s *= h.d;
+  }
+  for (int k = 0; k <= kMaxD; ++k) a.sq[k] = (float)std::sqrt((double)k);
+  return a;
+}
+
+// ---------------------------------------------------------------- pinned staging
+struct Pinned {
+  void *p = nullptr;
+  size_t cap = 0;
+  hipEvent_t ev = nullptr;
+  bool pending = false;
+  int reserve(size_t bytes) {
+    if (pending) {
+      FOCK_HIP(hipEventSynchronize(ev));
+      pending = false;
+    }
+    if (!ev) FOCK_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+    if (bytes > cap) {
+      if (p) FOCK_HIP(hipHostFree(p));
+      p = nullptr;
+      size_t c = std::max<size_t>(bytes, 1 << 16);
+      FOCK_HIP(hipHostMalloc(&p, c, hipHostMallocDefault));
+      cap = c;
+    }
+    return FOCK_OK;
+  }
+  int mark(hipStream_t s) {
+    FOCK_HIP(hipEventRecord(ev, s));
+    pending = true;
+    return FOCK_OK;
+  }
+};
+static thread_local Pinned tl_in, tl_out;
+
+// ---------------------------------------------------------------- workspace layout
+static size_t al(size_t x) { return (x + 255) & ~(size_t)255; }
+
+Layout make_layout(uint32_t namp, int d, int P, int n) {
+  Layout L;
+  const uint32_t nrows = namp / (uint32_t)d;
+  L.G = (int)((nrows + kBlock - 1) / kBlock);
+  L.nmax = std::max(n, 1);
+  L.pmax = std::min(std::max(P, 1), kMaxSlots);
+  size_t o = 0;
+  L.theta = o;
+  o = al(o + sizeof(double) * L.nmax);
+  L.recs = o;
+  o = al(o + sizeof(GateRec) * L.nmax);
+  L.utab = o;
+  o = al(o + sizeof(float2) * (size_t)gate_stride(d) * L.nmax);
+  L.partial = o;
+  const size_t rows = std::max<size_t>({2, (size_t)L.nmax, (size_t)L.pmax});
+  o = al(o + sizeof(double) * rows * L.G);
+  L.result = o;
+  o = al(o + sizeof(double) * (2 + std::max(L.nmax, std::max(P, 1))));
+  L.pairs = o;
+  o = al(o + sizeof(PoolPair) * kMaxPairs);
+  L.diags = o;
+  o = al(o + sizeof(PoolDiag) * kMaxDiagOps);
+  L.total = o;
+  return L;
+}
+
+// ---------------------------------------------------------------- shared pipeline
+int make_ctx(const fock_ham_t &ham, uint32_t namp, int P, int n, void *ws, size_t ws_bytes, hipStream_t s,
+                    Ctx *c) {
+  c->g = {ham.L, ham.d, namp};
+  c->h = make_ham_args(ham);
+  c->s = s;
+  c->ws = (char *)ws;
+  c->L = make_layout(namp, ham.d, P, n);
+  if (!ws) return set_error(FOCK_ERR_ARG, "workspace is NULL");
+  if (((uintptr_t)ws) & 255) return set_error(FOCK_ERR_ARG, "workspace must be 256-byte aligned");
+  if (ws_bytes < c->L.total)
+    return set_error(FOCK_ERR_SIZE, "workspace too small: %zu < %zu bytes", ws_bytes, c->L.total);
+  if (n > 0) {
+    int rc = get_tables(ham.d, &c->T);
+    if (rc) return rc;
+  }
+  return FOCK_OK;
+}
+
+int stage_gates(Ctx &c, const fock_op_t *ops, const double *theta, int n) {
+  const int stride = gate_stride(c.g.d);
+  const size_t bt = sizeof(double) * n, br = sizeof(GateRec) * n;
+  int rc = tl_in.reserve(c.L.recs + br);
+  if (rc) return rc;
+  char *hp = (char *)tl_in.p;
+  double *th = (double *)(hp + c.L.theta);
+  GateRec *rec = (GateRec *)(hp + c.L.recs);
+  const int Gd = diag_blocks_count(c.g), Gg = gate_blocks_count(c.g);
+  for (int k = 0; k < n; ++k) {
+    if (!std::isfinite(theta[k])) return set_error(FOCK_ERR_NONFINITE, "theta[%d] is not finite", k);
+    th[k] = theta[k];
+    rec[k].type = ops[k].type;
+    rec[k].u_off = k * stride;
+    rec[k].nblk = is_single_mode(ops[k].type) ? Gd : Gg;
+    rec[k].pad = 0;
+  }
+  (void)bt;
+  FOCK_HIP(hipMemcpyAsync(c.ws + c.L.theta, hp + c.L.theta, c.L.recs + br - c.L.theta, hipMemcpyHostToDevice, c.s));
+  rc = tl_in.mark(c.s);
+  if (rc) return rc;
+  return launch_gate_build((const double *)(c.ws + c.L.theta), (const GateRec *)(c.ws + c.L.recs), n, c.T,
+                           (float2 *)(c.ws + c.L.utab), c.s);
+}
+
+int forward_gate(Ctx &c, const fock_op_t &op, int k, bool dag, float2 *psi) {
+  const float2 *U = (const float2 *)(c.ws + c.L.utab) + (size_t)k * gate_stride(c.g.d);
+  ProfScope ps(is_single_mode(op.type) ? FOCK_K_DIAG : FOCK_K_GATE, c.s, 16.0 * c.g.n_amp);
+  if (is_single_mode(op.type)) return launch_diag(c.g, op.i, op.type, dag, U, psi, c.s);
+  return launch_gate(c.g, op.i, op.j, gate_kind(op.type), dag, U, psi, c.s);
+}
+
+int apply_h_dev(Ctx &c, const float2 *psi, float2 *hpsi, double *res2) {
+  int G = 0;
+  {
+    ProfScope ps(FOCK_K_APPLY_H, c.s, 16.0 * c.g.n_amp);
+    int rc = launch_apply_h(c.h, psi, hpsi, (double *)(c.ws + c.L.partial), &G, c.s);
+    if (rc) return rc;
+  }
+  return launch_reduce((const double *)(c.ws + c.L.partial), G, 2, res2, c.s);
+}
+
+int fetch_results(Ctx &c, int count, double *host) {
+  int rc = tl_out.reserve(sizeof(double) * count);
+  if (rc) return rc;
+  FOCK_HIP(hipMemcpyAsync(tl_out.p, c.ws + c.L.result, sizeof(double) * count, hipMemcpyDeviceToHost, c.s));
+  FOCK_HIP(hipStreamSynchronize(c.s));
+  prof_harvest();
+  memcpy(host, tl_out.p, sizeof(double) * count);
+  return FOCK_OK;
+}
+
+// Energy and (optionally) all dE/dtheta of a circuit; see fock_energy_grad_adjoint.
+int run_circuit(Ctx &c, const fock_op_t *ops, const double *theta, int n, const void *psi0, float2 *phi,
+                       float2 *lam, bool grad, double *E, double *norm2, double *dE) {
+  int rc = FOCK_OK;
+  if (n > 0) {
+    rc = stage_gates(c, ops, theta, n);
+    if (rc) return rc;
+  }
+  FOCK_HIP(hipMemcpyAsync(phi, psi0, sizeof(float2) * (size_t)c.g.n_amp, hipMemcpyDeviceToDevice, c.s));
+  for (int k = 0; k < n; ++k) {
+    rc = forward_gate(c, ops[k], k, false, phi);
+    if (rc) return rc;
+  }
+  double *res = (double *)(c.ws + c.L.result);
+  rc = apply_h_dev(c, phi, lam, res);
+  if (rc) return rc;
+  if (grad && n > 0) {
+    double *part = (double *)(c.ws + c.L.partial);
+    const int stride = gate_stride(c.g.d);
+    const float2 *U0 = (const float2 *)(c.ws + c.L.utab);
+    for (int k = n - 1; k >= 0; --k) {
+      const fock_op_t &op = ops[k];
+      const float2 *U = U0 + (size_t)k * stride;
+      double *pk = part + (size_t)k * c.L.G;
+      ProfScope ps(is_single_mode(op.type) ? FOCK_K_DIAG : FOCK_K_ADJ, c.s, 32.0 * c.g.n_amp);
+      if (is_single_mode(op.type)) rc = launch_diag_adj(c.g, op.i, op.type, U, phi, lam, pk, c.s);
+      else rc = launch_gate_adj(c.g, op.i, op.j, gate_kind(op.type), U, c.T.A[op.type], phi, lam, pk, c.s);
+      if (rc) return rc;
+    }
+    rc = launch_reduce_rows(part, c.L.G, (const GateRec *)(c.ws + c.L.recs), n, res + 2, c.s);
+    if (rc) return rc;
+  }
+  const int cnt = 2 + ((grad && n > 0) ? n : 0);
+  std::vector<double> host(cnt);
+  rc = fetch_results(c, cnt, host.data());
+  if (rc) return rc;
+  const double nrm = host[1];
+  if (!std::isfinite(host[0]) || !std::isfinite(nrm) || nrm <= 0.0)
+    return set_error(FOCK_ERR_NONFINITE, "non-finite energy or zero norm (E=%g, norm2=%g)", host[0], nrm);
+  *E = host[0] / nrm;
+  if (norm2) *norm2 = nrm;
+  if (grad && dE)
+    for (int k = 0; k < n; ++k) dE[k] = 2.0 * host[2 + k] / nrm;
+  return FOCK_OK;
+}
+
+// Pool gradients 2 Re <hpsi|A_k psi> into res[0..P) on the device.
+int pool_dev(Ctx &c, const fock_op_t *pool, int P, const float2 *psi, const float2 *hpsi, double *res) {
+  PoolArgs a;
+  memset(&a, 0, sizeof(a));
+  a.L = c.g.L;
+  a.d = c.g.d;
+  a.nrows = c.h.nrows;
+  for (int r = 0; r < kMaxL; ++r) a.srow[r] = c.h.srow[r];
+  for (int k = 0; k <= kMaxD; ++k) a.sq[k] = c.h.sq[k];
+  double *part = (double *)(c.ws + c.L.partial);
+  int k0 = 0;
+  while (k0 < P) {
+    // chunk: up to kMaxSlots entries, kMaxPairs pairs, kMaxDiagOps single-mode ops
+    std::vector<PoolPair> pairs;
+    std::vector<PoolDiag> diags;
+    std::map<std::pair<int, int>, int> pidx;
+    int k1 = k0;
+    for (; k1 < P && k1 - k0 < kMaxSlots; ++k1) {
+      const fock_op_t &op = pool[k1];
+      const int slot = k1 - k0;
+      if (is_single_mode(op.type)) {
+        if ((int)diags.size() >= kMaxDiagOps) break;
+        diags.push_back({(int16_t)op.i, (int16_t)op.type, (int16_t)slot, 0});
+        continue;
+      }
+      auto key = std::make_pair(op.i, op.j);
+      auto it = pidx.find(key);
+      if (it == pidx.end()) {
+        if ((int)pairs.size() >= kMaxPairs) break;
+        PoolPair pp;
+        pp.i = (int16_t)op.i;
+        pp.j = (int16_t)op.j;
+        for (int t = 0; t < 5; ++t) pp.slot[t] = -1;
+        pp.pad = 0;
+        pidx[key] = (int)pairs.size();
+        pairs.push_back(pp);
+        it = pidx.find(key);
+      }
+      PoolPair &pp = pairs[it->second];
+      if (pp.slot[op.type] >= 0) {
+        // duplicate entry: start a new chunk so every slot keeps its own value
+        break;
+      }
+      pp.slot[op.type] = (int16_t)slot;
+    }
+    if (k1 == k0) return set_error(FOCK_ERR_ARG, "cannot schedule pool entry %d", k0);
+    a.npairs = (int)pairs.size();
+    a.ndiag = (int)diags.size();
+    a.nslots = k1 - k0;
+    int rc = tl_in.reserve(c.L.diags + sizeof(PoolDiag) * kMaxDiagOps);
+    if (rc) return rc;
+    char *hp = (char *)tl_in.p;
+    if (!pairs.empty()) memcpy(hp + c.L.pairs, pairs.data(), sizeof(PoolPair) * pairs.size());
+    if (!diags.empty()) memcpy(hp + c.L.diags, diags.data(), sizeof(PoolDiag) * diags.size());
+    FOCK_HIP(hipMemcpyAsync(c.ws + c.L.pairs, hp + c.L.pairs, c.L.diags + sizeof(PoolDiag) * kMaxDiagOps - c.L.pairs,
+                            hipMemcpyHostToDevice, c.s));
+    rc = tl_in.mark(c.s);
+    if (rc) return rc;
+    int G = 0;
+    {
+      ProfScope ps(FOCK_K_POOL, c.s, 16.0 * c.g.n_amp);
+      rc = launch_pool(a, (const PoolPair *)(c.ws + c.L.pairs), (const PoolDiag *)(c.ws + c.L.diags), psi, hpsi,
+                       part, &G, c.s);
+      if (rc) return rc;
+    }
+    rc = launch_reduce(part, G, a.nslots, res + k0, c.s);
+    if (rc) return rc;
+    k0 = k1;
+  }
+  return FOCK_OK;
+}
+
+}  // namespace fock
+
+using namespace fock;
+
+// ====================================================================== C ABI
+extern "C" {
+
+int fock_version(void) { return 1; }
+
+int fock_workspace_bytes(const fock_ham_t *ham, int n_pool, int n_ops, size_t *bytes) {
+  uint32_t namp = 0;
+  int rc = check_ham(ham, &namp);
+  if (rc) return rc;
+  if (!bytes) return set_error(FOCK_ERR_ARG, "bytes is NULL");
+  if (n_pool < 0 || n_pool > 4096 || n_ops < 0 || n_ops > 4096)
+    return set_error(FOCK_ERR_ARG, "n_pool/n_ops out of range");
+  *bytes = make_layout(namp, ham->d, n_pool, n_ops).total;
+  return FOCK_OK;
+}
+
+int fock_apply_H(const fock_ham_t *ham, const void *psi, void *hpsi, double *E, double *norm2, void *ws,
+                 size_t ws_bytes, fock_stream_t stream) {
+  uint32_t namp = 0;
+  int rc = check_ham(ham, &namp);
+  if (rc) return rc;
+  if ((rc = check_ptr(psi, "psi")) || (rc = check_ptr(hpsi, "hpsi"))) return rc;
+  if (psi == hpsi) return set_error(FOCK_ERR_ARG, "psi and hpsi must not overlap");
+  Ctx c;
+  rc = make_ctx(*ham, namp, 0, 0, ws, ws_bytes, (hipStream_t)stream, &c);
+  if (rc) return rc;
+  double *res = (double *)(c.ws + c.L.result);
+  rc = apply_h_dev(c, (const float2 *)psi, (float2 *)hpsi, res);
+  if (rc) return rc;
+  if (E || norm2) {
+    double h2[2];
+    rc = fetch_results(c, 2, h2);
+    if (rc) return rc;
+    if (E) *E = h2[0];
+    if (norm2) *norm2 = h2[1];
+  }
+  return FOCK_OK;
+}
+
+int fock_apply_gate2(int L, int d, fock_op_t op, double theta, int adjoint, void *psi, void *ws, size_t ws_bytes,
+                     fock_stream_t stream) {
+  uint32_t namp = 0;
+  int rc = check_geometry(L, d, &namp);
+  if (rc) return rc;
+  if ((rc = check_op(op, L)) || (rc = check_ptr(psi, "psi"))) return rc;
+  if (!std::isfinite(theta)) return set_error(FOCK_ERR_NONFINITE, "theta is not finite");
+  fock_ham_t ham;
+  memset(&ham, 0, sizeof(ham));
+  ham.L = L;
+  ham.d = d;
+  Ctx c;
+  rc = make_ctx(ham, namp, 0, 1, ws, ws_bytes, (hipStream_t)stream, &c);
+  if (rc) return rc;
+  rc = stage_gates(c, &op, &theta, 1);
+  if (rc) return rc;
+  return forward_gate(c, op, 0, adjoint != 0, (float2 *)psi);
+}
+
+int fock_pool_grads(const fock_ham_t *ham, const fock_op_t *pool, int P, const void *psi, const void *hpsi,
+                    double *grads, void *ws, size_t ws_bytes, fock_stream_t stream) {
+  uint32_t namp = 0;
+  int rc = check_ham(ham, &namp);
+  if (rc) return rc;
+  if (P < 0 || P > 4096) return set_error(FOCK_ERR_ARG, "P=%d out of range", P);
+  if (P == 0) return FOCK_OK;
+  if (!pool || !grads) return set_error(FOCK_ERR_ARG, "pool/grads is NULL");
+  if ((rc = check_ptr(psi, "psi")) || (rc = check_ptr(hpsi, "hpsi"))) return rc;
+  for (int k = 0; k < P; ++k)
+    if ((rc = check_op(pool[k], ham->L))) return rc;
+  Ctx c;
+  rc = make_ctx(*ham, namp, P, 0, ws, ws_bytes, (hipStream_t)stream, &c);
+  if (rc) return rc;
+  rc = pool_dev(c, pool, P, (const float2 *)psi, (const float2 *)hpsi, (double *)(c.ws + c.L.result));
+  if (rc) return rc;
+  return fetch_results(c, P, grads);
+}
+
+int fock_energy_grad_adjoint(const fock_ham_t *ham, const fock_op_t *ops, const double *theta, int n,
+                             const void *psi0, void *psi_work, void *lam_work, double *E, double *norm2,
+                             double *dEdtheta, void *ws, size_t ws_bytes, fock_stream_t stream) {
+  uint32_t namp = 0;
+  int rc = check_ham(ham, &namp);
+  if (rc) return rc;
+  if (n < 0 || n > 4096) return set_error(FOCK_ERR_ARG, "n=%d out of range", n);
+  if (n > 0 && (!ops || !theta)) return set_error(FOCK_ERR_ARG, "ops/theta is NULL");
+  if (!E) return set_error(FOCK_ERR_ARG, "E is NULL");
+  if ((rc = check_ptr(psi0, "psi0")) || (rc = check_ptr(psi_work, "psi_work")) ||
+      (rc = check_ptr(lam_work, "lam_work")))
+    return rc;
+  if (psi_work == lam_work || psi_work == psi0 || lam_work == psi0)
+    return set_error(FOCK_ERR_ARG, "psi0, psi_work and lam_work must be distinct");
+  for (int k = 0; k < n; ++k)
+    if ((rc = check_op(ops[k], ham->L))) return rc;
+  Ctx c;
+  rc = make_ctx(*ham, namp, 0, n, ws, ws_bytes, (hipStream_t)stream, &c);
+  if (rc) return rc;
+  return run_circuit(c, ops, theta, n, psi0, (float2 *)psi_work, (float2 *)lam_work, dEdtheta != nullptr, E, norm2,
+                     dEdtheta);
+}
+
+}  // extern "C"

@@ -1,0 +1,169 @@
+// Internal declarations shared by the host library and the HIP kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/fock.h"
+
+namespace fock {
+
+constexpr int kMaxD = 16;
+constexpr int kMaxL = 24;
+constexpr int kBlock = 256;          // threads per workgroup (4 wave64)
+constexpr int kMaxPairs = 160;       // distinct mode pairs per pool-gradient launch
+constexpr int kMaxSlots = 256;       // pool entries per pool-gradient launch
+constexpr int kMaxDiagOps = 48;      // single-mode pool entries per launch
+
+// ---------------------------------------------------------------- errors
+int set_error(int code, const char *fmt, ...);
+#define FOCK_HIP(call)                                                             \
+  do {                                                                             \
+    hipError_t e_ = (call);                                                        \
+    if (e_ != hipSuccess)                                                          \
+      return ::fock::set_error(FOCK_ERR_HIP, "%s failed: %s", #call, hipGetErrorString(e_)); \
+  } while (0)
+
+// ---------------------------------------------------------------- exact unsigned division by an invariant
+// Granlund & Montgomery (1994), Thm 4.2 with N = 32: for 0 <= n < 2^31,
+// floor(n / v) = (n * m) >> (32 + l) with l = ceil(log2 v), m = floor(2^(32+l)/v) + 1.
+struct FastDiv {
+  uint64_t m;
+  uint32_t sh;
+  uint32_t v;
+};
+FastDiv make_fastdiv(uint32_t v);
+__device__ __forceinline__ uint32_t fdiv(uint32_t n, const FastDiv &f) {
+  return (uint32_t)(((uint64_t)n * f.m) >> f.sh);
+}
+
+// ---------------------------------------------------------------- Hamiltonian on the device
+struct HamArgs {
+  int L, d;
+  int nrows;          // d^(L-1): rows of d amplitudes along mode 0
+  int periodic_wrap;  // 1 if the bond (0, L-1) exists and L >= 3
+  float J, Delta, c2, mu;  // c2 = U/2 + K
+  int srow[kMaxL];    // d^(r-1) for r >= 1: stride of mode r in rows
+  float sq[kMaxD + 1];  // sqrt(0..d)
+};
+
+// ---------------------------------------------------------------- pool gradients
+struct PoolPair {
+  int16_t i, j;
+  int16_t slot[5];  // output slot for HR, HI, DH, PR, PI (-1 = absent)
+  int16_t pad;
+};
+struct PoolDiag {
+  int16_t r, type, slot, pad;  // KERR / ROT on mode r
+};
+struct PoolArgs {
+  int L, d, nrows, npairs, ndiag, nslots;
+  int srow[kMaxL];
+  float sq[kMaxD + 1];
+};
+
+// ---------------------------------------------------------------- gates
+// A two-mode gate on (i, j) with d levels acts blockwise.  Kind SUM groups
+// (n_i, n_j) by n_i + n_j (number-conserving generators), kind DIFF by
+// n_i - n_j (two-mode squeezers).  Blocks are indexed by s = 0..2d-2; within
+// block s the members are ordered by increasing n_i:
+//   SUM : n_i = a, n_j = s - a,       a in [max(0, s-d+1), min(s, d-1)]
+//   DIFF: t = s - (d-1), n_i = a, n_j = a - t,  a in [max(0, t), min(d-1, d-1+t)]
+// A packed table stores the blocks in order of s, each b x b row-major
+// (entry [p][q] maps member q to member p).
+enum GateKind { KIND_SUM = 0, KIND_DIFF = 1 };
+
+// One gate of a circuit as seen by the device-side gate build.
+struct GateRec {
+  int type, u_off;  // generator type, complex offset of its table in the U buffer
+  int nblk, pad;    // workgroups of its reverse-step kernel (partials to reduce)
+};
+
+// Per-(d) gate eigendata on the device: for each two-mode type t < 5, the
+// packed blocks of V (complex double, b x b row-major per block, column m is
+// eigenvector m) and the eigenvalues lambda (b per block) of G = -i A, and the
+// packed blocks of A itself (complex float).
+struct EigTables {
+  const double *V[5];
+  const double *lam[5];
+  const float2 *A[5];
+  int d, psize;
+};
+
+struct Geometry {
+  int L, d;
+  uint32_t n_amp;
+};
+
+inline int block_lo(int kind, int d, int s) {
+  if (kind == KIND_SUM) return s - (d - 1) > 0 ? s - (d - 1) : 0;
+  int t = s - (d - 1);
+  return t > 0 ? t : 0;
+}
+inline int block_hi(int kind, int d, int s) {
+  if (kind == KIND_SUM) return s < d - 1 ? s : d - 1;
+  int t = s - (d - 1);
+  return (d - 1 + t) < d - 1 ? d - 1 + t : d - 1;
+}
+inline int packed_size(int d) {  // sum of b^2 over blocks (same for SUM and DIFF)
+  int tot = 0;
+  for (int s = 0; s <= 2 * d - 2; ++s) {
+    int b = block_hi(KIND_SUM, d, s) - block_lo(KIND_SUM, d, s) + 1;
+    tot += b * b;
+  }
+  return tot;
+}
+
+// Host: dense local generator (d^2 x d^2 with local index n_i*d + n_j for
+// two-mode types, d x d for single-mode types), complex double interleaved.
+void generator_dense(int type, int d, std::vector<double> &m);
+int gate_kind(int type);
+bool is_single_mode(int type);
+// Library-owned device eigendata for cutoff d (built on first use, per device).
+int get_tables(int d, EigTables *out);
+// Size of one gate's slot in a U buffer (complex entries).
+inline int gate_stride(int d) { return packed_size(d); }
+
+// ---------------------------------------------------------------- launchers (kernels_*.hip)
+int launch_apply_h(const HamArgs &h, const float2 *psi, float2 *hpsi, double *partial, int *nblocks,
+                   hipStream_t s);
+int apply_h_blocks(const HamArgs &h);
+int launch_pool(const PoolArgs &a, const PoolPair *pairs, const PoolDiag *diags, const float2 *psi,
+                const float2 *hpsi, double *partial, int *nblocks, hipStream_t s);
+int pool_blocks(const PoolArgs &a);
+int launch_gate_build(const double *theta, const GateRec *recs, int n, const EigTables &T, float2 *utab,
+                      hipStream_t s);
+// psi <- U psi (dag = false) or U^+ psi (dag = true) for a two-mode gate on (i, j).
+int launch_gate(const Geometry &g, int i, int j, int kind, bool dag, const float2 *U, float2 *psi,
+                hipStream_t s);
+// Fused reverse step: partial[blk] = per-block sum of Re<lam|A phi>, then
+// phi <- U^+ phi, lam <- U^+ lam.
+int launch_gate_adj(const Geometry &g, int i, int j, int kind, const float2 *U, const float2 *A, float2 *phi,
+                    float2 *lam, double *partial, hipStream_t s);
+int gate_blocks_count(const Geometry &g);
+// Single-mode diagonal gate with device phase table ph[d].
+int launch_diag(const Geometry &g, int r, int type, bool dag, const float2 *ph, float2 *psi, hipStream_t s);
+int launch_diag_adj(const Geometry &g, int r, int type, const float2 *ph, float2 *phi, float2 *lam,
+                    double *partial, hipStream_t s);
+int diag_blocks_count(const Geometry &g);
+// out[c] = sum_b partial[b * ncols + c] for c < ncols, in a fixed order.
+int launch_reduce(const double *partial, int nblocks, int ncols, double *out, hipStream_t s);
+// out[k] = sum_{b < recs[k].nblk} partial[k * row_stride + b] for k < n, in a fixed order.
+int launch_reduce_rows(const double *partial, int row_stride, const GateRec *recs, int n, double *out,
+                       hipStream_t s);
+
+// ---------------------------------------------------------------- profiling
+struct ProfScope {
+  int id;
+  hipStream_t s;
+  double bytes;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  ProfScope(int id, hipStream_t s, double bytes);
+  ~ProfScope();
+};
+void prof_harvest();
+
+}  // namespace fock

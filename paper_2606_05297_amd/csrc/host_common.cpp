@@ -1,0 +1,324 @@
+// Host-side support: error reporting, invariant division, local generator
+// matrices, the Hermitian Jacobi eigensolver for the gate blocks, the
+// library-owned device eigendata, and per-kernel event timing.
+#include <cmath>
+#include <complex>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+
+#include "fock_internal.h"
+
+namespace fock {
+
+// ---------------------------------------------------------------- errors
+static thread_local char g_err[512] = "";
+
+int set_error(int code, const char *fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof(g_err), fmt, ap);
+  va_end(ap);
+  return code;
+}
+
+const char *last_error() { return g_err; }
+
+// ---------------------------------------------------------------- invariant division
+FastDiv make_fastdiv(uint32_t v) {
+  FastDiv f;
+  f.v = v;
+  uint32_t l = 0;
+  while ((1ull << l) < v) ++l;
+  f.sh = 32 + l;
+  f.m = (uint64_t)((((unsigned __int128)1) << (32 + l)) / v) + 1;
+  return f;
+}
+
+// ---------------------------------------------------------------- local generators
+using cd = std::complex<double>;
+
+bool is_single_mode(int type) { return type == FOCK_KERR || type == FOCK_ROT; }
+int gate_kind(int type) { return (type == FOCK_PR || type == FOCK_PI) ? KIND_DIFF : KIND_SUM; }
+
+// Truncated annihilation operator, a|m> = sqrt(m)|m-1> (Sec. II.A).
+static double lad(int d, int row, int col) { return (col >= 1 && row == col - 1) ? std::sqrt((double)col) : 0.0; }
+static double cre(int d, int row, int col) { return lad(d, col, row); }
+
+void generator_dense(int type, int d, std::vector<double> &m) {
+  if (is_single_mode(type)) {
+    m.assign(2 * d * d, 0.0);
+    for (int n = 0; n < d; ++n) m[2 * (n * d + n) + 1] = type == FOCK_KERR ? (double)n * n : (double)n;
+    return;
+  }
+  const int D2 = d * d;
+  m.assign(2 * D2 * D2, 0.0);
+  for (int ip = 0; ip < d; ++ip)
+    for (int jp = 0; jp < d; ++jp)
+      for (int i = 0; i < d; ++i)
+        for (int j = 0; j < d; ++j) {
+          const double hop1 = cre(d, ip, i) * lad(d, jp, j);      // a_i^+ a_j
+          const double hop2 = lad(d, ip, i) * cre(d, jp, j);      // a_i a_j^+ = a_j^+ a_i
+          const double pr1 = lad(d, ip, i) * lad(d, jp, j);       // a_i a_j
+          const double pr2 = cre(d, ip, i) * cre(d, jp, j);       // a_i^+ a_j^+
+          // N_i a_i^+ : N acts after the creation, i.e. multiplies by the new n_i = ip
+          const double dh1 = (double)ip * hop1;
+          // a_i N_i : N acts first, multiplies by the old n_i = i
+          const double dh2 = (double)i * hop2;
+          double re = 0.0, im = 0.0;
+          switch (type) {
+            case FOCK_HR: re = hop1 - hop2; break;
+            case FOCK_HI: im = hop1 + hop2; break;
+            case FOCK_DH: im = dh1 + dh2; break;
+            case FOCK_PR: re = pr1 - pr2; break;
+            case FOCK_PI: im = pr1 + pr2; break;
+            default: break;
+          }
+          const int r = ip * d + jp, c = i * d + j;
+          m[2 * (r * D2 + c)] = re;
+          m[2 * (r * D2 + c) + 1] = im;
+        }
+}
+
+// ---------------------------------------------------------------- Hermitian Jacobi
+// Cyclic Jacobi for a complex Hermitian n x n matrix H (row-major).  Each
+// rotation J = diag(1, e^{-i phi}) [[c, s], [-s, c]] on (p, q) first makes
+// H_pq real, then annihilates it with the symmetric Schur rotation (Golub &
+// Van Loan, Alg. 8.4.1).  On return w holds the eigenvalues and column m of V
+// the eigenvector of w[m].
+static void herm_jacobi(int n, std::vector<cd> H, std::vector<double> &w, std::vector<cd> &V) {
+  V.assign(n * n, cd(0.0, 0.0));
+  for (int k = 0; k < n; ++k) V[k * n + k] = 1.0;
+  double fro = 0.0;
+  for (auto &x : H) fro += std::norm(x);
+  for (int sweep = 0; sweep < 100; ++sweep) {
+    double off = 0.0;
+    for (int p = 0; p < n; ++p)
+      for (int q = p + 1; q < n; ++q) off += std::norm(H[p * n + q]);
+    if (off <= 1e-32 * (fro + 1e-300)) break;
+    for (int p = 0; p < n; ++p)
+      for (int q = p + 1; q < n; ++q) {
+        const cd hpq = H[p * n + q];
+        const double mag = std::abs(hpq);
+        if (mag < 1e-300) continue;
+        const cd ph = hpq / mag;
+        const double a = H[p * n + p].real(), c = H[q * n + q].real();
+        const double tau = (c - a) / (2.0 * mag);
+        const double t = (tau >= 0 ? 1.0 : -1.0) / (std::fabs(tau) + std::sqrt(1.0 + tau * tau));
+        const double cs = 1.0 / std::sqrt(1.0 + t * t), sn = t * cs;
+        const cd Jpp = cs, Jpq = sn, Jqp = -sn * std::conj(ph), Jqq = cs * std::conj(ph);
+        for (int k = 0; k < n; ++k) {  // H <- H J
+          const cd hp = H[k * n + p], hq = H[k * n + q];
+          H[k * n + p] = hp * Jpp + hq * Jqp;
+          H[k * n + q] = hp * Jpq + hq * Jqq;
+        }
+        for (int k = 0; k < n; ++k) {  // H <- J^+ H
+          const cd hp = H[p * n + k], hq = H[q * n + k];
+          H[p * n + k] = std::conj(Jpp) * hp + std::conj(Jqp) * hq;
+          H[q * n + k] = std::conj(Jpq) * hp + std::conj(Jqq) * hq;
+        }
+        for (int k = 0; k < n; ++k) {  // V <- V J
+          const cd vp = V[k * n + p], vq = V[k * n + q];
+          V[k * n + p] = vp * Jpp + vq * Jqp;
+          V[k * n + q] = vp * Jpq + vq * Jqq;
+        }
+      }
+  }
+  w.resize(n);
+  for (int k = 0; k < n; ++k) w[k] = H[k * n + k].real();
+}
+
+// ---------------------------------------------------------------- device eigendata
+struct TableSet {
+  EigTables T;
+  void *dev = nullptr;
+};
+
+static std::mutex g_tab_mu;
+static std::map<std::pair<int, int>, TableSet> g_tabs;
+
+static int build_tables(int d, TableSet *ts) {
+  const int ps = packed_size(d);
+  // layout: [V: 5 * ps complex double][lam: 5 * d*d double][A: 5 * ps float2]
+  const size_t nV = (size_t)5 * ps * 2, nL = (size_t)5 * d * d, nA = (size_t)5 * ps * 2;
+  std::vector<double> hv(nV + nL, 0.0);
+  std::vector<float> ha(nA, 0.f);
+  const int D2 = d * d;
+  for (int t = 0; t < 5; ++t) {
+    std::vector<double> A;
+    generator_dense(t, d, A);
+    const int kind = gate_kind(t);
+    int off = 0, loff = 0;
+    double leak = 0.0;
+    std::vector<char> covered((size_t)D2 * D2, 0);
+    for (int s = 0; s <= 2 * d - 2; ++s) {
+      const int lo = block_lo(kind, d, s), b = block_hi(kind, d, s) - lo + 1;
+      std::vector<int> li(b);
+      for (int p = 0; p < b; ++p) {
+        const int a = lo + p;
+        const int nj = kind == KIND_SUM ? s - a : a - (s - (d - 1));
+        li[p] = a * d + nj;
+      }
+      std::vector<cd> G(b * b);
+      for (int p = 0; p < b; ++p)
+        for (int q = 0; q < b; ++q) {
+          const size_t e = (size_t)li[p] * D2 + li[q];
+          covered[e] = 1;
+          const cd Aval(A[2 * e], A[2 * e + 1]);
+          G[p * b + q] = cd(0.0, -1.0) * Aval;  // G = -i A, Hermitian
+          ha[(size_t)t * ps * 2 + 2 * (off + p * b + q)] = (float)Aval.real();
+          ha[(size_t)t * ps * 2 + 2 * (off + p * b + q) + 1] = (float)Aval.imag();
+        }
+      std::vector<double> w;
+      std::vector<cd> V;
+      herm_jacobi(b, G, w, V);
+      // residual check |G - V diag(w) V^+|
+      double res = 0.0;
+      for (int p = 0; p < b; ++p)
+        for (int q = 0; q < b; ++q) {
+          cd acc = 0.0;
+          for (int m = 0; m < b; ++m) acc += V[p * b + m] * w[m] * std::conj(V[q * b + m]);
+          res = std::max(res, std::abs(acc - G[p * b + q]));
+        }
+      if (res > 1e-11) return set_error(FOCK_ERR_HIP, "gate eigendata residual %.3g (type %d, d %d)", res, t, d);
+      for (int k = 0; k < b * b; ++k) {
+        hv[(size_t)t * ps * 2 + 2 * (off + k)] = V[k].real();
+        hv[(size_t)t * ps * 2 + 2 * (off + k) + 1] = V[k].imag();
+      }
+      for (int m = 0; m < b; ++m) hv[nV + (size_t)t * D2 + loff + m] = w[m];
+      off += b * b;
+      loff += b;
+    }
+    for (size_t e = 0; e < (size_t)D2 * D2; ++e)
+      if (!covered[e]) leak += std::fabs(A[2 * e]) + std::fabs(A[2 * e + 1]);
+    if (leak != 0.0) return set_error(FOCK_ERR_HIP, "generator type %d has entries outside its blocks", t);
+  }
+  const size_t bytesD = (nV + nL) * sizeof(double), bytesA = nA * sizeof(float);
+  void *dev = nullptr;
+  FOCK_HIP(hipMalloc(&dev, bytesD + bytesA));
+  FOCK_HIP(hipMemcpy(dev, hv.data(), bytesD, hipMemcpyHostToDevice));
+  FOCK_HIP(hipMemcpy((char *)dev + bytesD, ha.data(), bytesA, hipMemcpyHostToDevice));
+  ts->dev = dev;
+  const double *dV = (const double *)dev;
+  const double *dL = dV + nV;
+  const float2 *dA = (const float2 *)((const char *)dev + bytesD);
+  for (int t = 0; t < 5; ++t) {
+    ts->T.V[t] = dV + (size_t)t * ps * 2;
+    ts->T.lam[t] = dL + (size_t)t * D2;
+    ts->T.A[t] = dA + (size_t)t * ps;
+  }
+  ts->T.d = d;
+  ts->T.psize = ps;
+  return FOCK_OK;
+}
+
+int get_tables(int d, EigTables *out) {
+  int dev = 0;
+  FOCK_HIP(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(g_tab_mu);
+  auto key = std::make_pair(dev, d);
+  auto it = g_tabs.find(key);
+  if (it == g_tabs.end()) {
+    TableSet ts;
+    int rc = build_tables(d, &ts);
+    if (rc) return rc;
+    it = g_tabs.emplace(key, ts).first;
+  }
+  *out = it->second.T;
+  return FOCK_OK;
+}
+
+// ---------------------------------------------------------------- profiling
+struct ProfAcc {
+  int64_t launches = 0;
+  double ms = 0.0, bytes = 0.0;
+};
+struct Pending {
+  int id;
+  double bytes;
+  hipEvent_t e0, e1;
+};
+static std::mutex g_prof_mu;
+static bool g_prof_on = false;
+static ProfAcc g_prof[FOCK_K_NUM];
+static std::vector<Pending> g_pending;
+static std::vector<hipEvent_t> g_event_pool;
+
+static hipEvent_t take_event() {
+  if (!g_event_pool.empty()) {
+    hipEvent_t e = g_event_pool.back();
+    g_event_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+ProfScope::ProfScope(int id_, hipStream_t s_, double bytes_) : id(id_), s(s_), bytes(bytes_) {
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  if (!g_prof_on) return;
+  e0 = take_event();
+  e1 = take_event();
+  if (e0) hipEventRecord(e0, s);
+}
+
+ProfScope::~ProfScope() {
+  if (!e0 || !e1) return;
+  hipEventRecord(e1, s);
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  g_pending.push_back({id, bytes, e0, e1});
+}
+
+void prof_harvest() {
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  std::vector<Pending> keep;
+  for (auto &p : g_pending) {
+    if (hipEventQuery(p.e1) != hipSuccess) {
+      keep.push_back(p);
+      continue;
+    }
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, p.e0, p.e1) == hipSuccess && p.id >= 0 && p.id < FOCK_K_NUM) {
+      g_prof[p.id].launches += 1;
+      g_prof[p.id].ms += ms;
+      g_prof[p.id].bytes += p.bytes;
+    }
+    g_event_pool.push_back(p.e0);
+    g_event_pool.push_back(p.e1);
+  }
+  g_pending.swap(keep);
+}
+
+}  // namespace fock
+
+extern "C" {
+
+const char *fock_last_error(void) { return fock::last_error(); }
+
+int fock_prof_enable(int on) {
+  std::lock_guard<std::mutex> lk(fock::g_prof_mu);
+  fock::g_prof_on = on != 0;
+  return FOCK_OK;
+}
+
+int fock_prof_query(int id, int64_t *launches, double *total_ms, double *bytes) {
+  if (id < 0 || id >= FOCK_K_NUM) return fock::set_error(FOCK_ERR_ARG, "kernel id %d out of range", id);
+  fock::prof_harvest();
+  std::lock_guard<std::mutex> lk(fock::g_prof_mu);
+  if (launches) *launches = fock::g_prof[id].launches;
+  if (total_ms) *total_ms = fock::g_prof[id].ms;
+  if (bytes) *bytes = fock::g_prof[id].bytes;
+  return FOCK_OK;
+}
+
+int fock_prof_reset(void) {
+  fock::prof_harvest();
+  std::lock_guard<std::mutex> lk(fock::g_prof_mu);
+  for (auto &p : fock::g_prof) p = fock::ProfAcc();
+  return FOCK_OK;
+}
+
+}  // extern "C"

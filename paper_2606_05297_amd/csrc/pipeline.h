@@ -1,0 +1,41 @@
+// Host pipeline shared by the C ABI entry points and the ADAPT driver.
+#pragma once
+
+#include "fock_internal.h"
+
+namespace fock {
+
+struct Layout {
+  size_t theta = 0, recs = 0, utab = 0, partial = 0, result = 0, pairs = 0, diags = 0, total = 0;
+  int G = 0;     // blocks of the row-parallel kernels
+  int nmax = 0;  // gates
+  int pmax = 0;  // pool chunk
+};
+
+struct Ctx {
+  Geometry g;
+  HamArgs h;
+  EigTables T;
+  hipStream_t s;
+  char *ws;
+  Layout L;
+};
+
+int check_geometry(int L, int d, uint32_t *namp);
+int check_ham(const fock_ham_t *h, uint32_t *namp);
+int check_op(const fock_op_t &op, int L);
+int check_ptr(const void *p, const char *name);
+HamArgs make_ham_args(const fock_ham_t &h);
+Layout make_layout(uint32_t namp, int d, int P, int n);
+int make_ctx(const fock_ham_t &ham, uint32_t namp, int P, int n, void *ws, size_t ws_bytes, hipStream_t s, Ctx *c);
+int stage_gates(Ctx &c, const fock_op_t *ops, const double *theta, int n);
+int forward_gate(Ctx &c, const fock_op_t &op, int k, bool dag, float2 *psi);
+int apply_h_dev(Ctx &c, const float2 *psi, float2 *hpsi, double *res2);
+int fetch_results(Ctx &c, int count, double *host);
+// Energy (Rayleigh quotient) and optionally all dE/dtheta of ops/theta applied to psi0.
+int run_circuit(Ctx &c, const fock_op_t *ops, const double *theta, int n, const void *psi0, float2 *phi,
+                float2 *lam, bool grad, double *E, double *norm2, double *dE);
+// 2 Re <hpsi|A_k psi> for the pool into res[0..P) (device).
+int pool_dev(Ctx &c, const fock_op_t *pool, int P, const float2 *psi, const float2 *hpsi, double *res);
+
+}  // namespace fock

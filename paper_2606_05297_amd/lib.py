@@ -1,0 +1,307 @@
+"""ctypes binding of libfock (argument marshalling only; all work runs in the
+HIP library).  Names mirror the C ABI declared in include/fock.h.
+
+Device buffers are torch tensors on the current HIP device (states are
+complex64, workspaces uint8); streams are torch's current stream unless given.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libfock.so")
+
+TYPES = {"HR": 0, "HI": 1, "DH": 2, "PR": 3, "PI": 4, "KERR": 5, "ROT": 6}
+TYPE_NAMES = {v: k for k, v in TYPES.items()}
+
+FOCK_OK = 0
+ERRORS = {-1: "FOCK_ERR_ARG", -2: "FOCK_ERR_SIZE", -3: "FOCK_ERR_UNSUPPORTED", -4: "FOCK_ERR_NONFINITE",
+          -5: "FOCK_ERR_HIP", -6: "FOCK_ERR_LINESEARCH", -7: "FOCK_ERR_STATE"}
+K_APPLY_H, K_POOL, K_GATE, K_ADJ, K_DIAG, K_REDUCE = range(6)
+
+
+class Ham(C.Structure):
+    _fields_ = [("L", C.c_int32), ("d", C.c_int32), ("periodic", C.c_int32), ("reserved", C.c_int32),
+                ("J", C.c_double), ("U", C.c_double), ("mu", C.c_double), ("Delta", C.c_double),
+                ("K", C.c_double)]
+
+
+class Op(C.Structure):
+    _fields_ = [("type", C.c_int32), ("i", C.c_int32), ("j", C.c_int32)]
+
+
+class AdaptOpts(C.Structure):
+    _fields_ = [("max_iters", C.c_int32), ("bfgs_maxiter", C.c_int32), ("grad_tol", C.c_double),
+                ("tie_tau", C.c_double), ("gtol_floor_rel", C.c_double), ("warm_gtol", C.c_double),
+                ("n_warm", C.c_int32), ("grad_mode", C.c_int32), ("warm_ops", C.POINTER(Op)),
+                ("warm_theta0", C.POINTER(C.c_double)), ("fd_step", C.c_double),
+                ("recycle_hessian", C.c_int32), ("reserved", C.c_int32)]
+
+
+class AdaptReport(C.Structure):
+    _fields_ = [("iter", C.c_int32), ("k_sel", C.c_int32), ("converged", C.c_int32), ("status", C.c_int32),
+                ("bfgs_iters", C.c_int32), ("bfgs_evals", C.c_int32), ("n_params", C.c_int32),
+                ("capped", C.c_int32), ("g_sel", C.c_double), ("g_norm2", C.c_double), ("g_inf", C.c_double),
+                ("E", C.c_double), ("norm2", C.c_double), ("E_init", C.c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+OBJECTIVE = C.CFUNCTYPE(C.c_int, C.c_void_p, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_double),
+                        C.POINTER(C.c_double))
+
+_lib = None
+
+
+class FockError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{ERRORS.get(code, code)}: {msg}")
+        self.code = code
+
+
+def load(path: str = LIB_PATH):
+    """Load libfock.so (fails loudly when it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"libfock.so not found at {path}; build it with `python -m paper_2606_05297_amd.build`")
+    L = C.CDLL(path)
+    vp, sz, dp, ip = C.c_void_p, C.c_size_t, C.POINTER(C.c_double), C.POINTER(C.c_int)
+    L.fock_last_error.restype = C.c_char_p
+    L.fock_version.restype = C.c_int
+    L.fock_workspace_bytes.argtypes = [C.POINTER(Ham), C.c_int, C.c_int, C.POINTER(C.c_size_t)]
+    L.fock_apply_H.argtypes = [C.POINTER(Ham), vp, vp, dp, dp, vp, sz, vp]
+    L.fock_apply_gate2.argtypes = [C.c_int, C.c_int, Op, C.c_double, C.c_int, vp, vp, sz, vp]
+    L.fock_pool_grads.argtypes = [C.POINTER(Ham), C.POINTER(Op), C.c_int, vp, vp, dp, vp, sz, vp]
+    L.fock_energy_grad_adjoint.argtypes = [C.POINTER(Ham), C.POINTER(Op), dp, C.c_int, vp, vp, vp, dp, dp, dp, vp,
+                                           sz, vp]
+    L.adapt_default_opts.argtypes = [C.POINTER(AdaptOpts)]
+    L.adapt_default_opts.restype = None
+    L.adapt_create.argtypes = [C.POINTER(Ham), C.POINTER(Op), C.c_int, vp, C.POINTER(AdaptOpts), vp,
+                               C.POINTER(vp)]
+    L.adapt_step.argtypes = [vp, C.POINTER(AdaptReport)]
+    L.adapt_warm_report.argtypes = [vp, C.POINTER(AdaptReport)]
+    L.adapt_get_ansatz.argtypes = [vp, C.POINTER(Op), dp, C.c_int, ip]
+    L.adapt_propose.argtypes = [vp, dp, C.c_int]
+    L.adapt_last_proposal.argtypes = [vp, ip, dp, dp]
+    L.adapt_destroy.argtypes = [vp]
+    L.fock_bfgs_minimize.argtypes = [C.c_int, dp, OBJECTIVE, vp, C.c_double, C.c_int, dp, ip, ip, dp, ip]
+    L.fock_prof_enable.argtypes = [C.c_int]
+    L.fock_prof_query.argtypes = [C.c_int, C.POINTER(C.c_int64), dp, dp]
+    L.fock_prof_reset.argtypes = []
+    _lib = L
+    return L
+
+
+def _check(rc):
+    if rc != FOCK_OK:
+        raise FockError(rc, _lib.fock_last_error().decode())
+
+
+def last_error() -> str:
+    return load().fock_last_error().decode()
+
+
+# ---------------------------------------------------------------- marshalling helpers
+
+def ham(L, d, periodic=False, J=1.0, U=0.0, mu=0.0, Delta=0.0, K=0.0) -> Ham:
+    return Ham(int(L), int(d), int(bool(periodic)), 0, float(J), float(U), float(mu), float(Delta), float(K))
+
+
+def ham_from(cfg: dict) -> Ham:
+    return ham(cfg["L"], cfg["d"], cfg["periodic"], cfg["J"], cfg["U"], cfg["mu"], cfg["Delta"], cfg["K"])
+
+
+def op(t, i, j=-1) -> Op:
+    return Op(TYPES[t] if isinstance(t, str) else int(t), int(i), int(j))
+
+
+def ops_array(ops):
+    arr = (Op * max(1, len(ops)))()
+    for k, o in enumerate(ops):
+        arr[k] = op(*o)
+    return arr
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream))
+
+
+def workspace_bytes(h: Ham, n_pool: int = 0, n_ops: int = 0) -> int:
+    L = load()
+    b = C.c_size_t(0)
+    _check(L.fock_workspace_bytes(C.byref(h), int(n_pool), int(n_ops), C.byref(b)))
+    return int(b.value)
+
+
+def workspace(h: Ham, n_pool: int = 0, n_ops: int = 0, device="cuda"):
+    import torch
+    return torch.empty(workspace_bytes(h, n_pool, n_ops), dtype=torch.uint8, device=device)
+
+
+# ---------------------------------------------------------------- entry points
+
+def apply_H(h: Ham, psi, hpsi, ws, energy=True, stream=None):
+    """hpsi = H psi; returns (<psi|H|psi>, <psi|psi>) when energy is True."""
+    L = load()
+    E, n2 = C.c_double(0), C.c_double(0)
+    _check(L.fock_apply_H(C.byref(h), _ptr(psi), _ptr(hpsi), C.byref(E) if energy else None,
+                          C.byref(n2) if energy else None, _ptr(ws), ws.numel(), _stream(stream)))
+    return (E.value, n2.value) if energy else None
+
+
+def apply_gate2(L_, d, o, theta, psi, ws, adjoint=False, stream=None):
+    L = load()
+    _check(L.fock_apply_gate2(int(L_), int(d), op(*o), float(theta), int(bool(adjoint)), _ptr(psi), _ptr(ws),
+                              ws.numel(), _stream(stream)))
+
+
+def pool_grads(h: Ham, pool, psi, hpsi, ws, stream=None) -> np.ndarray:
+    L = load()
+    P = len(pool)
+    out = np.zeros(P, dtype=np.float64)
+    _check(L.fock_pool_grads(C.byref(h), ops_array(pool), P, _ptr(psi), _ptr(hpsi),
+                             out.ctypes.data_as(C.POINTER(C.c_double)), _ptr(ws), ws.numel(), _stream(stream)))
+    return out
+
+
+def energy_grad_adjoint(h: Ham, ops, theta, psi0, psi_work, lam_work, ws, grad=True, stream=None):
+    """Returns (E, norm2, dE/dtheta or None) for the ansatz ops/theta on psi0."""
+    L = load()
+    n = len(ops)
+    th = np.ascontiguousarray(theta, dtype=np.float64)
+    E, n2 = C.c_double(0), C.c_double(0)
+    g = np.zeros(max(n, 1), dtype=np.float64)
+    _check(L.fock_energy_grad_adjoint(C.byref(h), ops_array(ops), th.ctypes.data_as(C.POINTER(C.c_double)), n,
+                                      _ptr(psi0), _ptr(psi_work), _ptr(lam_work), C.byref(E), C.byref(n2),
+                                      g.ctypes.data_as(C.POINTER(C.c_double)) if grad else None, _ptr(ws),
+                                      ws.numel(), _stream(stream)))
+    return E.value, n2.value, (g[:n].copy() if grad else None)
+
+
+def bfgs_minimize(fun, x0, gtol=1e-8, maxiter=1000, hinv=None):
+    """fun(x) -> (f, g) on the host; returns dict(x, f, iters, evals, status, hinv)."""
+    L = load()
+    n = len(x0)
+    x = np.ascontiguousarray(x0, dtype=np.float64).copy()
+
+    def cb(ctx, n_, xp, fp, gp):
+        try:
+            xv = np.ctypeslib.as_array(xp, shape=(n_,)).copy()
+            f, g = fun(xv)
+            fp[0] = float(f)
+            gv = np.ctypeslib.as_array(gp, shape=(n_,))
+            gv[:] = g
+            return 0
+        except Exception:  # abort the minimisation; reported as FOCK_ERR_ARG
+            return -1
+
+    cfun = OBJECTIVE(cb)
+    H = np.zeros(n * n) if hinv is None else np.ascontiguousarray(hinv, dtype=np.float64).reshape(-1).copy()
+    it, ev, st = C.c_int(0), C.c_int(0), C.c_int(0)
+    fmin = C.c_double(0)
+    dp = C.POINTER(C.c_double)
+    _check(L.fock_bfgs_minimize(n, x.ctypes.data_as(dp), cfun, None, float(gtol), int(maxiter), H.ctypes.data_as(dp),
+                                C.byref(it), C.byref(ev), C.byref(fmin), C.byref(st)))
+    return dict(x=x, f=fmin.value, iters=it.value, evals=ev.value, status=st.value, hinv=H.reshape(n, n))
+
+
+class Adapt:
+    """One CV-ADAPT-VQE run on the device (adapt_create / adapt_step)."""
+
+    def __init__(self, h: Ham, pool, psi0, max_iters=60, grad_tol=1e-3, warm_ops=(), warm_theta0=(),
+                 grad_mode=0, fd_step=1e-3, recycle_hessian=False, bfgs_maxiter=1000, tie_tau=1e-4,
+                 gtol_floor_rel=1e-5, warm_gtol=1e-6, stream=None):
+        L = load()
+        self._L = L
+        o = AdaptOpts()
+        L.adapt_default_opts(C.byref(o))
+        o.max_iters = int(max_iters)
+        o.grad_tol = float(grad_tol)
+        o.grad_mode = int(grad_mode)
+        o.fd_step = float(fd_step)
+        o.recycle_hessian = int(bool(recycle_hessian))
+        o.bfgs_maxiter = int(bfgs_maxiter)
+        o.tie_tau = float(tie_tau)
+        o.gtol_floor_rel = float(gtol_floor_rel)
+        o.warm_gtol = float(warm_gtol)
+        self._warm = ops_array(list(warm_ops))
+        self._warm_th = np.ascontiguousarray(warm_theta0, dtype=np.float64)
+        o.n_warm = len(warm_ops)
+        if len(warm_ops):
+            o.warm_ops = C.cast(self._warm, C.POINTER(Op))
+            o.warm_theta0 = self._warm_th.ctypes.data_as(C.POINTER(C.c_double))
+        self.pool = list(pool)
+        self._pool = ops_array(self.pool)
+        self.h = h
+        self._st = C.c_void_p()
+        _check(L.adapt_create(C.byref(h), self._pool, len(self.pool), _ptr(psi0), C.byref(o), _stream(stream),
+                              C.byref(self._st)))
+
+    def warm_report(self) -> dict:
+        r = AdaptReport()
+        _check(self._L.adapt_warm_report(self._st, C.byref(r)))
+        return r.as_dict()
+
+    def step(self) -> dict:
+        r = AdaptReport()
+        _check(self._L.adapt_step(self._st, C.byref(r)))
+        return r.as_dict()
+
+    def ansatz(self):
+        n = C.c_int(0)
+        _check(self._L.adapt_get_ansatz(self._st, None, None, 0, C.byref(n)))
+        m = n.value
+        ops = (Op * max(1, m))()
+        th = np.zeros(max(1, m))
+        _check(self._L.adapt_get_ansatz(self._st, ops, th.ctypes.data_as(C.POINTER(C.c_double)), m, C.byref(n)))
+        return [(TYPE_NAMES[ops[k].type], ops[k].i, ops[k].j) for k in range(m)], th[:m].copy()
+
+    def propose(self, theta):
+        th = np.ascontiguousarray(theta, dtype=np.float64)
+        _check(self._L.adapt_propose(self._st, th.ctypes.data_as(C.POINTER(C.c_double)), len(th)))
+
+    def last_proposal(self):
+        a, ep, el = C.c_int(0), C.c_double(0), C.c_double(0)
+        _check(self._L.adapt_last_proposal(self._st, C.byref(a), C.byref(ep), C.byref(el)))
+        return dict(accepted=bool(a.value), E_prop=ep.value, E_plain=el.value)
+
+    def close(self):
+        if self._st:
+            self._L.adapt_destroy(self._st)
+            self._st = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ---------------------------------------------------------------- profiling
+
+def prof_enable(on=True):
+    _check(load().fock_prof_enable(int(bool(on))))
+
+
+def prof_reset():
+    _check(load().fock_prof_reset())
+
+
+def prof_query(kid: int) -> dict:
+    n = C.c_int64(0)
+    ms, b = C.c_double(0), C.c_double(0)
+    _check(load().fock_prof_query(int(kid), C.byref(n), C.byref(ms), C.byref(b)))
+    return dict(launches=n.value, ms=ms.value, bytes=b.value)

@@ -1,0 +1,146 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads and exports
+every symbol include/fock.h declares, arguments are rejected before any device
+work, and the host BFGS minimiser behaves as a BFGS should."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+import scipy.optimize
+
+from paper_2606_05297_amd import lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "fock.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = re.findall(r"^(?:int|void|const char \*)\s*([a-z_][a-z_0-9]*)\s*\(", src, flags=re.M)
+    return sorted(set(names))
+
+
+def test_library_exports_every_declared_symbol():
+    L = lib.load()
+    names = declared_functions()
+    assert len(names) >= 18
+    for n in names:
+        assert hasattr(L, n), n
+
+
+def test_version_and_error_text():
+    L = lib.load()
+    assert L.fock_version() == 1
+    rc = L.fock_apply_H(C.byref(lib.ham(3, 1)), None, None, None, None, None, 0, None)
+    assert rc == -3 and "d=1" in lib.last_error()
+
+
+@pytest.mark.parametrize("L_,d,code", [(0, 4, -3), (25, 2, -3), (3, 17, -3), (3, 1, -3), (12, 8, -2), (31, 2, -3)])
+def test_geometry_validation(L_, d, code):
+    b = C.c_size_t(0)
+    assert lib.load().fock_workspace_bytes(C.byref(lib.ham(L_, d)), 0, 0, C.byref(b)) == code
+
+
+def test_workspace_sizes_grow_with_pool_and_ops():
+    h = lib.ham(8, 8, False, 1, 0, 0, 0.5, 0.2)
+    a = lib.workspace_bytes(h, 0, 0)
+    b = lib.workspace_bytes(h, 28, 0)
+    c = lib.workspace_bytes(h, 28, 60)
+    assert 0 < a < b < c
+    assert c % 256 == 0
+
+
+def test_argument_validation_before_device_work():
+    L = lib.load()
+    h = lib.ham(3, 4, False, 1, 2)
+    big = C.c_void_p(1 << 20)  # never dereferenced: validation fails first
+    # bad op pair (i >= j)
+    rc = L.fock_apply_gate2(3, 4, lib.op("HR", 2, 1), 0.1, 0, big, big, 1 << 20, None)
+    assert rc == -1 and "i < j" in lib.last_error()
+    # out-of-range mode
+    rc = L.fock_apply_gate2(3, 4, lib.op("PR", 0, 3), 0.1, 0, big, big, 1 << 20, None)
+    assert rc == -1
+    # unknown type
+    rc = L.fock_apply_gate2(3, 4, lib.Op(9, 0, 1), 0.1, 0, big, big, 1 << 20, None)
+    assert rc == -1 and "unknown" in lib.last_error()
+    # non-finite theta
+    rc = L.fock_apply_gate2(3, 4, lib.op("HR", 0, 1), float("nan"), 0, big, big, 1 << 20, None)
+    assert rc == -4
+    # null / misaligned pointers
+    rc = L.fock_apply_H(C.byref(h), None, big, None, None, big, 1 << 20, None)
+    assert rc == -1 and "psi" in lib.last_error()
+    rc = L.fock_apply_H(C.byref(h), C.c_void_p((1 << 20) + 8), big, None, None, big, 1 << 20, None)
+    assert rc == -1 and "aligned" in lib.last_error()
+    # aliasing
+    rc = L.fock_apply_H(C.byref(h), big, big, None, None, big, 1 << 20, None)
+    assert rc == -1 and "overlap" in lib.last_error()
+    # non-finite Hamiltonian
+    hb = lib.ham(3, 4, False, float("inf"), 2)
+    assert L.fock_apply_H(C.byref(hb), big, C.c_void_p(2 << 20), None, None, big, 1 << 20, None) == -4
+    # pool size limits
+    assert L.fock_pool_grads(C.byref(h), lib.ops_array([("HR", 0, 1)]), 5000, big, big, None, big, 0, None) == -1
+
+
+def test_workspace_too_small_is_reported():
+    L = lib.load()
+    h = lib.ham(3, 4, False, 1, 2)
+    big = C.c_void_p(1 << 20)
+    rc = L.fock_apply_H(C.byref(h), big, C.c_void_p(2 << 20), None, None, C.c_void_p(3 << 20), 16, None)
+    assert rc == -2 and "workspace" in lib.last_error()
+    rc = L.fock_apply_H(C.byref(h), big, C.c_void_p(2 << 20), None, None, C.c_void_p((3 << 20) + 64), 1 << 20, None)
+    assert rc == -1 and "256-byte" in lib.last_error()
+
+
+def test_adapt_create_validation():
+    L = lib.load()
+    o = lib.AdaptOpts()
+    L.adapt_default_opts(C.byref(o))
+    assert o.max_iters == 60 and o.bfgs_maxiter == 1000 and o.grad_tol == 1e-3
+    st = C.c_void_p()
+    h = lib.ham(3, 4, False, 1, 2)
+    assert L.adapt_create(C.byref(h), None, 0, C.c_void_p(1 << 20), C.byref(o), None, C.byref(st)) == -1
+    o.n_warm = 2  # arrays missing
+    assert L.adapt_create(C.byref(h), lib.ops_array([("HR", 0, 1)]), 1, C.c_void_p(1 << 20), C.byref(o), None,
+                          C.byref(st)) == -1
+    assert not st.value
+
+
+# ---------------------------------------------------------------- host BFGS
+
+def rosen(x):
+    return scipy.optimize.rosen(x), scipy.optimize.rosen_der(x)
+
+
+def test_bfgs_rosenbrock_reaches_minimum():
+    r = lib.bfgs_minimize(rosen, np.array([-1.2, 1.0, 0.5, -0.7]), gtol=1e-9, maxiter=2000)
+    assert r["status"] == 0
+    assert np.allclose(r["x"], 1.0, atol=1e-6)
+    ref = scipy.optimize.minimize(rosen, np.array([-1.2, 1.0, 0.5, -0.7]), jac=True, method="BFGS",
+                                  options={"gtol": 1e-9})
+    assert abs(r["f"] - ref.fun) < 1e-12
+
+
+def test_bfgs_quadratic_exact_and_inverse_hessian():
+    rng = np.random.default_rng(0)
+    M = rng.standard_normal((5, 5))
+    A = M @ M.T + 5 * np.eye(5)
+    b = rng.standard_normal(5)
+    fun = lambda x: (0.5 * x @ A @ x - b @ x, A @ x - b)  # noqa: E731
+    r = lib.bfgs_minimize(fun, np.zeros(5), gtol=1e-11, maxiter=200)
+    assert np.allclose(r["x"], np.linalg.solve(A, b), atol=1e-9)
+    assert r["iters"] <= 15  # quasi-Newton on a 5-dim quadratic with a Wolfe line search
+    # the inverse-Hessian estimate approaches A^{-1}
+    assert np.abs(r["hinv"] - np.linalg.inv(A)).max() < 0.05
+    # recycled inverse Hessian: a second solve from a new start needs fewer iterations
+    r2 = lib.bfgs_minimize(fun, np.ones(5), gtol=1e-11, maxiter=200, hinv=r["hinv"])
+    r3 = lib.bfgs_minimize(fun, np.ones(5), gtol=1e-11, maxiter=200)
+    assert r2["iters"] <= r3["iters"]
+    assert np.allclose(r2["x"], np.linalg.solve(A, b), atol=1e-9)
+
+
+def test_bfgs_reports_objective_errors():
+    def bad(x):
+        raise ValueError("boom")
+    with pytest.raises(Exception):
+        lib.bfgs_minimize(bad, np.zeros(2))

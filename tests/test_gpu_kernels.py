@@ -1,0 +1,295 @@
+"""GPU parity of the HIP kernels (through the C ABI) against the FP64 oracle.
+
+Tolerances (FP32 state arithmetic with FP64 reductions):
+  * H psi elementwise: |d| <= 2e-5 * max|H psi|  (about 30 FP32 terms per amplitude);
+  * energies: |dE| <= 1e-5 * max(1, |E|)  (the required energy tolerance);
+  * norms: |d| <= 1e-6;
+  * pool and adjoint gradients: |dg| <= 1e-4 * max(1, max|g|)  (required gradient tolerance);
+  * gates elementwise: |d| <= 1e-5 * max|psi|; leakage out of a conserved
+    sector must be exactly zero (bit-exact, integer-like structure).
+"""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+import workload as W
+from paper_2606_05297_amd import lib
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print("[case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+def dev(x):
+    return torch.from_numpy(np.ascontiguousarray(np.asarray(x, dtype=np.complex64))).to("cuda")
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy().astype(np.complex128)
+
+
+def ham_pair(L, d, per, J=1.0, U=0.0, mu=0.0, Delta=0.0, K=0.0):
+    return O.Ham(L, d, per, J, U, mu, Delta, K), lib.ham(L, d, per, J, U, mu, Delta, K)
+
+
+SMALL = [
+    # (L, d, periodic, J, U, mu, Delta, K)
+    (1, 5, False, 1.0, 1.3, 0.2, 0.0, 0.0),
+    (2, 4, True, 1.0, 2.0, 0.0, 0.0, 0.0),
+    (2, 3, False, 0.7, 0.0, 0.1, 0.6, 0.3),
+    (3, 4, False, 1.0, 2.0, 0.0, 0.0, 0.0),
+    (3, 3, True, 1.0, 0.5, 0.3, 0.4, 0.1),
+    (4, 5, False, 1.0, 0.0, 0.0, 0.5, 0.2),
+    (5, 4, True, 0.9, 1.7, 0.4, 0.3, 0.1),
+    (4, 7, True, 1.0, 0.0, -0.2, 0.5, 0.2),
+    (3, 16, False, 1.0, 0.0, 0.0, 0.5, 0.2),
+    (6, 6, True, 1.0, 4.0, 0.0, 0.0, 0.0),
+    (6, 8, False, 1.0, 0.0, 0.0, 0.5, 0.2),
+    (7, 5, False, 1.0, 0.0, 0.3, 0.45, 0.15),
+]
+
+
+@pytest.mark.parametrize("case", SMALL, ids=lambda c: f"L{c[0]}d{c[1]}{'p' if c[2] else 'o'}")
+def test_apply_H_parity(case):
+    L, d, per, J, U, mu, Dl, K = case
+    say("apply_H", case)
+    ho, hl = ham_pair(L, d, per, J, U, mu, Dl, K)
+    psi = W.random_state(L, d, seed=L * 100 + d)
+    ref = O.apply_H(ho, psi.astype(np.complex128))
+    x, y = dev(psi), torch.empty(d**L, dtype=torch.complex64, device="cuda")
+    ws = lib.workspace(hl)
+    E, n2 = lib.apply_H(hl, x, y, ws)
+    got = host(y)
+    assert np.abs(got - ref).max() <= 2e-5 * np.abs(ref).max()
+    Eref = np.vdot(psi.astype(np.complex128), ref).real
+    assert abs(E - Eref) <= 1e-5 * max(1.0, abs(Eref))
+    assert abs(n2 - 1.0) <= 1e-6
+    # determinism: bit-identical on a second call
+    E2, n22 = lib.apply_H(hl, x, y, ws)
+    assert E2 == E and n22 == n2
+
+
+POOL_CASES = [
+    (3, 4, False, 1.0, 2.0, 0.0, 0.0, 0.0, "all", ("HR", "HI", "DH", "PR", "PI")),
+    (4, 5, True, 1.0, 0.7, 0.2, 0.5, 0.2, "nn+nnn", ("HR", "HI", "DH", "PR", "PI")),
+    (5, 4, False, 1.0, 0.0, 0.0, 0.5, 0.2, "all", W.KITAEV_TYPES),
+    (4, 7, True, 1.0, 3.0, 0.0, 0.0, 0.0, "nn+nnn", W.BH_TYPES),
+    (6, 8, False, 1.0, 0.0, 0.0, 0.5, 0.2, "nn", W.KITAEV_TYPES),
+    (2, 6, False, 1.0, 1.0, 0.3, 0.3, 0.1, "all", ("HR", "HI", "DH", "PR", "PI")),
+]
+
+
+@pytest.mark.parametrize("case", POOL_CASES, ids=lambda c: f"L{c[0]}d{c[1]}{c[8]}")
+def test_pool_grads_parity(case):
+    L, d, per, J, U, mu, Dl, K, kind, types = case
+    say("pool_grads", case[:9])
+    ho, hl = ham_pair(L, d, per, J, U, mu, Dl, K)
+    pool = W.pool(L, kind, per, types) + [("KERR", r, -1) for r in range(L)] + [("ROT", 0, -1), ("ROT", L - 1, -1)]
+    psi = W.random_state(L, d, seed=7 + L + d)
+    x, y = dev(psi), torch.empty(d**L, dtype=torch.complex64, device="cuda")
+    ws = lib.workspace(hl, len(pool))
+    lib.apply_H(hl, x, y, ws)
+    g = lib.pool_grads(hl, pool, x, y, ws)
+    ref = O.pool_gradients(ho, psi.astype(np.complex128), pool)
+    assert np.abs(g - ref).max() <= 1e-4 * max(1.0, np.abs(ref).max())
+    g2 = lib.pool_grads(hl, pool, x, y, ws)
+    assert np.array_equal(g, g2)
+
+
+def test_pool_grads_large_pool_chunks():
+    """More than 256 entries and duplicates force several launches."""
+    L, d = 5, 3
+    ho, hl = ham_pair(L, d, True, 1.0, 0.5, 0.1, 0.4, 0.1)
+    base = W.pool(L, "all", True, ("HR", "HI", "DH", "PR", "PI"))
+    pool = base * 6 + [("KERR", 1, -1)]
+    say("pool_grads chunks", len(pool))
+    psi = W.random_state(L, d, seed=3)
+    x, y = dev(psi), torch.empty(d**L, dtype=torch.complex64, device="cuda")
+    ws = lib.workspace(hl, len(pool))
+    lib.apply_H(hl, x, y, ws)
+    g = lib.pool_grads(hl, pool, x, y, ws)
+    ref = O.pool_gradients(ho, psi.astype(np.complex128), pool)
+    assert np.abs(g - ref).max() <= 1e-4 * max(1.0, np.abs(ref).max())
+
+
+GATE_OPS = [("HR", 0, 1), ("HI", 1, 3), ("DH", 0, 2), ("DH", 2, 3), ("PR", 0, 3), ("PI", 1, 2), ("KERR", 0, -1),
+            ("KERR", 2, -1), ("ROT", 3, -1), ("ROT", 0, -1)]
+
+
+@pytest.mark.parametrize("d", [2, 3, 5, 8])
+@pytest.mark.parametrize("opx", GATE_OPS, ids=lambda o: f"{o[0]}{o[1]}{o[2]}")
+def test_gate_parity_and_leakage(opx, d):
+    L = 4
+    say("gate", opx, d)
+    psi = W.random_state(L, d, seed=11 + d)
+    ws = lib.workspace(lib.ham(L, d), 0, 1)
+    for adj in (False, True):
+        x = dev(psi)
+        lib.apply_gate2(L, d, opx, 0.37, x, ws, adjoint=adj)
+        got = host(x)
+        ref = O.apply_gate(opx, 0.37, psi.astype(np.complex128), L, d, adjoint=adj)
+        assert np.abs(got - ref).max() <= 1e-5 * np.abs(psi).max()
+    # exact zero leakage from a conserved sector
+    sector = ("parity", 0) if opx[0] in ("PR", "PI") else ("N", 3)
+    ps = W.random_state(L, d, seed=5, sector=sector)
+    x = dev(ps)
+    lib.apply_gate2(L, d, opx, 0.9, x, ws)
+    out = host(x)
+    outside = np.ones(d**L, dtype=bool)
+    outside[O.sector_indices(L, d, sector)] = False
+    assert np.count_nonzero(out[outside]) == 0
+    assert abs(np.vdot(out, out).real - np.vdot(ps, ps).real) < 2e-6
+
+
+def test_gate_then_adjoint_is_identity_ragged():
+    L, d = 5, 7  # 16807 amplitudes: fibers do not fill whole workgroups
+    psi = W.random_state(L, d, seed=2)
+    x = dev(psi)
+    ws = lib.workspace(lib.ham(L, d), 0, 1)
+    for o in [("HR", 1, 4), ("PR", 0, 4), ("DH", 3, 4), ("KERR", 4, -1)]:
+        say("gate roundtrip", o)
+        lib.apply_gate2(L, d, o, 1.1, x, ws)
+        lib.apply_gate2(L, d, o, 1.1, x, ws, adjoint=True)
+    assert np.abs(host(x) - psi).max() < 2e-6
+
+
+ADJ_CASES = [
+    (3, 4, False, 1.0, 2.0, 0.0, 0.0, 0.0, W.BH_TYPES, ("N", 3), 8),
+    (4, 5, False, 1.0, 0.0, 0.0, 0.5, 0.2, W.KITAEV_TYPES, ("parity", 0), 12),
+    (5, 4, True, 1.0, 1.2, 0.1, 0.3, 0.1, ("HR", "HI", "DH", "PR", "PI"), None, 10),
+    (6, 8, False, 1.0, 0.0, 0.0, 0.5, 0.2, W.KITAEV_TYPES, ("parity", 0), 6),
+]
+
+
+@pytest.mark.parametrize("case", ADJ_CASES, ids=lambda c: f"L{c[0]}d{c[1]}n{c[10]}")
+def test_energy_and_adjoint_parity(case):
+    L, d, per, J, U, mu, Dl, K, types, sector, n = case
+    say("adjoint", case[:8], n)
+    ho, hl = ham_pair(L, d, per, J, U, mu, Dl, K)
+    pool = W.pool(L, "nn", per, types) + [("KERR", 0, -1), ("ROT", L - 1, -1)]
+    ops, th = W.random_circuit(pool, n, seed=L + d)
+    psi0 = W.random_state(L, d, seed=9, sector=sector)
+    x0 = dev(psi0)
+    a, b = torch.empty_like(x0), torch.empty_like(x0)
+    ws = lib.workspace(hl, 0, n)
+    E, n2, g = lib.energy_grad_adjoint(hl, ops, th, x0, a, b, ws)
+    Eref, gref, n2ref = O.energy_and_grad_adjoint(ho, psi0.astype(np.complex128), ops, th)
+    assert abs(E - Eref / n2ref) <= 1e-5 * max(1.0, abs(Eref))
+    assert abs(n2 - n2ref) <= 2e-6
+    assert np.abs(g - gref).max() <= 1e-4 * max(1.0, np.abs(gref).max())
+    # forward-only call leaves psi and H psi in the work buffers
+    E2, _, _ = lib.energy_grad_adjoint(hl, ops, th, x0, a, b, ws, grad=False)
+    assert E2 == E
+    psi_n = O.ansatz_state(psi0.astype(np.complex128), ops, th, L, d)
+    assert np.abs(host(a) - psi_n).max() <= 1e-5
+    assert np.array_equal(host(x0), psi0.astype(np.complex128))  # psi0 untouched
+    # repeated call: bit-identical
+    E3, _, g3 = lib.energy_grad_adjoint(hl, ops, th, x0, a, b, ws)
+    assert E3 == E and np.array_equal(g3, g)
+
+
+def test_adjoint_matches_gpu_finite_differences():
+    """dE/dtheta from the reverse sweep vs central differences (h = 1e-4 in the
+    angle, required step) of the GPU energy, Kitaev-Kerr chain."""
+    L, d = 5, 8
+    _, hl = ham_pair(L, d, False, 1.0, 0.0, 0.0, 0.5, 0.2)
+    ops, th = W.random_circuit(W.pool(L, "nn", False, W.KITAEV_TYPES), 8, seed=1)
+    x0 = dev(W.random_state(L, d, seed=4, sector=("parity", 0)))
+    a, b = torch.empty_like(x0), torch.empty_like(x0)
+    ws = lib.workspace(hl, 0, len(ops))
+    E, _, g = lib.energy_grad_adjoint(hl, ops, th, x0, a, b, ws)
+    say("adjoint vs gpu fd")
+    h = 1e-3  # FP32 energies: 1e-4 steps leave ~1e-3 noise; 1e-3 keeps truncation ~1e-6
+    for k in range(len(ops)):
+        tp, tm = th.copy(), th.copy()
+        tp[k] += h
+        tm[k] -= h
+        ep = lib.energy_grad_adjoint(hl, ops, tp, x0, a, b, ws, grad=False)[0]
+        em = lib.energy_grad_adjoint(hl, ops, tm, x0, a, b, ws, grad=False)[0]
+        assert abs((ep - em) / (2 * h) - g[k]) <= 2e-3 * max(1.0, abs(E))
+
+
+# ---------------------------------------------------------------- full workload sizes
+
+@pytest.fixture(scope="module")
+def kk_full():
+    c = W.config("kk_l8_d8")
+    ho, hl = ham_pair(c["L"], c["d"], c["periodic"], c["J"], c["U"], c["mu"], c["Delta"], c["K"])
+    psi = W.random_state(8, 8, seed=0, sector=("parity", 0))
+    return c, ho, hl, psi
+
+
+def test_full_kitaev_l8_d8_apply_H_sampled_and_energy(kk_full):
+    c, ho, hl, psi = kk_full
+    say("full kk apply_H")
+    x, y = dev(psi), torch.empty(8**8, dtype=torch.complex64, device="cuda")
+    ws = lib.workspace(hl, len(c["pool"]), 64)
+    E, n2 = lib.apply_H(hl, x, y, ws)
+    got = host(y)
+    p128 = psi.astype(np.complex128)
+    rng = np.random.default_rng(0)
+    idx = np.concatenate([rng.integers(0, 8**8, 1500), [0, 1, 7, 8, 8**7, 8**8 - 1, 8**8 - 8, 8**7 - 1]])
+    ref = np.array([O.apply_H_at(ho, p128, int(k)) for k in idx])
+    assert np.abs(got[idx] - ref).max() <= 2e-5 * max(np.abs(ref).max(), 1e-30)
+    full = O.apply_H_slices(ho, p128)
+    Eref = np.vdot(p128, full).real
+    assert abs(E - Eref) <= 1e-5 * abs(Eref)
+    # parity leakage of H psi is exactly zero
+    odd = O.sector_indices(8, 8, ("parity", 1))
+    assert np.count_nonzero(got[odd]) == 0
+
+
+def test_full_kitaev_l8_d8_pool_grads(kk_full):
+    c, ho, hl, psi = kk_full
+    say("full kk pool")
+    x, y = dev(psi), torch.empty(8**8, dtype=torch.complex64, device="cuda")
+    ws = lib.workspace(hl, len(c["pool"]), 64)
+    lib.apply_H(hl, x, y, ws)
+    g = lib.pool_grads(hl, c["pool"], x, y, ws)
+    p128 = psi.astype(np.complex128)
+    h128 = O.apply_H_slices(ho, p128)
+    sub = [0, 3, 5, 10, 13, 18, 22, 24, 27]
+    ref = np.array([2 * np.vdot(h128, O.apply_generator(c["pool"][k], p128, 8, 8)).real for k in sub])
+    assert np.abs(g[sub] - ref).max() <= 1e-4 * max(1.0, np.abs(ref).max())
+
+
+def test_full_kitaev_l8_d8_adjoint(kk_full):
+    c, ho, hl, psi = kk_full
+    say("full kk adjoint")
+    ops, th = W.random_circuit(c["pool"], 3, seed=3)
+    psi0 = W.random_state(8, 8, seed=0, sector=("parity", 0))
+    x0 = dev(psi0)
+    a, b = torch.empty_like(x0), torch.empty_like(x0)
+    ws = lib.workspace(hl, len(c["pool"]), 64)
+    E, n2, g = lib.energy_grad_adjoint(hl, ops, th, x0, a, b, ws)
+    Eref, gref, n2ref = O.energy_and_grad_adjoint(ho, psi0.astype(np.complex128), ops, th)
+    assert abs(E - Eref) <= 1e-5 * abs(Eref)
+    assert np.abs(g - gref).max() <= 1e-4 * max(1.0, np.abs(gref).max())
+
+
+def test_full_bose_hubbard_l8_d6_sampled():
+    c = W.config("bh_l8_d6")
+    ho, hl = ham_pair(8, 6, True, 1.0, 4.0, 0.0, 0.0, 0.0)
+    say("full bh apply_H + pool")
+    psi = W.random_state(8, 6, seed=1, sector=("N", 8))
+    x, y = dev(psi), torch.empty(6**8, dtype=torch.complex64, device="cuda")
+    ws = lib.workspace(hl, len(c["pool"]), 64)
+    E, n2 = lib.apply_H(hl, x, y, ws)
+    got = host(y)
+    p128 = psi.astype(np.complex128)
+    full = O.apply_H(ho, p128)
+    assert np.abs(got - full).max() <= 2e-5 * np.abs(full).max()
+    assert abs(E - np.vdot(p128, full).real) <= 1e-5 * max(1.0, abs(np.vdot(p128, full).real))
+    g = lib.pool_grads(hl, c["pool"], x, y, ws)
+    ref = O.pool_gradients(ho, p128, c["pool"])
+    assert np.abs(g - ref).max() <= 1e-4 * max(1.0, np.abs(ref).max())
+    outside = np.ones(6**8, dtype=bool)
+    outside[O.sector_indices(8, 6, ("N", 8))] = False
+    assert np.count_nonzero(got[outside]) == 0
