@@ -138,6 +138,7 @@ typedef struct {
   double fd_step;         /* finite-difference step for grad_mode 1 */
   int32_t recycle_hessian;/* 1: seed each BFGS with the previous inverse Hessian (Appendix D) */
   int32_t reserved;
+  double noise_rel;       /* BFGS also stops once the predicted decrease < noise_rel*max(1,|E|) (FP32 noise) */
 } fock_adapt_opts_t;
 
 typedef struct {
@@ -156,7 +157,7 @@ typedef struct {
 typedef struct fock_adapt fock_adapt_t;
 
 /* Default options: max_iters 60, bfgs_maxiter 1000, grad_tol 1e-3,
- * tie_tau 1e-4, gtol_floor_rel 1e-5, warm_gtol 1e-6, fd_step 1e-3. */
+ * tie_tau 1e-4, gtol_floor_rel 1e-5, warm_gtol 1e-6, fd_step 1e-3, noise_rel 1e-7. */
 void adapt_default_opts(fock_adapt_opts_t *opts);
 
 /* Create an ADAPT run on `ham` with `pool` (P ops, host, copied) from the

@@ -23,6 +23,12 @@ SOURCES = [
     "kernels_h.hip",
     "kernels_pool.hip",
     "kernels_gate.hip",
+    "kernels_gate_da.hip",
+    "kernels_gate_db.hip",
+    "kernels_gate_dc.hip",
+    "kernels_gate_dd.hip",
+    "kernels_gate_de.hip",
+    "kernels_gate_df.hip",
     "host_common.cpp",
     "api.cpp",
     "adapt.cpp",

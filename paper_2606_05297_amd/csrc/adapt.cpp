@@ -85,7 +85,7 @@ int optimise(fock_adapt *st, double gtol, fock_adapt_report_t *rep) {
     H = &st->Hinv;
   }
   BfgsOut bo;
-  int rc = bfgs_minimize(st->theta, fn, gtol, st->opt.bfgs_maxiter, H, &bo);
+  int rc = bfgs_minimize(st->theta, fn, gtol, st->opt.bfgs_maxiter, H, &bo, st->opt.noise_rel);
   if (rc) return rc;
   double E = 0.0, n2 = 0.0;
   rc = eval_energy(st, st->theta, &E, &n2, nullptr);
@@ -119,6 +119,7 @@ void adapt_default_opts(fock_adapt_opts_t *o) {
   o->gtol_floor_rel = 1e-5;
   o->warm_gtol = 1e-6;
   o->fd_step = 1e-3;
+  o->noise_rel = 1e-7;
 }
 
 int adapt_create(const fock_ham_t *ham, const fock_op_t *pool, int P, const void *psi0, const fock_adapt_opts_t *opts,
@@ -154,7 +155,7 @@ int adapt_create(const fock_ham_t *ham, const fock_op_t *pool, int P, const void
     st->theta.push_back(opts->warm_theta0[k]);
   }
   const int nmax = opts->n_warm + opts->max_iters + 1;
-  const Layout L = make_layout(namp, ham->d, P, nmax);
+  const Layout L = make_layout(namp, ham->L, ham->d, P, nmax);
   const size_t sbytes = (sizeof(float2) * (size_t)namp + 255) & ~(size_t)255;
   st->ws_bytes = L.total;
   if (hipMalloc(&st->dbuf, 3 * sbytes + st->ws_bytes) != hipSuccess) {

@@ -106,10 +106,15 @@ static thread_local Pinned tl_in, tl_out;
 // ---------------------------------------------------------------- workspace layout
 static size_t al(size_t x) { return (x + 255) & ~(size_t)255; }
 
-Layout make_layout(uint32_t namp, int d, int P, int n) {
+Layout make_layout(uint32_t namp, int Lm, int d, int P, int n) {
   Layout L;
   const uint32_t nrows = namp / (uint32_t)d;
   L.G = (int)((nrows + kBlock - 1) / kBlock);
+  L.rs = L.G;
+  if (Lm >= 2) {
+    const Geometry g{Lm, d, namp};
+    L.rs = std::max(L.G, gate_blocks_max(g));
+  }
   L.nmax = std::max(n, 1);
   L.pmax = std::min(std::max(P, 1), kMaxSlots);
   size_t o = 0;
@@ -121,7 +126,7 @@ Layout make_layout(uint32_t namp, int d, int P, int n) {
   o = al(o + sizeof(float2) * (size_t)gate_stride(d) * L.nmax);
   L.partial = o;
   const size_t rows = std::max<size_t>({2, (size_t)L.nmax, (size_t)L.pmax});
-  o = al(o + sizeof(double) * rows * L.G);
+  o = al(o + sizeof(double) * rows * std::max(L.G, L.rs));
   L.result = o;
   o = al(o + sizeof(double) * (2 + std::max(L.nmax, std::max(P, 1))));
   L.pairs = o;
@@ -139,7 +144,7 @@ int make_ctx(const fock_ham_t &ham, uint32_t namp, int P, int n, void *ws, size_
   c->h = make_ham_args(ham);
   c->s = s;
   c->ws = (char *)ws;
-  c->L = make_layout(namp, ham.d, P, n);
+  c->L = make_layout(namp, ham.L, ham.d, P, n);
   if (!ws) return set_error(FOCK_ERR_ARG, "workspace is NULL");
   if (((uintptr_t)ws) & 255) return set_error(FOCK_ERR_ARG, "workspace must be 256-byte aligned");
   if (ws_bytes < c->L.total)
@@ -159,13 +164,13 @@ int stage_gates(Ctx &c, const fock_op_t *ops, const double *theta, int n) {
   char *hp = (char *)tl_in.p;
   double *th = (double *)(hp + c.L.theta);
   GateRec *rec = (GateRec *)(hp + c.L.recs);
-  const int Gd = diag_blocks_count(c.g), Gg = gate_blocks_count(c.g);
+  const int Gd = diag_blocks_count(c.g);
   for (int k = 0; k < n; ++k) {
     if (!std::isfinite(theta[k])) return set_error(FOCK_ERR_NONFINITE, "theta[%d] is not finite", k);
     th[k] = theta[k];
     rec[k].type = ops[k].type;
     rec[k].u_off = k * stride;
-    rec[k].nblk = is_single_mode(ops[k].type) ? Gd : Gg;
+    rec[k].nblk = is_single_mode(ops[k].type) ? Gd : gate_blocks_count(c.g, ops[k].i);
     rec[k].pad = 0;
   }
   (void)bt;
@@ -226,13 +231,13 @@ int run_circuit(Ctx &c, const fock_op_t *ops, const double *theta, int n, const 
     for (int k = n - 1; k >= 0; --k) {
       const fock_op_t &op = ops[k];
       const float2 *U = U0 + (size_t)k * stride;
-      double *pk = part + (size_t)k * c.L.G;
+      double *pk = part + (size_t)k * c.L.rs;
       ProfScope ps(is_single_mode(op.type) ? FOCK_K_DIAG : FOCK_K_ADJ, c.s, 32.0 * c.g.n_amp);
       if (is_single_mode(op.type)) rc = launch_diag_adj(c.g, op.i, op.type, U, phi, lam, pk, c.s);
       else rc = launch_gate_adj(c.g, op.i, op.j, gate_kind(op.type), U, c.T.A[op.type], phi, lam, pk, c.s);
       if (rc) return rc;
     }
-    rc = launch_reduce_rows(part, c.L.G, (const GateRec *)(c.ws + c.L.recs), n, res + 2, c.s);
+    rc = launch_reduce_rows(part, c.L.rs, (const GateRec *)(c.ws + c.L.recs), n, res + 2, c.s);
     if (rc) return rc;
   }
   const int cnt = 2 + ((grad && n > 0) ? n : 0);
@@ -337,7 +342,7 @@ int fock_workspace_bytes(const fock_ham_t *ham, int n_pool, int n_ops, size_t *b
   if (!bytes) return set_error(FOCK_ERR_ARG, "bytes is NULL");
   if (n_pool < 0 || n_pool > 4096 || n_ops < 0 || n_ops > 4096)
     return set_error(FOCK_ERR_ARG, "n_pool/n_ops out of range");
-  *bytes = make_layout(namp, ham->d, n_pool, n_ops).total;
+  *bytes = make_layout(namp, ham->L, ham->d, n_pool, n_ops).total;
   return FOCK_OK;
 }
 

@@ -46,7 +46,7 @@ struct LsPoint {
 }  // namespace
 
 int bfgs_minimize(std::vector<double> &x, const ObjFn &fn, double gtol, int maxiter, std::vector<double> *Hinv,
-                  BfgsOut *out) {
+                  BfgsOut *out, double noise_rel) {
   const int n = (int)x.size();
   BfgsOut o;
   std::vector<double> g(n), xn(n), gn(n), p(n), s(n), y(n), Hy(n);
@@ -82,6 +82,10 @@ int bfgs_minimize(std::vector<double> &x, const ObjFn &fn, double gtol, int maxi
       dphi0 = dot(g, p);
       scaled = false;
     }
+    if (noise_rel > 0.0 && -0.5 * dphi0 < noise_rel * std::max(1.0, std::fabs(f))) {
+      o.noise_stop = 1;
+      break;
+    }
     // initial trial step (as in SciPy: from the previous decrease, at most 1)
     double a1 = 1.0;
     if (dphi0 != 0.0) a1 = std::min(1.0, 1.01 * 2.0 * (f - f_prev) / dphi0);
@@ -105,7 +109,7 @@ int bfgs_minimize(std::vector<double> &x, const ObjFn &fn, double gtol, int maxi
     LsPoint prev{0.0, f, dphi0, g}, cur, acc;
     bool found = false, fail = false;
     double a = a1;
-    const int max_ls = 30;
+    const int max_ls = 20;
     for (int k = 0; k < max_ls && !found && !fail; ++k) {
       rc = phi(a, &cur);
       if (rc) return rc;

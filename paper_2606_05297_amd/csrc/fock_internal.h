@@ -143,7 +143,8 @@ int launch_gate(const Geometry &g, int i, int j, int kind, bool dag, const float
 // phi <- U^+ phi, lam <- U^+ lam.
 int launch_gate_adj(const Geometry &g, int i, int j, int kind, const float2 *U, const float2 *A, float2 *phi,
                     float2 *lam, double *partial, hipStream_t s);
-int gate_blocks_count(const Geometry &g);
+int gate_blocks_count(const Geometry &g, int i);  // workgroups of a gate on (i, j)
+int gate_blocks_max(const Geometry &g);
 // Single-mode diagonal gate with device phase table ph[d].
 int launch_diag(const Geometry &g, int r, int type, bool dag, const float2 *ph, float2 *psi, hipStream_t s);
 int launch_diag_adj(const Geometry &g, int r, int type, const float2 *ph, float2 *phi, float2 *lam,

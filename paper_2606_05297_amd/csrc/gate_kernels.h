@@ -1,0 +1,491 @@
+// Gate kernels (templated on the cutoff d); instantiated per d in the
+// kernels_gate_d*.hip translation units so they compile in parallel.
+#pragma once
+
+#include "device_common.h"
+
+namespace fock {
+
+struct GateLaunch {
+  uint32_t nfib, si, sj;
+  FastDiv dsi, dm1;
+};
+
+__device__ __forceinline__ uint32_t fiber_base(uint32_t f, const GateLaunch &g, int D) {
+  const uint32_t t = fdiv(f, g.dsi);
+  const uint32_t low = f - t * g.si;
+  const uint32_t high = fdiv(t, g.dm1);
+  const uint32_t mid = t - high * g.dm1.v;
+  return low + mid * g.si * (uint32_t)D + high * g.sj * (uint32_t)D;
+}
+
+__device__ __forceinline__ void cmac(float2 &o, float2 u, float2 v) {
+  o.x = fmaf(u.x, v.x, fmaf(-u.y, v.y, o.x));
+  o.y = fmaf(u.x, v.y, fmaf(u.y, v.x, o.y));
+}
+// o += conj(u) * v
+__device__ __forceinline__ void cmac_conj(float2 &o, float2 u, float2 v) {
+  o.x = fmaf(u.x, v.x, fmaf(u.y, v.y, o.x));
+  o.y = fmaf(u.x, v.y, fmaf(-u.y, v.x, o.y));
+}
+
+// ---------------------------------------------------------------- block groups
+// The 2d-1 conserved blocks of a fiber are split into NG groups of nearly
+// equal size (greedy, largest block first).  One wavefront handles one group
+// for 64 fibers, so every lane of a wave runs the same compile-time block
+// code (no divergence) and the gate matrix entries are wave-uniform.
+template <int D, int NG>
+struct Groups {
+  static constexpr int NB = 2 * D - 1;
+  int grp[NB];
+  int size[NG];
+  constexpr Groups() : grp(), size() {
+    for (int k = 0; k < NB; ++k) grp[k] = 0;
+    for (int g = 0; g < NG; ++g) size[g] = 0;
+    // blocks in order of decreasing size: s = D-1, D-2, D, D-3, D+1, ...
+    for (int k = 0; k < NB; ++k) {
+      const int s = (k == 0) ? D - 1 : ((k & 1) ? D - 1 - (k + 1) / 2 : D - 1 + k / 2);
+      const int b = (s < D - 1 ? s : 2 * D - 2 - s) + 1;
+      int best = 0;
+      for (int g = 1; g < NG; ++g)
+        if (size[g] < size[best]) best = g;
+      grp[s] = best;
+      size[best] += b;
+    }
+  }
+};
+
+template <int D>
+constexpr int direct_groups() { return D <= 3 ? 1 : (D <= 6 ? 2 : 4); }
+
+template <int D, int KIND>
+__device__ __forceinline__ uint32_t member_off(int s, int a, uint32_t si, uint32_t sj) {
+  return (uint32_t)a * si + (uint32_t)blk_nj(KIND, D, s, a) * sj;
+}
+
+// Apply U (or U^+) to the members of group G of one fiber.  ld/st address the
+// member (s, a): global memory (direct) or an LDS tile (mode-0 pairs).
+template <int D, int KIND, bool DAG, int NG, int G, class Ptr>
+__device__ __forceinline__ void gate_group_blockwise(Ptr base, uint32_t si, uint32_t sj, const float2 *__restrict__ U) {
+  constexpr Groups<D, NG> P{};
+  int off = 0;
+#pragma unroll
+  for (int s = 0; s < 2 * D - 1; ++s) {
+    const int lo = blk_lo(KIND, D, s), b = blk_hi(KIND, D, s) - lo + 1;
+    if (P.grp[s] == G) {
+      float2 v[D];
+#pragma unroll
+      for (int q = 0; q < D; ++q)
+        if (q < b) v[q] = base[member_off<D, KIND>(s, lo + q, si, sj)];
+#pragma unroll
+      for (int p = 0; p < D; ++p)
+        if (p < b) {
+          float2 o = make_float2(0.f, 0.f);
+#pragma unroll
+          for (int q = 0; q < D; ++q)
+            if (q < b) {
+              if (DAG) cmac_conj(o, U[off + q * b + p], v[q]);
+              else cmac(o, U[off + p * b + q], v[q]);
+            }
+          base[member_off<D, KIND>(s, lo + p, si, sj)] = o;
+        }
+    }
+    off += b * b;
+  }
+}
+
+template <int D, int KIND, bool DAG, int NG, int G, class Ptr>
+__device__ __forceinline__ void gate_group(Ptr base, uint32_t si, uint32_t sj, const float2 *__restrict__ U) {
+  if constexpr (D > 8) {
+    gate_group_blockwise<D, KIND, DAG, NG, G>(base, si, sj, U);
+    return;
+  }
+  constexpr Groups<D, NG> P{};
+  float2 v[D * D];
+  int m = 0;
+#pragma unroll
+  for (int s = 0; s < 2 * D - 1; ++s)
+    if (P.grp[s] == G) {
+      const int lo = blk_lo(KIND, D, s), b = blk_hi(KIND, D, s) - lo + 1;
+#pragma unroll
+      for (int q = 0; q < D; ++q)
+        if (q < b) v[m + q] = base[member_off<D, KIND>(s, lo + q, si, sj)];
+      m += b;
+    }
+  m = 0;
+  int off = 0;
+#pragma unroll
+  for (int s = 0; s < 2 * D - 1; ++s) {
+    const int lo = blk_lo(KIND, D, s), b = blk_hi(KIND, D, s) - lo + 1;
+    if (P.grp[s] == G) {
+#pragma unroll
+      for (int p = 0; p < D; ++p)
+        if (p < b) {
+          float2 o = make_float2(0.f, 0.f);
+#pragma unroll
+          for (int q = 0; q < D; ++q)
+            if (q < b) {
+              if (DAG) cmac_conj(o, U[off + q * b + p], v[m + q]);
+              else cmac(o, U[off + p * b + q], v[m + q]);
+            }
+          base[member_off<D, KIND>(s, lo + p, si, sj)] = o;
+        }
+      m += b;
+    }
+    off += b * b;
+  }
+}
+
+// Fused reverse step on group G: returns sum Re(conj(lam) A phi) over the
+// group's members, then phi <- U^+ phi, lam <- U^+ lam.  A's blocks are
+// tridiagonal in the member order (the generators move n_i by one).
+template <int D, int KIND, int NG, int G, class Ptr>
+__device__ __forceinline__ float adj_group_blockwise(Ptr pb, Ptr lb, uint32_t si, uint32_t sj,
+                                                     const float2 *__restrict__ U, const float2 *__restrict__ A) {
+  constexpr Groups<D, NG> P{};
+  float gacc = 0.f;
+  int off = 0;
+#pragma unroll
+  for (int s = 0; s < 2 * D - 1; ++s) {
+    const int lo = blk_lo(KIND, D, s), b = blk_hi(KIND, D, s) - lo + 1;
+    if (P.grp[s] == G) {
+      float2 pv[D], lv[D];
+#pragma unroll
+      for (int q = 0; q < D; ++q)
+        if (q < b) {
+          const uint32_t o = member_off<D, KIND>(s, lo + q, si, sj);
+          pv[q] = pb[o];
+          lv[q] = lb[o];
+        }
+#pragma unroll
+      for (int p = 0; p < D; ++p)
+        if (p < b) {
+          float2 ap = make_float2(0.f, 0.f);
+#pragma unroll
+          for (int q = 0; q < D; ++q)
+            if (q < b && q >= p - 1 && q <= p + 1) cmac(ap, A[off + p * b + q], pv[q]);
+          gacc = fmaf(lv[p].x, ap.x, fmaf(lv[p].y, ap.y, gacc));
+        }
+#pragma unroll
+      for (int p = 0; p < D; ++p)
+        if (p < b) {
+          float2 np = make_float2(0.f, 0.f), nl = make_float2(0.f, 0.f);
+#pragma unroll
+          for (int q = 0; q < D; ++q)
+            if (q < b) {
+              const float2 u = U[off + q * b + p];
+              cmac_conj(np, u, pv[q]);
+              cmac_conj(nl, u, lv[q]);
+            }
+          const uint32_t o = member_off<D, KIND>(s, lo + p, si, sj);
+          pb[o] = np;
+          lb[o] = nl;
+        }
+    }
+    off += b * b;
+  }
+  return gacc;
+}
+
+template <int D, int KIND, int NG, int G, class Ptr>
+__device__ __forceinline__ float adj_group(Ptr pb, Ptr lb, uint32_t si, uint32_t sj, const float2 *__restrict__ U,
+                                           const float2 *__restrict__ A) {
+  if constexpr (D > 8) return adj_group_blockwise<D, KIND, NG, G>(pb, lb, si, sj, U, A);
+  constexpr Groups<D, NG> P{};
+  float2 pv[D * D], lv[D * D];
+  int m = 0;
+#pragma unroll
+  for (int s = 0; s < 2 * D - 1; ++s)
+    if (P.grp[s] == G) {
+      const int lo = blk_lo(KIND, D, s), b = blk_hi(KIND, D, s) - lo + 1;
+#pragma unroll
+      for (int q = 0; q < D; ++q)
+        if (q < b) {
+          const uint32_t o = member_off<D, KIND>(s, lo + q, si, sj);
+          pv[m + q] = pb[o];
+          lv[m + q] = lb[o];
+        }
+      m += b;
+    }
+  float gacc = 0.f;
+  m = 0;
+  int off = 0;
+#pragma unroll
+  for (int s = 0; s < 2 * D - 1; ++s) {
+    const int lo = blk_lo(KIND, D, s), b = blk_hi(KIND, D, s) - lo + 1;
+    if (P.grp[s] == G) {
+#pragma unroll
+      for (int p = 0; p < D; ++p)
+        if (p < b) {
+          float2 ap = make_float2(0.f, 0.f);
+#pragma unroll
+          for (int q = 0; q < D; ++q)
+            if (q < b && q >= p - 1 && q <= p + 1) cmac(ap, A[off + p * b + q], pv[m + q]);
+          gacc = fmaf(lv[m + p].x, ap.x, fmaf(lv[m + p].y, ap.y, gacc));
+        }
+#pragma unroll
+      for (int p = 0; p < D; ++p)
+        if (p < b) {
+          float2 np = make_float2(0.f, 0.f), nl = make_float2(0.f, 0.f);
+#pragma unroll
+          for (int q = 0; q < D; ++q)
+            if (q < b) {
+              const float2 u = U[off + q * b + p];
+              cmac_conj(np, u, pv[m + q]);
+              cmac_conj(nl, u, lv[m + q]);
+            }
+          const uint32_t o = member_off<D, KIND>(s, lo + p, si, sj);
+          pb[o] = np;
+          lb[o] = nl;
+        }
+      m += b;
+    }
+    off += b * b;
+  }
+  return gacc;
+}
+
+// ---------------------------------------------------------------- pairs (i, j) with i >= 1
+// Consecutive lanes own fibers that differ in the lowest free mode (mode 0),
+// so each member access of a wavefront is one contiguous 512-byte run.
+template <int D, int KIND, bool DAG>
+__global__ __launch_bounds__(kBlock) void k_gate2(float2 *__restrict__ psi, const float2 *__restrict__ U, GateLaunch g) {
+  constexpr int NG = direct_groups<D>();
+  constexpr int FPB = 64 * (4 / NG);
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int gi = wave % NG;
+  const uint32_t f = (uint32_t)xcd_remap(blockIdx.x, gridDim.x) * FPB + (uint32_t)(wave / NG) * 64 + lane;
+  if (f >= g.nfib) return;
+  float2 *base = psi + fiber_base(f, g, D);
+  switch (gi) {
+    case 0: gate_group<D, KIND, DAG, NG, 0>(base, g.si, g.sj, U); break;
+    case 1: if constexpr (NG > 1) gate_group<D, KIND, DAG, NG, 1>(base, g.si, g.sj, U); break;
+    case 2: if constexpr (NG > 2) gate_group<D, KIND, DAG, NG, 2>(base, g.si, g.sj, U); break;
+    default: if constexpr (NG > 3) gate_group<D, KIND, DAG, NG, 3>(base, g.si, g.sj, U); break;
+  }
+}
+
+template <int D, int KIND>
+__global__ __launch_bounds__(kBlock) void k_gate2_adj(float2 *__restrict__ phi, float2 *__restrict__ lam,
+                                                      const float2 *__restrict__ U, const float2 *__restrict__ A,
+                                                      double *__restrict__ partial, GateLaunch g) {
+  __shared__ double red[4];
+  constexpr int NG = direct_groups<D>();
+  constexpr int FPB = 64 * (4 / NG);
+  const int vb = xcd_remap(blockIdx.x, gridDim.x);
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int gi = wave % NG;
+  const uint32_t f = (uint32_t)vb * FPB + (uint32_t)(wave / NG) * 64 + lane;
+  float gacc = 0.f;
+  if (f < g.nfib) {
+    const uint32_t fb = fiber_base(f, g, D);
+    float2 *pb = phi + fb, *lb = lam + fb;
+    switch (gi) {
+      case 0: gacc = adj_group<D, KIND, NG, 0>(pb, lb, g.si, g.sj, U, A); break;
+      case 1: if constexpr (NG > 1) gacc = adj_group<D, KIND, NG, 1>(pb, lb, g.si, g.sj, U, A); break;
+      case 2: if constexpr (NG > 2) gacc = adj_group<D, KIND, NG, 2>(pb, lb, g.si, g.sj, U, A); break;
+      default: if constexpr (NG > 3) gacc = adj_group<D, KIND, NG, 3>(pb, lb, g.si, g.sj, U, A); break;
+    }
+  }
+  const double sg = block_sum_d((double)gacc, red);
+  if (threadIdx.x == 0) partial[vb] = sg;
+}
+
+// ---------------------------------------------------------------- pairs (0, j): LDS-staged
+// Mode 0 is the contiguous one, so a fiber's members are runs of d amplitudes
+// and thread-per-fiber access would scatter a wavefront over 64 runs.  The
+// workgroup instead copies FL fibers into LDS with contiguous global accesses
+// (lanes run along n_0, then along consecutive fibers), the four waves apply
+// the four block groups from LDS, and the tile is copied back.
+template <int D>
+constexpr int lds_fibers() { return D * D <= 64 ? 64 : 16; }
+
+template <int D>
+__device__ __forceinline__ void tile_copy(float2 *tile, float2 *__restrict__ gmem, const uint32_t *fbase, uint32_t sj,
+                                          bool to_lds, uint32_t nf) {
+  constexpr int FL = lds_fibers<D>(), ST = D * D + 1;
+  for (int e = threadIdx.x; e < FL * D * D; e += kBlock) {
+    const int b = e / (FL * D), r = e % (FL * D);
+    const int fl = r / D, a = r % D;
+    if ((uint32_t)fl < nf) {
+      const uint32_t gi = fbase[fl] + (uint32_t)a + (uint32_t)b * sj;
+      if (to_lds) tile[fl * ST + b * D + a] = gmem[gi];
+      else gmem[gi] = tile[fl * ST + b * D + a];
+    }
+  }
+}
+
+template <int D, int KIND, bool DAG>
+__global__ __launch_bounds__(kBlock) void k_gate2_m0(float2 *__restrict__ psi, const float2 *__restrict__ U, GateLaunch g) {
+  constexpr int FL = lds_fibers<D>(), ST = D * D + 1;
+  __shared__ float2 tile[FL * ST];
+  __shared__ uint32_t fbase[FL];
+  const uint32_t f0 = (uint32_t)xcd_remap(blockIdx.x, gridDim.x) * FL;
+  const uint32_t nf = g.nfib - f0 < (uint32_t)FL ? g.nfib - f0 : (uint32_t)FL;
+  if (threadIdx.x < FL && threadIdx.x < nf) fbase[threadIdx.x] = fiber_base(f0 + threadIdx.x, g, D);
+  __syncthreads();
+  tile_copy<D>(tile, psi, fbase, g.sj, true, nf);
+  __syncthreads();
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  if ((uint32_t)lane < nf && lane < FL) {
+    float2 *base = tile + lane * ST;
+    // member (n_0 = a, n_j = b) sits at b * D + a in the fiber's LDS row
+    switch (wave) {
+      case 0: gate_group<D, KIND, DAG, 4, 0>(base, 1u, (uint32_t)D, U); break;
+      case 1: gate_group<D, KIND, DAG, 4, 1>(base, 1u, (uint32_t)D, U); break;
+      case 2: gate_group<D, KIND, DAG, 4, 2>(base, 1u, (uint32_t)D, U); break;
+      default: gate_group<D, KIND, DAG, 4, 3>(base, 1u, (uint32_t)D, U); break;
+    }
+  }
+  __syncthreads();
+  tile_copy<D>(tile, psi, fbase, g.sj, false, nf);
+}
+
+template <int D, int KIND>
+__global__ __launch_bounds__(kBlock) void k_gate2_adj_m0(float2 *__restrict__ phi, float2 *__restrict__ lam,
+                                                         const float2 *__restrict__ U, const float2 *__restrict__ A,
+                                                         double *__restrict__ partial, GateLaunch g) {
+  constexpr int FL = lds_fibers<D>(), ST = D * D + 1;
+  __shared__ float2 tp[FL * ST], tl[FL * ST];
+  __shared__ uint32_t fbase[FL];
+  __shared__ double red[4];
+  const int vb = xcd_remap(blockIdx.x, gridDim.x);
+  const uint32_t f0 = (uint32_t)vb * FL;
+  const uint32_t nf = g.nfib - f0 < (uint32_t)FL ? g.nfib - f0 : (uint32_t)FL;
+  if (threadIdx.x < FL && threadIdx.x < nf) fbase[threadIdx.x] = fiber_base(f0 + threadIdx.x, g, D);
+  __syncthreads();
+  tile_copy<D>(tp, phi, fbase, g.sj, true, nf);
+  tile_copy<D>(tl, lam, fbase, g.sj, true, nf);
+  __syncthreads();
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  float gacc = 0.f;
+  if ((uint32_t)lane < nf && lane < FL) {
+    float2 *pb = tp + lane * ST, *lb = tl + lane * ST;
+    switch (wave) {
+      case 0: gacc = adj_group<D, KIND, 4, 0>(pb, lb, 1u, (uint32_t)D, U, A); break;
+      case 1: gacc = adj_group<D, KIND, 4, 1>(pb, lb, 1u, (uint32_t)D, U, A); break;
+      case 2: gacc = adj_group<D, KIND, 4, 2>(pb, lb, 1u, (uint32_t)D, U, A); break;
+      default: gacc = adj_group<D, KIND, 4, 3>(pb, lb, 1u, (uint32_t)D, U, A); break;
+    }
+  }
+  __syncthreads();
+  tile_copy<D>(tp, phi, fbase, g.sj, false, nf);
+  tile_copy<D>(tl, lam, fbase, g.sj, false, nf);
+  const double sg = block_sum_d((double)gacc, red);
+  if (threadIdx.x == 0) partial[vb] = sg;
+}
+
+// ---------------------------------------------------------------- single-mode diagonal gates
+// O = exp(theta A) with A = i f(N_r) is diag(exp(i theta f(n_r))); f = n^2 (KERR) or n (ROT).
+struct DiagLaunch {
+  int nrows, r, kerr;
+  FastDiv dsr;  // divide a row index by d^(r-1) (r >= 1)
+};
+
+template <int D, bool DAG>
+__global__ __launch_bounds__(kBlock) void k_diag(float2 *__restrict__ psi, const float2 *__restrict__ phg, DiagLaunch a) {
+  __shared__ float2 ph[kMaxD];
+  if (threadIdx.x < D) {
+    const float2 p = phg[threadIdx.x];
+    ph[threadIdx.x] = DAG ? make_float2(p.x, -p.y) : p;
+  }
+  __syncthreads();
+  const int row = xcd_remap(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+  if (row >= a.nrows) return;
+  float2 v[D];
+  load_row<D>(psi + (size_t)row * D, v);
+  const int n = a.r == 0 ? 0 : (int)(fdiv((uint32_t)row, a.dsr) % D);
+#pragma unroll
+  for (int q = 0; q < D; ++q) {
+    const float2 p = ph[a.r == 0 ? q : n];
+    float2 o = make_float2(0.f, 0.f);
+    cmac(o, p, v[q]);
+    v[q] = o;
+  }
+  store_row<D>(psi + (size_t)row * D, v);
+}
+
+template <int D>
+__global__ __launch_bounds__(kBlock) void k_diag_adj(float2 *__restrict__ phi, float2 *__restrict__ lam,
+                                                     const float2 *__restrict__ phg, double *__restrict__ partial,
+                                                     DiagLaunch a) {
+  __shared__ float2 ph[kMaxD];
+  __shared__ double red[4];
+  if (threadIdx.x < D) ph[threadIdx.x] = phg[threadIdx.x];
+  __syncthreads();
+  const int vb = xcd_remap(blockIdx.x, gridDim.x);
+  const int row = vb * kBlock + threadIdx.x;
+  float gacc = 0.f;
+  if (row < a.nrows) {
+    float2 pv[D], lv[D];
+    load_row<D>(phi + (size_t)row * D, pv);
+    load_row<D>(lam + (size_t)row * D, lv);
+    const int n = a.r == 0 ? 0 : (int)(fdiv((uint32_t)row, a.dsr) % D);
+#pragma unroll
+    for (int q = 0; q < D; ++q) {
+      const int lev = a.r == 0 ? q : n;
+      const float f = a.kerr ? (float)(lev * lev) : (float)lev;
+      // Re(conj(lam) * i f phi) = -f Im(conj(lam) phi)
+      gacc = fmaf(-f, lv[q].x * pv[q].y - lv[q].y * pv[q].x, gacc);
+      const float2 p = ph[lev];
+      float2 np = make_float2(0.f, 0.f), nl = make_float2(0.f, 0.f);
+      cmac_conj(np, p, pv[q]);
+      cmac_conj(nl, p, lv[q]);
+      pv[q] = np;
+      lv[q] = nl;
+    }
+    store_row<D>(phi + (size_t)row * D, pv);
+    store_row<D>(lam + (size_t)row * D, lv);
+  }
+  const double sg = block_sum_d((double)gacc, red);
+  if (threadIdx.x == 0) partial[vb] = sg;
+}
+
+
+template <int D>
+constexpr int lds_fibers_d() { return lds_fibers<D>(); }
+
+template <int D>
+int fibers_per_block_d(int i) { return i == 0 ? lds_fibers<D>() : 64 * (4 / direct_groups<D>()); }
+
+template <int D>
+void gate_launch_d(const GateLaunch &gl, int i, int kind, bool dag, const float2 *U, float2 *psi, int G,
+                   hipStream_t s) {
+#define GATE_K(KN, K, DG) hipLaunchKernelGGL((KN<D, K, DG>), dim3(G), dim3(kBlock), 0, s, psi, U, gl)
+#define GATE_SEL(KN)                                                         \
+  if (kind == KIND_SUM) {                                                    \
+    if (dag) GATE_K(KN, KIND_SUM, true); else GATE_K(KN, KIND_SUM, false);   \
+  } else {                                                                   \
+    if (dag) GATE_K(KN, KIND_DIFF, true); else GATE_K(KN, KIND_DIFF, false); \
+  }
+  if (i == 0) { GATE_SEL(k_gate2_m0); } else { GATE_SEL(k_gate2); }
+#undef GATE_SEL
+#undef GATE_K
+}
+
+template <int D>
+void adj_launch_d(const GateLaunch &gl, int i, int kind, const float2 *U, const float2 *A, float2 *phi, float2 *lam,
+                  double *partial, int G, hipStream_t s) {
+#define ADJ_K(KN, K) hipLaunchKernelGGL((KN<D, K>), dim3(G), dim3(kBlock), 0, s, phi, lam, U, A, partial, gl)
+  if (i == 0) {
+    if (kind == KIND_SUM) ADJ_K(k_gate2_adj_m0, KIND_SUM); else ADJ_K(k_gate2_adj_m0, KIND_DIFF);
+  } else {
+    if (kind == KIND_SUM) ADJ_K(k_gate2_adj, KIND_SUM); else ADJ_K(k_gate2_adj, KIND_DIFF);
+  }
+#undef ADJ_K
+}
+
+#define FOCK_GATE_INSTANTIATE(D)                                                                             \
+  template int fibers_per_block_d<D>(int);                                                                 \
+  template void gate_launch_d<D>(const GateLaunch &, int, int, bool, const float2 *, float2 *, int,        \
+                                 hipStream_t);                                                             \
+  template void adj_launch_d<D>(const GateLaunch &, int, int, const float2 *, const float2 *, float2 *,    \
+                                float2 *, double *, int, hipStream_t);
+#define FOCK_GATE_EXTERN(D)                                                                                  \
+  extern template int fibers_per_block_d<D>(int);                                                          \
+  extern template void gate_launch_d<D>(const GateLaunch &, int, int, bool, const float2 *, float2 *, int, \
+                                        hipStream_t);                                                      \
+  extern template void adj_launch_d<D>(const GateLaunch &, int, int, const float2 *, const float2 *,       \
+                                       float2 *, float2 *, double *, int, hipStream_t);
+
+}  // namespace fock

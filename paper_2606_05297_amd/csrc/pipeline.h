@@ -8,6 +8,7 @@ namespace fock {
 struct Layout {
   size_t theta = 0, recs = 0, utab = 0, partial = 0, result = 0, pairs = 0, diags = 0, total = 0;
   int G = 0;     // blocks of the row-parallel kernels
+  int rs = 0;    // row stride of the per-gate reverse-step partials
   int nmax = 0;  // gates
   int pmax = 0;  // pool chunk
 };
@@ -26,7 +27,7 @@ int check_ham(const fock_ham_t *h, uint32_t *namp);
 int check_op(const fock_op_t &op, int L);
 int check_ptr(const void *p, const char *name);
 HamArgs make_ham_args(const fock_ham_t &h);
-Layout make_layout(uint32_t namp, int d, int P, int n);
+Layout make_layout(uint32_t namp, int L, int d, int P, int n);
 int make_ctx(const fock_ham_t &ham, uint32_t namp, int P, int n, void *ws, size_t ws_bytes, hipStream_t s, Ctx *c);
 int stage_gates(Ctx &c, const fock_op_t *ops, const double *theta, int n);
 int forward_gate(Ctx &c, const fock_op_t &op, int k, bool dag, float2 *psi);

@@ -1,0 +1,99 @@
+"""Kernel micro-benchmark of libfock on one GPU (used for rocprofv3 runs).
+
+    python -m paper_2606_05297_amd.kbench [--workload kk_l8_d8|bh_l8_d6] [--iters N] [--kernels ...]
+
+Runs each kernel family on seeded synthetic states of the workload's size,
+rotating three state buffers (working set larger than the 256 MiB Infinity
+Cache at L=8, d=8), and prints per-kernel launches, average duration (HIP
+events on the launch stream) and algorithmic GB/s.  A plain device copy of
+one state is timed alongside as the bandwidth reference.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+NAMES = {0: "apply_h", 1: "pool_grads", 2: "gate2", 3: "gate2_adjoint", 4: "diag_gate"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--workload", default="kk_l8_d8")
+    ap.add_argument("--iters", type=int, default=20)
+    ap.add_argument("--kernels", default="copy,apply_h,pool,gate,adjoint")
+    args = ap.parse_args()
+    import numpy as np
+    import torch
+
+    import workload as W
+    from paper_2606_05297_amd import lib
+
+    torch.cuda.set_device(0)
+    cfg = W.config(args.workload)
+    h = lib.ham_from(cfg)
+    L, d = cfg["L"], cfg["d"]
+    n = d**L
+    sector = cfg["sector"]
+    states = [torch.from_numpy(W.random_state(L, d, seed=s, sector=sector)).to("cuda") for s in range(3)]
+    outs = [torch.empty_like(states[0]) for _ in range(3)]
+    ws = lib.workspace(h, len(cfg["pool"]), 64)
+    want = set(args.kernels.split(","))
+    res = {}
+    lib.prof_reset()
+    lib.prof_enable(True)
+    if "copy" in want:
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        outs[0].copy_(states[0])
+        torch.cuda.synchronize()
+        ev0.record()
+        for k in range(args.iters):
+            outs[k % 3].copy_(states[k % 3])
+        ev1.record()
+        torch.cuda.synchronize()
+        ms = ev0.elapsed_time(ev1) / args.iters
+        res["copy"] = {"avg_us": ms * 1e3, "GBs": 16.0 * n / (ms * 1e-3) / 1e9}
+        print(f"[kbench] copy done", file=sys.stderr, flush=True)
+    if "apply_h" in want:
+        for k in range(args.iters):
+            lib.apply_H(h, states[k % 3], outs[k % 3], ws, energy=(k == args.iters - 1))
+        print(f"[kbench] apply_h done", file=sys.stderr, flush=True)
+    if "pool" in want:
+        for k in range(3):
+            lib.apply_H(h, states[k], outs[k], ws, energy=False)
+        for k in range(args.iters):
+            lib.pool_grads(h, cfg["pool"], states[k % 3], outs[k % 3], ws)
+        print(f"[kbench] pool done", file=sys.stderr, flush=True)
+    if "gate" in want:
+        pairs = [(0, 1), (3, 4), (L - 2, L - 1), (1, 2)]
+        types = ["HR", "PR"] if cfg["Delta"] != 0 else ["HR", "DH"]
+        for k in range(args.iters):
+            for (i, j) in pairs:
+                for t in types:
+                    lib.apply_gate2(L, d, (t, i, j), 0.37, states[k % 3], ws)
+        torch.cuda.synchronize()
+        print(f"[kbench] gate done", file=sys.stderr, flush=True)
+    if "adjoint" in want:
+        ops, th = W.random_circuit(cfg["pool"], 8, seed=3)
+        for k in range(max(1, args.iters // 4)):
+            lib.energy_grad_adjoint(h, ops, th, states[k % 3], outs[(k + 1) % 3], outs[(k + 2) % 3], ws)
+        print(f"[kbench] adjoint done", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    lib.prof_enable(False)
+    for kid, name in NAMES.items():
+        p = lib.prof_query(kid)
+        if p["launches"]:
+            avg = p["ms"] / p["launches"]
+            res[name] = {"launches": p["launches"], "avg_us": avg * 1e3,
+                         "GBs": (p["bytes"] / p["launches"]) / (avg * 1e-3) / 1e9}
+    print(json.dumps({"workload": args.workload, "iters": args.iters, "kernels": res}), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -38,7 +38,7 @@ class AdaptOpts(C.Structure):
                 ("tie_tau", C.c_double), ("gtol_floor_rel", C.c_double), ("warm_gtol", C.c_double),
                 ("n_warm", C.c_int32), ("grad_mode", C.c_int32), ("warm_ops", C.POINTER(Op)),
                 ("warm_theta0", C.POINTER(C.c_double)), ("fd_step", C.c_double),
-                ("recycle_hessian", C.c_int32), ("reserved", C.c_int32)]
+                ("recycle_hessian", C.c_int32), ("reserved", C.c_int32), ("noise_rel", C.c_double)]
 
 
 class AdaptReport(C.Structure):
@@ -223,7 +223,7 @@ class Adapt:
 
     def __init__(self, h: Ham, pool, psi0, max_iters=60, grad_tol=1e-3, warm_ops=(), warm_theta0=(),
                  grad_mode=0, fd_step=1e-3, recycle_hessian=False, bfgs_maxiter=1000, tie_tau=1e-4,
-                 gtol_floor_rel=1e-5, warm_gtol=1e-6, stream=None):
+                 gtol_floor_rel=1e-5, warm_gtol=1e-6, noise_rel=1e-7, stream=None):
         L = load()
         self._L = L
         o = AdaptOpts()
@@ -237,6 +237,7 @@ class Adapt:
         o.tie_tau = float(tie_tau)
         o.gtol_floor_rel = float(gtol_floor_rel)
         o.warm_gtol = float(warm_gtol)
+        o.noise_rel = float(noise_rel)
         self._warm = ops_array(list(warm_ops))
         self._warm_th = np.ascontiguousarray(warm_theta0, dtype=np.float64)
         o.n_warm = len(warm_ops)

@@ -1,0 +1,88 @@
+"""Summarise rocprofv3 SQLite output (kernel trace and FETCH_SIZE / WRITE_SIZE
+counter passes) as text.
+
+    python -m paper_2606_05297_amd.rocprof_summary --trace T.db [--fetch F.db] [--write W.db]
+           [--copy-bytes N] [--json out.json]
+
+Counter scaling: FETCH_SIZE and WRITE_SIZE (KiB per dispatch) are converted to
+bytes with the factor that makes the plain device copy kernel
+(__amd_rocclr_copyBuffer, reading and writing N bytes) read exactly N bytes,
+resp. write exactly N bytes.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import re
+import sqlite3
+from collections import defaultdict
+
+COPY = "__amd_rocclr_copyBuffer"
+
+
+def short(name: str) -> str:
+    m = re.match(r"^(?:void )?([\w:]+(?:<[^()]*>)?)", name)
+    return m.group(1) if m else name[:80]
+
+
+def trace(db):
+    con = sqlite3.connect(db)
+    rows = con.execute("select name, duration from kernels").fetchall()
+    agg = defaultdict(list)
+    for n, d in rows:
+        agg[short(n)].append(d)
+    return agg
+
+
+def counter(db, cname):
+    """Per-kernel counter values; copy-kernel dispatches are kept only at the
+    largest grid (the full-state copy of known size)."""
+    con = sqlite3.connect(db)
+    rows = con.execute("select kernel_name, value, grid_size from counters_collection where counter_name = ?",
+                       (cname,)).fetchall()
+    gmax = max([g for n, v, g in rows if short(n) == COPY] or [0])
+    agg = defaultdict(list)
+    for n, v, g in rows:
+        if short(n) == COPY and g != gmax:
+            continue
+        agg[short(n)].append(v)
+    return agg
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--trace", required=True)
+    ap.add_argument("--fetch")
+    ap.add_argument("--write")
+    ap.add_argument("--copy-bytes", type=float, default=0.0)
+    ap.add_argument("--json")
+    a = ap.parse_args()
+    tr = trace(a.trace)
+    fe = counter(a.fetch, "FETCH_SIZE") if a.fetch else {}
+    wr = counter(a.write, "WRITE_SIZE") if a.write else {}
+    ffac = wfac = None
+    if a.copy_bytes and COPY in fe:
+        ffac = a.copy_bytes / (1024.0 * sum(fe[COPY]) / len(fe[COPY]))
+    if a.copy_bytes and COPY in wr:
+        wfac = a.copy_bytes / (1024.0 * sum(wr[COPY]) / len(wr[COPY]))
+    print(f"{'kernel':60s} {'calls':>6s} {'avg_us':>10s} {'total_ms':>10s} {'fetch_MB':>10s} {'write_MB':>10s}")
+    out = {"fetch_factor": ffac, "write_factor": wfac, "kernels": {}}
+    for k in sorted(tr, key=lambda k: -sum(tr[k])):
+        d = tr[k]
+        avg = sum(d) / len(d) / 1e3
+        f = (sum(fe[k]) / len(fe[k]) * 1024.0 * (ffac or 1.0)) if k in fe else None
+        w = (sum(wr[k]) / len(wr[k]) * 1024.0 * (wfac or 1.0)) if k in wr else None
+        out["kernels"][k] = {"calls": len(d), "avg_us": avg, "total_ms": sum(d) / 1e6, "fetch_bytes": f,
+                             "write_bytes": w}
+        fs = f"{f / 1e6:10.1f}" if f is not None else f"{'-':>10s}"
+        ws = f"{w / 1e6:10.1f}" if w is not None else f"{'-':>10s}"
+        print(f"{k[:60]:60s} {len(d):6d} {avg:10.2f} {sum(d) / 1e6:10.3f} {fs} {ws}")
+    if ffac or wfac:
+        print(f"counter scale factors (copy kernel): fetch x{ffac}, write x{wfac}")
+    if a.json:
+        with open(a.json, "w") as fh:
+            json.dump(out, fh, indent=1)
+
+
+if __name__ == "__main__":
+    main()

@@ -123,7 +123,7 @@ GATE_OPS = [("HR", 0, 1), ("HI", 1, 3), ("DH", 0, 2), ("DH", 2, 3), ("PR", 0, 3)
             ("KERR", 2, -1), ("ROT", 3, -1), ("ROT", 0, -1)]
 
 
-@pytest.mark.parametrize("d", [2, 3, 5, 8])
+@pytest.mark.parametrize("d", [2, 3, 5, 8, 12, 16])
 @pytest.mark.parametrize("opx", GATE_OPS, ids=lambda o: f"{o[0]}{o[1]}{o[2]}")
 def test_gate_parity_and_leakage(opx, d):
     L = 4
