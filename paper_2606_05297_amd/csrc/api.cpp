@@ -110,6 +110,7 @@ Layout make_layout(uint32_t namp, int Lm, int d, int P, int n) {
   Layout L;
   const uint32_t nrows = namp / (uint32_t)d;
   L.G = (int)((nrows + kBlock - 1) / kBlock);
+  L.G = std::max(L.G, (int)(nrows / (uint32_t)apply_h_tile_rows(Lm, d)));
   L.rs = L.G;
   if (Lm >= 2) {
     const Geometry g{Lm, d, namp};
@@ -181,11 +182,11 @@ int stage_gates(Ctx &c, const fock_op_t *ops, const double *theta, int n) {
                            (float2 *)(c.ws + c.L.utab), c.s);
 }
 
-int forward_gate(Ctx &c, const fock_op_t &op, int k, bool dag, float2 *psi) {
+int forward_gate(Ctx &c, const fock_op_t &op, int k, bool dag, const float2 *src, float2 *psi) {
   const float2 *U = (const float2 *)(c.ws + c.L.utab) + (size_t)k * gate_stride(c.g.d);
   ProfScope ps(is_single_mode(op.type) ? FOCK_K_DIAG : FOCK_K_GATE, c.s, 16.0 * c.g.n_amp);
-  if (is_single_mode(op.type)) return launch_diag(c.g, op.i, op.type, dag, U, psi, c.s);
-  return launch_gate(c.g, op.i, op.j, gate_kind(op.type), dag, U, psi, c.s);
+  if (is_single_mode(op.type)) return launch_diag(c.g, op.i, op.type, dag, U, src, psi, c.s);
+  return launch_gate(c.g, op.i, op.j, gate_kind(op.type), dag, U, src, psi, c.s);
 }
 
 int apply_h_dev(Ctx &c, const float2 *psi, float2 *hpsi, double *res2) {
@@ -216,9 +217,11 @@ int run_circuit(Ctx &c, const fock_op_t *ops, const double *theta, int n, const 
     rc = stage_gates(c, ops, theta, n);
     if (rc) return rc;
   }
-  FOCK_HIP(hipMemcpyAsync(phi, psi0, sizeof(float2) * (size_t)c.g.n_amp, hipMemcpyDeviceToDevice, c.s));
+  // the first gate reads psi0 and writes phi (no separate copy)
+  if (n == 0)
+    FOCK_HIP(hipMemcpyAsync(phi, psi0, sizeof(float2) * (size_t)c.g.n_amp, hipMemcpyDeviceToDevice, c.s));
   for (int k = 0; k < n; ++k) {
-    rc = forward_gate(c, ops[k], k, false, phi);
+    rc = forward_gate(c, ops[k], k, false, k == 0 ? (const float2 *)psi0 : phi, phi);
     if (rc) return rc;
   }
   double *res = (double *)(c.ws + c.L.result);
@@ -385,7 +388,7 @@ int fock_apply_gate2(int L, int d, fock_op_t op, double theta, int adjoint, void
   if (rc) return rc;
   rc = stage_gates(c, &op, &theta, 1);
   if (rc) return rc;
-  return forward_gate(c, op, 0, adjoint != 0, (float2 *)psi);
+  return forward_gate(c, op, 0, adjoint != 0, (const float2 *)psi, (float2 *)psi);
 }
 
 int fock_pool_grads(const fock_ham_t *ham, const fock_op_t *pool, int P, const void *psi, const void *hpsi,

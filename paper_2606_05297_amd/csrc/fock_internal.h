@@ -131,13 +131,16 @@ inline int gate_stride(int d) { return packed_size(d); }
 int launch_apply_h(const HamArgs &h, const float2 *psi, float2 *hpsi, double *partial, int *nblocks,
                    hipStream_t s);
 int apply_h_blocks(const HamArgs &h);
+// Rows per workgroup tile of the stencil-type kernels (apply-H, pool gradients).
+int apply_h_tile_rows(int L, int d);
 int launch_pool(const PoolArgs &a, const PoolPair *pairs, const PoolDiag *diags, const float2 *psi,
                 const float2 *hpsi, double *partial, int *nblocks, hipStream_t s);
 int pool_blocks(const PoolArgs &a);
 int launch_gate_build(const double *theta, const GateRec *recs, int n, const EigTables &T, float2 *utab,
                       hipStream_t s);
-// psi <- U psi (dag = false) or U^+ psi (dag = true) for a two-mode gate on (i, j).
-int launch_gate(const Geometry &g, int i, int j, int kind, bool dag, const float2 *U, float2 *psi,
+// psi <- U src (dag = false) or U^+ src (dag = true) for a two-mode gate on
+// (i, j); src == psi applies it in place.
+int launch_gate(const Geometry &g, int i, int j, int kind, bool dag, const float2 *U, const float2 *src, float2 *psi,
                 hipStream_t s);
 // Fused reverse step: partial[blk] = per-block sum of Re<lam|A phi>, then
 // phi <- U^+ phi, lam <- U^+ lam.
@@ -146,7 +149,8 @@ int launch_gate_adj(const Geometry &g, int i, int j, int kind, const float2 *U, 
 int gate_blocks_count(const Geometry &g, int i);  // workgroups of a gate on (i, j)
 int gate_blocks_max(const Geometry &g);
 // Single-mode diagonal gate with device phase table ph[d].
-int launch_diag(const Geometry &g, int r, int type, bool dag, const float2 *ph, float2 *psi, hipStream_t s);
+int launch_diag(const Geometry &g, int r, int type, bool dag, const float2 *ph, const float2 *src, float2 *psi,
+                hipStream_t s);
 int launch_diag_adj(const Geometry &g, int r, int type, const float2 *ph, float2 *phi, float2 *lam,
                     double *partial, hipStream_t s);
 int diag_blocks_count(const Geometry &g);

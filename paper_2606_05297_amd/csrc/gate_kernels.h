@@ -65,8 +65,9 @@ __device__ __forceinline__ uint32_t member_off(int s, int a, uint32_t si, uint32
 
 // Apply U (or U^+) to the members of group G of one fiber.  ld/st address the
 // member (s, a): global memory (direct) or an LDS tile (mode-0 pairs).
-template <int D, int KIND, bool DAG, int NG, int G, class Ptr>
-__device__ __forceinline__ void gate_group_blockwise(Ptr base, uint32_t si, uint32_t sj, const float2 *__restrict__ U) {
+template <int D, int KIND, bool DAG, int NG, int G, class Ptr, class CPtr>
+__device__ __forceinline__ void gate_group_blockwise(CPtr src, Ptr base, uint32_t si, uint32_t sj,
+                                                     const float2 *__restrict__ U) {
   constexpr Groups<D, NG> P{};
   int off = 0;
 #pragma unroll
@@ -76,7 +77,7 @@ __device__ __forceinline__ void gate_group_blockwise(Ptr base, uint32_t si, uint
       float2 v[D];
 #pragma unroll
       for (int q = 0; q < D; ++q)
-        if (q < b) v[q] = base[member_off<D, KIND>(s, lo + q, si, sj)];
+        if (q < b) v[q] = src[member_off<D, KIND>(s, lo + q, si, sj)];
 #pragma unroll
       for (int p = 0; p < D; ++p)
         if (p < b) {
@@ -94,10 +95,12 @@ __device__ __forceinline__ void gate_group_blockwise(Ptr base, uint32_t si, uint
   }
 }
 
-template <int D, int KIND, bool DAG, int NG, int G, class Ptr>
-__device__ __forceinline__ void gate_group(Ptr base, uint32_t si, uint32_t sj, const float2 *__restrict__ U) {
+// src: members are read there; base: results are written there (src == base
+// for the in-place gate).
+template <int D, int KIND, bool DAG, int NG, int G, class Ptr, class CPtr>
+__device__ __forceinline__ void gate_group(CPtr src, Ptr base, uint32_t si, uint32_t sj, const float2 *__restrict__ U) {
   if constexpr (D > 8) {
-    gate_group_blockwise<D, KIND, DAG, NG, G>(base, si, sj, U);
+    gate_group_blockwise<D, KIND, DAG, NG, G>(src, base, si, sj, U);
     return;
   }
   constexpr Groups<D, NG> P{};
@@ -109,7 +112,7 @@ __device__ __forceinline__ void gate_group(Ptr base, uint32_t si, uint32_t sj, c
       const int lo = blk_lo(KIND, D, s), b = blk_hi(KIND, D, s) - lo + 1;
 #pragma unroll
       for (int q = 0; q < D; ++q)
-        if (q < b) v[m + q] = base[member_off<D, KIND>(s, lo + q, si, sj)];
+        if (q < b) v[m + q] = src[member_off<D, KIND>(s, lo + q, si, sj)];
       m += b;
     }
   m = 0;
@@ -249,19 +252,22 @@ __device__ __forceinline__ float adj_group(Ptr pb, Ptr lb, uint32_t si, uint32_t
 // Consecutive lanes own fibers that differ in the lowest free mode (mode 0),
 // so each member access of a wavefront is one contiguous 512-byte run.
 template <int D, int KIND, bool DAG>
-__global__ __launch_bounds__(kBlock) void k_gate2(float2 *__restrict__ psi, const float2 *__restrict__ U, GateLaunch g) {
+__global__ __launch_bounds__(kBlock) void k_gate2(const float2 *src, float2 *psi, const float2 *__restrict__ U,
+                                                  GateLaunch g) {
   constexpr int NG = direct_groups<D>();
   constexpr int FPB = 64 * (4 / NG);
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int gi = wave % NG;
   const uint32_t f = (uint32_t)xcd_remap(blockIdx.x, gridDim.x) * FPB + (uint32_t)(wave / NG) * 64 + lane;
   if (f >= g.nfib) return;
-  float2 *base = psi + fiber_base(f, g, D);
+  const uint32_t fb = fiber_base(f, g, D);
+  const float2 *sb = src + fb;
+  float2 *base = psi + fb;
   switch (gi) {
-    case 0: gate_group<D, KIND, DAG, NG, 0>(base, g.si, g.sj, U); break;
-    case 1: if constexpr (NG > 1) gate_group<D, KIND, DAG, NG, 1>(base, g.si, g.sj, U); break;
-    case 2: if constexpr (NG > 2) gate_group<D, KIND, DAG, NG, 2>(base, g.si, g.sj, U); break;
-    default: if constexpr (NG > 3) gate_group<D, KIND, DAG, NG, 3>(base, g.si, g.sj, U); break;
+    case 0: gate_group<D, KIND, DAG, NG, 0>(sb, base, g.si, g.sj, U); break;
+    case 1: if constexpr (NG > 1) gate_group<D, KIND, DAG, NG, 1>(sb, base, g.si, g.sj, U); break;
+    case 2: if constexpr (NG > 2) gate_group<D, KIND, DAG, NG, 2>(sb, base, g.si, g.sj, U); break;
+    default: if constexpr (NG > 3) gate_group<D, KIND, DAG, NG, 3>(sb, base, g.si, g.sj, U); break;
   }
 }
 
@@ -301,9 +307,29 @@ template <int D>
 constexpr int lds_fibers() { return D * D <= 64 ? 64 : 16; }
 
 template <int D>
-__device__ __forceinline__ void tile_copy(float2 *tile, float2 *__restrict__ gmem, const uint32_t *fbase, uint32_t sj,
+__device__ __forceinline__ void tile_copy(float2 *tile, float2 *gmem, const uint32_t *fbase, uint32_t sj,
                                           bool to_lds, uint32_t nf) {
   constexpr int FL = lds_fibers<D>(), ST = D * D + 1;
+  if constexpr (D % 2 == 0) {
+    // two consecutive n_0 values per access: 16-byte global loads/stores
+    for (int e = threadIdx.x; e < FL * D * D / 2; e += kBlock) {
+      const int b = e / (FL * D / 2), r = e % (FL * D / 2);
+      const int fl = r / (D / 2), a = 2 * (r % (D / 2));
+      if ((uint32_t)fl < nf) {
+        const uint32_t gi = fbase[fl] + (uint32_t)a + (uint32_t)b * sj;
+        float4 *gp = reinterpret_cast<float4 *>(gmem + gi);
+        float2 *tp = tile + fl * ST + b * D + a;
+        if (to_lds) {
+          const float4 v = *gp;
+          tp[0] = make_float2(v.x, v.y);
+          tp[1] = make_float2(v.z, v.w);
+        } else {
+          *gp = make_float4(tp[0].x, tp[0].y, tp[1].x, tp[1].y);
+        }
+      }
+    }
+    return;
+  }
   for (int e = threadIdx.x; e < FL * D * D; e += kBlock) {
     const int b = e / (FL * D), r = e % (FL * D);
     const int fl = r / D, a = r % D;
@@ -316,7 +342,8 @@ __device__ __forceinline__ void tile_copy(float2 *tile, float2 *__restrict__ gme
 }
 
 template <int D, int KIND, bool DAG>
-__global__ __launch_bounds__(kBlock) void k_gate2_m0(float2 *__restrict__ psi, const float2 *__restrict__ U, GateLaunch g) {
+__global__ __launch_bounds__(kBlock) void k_gate2_m0(const float2 *src, float2 *psi, const float2 *__restrict__ U,
+                                                     GateLaunch g) {
   constexpr int FL = lds_fibers<D>(), ST = D * D + 1;
   __shared__ float2 tile[FL * ST];
   __shared__ uint32_t fbase[FL];
@@ -324,17 +351,17 @@ __global__ __launch_bounds__(kBlock) void k_gate2_m0(float2 *__restrict__ psi, c
   const uint32_t nf = g.nfib - f0 < (uint32_t)FL ? g.nfib - f0 : (uint32_t)FL;
   if (threadIdx.x < FL && threadIdx.x < nf) fbase[threadIdx.x] = fiber_base(f0 + threadIdx.x, g, D);
   __syncthreads();
-  tile_copy<D>(tile, psi, fbase, g.sj, true, nf);
+  tile_copy<D>(tile, const_cast<float2 *>(src), fbase, g.sj, true, nf);
   __syncthreads();
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   if ((uint32_t)lane < nf && lane < FL) {
     float2 *base = tile + lane * ST;
     // member (n_0 = a, n_j = b) sits at b * D + a in the fiber's LDS row
     switch (wave) {
-      case 0: gate_group<D, KIND, DAG, 4, 0>(base, 1u, (uint32_t)D, U); break;
-      case 1: gate_group<D, KIND, DAG, 4, 1>(base, 1u, (uint32_t)D, U); break;
-      case 2: gate_group<D, KIND, DAG, 4, 2>(base, 1u, (uint32_t)D, U); break;
-      default: gate_group<D, KIND, DAG, 4, 3>(base, 1u, (uint32_t)D, U); break;
+      case 0: gate_group<D, KIND, DAG, 4, 0>(base, base, 1u, (uint32_t)D, U); break;
+      case 1: gate_group<D, KIND, DAG, 4, 1>(base, base, 1u, (uint32_t)D, U); break;
+      case 2: gate_group<D, KIND, DAG, 4, 2>(base, base, 1u, (uint32_t)D, U); break;
+      default: gate_group<D, KIND, DAG, 4, 3>(base, base, 1u, (uint32_t)D, U); break;
     }
   }
   __syncthreads();
@@ -383,7 +410,8 @@ struct DiagLaunch {
 };
 
 template <int D, bool DAG>
-__global__ __launch_bounds__(kBlock) void k_diag(float2 *__restrict__ psi, const float2 *__restrict__ phg, DiagLaunch a) {
+__global__ __launch_bounds__(kBlock) void k_diag(const float2 *src, float2 *psi, const float2 *__restrict__ phg,
+                                                 DiagLaunch a) {
   __shared__ float2 ph[kMaxD];
   if (threadIdx.x < D) {
     const float2 p = phg[threadIdx.x];
@@ -393,7 +421,7 @@ __global__ __launch_bounds__(kBlock) void k_diag(float2 *__restrict__ psi, const
   const int row = xcd_remap(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
   if (row >= a.nrows) return;
   float2 v[D];
-  load_row<D>(psi + (size_t)row * D, v);
+  load_row<D>(src + (size_t)row * D, v);
   const int n = a.r == 0 ? 0 : (int)(fdiv((uint32_t)row, a.dsr) % D);
 #pragma unroll
   for (int q = 0; q < D; ++q) {
@@ -449,9 +477,9 @@ template <int D>
 int fibers_per_block_d(int i) { return i == 0 ? lds_fibers<D>() : 64 * (4 / direct_groups<D>()); }
 
 template <int D>
-void gate_launch_d(const GateLaunch &gl, int i, int kind, bool dag, const float2 *U, float2 *psi, int G,
-                   hipStream_t s) {
-#define GATE_K(KN, K, DG) hipLaunchKernelGGL((KN<D, K, DG>), dim3(G), dim3(kBlock), 0, s, psi, U, gl)
+void gate_launch_d(const GateLaunch &gl, int i, int kind, bool dag, const float2 *U, const float2 *src, float2 *psi,
+                   int G, hipStream_t s) {
+#define GATE_K(KN, K, DG) hipLaunchKernelGGL((KN<D, K, DG>), dim3(G), dim3(kBlock), 0, s, src, psi, U, gl)
 #define GATE_SEL(KN)                                                         \
   if (kind == KIND_SUM) {                                                    \
     if (dag) GATE_K(KN, KIND_SUM, true); else GATE_K(KN, KIND_SUM, false);   \
@@ -477,14 +505,14 @@ void adj_launch_d(const GateLaunch &gl, int i, int kind, const float2 *U, const 
 
 #define FOCK_GATE_INSTANTIATE(D)                                                                             \
   template int fibers_per_block_d<D>(int);                                                                 \
-  template void gate_launch_d<D>(const GateLaunch &, int, int, bool, const float2 *, float2 *, int,        \
-                                 hipStream_t);                                                             \
+  template void gate_launch_d<D>(const GateLaunch &, int, int, bool, const float2 *, const float2 *,       \
+                                 float2 *, int, hipStream_t);                                              \
   template void adj_launch_d<D>(const GateLaunch &, int, int, const float2 *, const float2 *, float2 *,    \
                                 float2 *, double *, int, hipStream_t);
 #define FOCK_GATE_EXTERN(D)                                                                                  \
   extern template int fibers_per_block_d<D>(int);                                                          \
-  extern template void gate_launch_d<D>(const GateLaunch &, int, int, bool, const float2 *, float2 *, int, \
-                                        hipStream_t);                                                      \
+  extern template void gate_launch_d<D>(const GateLaunch &, int, int, bool, const float2 *, const float2 *, \
+                                        float2 *, int, hipStream_t);                                       \
   extern template void adj_launch_d<D>(const GateLaunch &, int, int, const float2 *, const float2 *,       \
                                        float2 *, float2 *, double *, int, hipStream_t);
 

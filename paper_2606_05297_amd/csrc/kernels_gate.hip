@@ -121,11 +121,11 @@ int gate_blocks_max(const Geometry &g) {
   return a > b ? a : b;
 }
 
-int launch_gate(const Geometry &g, int i, int j, int kind, bool dag, const float2 *U, float2 *psi,
+int launch_gate(const Geometry &g, int i, int j, int kind, bool dag, const float2 *U, const float2 *src, float2 *psi,
                 hipStream_t s) {
   const GateLaunch gl = make_gate_launch(g, i, j);
   const int G = gate_blocks_count(g, i);
-  FOCK_D_SWITCH(g.d, gate_launch_d<D>(gl, i, kind, dag, U, psi, G, s));
+  FOCK_D_SWITCH(g.d, gate_launch_d<D>(gl, i, kind, dag, U, src, psi, G, s));
   FOCK_HIP(hipGetLastError());
   return FOCK_OK;
 }
@@ -155,13 +155,14 @@ static DiagLaunch make_diag_launch(const Geometry &g, int r, int type) {
   return a;
 }
 
-int launch_diag(const Geometry &g, int r, int type, bool dag, const float2 *ph, float2 *psi, hipStream_t s) {
+int launch_diag(const Geometry &g, int r, int type, bool dag, const float2 *ph, const float2 *src, float2 *psi,
+                hipStream_t s) {
   const DiagLaunch a = make_diag_launch(g, r, type);
   const int G = diag_blocks_count(g);
   if (dag) {
-    FOCK_D_SWITCH(g.d, hipLaunchKernelGGL((k_diag<D, true>), dim3(G), dim3(kBlock), 0, s, psi, ph, a));
+    FOCK_D_SWITCH(g.d, hipLaunchKernelGGL((k_diag<D, true>), dim3(G), dim3(kBlock), 0, s, src, psi, ph, a));
   } else {
-    FOCK_D_SWITCH(g.d, hipLaunchKernelGGL((k_diag<D, false>), dim3(G), dim3(kBlock), 0, s, psi, ph, a));
+    FOCK_D_SWITCH(g.d, hipLaunchKernelGGL((k_diag<D, false>), dim3(G), dim3(kBlock), 0, s, src, psi, ph, a));
   }
   FOCK_HIP(hipGetLastError());
   return FOCK_OK;

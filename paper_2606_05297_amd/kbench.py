@@ -28,6 +28,7 @@ def main():
     ap.add_argument("--workload", default="kk_l8_d8")
     ap.add_argument("--iters", type=int, default=20)
     ap.add_argument("--kernels", default="copy,apply_h,pool,gate,adjoint")
+    ap.add_argument("--lib", default=None, help="path of an alternative libfock.so build")
     args = ap.parse_args()
     import numpy as np
     import torch
@@ -36,6 +37,8 @@ def main():
     from paper_2606_05297_amd import lib
 
     torch.cuda.set_device(0)
+    if args.lib:
+        lib.load(args.lib)
     cfg = W.config(args.workload)
     h = lib.ham_from(cfg)
     L, d = cfg["L"], cfg["d"]
