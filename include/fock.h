@@ -189,6 +189,46 @@ int adapt_last_proposal(fock_adapt_t *st, int *accepted, double *E_prop, double 
 
 int adapt_destroy(fock_adapt_t *st);
 
+/* ------------------------------------------------------------------ batched sweep */
+
+/* One point of a parameter sweep: its Hamiltonian, pool (P <= 256 ops, host,
+ * copied), optional warm-up layer and initial state (device, copied). */
+typedef struct {
+  fock_ham_t ham;
+  const fock_op_t *pool;
+  int32_t P;
+  int32_t n_warm;
+  const fock_op_t *warm_ops;
+  const double *warm_theta0;
+  const void *psi0;
+} fock_sweep_point_t;
+
+typedef struct fock_sweep fock_sweep_t;
+
+/* CV-ADAPT-VQE (Sec. IV.B) on npts points of uneven (L, d), d in {4, 6, 8},
+ * run in lockstep: every phase of all points is one batched launch per d,
+ * and each energy + adjoint-gradient round of the BFGS re-optimisations is a
+ * replay of one captured HIP graph.  Results per point are identical to
+ * adapt_step on that point alone (same kernels, same reduction order).
+ * opts: iteration caps, tolerances and BFGS settings shared by all points
+ * (its warm-up fields are ignored; each point brings its own).  The sweep owns
+ * its device buffers and a private stream; `stream` is synchronised once at
+ * creation (psi0 buffers must be ready on it). */
+int fock_sweep_create(const fock_sweep_point_t *pts, int npts, const fock_adapt_opts_t *opts,
+                      fock_stream_t stream, fock_sweep_t **out);
+/* One ADAPT iteration on every unfinished point; reps: host array of npts
+ * reports (unfinished points only are updated).  *n_active (nullable)
+ * receives the number of points that took part.  FOCK_ERR_STATE when every
+ * point has finished. */
+int fock_sweep_step(fock_sweep_t *sw, fock_adapt_report_t *reps, int *n_active);
+/* Reports of the warm-up optimisations done at creation (npts entries). */
+int fock_sweep_warm_reports(fock_sweep_t *sw, fock_adapt_report_t *reps);
+/* Ansatz of one point (warm-up layer first); see adapt_get_ansatz. */
+int fock_sweep_get_ansatz(fock_sweep_t *sw, int point, fock_op_t *ops, double *theta, int cap, int *n);
+/* Workgroups of the persistent batched launches (autotuner knob). */
+int fock_sweep_set_grid(fock_sweep_t *sw, int grid);
+int fock_sweep_destroy(fock_sweep_t *sw);
+
 /* ------------------------------------------------------------------ BFGS */
 
 /* Objective for fock_bfgs_minimize: f(x) and its gradient g (both host);

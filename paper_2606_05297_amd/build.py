@@ -29,6 +29,8 @@ SOURCES = [
     "kernels_gate_dd.hip",
     "kernels_gate_de.hip",
     "kernels_gate_df.hip",
+    "sweep_kernels.hip",
+    "sweep.cpp",
     "host_common.cpp",
     "api.cpp",
     "adapt.cpp",

@@ -251,14 +251,16 @@ __device__ __forceinline__ float adj_group(Ptr pb, Ptr lb, uint32_t si, uint32_t
 // ---------------------------------------------------------------- pairs (i, j) with i >= 1
 // Consecutive lanes own fibers that differ in the lowest free mode (mode 0),
 // so each member access of a wavefront is one contiguous 512-byte run.
+// The *_block device functions do the work of workgroup vb; the kernels below
+// and the batched sweep kernels call them.
 template <int D, int KIND, bool DAG>
-__global__ __launch_bounds__(kBlock) void k_gate2(const float2 *src, float2 *psi, const float2 *__restrict__ U,
-                                                  GateLaunch g) {
+__device__ __forceinline__ void gate2_direct_block(int vb, const float2 *src, float2 *psi,
+                                                   const float2 *__restrict__ U, const GateLaunch &g) {
   constexpr int NG = direct_groups<D>();
   constexpr int FPB = 64 * (4 / NG);
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int gi = wave % NG;
-  const uint32_t f = (uint32_t)xcd_remap(blockIdx.x, gridDim.x) * FPB + (uint32_t)(wave / NG) * 64 + lane;
+  const uint32_t f = (uint32_t)vb * FPB + (uint32_t)(wave / NG) * 64 + lane;
   if (f >= g.nfib) return;
   const uint32_t fb = fiber_base(f, g, D);
   const float2 *sb = src + fb;
@@ -272,13 +274,10 @@ __global__ __launch_bounds__(kBlock) void k_gate2(const float2 *src, float2 *psi
 }
 
 template <int D, int KIND>
-__global__ __launch_bounds__(kBlock) void k_gate2_adj(float2 *__restrict__ phi, float2 *__restrict__ lam,
-                                                      const float2 *__restrict__ U, const float2 *__restrict__ A,
-                                                      double *__restrict__ partial, GateLaunch g) {
-  __shared__ double red[4];
+__device__ __forceinline__ float adj_direct_block(int vb, float2 *phi, float2 *lam, const float2 *__restrict__ U,
+                                                  const float2 *__restrict__ A, const GateLaunch &g) {
   constexpr int NG = direct_groups<D>();
   constexpr int FPB = 64 * (4 / NG);
-  const int vb = xcd_remap(blockIdx.x, gridDim.x);
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int gi = wave % NG;
   const uint32_t f = (uint32_t)vb * FPB + (uint32_t)(wave / NG) * 64 + lane;
@@ -293,6 +292,22 @@ __global__ __launch_bounds__(kBlock) void k_gate2_adj(float2 *__restrict__ phi, 
       default: if constexpr (NG > 3) gacc = adj_group<D, KIND, NG, 3>(pb, lb, g.si, g.sj, U, A); break;
     }
   }
+  return gacc;
+}
+
+template <int D, int KIND, bool DAG>
+__global__ __launch_bounds__(kBlock) void k_gate2(const float2 *src, float2 *psi, const float2 *__restrict__ U,
+                                                  GateLaunch g) {
+  gate2_direct_block<D, KIND, DAG>(xcd_remap(blockIdx.x, gridDim.x), src, psi, U, g);
+}
+
+template <int D, int KIND>
+__global__ __launch_bounds__(kBlock) void k_gate2_adj(float2 *__restrict__ phi, float2 *__restrict__ lam,
+                                                      const float2 *__restrict__ U, const float2 *__restrict__ A,
+                                                      double *__restrict__ partial, GateLaunch g) {
+  __shared__ double red[4];
+  const int vb = xcd_remap(blockIdx.x, gridDim.x);
+  const float gacc = adj_direct_block<D, KIND>(vb, phi, lam, U, A, g);
   const double sg = block_sum_d((double)gacc, red);
   if (threadIdx.x == 0) partial[vb] = sg;
 }
@@ -305,6 +320,9 @@ __global__ __launch_bounds__(kBlock) void k_gate2_adj(float2 *__restrict__ phi, 
 // the four block groups from LDS, and the tile is copied back.
 template <int D>
 constexpr int lds_fibers() { return D * D <= 64 ? 64 : 16; }
+// LDS floats (float2 units) of one fiber tile and of the fiber base table
+template <int D>
+constexpr int m0_tile_elems() { return lds_fibers<D>() * (D * D + 1); }
 
 template <int D>
 __device__ __forceinline__ void tile_copy(float2 *tile, float2 *gmem, const uint32_t *fbase, uint32_t sj,
@@ -341,13 +359,13 @@ __device__ __forceinline__ void tile_copy(float2 *tile, float2 *gmem, const uint
   }
 }
 
+// tile: m0_tile_elems<D>() float2 of LDS; fbase: lds_fibers<D>() words of LDS.
+// Contains barriers: every thread of the workgroup must call it.
 template <int D, int KIND, bool DAG>
-__global__ __launch_bounds__(kBlock) void k_gate2_m0(const float2 *src, float2 *psi, const float2 *__restrict__ U,
-                                                     GateLaunch g) {
+__device__ __forceinline__ void gate2_m0_block(int vb, const float2 *src, float2 *psi, const float2 *__restrict__ U,
+                                               const GateLaunch &g, float2 *tile, uint32_t *fbase) {
   constexpr int FL = lds_fibers<D>(), ST = D * D + 1;
-  __shared__ float2 tile[FL * ST];
-  __shared__ uint32_t fbase[FL];
-  const uint32_t f0 = (uint32_t)xcd_remap(blockIdx.x, gridDim.x) * FL;
+  const uint32_t f0 = (uint32_t)vb * FL;
   const uint32_t nf = g.nfib - f0 < (uint32_t)FL ? g.nfib - f0 : (uint32_t)FL;
   if (threadIdx.x < FL && threadIdx.x < nf) fbase[threadIdx.x] = fiber_base(f0 + threadIdx.x, g, D);
   __syncthreads();
@@ -366,17 +384,14 @@ __global__ __launch_bounds__(kBlock) void k_gate2_m0(const float2 *src, float2 *
   }
   __syncthreads();
   tile_copy<D>(tile, psi, fbase, g.sj, false, nf);
+  __syncthreads();
 }
 
 template <int D, int KIND>
-__global__ __launch_bounds__(kBlock) void k_gate2_adj_m0(float2 *__restrict__ phi, float2 *__restrict__ lam,
-                                                         const float2 *__restrict__ U, const float2 *__restrict__ A,
-                                                         double *__restrict__ partial, GateLaunch g) {
+__device__ __forceinline__ float adj_m0_block(int vb, float2 *phi, float2 *lam, const float2 *__restrict__ U,
+                                              const float2 *__restrict__ A, const GateLaunch &g, float2 *tp,
+                                              float2 *tl, uint32_t *fbase) {
   constexpr int FL = lds_fibers<D>(), ST = D * D + 1;
-  __shared__ float2 tp[FL * ST], tl[FL * ST];
-  __shared__ uint32_t fbase[FL];
-  __shared__ double red[4];
-  const int vb = xcd_remap(blockIdx.x, gridDim.x);
   const uint32_t f0 = (uint32_t)vb * FL;
   const uint32_t nf = g.nfib - f0 < (uint32_t)FL ? g.nfib - f0 : (uint32_t)FL;
   if (threadIdx.x < FL && threadIdx.x < nf) fbase[threadIdx.x] = fiber_base(f0 + threadIdx.x, g, D);
@@ -398,6 +413,27 @@ __global__ __launch_bounds__(kBlock) void k_gate2_adj_m0(float2 *__restrict__ ph
   __syncthreads();
   tile_copy<D>(tp, phi, fbase, g.sj, false, nf);
   tile_copy<D>(tl, lam, fbase, g.sj, false, nf);
+  __syncthreads();
+  return gacc;
+}
+
+template <int D, int KIND, bool DAG>
+__global__ __launch_bounds__(kBlock) void k_gate2_m0(const float2 *src, float2 *psi, const float2 *__restrict__ U,
+                                                     GateLaunch g) {
+  __shared__ float2 tile[m0_tile_elems<D>()];
+  __shared__ uint32_t fbase[lds_fibers<D>()];
+  gate2_m0_block<D, KIND, DAG>(xcd_remap(blockIdx.x, gridDim.x), src, psi, U, g, tile, fbase);
+}
+
+template <int D, int KIND>
+__global__ __launch_bounds__(kBlock) void k_gate2_adj_m0(float2 *__restrict__ phi, float2 *__restrict__ lam,
+                                                         const float2 *__restrict__ U, const float2 *__restrict__ A,
+                                                         double *__restrict__ partial, GateLaunch g) {
+  __shared__ float2 tp[m0_tile_elems<D>()], tl[m0_tile_elems<D>()];
+  __shared__ uint32_t fbase[lds_fibers<D>()];
+  __shared__ double red[4];
+  const int vb = xcd_remap(blockIdx.x, gridDim.x);
+  const float gacc = adj_m0_block<D, KIND>(vb, phi, lam, U, A, g, tp, tl, fbase);
   const double sg = block_sum_d((double)gacc, red);
   if (threadIdx.x == 0) partial[vb] = sg;
 }
@@ -409,39 +445,37 @@ struct DiagLaunch {
   FastDiv dsr;  // divide a row index by d^(r-1) (r >= 1)
 };
 
+// phs: kMaxD float2 of LDS.  Contains a barrier.
 template <int D, bool DAG>
-__global__ __launch_bounds__(kBlock) void k_diag(const float2 *src, float2 *psi, const float2 *__restrict__ phg,
-                                                 DiagLaunch a) {
-  __shared__ float2 ph[kMaxD];
+__device__ __forceinline__ void diag_block(int vb, const float2 *src, float2 *psi, const float2 *__restrict__ phg,
+                                           const DiagLaunch &a, float2 *phs) {
   if (threadIdx.x < D) {
     const float2 p = phg[threadIdx.x];
-    ph[threadIdx.x] = DAG ? make_float2(p.x, -p.y) : p;
+    phs[threadIdx.x] = DAG ? make_float2(p.x, -p.y) : p;
   }
   __syncthreads();
-  const int row = xcd_remap(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
-  if (row >= a.nrows) return;
-  float2 v[D];
-  load_row<D>(src + (size_t)row * D, v);
-  const int n = a.r == 0 ? 0 : (int)(fdiv((uint32_t)row, a.dsr) % D);
+  const int row = vb * kBlock + threadIdx.x;
+  if (row < a.nrows) {
+    float2 v[D];
+    load_row<D>(src + (size_t)row * D, v);
+    const int n = a.r == 0 ? 0 : (int)(fdiv((uint32_t)row, a.dsr) % D);
 #pragma unroll
-  for (int q = 0; q < D; ++q) {
-    const float2 p = ph[a.r == 0 ? q : n];
-    float2 o = make_float2(0.f, 0.f);
-    cmac(o, p, v[q]);
-    v[q] = o;
+    for (int q = 0; q < D; ++q) {
+      const float2 p = phs[a.r == 0 ? q : n];
+      float2 o = make_float2(0.f, 0.f);
+      cmac(o, p, v[q]);
+      v[q] = o;
+    }
+    store_row<D>(psi + (size_t)row * D, v);
   }
-  store_row<D>(psi + (size_t)row * D, v);
+  __syncthreads();
 }
 
 template <int D>
-__global__ __launch_bounds__(kBlock) void k_diag_adj(float2 *__restrict__ phi, float2 *__restrict__ lam,
-                                                     const float2 *__restrict__ phg, double *__restrict__ partial,
-                                                     DiagLaunch a) {
-  __shared__ float2 ph[kMaxD];
-  __shared__ double red[4];
-  if (threadIdx.x < D) ph[threadIdx.x] = phg[threadIdx.x];
+__device__ __forceinline__ float diag_adj_block(int vb, float2 *phi, float2 *lam, const float2 *__restrict__ phg,
+                                                const DiagLaunch &a, float2 *phs) {
+  if (threadIdx.x < D) phs[threadIdx.x] = phg[threadIdx.x];
   __syncthreads();
-  const int vb = xcd_remap(blockIdx.x, gridDim.x);
   const int row = vb * kBlock + threadIdx.x;
   float gacc = 0.f;
   if (row < a.nrows) {
@@ -455,7 +489,7 @@ __global__ __launch_bounds__(kBlock) void k_diag_adj(float2 *__restrict__ phi, f
       const float f = a.kerr ? (float)(lev * lev) : (float)lev;
       // Re(conj(lam) * i f phi) = -f Im(conj(lam) phi)
       gacc = fmaf(-f, lv[q].x * pv[q].y - lv[q].y * pv[q].x, gacc);
-      const float2 p = ph[lev];
+      const float2 p = phs[lev];
       float2 np = make_float2(0.f, 0.f), nl = make_float2(0.f, 0.f);
       cmac_conj(np, p, pv[q]);
       cmac_conj(nl, p, lv[q]);
@@ -465,10 +499,28 @@ __global__ __launch_bounds__(kBlock) void k_diag_adj(float2 *__restrict__ phi, f
     store_row<D>(phi + (size_t)row * D, pv);
     store_row<D>(lam + (size_t)row * D, lv);
   }
+  __syncthreads();
+  return gacc;
+}
+
+template <int D, bool DAG>
+__global__ __launch_bounds__(kBlock) void k_diag(const float2 *src, float2 *psi, const float2 *__restrict__ phg,
+                                                 DiagLaunch a) {
+  __shared__ float2 phs[kMaxD];
+  diag_block<D, DAG>(xcd_remap(blockIdx.x, gridDim.x), src, psi, phg, a, phs);
+}
+
+template <int D>
+__global__ __launch_bounds__(kBlock) void k_diag_adj(float2 *__restrict__ phi, float2 *__restrict__ lam,
+                                                     const float2 *__restrict__ phg, double *__restrict__ partial,
+                                                     DiagLaunch a) {
+  __shared__ float2 phs[kMaxD];
+  __shared__ double red[4];
+  const int vb = xcd_remap(blockIdx.x, gridDim.x);
+  const float gacc = diag_adj_block<D>(vb, phi, lam, phg, a, phs);
   const double sg = block_sum_d((double)gacc, red);
   if (threadIdx.x == 0) partial[vb] = sg;
 }
-
 
 template <int D>
 constexpr int lds_fibers_d() { return lds_fibers<D>(); }

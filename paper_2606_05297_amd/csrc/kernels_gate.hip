@@ -109,6 +109,8 @@ static GateLaunch make_gate_launch(const Geometry &g, int i, int j) {
     default: return set_error(FOCK_ERR_UNSUPPORTED, "d=%d unsupported", d);                        \
   }
 
+GateLaunch gate_launch_params(const Geometry &g, int i, int j) { return make_gate_launch(g, i, j); }
+
 int gate_blocks_count(const Geometry &g, int i) {
   const uint32_t nf = g.n_amp / (uint32_t)(g.d * g.d);
   int fpb = 64;
@@ -154,6 +156,8 @@ static DiagLaunch make_diag_launch(const Geometry &g, int r, int type) {
   a.dsr = make_fastdiv(sr);
   return a;
 }
+
+DiagLaunch diag_launch_params(const Geometry &g, int r, int type) { return make_diag_launch(g, r, type); }
 
 int launch_diag(const Geometry &g, int r, int type, bool dag, const float2 *ph, const float2 *src, float2 *psi,
                 hipStream_t s) {

@@ -51,6 +51,11 @@ class AdaptReport(C.Structure):
         return {f: getattr(self, f) for f, _ in self._fields_}
 
 
+class SweepPoint(C.Structure):
+    _fields_ = [("ham", Ham), ("pool", C.POINTER(Op)), ("P", C.c_int32), ("n_warm", C.c_int32),
+                ("warm_ops", C.POINTER(Op)), ("warm_theta0", C.POINTER(C.c_double)), ("psi0", C.c_void_p)]
+
+
 OBJECTIVE = C.CFUNCTYPE(C.c_int, C.c_void_p, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_double),
                         C.POINTER(C.c_double))
 
@@ -90,6 +95,12 @@ def load(path: str = LIB_PATH):
     L.adapt_propose.argtypes = [vp, dp, C.c_int]
     L.adapt_last_proposal.argtypes = [vp, ip, dp, dp]
     L.adapt_destroy.argtypes = [vp]
+    L.fock_sweep_create.argtypes = [C.POINTER(SweepPoint), C.c_int, C.POINTER(AdaptOpts), vp, C.POINTER(vp)]
+    L.fock_sweep_step.argtypes = [vp, C.POINTER(AdaptReport), C.POINTER(C.c_int)]
+    L.fock_sweep_warm_reports.argtypes = [vp, C.POINTER(AdaptReport)]
+    L.fock_sweep_get_ansatz.argtypes = [vp, C.c_int, C.POINTER(Op), dp, C.c_int, ip]
+    L.fock_sweep_set_grid.argtypes = [vp, C.c_int]
+    L.fock_sweep_destroy.argtypes = [vp]
     L.fock_bfgs_minimize.argtypes = [C.c_int, dp, OBJECTIVE, vp, C.c_double, C.c_int, dp, ip, ip, dp, ip]
     L.fock_prof_enable.argtypes = [C.c_int]
     L.fock_prof_query.argtypes = [C.c_int, C.POINTER(C.c_int64), dp, dp]
@@ -282,6 +293,81 @@ class Adapt:
     def close(self):
         if self._st:
             self._L.adapt_destroy(self._st)
+            self._st = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _opts(max_iters=60, grad_tol=1e-3, bfgs_maxiter=1000, tie_tau=1e-4, gtol_floor_rel=1e-5, warm_gtol=1e-6,
+          noise_rel=1e-7, grad_mode=0, fd_step=1e-3, recycle_hessian=False):
+    o = AdaptOpts()
+    load().adapt_default_opts(C.byref(o))
+    o.max_iters, o.grad_tol, o.bfgs_maxiter, o.tie_tau = int(max_iters), float(grad_tol), int(bfgs_maxiter), float(tie_tau)
+    o.gtol_floor_rel, o.warm_gtol, o.noise_rel = float(gtol_floor_rel), float(warm_gtol), float(noise_rel)
+    o.grad_mode, o.fd_step, o.recycle_hessian = int(grad_mode), float(fd_step), int(bool(recycle_hessian))
+    return o
+
+
+class Sweep:
+    """CV-ADAPT-VQE on many points in lockstep (fock_sweep_*).
+
+    points: list of dicts with keys ham (Ham), pool (list of ops), psi0 (device
+    complex64 tensor), and optionally warm_ops / warm_theta0."""
+
+    def __init__(self, points, stream=None, **opts):
+        L = load()
+        self._L = L
+        self.n = len(points)
+        self._keep = []
+        arr = (SweepPoint * self.n)()
+        for k, p in enumerate(points):
+            pool = ops_array(p["pool"])
+            wo = p.get("warm_ops", ())
+            wops = ops_array(list(wo))
+            wth = np.ascontiguousarray(p.get("warm_theta0", ()), dtype=np.float64)
+            self._keep += [pool, wops, wth, p["psi0"]]
+            arr[k].ham = p["ham"]
+            arr[k].pool = C.cast(pool, C.POINTER(Op))
+            arr[k].P = len(p["pool"])
+            arr[k].n_warm = len(wo)
+            arr[k].warm_ops = C.cast(wops, C.POINTER(Op))
+            arr[k].warm_theta0 = wth.ctypes.data_as(C.POINTER(C.c_double)) if len(wo) else None
+            arr[k].psi0 = C.c_void_p(p["psi0"].data_ptr())
+        o = _opts(**opts)
+        self._st = C.c_void_p()
+        _check(L.fock_sweep_create(arr, self.n, C.byref(o), _stream(stream), C.byref(self._st)))
+
+    def step(self):
+        reps = (AdaptReport * self.n)()
+        na = C.c_int(0)
+        _check(self._L.fock_sweep_step(self._st, reps, C.byref(na)))
+        return [reps[k].as_dict() for k in range(self.n)], na.value
+
+    def warm_reports(self):
+        reps = (AdaptReport * self.n)()
+        _check(self._L.fock_sweep_warm_reports(self._st, reps))
+        return [reps[k].as_dict() for k in range(self.n)]
+
+    def ansatz(self, point):
+        n = C.c_int(0)
+        _check(self._L.fock_sweep_get_ansatz(self._st, int(point), None, None, 0, C.byref(n)))
+        m = n.value
+        ops = (Op * max(1, m))()
+        th = np.zeros(max(1, m))
+        _check(self._L.fock_sweep_get_ansatz(self._st, int(point), ops, th.ctypes.data_as(C.POINTER(C.c_double)), m,
+                                             C.byref(n)))
+        return [(TYPE_NAMES[ops[k].type], ops[k].i, ops[k].j) for k in range(m)], th[:m].copy()
+
+    def set_grid(self, grid):
+        _check(self._L.fock_sweep_set_grid(self._st, int(grid)))
+
+    def close(self):
+        if self._st:
+            self._L.fock_sweep_destroy(self._st)
             self._st = C.c_void_p()
 
     def __del__(self):

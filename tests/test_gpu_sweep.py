@@ -1,0 +1,88 @@
+"""Batched sweep (fock_sweep_*): every point's ADAPT trajectory equals its
+unbatched run (adapt_step on the point alone) bit for bit, and the oracle's
+energy of each point's final ansatz matches the GPU energy (|dE| <= 1e-5 |E|)."""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+import workload as W
+from paper_2606_05297_amd import lib
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print("[case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+def dev(x):
+    return torch.from_numpy(np.ascontiguousarray(np.asarray(x, dtype=np.complex64))).to("cuda")
+
+
+def small_points():
+    pts = W.sweep_points()
+    # Bose-Hubbard L=4 d=4 and d=6 (ring, warm-up layer), L=6 d=4, Kitaev-Kerr L=4 d=8 (open)
+    pick = [0, 9, 20, 48, 50]
+    return [pts[k] for k in pick]
+
+
+def entry(p):
+    h = lib.ham_from(p)
+    psi0 = dev(O.fock_state(p["L"], p["d"], p["occ"]))
+    wops = W.warmup_ops(p["L"], p["periodic"]) if p["warm"] else []
+    wth = W.warmup_theta0(len(wops), p["warm_seed"]) if p["warm"] else np.zeros(0)
+    return dict(ham=h, pool=p["pool"], psi0=psi0, warm_ops=wops, warm_theta0=wth)
+
+
+def test_sweep_equals_unbatched_and_oracle():
+    pts = small_points()
+    say("sweep", [(p["model"], p["L"], p["d"]) for p in pts])
+    entries = [entry(p) for p in pts]
+    singles = [lib.Adapt(e["ham"], e["pool"], e["psi0"], max_iters=4, warm_ops=e["warm_ops"],
+                         warm_theta0=e["warm_theta0"]) for e in entries]
+    sw = lib.Sweep(entries, max_iters=4)
+    wb = sw.warm_reports()
+    for k, a in enumerate(singles):
+        if len(entries[k]["warm_ops"]):
+            assert wb[k]["E"] == a.warm_report()["E"], k
+    last = [None] * len(pts)
+    for it in range(5):
+        reps, na = sw.step()
+        say("sweep step", it, "active", na)
+        for k, a in enumerate(singles):
+            if a is None:
+                continue
+            r = a.step()
+            assert reps[k]["k_sel"] == r["k_sel"], (k, it)
+            assert reps[k]["E"] == r["E"], (k, it, reps[k]["E"], r["E"])
+            assert reps[k]["bfgs_evals"] == r["bfgs_evals"], (k, it)
+            last[k] = reps[k]
+            if r["converged"] or r["capped"]:
+                a.close()
+                singles[k] = None
+        if all(s is None for s in singles):
+            break
+    for k, p in enumerate(pts):
+        ops, th = sw.ansatz(k)
+        ho = O.Ham(p["L"], p["d"], p["periodic"], p["J"], p["U"], p["mu"], p["Delta"], p["K"])
+        E = O.energy_of(ho, O.fock_state(p["L"], p["d"], p["occ"]), ops, th)
+        assert abs(last[k]["E"] - E) <= 1e-5 * max(1.0, abs(E)), (k, last[k]["E"], E)
+    with pytest.raises(lib.FockError):
+        while True:
+            sw.step()
+    sw.close()
+
+
+def test_sweep_rejects_unsupported_cutoff():
+    p = dict(W.sweep_points()[0])
+    e = entry(p)
+    e["ham"] = lib.ham(3, 5, True, 1.0, 1.0)
+    e["pool"] = W.pool(3, "nn", True, W.BH_TYPES)
+    e["psi0"] = dev(O.fock_state(3, 5, [1, 1, 1]))
+    e["warm_ops"], e["warm_theta0"] = [], np.zeros(0)
+    with pytest.raises(lib.FockError):
+        lib.Sweep([e], max_iters=2)
