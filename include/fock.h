@@ -227,6 +227,11 @@ int fock_sweep_warm_reports(fock_sweep_t *sw, fock_adapt_report_t *reps);
 int fock_sweep_get_ansatz(fock_sweep_t *sw, int point, fock_op_t *ops, double *theta, int cap, int *n);
 /* Workgroups of the persistent batched launches (autotuner knob). */
 int fock_sweep_set_grid(fock_sweep_t *sw, int grid);
+/* Choose that grid by timing one forward + H psi round of the unfinished
+ * points for 256..4096 workgroups (HIP events).  cache_path (nullable): JSON
+ * lines keyed by architecture and sweep size, read first, appended after
+ * tuning.  *best_grid (nullable) receives the choice. */
+int fock_sweep_autotune(fock_sweep_t *sw, const char *cache_path, int *best_grid);
 int fock_sweep_destroy(fock_sweep_t *sw);
 
 /* ------------------------------------------------------------------ BFGS */

@@ -818,6 +818,94 @@ int fock_sweep_set_grid(fock_sweep_t *sw, int grid) {
   return FOCK_OK;
 }
 
+// Autotuner: times one forward + H psi evaluation of every unfinished point
+// for each candidate persistent-grid size (HIP events on the sweep's stream,
+// median of 3 after a warm-up) and keeps the fastest.  With a cache file the
+// choice is looked up first by (architecture, point count, amplitudes, gate
+// slots) and appended after tuning, one JSON object per line.
+int fock_sweep_autotune(fock_sweep_t *sw, const char *cache_path, int *best_grid) {
+  if (!sw) return set_error(FOCK_ERR_ARG, "NULL sweep");
+  hipDeviceProp_t prop;
+  FOCK_HIP(hipGetDeviceProperties(&prop, 0));
+  size_t amps = 0, gates = 0;
+  for (auto &P : sw->pts) {
+    amps += P.g.n_amp;
+    gates += P.ops.size();
+  }
+  char key[256];
+  snprintf(key, sizeof(key), "%s|sweep|npts=%zu|amps=%zu|gates=%zu", prop.gcnArchName, sw->pts.size(), amps, gates);
+  if (cache_path) {
+    if (FILE *f = fopen(cache_path, "r")) {
+      char line[512];
+      int found = -1;
+      while (fgets(line, sizeof(line), f)) {
+        const char *k = strstr(line, key);
+        const char *g = strstr(line, "\"grid\": ");
+        if (k && g) found = atoi(g + 8);
+      }
+      fclose(f);
+      if (found > 0) {
+        sw->grid = found;
+        if (best_grid) *best_grid = found;
+        return FOCK_OK;
+      }
+    }
+  }
+  std::vector<char> sel(sw->pts.size(), 0);
+  for (size_t p = 0; p < sw->pts.size(); ++p) sel[p] = !sw->pts[p].done;
+  Lists Ls;
+  build_lists(sw, sel, false, &Ls);
+  std::vector<size_t> offs;
+  int rc = upload_recs(sw);
+  if (rc) return rc;
+  rc = stage_lists(sw, Ls, false, &offs);
+  if (rc) return rc;
+  for (size_t pi = 0; pi < sw->pts.size(); ++pi) {
+    SPoint &P = sw->pts[pi];
+    P.want = sel[pi] != 0;
+    P.x = P.theta;
+    pin_active(sw)[pi] = P.want ? 1 : 0;
+  }
+  pack_angles(sw);
+  for (auto &P : sw->pts) P.want = false;
+  hipEvent_t e0, e1;
+  FOCK_HIP(hipEventCreate(&e0));
+  FOCK_HIP(hipEventCreate(&e1));
+  const int cand[] = {256, 512, 1024, 2048, 4096};
+  int best = sw->grid;
+  float best_ms = 1e30f;
+  for (int c : cand) {
+    sw->grid = c;
+    float t[3];
+    for (int r = -1; r < 3; ++r) {
+      FOCK_HIP(hipEventRecord(e0, sw->s));
+      rc = enqueue_eval(sw, Ls, offs, false, true);
+      if (rc) break;
+      FOCK_HIP(hipEventRecord(e1, sw->s));
+      FOCK_HIP(hipEventSynchronize(e1));
+      if (r >= 0) FOCK_HIP(hipEventElapsedTime(&t[r], e0, e1));
+    }
+    if (rc) break;
+    std::sort(t, t + 3);
+    if (t[1] < best_ms) {
+      best_ms = t[1];
+      best = c;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rc) return rc;
+  sw->grid = best;
+  if (best_grid) *best_grid = best;
+  if (cache_path) {
+    if (FILE *f = fopen(cache_path, "a")) {
+      fprintf(f, "{\"key\": \"%s\", \"grid\": %d, \"ms\": %.4f}\n", key, best, best_ms);
+      fclose(f);
+    }
+  }
+  return FOCK_OK;
+}
+
 int fock_sweep_destroy(fock_sweep_t *sw) {
   if (!sw) return FOCK_OK;
   (void)hipStreamSynchronize(sw->s);

@@ -101,6 +101,7 @@ def load(path: str = LIB_PATH):
     L.fock_sweep_get_ansatz.argtypes = [vp, C.c_int, C.POINTER(Op), dp, C.c_int, ip]
     L.fock_sweep_set_grid.argtypes = [vp, C.c_int]
     L.fock_sweep_destroy.argtypes = [vp]
+    L.fock_sweep_autotune.argtypes = [vp, C.c_char_p, ip]
     L.fock_bfgs_minimize.argtypes = [C.c_int, dp, OBJECTIVE, vp, C.c_double, C.c_int, dp, ip, ip, dp, ip]
     L.fock_prof_enable.argtypes = [C.c_int]
     L.fock_prof_query.argtypes = [C.c_int, C.POINTER(C.c_int64), dp, dp]
@@ -364,6 +365,11 @@ class Sweep:
 
     def set_grid(self, grid):
         _check(self._L.fock_sweep_set_grid(self._st, int(grid)))
+
+    def autotune(self, cache_path=None):
+        g = C.c_int(0)
+        _check(self._L.fock_sweep_autotune(self._st, cache_path.encode() if cache_path else None, C.byref(g)))
+        return g.value
 
     def close(self):
         if self._st:

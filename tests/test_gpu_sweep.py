@@ -38,13 +38,18 @@ def entry(p):
     return dict(ham=h, pool=p["pool"], psi0=psi0, warm_ops=wops, warm_theta0=wth)
 
 
-def test_sweep_equals_unbatched_and_oracle():
+def test_sweep_equals_unbatched_and_oracle(tmp_path):
     pts = small_points()
     say("sweep", [(p["model"], p["L"], p["d"]) for p in pts])
     entries = [entry(p) for p in pts]
     singles = [lib.Adapt(e["ham"], e["pool"], e["psi0"], max_iters=4, warm_ops=e["warm_ops"],
                          warm_theta0=e["warm_theta0"]) for e in entries]
     sw = lib.Sweep(entries, max_iters=4)
+    cache = str(tmp_path / "tune.jsonl")
+    grid = sw.autotune(cache)
+    say("autotuned grid", grid)
+    assert grid in (256, 512, 1024, 2048, 4096)
+    assert sw.autotune(cache) == grid  # second call is a cache hit
     wb = sw.warm_reports()
     for k, a in enumerate(singles):
         if len(entries[k]["warm_ops"]):
