@@ -15,7 +15,6 @@ Prints one JSON line.
 from __future__ import annotations
 
 import argparse
-import hashlib
 import json
 import os
 import sys
@@ -28,25 +27,21 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0
 METRIC = "ADAPT steps/s, Kitaev-Kerr L=8 d=8, |ΔE|<1e-5 vs ED; apply-H GB/s vs peak"
 KERNEL_NAMES = {0: "apply_h", 1: "pool_grads", 2: "gate2", 3: "gate2_adjoint", 4: "diag_gate"}
-KERNEL_SOURCES = {0: "kernels_h.hip", 1: "kernels_pool.hip", 2: "kernels_gate.hip", 3: "kernels_gate.hip",
-                  4: "kernels_gate.hip"}
 
 
 def traffic_for(kid: int):
     """HBM bytes per launch from the committed rocprofv3 counter summary, or
     None when absent or when the kernel source changed since it was taken."""
+    from paper_2606_05297_amd.rocprof_summary import source_sha
+
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
     try:
-        t = json.load(open(path)).get(KERNEL_NAMES[kid])
+        t = json.load(open(path)).get("families", {}).get(KERNEL_NAMES[kid])
     except (ValueError, OSError):
         return None
-    if not t:
-        return None
-    src = os.path.join(ROOT, "paper_2606_05297_amd", "csrc", KERNEL_SOURCES[kid])
-    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
-    if t.get("source_sha") != sha:
+    if not t or t.get("source_sha") != source_sha(KERNEL_NAMES[kid]):
         return None
     return t.get("hbm_bytes_per_launch")
 

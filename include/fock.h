@@ -249,6 +249,32 @@ typedef int (*fock_objective_fn)(void *ctx, int n, const double *x, double *f, d
 int fock_bfgs_minimize(int n, double *x, fock_objective_fn fn, void *ctx, double gtol, int maxiter, double *Hinv,
                        int *iters, int *evals, double *fmin, int *status);
 
+/* ------------------------------------------------------------------ stencil schedules */
+
+/* Order in which the workgroups of fock_apply_H and fock_pool_grads visit the
+ * LDS tiles (d^K consecutive rows; tile t has base-d digits c_0..c_{m-1}, the
+ * occupations of the modes above the tile).  Workgroup b runs on XCD b % 8.
+ *   0: each XCD takes a contiguous run of tiles, natural order (default);
+ *   1: contiguous runs, the highest free digit fastest;
+ *   2: each XCD takes an octant of the three top digits, natural order;
+ *   3: octants, the three top digits fastest.
+ * Results do not depend on the schedule (partials are indexed by tile), only
+ * the L2 reuse of neighbour rows does.  Process-wide; schemes that do not
+ * divide the tiles over the 8 XCDs evenly run as scheme 0. */
+enum { FOCK_SCHED_NUM = 4 };
+int fock_set_stencil_schedule(int scheme);
+int fock_get_stencil_schedule(void);
+/* Host-side copy of scheme's permutation for n tiles (order[b] = tile of
+ * workgroup b); the identity-per-XCD map for scheme 0 or a fallback. */
+int fock_stencil_schedule_table(int L, int d, int scheme, int *order, int n);
+/* Autotuner: times fock_apply_H on (psi -> hpsi) under every schedule (HIP
+ * events on stream, median of 5 after a warm-up), selects the fastest and
+ * returns it in *best_scheme (nullable).  cache_path (nullable): JSON lines
+ * keyed by architecture and (L, d, boundary, model), read first, appended after
+ * tuning.  hpsi is overwritten. */
+int fock_autotune_stencil(const fock_ham_t *ham, const void *psi, void *hpsi, void *ws, size_t ws_bytes,
+                          fock_stream_t stream, const char *cache_path, int *best_scheme);
+
 /* ------------------------------------------------------------------ profiling */
 
 /* Kernel ids for per-kernel timing by HIP events recorded on the launch stream. */

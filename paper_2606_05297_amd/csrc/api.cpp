@@ -143,6 +143,10 @@ int make_ctx(const fock_ham_t &ham, uint32_t namp, int P, int n, void *ws, size_
                     Ctx *c) {
   c->g = {ham.L, ham.d, namp};
   c->h = make_ham_args(ham);
+  {
+    int rc = stencil_order_table(ham.L, ham.d, apply_h_blocks(c->h), &c->h.order);
+    if (rc) return rc;
+  }
   c->s = s;
   c->ws = (char *)ws;
   c->L = make_layout(namp, ham.L, ham.d, P, n);
@@ -266,6 +270,7 @@ int pool_dev(Ctx &c, const fock_op_t *pool, int P, const float2 *psi, const floa
   a.nrows = c.h.nrows;
   for (int r = 0; r < kMaxL; ++r) a.srow[r] = c.h.srow[r];
   for (int k = 0; k <= kMaxD; ++k) a.sq[k] = c.h.sq[k];
+  a.order = c.h.order;  // same tiles as the Hamiltonian stencil
   double *part = (double *)(c.ws + c.L.partial);
   int k0 = 0;
   while (k0 < P) {
@@ -368,6 +373,79 @@ int fock_apply_H(const fock_ham_t *ham, const void *psi, void *hpsi, double *E, 
     if (rc) return rc;
     if (E) *E = h2[0];
     if (norm2) *norm2 = h2[1];
+  }
+  return FOCK_OK;
+}
+
+int fock_autotune_stencil(const fock_ham_t *ham, const void *psi, void *hpsi, void *ws, size_t ws_bytes,
+                          fock_stream_t stream, const char *cache_path, int *best_scheme) {
+  uint32_t namp = 0;
+  int rc = check_ham(ham, &namp);
+  if (rc) return rc;
+  if ((rc = check_ptr(psi, "psi")) || (rc = check_ptr(hpsi, "hpsi"))) return rc;
+  if (psi == hpsi) return set_error(FOCK_ERR_ARG, "psi and hpsi must not overlap");
+  hipDeviceProp_t prop;
+  int dev = 0;
+  FOCK_HIP(hipGetDevice(&dev));
+  FOCK_HIP(hipGetDeviceProperties(&prop, dev));
+  char key[256];
+  snprintf(key, sizeof(key), "%s|stencil|L=%d|d=%d|periodic=%d|kitaev=%d", prop.gcnArchName, ham->L, ham->d,
+           ham->periodic ? 1 : 0, ham->Delta != 0.0 ? 1 : 0);
+  if (cache_path) {
+    if (FILE *f = fopen(cache_path, "r")) {
+      char line[512];
+      int found = -1;
+      while (fgets(line, sizeof(line), f)) {
+        const char *k = strstr(line, key);
+        const char *g = strstr(line, "\"scheme\": ");
+        if (k && g) found = atoi(g + 10);
+      }
+      fclose(f);
+      if (found >= 0 && found < FOCK_SCHED_NUM) {
+        fock_set_stencil_schedule(found);
+        if (best_scheme) *best_scheme = found;
+        return FOCK_OK;
+      }
+    }
+  }
+  hipStream_t s = (hipStream_t)stream;
+  hipEvent_t e0, e1;
+  FOCK_HIP(hipEventCreate(&e0));
+  FOCK_HIP(hipEventCreate(&e1));
+  const int prev = fock_get_stencil_schedule();
+  int best = prev;
+  float best_ms = 1e30f;
+  for (int sc = 0; sc < FOCK_SCHED_NUM && !rc; ++sc) {
+    fock_set_stencil_schedule(sc);
+    Ctx c;
+    rc = make_ctx(*ham, namp, 0, 0, ws, ws_bytes, s, &c);
+    if (rc) break;
+    double *res = (double *)(c.ws + c.L.result);
+    float t[5];
+    for (int r = -1; r < 5 && !rc; ++r) {
+      FOCK_HIP(hipEventRecord(e0, s));
+      rc = apply_h_dev(c, (const float2 *)psi, (float2 *)hpsi, res);
+      FOCK_HIP(hipEventRecord(e1, s));
+      FOCK_HIP(hipEventSynchronize(e1));
+      if (r >= 0) FOCK_HIP(hipEventElapsedTime(&t[r], e0, e1));
+    }
+    if (rc) break;
+    std::sort(t, t + 5);
+    if (t[2] < best_ms) {
+      best_ms = t[2];
+      best = sc;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  fock_set_stencil_schedule(rc ? prev : best);
+  if (rc) return rc;
+  if (best_scheme) *best_scheme = best;
+  if (cache_path) {
+    if (FILE *f = fopen(cache_path, "a")) {
+      fprintf(f, "{\"key\": \"%s\", \"scheme\": %d, \"ms\": %.5f}\n", key, best, best_ms);
+      fclose(f);
+    }
   }
   return FOCK_OK;
 }

@@ -48,6 +48,7 @@ struct HamArgs {
   float J, Delta, c2, mu;  // c2 = U/2 + K
   int srow[kMaxL];    // d^(r-1) for r >= 1: stride of mode r in rows
   float sq[kMaxD + 1];  // sqrt(0..d)
+  const int *order;   // tile processed by workgroup b (device table), or null: contiguous runs per XCD
 };
 
 // ---------------------------------------------------------------- pool gradients
@@ -63,6 +64,7 @@ struct PoolArgs {
   int L, d, nrows, npairs, ndiag, nslots;
   int srow[kMaxL];
   float sq[kMaxD + 1];
+  const int *order;  // as HamArgs::order
 };
 
 // ---------------------------------------------------------------- gates
@@ -161,6 +163,14 @@ int launch_reduce_rows(const double *partial, int row_stride, const GateRec *rec
                        hipStream_t s);
 
 // ---------------------------------------------------------------- profiling
+// Tile schedule of the stencil kernels (H psi, pool scoring): which tile each
+// workgroup processes.  Scheme 0 = contiguous runs of tiles per XCD (no
+// table); others are host-built permutations (see build_tile_order).  The
+// result of a kernel does not depend on the schedule (partials are indexed by
+// tile).  *order receives a device table of ntiles entries or nullptr.
+int stencil_order_table(int L, int d, int ntiles, const int **order);
+int stencil_schedule();
+
 struct ProfScope {
   int id;
   hipStream_t s;

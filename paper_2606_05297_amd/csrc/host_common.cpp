@@ -6,7 +6,11 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <algorithm>
+#include <atomic>
 #include <map>
+#include <tuple>
+#include <vector>
 #include <mutex>
 
 #include "fock_internal.h"
@@ -229,6 +233,116 @@ int get_tables(int d, EigTables *out) {
   *out = it->second.T;
   return FOCK_OK;
 }
+
+// ---------------------------------------------------------------- stencil tile schedules
+// Tile t of the stencil kernels has digits c_0..c_{m-1} (base d; c_k is the
+// occupation of mode K+1+k, the modes above the LDS tile).  Workgroup b runs on
+// XCD b % 8 (round-robin dispatch), as its (b / 8)-th workgroup there.  A
+// schedule assigns every tile to an XCD and orders each XCD's tiles:
+//   1: XCD = contiguous run (top digits), the highest free digit fastest;
+//   2: XCD = octant of the top three digits (upper or lower half of each),
+//      natural order inside;
+//   3: octants, with the three top digits fastest inside.
+// A schedule that does not divide the tiles evenly over the XCDs falls back
+// to scheme 0 (contiguous runs, natural order; no table).
+static std::atomic<int> g_sched{0};
+static std::mutex g_ord_mu;
+static std::map<std::tuple<int, int, int, int, int>, int *> g_ord;
+
+static bool build_tile_order(int d, int ntiles, int scheme, std::vector<int> *out) {
+  if (ntiles % 8 || ntiles < 64) return false;
+  int m = 0;
+  for (long t = 1; t < ntiles; t *= d) ++m;
+  long pw = 1;
+  for (int k = 0; k < m; ++k) pw *= d;
+  if (pw != ntiles) return false;
+  const int q = ntiles / 8, h = d / 2;
+  if ((scheme == 2 || scheme == 3) && (m < 3 || d % 2)) return false;
+  std::vector<std::vector<std::pair<long, int>>> xs(8);
+  std::vector<int> c(m);
+  for (int t = 0; t < ntiles; ++t) {
+    int u = t;
+    for (int k = 0; k < m; ++k) {
+      c[k] = u % d;
+      u /= d;
+    }
+    int x = 0;
+    long key = 0;
+    if (scheme == 1) {
+      x = t / q;
+      for (int k = 0; k < m; ++k) key = key * d + c[k];  // c_0 most significant
+    } else {
+      x = 4 * (c[m - 1] >= h) + 2 * (c[m - 2] >= h) + (c[m - 3] >= h);
+      if (scheme == 2) {
+        key = t;
+      } else {
+        for (int k = 0; k < m - 3; ++k) key = key * d + c[m - 4 - k];
+        for (int k = m - 3; k < m; ++k) key = key * h + (c[k] % h);
+      }
+    }
+    xs[x].push_back({key, t});
+  }
+  for (auto &v : xs)
+    if ((int)v.size() != q) return false;
+  out->assign(ntiles, 0);
+  for (int x = 0; x < 8; ++x) {
+    std::sort(xs[x].begin(), xs[x].end());
+    for (int p = 0; p < q; ++p) (*out)[p * 8 + x] = xs[x][p].second;
+  }
+  return true;
+}
+
+int stencil_schedule() { return g_sched.load(); }
+
+int stencil_order_table(int L, int d, int ntiles, const int **order) {
+  *order = nullptr;
+  const int scheme = g_sched.load();
+  if (scheme == 0) return FOCK_OK;
+  int dev = 0;
+  FOCK_HIP(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(g_ord_mu);
+  const auto key = std::make_tuple(dev, L, d, ntiles, scheme);
+  auto it = g_ord.find(key);
+  if (it == g_ord.end()) {
+    std::vector<int> ord;
+    int *p = nullptr;
+    if (build_tile_order(d, ntiles, scheme, &ord)) {
+      FOCK_HIP(hipMalloc(&p, sizeof(int) * ord.size()));
+      FOCK_HIP(hipMemcpy(p, ord.data(), sizeof(int) * ord.size(), hipMemcpyHostToDevice));
+    }
+    it = g_ord.emplace(key, p).first;
+  }
+  *order = it->second;
+  return FOCK_OK;
+}
+
+}  // namespace fock
+
+extern "C" int fock_set_stencil_schedule(int scheme) {
+  if (scheme < 0 || scheme >= FOCK_SCHED_NUM)
+    return fock::set_error(FOCK_ERR_ARG, "stencil schedule %d out of range [0, %d)", scheme, FOCK_SCHED_NUM);
+  fock::g_sched.store(scheme);
+  return FOCK_OK;
+}
+
+extern "C" int fock_get_stencil_schedule(void) { return fock::g_sched.load(); }
+
+extern "C" int fock_stencil_schedule_table(int L, int d, int scheme, int *order, int n) {
+  if (!order || n <= 0) return fock::set_error(FOCK_ERR_ARG, "NULL or empty order buffer");
+  std::vector<int> ord;
+  if (scheme == 0 || !fock::build_tile_order(d, n, scheme, &ord)) {
+    for (int b = 0; b < n; ++b) {
+      const int q = n >> 3;
+      order[b] = b >= (q << 3) ? b : (b & 7) * q + (b >> 3);
+    }
+    (void)L;
+    return FOCK_OK;
+  }
+  std::copy(ord.begin(), ord.end(), order);
+  return FOCK_OK;
+}
+
+namespace fock {
 
 // ---------------------------------------------------------------- profiling
 struct ProfAcc {

@@ -23,7 +23,7 @@ __global__ __launch_bounds__(kBlock) void k_apply_h(const float2 *__restrict__ p
                                                     double *__restrict__ partial, HamArgs h) {
   __shared__ double red[4];
   __shared__ float4 tile4[(TileCfg<D>::MAXROWS * TileCfg<D>::RS + 1) / 2];
-  const int vb = xcd_remap(blockIdx.x, gridDim.x);
+  const int vb = h.order ? h.order[blockIdx.x] : xcd_remap(blockIdx.x, gridDim.x);
   float e = 0.f, nn = 0.f;
   hblock<D>(vb, psi, hpsi, h, reinterpret_cast<float2 *>(tile4), e, nn);
   const double se = block_sum_d((double)e, red);

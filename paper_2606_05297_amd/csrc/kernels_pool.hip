@@ -27,7 +27,7 @@ __global__ __launch_bounds__(kBlock) void k_pool(const float2 *__restrict__ psi,
                                                  const PoolDiag *__restrict__ diags) {
   __shared__ double acc[4][kMaxSlots];
   __shared__ float4 tile4[(PTile<D>::MAXROWS * PTile<D>::RS + 1) / 2];
-  pool_block<D>(xcd_remap(blockIdx.x, gridDim.x), psi, hpsi, partial, a, pairs, diags,
+  pool_block<D>(a.order ? a.order[blockIdx.x] : xcd_remap(blockIdx.x, gridDim.x), psi, hpsi, partial, a, pairs, diags,
                 reinterpret_cast<float2 *>(tile4), acc);
 }
 

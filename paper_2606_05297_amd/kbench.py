@@ -29,6 +29,7 @@ def main():
     ap.add_argument("--iters", type=int, default=20)
     ap.add_argument("--kernels", default="copy,apply_h,pool,gate,adjoint")
     ap.add_argument("--lib", default=None, help="path of an alternative libfock.so build")
+    ap.add_argument("--schedule", type=int, default=None, help="stencil tile schedule (fock_set_stencil_schedule)")
     args = ap.parse_args()
     import numpy as np
     import torch
@@ -39,6 +40,8 @@ def main():
     torch.cuda.set_device(0)
     if args.lib:
         lib.load(args.lib)
+    if args.schedule is not None:
+        lib.set_stencil_schedule(args.schedule)
     cfg = W.config(args.workload)
     h = lib.ham_from(cfg)
     L, d = cfg["L"], cfg["d"]
@@ -95,7 +98,8 @@ def main():
             avg = p["ms"] / p["launches"]
             res[name] = {"launches": p["launches"], "avg_us": avg * 1e3,
                          "GBs": (p["bytes"] / p["launches"]) / (avg * 1e-3) / 1e9}
-    print(json.dumps({"workload": args.workload, "iters": args.iters, "kernels": res}), flush=True)
+    print(json.dumps({"workload": args.workload, "iters": args.iters, "schedule": lib.get_stencil_schedule(),
+                      "kernels": res}), flush=True)
 
 
 if __name__ == "__main__":

@@ -80,6 +80,9 @@ def load(path: str = LIB_PATH):
     L.fock_last_error.restype = C.c_char_p
     L.fock_version.restype = C.c_int
     L.fock_workspace_bytes.argtypes = [C.POINTER(Ham), C.c_int, C.c_int, C.POINTER(C.c_size_t)]
+    L.fock_set_stencil_schedule.argtypes = [C.c_int]
+    L.fock_autotune_stencil.argtypes = [C.POINTER(Ham), vp, vp, vp, sz, vp, C.c_char_p, C.POINTER(C.c_int)]
+    L.fock_stencil_schedule_table.argtypes = [C.c_int, C.c_int, C.c_int, C.POINTER(C.c_int), C.c_int]
     L.fock_apply_H.argtypes = [C.POINTER(Ham), vp, vp, dp, dp, vp, sz, vp]
     L.fock_apply_gate2.argtypes = [C.c_int, C.c_int, Op, C.c_double, C.c_int, vp, vp, sz, vp]
     L.fock_pool_grads.argtypes = [C.POINTER(Ham), C.POINTER(Op), C.c_int, vp, vp, dp, vp, sz, vp]
@@ -381,6 +384,32 @@ class Sweep:
             self.close()
         except Exception:
             pass
+
+
+# ---------------------------------------------------------------- stencil schedules
+
+def set_stencil_schedule(scheme: int):
+    _check(load().fock_set_stencil_schedule(int(scheme)))
+
+
+def autotune_stencil(h: Ham, psi, hpsi, ws, cache_path=None, stream=None) -> int:
+    """Time fock_apply_H under every tile schedule, keep the fastest."""
+    L = load()
+    best = C.c_int(0)
+    _check(L.fock_autotune_stencil(C.byref(h), _ptr(psi), _ptr(hpsi), _ptr(ws), ws.numel(), _stream(stream),
+                                   cache_path.encode() if cache_path else None, C.byref(best)))
+    return best.value
+
+
+def get_stencil_schedule() -> int:
+    return int(load().fock_get_stencil_schedule())
+
+
+def stencil_schedule_table(L: int, d: int, scheme: int, n: int):
+    out = np.zeros(n, dtype=np.int32)
+    _check(load().fock_stencil_schedule_table(int(L), int(d), int(scheme),
+                                              out.ctypes.data_as(C.POINTER(C.c_int)), int(n)))
+    return out
 
 
 # ---------------------------------------------------------------- profiling

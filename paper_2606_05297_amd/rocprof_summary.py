@@ -2,22 +2,57 @@
 counter passes) as text.
 
     python -m paper_2606_05297_amd.rocprof_summary --trace T.db [--fetch F.db] [--write W.db]
-           [--copy-bytes N] [--json out.json]
+           [--copy-bytes N | --fetch-factor F --write-factor W] [--json out.json]
+           [--traffic-out traffic.json]
 
 Counter scaling: FETCH_SIZE and WRITE_SIZE (KiB per dispatch) are converted to
 bytes with the factor that makes the plain device copy kernel
 (__amd_rocclr_copyBuffer, reading and writing N bytes) read exactly N bytes,
-resp. write exactly N bytes.
+resp. write exactly N bytes; runs without such a copy take the factors
+measured in a run that has one.
+
+--traffic-out writes, per kernel family (the groups the library's own
+profiling counters use), the mean HBM bytes per launch (fetch + write) and a
+hash of the family's sources, so that a reader can tell whether the kernels
+changed since the counters were taken.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
+import os
 import re
 import sqlite3
 from collections import defaultdict
 
 COPY = "__amd_rocclr_copyBuffer"
+CSRC = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc")
+
+# kernel family -> (kernel base names, source files the family is built from)
+FAMILIES = {
+    "apply_h": (("k_apply_h",), ("kernels_h.hip", "stencil_kernels.h", "device_common.h")),
+    "pool_grads": (("k_pool",), ("kernels_pool.hip", "stencil_kernels.h", "device_common.h")),
+    "gate2": (("k_gate2", "k_gate2_m0"), ("gate_kernels.h", "kernels_gate.hip", "device_common.h")),
+    "gate2_adjoint": (("k_gate2_adj", "k_gate2_adj_m0"), ("gate_kernels.h", "kernels_gate.hip", "device_common.h")),
+    "diag_gate": (("k_diag", "k_diag_adj"), ("gate_kernels.h", "kernels_gate.hip", "device_common.h")),
+}
+
+
+def source_sha(family: str) -> str:
+    h = hashlib.sha256()
+    for f in FAMILIES[family][1]:
+        with open(os.path.join(CSRC, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def family_of(kname: str):
+    base = kname.split("<")[0].split("::")[-1]
+    for fam, (names, _) in FAMILIES.items():
+        if base in names:
+            return fam
+    return None
 
 
 def short(name: str) -> str:
@@ -55,7 +90,10 @@ def main():
     ap.add_argument("--fetch")
     ap.add_argument("--write")
     ap.add_argument("--copy-bytes", type=float, default=0.0)
+    ap.add_argument("--fetch-factor", type=float, default=None)
+    ap.add_argument("--write-factor", type=float, default=None)
     ap.add_argument("--json")
+    ap.add_argument("--traffic-out")
     a = ap.parse_args()
     tr = trace(a.trace)
     fe = counter(a.fetch, "FETCH_SIZE") if a.fetch else {}
@@ -65,6 +103,8 @@ def main():
         ffac = a.copy_bytes / (1024.0 * sum(fe[COPY]) / len(fe[COPY]))
     if a.copy_bytes and COPY in wr:
         wfac = a.copy_bytes / (1024.0 * sum(wr[COPY]) / len(wr[COPY]))
+    ffac = a.fetch_factor if a.fetch_factor is not None else ffac
+    wfac = a.write_factor if a.write_factor is not None else wfac
     print(f"{'kernel':60s} {'calls':>6s} {'avg_us':>10s} {'total_ms':>10s} {'fetch_MB':>10s} {'write_MB':>10s}")
     out = {"fetch_factor": ffac, "write_factor": wfac, "kernels": {}}
     for k in sorted(tr, key=lambda k: -sum(tr[k])):
@@ -82,6 +122,19 @@ def main():
     if a.json:
         with open(a.json, "w") as fh:
             json.dump(out, fh, indent=1)
+    if a.traffic_out and fe and wr and ffac and wfac:
+        fam = {}
+        for f in FAMILIES:
+            fb = [v for k, vs in fe.items() if family_of(k) == f for v in vs]
+            wb = [v for k, vs in wr.items() if family_of(k) == f for v in vs]
+            if fb and wb:
+                per = 1024.0 * (ffac * sum(fb) / len(fb) + wfac * sum(wb) / len(wb))
+                fam[f] = {"hbm_bytes_per_launch": per, "fetch_bytes_per_launch": 1024.0 * ffac * sum(fb) / len(fb),
+                          "write_bytes_per_launch": 1024.0 * wfac * sum(wb) / len(wb), "launches": len(fb),
+                          "source_sha": source_sha(f)}
+                print(f"family {f:14s} launches {len(fb):5d}  HBM bytes/launch {per / 1e6:10.1f} MB")
+        with open(a.traffic_out, "w") as fh:
+            json.dump({"fetch_factor": ffac, "write_factor": wfac, "families": fam}, fh, indent=1)
 
 
 if __name__ == "__main__":

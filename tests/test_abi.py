@@ -144,3 +144,28 @@ def test_bfgs_reports_objective_errors():
         raise ValueError("boom")
     with pytest.raises(Exception):
         lib.bfgs_minimize(bad, np.zeros(2))
+
+
+def test_stencil_schedules_are_permutations():
+    """Every tile schedule visits each tile exactly once and gives every XCD
+    (workgroup b runs on XCD b % 8) the same number of tiles; octant schemes
+    keep each XCD inside one octant of the three top digits."""
+    for (L, d) in [(8, 8), (8, 6), (6, 8), (8, 4), (5, 4), (3, 4)]:
+        K = 0
+        T = 1
+        while K < L - 1 and T * d <= min(4096 // d, 512):
+            T *= d
+            K += 1
+        n = d ** (L - 1) // T
+        for s in range(4):
+            o = lib.stencil_schedule_table(L, d, s, n)
+            assert sorted(o.tolist()) == list(range(n)), (L, d, s)
+            if s >= 2 and n % 8 == 0 and d % 2 == 0 and n >= 64 and (L - 1 - K) >= 3:
+                m = L - 1 - K
+                for x in range(8):
+                    tiles = o[x::8]
+                    digs = [[(t // d ** k) % d for k in range(m)] for t in tiles]
+                    key = {(c[m - 1] >= d // 2, c[m - 2] >= d // 2, c[m - 3] >= d // 2) for c in digs}
+                    assert len(key) == 1, (L, d, s, x)
+    with pytest.raises(lib.FockError):
+        lib.set_stencil_schedule(99)

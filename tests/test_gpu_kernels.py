@@ -293,3 +293,35 @@ def test_full_bose_hubbard_l8_d6_sampled():
     outside = np.ones(6**8, dtype=bool)
     outside[O.sector_indices(8, 6, ("N", 8))] = False
     assert np.count_nonzero(got[outside]) == 0
+
+
+def test_stencil_schedules_bitwise_equal_and_autotune(kk_full, tmp_path):
+    """H psi, E, norm and pool gradients are bit-identical under every tile
+    schedule (partials are indexed by tile, not by workgroup); the autotuner
+    returns a valid scheme and its cache is hit on the second call."""
+    c, ho, hl, psi = kk_full
+    say("schedules kk L8 d8")
+    x, y = dev(psi), torch.empty(8**8, dtype=torch.complex64, device="cuda")
+    ws = lib.workspace(hl, len(c["pool"]), 64)
+    prev = lib.get_stencil_schedule()
+    try:
+        base = None
+        for s in range(4):
+            lib.set_stencil_schedule(s)
+            E, n2 = lib.apply_H(hl, x, y, ws)
+            g = lib.pool_grads(hl, c["pool"], x, y, ws)
+            cur = (E, n2, host(y), g)
+            if base is None:
+                base = cur
+            else:
+                assert cur[0] == base[0] and cur[1] == base[1], s
+                assert np.array_equal(cur[2], base[2]), s
+                assert np.array_equal(cur[3], base[3]), s
+        cache = str(tmp_path / "stencil.jsonl")
+        best = lib.autotune_stencil(hl, x, y, ws, cache)
+        say("autotuned schedule", best)
+        assert 0 <= best < 4 and lib.get_stencil_schedule() == best
+        lib.set_stencil_schedule(0)
+        assert lib.autotune_stencil(hl, x, y, ws, cache) == best
+    finally:
+        lib.set_stencil_schedule(prev)
