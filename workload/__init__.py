@@ -168,3 +168,25 @@ def warmstart_points(split: str) -> list[dict]:
         p["Delta"], p["K"] = float(Dl), float(K)
         out.append(p)
     return out
+
+
+# ---------------------------------------------------------------- warm-start network inputs
+
+MLP_SHAPES = [((128, 4), 4), ((128,), 4), ((128, 128), 128), ((128,), 128), ((64, 128), 128), ((64,), 128)]
+
+
+def mlp_init(seed: int = 0) -> np.ndarray:
+    """Seeded float32 initial parameters of the 4 -> 128 -> 128 -> 64 network,
+    uniform in [-1/sqrt(fan_in), 1/sqrt(fan_in)] (W1, b1, W2, b2, W3, b3, W
+    stored [out x in] row-major)."""
+    rng = np.random.default_rng(seed)
+    parts = []
+    for shp, fan_in in MLP_SHAPES:
+        b = 1.0 / np.sqrt(fan_in)
+        parts.append(rng.uniform(-b, b, size=shp).astype(np.float32).ravel())
+    return np.concatenate(parts)
+
+
+def mlp_features(J: float, Delta: float, K: float, step: int) -> np.ndarray:
+    """Network input of an ADAPT point at step n: (J, Delta, K, n / 64)."""
+    return np.array([J, Delta, K, step / 64.0], dtype=np.float32)
