@@ -225,6 +225,11 @@ int fock_sweep_step(fock_sweep_t *sw, fock_adapt_report_t *reps, int *n_active);
 int fock_sweep_warm_reports(fock_sweep_t *sw, fock_adapt_report_t *reps);
 /* Ansatz of one point (warm-up layer first); see adapt_get_ansatz. */
 int fock_sweep_get_ansatz(fock_sweep_t *sw, int point, fock_op_t *ops, double *theta, int cap, int *n);
+/* Warm-start proposal for point's next step (n = its current parameter
+ * count + 1), as adapt_propose: used only when its energy is not above the
+ * plain start.  Outcome of the last step's proposal: fock_sweep_last_proposal. */
+int fock_sweep_propose(fock_sweep_t *sw, int point, const double *theta, int n);
+int fock_sweep_last_proposal(fock_sweep_t *sw, int point, int *accepted, double *E_prop, double *E_plain);
 /* Workgroups of the persistent batched launches (autotuner knob). */
 int fock_sweep_set_grid(fock_sweep_t *sw, int grid);
 /* Choose that grid by timing one forward + H psi round of the unfinished
@@ -275,15 +280,53 @@ int fock_stencil_schedule_table(int L, int d, int scheme, int *order, int n);
 int fock_autotune_stencil(const fock_ham_t *ham, const void *psi, void *hpsi, void *ws, size_t ws_bytes,
                           fock_stream_t stream, const char *cache_path, int *best_scheme);
 
+/* ------------------------------------------------------------------ warm-start network */
+
+/* A small network proposes the initial angles of an ADAPT step from the
+ * point's features (J, Delta, K, n / 64): an addition on top of the plain
+ * {theta_prev, 0} initialisation of Sec. IV.B (the paper notes that initial
+ * parameters matter, Sec. V.B, and re-uses optimiser information across steps,
+ * Appendix D).  Architecture 4 -> 128 -> 128 -> 64, SiLU hidden activations,
+ * linear output; bf16 inputs, weights and hidden activations (round to nearest
+ * even), FP32 biases, FP32 MFMA accumulation, FP32 output.  Loss: masked mean
+ * squared error over the first nvalid[b] outputs of row b.  Training: Adam
+ * (beta1 0.9, beta2 0.999, eps 1e-8) on FP32 master parameters; the backward
+ * pass rounds its error signals to bf16 before the products.  Parameter vector
+ * (FP32, this order): W1 [128 x 4], b1 [128], W2 [128 x 128], b2 [128],
+ * W3 [64 x 128], b3 [64]; W is [out x in] row-major.
+ * X [B x 4], T [B x 64], Y [B x 64] (FP32, row-major) and nvalid [B] (int32) are
+ * DEVICE pointers; parameters and gradients cross as host arrays.  All calls
+ * are ordered on `stream`; those returning host values synchronise it.  The
+ * object owns its device buffers (about 101.6 kB x ceil(max_batch / 64)). */
+typedef struct fock_mlp fock_mlp_t;
+enum { FOCK_MLP_IN = 4, FOCK_MLP_HIDDEN = 128, FOCK_MLP_OUT = 64, FOCK_MLP_NPARAMS = 25408 };
+
+int fock_mlp_create(int max_batch, fock_mlp_t **out);
+/* Load FP32 master parameters (host, FOCK_MLP_NPARAMS); resets Adam state. */
+int fock_mlp_set_params(fock_mlp_t *net, const float *params, int n, fock_stream_t stream);
+int fock_mlp_get_params(fock_mlp_t *net, float *params, int n, fock_stream_t stream);
+/* Y = net(X) for B <= max_batch rows. */
+int fock_mlp_forward(fock_mlp_t *net, const float *X, int B, float *Y, fock_stream_t stream);
+/* Masked-MSE loss (nullable) and its gradient (host, nullable) at the current
+ * parameters; no update. */
+int fock_mlp_loss_grad(fock_mlp_t *net, const float *X, const float *T, const int *nvalid, int B, double *loss,
+                       float *grad, fock_stream_t stream);
+/* One Adam step on the batch; *loss (nullable; non-null synchronises) is the
+ * loss before the step. */
+int fock_mlp_adam_step(fock_mlp_t *net, const float *X, const float *T, const int *nvalid, int B, float lr,
+                       double *loss, fock_stream_t stream);
+int fock_mlp_destroy(fock_mlp_t *net);
+
 /* ------------------------------------------------------------------ profiling */
 
 /* Kernel ids for per-kernel timing by HIP events recorded on the launch stream. */
 enum { FOCK_K_APPLY_H = 0, FOCK_K_POOL = 1, FOCK_K_GATE = 2, FOCK_K_ADJ = 3, FOCK_K_DIAG = 4,
-       FOCK_K_REDUCE = 5, FOCK_K_NUM = 8 };
+       FOCK_K_REDUCE = 5, FOCK_K_MLP_FWD = 6, FOCK_K_MLP_TRAIN = 7, FOCK_K_NUM = 8 };
 
 /* Enable/disable event timing of every launch (off by default). */
 int fock_prof_enable(int on);
-/* Launch count, summed duration (ms) and summed algorithmic bytes of kernel id
+/* Launch count, summed duration (ms) and summed algorithmic bytes (FLOPs for
+ * the two network kernels) of kernel id
  * since the last reset (completed launches only; call after a synchronise). */
 int fock_prof_query(int kernel_id, int64_t *launches, double *total_ms, double *bytes);
 int fock_prof_reset(void);

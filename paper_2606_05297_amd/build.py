@@ -35,6 +35,8 @@ SOURCES = [
     "api.cpp",
     "adapt.cpp",
     "bfgs.cpp",
+    "mlp_kernels.hip",
+    "mlp.cpp",
 ]
 
 COMMON = [

@@ -43,6 +43,11 @@ struct SPoint {
   int iter = 0;
   bool done = false;
   fock_adapt_report_t warm{}, last{};
+  // warm-start proposal for the next step (see fock_sweep_propose)
+  std::vector<double> proposal;
+  bool has_prop = false;
+  int prop_acc = 0;
+  double prop_E = 0.0, plain_E = 0.0;
   // lockstep BFGS
   bool want = false, finished = true;
   std::vector<double> x, grad;
@@ -311,6 +316,30 @@ int destroy_graph(fock_sweep *sw) {
   return FOCK_OK;
 }
 
+// Energy and norm of the selected points at their angles P.x (forward gates
+// and H psi, direct launches); results in P.f, P.n2 (P.rc on failure).
+int eval_forward(fock_sweep *sw, const std::vector<char> &sel) {
+  Lists Lf;
+  build_lists(sw, sel, false, &Lf);
+  std::vector<size_t> offf;
+  int rc = upload_recs(sw);
+  if (rc) return rc;
+  rc = stage_lists(sw, Lf, false, &offf);
+  if (rc) return rc;
+  for (size_t pi = 0; pi < sw->pts.size(); ++pi) {
+    SPoint &P = sw->pts[pi];
+    P.want = sel[pi] != 0;
+    pin_active(sw)[pi] = P.want ? 1 : 0;
+  }
+  pack_angles(sw);
+  rc = enqueue_eval(sw, Lf, offf, false, true);
+  if (rc) return rc;
+  FOCK_HIP(hipStreamSynchronize(sw->s));
+  unpack(sw, false);
+  for (auto &P : sw->pts) P.want = false;
+  return FOCK_OK;
+}
+
 // Lockstep BFGS over the points in `sel`: one thread per point runs the
 // minimiser; the calling thread gathers their objective requests into rounds
 // and replays the captured evaluation graph once per round.
@@ -406,26 +435,13 @@ int bfgs_phase(fock_sweep *sw, const std::vector<char> &sel, const std::vector<d
   for (auto &t : th) t.join();
   if (err) return err;
   // final energies at the accepted angles (forward only, graph-free)
-  Lists Lf;
-  build_lists(sw, sel, false, &Lf);
-  std::vector<size_t> offf;
-  rc = stage_lists(sw, Lf, false, &offf);
+  for (size_t pi = 0; pi < sw->pts.size(); ++pi)
+    if (sel[pi]) sw->pts[pi].x = sw->pts[pi].theta;
+  rc = eval_forward(sw, sel);
   if (rc) return rc;
-  for (size_t pi = 0; pi < sw->pts.size(); ++pi) {
-    SPoint &P = sw->pts[pi];
-    P.want = sel[pi] != 0;
-    if (P.want) P.x = P.theta;
-    pin_active(sw)[pi] = P.want ? 1 : 0;
-  }
-  pack_angles(sw);
-  rc = enqueue_eval(sw, Lf, offf, false, true);
-  if (rc) return rc;
-  FOCK_HIP(hipStreamSynchronize(sw->s));
-  unpack(sw, false);
   for (size_t pi = 0; pi < sw->pts.size(); ++pi) {
     if (!sel[pi]) continue;
     SPoint &P = sw->pts[pi];
-    P.want = false;
     if (P.rc) return P.rc;
     fock_adapt_report_t &r = (*reps)[pi];
     r.bfgs_iters = outs[pi].iters;
@@ -772,6 +788,40 @@ int fock_sweep_step(fock_sweep_t *sw, fock_adapt_report_t *reps, int *n_active) 
     opt[p] = 1;
     gt[p] = gtol_for(sw->opt, r.g_sel, P.f);
   }
+  // warm-start proposals: keep one only if its energy is not above the plain
+  // start {theta_prev, 0} (whose energy is the one just scored)
+  {
+    std::vector<char> ps(npts, 0);
+    bool anyp = false;
+    for (int p = 0; p < npts; ++p) {
+      SPoint &P = sw->pts[p];
+      P.prop_acc = 0;
+      if (!opt[p] || !P.has_prop) {
+        P.has_prop = false;
+        continue;
+      }
+      P.has_prop = false;
+      if (P.proposal.size() != P.theta.size()) continue;
+      P.plain_E = P.f;
+      P.x = P.proposal;
+      ps[p] = 1;
+      anyp = true;
+    }
+    if (anyp) {
+      rc = eval_forward(sw, ps);
+      if (rc) return rc;
+      for (int p = 0; p < npts; ++p) {
+        if (!ps[p]) continue;
+        SPoint &P = sw->pts[p];
+        if (P.rc) return P.rc;
+        P.prop_E = P.f;
+        if (P.prop_E <= P.plain_E) {
+          P.theta = P.proposal;
+          P.prop_acc = 1;
+        }
+      }
+    }
+  }
   bool any = false;
   for (char c : opt) any |= c != 0;
   if (any) {
@@ -809,6 +859,29 @@ int fock_sweep_get_ansatz(fock_sweep_t *sw, int point, fock_op_t *ops, double *t
     if (ops) ops[k] = P.ops[k];
     if (theta) theta[k] = P.theta[k];
   }
+  return FOCK_OK;
+}
+
+int fock_sweep_propose(fock_sweep_t *sw, int point, const double *theta, int n) {
+  if (!sw || (!theta && n > 0)) return set_error(FOCK_ERR_ARG, "NULL argument");
+  if (point < 0 || point >= (int)sw->pts.size()) return set_error(FOCK_ERR_ARG, "point %d out of range", point);
+  SPoint &P = sw->pts[point];
+  if (n != (int)P.theta.size() + 1)
+    return set_error(FOCK_ERR_ARG, "proposal length %d != current parameters + 1 (%d)", n, (int)P.theta.size() + 1);
+  for (int k = 0; k < n; ++k)
+    if (!std::isfinite(theta[k])) return set_error(FOCK_ERR_NONFINITE, "proposal[%d] not finite", k);
+  P.proposal.assign(theta, theta + n);
+  P.has_prop = true;
+  return FOCK_OK;
+}
+
+int fock_sweep_last_proposal(fock_sweep_t *sw, int point, int *accepted, double *E_prop, double *E_plain) {
+  if (!sw) return set_error(FOCK_ERR_ARG, "NULL argument");
+  if (point < 0 || point >= (int)sw->pts.size()) return set_error(FOCK_ERR_ARG, "point %d out of range", point);
+  const SPoint &P = sw->pts[point];
+  if (accepted) *accepted = P.prop_acc;
+  if (E_prop) *E_prop = P.prop_E;
+  if (E_plain) *E_plain = P.plain_E;
   return FOCK_OK;
 }
 

@@ -81,6 +81,14 @@ def load(path: str = LIB_PATH):
     L.fock_version.restype = C.c_int
     L.fock_workspace_bytes.argtypes = [C.POINTER(Ham), C.c_int, C.c_int, C.POINTER(C.c_size_t)]
     L.fock_set_stencil_schedule.argtypes = [C.c_int]
+    fp = C.POINTER(C.c_float)
+    L.fock_mlp_create.argtypes = [C.c_int, C.POINTER(C.c_void_p)]
+    L.fock_mlp_set_params.argtypes = [vp, fp, C.c_int, vp]
+    L.fock_mlp_get_params.argtypes = [vp, fp, C.c_int, vp]
+    L.fock_mlp_forward.argtypes = [vp, vp, C.c_int, vp, vp]
+    L.fock_mlp_loss_grad.argtypes = [vp, vp, vp, vp, C.c_int, dp, fp, vp]
+    L.fock_mlp_adam_step.argtypes = [vp, vp, vp, vp, C.c_int, C.c_float, dp, vp]
+    L.fock_mlp_destroy.argtypes = [vp]
     L.fock_autotune_stencil.argtypes = [C.POINTER(Ham), vp, vp, vp, sz, vp, C.c_char_p, C.POINTER(C.c_int)]
     L.fock_stencil_schedule_table.argtypes = [C.c_int, C.c_int, C.c_int, C.POINTER(C.c_int), C.c_int]
     L.fock_apply_H.argtypes = [C.POINTER(Ham), vp, vp, dp, dp, vp, sz, vp]
@@ -105,6 +113,8 @@ def load(path: str = LIB_PATH):
     L.fock_sweep_set_grid.argtypes = [vp, C.c_int]
     L.fock_sweep_destroy.argtypes = [vp]
     L.fock_sweep_autotune.argtypes = [vp, C.c_char_p, ip]
+    L.fock_sweep_propose.argtypes = [vp, C.c_int, dp, C.c_int]
+    L.fock_sweep_last_proposal.argtypes = [vp, C.c_int, ip, dp, dp]
     L.fock_bfgs_minimize.argtypes = [C.c_int, dp, OBJECTIVE, vp, C.c_double, C.c_int, dp, ip, ip, dp, ip]
     L.fock_prof_enable.argtypes = [C.c_int]
     L.fock_prof_query.argtypes = [C.c_int, C.POINTER(C.c_int64), dp, dp]
@@ -369,6 +379,15 @@ class Sweep:
     def set_grid(self, grid):
         _check(self._L.fock_sweep_set_grid(self._st, int(grid)))
 
+    def propose(self, point, theta):
+        t = np.ascontiguousarray(theta, dtype=np.float64)
+        _check(self._L.fock_sweep_propose(self._st, int(point), t.ctypes.data_as(C.POINTER(C.c_double)), len(t)))
+
+    def last_proposal(self, point):
+        acc, ep, e0 = C.c_int(0), C.c_double(0), C.c_double(0)
+        _check(self._L.fock_sweep_last_proposal(self._st, int(point), C.byref(acc), C.byref(ep), C.byref(e0)))
+        return {"accepted": bool(acc.value), "E_prop": ep.value, "E_plain": e0.value}
+
     def autotune(self, cache_path=None):
         g = C.c_int(0)
         _check(self._L.fock_sweep_autotune(self._st, cache_path.encode() if cache_path else None, C.byref(g)))
@@ -377,6 +396,96 @@ class Sweep:
     def close(self):
         if self._st:
             self._L.fock_sweep_destroy(self._st)
+            self._st = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ---------------------------------------------------------------- warm-start network
+
+MLP_NPARAMS = 25408
+
+
+def _mlp_arg(t, cols, dtype, name):
+    import torch
+    want = torch.float32 if dtype == "f32" else torch.int32
+    if not (t.is_cuda and t.dtype == want and t.is_contiguous()):
+        raise FockError(-1, f"{name} must be a contiguous CUDA {want} tensor")
+    if cols is not None and (t.dim() != 2 or t.shape[1] != cols):
+        raise FockError(-1, f"{name} must have shape [B, {cols}], got {tuple(t.shape)}")
+    if cols is None and t.dim() != 1:
+        raise FockError(-1, f"{name} must be one-dimensional")
+
+
+class Mlp:
+    """Warm-start network 4 -> 128 -> 128 -> 64 (fock_mlp_*).  X, T, Y are
+    float32 CUDA tensors, nvalid an int32 CUDA tensor; parameters and
+    gradients are numpy float32 arrays."""
+
+    def __init__(self, max_batch, params=None, stream=None):
+        self._L = load()
+        self._st = C.c_void_p()
+        self.max_batch = int(max_batch)
+        self._s = stream
+        _check(self._L.fock_mlp_create(self.max_batch, C.byref(self._st)))
+        if params is not None:
+            self.set_params(params)
+
+    def set_params(self, params):
+        p = np.ascontiguousarray(params, dtype=np.float32)
+        _check(self._L.fock_mlp_set_params(self._st, p.ctypes.data_as(C.POINTER(C.c_float)), len(p),
+                                           _stream(self._s)))
+
+    def params(self):
+        p = np.zeros(MLP_NPARAMS, dtype=np.float32)
+        _check(self._L.fock_mlp_get_params(self._st, p.ctypes.data_as(C.POINTER(C.c_float)), len(p),
+                                           _stream(self._s)))
+        return p
+
+    def _batch(self, X, T=None, nvalid=None):
+        _mlp_arg(X, 4, "f32", "X")
+        B = X.shape[0]
+        if T is not None:
+            _mlp_arg(T, 64, "f32", "T")
+            _mlp_arg(nvalid, None, "i32", "nvalid")
+            if T.shape[0] != B or nvalid.shape[0] != B:
+                raise FockError(-1, "X, T and nvalid must have the same number of rows")
+        return B
+
+    def forward(self, X, Y=None):
+        import torch
+        self._batch(X)
+        if Y is None:
+            Y = torch.empty((X.shape[0], 64), dtype=torch.float32, device=X.device)
+        _mlp_arg(Y, 64, "f32", "Y")
+        if Y.shape[0] != X.shape[0]:
+            raise FockError(-1, "Y must have as many rows as X")
+        _check(self._L.fock_mlp_forward(self._st, _ptr(X), int(X.shape[0]), _ptr(Y), _stream(self._s)))
+        return Y
+
+    def loss_grad(self, X, T, nvalid, grad=True):
+        self._batch(X, T, nvalid)
+        loss = C.c_double(0)
+        g = np.zeros(MLP_NPARAMS, dtype=np.float32) if grad else None
+        _check(self._L.fock_mlp_loss_grad(self._st, _ptr(X), _ptr(T), _ptr(nvalid), int(X.shape[0]), C.byref(loss),
+                                          g.ctypes.data_as(C.POINTER(C.c_float)) if grad else None,
+                                          _stream(self._s)))
+        return loss.value, g
+
+    def adam_step(self, X, T, nvalid, lr, want_loss=False):
+        self._batch(X, T, nvalid)
+        loss = C.c_double(0)
+        _check(self._L.fock_mlp_adam_step(self._st, _ptr(X), _ptr(T), _ptr(nvalid), int(X.shape[0]), float(lr),
+                                          C.byref(loss) if want_loss else None, _stream(self._s)))
+        return loss.value if want_loss else None
+
+    def close(self):
+        if self._st:
+            self._L.fock_mlp_destroy(self._st)
             self._st = C.c_void_p()
 
     def __del__(self):
