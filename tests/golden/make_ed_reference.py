@@ -3,6 +3,11 @@ of the benchmark workloads in their symmetry sectors, computed by the FP64
 oracle only (dense eigh for small sectors, Lanczos otherwise).
 
     python tests/golden/make_ed_reference.py [names...]
+    python tests/golden/make_ed_reference.py --warmstart-held [--jobs N]
+
+The second form writes tests/golden/warmstart_held_ed.json: the even-parity
+ground energies of the 64 held-out Kitaev-Kerr L=6 d=8 warm-start points (in
+the order of workload.warmstart_points("held")).
 """
 import json
 import os
@@ -16,6 +21,27 @@ import oracle as O  # noqa: E402
 import workload as W  # noqa: E402
 
 OUT = os.path.join(HERE, "ed_reference.json")
+OUT_HELD = os.path.join(HERE, "warmstart_held_ed.json")
+
+
+def held_one(k):
+    p = W.warmstart_points("held")[k]
+    h = O.Ham(p["L"], p["d"], p["periodic"], p["J"], p["U"], p["mu"], p["Delta"], p["K"])
+    t = time.time()
+    gs = O.ground_state(h, p["sector"], want_vector=False, tol=1e-10)
+    print(f"held {k}: Delta={p['Delta']:.4f} K={p['K']:.4f} E0={gs['E0']:.10f} ({time.time() - t:.0f} s)", flush=True)
+    return gs["E0"]
+
+
+def held(jobs):
+    from concurrent.futures import ProcessPoolExecutor
+    pts = W.warmstart_points("held")
+    with ProcessPoolExecutor(jobs) as ex:
+        E0 = list(ex.map(held_one, range(len(pts))))
+    with open(OUT_HELD, "w") as f:
+        json.dump({"E0": E0, "Delta": [p["Delta"] for p in pts], "K": [p["K"] for p in pts],
+                   "sector": list(pts[0]["sector"]), "L": pts[0]["L"], "d": pts[0]["d"],
+                   "method": "eigsh (tol 1e-10) on the even-parity sector"}, f, indent=1)
 
 
 def entries():
@@ -49,4 +75,8 @@ def main(names):
 
 
 if __name__ == "__main__":
-    main(sys.argv[1:])
+    if "--warmstart-held" in sys.argv:
+        j = sys.argv.index("--jobs") if "--jobs" in sys.argv else -1
+        held(int(sys.argv[j + 1]) if j >= 0 else 4)
+    else:
+        main(sys.argv[1:])
