@@ -262,11 +262,18 @@ int fock_bfgs_minimize(int n, double *x, fock_objective_fn fn, void *ctx, double
  *   0: each XCD takes a contiguous run of tiles, natural order (default);
  *   1: contiguous runs, the highest free digit fastest;
  *   2: each XCD takes an octant of the three top digits, natural order;
- *   3: octants, the three top digits fastest.
- * Results do not depend on the schedule (partials are indexed by tile), only
- * the L2 reuse of neighbour rows does.  Process-wide; schemes that do not
- * divide the tiles over the 8 XCDs evenly run as scheme 0. */
-enum { FOCK_SCHED_NUM = 4 };
+ *   3: octants, the three top digits fastest;
+ *   4: two passes for fock_apply_H: the first stages the rows of the top m
+ *      modes (d^m <= 512 rows) in LDS and applies the bonds among them and the
+ *      ring bond, writing H psi; the second runs the contiguous tiles of
+ *      scheme 0 for the remaining bonds and the diagonal and adds in place.
+ *      Fewer neighbour rows cross XCDs at the price of one more state
+ *      read + write.  Pool scoring runs as scheme 0.
+ * Schemes 0-3 give bit-identical results (partials are indexed by tile);
+ * scheme 4 sums the bond terms of a row in another order (FP32 rounding
+ * level).  Process-wide; schemes 1-3 that do not divide the tiles over the 8
+ * XCDs evenly run as scheme 0. */
+enum { FOCK_SCHED_TWO_PASS = 4, FOCK_SCHED_NUM = 5 };
 int fock_set_stencil_schedule(int scheme);
 int fock_get_stencil_schedule(void);
 /* Host-side copy of scheme's permutation for n tiles (order[b] = tile of

@@ -146,6 +146,8 @@ int make_ctx(const fock_ham_t &ham, uint32_t namp, int P, int n, void *ws, size_
   {
     int rc = stencil_order_table(ham.L, ham.d, apply_h_blocks(c->h), &c->h.order);
     if (rc) return rc;
+    if (stencil_schedule() == FOCK_SCHED_TWO_PASS)
+      c->h.hi_m = apply_h_hi_modes(ham.L, ham.d, c->h.periodic_wrap);
   }
   c->s = s;
   c->ws = (char *)ws;

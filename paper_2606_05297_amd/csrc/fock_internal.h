@@ -49,6 +49,8 @@ struct HamArgs {
   int srow[kMaxL];    // d^(r-1) for r >= 1: stride of mode r in rows
   float sq[kMaxD + 1];  // sqrt(0..d)
   const int *order;   // tile processed by workgroup b (device table), or null: contiguous runs per XCD
+  int hi_m;           // two-pass stencil: bonds among the top hi_m modes (and the ring bond) are applied
+                      // by a first pass that stages those modes in LDS; 0 = single pass
 };
 
 // ---------------------------------------------------------------- pool gradients
@@ -135,6 +137,7 @@ int launch_apply_h(const HamArgs &h, const float2 *psi, float2 *hpsi, double *pa
 int apply_h_blocks(const HamArgs &h);
 // Rows per workgroup tile of the stencil-type kernels (apply-H, pool gradients).
 int apply_h_tile_rows(int L, int d);
+int apply_h_hi_modes(int L, int d, int periodic_wrap);
 int launch_pool(const PoolArgs &a, const PoolPair *pairs, const PoolDiag *diags, const float2 *psi,
                 const float2 *hpsi, double *partial, int *nblocks, hipStream_t s);
 int pool_blocks(const PoolArgs &a);

@@ -297,7 +297,7 @@ int stencil_schedule() { return g_sched.load(); }
 int stencil_order_table(int L, int d, int ntiles, const int **order) {
   *order = nullptr;
   const int scheme = g_sched.load();
-  if (scheme == 0) return FOCK_OK;
+  if (scheme == 0 || scheme == FOCK_SCHED_TWO_PASS) return FOCK_OK;
   int dev = 0;
   FOCK_HIP(hipGetDevice(&dev));
   std::lock_guard<std::mutex> lk(g_ord_mu);
@@ -330,7 +330,7 @@ extern "C" int fock_get_stencil_schedule(void) { return fock::g_sched.load(); }
 extern "C" int fock_stencil_schedule_table(int L, int d, int scheme, int *order, int n) {
   if (!order || n <= 0) return fock::set_error(FOCK_ERR_ARG, "NULL or empty order buffer");
   std::vector<int> ord;
-  if (scheme == 0 || !fock::build_tile_order(d, n, scheme, &ord)) {
+  if (scheme == 0 || scheme == FOCK_SCHED_TWO_PASS || !fock::build_tile_order(d, n, scheme, &ord)) {
     for (int b = 0; b < n; ++b) {
       const int q = n >> 3;
       order[b] = b >= (q << 3) ? b : (b & 7) * q + (b >> 3);

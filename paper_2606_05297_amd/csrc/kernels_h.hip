@@ -22,7 +22,7 @@ template <int D>
 __global__ __launch_bounds__(kBlock) void k_apply_h(const float2 *__restrict__ psi, float2 *__restrict__ hpsi,
                                                     double *__restrict__ partial, HamArgs h) {
   __shared__ double red[4];
-  __shared__ float4 tile4[(TileCfg<D>::MAXROWS * TileCfg<D>::RS + 1) / 2];
+  __shared__ float4 tile4[TileCfg<D>::PWORDS];
   const int vb = h.order ? h.order[blockIdx.x] : xcd_remap(blockIdx.x, gridDim.x);
   float e = 0.f, nn = 0.f;
   hblock<D>(vb, psi, hpsi, h, reinterpret_cast<float2 *>(tile4), e, nn);
@@ -32,6 +32,15 @@ __global__ __launch_bounds__(kBlock) void k_apply_h(const float2 *__restrict__ p
     partial[2 * vb] = se;
     partial[2 * vb + 1] = sn;
   }
+}
+
+// First pass of the two-pass stencil (see hblock_hi); tile t = workgroup's
+// virtual index.
+template <int D>
+__global__ __launch_bounds__(kBlock) void k_apply_h_hi(const float2 *__restrict__ psi, float2 *__restrict__ hpsi,
+                                                       HamArgs h) {
+  __shared__ float4 tile4[TileCfg<D>::PWORDS];
+  hblock_hi<D>(xcd_remap(blockIdx.x, gridDim.x), psi, hpsi, h, reinterpret_cast<float2 *>(tile4));
 }
 
 __global__ __launch_bounds__(kBlock) void k_reduce(const double *__restrict__ partial, int nblocks, int ncols,
@@ -87,8 +96,27 @@ int apply_h_tile_rows(int L, int d) {
 
 int apply_h_blocks(const HamArgs &h) { return h.nrows / apply_h_tile_rows(h.L, h.d); }
 
+// Number of top modes the first pass of the two-pass stencil stages in LDS:
+// the most with d^m rows fitting the tile and not reaching the single-pass
+// tile's modes 0..K; 0 when that leaves no bond to take over.
+int apply_h_hi_modes(int L, int d, int periodic_wrap) {
+  const int T = apply_h_tile_rows(L, d);
+  int K = 0;
+  for (int t = 1; t < T; t *= d) ++K;
+  const int maxrows = (4096 / d) < 512 ? (4096 / d) : 512;
+  int m = 0;
+  for (int t = d; t <= maxrows && m < L - 1 - K; t *= d) ++m;
+  if (m < 2 && !(m == 1 && periodic_wrap)) return 0;
+  return m;
+}
+
 template <int D>
 static void launch_h_t(const HamArgs &h, const float2 *psi, float2 *hpsi, double *partial, int G, hipStream_t s) {
+  if (h.hi_m > 0) {
+    int GA = 1;
+    for (int r = 1; r < h.L - h.hi_m; ++r) GA *= h.d;
+    hipLaunchKernelGGL(k_apply_h_hi<D>, dim3(GA), dim3(kBlock), 0, s, psi, hpsi, h);
+  }
   hipLaunchKernelGGL(k_apply_h<D>, dim3(G), dim3(kBlock), 0, s, psi, hpsi, partial, h);
 }
 

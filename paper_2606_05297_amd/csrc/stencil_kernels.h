@@ -15,6 +15,7 @@ template <int D>
 struct TileCfg {
   static constexpr int RS = (D % 2 == 0) ? D + 2 : D + 1;  // LDS row stride (float2)
   static constexpr int MAXROWS = (4096 / D) < 512 ? (4096 / D) : 512;
+  static constexpr int PWORDS = (MAXROWS * RS + 1) / 2;     // float4 words of a tile
 };
 
 __device__ __forceinline__ int tile_k(int L, int D, int maxrows) {
@@ -69,7 +70,7 @@ __device__ __forceinline__ void load_tile(float2 *tile, const float2 *__restrict
 }
 
 // Work of tile vb: H psi on its rows; e, nn receive this thread's share of
-// <psi|H|psi> and <psi|psi>.  tile: TileCfg<D>::MAXROWS * RS float2 of LDS
+// <psi|H|psi> and <psi|psi>.  tile: TileCfg<D>::PWORDS float4 of LDS
 // (16-byte aligned).  Contains barriers: every thread must call it.
 template <int D>
 __device__ __forceinline__ void hblock(int vb, const float2 *__restrict__ psi, float2 *__restrict__ hpsi,
@@ -143,7 +144,8 @@ __device__ __forceinline__ void hblock(int vb, const float2 *__restrict__ psi, f
         off[3] = v3 ? -si - sj : 0; cf[3] = v3 ? Dl * smi * smj : 0.f;
       };
       const int nt = Dl != 0.f ? 4 : 2;  // pairing terms only when Delta != 0
-      for (; r + 1 < h.L; r += 2) {
+      const int rend = h.L - h.hi_m + (h.hi_m > 0 ? 1 : 0);  // bonds (r-1, r) with r < rend are this pass's
+      for (; r + 1 < rend; r += 2) {
         int oa[4], ob[4];
         float ca[4], cb[4];
         bond_offsets(r, oa, ca);
@@ -162,7 +164,7 @@ __device__ __forceinline__ void hblock(int vb, const float2 *__restrict__ psi, f
             axpy_v<D>(acc, vb2[k], cb[k]);
           }
       }
-      if (r < h.L) {
+      if (r < rend) {
         int oa[4];
         float ca[4];
         bond_offsets(r, oa, ca);
@@ -176,7 +178,7 @@ __device__ __forceinline__ void hblock(int vb, const float2 *__restrict__ psi, f
       }
     }
     // bonds touching mode 0: (0, 1) and the ring bond (0, L-1)
-    const int nb0 = (h.L >= 2 ? 1 : 0) + h.periodic_wrap;
+    const int nb0 = (h.L >= 2 ? 1 : 0) + (h.hi_m > 0 ? 0 : h.periodic_wrap);
     for (int b = 0; b < nb0; ++b) {
       const int j = (b == 0) ? 1 : h.L - 1;
       const int nj = (b == 0) ? n1 : nprev;
@@ -227,6 +229,16 @@ __device__ __forceinline__ void hblock(int vb, const float2 *__restrict__ psi, f
         }
       }
     }
+    // two-pass: the first pass left its bonds' share of this row in hpsi
+    if (h.hi_m > 0) {
+      float2 pa[D];
+      load_row<D>(hpsi + (size_t)row * D, pa);
+#pragma unroll
+      for (int q = 0; q < D; ++q) {
+        acc[q].x += pa[q].x;
+        acc[q].y += pa[q].y;
+      }
+    }
     // diagonal, energy and norm
 #pragma unroll
     for (int q = 0; q < D; ++q) {
@@ -244,6 +256,113 @@ __device__ __forceinline__ void hblock(int vb, const float2 *__restrict__ psi, f
   __syncthreads();
 }
 
+
+// First pass of the two-pass stencil.  Tile t holds the rows whose digits of
+// the top m = h.hi_m modes take all values, for fixed digits of modes
+// 1..L-1-m (row = t + lr S, S = d^(L-1-m), lr = the top digits).  It applies
+// the bonds among the top modes and the ring bond (0, L-1) with neighbours
+// from LDS and writes that share of H psi; the second pass (hblock with
+// hi_m > 0) adds the remaining bonds and the diagonal in place.
+template <int D>
+__device__ __forceinline__ void hblock_hi(int t, const float2 *__restrict__ psi, float2 *__restrict__ hpsi,
+                                          const HamArgs &h, float2 *tile) {
+  constexpr int RS = TileCfg<D>::RS;
+  const int m = h.hi_m, L = h.L;
+  int T = 1;
+  for (int k = 0; k < m; ++k) T *= D;
+  const int S = h.srow[L - m];  // d^(L-1-m): row stride of the lowest top mode
+  if constexpr (D % 2 == 0) {
+    for (int e = threadIdx.x; e < T * D / 2; e += kBlock) {
+      const int lr = e / (D / 2), c = e % (D / 2);
+      reinterpret_cast<float4 *>(tile + lr * RS)[c] =
+          reinterpret_cast<const float4 *>(psi + ((size_t)t + (size_t)lr * S) * D)[c];
+    }
+  } else {
+    for (int e = threadIdx.x; e < T * D; e += kBlock)
+      tile[(e / D) * RS + e % D] = psi[((size_t)t + (size_t)(e / D) * S) * D + e % D];
+  }
+  __syncthreads();
+  const float J = h.J, Dl = h.Delta;
+  for (int lr = threadIdx.x; lr < T; lr += kBlock) {
+    float2 acc[D];
+#pragma unroll
+    for (int q = 0; q < D; ++q) acc[q] = make_float2(0.f, 0.f);
+    int dg[kMaxL];
+    {
+      int u = lr;
+      for (int k = 0; k < m; ++k) {
+        dg[k] = u % D;
+        u /= D;
+      }
+    }
+    // bonds (L-m+k-1, L-m+k), k = 1..m-1, local strides D^(k-1), D^k
+    int si = 1;
+    for (int k = 1; k < m; ++k) {
+      const int sj = si * D;
+      const int ni = dg[k - 1], nj = dg[k];
+      const float smi = sqrtf((float)ni), spi = sqrtf((float)ni + 1.f);
+      const float smj = sqrtf((float)nj), spj = sqrtf((float)nj + 1.f);
+      float2 v[D];
+      if (J != 0.f) {
+        if (ni >= 1 && nj <= D - 2) { lds_row<D>(tile, lr - si + sj, v); axpy_v<D>(acc, v, -J * smi * spj); }
+        if (ni <= D - 2 && nj >= 1) { lds_row<D>(tile, lr + si - sj, v); axpy_v<D>(acc, v, -J * spi * smj); }
+      }
+      if (Dl != 0.f) {
+        if (ni <= D - 2 && nj <= D - 2) { lds_row<D>(tile, lr + si + sj, v); axpy_v<D>(acc, v, Dl * spi * spj); }
+        if (ni >= 1 && nj >= 1) { lds_row<D>(tile, lr - si - sj, v); axpy_v<D>(acc, v, Dl * smi * smj); }
+      }
+      si = sj;
+    }
+    // ring bond (0, L-1): mode 0 inside the row, mode L-1 = local digit m-1
+    if (h.periodic_wrap) {
+      const int nj = dg[m - 1], sj = si;  // si = D^(m-1) here
+      if (nj <= D - 2) {
+        float2 P[D];
+        lds_row<D>(tile, lr + sj, P);
+        const float spj = sqrtf((float)nj + 1.f);
+        if (J != 0.f) {
+          const float c = -J * spj;
+#pragma unroll
+          for (int q = 1; q < D; ++q) {
+            acc[q].x = fmaf(c * h.sq[q], P[q - 1].x, acc[q].x);
+            acc[q].y = fmaf(c * h.sq[q], P[q - 1].y, acc[q].y);
+          }
+        }
+        if (Dl != 0.f) {
+          const float c = Dl * spj;
+#pragma unroll
+          for (int q = 0; q < D - 1; ++q) {
+            acc[q].x = fmaf(c * h.sq[q + 1], P[q + 1].x, acc[q].x);
+            acc[q].y = fmaf(c * h.sq[q + 1], P[q + 1].y, acc[q].y);
+          }
+        }
+      }
+      if (nj >= 1) {
+        float2 Mv[D];
+        lds_row<D>(tile, lr - sj, Mv);
+        const float smj = sqrtf((float)nj);
+        if (J != 0.f) {
+          const float c = -J * smj;
+#pragma unroll
+          for (int q = 0; q < D - 1; ++q) {
+            acc[q].x = fmaf(c * h.sq[q + 1], Mv[q + 1].x, acc[q].x);
+            acc[q].y = fmaf(c * h.sq[q + 1], Mv[q + 1].y, acc[q].y);
+          }
+        }
+        if (Dl != 0.f) {
+          const float c = Dl * smj;
+#pragma unroll
+          for (int q = 1; q < D; ++q) {
+            acc[q].x = fmaf(c * h.sq[q], Mv[q - 1].x, acc[q].x);
+            acc[q].y = fmaf(c * h.sq[q], Mv[q - 1].y, acc[q].y);
+          }
+        }
+      }
+    }
+    store_row<D>(hpsi + ((size_t)t + (size_t)lr * S) * D, acc);
+  }
+  __syncthreads();
+}
 
 // ---------------------------------------------------------------- pool scoring (Eq. grad)
 // z += conj(a) * b

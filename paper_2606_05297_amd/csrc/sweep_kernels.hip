@@ -55,7 +55,7 @@ template <int D>
 __global__ __launch_bounds__(kBlock) void k_sweep_h(const SweepHItem *__restrict__ items, int n,
                                                     const HamArgs *__restrict__ hams, const int *__restrict__ active) {
   __shared__ double red[4];
-  __shared__ float4 tile4[(TileCfg<D>::MAXROWS * TileCfg<D>::RS + 1) / 2];
+  __shared__ float4 tile4[TileCfg<D>::PWORDS];
   for (int it = blockIdx.x; it < n; it += gridDim.x) {
     const SweepHItem g = items[it];
     if (!active[g.p]) continue;

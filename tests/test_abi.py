@@ -157,7 +157,7 @@ def test_stencil_schedules_are_permutations():
             T *= d
             K += 1
         n = d ** (L - 1) // T
-        for s in range(4):
+        for s in range(5):
             o = lib.stencil_schedule_table(L, d, s, n)
             assert sorted(o.tolist()) == list(range(n)), (L, d, s)
             if s >= 2 and n % 8 == 0 and d % 2 == 0 and n >= 64 and (L - 1 - K) >= 3:

@@ -56,10 +56,23 @@ SMALL = [
 ]
 
 
-@pytest.mark.parametrize("case", SMALL, ids=lambda c: f"L{c[0]}d{c[1]}{'p' if c[2] else 'o'}")
-def test_apply_H_parity(case):
+@pytest.fixture
+def schedule(request):
+    prev = lib.get_stencil_schedule()
+    lib.set_stencil_schedule(request.param)
+    yield request.param
+    lib.set_stencil_schedule(prev)
+
+
+SMALL_2P = SMALL + [(7, 5, True, 1.0, 0.0, 0.3, 0.45, 0.15), (8, 4, True, 1.0, 1.5, 0.0, 0.0, 0.0),
+                    (6, 6, False, 1.0, 0.0, 0.0, 0.5, 0.2)]
+
+
+@pytest.mark.parametrize("schedule", [0, 4], indirect=True, ids=["1pass", "2pass"])
+@pytest.mark.parametrize("case", SMALL_2P, ids=lambda c: f"L{c[0]}d{c[1]}{'p' if c[2] else 'o'}")
+def test_apply_H_parity(case, schedule):
     L, d, per, J, U, mu, Dl, K = case
-    say("apply_H", case)
+    say("apply_H", case, "schedule", schedule)
     ho, hl = ham_pair(L, d, per, J, U, mu, Dl, K)
     psi = W.random_state(L, d, seed=L * 100 + d)
     ref = O.apply_H(ho, psi.astype(np.complex128))
@@ -306,7 +319,7 @@ def test_stencil_schedules_bitwise_equal_and_autotune(kk_full, tmp_path):
     prev = lib.get_stencil_schedule()
     try:
         base = None
-        for s in range(4):
+        for s in range(4):  # schemes 0-3 only reorder tiles
             lib.set_stencil_schedule(s)
             E, n2 = lib.apply_H(hl, x, y, ws)
             g = lib.pool_grads(hl, c["pool"], x, y, ws)
@@ -317,10 +330,21 @@ def test_stencil_schedules_bitwise_equal_and_autotune(kk_full, tmp_path):
                 assert cur[0] == base[0] and cur[1] == base[1], s
                 assert np.array_equal(cur[2], base[2]), s
                 assert np.array_equal(cur[3], base[3]), s
+        # two passes: same values to FP32 rounding, the exact ones at sampled rows
+        lib.set_stencil_schedule(4)
+        E4, n24 = lib.apply_H(hl, x, y, ws)
+        got = host(y)
+        assert abs(E4 - base[0]) <= 1e-5 * abs(base[0]) and abs(n24 - base[1]) <= 1e-6
+        p128 = psi.astype(np.complex128)
+        rng = np.random.default_rng(7)
+        idx = np.concatenate([rng.integers(0, 8**8, 1000), [0, 8**8 - 1, 8**7, 8**7 - 1]])
+        ref = np.array([O.apply_H_at(ho, p128, int(k)) for k in idx])
+        assert np.abs(got[idx] - ref).max() <= 2e-5 * np.abs(ref).max()
+        assert np.abs(got - base[2]).max() <= 2e-5 * np.abs(base[2]).max()
         cache = str(tmp_path / "stencil.jsonl")
         best = lib.autotune_stencil(hl, x, y, ws, cache)
         say("autotuned schedule", best)
-        assert 0 <= best < 4 and lib.get_stencil_schedule() == best
+        assert 0 <= best < 5 and lib.get_stencil_schedule() == best
         lib.set_stencil_schedule(0)
         assert lib.autotune_stencil(hl, x, y, ws, cache) == best
     finally:
