@@ -9,8 +9,10 @@ angles with energy + adjoint-gradient evaluations (gate build, forward gates,
 H psi, fused reverse sweep).  W warm-up steps run on a separate ADAPT instance;
 the K timed steps are steps 1..K of a fresh run from the vacuum.  Per-kernel
 durations come from HIP events recorded on the launch stream inside the timed
-region; the roofline entry is the kernel with the largest total time.
-Prints one JSON line.
+region; the roofline entry is the kernel with the largest total time.  After
+the timed region, "variants" reports the same workload with central-difference
+BFGS gradients (the plain method, first few steps) and with Hessian recycling
+(Appendix D).  Prints one JSON line.
 """
 from __future__ import annotations
 
@@ -81,6 +83,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--grad-mode", choices=["adjoint", "fd"], default="adjoint")
+    ap.add_argument("--no-variants", action="store_true", help="skip the FD-gradient and Hessian-recycling lines")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU design is "
@@ -168,6 +171,28 @@ def main():
                   "bfgs_evals_per_step": evals, "n_params": reps[-1]["n_params"],
                   "selected": [r["k_sel"] for r in reps]},
     }
+    # the same workload by other gradient / optimiser settings (steps 1..k of a fresh run each)
+    def variant(k, **kw):
+        a = lib.Adapt(hl, cfg["pool"], psi0, max_iters=cfg["max_iters"], **kw)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        rs = [a.step() for _ in range(k)]
+        torch.cuda.synchronize()
+        dt_v = time.perf_counter() - t
+        a.close()
+        return {"steps": k, "steps_per_s": k / dt_v, "E_final": rs[-1]["E"],
+                "bfgs_evals_per_step": float(np.mean([r["bfgs_evals"] for r in rs])),
+                "bfgs_iters_per_step": float(np.mean([r["bfgs_iters"] for r in rs]))}
+
+    if not args.no_variants and args.grad_mode == "adjoint":
+        print("[bench] variants: central-difference gradients, Hessian recycling", file=sys.stderr, flush=True)
+        out["variants"] = {
+            "plain_fd_gradients": variant(args.steps, grad_mode=1),
+            "adjoint": {"steps": args.steps, "steps_per_s": value, "E_final": reps[-1]["E"],
+                        "bfgs_evals_per_step": evals,
+                        "bfgs_iters_per_step": float(np.mean([r["bfgs_iters"] for r in reps]))},
+            "adjoint_hessian_recycling": variant(args.steps, recycle_hessian=True),
+        }
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(cfg, ops[0], th[0], evals)
