@@ -84,6 +84,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--grad-mode", choices=["adjoint", "fd"], default="adjoint")
     ap.add_argument("--no-variants", action="store_true", help="skip the FD-gradient and Hessian-recycling lines")
+    ap.add_argument("--gate-fusion", type=int, choices=[0, 1, 2], default=None,
+                    help="0 per-gate passes (library default), 1 fused forward circuit, 2 fused forward and adjoint")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU design is "
@@ -97,6 +99,8 @@ def main():
     from paper_2606_05297_amd import lib
 
     torch.cuda.set_device(0)
+    if args.gate_fusion is not None:
+        lib.set_gate_fusion(args.gate_fusion)
     cfg = W.config("kk_l8_d8")
     hl = lib.ham_from(cfg)
     n = cfg["d"] ** cfg["L"]
@@ -163,7 +167,8 @@ def main():
         "config": {"workload": (f"Kitaev-Kerr open chain L=8 d=8 (16,777,216 amplitudes), J=1 Delta=0.5 K=0.2, "
                                 f"vacuum start, 28-op nearest-neighbour pool, ADAPT steps 1..{args.steps} with "
                                 f"{args.grad_mode} BFGS gradients"),
-                   "L": 8, "d": 8, "pool": len(cfg["pool"]), "grad_mode": args.grad_mode},
+                   "L": 8, "d": 8, "pool": len(cfg["pool"]), "grad_mode": args.grad_mode,
+                   "gate_fusion": lib.get_gate_fusion()},
         "roofline": roof,
         "apply_h": kernel_entry(0),
         "kernels": {KERNEL_NAMES[k]: kernel_entry(k) for k in KERNEL_NAMES if prof[k]["launches"]},

@@ -254,6 +254,22 @@ typedef int (*fock_objective_fn)(void *ctx, int n, const double *x, double *f, d
 int fock_bfgs_minimize(int n, double *x, fock_objective_fn fn, void *ctx, double gtol, int maxiter, double *Hinv,
                        int *iters, int *evals, double *fmin, int *status);
 
+/* ------------------------------------------------------------------ gate fusion */
+
+/* Circuits evaluated by fock_energy_grad_adjoint and adapt_step run runs of
+ * consecutive gates whose modes (with mode 0) fit one tile of d^s <= 4096
+ * amplitudes as one pass: the tile is staged in LDS and the gates are applied
+ * there one after another (forward), or the tiles of phi and lambda are staged
+ * and the reverse steps of the run are taken there (adjoint sweep).  Same
+ * operations as the per-gate kernels (same block arithmetic); gradient partials
+ * are summed over other tiles, so results agree to FP32/FP64 rounding, not
+ * bitwise.  d in {2, 4, 6, 8}; process-wide mode: FOCK_FUSE_OFF (the
+ * default), FOCK_FUSE_FORWARD (forward circuit only) or FOCK_FUSE_ALL (forward
+ * and adjoint sweep).  The batched sweep does not fuse. */
+enum { FOCK_FUSE_OFF = 0, FOCK_FUSE_FORWARD = 1, FOCK_FUSE_ALL = 2 };
+int fock_set_gate_fusion(int mode);
+int fock_get_gate_fusion(void);
+
 /* ------------------------------------------------------------------ stencil schedules */
 
 /* Order in which the workgroups of fock_apply_H and fock_pool_grads visit the

@@ -35,6 +35,7 @@ SOURCES = [
     "api.cpp",
     "adapt.cpp",
     "bfgs.cpp",
+    "fuse_kernels.hip",
     "mlp_kernels.hip",
     "mlp.cpp",
 ]

@@ -1,12 +1,14 @@
 // C ABI of libfock: argument validation, workspace layout, the energy /
 // adjoint-gradient pipeline, pool scoring, and the ADAPT state machine.
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstring>
 #include <map>
 #include <vector>
 
 #include "bfgs.h"
+#include "fuse_internal.h"
 #include "pipeline.h"
 
 namespace fock {
@@ -163,7 +165,7 @@ int make_ctx(const fock_ham_t &ham, uint32_t namp, int P, int n, void *ws, size_
   return FOCK_OK;
 }
 
-int stage_gates(Ctx &c, const fock_op_t *ops, const double *theta, int n) {
+int stage_gates(Ctx &c, const fock_op_t *ops, const double *theta, int n, const int *nblk) {
   const int stride = gate_stride(c.g.d);
   const size_t bt = sizeof(double) * n, br = sizeof(GateRec) * n;
   int rc = tl_in.reserve(c.L.recs + br);
@@ -177,7 +179,7 @@ int stage_gates(Ctx &c, const fock_op_t *ops, const double *theta, int n) {
     th[k] = theta[k];
     rec[k].type = ops[k].type;
     rec[k].u_off = k * stride;
-    rec[k].nblk = is_single_mode(ops[k].type) ? Gd : gate_blocks_count(c.g, ops[k].i);
+    rec[k].nblk = nblk && nblk[k] > 0 ? nblk[k] : is_single_mode(ops[k].type) ? Gd : gate_blocks_count(c.g, ops[k].i);
     rec[k].pad = 0;
   }
   (void)bt;
@@ -215,19 +217,132 @@ int fetch_results(Ctx &c, int count, double *host) {
   return FOCK_OK;
 }
 
+// ---------------------------------------------------------------- gate fusion
+static std::atomic<int> g_fuse{FOCK_FUSE_OFF};
+
+bool fuse_supported(int d) { return d == 2 || d == 4 || d == 6 || d == 8; }
+
+int fuse_max_modes(int L, int d) {
+  int s = 0;
+  for (long t = d; t <= 4096 && s < kMaxFuseModes && s < L; t *= d) ++s;
+  return s;
+}
+
+// Greedy grouping: a group grows while the union of its gates' modes and mode
+// 0 fits smax modes; its tile is that union filled up with the lowest other
+// modes.  Kept when it has at least two gates and its tile holds mode 1 (rows
+// of d^2 contiguous amplitudes) or at least three gates; groups whose tile
+// count exceeds the partial-row stride are not fused.
+static void plan_gate_groups(const Ctx &c, const fock_op_t *ops, int n, std::vector<GateGroup> *out) {
+  out->clear();
+  const int L = c.g.L, d = c.g.d, smax = fuse_max_modes(L, d);
+  const bool on = g_fuse.load() != FOCK_FUSE_OFF && fuse_supported(d) && smax >= 2;
+  int k = 0;
+  while (k < n) {
+    GateGroup gr;
+    gr.k0 = k;
+    gr.k1 = k + 1;
+    gr.s = 0;
+    if (on) {
+      unsigned mask = 1u;  // modes in the union (mode 0 always)
+      auto modes = [&](const fock_op_t &o) { return is_single_mode(o.type) ? (1u << o.i) : ((1u << o.i) | (1u << o.j)); };
+      mask |= modes(ops[k]);
+      int k1 = k + 1;
+      while (k1 < n && k1 - k < kMaxFuseGates) {
+        const unsigned nm = mask | modes(ops[k1]);
+        if (__builtin_popcount(nm) > smax) break;
+        mask = nm;
+        ++k1;
+      }
+      for (int r = 0; r < L && __builtin_popcount(mask) < smax; ++r) mask |= 1u << r;
+      const int size = k1 - k;
+      const int s = __builtin_popcount(mask);
+      long ntile = 1;
+      for (int r = 0; r < L - s; ++r) ntile *= d;
+      if (size >= 2 && ((mask & 2u) || size >= 3) && ntile <= c.L.rs) {
+        gr.k1 = k1;
+        gr.s = 0;
+        for (int r = 0; r < L; ++r)
+          if (mask & (1u << r)) gr.m[gr.s++] = r;
+      }
+    }
+    out->push_back(gr);
+    k = gr.k1;
+  }
+}
+
+static FuseArgs make_fuse_args(const Ctx &c, const GateGroup &gr, const fock_op_t *ops) {
+  FuseArgs a;
+  memset(&a, 0, sizeof(a));
+  const int L = c.g.L, d = c.g.d;
+  std::vector<uint32_t> pw(L, 1);
+  for (int r = 1; r < L; ++r) pw[r] = pw[r - 1] * (uint32_t)d;
+  a.s = gr.s;
+  int pos[kMaxL];
+  for (int r = 0; r < L; ++r) pos[r] = -1;
+  for (int k = 0; k < gr.s; ++k) {
+    a.tstride[k] = pw[gr.m[k]];
+    pos[gr.m[k]] = k;
+  }
+  a.nc = 0;
+  a.ntile = 1;
+  for (int r = 0; r < L; ++r)
+    if (pos[r] < 0) {
+      a.cstride[a.nc++] = pw[r];
+      a.ntile *= d;
+    }
+  int off = 0;
+  for (int sb = 0; sb <= 2 * d - 2; ++sb) {
+    a.boff[sb] = off;
+    const int b = blk_hi(KIND_SUM, d, sb) - blk_lo(KIND_SUM, d, sb) + 1;
+    off += b * b;
+  }
+  for (int t = 0; t < 5; ++t) a.A[t] = c.T.A[t];
+  a.ng = gr.k1 - gr.k0;
+  for (int q = 0; q < a.ng; ++q) {
+    const int k = gr.k0 + q;
+    const fock_op_t &o = ops[k];
+    FuseGate &g = a.g[q];
+    g.type = o.type;
+    g.kind = is_single_mode(o.type) ? 0 : gate_kind(o.type);
+    g.ki = pos[o.i];
+    g.kj = is_single_mode(o.type) ? -1 : pos[o.j];
+    g.u_off = k * gate_stride(d);
+    g.k = k;
+  }
+  return a;
+}
+
 // Energy and (optionally) all dE/dtheta of a circuit; see fock_energy_grad_adjoint.
 int run_circuit(Ctx &c, const fock_op_t *ops, const double *theta, int n, const void *psi0, float2 *phi,
                        float2 *lam, bool grad, double *E, double *norm2, double *dE) {
   int rc = FOCK_OK;
+  std::vector<GateGroup> groups;
+  plan_gate_groups(c, ops, n, &groups);
+  const bool fuse_rev = g_fuse.load() == FOCK_FUSE_ALL;
   if (n > 0) {
-    rc = stage_gates(c, ops, theta, n);
+    std::vector<int> nblk(n, 0);
+    for (const GateGroup &gr : groups)
+      if (gr.s > 0 && fuse_rev) {
+        int nt = 1;
+        for (int r = 0; r < c.g.L - gr.s; ++r) nt *= c.g.d;
+        for (int k = gr.k0; k < gr.k1; ++k) nblk[k] = nt;
+      }
+    rc = stage_gates(c, ops, theta, n, nblk.data());
     if (rc) return rc;
   }
+  const float2 *utab = (const float2 *)(c.ws + c.L.utab);
   // the first gate reads psi0 and writes phi (no separate copy)
   if (n == 0)
     FOCK_HIP(hipMemcpyAsync(phi, psi0, sizeof(float2) * (size_t)c.g.n_amp, hipMemcpyDeviceToDevice, c.s));
-  for (int k = 0; k < n; ++k) {
-    rc = forward_gate(c, ops[k], k, false, k == 0 ? (const float2 *)psi0 : phi, phi);
+  for (const GateGroup &gr : groups) {
+    const float2 *src = gr.k0 == 0 ? (const float2 *)psi0 : phi;
+    if (gr.s == 0) {
+      rc = forward_gate(c, ops[gr.k0], gr.k0, false, src, phi);
+    } else {
+      ProfScope ps(FOCK_K_GATE, c.s, 16.0 * c.g.n_amp);
+      rc = launch_fuse_fwd(c.g.d, make_fuse_args(c, gr, ops), src, phi, utab, c.s);
+    }
     if (rc) return rc;
   }
   double *res = (double *)(c.ws + c.L.result);
@@ -237,7 +352,15 @@ int run_circuit(Ctx &c, const fock_op_t *ops, const double *theta, int n, const 
     double *part = (double *)(c.ws + c.L.partial);
     const int stride = gate_stride(c.g.d);
     const float2 *U0 = (const float2 *)(c.ws + c.L.utab);
-    for (int k = n - 1; k >= 0; --k) {
+    for (int gi = (int)groups.size() - 1; gi >= 0; --gi) {
+      const GateGroup &gr = groups[gi];
+      if (gr.s > 0 && fuse_rev) {
+        ProfScope ps(FOCK_K_ADJ, c.s, 32.0 * c.g.n_amp);
+        rc = launch_fuse_adj(c.g.d, make_fuse_args(c, gr, ops), phi, lam, utab, part, c.L.rs, c.s);
+        if (rc) return rc;
+        continue;
+      }
+      for (int k = gr.k1 - 1; k >= gr.k0; --k) {
       const fock_op_t &op = ops[k];
       const float2 *U = U0 + (size_t)k * stride;
       double *pk = part + (size_t)k * c.L.rs;
@@ -245,6 +368,7 @@ int run_circuit(Ctx &c, const fock_op_t *ops, const double *theta, int n, const 
       if (is_single_mode(op.type)) rc = launch_diag_adj(c.g, op.i, op.type, U, phi, lam, pk, c.s);
       else rc = launch_gate_adj(c.g, op.i, op.j, gate_kind(op.type), U, c.T.A[op.type], phi, lam, pk, c.s);
       if (rc) return rc;
+      }
     }
     rc = launch_reduce_rows(part, c.L.rs, (const GateRec *)(c.ws + c.L.recs), n, res + 2, c.s);
     if (rc) return rc;
@@ -379,6 +503,15 @@ int fock_apply_H(const fock_ham_t *ham, const void *psi, void *hpsi, double *E, 
   return FOCK_OK;
 }
 
+int fock_set_gate_fusion(int mode) {
+  if (mode < FOCK_FUSE_OFF || mode > FOCK_FUSE_ALL)
+    return set_error(FOCK_ERR_ARG, "gate fusion mode %d not in [0, 2]", mode);
+  g_fuse.store(mode);
+  return FOCK_OK;
+}
+
+int fock_get_gate_fusion(void) { return g_fuse.load(); }
+
 int fock_autotune_stencil(const fock_ham_t *ham, const void *psi, void *hpsi, void *ws, size_t ws_bytes,
                           fock_stream_t stream, const char *cache_path, int *best_scheme) {
   uint32_t namp = 0;
@@ -466,7 +599,7 @@ int fock_apply_gate2(int L, int d, fock_op_t op, double theta, int adjoint, void
   Ctx c;
   rc = make_ctx(ham, namp, 0, 1, ws, ws_bytes, (hipStream_t)stream, &c);
   if (rc) return rc;
-  rc = stage_gates(c, &op, &theta, 1);
+  rc = stage_gates(c, &op, &theta, 1, nullptr);
   if (rc) return rc;
   return forward_gate(c, op, 0, adjoint != 0, (const float2 *)psi, (float2 *)psi);
 }

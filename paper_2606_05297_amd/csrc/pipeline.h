@@ -29,7 +29,7 @@ int check_ptr(const void *p, const char *name);
 HamArgs make_ham_args(const fock_ham_t &h);
 Layout make_layout(uint32_t namp, int L, int d, int P, int n);
 int make_ctx(const fock_ham_t &ham, uint32_t namp, int P, int n, void *ws, size_t ws_bytes, hipStream_t s, Ctx *c);
-int stage_gates(Ctx &c, const fock_op_t *ops, const double *theta, int n);
+int stage_gates(Ctx &c, const fock_op_t *ops, const double *theta, int n, const int *nblk);
 // psi <- O_k src (src == psi: in place)
 int forward_gate(Ctx &c, const fock_op_t &op, int k, bool dag, const float2 *src, float2 *psi);
 int apply_h_dev(Ctx &c, const float2 *psi, float2 *hpsi, double *res2);

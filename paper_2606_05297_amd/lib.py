@@ -510,6 +510,18 @@ def autotune_stencil(h: Ham, psi, hpsi, ws, cache_path=None, stream=None) -> int
     return best.value
 
 
+FUSE_OFF, FUSE_FORWARD, FUSE_ALL = 0, 1, 2
+
+
+def set_gate_fusion(mode: int):
+    """0: per-gate passes (default); 1: fused forward circuit; 2: fused forward and adjoint sweep."""
+    _check(load().fock_set_gate_fusion(int(mode)))
+
+
+def get_gate_fusion() -> int:
+    return int(load().fock_get_gate_fusion())
+
+
 def get_stencil_schedule() -> int:
     return int(load().fock_get_stencil_schedule())
 

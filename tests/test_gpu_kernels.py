@@ -349,3 +349,52 @@ def test_stencil_schedules_bitwise_equal_and_autotune(kk_full, tmp_path):
         assert lib.autotune_stencil(hl, x, y, ws, cache) == best
     finally:
         lib.set_stencil_schedule(prev)
+
+
+FUSE_CASES = [
+    # (L, d, periodic, J, U, mu, Delta, K, ops as (type, i, j))
+    (5, 4, True, 1.0, 0.7, 0.1, 0.4, 0.2,
+     [("HR", 0, 1), ("PR", 1, 2), ("HI", 2, 3), ("KERR", 2, -1), ("DH", 0, 1), ("PI", 3, 4), ("ROT", 0, -1),
+      ("HR", 0, 4), ("PR", 3, 4), ("HR", 0, 1)]),
+    (6, 6, True, 1.0, 4.0, 0.0, 0.0, 0.0,
+     [("HR", 0, 1), ("HR", 1, 2), ("HR", 2, 3), ("HR", 3, 4), ("HR", 4, 5), ("HR", 0, 5), ("KERR", 5, -1),
+      ("ROT", 5, -1), ("DH", 4, 5), ("HI", 1, 2), ("HR", 0, 1)]),
+    (6, 8, False, 1.0, 0.0, 0.0, 0.5, 0.2,
+     [("PR", 0, 1), ("PR", 1, 2), ("PR", 2, 3), ("PR", 3, 4), ("PR", 4, 5), ("HR", 0, 1), ("PR", 1, 2),
+      ("PR", 0, 1), ("PI", 2, 3), ("HI", 2, 3)]),
+]
+
+
+@pytest.mark.parametrize("case", FUSE_CASES, ids=lambda c: f"L{c[0]}d{c[1]}")
+def test_gate_fusion_matches_unfused_and_oracle(case):
+    """Fused gate groups (one pass per run of gates sharing a tile) give the
+    per-gate kernels' energy and gradients to rounding, and the oracle's to
+    the stated tolerances."""
+    L, d, per, J, U, mu, Dl, K, ops = case
+    say("fusion", L, d, len(ops))
+    ho, hl = ham_pair(L, d, per, J, U, mu, Dl, K)
+    rng = np.random.default_rng(L * 10 + d)
+    th = rng.uniform(-0.6, 0.6, len(ops))
+    psi0 = W.random_state(L, d, seed=11, sector=("parity", 0) if Dl != 0 else ("N", L))
+    x0 = dev(psi0)
+    a, b = torch.empty_like(x0), torch.empty_like(x0)
+    ws = lib.workspace(hl, 0, len(ops))
+    prev = lib.get_gate_fusion()
+    res = {}
+    try:
+        for mode in (lib.FUSE_ALL, lib.FUSE_FORWARD, lib.FUSE_OFF):
+            lib.set_gate_fusion(mode)
+            E, n2, g = lib.energy_grad_adjoint(hl, ops, th, x0, a, b, ws)
+            res[mode] = (E, g, host(a))
+    finally:
+        lib.set_gate_fusion(prev)
+    Er, gr, _ = O.energy_and_grad_adjoint(ho, psi0.astype(np.complex128), ops, th)
+    Eu, gu, _ = res[lib.FUSE_OFF]
+    for mode in (lib.FUSE_ALL, lib.FUSE_FORWARD):
+        Ef, gf, phif = res[mode]
+        assert abs(Ef - Eu) <= 1e-6 * max(1.0, abs(Eu)), mode
+        assert np.abs(gf - gu).max() <= 1e-5 * max(1.0, np.abs(gu).max()), mode
+        assert abs(Ef - Er) <= 1e-5 * max(1.0, abs(Er)), mode
+        assert np.abs(gf - gr).max() <= 1e-4 * max(1.0, np.abs(gr).max()), mode
+        # after the reverse sweep phi is back at psi0 (U^+ ... U^+ U ... U = 1)
+        assert np.abs(phif - psi0).max() <= 1e-5, mode

@@ -38,7 +38,17 @@ def entry(p):
     return dict(ham=h, pool=p["pool"], psi0=psi0, warm_ops=wops, warm_theta0=wth)
 
 
-def test_sweep_equals_unbatched_and_oracle(tmp_path):
+@pytest.fixture
+def unfused():
+    """The batched sweep runs gates one per pass; its point-by-point reference
+    must do the same for bitwise equality."""
+    prev = lib.get_gate_fusion()
+    lib.set_gate_fusion(lib.FUSE_OFF)
+    yield
+    lib.set_gate_fusion(prev)
+
+
+def test_sweep_equals_unbatched_and_oracle(tmp_path, unfused):
     pts = small_points()
     say("sweep", [(p["model"], p["L"], p["d"]) for p in pts])
     entries = [entry(p) for p in pts]
