@@ -9,10 +9,12 @@ angles with energy + adjoint-gradient evaluations (gate build, forward gates,
 H psi, fused reverse sweep).  W warm-up steps run on a separate ADAPT instance;
 the K timed steps are steps 1..K of a fresh run from the vacuum.  Per-kernel
 durations come from HIP events recorded on the launch stream inside the timed
-region; the roofline entry is the kernel with the largest total time.  After
-the timed region, "variants" reports the same workload with central-difference
-BFGS gradients (the plain method, first few steps) and with Hessian recycling
-(Appendix D).  Prints one JSON line.
+region; the roofline entry is the kernel with the largest total time.  BFGS
+starts every step from the previous step's inverse Hessian, padded with the
+identity for the new angle (Appendix D); --no-hessian-recycling starts from
+the scaled identity.  After the timed region, "variants" reports the same
+workload with central-difference BFGS gradients (the plain method), adjoint
+gradients without and with Hessian recycling.  Prints one JSON line.
 """
 from __future__ import annotations
 
@@ -83,6 +85,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--grad-mode", choices=["adjoint", "fd"], default="adjoint")
+    ap.add_argument("--no-hessian-recycling", action="store_true",
+                    help="start every BFGS from the scaled identity instead of the previous inverse Hessian")
     ap.add_argument("--no-variants", action="store_true", help="skip the FD-gradient and Hessian-recycling lines")
     ap.add_argument("--gate-fusion", type=int, choices=[0, 1, 2], default=None,
                     help="0 per-gate passes (library default), 1 fused forward circuit, 2 fused forward and adjoint")
@@ -107,13 +111,14 @@ def main():
     psi0 = torch.zeros(n, dtype=torch.complex64, device="cuda")
     psi0[0] = 1.0  # vacuum
     gm = 0 if args.grad_mode == "adjoint" else 1
+    rh = not args.no_hessian_recycling
     print(f"[bench] warmup {args.warmup} steps", file=sys.stderr, flush=True)
     if args.warmup > 0:
-        ad = lib.Adapt(hl, cfg["pool"], psi0, max_iters=cfg["max_iters"], grad_mode=gm)
+        ad = lib.Adapt(hl, cfg["pool"], psi0, max_iters=cfg["max_iters"], grad_mode=gm, recycle_hessian=rh)
         for _ in range(args.warmup):
             ad.step()
         ad.close()
-    ad = lib.Adapt(hl, cfg["pool"], psi0, max_iters=cfg["max_iters"], grad_mode=gm)
+    ad = lib.Adapt(hl, cfg["pool"], psi0, max_iters=cfg["max_iters"], grad_mode=gm, recycle_hessian=rh)
     lib.prof_reset()
     lib.prof_enable(True)
     torch.cuda.synchronize()
@@ -166,8 +171,9 @@ def main():
         "data": "synthetic",
         "config": {"workload": (f"Kitaev-Kerr open chain L=8 d=8 (16,777,216 amplitudes), J=1 Delta=0.5 K=0.2, "
                                 f"vacuum start, 28-op nearest-neighbour pool, ADAPT steps 1..{args.steps} with "
-                                f"{args.grad_mode} BFGS gradients"),
-                   "L": 8, "d": 8, "pool": len(cfg["pool"]), "grad_mode": args.grad_mode,
+                                f"{args.grad_mode} BFGS gradients"
+                                f"{', inverse Hessian recycled across steps' if rh else ''}"),
+                   "L": 8, "d": 8, "pool": len(cfg["pool"]), "grad_mode": args.grad_mode, "hessian_recycling": rh,
                    "gate_fusion": lib.get_gate_fusion()},
         "roofline": roof,
         "apply_h": kernel_entry(0),
@@ -191,12 +197,12 @@ def main():
 
     if not args.no_variants and args.grad_mode == "adjoint":
         print("[bench] variants: central-difference gradients, Hessian recycling", file=sys.stderr, flush=True)
+        main = {"steps": args.steps, "steps_per_s": value, "E_final": reps[-1]["E"], "bfgs_evals_per_step": evals,
+                "bfgs_iters_per_step": float(np.mean([r["bfgs_iters"] for r in reps]))}
         out["variants"] = {
             "plain_fd_gradients": variant(args.steps, grad_mode=1),
-            "adjoint": {"steps": args.steps, "steps_per_s": value, "E_final": reps[-1]["E"],
-                        "bfgs_evals_per_step": evals,
-                        "bfgs_iters_per_step": float(np.mean([r["bfgs_iters"] for r in reps]))},
-            "adjoint_hessian_recycling": variant(args.steps, recycle_hessian=True),
+            "adjoint": main if not rh else variant(args.steps),
+            "adjoint_hessian_recycling": main if rh else variant(args.steps, recycle_hessian=True),
         }
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)

@@ -254,6 +254,18 @@ typedef int (*fock_objective_fn)(void *ctx, int n, const double *x, double *f, d
 int fock_bfgs_minimize(int n, double *x, fock_objective_fn fn, void *ctx, double gtol, int maxiter, double *Hinv,
                        int *iters, int *evals, double *fmin, int *status);
 
+/* ------------------------------------------------------------------ dense gate variant */
+
+/* Forward two-mode gates (fock_apply_gate2 and the forward circuit of the
+ * adjoint evaluation) as a dense d^2 x d^2 contraction on FP32 matrix cores
+ * (v_mfma_f32_16x16x4_f32): each fibre's 2d^2 real components times the real
+ * form of U, ignoring its conserved-block structure (Sec. II.B).  d in
+ * {4, 6, 8}; other cutoffs and single-mode gates keep the block kernels.
+ * Same results to FP32 rounding.  Process-wide; FOCK_GATE_BLOCK by default. */
+enum { FOCK_GATE_BLOCK = 0, FOCK_GATE_DENSE_MFMA = 1 };
+int fock_set_gate_variant(int variant);
+int fock_get_gate_variant(void);
+
 /* ------------------------------------------------------------------ gate fusion */
 
 /* Circuits evaluated by fock_energy_grad_adjoint and adapt_step run runs of
@@ -344,7 +356,7 @@ int fock_mlp_destroy(fock_mlp_t *net);
 
 /* Kernel ids for per-kernel timing by HIP events recorded on the launch stream. */
 enum { FOCK_K_APPLY_H = 0, FOCK_K_POOL = 1, FOCK_K_GATE = 2, FOCK_K_ADJ = 3, FOCK_K_DIAG = 4,
-       FOCK_K_REDUCE = 5, FOCK_K_MLP_FWD = 6, FOCK_K_MLP_TRAIN = 7, FOCK_K_NUM = 8 };
+       FOCK_K_REDUCE = 5, FOCK_K_MLP_FWD = 6, FOCK_K_MLP_TRAIN = 7, FOCK_K_GATE_DENSE = 8, FOCK_K_NUM = 9 };
 
 /* Enable/disable event timing of every launch (off by default). */
 int fock_prof_enable(int on);

@@ -36,6 +36,7 @@ SOURCES = [
     "adapt.cpp",
     "bfgs.cpp",
     "fuse_kernels.hip",
+    "dense_gate.hip",
     "mlp_kernels.hip",
     "mlp.cpp",
 ]

@@ -8,6 +8,7 @@
 #include <vector>
 
 #include "bfgs.h"
+#include "dense_internal.h"
 #include "fuse_internal.h"
 #include "pipeline.h"
 
@@ -136,6 +137,8 @@ Layout make_layout(uint32_t namp, int Lm, int d, int P, int n) {
   o = al(o + sizeof(PoolPair) * kMaxPairs);
   L.diags = o;
   o = al(o + sizeof(PoolDiag) * kMaxDiagOps);
+  L.wdense = o;
+  o = al(o + dense_w_bytes(d));
   L.total = o;
   return L;
 }
@@ -190,8 +193,17 @@ int stage_gates(Ctx &c, const fock_op_t *ops, const double *theta, int n, const 
                            (float2 *)(c.ws + c.L.utab), c.s);
 }
 
+static std::atomic<int> g_gate_variant{FOCK_GATE_BLOCK};
+
+int gate_variant() { return g_gate_variant.load(); }
+
 int forward_gate(Ctx &c, const fock_op_t &op, int k, bool dag, const float2 *src, float2 *psi) {
   const float2 *U = (const float2 *)(c.ws + c.L.utab) + (size_t)k * gate_stride(c.g.d);
+  if (!is_single_mode(op.type) && gate_variant() == FOCK_GATE_DENSE_MFMA && dense_supported(c.g.d)) {
+    ProfScope ps(FOCK_K_GATE_DENSE, c.s, 16.0 * c.g.n_amp);
+    return launch_gate_dense(c.g, op.i, op.j, gate_kind(op.type), dag, U, src, psi, (float *)(c.ws + c.L.wdense),
+                             c.s);
+  }
   ProfScope ps(is_single_mode(op.type) ? FOCK_K_DIAG : FOCK_K_GATE, c.s, 16.0 * c.g.n_amp);
   if (is_single_mode(op.type)) return launch_diag(c.g, op.i, op.type, dag, U, src, psi, c.s);
   return launch_gate(c.g, op.i, op.j, gate_kind(op.type), dag, U, src, psi, c.s);
@@ -502,6 +514,15 @@ int fock_apply_H(const fock_ham_t *ham, const void *psi, void *hpsi, double *E, 
   }
   return FOCK_OK;
 }
+
+int fock_set_gate_variant(int variant) {
+  if (variant != FOCK_GATE_BLOCK && variant != FOCK_GATE_DENSE_MFMA)
+    return set_error(FOCK_ERR_ARG, "gate variant %d not in {0, 1}", variant);
+  g_gate_variant.store(variant);
+  return FOCK_OK;
+}
+
+int fock_get_gate_variant(void) { return g_gate_variant.load(); }
 
 int fock_set_gate_fusion(int mode) {
   if (mode < FOCK_FUSE_OFF || mode > FOCK_FUSE_ALL)

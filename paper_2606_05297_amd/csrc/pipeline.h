@@ -6,7 +6,7 @@
 namespace fock {
 
 struct Layout {
-  size_t theta = 0, recs = 0, utab = 0, partial = 0, result = 0, pairs = 0, diags = 0, total = 0;
+  size_t theta = 0, recs = 0, utab = 0, partial = 0, result = 0, pairs = 0, diags = 0, wdense = 0, total = 0;
   int G = 0;     // blocks of the row-parallel kernels
   int rs = 0;    // row stride of the per-gate reverse-step partials
   int nmax = 0;  // gates

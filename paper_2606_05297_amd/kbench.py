@@ -20,14 +20,14 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-NAMES = {0: "apply_h", 1: "pool_grads", 2: "gate2", 3: "gate2_adjoint", 4: "diag_gate"}
+NAMES = {0: "apply_h", 1: "pool_grads", 2: "gate2", 3: "gate2_adjoint", 4: "diag_gate", 8: "gate2_dense_mfma"}
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--workload", default="kk_l8_d8")
     ap.add_argument("--iters", type=int, default=20)
-    ap.add_argument("--kernels", default="copy,apply_h,pool,gate,adjoint")
+    ap.add_argument("--kernels", default="copy,apply_h,pool,gate,adjoint,dense")
     ap.add_argument("--lib", default=None, help="path of an alternative libfock.so build")
     ap.add_argument("--schedule", type=int, default=None, help="stencil tile schedule (fock_set_stencil_schedule)")
     args = ap.parse_args()
@@ -85,6 +85,17 @@ def main():
                     lib.apply_gate2(L, d, (t, i, j), 0.37, states[k % 3], ws)
         torch.cuda.synchronize()
         print(f"[kbench] gate done", file=sys.stderr, flush=True)
+    if "dense" in want:
+        lib.set_gate_variant(lib.GATE_DENSE_MFMA)
+        pairs = [(0, 1), (3, 4), (L - 2, L - 1), (1, 2)]
+        types = ["HR", "PR"] if cfg["Delta"] != 0 else ["HR", "DH"]
+        for k in range(max(1, args.iters // 2)):
+            for (i, j) in pairs:
+                for t in types:
+                    lib.apply_gate2(L, d, (t, i, j), 0.37, states[k % 3], ws)
+        torch.cuda.synchronize()
+        lib.set_gate_variant(lib.GATE_BLOCK)
+        print(f"[kbench] dense done", file=sys.stderr, flush=True)
     if "adjoint" in want:
         ops, th = W.random_circuit(cfg["pool"], 8, seed=3)
         for k in range(max(1, args.iters // 4)):
@@ -98,6 +109,10 @@ def main():
             avg = p["ms"] / p["launches"]
             res[name] = {"launches": p["launches"], "avg_us": avg * 1e3,
                          "GBs": (p["bytes"] / p["launches"]) / (avg * 1e-3) / 1e9}
+            if kid == 8:  # dense GEMM: (2 d^2)^2 x 2 flop per fibre, d^(L-2) fibres
+                fl = (2 * d * d) ** 2 * 2 * d ** (L - 2)
+                res[name]["TFLOPs"] = fl / (avg * 1e-3) / 1e12
+                res[name]["mfma_frac_fp32"] = res[name]["TFLOPs"] / 157.3
     print(json.dumps({"workload": args.workload, "iters": args.iters, "schedule": lib.get_stencil_schedule(),
                       "kernels": res}), flush=True)
 

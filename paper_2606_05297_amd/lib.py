@@ -510,6 +510,18 @@ def autotune_stencil(h: Ham, psi, hpsi, ws, cache_path=None, stream=None) -> int
     return best.value
 
 
+GATE_BLOCK, GATE_DENSE_MFMA = 0, 1
+
+
+def set_gate_variant(variant: int):
+    """0: block-sparse gate kernels (default); 1: dense d^2 x d^2 gates on FP32 matrix cores (d in {4, 6, 8})."""
+    _check(load().fock_set_gate_variant(int(variant)))
+
+
+def get_gate_variant() -> int:
+    return int(load().fock_get_gate_variant())
+
+
 FUSE_OFF, FUSE_FORWARD, FUSE_ALL = 0, 1, 2
 
 

@@ -171,3 +171,34 @@ def test_autograd_adjoint_energy_matches_oracle_and_fd():
     theta.grad = None
     (3.0 * f(theta)).backward()
     assert np.allclose(theta.grad.numpy(), 3.0 * g, rtol=0, atol=1e-12)
+
+
+def test_adapt_hessian_recycling_replay():
+    """Hessian recycling (the benchmark's default): every step still passes the
+    replay check, the trajectory selects the same operators as the fresh-Hessian
+    run, energies agree with it to the BFGS tolerance, and fewer BFGS iterations
+    are needed in total."""
+    L, d = 4, 6
+    c = dict(L=L, d=d, periodic=False, J=1.0, U=0.0, mu=0.0, Delta=0.5, K=0.2)
+    ho, hl = oham(c), lib.ham_from(c)
+    pool = W.pool(L, "nn", False, W.KITAEV_TYPES)
+    psi0 = O.fock_state(L, d, [0] * L)
+    say("adapt kitaev L4 d6 recycled vs fresh Hessian")
+    runs = {}
+    for rh in (False, True):
+        ad = lib.Adapt(hl, pool, dev(psi0), max_iters=8, recycle_hessian=rh)
+        ops, th = [], np.zeros(0)
+        reps = []
+        for _ in range(6):
+            rep = ad.step()
+            ops, th = replay_check(ad, ho, psi0, ops, th, rep, pool)
+            reps.append(rep)
+        runs[rh] = reps
+        ad.close()
+    for a, b in zip(runs[False], runs[True]):
+        assert a["k_sel"] == b["k_sel"]
+        assert abs(a["E"] - b["E"]) <= 1e-5 * max(1.0, abs(a["E"]))
+    it_f = sum(r["bfgs_iters"] for r in runs[False])
+    it_r = sum(r["bfgs_iters"] for r in runs[True])
+    say("BFGS iterations fresh", it_f, "recycled", it_r)
+    assert it_r <= it_f

@@ -398,3 +398,30 @@ def test_gate_fusion_matches_unfused_and_oracle(case):
         assert np.abs(gf - gr).max() <= 1e-4 * max(1.0, np.abs(gr).max()), mode
         # after the reverse sweep phi is back at psi0 (U^+ ... U^+ U ... U = 1)
         assert np.abs(phif - psi0).max() <= 1e-5, mode
+
+
+@pytest.mark.parametrize("d", [4, 6, 8])
+def test_dense_mfma_gate_variant(d):
+    """The dense matrix-core gate gives the block kernel's and the oracle's
+    result (forward and adjoint), on a ragged tile count and on mode 0."""
+    L = 5 if d == 8 else 6
+    say("dense gate", L, d)
+    psi = W.random_state(L, d, seed=d)
+    p128 = psi.astype(np.complex128)
+    ws = lib.workspace(lib.ham(L, d), 0, 1)
+    prev = lib.get_gate_variant()
+    try:
+        for o in [("HR", 0, 1), ("PR", 1, 3), ("DH", L - 2, L - 1), ("PI", 0, L - 1), ("HI", 2, 3)]:
+            for adj in (False, True):
+                th = 0.41 if not adj else -0.23
+                out = {}
+                for v in (lib.GATE_BLOCK, lib.GATE_DENSE_MFMA):
+                    lib.set_gate_variant(v)
+                    x = dev(psi)
+                    lib.apply_gate2(L, d, o, th, x, ws, adjoint=adj)
+                    out[v] = host(x)
+                ref = O.apply_gate(o, th, p128, L, d, adjoint=adj)
+                assert np.abs(out[lib.GATE_DENSE_MFMA] - ref).max() <= 1e-5 * np.abs(ref).max(), (o, adj)
+                assert np.abs(out[lib.GATE_DENSE_MFMA] - out[lib.GATE_BLOCK]).max() <= 2e-6 * np.abs(ref).max()
+    finally:
+        lib.set_gate_variant(prev)
