@@ -606,6 +606,67 @@ def ham_column(ham: Ham, occ: Sequence[int]) -> dict:
     return out
 
 
+# --------------------------------------------------------------------------
+# Product states psi[n] = prod_r f_r[n_r]: exact values at chosen indices without
+# forming the d^L vector (used at the largest sizes the library accepts).
+
+def _product_amp(factors, occ) -> complex:
+    v = 1.0 + 0.0j
+    for f, n in zip(factors, occ):
+        v *= complex(f[n])
+    return v
+
+
+def product_H_at(ham: Ham, factors, flat_index: int) -> complex:
+    """(H psi)[flat_index] for the product state of `factors` (one length-d
+    vector per mode): the row of H from ham_column, contracted with the
+    product amplitudes."""
+    L, d = ham.L, ham.d
+    occ = [(flat_index // d**r) % d for r in range(L)]
+    tot = 0.0 + 0.0j
+    for k, c in ham_column(ham, occ).items():
+        tot += c * _product_amp(factors, [(k // d**r) % d for r in range(L)])
+    return complex(tot)
+
+
+def product_energy(ham: Ham, factors) -> float:
+    """<psi|H|psi> / <psi|psi> of a product state from single-mode expectation
+    values: every bond term is a product of two one-mode expectations times
+    the norms of the other modes (Sec. III Hamiltonians)."""
+    L, d = ham.L, ham.d
+    f = [np.asarray(x, dtype=np.complex128) for x in factors]
+    a = ladder(d)
+    ad = a.T
+    nrm = [np.vdot(x, x).real for x in f]
+    ex = lambda x, M: np.vdot(x, M @ x)
+    N = number(d)
+    onsite_m = (0.5 * ham.U + ham.K) * (N @ N - N) - ham.mu * N
+    E = 0.0 + 0.0j
+    for (i, j) in bonds(L, ham.periodic):
+        rest = np.prod([nrm[r] for r in range(L) if r not in (i, j)])
+        for (mi, mj, c) in ((ad, a, -ham.J), (a, ad, -ham.J), (a, a, ham.Delta), (ad, ad, ham.Delta)):
+            E += c * ex(f[i], mi) * ex(f[j], mj) * rest
+    for r in range(L):
+        E += ex(f[r], onsite_m) * np.prod([nrm[s] for s in range(L) if s != r])
+    return float(E.real / np.prod(nrm))
+
+
+def product_gate_at(op, theta: float, factors, L: int, d: int, flat_index: int) -> complex:
+    """(O(theta) psi)[flat_index] for a product state: the gate's local matrix
+    (exp of the truncated generator) applied to the factors of its modes."""
+    gtype, i, j = op
+    occ = [(flat_index // d**r) % d for r in range(L)]
+    rest = _product_amp([f for r, f in enumerate(factors) if r not in (i, j)],
+                        [n for r, n in enumerate(occ) if r not in (i, j)])
+    G = gate_local(gtype, d, theta)
+    if j is None or j < 0:
+        v = G[occ[i], :] @ np.asarray(factors[i], dtype=np.complex128)
+    else:
+        loc = np.kron(np.asarray(factors[i], dtype=np.complex128), np.asarray(factors[j], dtype=np.complex128))
+        v = G[occ[i] * d + occ[j], :] @ loc
+    return complex(rest * v)
+
+
 def apply_H_at(ham: Ham, psi: np.ndarray, flat_index: int) -> complex:
     """(H psi)[flat_index] from one row of H."""
     L, d = ham.L, ham.d

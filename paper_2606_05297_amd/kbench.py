@@ -20,14 +20,16 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-NAMES = {0: "apply_h", 1: "pool_grads", 2: "gate2", 3: "gate2_adjoint", 4: "diag_gate", 8: "gate2_dense_mfma"}
+NAMES = {0: "apply_h", 1: "pool_grads", 2: "gate2", 3: "gate2_adjoint", 4: "diag_gate", 6: "mlp_forward",
+         7: "mlp_train_step", 8: "gate2_dense_mfma"}
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--workload", default="kk_l8_d8")
     ap.add_argument("--iters", type=int, default=20)
-    ap.add_argument("--kernels", default="copy,apply_h,pool,gate,adjoint,dense")
+    ap.add_argument("--kernels", default="copy,apply_h,pool,gate,adjoint,dense,mlp")
+    ap.add_argument("--mlp-batch", type=int, default=16384)
     ap.add_argument("--lib", default=None, help="path of an alternative libfock.so build")
     ap.add_argument("--schedule", type=int, default=None, help="stencil tile schedule (fock_set_stencil_schedule)")
     args = ap.parse_args()
@@ -101,6 +103,20 @@ def main():
         for k in range(max(1, args.iters // 4)):
             lib.energy_grad_adjoint(h, ops, th, states[k % 3], outs[(k + 1) % 3], outs[(k + 2) % 3], ws)
         print(f"[kbench] adjoint done", file=sys.stderr, flush=True)
+    if "mlp" in want:
+        B = args.mlp_batch
+        rng = np.random.default_rng(0)
+        X = torch.from_numpy(rng.uniform(0, 1, (B, 4)).astype(np.float32)).cuda()
+        T = torch.from_numpy(rng.normal(0, 0.3, (B, 64)).astype(np.float32)).cuda()
+        nv = torch.from_numpy(rng.integers(1, 65, B).astype(np.int32)).cuda()
+        net = lib.Mlp(B, W.mlp_init(0))
+        Y = torch.empty((B, 64), dtype=torch.float32, device="cuda")
+        for k in range(args.iters):
+            net.forward(X, Y)
+            net.adam_step(X, T, nv, 1e-3)
+        torch.cuda.synchronize()
+        net.close()
+        print(f"[kbench] mlp done", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     lib.prof_enable(False)
     for kid, name in NAMES.items():
@@ -109,6 +125,10 @@ def main():
             avg = p["ms"] / p["launches"]
             res[name] = {"launches": p["launches"], "avg_us": avg * 1e3,
                          "GBs": (p["bytes"] / p["launches"]) / (avg * 1e-3) / 1e9}
+            if kid in (6, 7):  # recorded "bytes" are the kernels' algorithmic FLOPs
+                res[name] = {"launches": p["launches"], "avg_us": avg * 1e3, "batch": args.mlp_batch,
+                             "TFLOPs": (p["bytes"] / p["launches"]) / (avg * 1e-3) / 1e12}
+                res[name]["mfma_frac_bf16"] = res[name]["TFLOPs"] / 2500.0
             if kid == 8:  # dense GEMM: (2 d^2)^2 x 2 flop per fibre, d^(L-2) fibres
                 fl = (2 * d * d) ** 2 * 2 * d ** (L - 2)
                 res[name]["TFLOPs"] = fl / (avg * 1e-3) / 1e12

@@ -425,3 +425,39 @@ def test_dense_mfma_gate_variant(d):
                 assert np.abs(out[lib.GATE_DENSE_MFMA] - out[lib.GATE_BLOCK]).max() <= 2e-6 * np.abs(ref).max()
     finally:
         lib.set_gate_variant(prev)
+
+
+def test_maximum_size_product_state_apply_H_gate_energy():
+    """Largest state the library accepts with L <= 24, d <= 16: d^L = 7^11 =
+    1,977,326,743 amplitudes (2^31 limit; 15.8 GB per state), Kitaev-Kerr with mu,
+    ring.  The input is a product state built on the device from seeded factors;
+    the oracle gives exact (H psi) and gate outputs at sampled indices, including
+    both ends of the index range, and the exact energy."""
+    L, d = 11, 7
+    ho, hl = ham_pair(L, d, True, 1.0, 0.0, 0.2, 0.45, 0.15)
+    fac = W.product_factors(L, d, seed=17)
+    say("max size", L, d, d**L)
+    t = torch.from_numpy(fac[-1]).cuda()
+    for f in reversed(fac[:-1]):
+        t = (t[:, None] * torch.from_numpy(f).cuda()[None, :]).reshape(-1)
+    n = d**L
+    assert t.numel() == n
+    y = torch.empty_like(t)
+    ws = lib.workspace(hl, 0, 1)
+    E, n2 = lib.apply_H(hl, t, y, ws)
+    Eref = O.product_energy(ho, fac)
+    assert abs(E - Eref) <= 1e-5 * max(1.0, abs(Eref)), (E, Eref)
+    assert abs(n2 - 1.0) <= 1e-4
+    rng = np.random.default_rng(3)
+    idx = np.concatenate([rng.integers(0, n, 300), [0, 1, d - 1, n - 1, n - d, n // 2]]).astype(np.int64)
+    got = y[torch.from_numpy(idx).cuda()].cpu().numpy()
+    ref = np.array([O.product_H_at(ho, fac, int(k)) for k in idx])
+    assert np.abs(got - ref).max() <= 2e-5 * np.abs(ref).max()
+    del y
+    for o in [("PR", 0, 1), ("HR", L - 2, L - 1), ("DH", 3, 7)]:
+        x = t.clone()
+        lib.apply_gate2(L, d, o, 0.3, x, ws)
+        got = x[torch.from_numpy(idx).cuda()].cpu().numpy()
+        ref = np.array([O.product_gate_at(o, 0.3, fac, L, d, int(k)) for k in idx])
+        assert np.abs(got - ref).max() <= 1e-5 * np.abs(ref).max(), o
+        del x

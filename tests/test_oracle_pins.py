@@ -331,3 +331,22 @@ def test_golden_fixtures():
             psi = O.fock_state(h.L, h.d, c["occ"])
             g = O.pool_gradients(h, psi, [tuple(o) for o in c["pool"]])
             assert np.allclose(g, c["g"], atol=1e-12), c["name"]
+
+
+def test_product_state_oracle_functions():
+    """The product-state shortcuts equal the general oracle on the explicit
+    vector: (H psi) at every index, the energy, and gates at every index."""
+    import workload as W
+    for (L, d, per, U, mu, Dl, K) in [(4, 3, True, 1.2, 0.3, 0.4, 0.1), (3, 5, False, 0.0, 0.0, 0.5, 0.2)]:
+        h = O.Ham(L, d, per, 1.0, U, mu, Dl, K)
+        fac = W.product_factors(L, d, seed=L + d)
+        psi = W.product_state(fac, dtype=np.complex128)
+        Hpsi = O.apply_H(h, psi)
+        for k in range(d**L):
+            assert abs(O.product_H_at(h, fac, k) - Hpsi[k]) < 1e-12
+        E = np.vdot(psi, Hpsi).real / np.vdot(psi, psi).real
+        assert abs(O.product_energy(h, fac) - E) < 1e-12
+        for op in [("PR", 0, 1), ("DH", 1, L - 1), ("KERR", 1, -1)]:
+            out = O.apply_gate(op, 0.37, psi, L, d)
+            for k in range(d**L):
+                assert abs(O.product_gate_at(op, 0.37, fac, L, d, k) - out[k]) < 1e-12

@@ -190,3 +190,23 @@ def mlp_init(seed: int = 0) -> np.ndarray:
 def mlp_features(J: float, Delta: float, K: float, step: int) -> np.ndarray:
     """Network input of an ADAPT point at step n: (J, Delta, K, n / 64)."""
     return np.array([J, Delta, K, step / 64.0], dtype=np.float32)
+
+
+def product_factors(L: int, d: int, seed: int = 0) -> list:
+    """Seeded single-mode factors f_r (complex64, length d, unit norm) of the
+    product state psi[n] = prod_r f_r[n_r] used at the largest sizes."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(L):
+        v = rng.standard_normal(d) + 1j * rng.standard_normal(d)
+        v /= np.linalg.norm(v)
+        out.append(v.astype(np.complex64))
+    return out
+
+
+def product_state(factors, dtype=np.complex64) -> np.ndarray:
+    """The full product vector (index sum_r n_r d^r, mode 0 fastest)."""
+    psi = np.asarray(factors[-1], dtype=np.complex128)
+    for f in reversed(factors[:-1]):
+        psi = np.kron(psi, np.asarray(f, dtype=np.complex128))
+    return psi.astype(dtype)
