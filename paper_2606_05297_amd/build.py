@@ -10,6 +10,7 @@ from __future__ import annotations
 import argparse
 import concurrent.futures as cf
 import os
+import re
 import subprocess
 import sys
 
@@ -62,10 +63,49 @@ def _compile(src: str) -> str:
     return obj
 
 
+# Sources with matrix-core (MFMA) instructions; their device assembly is checked
+# after compilation (see check_mfma_operands).
+MFMA_SOURCES = ["dense_gate.hip", "mlp_kernels.hip"]
+
+_MFMA_RE = re.compile(r"v_mfma_\w+\s+([av])\[(\d+):(\d+)\],[^\n]*,\s*([av])\[(\d+):(\d+)\]\s*$", re.M)
+
+
+def check_mfma_operands(src: str) -> int:
+    """Compile `src` to gfx950 device assembly and reject any matrix instruction
+    whose destination registers partially overlap its accumulator input (the
+    two must be identical or disjoint; a partial overlap gives wrong sums).
+    Returns the number of MFMA instructions inspected."""
+    asm = os.path.join(BUILD, os.path.splitext(src)[0] + ".s")
+    cmd = [HIPCC, *COMMON, "--cuda-device-only", "-S", "-x", "hip", os.path.join(CSRC, src), "-o", asm]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"assembly generation failed: {' '.join(cmd)}\n{r.stderr}")
+    with open(asm) as fh:
+        n, bad = mfma_overlaps(fh.read())
+    if bad:
+        raise RuntimeError(f"{src}: matrix instruction with partially overlapping dst/srcC: {bad[0]}")
+    return n
+
+
+def mfma_overlaps(text: str):
+    """(number of MFMA instructions, those whose dst and srcC ranges overlap
+    without being identical) in device assembly text."""
+    n, bad = 0, []
+    for m in _MFMA_RE.finditer(text):
+        n += 1
+        dk, d0, d1, ck, c0, c1 = m.group(1), int(m.group(2)), int(m.group(3)), m.group(4), int(m.group(5)), int(m.group(6))
+        if dk == ck and (d0, d1) != (c0, c1) and not (d1 < c0 or c1 < d0):
+            bad.append(m.group(0).strip())
+    return n, bad
+
+
 def build(jobs: int = 8, verbose: bool = True) -> str:
     os.makedirs(BUILD, exist_ok=True)
     with cf.ThreadPoolExecutor(max_workers=max(1, jobs)) as ex:
         objs = list(ex.map(_compile, SOURCES))
+        nm = sum(ex.map(check_mfma_operands, MFMA_SOURCES))
+    if verbose:
+        print(f"checked {nm} matrix instructions")
     tmp = LIB + ".tmp"
     cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs]
     r = subprocess.run(cmd, capture_output=True, text=True)

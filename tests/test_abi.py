@@ -169,3 +169,20 @@ def test_stencil_schedules_are_permutations():
                     assert len(key) == 1, (L, d, s, x)
     with pytest.raises(lib.FockError):
         lib.set_stencil_schedule(99)
+
+
+def test_mfma_operand_overlap_check():
+    """The build rejects matrix instructions whose destination partially
+    overlaps the accumulator input (identical or disjoint ranges are fine)."""
+    from paper_2606_05297_amd import build as B
+    text = "\n".join([
+        "\tv_mfma_f32_16x16x4_f32 a[28:31], v15, v12, a[28:31]",
+        "\tv_mfma_f32_16x16x4_f32 a[0:3], v15, v12, a[4:7]",
+        "\tv_mfma_f32_16x16x4_f32 a[26:29], v16, v12, a[28:31]",
+        "\tv_mfma_f32_16x16x32_bf16 v[4:7], v[0:3], v[8:11], v[4:7]",
+        "\tv_mfma_f32_16x16x32_bf16 v[4:7], v[0:3], v[8:11], v[2:5]",
+    ])
+    n, bad = B.mfma_overlaps(text)
+    assert n == 5
+    assert bad == ["v_mfma_f32_16x16x4_f32 a[26:29], v16, v12, a[28:31]",
+                   "v_mfma_f32_16x16x32_bf16 v[4:7], v[0:3], v[8:11], v[2:5]"]
