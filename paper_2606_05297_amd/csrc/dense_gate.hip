@@ -74,41 +74,69 @@ __global__ __launch_bounds__(kBlock) void k_gate2_dense(const float2 *__restrict
   const int lr = lane & 15, lq = lane >> 4;
   const uint32_t ntile = (g.nfib + NF - 1) / NF;
   const bool i0 = g.si == 1;  // pair (0, j): member n_i runs along contiguous amplitudes
-  for (uint32_t t = blockIdx.x; t < ntile; t += gridDim.x) {
-    const uint32_t f0 = t * NF;
-    __syncthreads();  // W ready / previous tile's stores done before X is reused
-    for (int e = threadIdx.x; e < NF * C::D2; e += kBlock) {
+  constexpr int PER = (NF * C::D2 + kBlock - 1) / kBlock;  // amplitudes per thread per tile
+  // element e of a tile -> (fibre f, member q = n_i d + n_j); consecutive threads
+  // take consecutive amplitudes in memory
+  auto member = [&](int e, int &f, int &ni, int &nj) {
+    if (i0) {
+      ni = e % D;
+      f = (e / D) % NF;
+      nj = e / (D * NF);
+    } else {
+      f = e % NF;
+      const int q = e / NF;
+      ni = q / D;
+      nj = q % D;
+    }
+  };
+  auto gather = [&](uint32_t t, float2 (&pv)[PER]) {
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+      const int e = threadIdx.x + k * kBlock;
       int f, ni, nj;
-      if (i0) {
-        ni = e % D;
-        f = (e / D) % NF;
-        nj = e / (D * NF);
-      } else {
-        f = e % NF;
-        const int q = e / NF;
-        ni = q / D;
-        nj = q % D;
+      member(e, f, ni, nj);
+      const uint32_t fi = t * NF + (uint32_t)f;
+      pv[k] = (e < NF * C::D2 && fi < g.nfib) ? src[fiber_base(fi, g, D) + ni * g.si + nj * g.sj]
+                                               : make_float2(0.f, 0.f);
+    }
+  };
+  float2 pv[PER];
+  if (blockIdx.x < ntile) gather(blockIdx.x, pv);
+  for (uint32_t t = blockIdx.x; t < ntile; t += gridDim.x) {
+    __syncthreads();  // W ready / previous tile's stores have read X
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+      const int e = threadIdx.x + k * kBlock;
+      if (e < NF * C::D2) {
+        int f, ni, nj;
+        member(e, f, ni, nj);
+        const int q = ni * D + nj;
+        X[f * C::XS + q] = pv[k].x;
+        X[f * C::XS + C::D2 + q] = pv[k].y;
       }
-      const int q = ni * D + nj;
-      float2 v = make_float2(0.f, 0.f);
-      if (f0 + f < g.nfib) v = src[fiber_base(f0 + f, g, D) + ni * g.si + nj * g.sj];
-      X[f * C::XS + q] = v.x;
-      X[f * C::XS + C::D2 + q] = v.y;
     }
     for (int e = threadIdx.x; e < NF * (C::KP - 2 * C::D2); e += kBlock) {
       const int f = e / (C::KP - 2 * C::D2), k = 2 * C::D2 + e % (C::KP - 2 * C::D2);
       X[f * C::XS + k] = 0.f;
     }
     __syncthreads();
+    // the next tile's fibres are in flight while the matrix cores work on this one
+    if (t + gridDim.x < ntile) gather(t + gridDim.x, pv);
+    // output tiles in pairs: two independent accumulation chains per k-step
     f32x4 acc[C::KP / 16];
 #pragma unroll
-    for (int nt = 0; nt < C::KP / 16; ++nt) {
-      f32x4 c = {0.f, 0.f, 0.f, 0.f};
+    for (int nt = 0; nt < C::KP / 16; nt += 2) {
+      f32x4 c0 = {0.f, 0.f, 0.f, 0.f}, c1 = c0;
+      const bool two = nt + 1 < C::KP / 16;
 #pragma unroll 8
-      for (int ks = 0; ks < C::KP / 4; ++ks)
-        c = __builtin_amdgcn_mfma_f32_16x16x4f32(X[(16 * wave + lr) * C::XS + 4 * ks + lq],
-                                                 W[(4 * ks + lq) * C::WS + 16 * nt + lr], c, 0, 0, 0);
-      acc[nt] = c;
+      for (int ks = 0; ks < C::KP / 4; ++ks) {
+        const float av = X[(16 * wave + lr) * C::XS + 4 * ks + lq];
+        const float *wr = W + (4 * ks + lq) * C::WS + 16 * nt + lr;
+        c0 = __builtin_amdgcn_mfma_f32_16x16x4f32(av, wr[0], c0, 0, 0, 0);
+        if (two) c1 = __builtin_amdgcn_mfma_f32_16x16x4f32(av, wr[16], c1, 0, 0, 0);
+      }
+      acc[nt] = c0;
+      if (two) acc[nt + 1] = c1;
     }
     __syncthreads();  // every wavefront has read X
 #pragma unroll
@@ -116,18 +144,10 @@ __global__ __launch_bounds__(kBlock) void k_gate2_dense(const float2 *__restrict
 #pragma unroll
       for (int r = 0; r < 4; ++r) X[(16 * wave + 4 * lq + r) * C::XS + 16 * nt + lr] = acc[nt][r];
     __syncthreads();
+    const uint32_t f0 = t * NF;
     for (int e = threadIdx.x; e < NF * C::D2; e += kBlock) {
       int f, ni, nj;
-      if (i0) {
-        ni = e % D;
-        f = (e / D) % NF;
-        nj = e / (D * NF);
-      } else {
-        f = e % NF;
-        const int q = e / NF;
-        ni = q / D;
-        nj = q % D;
-      }
+      member(e, f, ni, nj);
       const int q = ni * D + nj;
       if (f0 + f < g.nfib)
         dst[fiber_base(f0 + f, g, D) + ni * g.si + nj * g.sj] = make_float2(X[f * C::XS + q], X[f * C::XS + C::D2 + q]);
