@@ -14,7 +14,9 @@ starts every step from the previous step's inverse Hessian, padded with the
 identity for the new angle (Appendix D); --no-hessian-recycling starts from
 the scaled identity.  After the timed region, "variants" reports the same
 workload with central-difference BFGS gradients (the plain method), adjoint
-gradients without and with Hessian recycling.  Prints one JSON line.
+gradients without and with Hessian recycling, and adjoint gradients through
+the batched engine (persistent kernels, graph-replayed BFGS rounds).  Prints
+one JSON line.
 """
 from __future__ import annotations
 
@@ -195,6 +197,22 @@ def main():
                 "bfgs_evals_per_step": float(np.mean([r["bfgs_evals"] for r in rs])),
                 "bfgs_iters_per_step": float(np.mean([r["bfgs_iters"] for r in rs]))}
 
+    def variant_graph(k):
+        """The same point through the batched engine: persistent kernels and one
+        captured graph replayed per BFGS round (fresh Hessian)."""
+        sw = lib.Sweep([dict(ham=hl, pool=cfg["pool"], psi0=psi0, warm_ops=[], warm_theta0=np.zeros(0))],
+                       max_iters=cfg["max_iters"])
+        sw.autotune(None)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        rs = [sw.step()[0][0] for _ in range(k)]
+        torch.cuda.synchronize()
+        dt_v = time.perf_counter() - t
+        sw.close()
+        return {"steps": k, "steps_per_s": k / dt_v, "E_final": rs[-1]["E"],
+                "bfgs_evals_per_step": float(np.mean([r["bfgs_evals"] for r in rs])),
+                "bfgs_iters_per_step": float(np.mean([r["bfgs_iters"] for r in rs]))}
+
     if not args.no_variants and args.grad_mode == "adjoint":
         print("[bench] variants: central-difference gradients, Hessian recycling", file=sys.stderr, flush=True)
         main = {"steps": args.steps, "steps_per_s": value, "E_final": reps[-1]["E"], "bfgs_evals_per_step": evals,
@@ -203,6 +221,7 @@ def main():
             "plain_fd_gradients": variant(args.steps, grad_mode=1),
             "adjoint": main if not rh else variant(args.steps),
             "adjoint_hessian_recycling": main if rh else variant(args.steps, recycle_hessian=True),
+            "adjoint_graph_replay": variant_graph(args.steps),
         }
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)

@@ -209,7 +209,7 @@ def main():
     tr = W.warmstart_points("train")[: args.train]
     he = W.warmstart_points("held")[: args.held]
     t0 = time.perf_counter()
-    _, ang = run_sweep(tr, args.steps)
+    _, ang = run_sweep(tr, args.steps, log=log)
     t_data = time.perf_counter() - t0
     X, T, n = dataset(tr, ang)
     log(f"{len(X)} samples from {len(tr)} points in {t_data:.1f} s")
@@ -217,10 +217,10 @@ def main():
     net, hist = train(X, T, n, args.epochs, args.batch, args.lr, log=log)
     t_train = time.perf_counter() - t0
     t0 = time.perf_counter()
-    plain, _ = run_sweep(he, args.steps)
+    plain, _ = run_sweep(he, args.steps, log=log)
     t_plain = time.perf_counter() - t0
     t0 = time.perf_counter()
-    warm, _ = run_sweep(he, args.steps, net=net, mode=args.mode)
+    warm, _ = run_sweep(he, args.steps, net=net, mode=args.mode, log=log)
     t_warm = time.perf_counter() - t0
     rep = {"mode": args.mode, "train_points": len(tr), "held_points": len(he), "max_steps": args.steps, "samples": int(len(X)),
            "loss_history": hist, "t_data_s": t_data, "t_train_s": t_train, "t_plain_s": t_plain, "t_warm_s": t_warm,
