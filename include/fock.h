@@ -315,6 +315,20 @@ int fock_stencil_schedule_table(int L, int d, int scheme, int *order, int n);
 int fock_autotune_stencil(const fock_ham_t *ham, const void *psi, void *hpsi, void *ws, size_t ws_bytes,
                           fock_stream_t stream, const char *cache_path, int *best_scheme);
 
+/* Work split of the H psi kernel (same operator, Sec. III; same output and
+ * energy/norm partials per tile):
+ *   FOCK_STENCIL_ROWS  - one thread per row of d amplitudes (every d, L, boundary);
+ *   FOCK_STENCIL_LANES - four lanes per row, two amplitudes each, with the bonds
+ *      beyond the LDS tile read as 1 kB blocks at wavefront-uniform offsets.
+ *      Used where d = 8, 4 <= L <= 10, the chain is open and the schedule is
+ *      single-pass; elsewhere the row split runs.
+ * The two sum a row's terms in different orders (FP32 rounding level).  Takes
+ * effect for handles (ADAPT runs, sweeps) created after the call and for the
+ * direct fock_apply_H calls; process-wide. */
+enum { FOCK_STENCIL_ROWS = 0, FOCK_STENCIL_LANES = 1 };
+int fock_set_stencil_variant(int variant);
+int fock_get_stencil_variant(void);
+
 /* ------------------------------------------------------------------ warm-start network */
 
 /* A small network proposes the initial angles of an ADAPT step from the

@@ -153,6 +153,8 @@ int make_ctx(const fock_ham_t &ham, uint32_t namp, int P, int n, void *ws, size_
     if (rc) return rc;
     if (stencil_schedule() == FOCK_SCHED_TWO_PASS)
       c->h.hi_m = apply_h_hi_modes(ham.L, ham.d, c->h.periodic_wrap);
+    c->h.lanes = (stencil_variant() == FOCK_STENCIL_LANES && c->h.hi_m == 0 &&
+                  lanes_stencil_ok(ham.L, ham.d, c->h.periodic_wrap)) ? 1 : 0;
   }
   c->s = s;
   c->ws = (char *)ws;

@@ -51,6 +51,7 @@ struct HamArgs {
   const int *order;   // tile processed by workgroup b (device table), or null: contiguous runs per XCD
   int hi_m;           // two-pass stencil: bonds among the top hi_m modes (and the ring bond) are applied
                       // by a first pass that stages those modes in LDS; 0 = single pass
+  int lanes;          // 1: lane-split stencil (d = 8, 4 <= L <= 10, open chain, single pass)
 };
 
 // ---------------------------------------------------------------- pool gradients
@@ -173,6 +174,10 @@ int launch_reduce_rows(const double *partial, int row_stride, const GateRec *rec
 // tile).  *order receives a device table of ntiles entries or nullptr.
 int stencil_order_table(int L, int d, int ntiles, const int **order);
 int stencil_schedule();
+// Work split of the H psi kernel (FOCK_STENCIL_*), and whether the lane
+// split covers (L, d, ring bond).
+int stencil_variant();
+bool lanes_stencil_ok(int L, int d, int periodic_wrap);
 
 struct ProfScope {
   int id;

@@ -294,6 +294,10 @@ static bool build_tile_order(int d, int ntiles, int scheme, std::vector<int> *ou
 
 int stencil_schedule() { return g_sched.load(); }
 
+static std::atomic<int> g_stencil_variant{FOCK_STENCIL_ROWS};
+int stencil_variant() { return g_stencil_variant.load(); }
+bool lanes_stencil_ok(int L, int d, int periodic_wrap) { return d == 8 && L >= 4 && L <= 10 && !periodic_wrap; }
+
 int stencil_order_table(int L, int d, int ntiles, const int **order) {
   *order = nullptr;
   const int scheme = g_sched.load();
@@ -326,6 +330,15 @@ extern "C" int fock_set_stencil_schedule(int scheme) {
 }
 
 extern "C" int fock_get_stencil_schedule(void) { return fock::g_sched.load(); }
+
+extern "C" int fock_set_stencil_variant(int variant) {
+  if (variant != FOCK_STENCIL_ROWS && variant != FOCK_STENCIL_LANES)
+    return fock::set_error(FOCK_ERR_ARG, "stencil variant %d is neither ROWS (0) nor LANES (1)", variant);
+  fock::g_stencil_variant.store(variant);
+  return FOCK_OK;
+}
+
+extern "C" int fock_get_stencil_variant(void) { return fock::g_stencil_variant.load(); }
 
 extern "C" int fock_stencil_schedule_table(int L, int d, int scheme, int *order, int n) {
   if (!order || n <= 0) return fock::set_error(FOCK_ERR_ARG, "NULL or empty order buffer");

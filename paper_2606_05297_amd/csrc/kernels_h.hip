@@ -34,6 +34,23 @@ __global__ __launch_bounds__(kBlock) void k_apply_h(const float2 *__restrict__ p
   }
 }
 
+// Lane-split H psi (see hblock_lanes8); same tiles and partials as k_apply_h<8>.
+template <int L>
+__global__ __launch_bounds__(kBlock) void k_apply_h_lanes8(const float2 *__restrict__ psi, float2 *__restrict__ hpsi,
+                                                           double *__restrict__ partial, HamArgs h) {
+  __shared__ double red[4];
+  __shared__ float4 tile4[kLanesTileF4];
+  const int vb = h.order ? h.order[blockIdx.x] : xcd_remap(blockIdx.x, gridDim.x);
+  float e = 0.f, nn = 0.f;
+  hblock_lanes8<L>(vb, psi, hpsi, h, tile4, e, nn);
+  const double se = block_sum_d((double)e, red);
+  const double sn = block_sum_d((double)nn, red);
+  if (threadIdx.x == 0) {
+    partial[2 * vb] = se;
+    partial[2 * vb + 1] = sn;
+  }
+}
+
 // First pass of the two-pass stencil (see hblock_hi); tile t = workgroup's
 // virtual index.
 template <int D>
@@ -116,6 +133,17 @@ static void launch_h_t(const HamArgs &h, const float2 *psi, float2 *hpsi, double
     int GA = 1;
     for (int r = 1; r < h.L - h.hi_m; ++r) GA *= h.d;
     hipLaunchKernelGGL(k_apply_h_hi<D>, dim3(GA), dim3(kBlock), 0, s, psi, hpsi, h);
+  }
+  if constexpr (D == 8) {
+    if (h.lanes) {
+      switch (h.L) {
+#define LCASE(LL) \
+  case LL: hipLaunchKernelGGL(k_apply_h_lanes8<LL>, dim3(G), dim3(kBlock), 0, s, psi, hpsi, partial, h); return;
+        LCASE(4) LCASE(5) LCASE(6) LCASE(7) LCASE(8) LCASE(9) LCASE(10)
+#undef LCASE
+        default: break;
+      }
+    }
   }
   hipLaunchKernelGGL(k_apply_h<D>, dim3(G), dim3(kBlock), 0, s, psi, hpsi, partial, h);
 }

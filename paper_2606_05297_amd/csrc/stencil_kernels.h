@@ -364,6 +364,202 @@ __device__ __forceinline__ void hblock_hi(int t, const float2 *__restrict__ psi,
   __syncthreads();
 }
 
+// ---------------------------------------------------------------- lane-split stencil (d = 8, open chains)
+// Four lanes share a row, two amplitudes each (c = t % 4 owns n_0 = 2c, 2c+1).
+// Tile: the 512 rows with n_1..n_3 free (32 kB of LDS, unpadded; the rows a
+// wavefront touches at one offset are 16 consecutive rows, 1 kB contiguous).
+// Thread t owns the rows with n_1 + 8 n_2 = t / 4 and walks n_3 = p = 0..7,
+// so within a wavefront n_3 and the tile's digits n_4..n_{L-1} are uniform:
+// the bonds (3,4) .. (L-2, L-1) read 1 kB blocks of rows from global memory
+// at wavefront-uniform offsets with wavefront-uniform coefficients and
+// validity, and the lane coefficients of the bonds (0,1), (1,2) and the lane
+// half of (2,3) are computed once per thread.  Terms and signs as in hblock.
+constexpr int kLanesTileF4 = 2048;  // float4 words of a tile: 512 rows x 8 amplitudes
+constexpr int kLanesMinL = 4, kLanesMaxL = 10;
+
+__device__ __forceinline__ void fma4(float4 &acc, float c, const float4 &v) {
+  acc.x = fmaf(c, v.x, acc.x);
+  acc.y = fmaf(c, v.y, acc.y);
+  acc.z = fmaf(c, v.z, acc.z);
+  acc.w = fmaf(c, v.w, acc.w);
+}
+
+template <int L>
+__device__ __forceinline__ void hblock_lanes8(int vb, const float2 *__restrict__ psi, float2 *__restrict__ hpsi,
+                                              const HamArgs &h, float4 *tile, float &e_out, float &nn_out) {
+  static_assert(L >= kLanesMinL && L <= kLanesMaxL, "lane-split stencil: 4 <= L <= 10");
+  constexpr int NB = L - 4;  // bonds (r-1, r), r = 4..L-1, whose neighbours lie outside the tile
+  constexpr int NBA = NB > 0 ? NB : 1;  // array extent
+  const float4 *__restrict__ g4 = reinterpret_cast<const float4 *>(psi);
+  float4 *__restrict__ o4 = reinterpret_cast<float4 *>(hpsi);
+  const float2 *tile2 = reinterpret_cast<const float2 *>(tile);
+  const size_t tb = (size_t)vb * kLanesTileF4;
+  for (int e = threadIdx.x; e < kLanesTileF4; e += kBlock) tile[e] = g4[tb + e];
+
+  const float J = h.J, Dl = h.Delta, c2 = h.c2, mu = h.mu;
+  auto fdiag = [&](float n) { return c2 * n * (n - 1.f) - mu * n; };
+  // tile digits n_4..n_{L-1} (wavefront-uniform) and their diagonal share
+  int hd[L + 1];
+  float dtile = 0.f;
+  {
+    uint32_t v = (uint32_t)vb;
+#pragma unroll
+    for (int r = 4; r < L; ++r) {
+      hd[r] = (int)(v & 7u);
+      v >>= 3;
+      dtile += fdiag((float)hd[r]);
+    }
+  }
+  // bonds (r-1, r), r >= 5: tile-uniform validity, float4 offsets, coefficients
+  bool ev[NBA][4];
+  int eo[NBA][4];
+  float ec[NBA][4];
+#pragma unroll
+  for (int b = 1; b < NB; ++b) {
+    const int r = b + 4, ni = hd[r - 1], nj = hd[r];
+    const int si = 4 << (3 * (r - 2)), sj = 4 << (3 * (r - 1));  // mode strides in float4 words
+    const float smi = sqrtf((float)ni), spi = sqrtf((float)ni + 1.f);
+    const float smj = sqrtf((float)nj), spj = sqrtf((float)nj + 1.f);
+    ev[b][0] = ni >= 1 && nj <= 6; eo[b][0] = -si + sj; ec[b][0] = -J * smi * spj;
+    ev[b][1] = ni <= 6 && nj >= 1; eo[b][1] = si - sj;  ec[b][1] = -J * spi * smj;
+    ev[b][2] = ni <= 6 && nj <= 6; eo[b][2] = si + sj;  ec[b][2] = Dl * spi * spj;
+    ev[b][3] = ni >= 1 && nj >= 1; eo[b][3] = -si - sj; ec[b][3] = Dl * smi * smj;
+  }
+  float s4m = 0.f, s4p = 0.f;
+  if constexpr (L > 4) {
+    s4m = sqrtf((float)hd[4]);
+    s4p = sqrtf((float)hd[4] + 1.f);
+  }
+
+  // lane-fixed part
+  const int t = threadIdx.x, c = t & 3, rip = t >> 2, n1 = rip & 7, n2 = rip >> 3;
+  const float s1m = sqrtf((float)n1), s1p = sqrtf((float)n1 + 1.f);
+  const float s2m = sqrtf((float)n2), s2p = sqrtf((float)n2 + 1.f);
+  const float sq0 = sqrtf((float)(2 * c)), sq1 = sqrtf((float)(2 * c + 1)), sq2 = sqrtf((float)(2 * c + 2));
+  // bond (0,1): rows n_1 + 1 (P) and n_1 - 1 (M), shifted by one amplitude
+  const bool vP = n1 <= 6, vM = n1 >= 1;
+  const float cPJ0 = vP ? -J * s1p * sq0 : 0.f;             // P[2c-1] -> n_0 = 2c
+  const float cPJ1 = vP ? -J * s1p * sq1 : 0.f;             // P[2c]   -> 2c+1
+  const float cPD0 = vP ? Dl * s1p * sq1 : 0.f;             // P[2c+1] -> 2c
+  const float cPD1 = (vP && c < 3) ? Dl * s1p * sq2 : 0.f;  // P[2c+2] -> 2c+1
+  const float cMJ0 = vM ? -J * s1m * sq1 : 0.f;             // M[2c+1] -> 2c
+  const float cMJ1 = (vM && c < 3) ? -J * s1m * sq2 : 0.f;  // M[2c+2] -> 2c+1
+  const float cMD0 = vM ? Dl * s1m * sq0 : 0.f;             // M[2c-1] -> 2c
+  const float cMD1 = vM ? Dl * s1m * sq1 : 0.f;             // M[2c]   -> 2c+1
+  const int oP = vP ? 4 : 0, oM = vM ? -4 : 0;              // float4 offsets of the rows n_1 +- 1
+  const int sm1 = c > 0 ? -1 : 0, sp2 = c < 3 ? 2 : 1;      // float2 offsets of amplitudes 2c-1, 2c+2 (clamped)
+  // bond (1,2): lane-fixed
+  float c12[4];
+  int o12[4];
+  {
+    const bool a0 = n1 >= 1 && n2 <= 6, a1 = n1 <= 6 && n2 >= 1, a2 = n1 <= 6 && n2 <= 6, a3 = n1 >= 1 && n2 >= 1;
+    c12[0] = a0 ? -J * s1m * s2p : 0.f; o12[0] = a0 ? 4 * 7 : 0;
+    c12[1] = a1 ? -J * s1p * s2m : 0.f; o12[1] = a1 ? -4 * 7 : 0;
+    c12[2] = a2 ? Dl * s1p * s2p : 0.f; o12[2] = a2 ? 4 * 9 : 0;
+    c12[3] = a3 ? Dl * s1m * s2m : 0.f; o12[3] = a3 ? -4 * 9 : 0;
+  }
+  // bond (2,3): lane half of the coefficients (times sqrt of n_3 or n_3 + 1 per pass)
+  float l23[4];
+  int o23[4];
+  {
+    const bool b_m = n2 >= 1, b_p = n2 <= 6;
+    l23[0] = b_m ? -J * s2m : 0.f; o23[0] = b_m ? 4 * 56 : 0;   // n_2 - 1, n_3 + 1
+    l23[1] = b_p ? -J * s2p : 0.f; o23[1] = b_p ? -4 * 56 : 0;  // n_2 + 1, n_3 - 1
+    l23[2] = b_p ? Dl * s2p : 0.f; o23[2] = b_p ? 4 * 72 : 0;   // n_2 + 1, n_3 + 1
+    l23[3] = b_m ? Dl * s2m : 0.f; o23[3] = b_m ? -4 * 72 : 0;  // n_2 - 1, n_3 - 1
+  }
+  const float dl0 = fdiag((float)n1) + fdiag((float)n2) + fdiag((float)(2 * c));
+  const float dl1 = fdiag((float)n1) + fdiag((float)n2) + fdiag((float)(2 * c + 1));
+  __syncthreads();
+
+  float e = 0.f, nn = 0.f;
+  const float4 *__restrict__ gt = g4 + tb;  // this tile's first word (wavefront-uniform)
+  const uint32_t ut = (uint32_t)t;
+#pragma unroll
+  for (int p = 0; p < 8; ++p) {
+    // p is a compile-time constant after unrolling: sqrt(n_3), validity of n_3 +- 1
+    const float smp = sqrtf((float)p), spp = sqrtf((float)p + 1.f);
+    const int w = p * 256 + t;  // this thread's float4 word in the tile
+    // bonds leaving the tile: all loads first, each under a wavefront-uniform
+    // validity test (the same test guards its use below)
+    float4 gv[NBA][4];
+    bool gvv[NBA][4];
+    if constexpr (L > 4) {
+      const int nj = hd[4];
+      gvv[0][0] = p >= 1 && nj <= 6;
+      gvv[0][1] = p <= 6 && nj >= 1;
+      gvv[0][2] = p <= 6 && nj <= 6;
+      gvv[0][3] = p >= 1 && nj >= 1;
+      const int o0[4] = {-256 + 2048, 256 - 2048, 256 + 2048, -256 - 2048};
+#pragma unroll
+      for (int k = 0; k < 4; ++k)
+        if (gvv[0][k]) gv[0][k] = (gt + (p * 256 + o0[k]))[ut];
+    }
+#pragma unroll
+    for (int b = 1; b < NB; ++b)
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        gvv[b][k] = ev[b][k];
+        if (gvv[b][k]) gv[b][k] = (gt + (p * 256 + eo[b][k]))[ut];
+      }
+    const float4 own = tile[w];
+    float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
+    // bond (0,1)
+    {
+      const float4 P = tile[w + oP], M = tile[w + oM];
+      const float2 Pm = tile2[2 * (w + oP) + sm1], Pp = tile2[2 * (w + oP) + sp2];
+      const float2 Mm = tile2[2 * (w + oM) + sm1], Mp = tile2[2 * (w + oM) + sp2];
+      acc.x = fmaf(cPJ0, Pm.x, acc.x); acc.y = fmaf(cPJ0, Pm.y, acc.y);
+      acc.x = fmaf(cPD0, P.z, acc.x);  acc.y = fmaf(cPD0, P.w, acc.y);
+      acc.x = fmaf(cMJ0, M.z, acc.x);  acc.y = fmaf(cMJ0, M.w, acc.y);
+      acc.x = fmaf(cMD0, Mm.x, acc.x); acc.y = fmaf(cMD0, Mm.y, acc.y);
+      acc.z = fmaf(cPJ1, P.x, acc.z);  acc.w = fmaf(cPJ1, P.y, acc.w);
+      acc.z = fmaf(cPD1, Pp.x, acc.z); acc.w = fmaf(cPD1, Pp.y, acc.w);
+      acc.z = fmaf(cMJ1, Mp.x, acc.z); acc.w = fmaf(cMJ1, Mp.y, acc.w);
+      acc.z = fmaf(cMD1, M.x, acc.z);  acc.w = fmaf(cMD1, M.y, acc.w);
+    }
+    // bond (1,2)
+#pragma unroll
+    for (int k = 0; k < 4; ++k) fma4(acc, c12[k], tile[w + o12[k]]);
+    // bond (2,3)
+    if (p <= 6) {
+      fma4(acc, l23[0] * spp, tile[w + o23[0]]);
+      fma4(acc, l23[2] * spp, tile[w + o23[2]]);
+    }
+    if (p >= 1) {
+      fma4(acc, l23[1] * smp, tile[w + o23[1]]);
+      fma4(acc, l23[3] * smp, tile[w + o23[3]]);
+    }
+    // bonds leaving the tile
+    if constexpr (L > 4) {
+      const float c0[4] = {-J * smp * s4p, -J * spp * s4m, Dl * spp * s4p, Dl * smp * s4m};
+#pragma unroll
+      for (int k = 0; k < 4; ++k)
+        if (gvv[0][k]) fma4(acc, c0[k], gv[0][k]);
+    }
+#pragma unroll
+    for (int b = 1; b < NB; ++b)
+#pragma unroll
+      for (int k = 0; k < 4; ++k)
+        if (gvv[b][k]) fma4(acc, ec[b][k], gv[b][k]);
+    // diagonal, energy and norm
+    const float dp = dtile + fdiag((float)p);
+    const float dg0 = dp + dl0, dg1 = dp + dl1;
+    acc.x = fmaf(dg0, own.x, acc.x);
+    acc.y = fmaf(dg0, own.y, acc.y);
+    acc.z = fmaf(dg1, own.z, acc.z);
+    acc.w = fmaf(dg1, own.w, acc.w);
+    e = fmaf(own.x, acc.x, fmaf(own.y, acc.y, e));
+    e = fmaf(own.z, acc.z, fmaf(own.w, acc.w, e));
+    nn = fmaf(own.x, own.x, fmaf(own.y, own.y, nn));
+    nn = fmaf(own.z, own.z, fmaf(own.w, own.w, nn));
+    (o4 + tb + p * 256)[ut] = acc;
+  }
+  e_out = e;
+  nn_out = nn;
+  __syncthreads();
+}
+
 // ---------------------------------------------------------------- pool scoring (Eq. grad)
 // z += conj(a) * b
 __device__ __forceinline__ void cdot_acc(float &zr, float &zi, float2 a, float2 b) {

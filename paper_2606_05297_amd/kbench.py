@@ -32,6 +32,7 @@ def main():
     ap.add_argument("--mlp-batch", type=int, default=16384)
     ap.add_argument("--lib", default=None, help="path of an alternative libfock.so build")
     ap.add_argument("--schedule", type=int, default=None, help="stencil tile schedule (fock_set_stencil_schedule)")
+    ap.add_argument("--stencil", type=int, default=None, help="H psi work split (fock_set_stencil_variant)")
     args = ap.parse_args()
     import numpy as np
     import torch
@@ -44,6 +45,8 @@ def main():
         lib.load(args.lib)
     if args.schedule is not None:
         lib.set_stencil_schedule(args.schedule)
+    if args.stencil is not None:
+        lib.set_stencil_variant(args.stencil)
     cfg = W.config(args.workload)
     h = lib.ham_from(cfg)
     L, d = cfg["L"], cfg["d"]
@@ -134,7 +137,7 @@ def main():
                 res[name]["TFLOPs"] = fl / (avg * 1e-3) / 1e12
                 res[name]["mfma_frac_fp32"] = res[name]["TFLOPs"] / 157.3
     print(json.dumps({"workload": args.workload, "iters": args.iters, "schedule": lib.get_stencil_schedule(),
-                      "kernels": res}), flush=True)
+                      "stencil": lib.get_stencil_variant(), "kernels": res}), flush=True)
 
 
 if __name__ == "__main__":

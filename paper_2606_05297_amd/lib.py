@@ -81,6 +81,7 @@ def load(path: str = LIB_PATH):
     L.fock_version.restype = C.c_int
     L.fock_workspace_bytes.argtypes = [C.POINTER(Ham), C.c_int, C.c_int, C.POINTER(C.c_size_t)]
     L.fock_set_stencil_schedule.argtypes = [C.c_int]
+    L.fock_set_stencil_variant.argtypes = [C.c_int]
     fp = C.POINTER(C.c_float)
     L.fock_mlp_create.argtypes = [C.c_int, C.POINTER(C.c_void_p)]
     L.fock_mlp_set_params.argtypes = [vp, fp, C.c_int, vp]
@@ -536,6 +537,19 @@ def get_gate_fusion() -> int:
 
 def get_stencil_schedule() -> int:
     return int(load().fock_get_stencil_schedule())
+
+
+STENCIL_ROWS, STENCIL_LANES = 0, 1
+
+
+def set_stencil_variant(variant: int):
+    """Work split of the H psi kernel: 0 = one thread per row, 1 = four lanes per
+    row (d = 8, 4 <= L <= 10, open chains; elsewhere the row split runs)."""
+    _check(load().fock_set_stencil_variant(int(variant)))
+
+
+def get_stencil_variant() -> int:
+    return int(load().fock_get_stencil_variant())
 
 
 def stencil_schedule_table(L: int, d: int, scheme: int, n: int):

@@ -171,6 +171,21 @@ def test_stencil_schedules_are_permutations():
         lib.set_stencil_schedule(99)
 
 
+def test_stencil_variant_setter():
+    """The H psi work split is a process-wide setting: both values round-trip,
+    anything else is rejected and leaves the setting unchanged."""
+    prev = lib.get_stencil_variant()
+    try:
+        for v in (lib.STENCIL_LANES, lib.STENCIL_ROWS):
+            lib.set_stencil_variant(v)
+            assert lib.get_stencil_variant() == v
+        with pytest.raises(lib.FockError):
+            lib.set_stencil_variant(2)
+        assert lib.get_stencil_variant() == lib.STENCIL_ROWS
+    finally:
+        lib.set_stencil_variant(prev)
+
+
 def test_mfma_operand_overlap_check():
     """The build rejects matrix instructions whose destination partially
     overlaps the accumulator input (identical or disjoint ranges are fine)."""

@@ -89,6 +89,65 @@ def test_apply_H_parity(case, schedule):
     assert E2 == E and n22 == n2
 
 
+@pytest.fixture
+def stencil(request):
+    prev = lib.get_stencil_variant()
+    lib.set_stencil_variant(request.param)
+    yield request.param
+    lib.set_stencil_variant(prev)
+
+
+LANE_CASES = [
+    # (L, d, periodic, J, U, mu, Delta, K): d = 8 open chains, the lane split's domain
+    (4, 8, False, 1.0, 0.0, 0.0, 0.5, 0.2),    # a single tile, no bond leaves it
+    (5, 8, False, 1.0, 0.0, 0.3, 0.45, 0.15),  # only the bond (3,4) leaves the tile
+    (6, 8, False, 0.8, 1.2, 0.2, 0.0, 0.0),    # Bose-Hubbard, open, Delta = 0
+    (7, 8, False, -0.6, 0.4, -0.3, 0.7, 0.25),
+]
+
+
+@pytest.mark.parametrize("case", LANE_CASES, ids=lambda c: f"L{c[0]}d{c[1]}o")
+def test_apply_H_lane_split_parity(case):
+    """Four-lanes-per-row H psi against the oracle; against the row split to
+    FP32 rounding; deterministic; a ring chain (outside its domain) runs the
+    row split and matches it bit for bit."""
+    L, d, per, J, U, mu, Dl, K = case
+    say("apply_H lanes", case)
+    ho, hl = ham_pair(L, d, per, J, U, mu, Dl, K)
+    psi = W.random_state(L, d, seed=L * 100 + d + 7)
+    ref = O.apply_H(ho, psi.astype(np.complex128))
+    x = dev(psi)
+    ys = {}
+    prev = lib.get_stencil_variant()
+    try:
+        for v in (lib.STENCIL_ROWS, lib.STENCIL_LANES):
+            lib.set_stencil_variant(v)
+            y = torch.empty(d**L, dtype=torch.complex64, device="cuda")
+            ws = lib.workspace(hl)
+            E, n2 = lib.apply_H(hl, x, y, ws)
+            ys[v] = (host(y), E, n2)
+            E2, n22 = lib.apply_H(hl, x, y, ws)
+            assert E2 == E and n22 == n2
+        got, E, n2 = ys[lib.STENCIL_LANES]
+        assert np.abs(got - ref).max() <= 2e-5 * np.abs(ref).max()
+        Eref = np.vdot(psi.astype(np.complex128), ref).real
+        assert abs(E - Eref) <= 1e-5 * max(1.0, abs(Eref))
+        assert abs(n2 - 1.0) <= 1e-6
+        rows = ys[lib.STENCIL_ROWS][0]
+        assert np.abs(got - rows).max() <= 4e-6 * np.abs(ref).max()
+        # a ring of the same size is outside the lane split: the row kernel runs
+        ho_r, hl_r = ham_pair(L, d, True, J, U, mu, Dl, K)
+        out = []
+        for v in (lib.STENCIL_ROWS, lib.STENCIL_LANES):
+            lib.set_stencil_variant(v)
+            y = torch.empty(d**L, dtype=torch.complex64, device="cuda")
+            lib.apply_H(hl_r, x, y, lib.workspace(hl_r))
+            out.append(host(y))
+        assert np.array_equal(out[0], out[1])
+    finally:
+        lib.set_stencil_variant(prev)
+
+
 POOL_CASES = [
     (3, 4, False, 1.0, 2.0, 0.0, 0.0, 0.0, "all", ("HR", "HI", "DH", "PR", "PI")),
     (4, 5, True, 1.0, 0.7, 0.2, 0.5, 0.2, "nn+nnn", ("HR", "HI", "DH", "PR", "PI")),
@@ -239,9 +298,10 @@ def kk_full():
     return c, ho, hl, psi
 
 
-def test_full_kitaev_l8_d8_apply_H_sampled_and_energy(kk_full):
+@pytest.mark.parametrize("stencil", [0, 1], indirect=True, ids=["rows", "lanes"])
+def test_full_kitaev_l8_d8_apply_H_sampled_and_energy(kk_full, stencil):
     c, ho, hl, psi = kk_full
-    say("full kk apply_H")
+    say("full kk apply_H, stencil", stencil)
     x, y = dev(psi), torch.empty(8**8, dtype=torch.complex64, device="cuda")
     ws = lib.workspace(hl, len(c["pool"]), 64)
     E, n2 = lib.apply_H(hl, x, y, ws)
