@@ -33,6 +33,9 @@ def main():
     ap.add_argument("--lib", default=None, help="path of an alternative libfock.so build")
     ap.add_argument("--schedule", type=int, default=None, help="stencil tile schedule (fock_set_stencil_schedule)")
     ap.add_argument("--stencil", type=int, default=None, help="H psi work split (fock_set_stencil_variant)")
+    ap.add_argument("--hot", action="store_true",
+                    help="apply H psi to one state and one output buffer every time (input stays cache-resident, "
+                         "as inside an ADAPT step) instead of rotating over three")
     args = ap.parse_args()
     import numpy as np
     import torch
@@ -73,7 +76,8 @@ def main():
         print(f"[kbench] copy done", file=sys.stderr, flush=True)
     if "apply_h" in want:
         for k in range(args.iters):
-            lib.apply_H(h, states[k % 3], outs[k % 3], ws, energy=(k == args.iters - 1))
+            j = 0 if args.hot else k % 3
+            lib.apply_H(h, states[j], outs[j], ws, energy=(k == args.iters - 1))
         print(f"[kbench] apply_h done", file=sys.stderr, flush=True)
     if "pool" in want:
         for k in range(3):
