@@ -31,7 +31,7 @@ CSRC = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc")
 
 # kernel family -> (kernel base names, source files the family is built from)
 FAMILIES = {
-    "apply_h": (("k_apply_h",), ("kernels_h.hip", "stencil_kernels.h", "device_common.h")),
+    "apply_h": (("k_apply_h", "k_apply_h_lanes8"), ("kernels_h.hip", "stencil_kernels.h", "device_common.h")),
     "pool_grads": (("k_pool",), ("kernels_pool.hip", "stencil_kernels.h", "device_common.h")),
     "gate2": (("k_gate2", "k_gate2_m0"), ("gate_kernels.h", "kernels_gate.hip", "device_common.h")),
     "gate2_adjoint": (("k_gate2_adj", "k_gate2_adj_m0"), ("gate_kernels.h", "kernels_gate.hip", "device_common.h")),
