@@ -139,6 +139,32 @@ def test_adapt_kitaev_kerr_l8_d8_first_steps_replay():
     ad.close()
 
 
+def test_adapt_kitaev_kerr_l8_d8_benchmark_trajectory_replay():
+    """The benchmark's run (Kitaev-Kerr L=8 d=8 from the vacuum, 12 ADAPT
+    steps, adjoint gradients, inverse Hessian recycled): every step lowers the
+    energy, and after steps 6 and 12 the oracle re-evaluates the GPU's own
+    ansatz and angles in FP64 (|dE| <= 1e-5 |E|)."""
+    c = W.config("kk_l8_d8")
+    ho, hl = oham(c), lib.ham_from(c)
+    psi0 = O.fock_state(8, 8, c["occ"])
+    say("adapt kk_l8_d8 12 steps, Hessian recycling")
+    ad = lib.Adapt(hl, c["pool"], dev(psi0), max_iters=c["max_iters"], recycle_hessian=True)
+    reps, checks = [], {}
+    for s in range(1, 13):
+        reps.append(ad.step())
+        if s in (6, 12):
+            checks[s] = ad.ansatz()
+    ad.close()
+    Es = [r["E"] for r in reps]
+    assert all(a > b for a, b in zip(Es, Es[1:])), Es
+    for s, (ops, th) in checks.items():
+        assert len(ops) == s
+        say("oracle replay after step", s)
+        psi = O.ansatz_state(psi0, ops, th, 8, 8)
+        E = np.vdot(psi, O.apply_H_slices(ho, psi)).real / np.vdot(psi, psi).real
+        assert abs(reps[s - 1]["E"] - E) <= 1e-5 * abs(E), (s, reps[s - 1]["E"], E)
+
+
 def test_autograd_adjoint_energy_matches_oracle_and_fd():
     """torch.autograd through the adjoint sweep: E and theta.grad match the
     oracle's adjoint gradient (<= 1e-4 max(1, |g|)) and the GPU central
