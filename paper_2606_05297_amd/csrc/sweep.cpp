@@ -103,7 +103,7 @@ double *pin_res(fock_sweep *sw) {
 
 // ---------------------------------------------------------------- item lists
 struct Lists {
-  std::vector<std::vector<std::vector<SweepItem>>> fwd, rev;  // [k][group]
+  std::vector<std::vector<std::vector<SweepItem>>> fwd, rev;  // [k][2 * group + item class]
   std::vector<std::vector<SweepHItem>> h;                     // [group]
   std::vector<SweepRItem> red;
 };
@@ -113,8 +113,8 @@ void build_lists(fock_sweep *sw, const std::vector<char> &sel, bool grad, Lists 
   for (size_t p = 0; p < sw->pts.size(); ++p)
     if (sel[p]) maxn = std::max(maxn, (int)sw->pts[p].ops.size());
   const int NG = (int)sw->groups.size();
-  Ls->fwd.assign(maxn, std::vector<std::vector<SweepItem>>(NG));
-  Ls->rev.assign(maxn, std::vector<std::vector<SweepItem>>(NG));
+  Ls->fwd.assign(maxn, std::vector<std::vector<SweepItem>>(2 * NG));
+  Ls->rev.assign(maxn, std::vector<std::vector<SweepItem>>(2 * NG));
   Ls->h.assign(NG, {});
   Ls->red.clear();
   for (size_t pi = 0; pi < sw->pts.size(); ++pi) {
@@ -142,19 +142,20 @@ void build_lists(fock_sweep *sw, const std::vector<char> &sel, bool grad, Lists 
         it.A = G.T.A[op.type];
         nb = sweep_gate_blocks(P.g.d, (int)P.g.n_amp, op.i);
       }
+      const int li = 2 * P.group + (it.variant == 1 && sweep_split_classes(P.g.d) ? 1 : 0);  // item class list
       for (int vb = 0; vb < nb; ++vb) {
         SweepItem f = it;
         f.vb = vb;
         f.src = k == 0 ? P.psi0 : P.phi;
         f.dst = P.phi;
-        Ls->fwd[k][P.group].push_back(f);
+        Ls->fwd[k][li].push_back(f);
         if (grad) {
           SweepItem r = it;
           r.vb = vb;
           r.dst = P.phi;
           r.lam = P.lam;
           r.partial = P.partial + (size_t)k * P.rs;
-          Ls->rev[k][P.group].push_back(r);
+          Ls->rev[k][li].push_back(r);
         }
       }
       if (grad) {
@@ -219,9 +220,9 @@ int enqueue_eval(fock_sweep *sw, const Lists &Ls, const std::vector<size_t> &off
   }
   const int NG = (int)sw->groups.size();
   for (size_t k = 0; k < Ls.fwd.size(); ++k)
-    for (int gi = 0; gi < NG; ++gi) {
-      const auto &v = Ls.fwd[k][gi];
-      int rc = sweep_launch_gate(sw->groups[gi].d, (const SweepItem *)(base + offs[oi++]), (int)v.size(),
+    for (int li = 0; li < 2 * NG; ++li) {
+      const auto &v = Ls.fwd[k][li];
+      int rc = sweep_launch_gate(sw->groups[li / 2].d, li % 2, (const SweepItem *)(base + offs[oi++]), (int)v.size(),
                                  sw->active_d, sw->grid, s);
       if (rc) return rc;
     }
@@ -240,13 +241,14 @@ int enqueue_eval(fock_sweep *sw, const Lists &Ls, const std::vector<size_t> &off
   }
   if (grad) {
     for (int k = (int)Ls.rev.size() - 1; k >= 0; --k)
-      for (int gi = 0; gi < NG; ++gi) {
-        const auto &v = Ls.rev[k][gi];
-        int rc = sweep_launch_adj(sw->groups[gi].d, (const SweepItem *)(base + offs[oi + (size_t)k * NG + gi]),
-                                  (int)v.size(), sw->active_d, sw->grid, s);
+      for (int li = 0; li < 2 * NG; ++li) {
+        const auto &v = Ls.rev[k][li];
+        int rc = sweep_launch_adj(sw->groups[li / 2].d, li % 2,
+                                  (const SweepItem *)(base + offs[oi + (size_t)k * 2 * NG + li]), (int)v.size(),
+                                  sw->active_d, sw->grid, s);
         if (rc) return rc;
       }
-    oi += Ls.rev.size() * NG;
+    oi += Ls.rev.size() * 2 * NG;
     int rc = sweep_launch_reduce((const SweepRItem *)(base + offs[oi]), (int)Ls.red.size(), sw->active_d, sw->grid,
                                  s);
     if (rc) return rc;
@@ -256,7 +258,8 @@ int enqueue_eval(fock_sweep *sw, const Lists &Ls, const std::vector<size_t> &off
 }
 
 // Lay out all item lists in one device blob; offs lists, in order: forward
-// [k][g], H [g], E/norm reduce (offset, count), reverse [k][g], grad reduce,
+// [k][2 g + class], H [g], E/norm reduce (offset, count), reverse
+// [k][2 g + class], grad reduce,
 // and finally the per-point HamArgs array.
 int stage_lists(fock_sweep *sw, const Lists &Ls, bool grad, std::vector<size_t> *offs) {
   std::vector<char> blob;

@@ -6,6 +6,31 @@
 
 namespace fock {
 
+// Device pointer stored in an item list.  It is typed in the global address
+// space: a kernel that reads a plain pointer from memory cannot tell where it
+// points and emits flat memory instructions (64-bit address registers, waits
+// shared with LDS traffic) for every access made through it.
+template <class T>
+struct GPtr {
+  __attribute__((address_space(1))) T *p;
+  GPtr() = default;
+  __host__ __device__ GPtr(T *q) : p((__attribute__((address_space(1))) T *)q) {}
+  __host__ __device__ operator T *() const { return (T *)p; }
+};
+
+// Read-only table pointer stored in an item list (gate matrices, generator
+// blocks, pool descriptors): typed in the constant address space, so that
+// wavefront-uniform reads through it become scalar loads, as they do through
+// const __restrict__ kernel arguments.  The data must not change while a
+// kernel that reads it runs.
+template <class T>
+struct CPtr {
+  __attribute__((address_space(4))) T *p;
+  CPtr() = default;
+  __host__ __device__ CPtr(T *q) : p((__attribute__((address_space(4))) T *)q) {}
+  __host__ __device__ operator T *() const { return (T *)p; }
+};
+
 // One workgroup's share of one gate (forward) or of its reverse step.
 // variant: 0 = two-mode gate with i >= 1, 1 = two-mode gate on (0, j) (LDS),
 // 2 = single-mode diagonal gate.  Forward: dst <- O src.  Reverse: dst = phi,
@@ -14,39 +39,44 @@ struct SweepItem {
   int p, vb, variant, kind;
   GateLaunch gl;
   DiagLaunch dl;
-  const float2 *U;
-  const float2 *A;
-  const float2 *src;
-  float2 *dst;
-  float2 *lam;
-  double *partial;
+  CPtr<const float2> U;
+  CPtr<const float2> A;
+  GPtr<const float2> src;
+  GPtr<float2> dst;
+  GPtr<float2> lam;
+  GPtr<double> partial;
 };
 
 // One tile of H psi or of pool scoring for point p.
 struct SweepHItem {
   int p, vb;
-  const float2 *psi;
-  float2 *hpsi;
-  double *partial;
+  GPtr<const float2> psi;
+  GPtr<float2> hpsi;
+  GPtr<double> partial;
 };
 
 // One fixed-order sum (see k_sweep_reduce).
 struct SweepRItem {
   int p, mode, nblocks, ncols, col, stride;
-  const double *partial;
-  double *out;
+  GPtr<const double> partial;
+  GPtr<double> out;
 };
 
 struct SweepPoolArgs {
   PoolArgs args;
-  const PoolPair *pairs;
-  const PoolDiag *diags;
+  CPtr<const PoolPair> pairs;
+  CPtr<const PoolDiag> diags;
 };
 
 bool sweep_supports_d(int d);
 int sweep_gate_blocks(int d, int namp, int i);
-int sweep_launch_gate(int d, const SweepItem *items, int n, const int *active, int grid, hipStream_t s);
-int sweep_launch_adj(int d, const SweepItem *items, int n, const int *active, int grid, hipStream_t s);
+// Whether the items of a gate layer at cutoff d are split into two classes
+// (separate lists and launches): 0 = two-mode gates on modes i >= 1 and
+// single-mode phases, 1 = two-mode gates on mode 0 (variant 1 items).  When
+// not split, every item sits in the class-0 list and cls is ignored.
+bool sweep_split_classes(int d);
+int sweep_launch_gate(int d, int cls, const SweepItem *items, int n, const int *active, int grid, hipStream_t s);
+int sweep_launch_adj(int d, int cls, const SweepItem *items, int n, const int *active, int grid, hipStream_t s);
 int sweep_launch_h(int d, const SweepHItem *items, int n, const HamArgs *hams, const int *active, int grid,
                    hipStream_t s);
 int sweep_launch_pool(int d, const SweepHItem *items, int n, const SweepPoolArgs *pa, const int *active, int grid,

@@ -9,9 +9,16 @@
 
 namespace fock {
 
+// Gate and reverse-step items of one gate layer: at d = 8 they come in two
+// classes launched separately, so that each kernel declares only the LDS its
+// items use (64 kB of mode-0 tiles would otherwise cap the occupancy of the
+// direct items): class 0 = two-mode gates on modes i >= 1 and single-mode
+// phases, class 1 = two-mode gates on mode 0.  At d <= 6 the mode-0 tiles are
+// small and one launch per layer runs all items (fewer launches for the small
+// states, whose kernels are short).
 template <int D>
-__global__ __launch_bounds__(kBlock) void k_sweep_gate(const SweepItem *__restrict__ items, int n,
-                                                       const int *__restrict__ active) {
+__global__ __launch_bounds__(kBlock) void k_sweep_gate_all(const SweepItem *__restrict__ items, int n,
+                                                           const int *__restrict__ active) {
   __shared__ float2 tile[m0_tile_elems<D>()];
   __shared__ uint32_t fbase[lds_fibers<D>()];
   __shared__ float2 phs[kMaxD];
@@ -29,8 +36,8 @@ __global__ __launch_bounds__(kBlock) void k_sweep_gate(const SweepItem *__restri
 }
 
 template <int D>
-__global__ __launch_bounds__(kBlock) void k_sweep_adj(const SweepItem *__restrict__ items, int n,
-                                                      const int *__restrict__ active) {
+__global__ __launch_bounds__(kBlock) void k_sweep_adj_all(const SweepItem *__restrict__ items, int n,
+                                                          const int *__restrict__ active) {
   __shared__ float2 tp[m0_tile_elems<D>()], tl[m0_tile_elems<D>()];
   __shared__ uint32_t fbase[lds_fibers<D>()];
   __shared__ float2 phs[kMaxD];
@@ -46,6 +53,70 @@ __global__ __launch_bounds__(kBlock) void k_sweep_adj(const SweepItem *__restric
       case 3: gacc = adj_m0_block<D, KIND_DIFF>(g.vb, g.dst, g.lam, g.U, g.A, g.gl, tp, tl, fbase); break;
       default: gacc = diag_adj_block<D>(g.vb, g.dst, g.lam, g.U, g.dl, phs); break;
     }
+    const double sg = block_sum_d((double)gacc, red);
+    if (threadIdx.x == 0) g.partial[g.vb] = sg;
+  }
+}
+
+template <int D>
+__global__ __launch_bounds__(kBlock) void k_sweep_gate(const SweepItem *__restrict__ items, int n,
+                                                       const int *__restrict__ active) {
+  __shared__ float2 phs[kMaxD];
+  for (int it = blockIdx.x; it < n; it += gridDim.x) {
+    const SweepItem g = items[it];
+    if (!active[g.p]) continue;
+    switch (g.variant * 2 + g.kind) {
+      case 0: gate2_direct_block<D, KIND_SUM, false>(g.vb, g.src, g.dst, g.U, g.gl); break;
+      case 1: gate2_direct_block<D, KIND_DIFF, false>(g.vb, g.src, g.dst, g.U, g.gl); break;
+      default: diag_block<D, false>(g.vb, g.src, g.dst, g.U, g.dl, phs); break;
+    }
+  }
+}
+
+template <int D>
+__global__ __launch_bounds__(kBlock) void k_sweep_gate_m0(const SweepItem *__restrict__ items, int n,
+                                                          const int *__restrict__ active) {
+  __shared__ float2 tile[m0_tile_elems<D>()];
+  __shared__ uint32_t fbase[lds_fibers<D>()];
+  for (int it = blockIdx.x; it < n; it += gridDim.x) {
+    const SweepItem g = items[it];
+    if (!active[g.p]) continue;
+    if (g.kind == KIND_SUM) gate2_m0_block<D, KIND_SUM, false>(g.vb, g.src, g.dst, g.U, g.gl, tile, fbase);
+    else gate2_m0_block<D, KIND_DIFF, false>(g.vb, g.src, g.dst, g.U, g.gl, tile, fbase);
+  }
+}
+
+template <int D>
+__global__ __launch_bounds__(kBlock) void k_sweep_adj(const SweepItem *__restrict__ items, int n,
+                                                      const int *__restrict__ active) {
+  __shared__ float2 phs[kMaxD];
+  __shared__ double red[4];
+  for (int it = blockIdx.x; it < n; it += gridDim.x) {
+    const SweepItem g = items[it];
+    if (!active[g.p]) continue;
+    float gacc = 0.f;
+    switch (g.variant * 2 + g.kind) {
+      case 0: gacc = adj_direct_block<D, KIND_SUM>(g.vb, g.dst, g.lam, g.U, g.A, g.gl); break;
+      case 1: gacc = adj_direct_block<D, KIND_DIFF>(g.vb, g.dst, g.lam, g.U, g.A, g.gl); break;
+      default: gacc = diag_adj_block<D>(g.vb, g.dst, g.lam, g.U, g.dl, phs); break;
+    }
+    const double sg = block_sum_d((double)gacc, red);
+    if (threadIdx.x == 0) g.partial[g.vb] = sg;
+  }
+}
+
+template <int D>
+__global__ __launch_bounds__(kBlock) void k_sweep_adj_m0(const SweepItem *__restrict__ items, int n,
+                                                         const int *__restrict__ active) {
+  __shared__ float2 tp[m0_tile_elems<D>()], tl[m0_tile_elems<D>()];
+  __shared__ uint32_t fbase[lds_fibers<D>()];
+  __shared__ double red[4];
+  for (int it = blockIdx.x; it < n; it += gridDim.x) {
+    const SweepItem g = items[it];
+    if (!active[g.p]) continue;
+    const float gacc = g.kind == KIND_SUM
+                           ? adj_m0_block<D, KIND_SUM>(g.vb, g.dst, g.lam, g.U, g.A, g.gl, tp, tl, fbase)
+                           : adj_m0_block<D, KIND_DIFF>(g.vb, g.dst, g.lam, g.U, g.A, g.gl, tp, tl, fbase);
     const double sg = block_sum_d((double)gacc, red);
     if (threadIdx.x == 0) g.partial[g.vb] = sg;
   }
@@ -110,18 +181,31 @@ __global__ __launch_bounds__(kBlock) void k_sweep_reduce(const SweepRItem *__res
 
 bool sweep_supports_d(int d) { return d == 4 || d == 6 || d == 8; }
 
-int sweep_launch_gate(int d, const SweepItem *items, int n, const int *active, int grid, hipStream_t s) {
+bool sweep_split_classes(int d) { return d == 8; }
+
+int sweep_launch_gate(int d, int cls, const SweepItem *items, int n, const int *active, int grid,
+                      hipStream_t s) {
   if (n <= 0) return FOCK_OK;
-  SWEEP_D_SWITCH(d, hipLaunchKernelGGL(k_sweep_gate<D>, dim3(grid < n ? grid : n), dim3(kBlock), 0, s, items, n,
-                                       active));
+  const dim3 g(grid < n ? grid : n);
+  if (!sweep_split_classes(d))
+    SWEEP_D_SWITCH(d, hipLaunchKernelGGL(k_sweep_gate_all<D>, g, dim3(kBlock), 0, s, items, n, active))
+  else if (cls == 0)
+    hipLaunchKernelGGL(k_sweep_gate<8>, g, dim3(kBlock), 0, s, items, n, active);
+  else
+    hipLaunchKernelGGL(k_sweep_gate_m0<8>, g, dim3(kBlock), 0, s, items, n, active);
   FOCK_HIP(hipGetLastError());
   return FOCK_OK;
 }
 
-int sweep_launch_adj(int d, const SweepItem *items, int n, const int *active, int grid, hipStream_t s) {
+int sweep_launch_adj(int d, int cls, const SweepItem *items, int n, const int *active, int grid, hipStream_t s) {
   if (n <= 0) return FOCK_OK;
-  SWEEP_D_SWITCH(d, hipLaunchKernelGGL(k_sweep_adj<D>, dim3(grid < n ? grid : n), dim3(kBlock), 0, s, items, n,
-                                       active));
+  const dim3 g(grid < n ? grid : n);
+  if (!sweep_split_classes(d))
+    SWEEP_D_SWITCH(d, hipLaunchKernelGGL(k_sweep_adj_all<D>, g, dim3(kBlock), 0, s, items, n, active))
+  else if (cls == 0)
+    hipLaunchKernelGGL(k_sweep_adj<8>, g, dim3(kBlock), 0, s, items, n, active);
+  else
+    hipLaunchKernelGGL(k_sweep_adj_m0<8>, g, dim3(kBlock), 0, s, items, n, active);
   FOCK_HIP(hipGetLastError());
   return FOCK_OK;
 }
