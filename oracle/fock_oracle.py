@@ -64,7 +64,7 @@ class Ham:
     K: float = 0.0
 
 
-GEN_TYPES = ("HR", "HI", "DH", "PR", "PI", "KERR", "ROT")
+GEN_TYPES = ("HR", "HI", "DH", "PR", "PI", "KERR", "ROT", "CK")
 SINGLE_MODE = ("KERR", "ROT")
 
 
@@ -255,6 +255,7 @@ def generator_local(gtype: str, d: int) -> np.ndarray:
       DH = i (N_i a_i^+ a_j + a_j^+ a_i N_i)   (density-assisted hop)
       PR = a_i a_j - a_i^+ a_j^+          (two-mode squeezer, phi = 0)
       PI = i (a_i a_j + a_i^+ a_j^+)      (two-mode squeezer, phi = pi/2)
+      CK = i N_i N_j                      (cross-Kerr, Sec. II.B)
     Single-mode: KERR = i N^2, ROT = i N.
     """
     a = ladder(d)
@@ -270,6 +271,8 @@ def generator_local(gtype: str, d: int) -> np.ndarray:
         return np.kron(a, a) - np.kron(ad, ad)
     if gtype == "PI":
         return 1j * (np.kron(a, a) + np.kron(ad, ad))
+    if gtype == "CK":
+        return 1j * np.kron(N, N)
     if gtype == "KERR":
         return 1j * (N @ N)
     if gtype == "ROT":

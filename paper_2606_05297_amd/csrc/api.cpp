@@ -38,7 +38,7 @@ int check_ham(const fock_ham_t *h, uint32_t *namp) {
 }
 
 int check_op(const fock_op_t &op, int L) {
-  if (op.type < FOCK_HR || op.type > FOCK_ROT) return set_error(FOCK_ERR_ARG, "unknown op type %d", op.type);
+  if (op.type < FOCK_HR || op.type > FOCK_CK) return set_error(FOCK_ERR_ARG, "unknown op type %d", op.type);
   if (is_single_mode(op.type)) {
     if (op.i < 0 || op.i >= L) return set_error(FOCK_ERR_ARG, "mode %d out of range for L=%d", op.i, L);
     return FOCK_OK;
@@ -311,7 +311,7 @@ static FuseArgs make_fuse_args(const Ctx &c, const GateGroup &gr, const fock_op_
     const int b = blk_hi(KIND_SUM, d, sb) - blk_lo(KIND_SUM, d, sb) + 1;
     off += b * b;
   }
-  for (int t = 0; t < 5; ++t) a.A[t] = c.T.A[t];
+  for (int t = 0; t < kTwoModeTypes; ++t) a.A[t] = c.T.A[t];
   a.ng = gr.k1 - gr.k0;
   for (int q = 0; q < a.ng; ++q) {
     const int k = gr.k0 + q;
@@ -380,7 +380,8 @@ int run_circuit(Ctx &c, const fock_op_t *ops, const double *theta, int n, const 
       double *pk = part + (size_t)k * c.L.rs;
       ProfScope ps(is_single_mode(op.type) ? FOCK_K_DIAG : FOCK_K_ADJ, c.s, 32.0 * c.g.n_amp);
       if (is_single_mode(op.type)) rc = launch_diag_adj(c.g, op.i, op.type, U, phi, lam, pk, c.s);
-      else rc = launch_gate_adj(c.g, op.i, op.j, gate_kind(op.type), U, c.T.A[op.type], phi, lam, pk, c.s);
+      else rc = launch_gate_adj(c.g, op.i, op.j, gate_kind(op.type), U, c.T.A[table_slot(op.type)], phi, lam, pk,
+                                c.s);
       if (rc) return rc;
       }
     }
@@ -422,9 +423,9 @@ int pool_dev(Ctx &c, const fock_op_t *pool, int P, const float2 *psi, const floa
     for (; k1 < P && k1 - k0 < kMaxSlots; ++k1) {
       const fock_op_t &op = pool[k1];
       const int slot = k1 - k0;
-      if (is_single_mode(op.type)) {
+      if (is_pool_diagonal(op.type)) {
         if ((int)diags.size() >= kMaxDiagOps) break;
-        diags.push_back({(int16_t)op.i, (int16_t)op.type, (int16_t)slot, 0});
+        diags.push_back({(int16_t)op.i, (int16_t)op.type, (int16_t)slot, (int16_t)(op.type == FOCK_CK ? op.j : -1)});
         continue;
       }
       auto key = std::make_pair(op.i, op.j);

@@ -11,6 +11,8 @@
 // tiles of 64 fibres; wavefront w computes fibres 16w..16w+15 of a tile.
 // MFMA lane layout (16x16x4): lane l holds A[m = l % 16][k = l / 16],
 // B[k = l / 16][n = l % 16] and C[m = 4 (l / 16) + r][n = l % 16], r < 4.
+#include <atomic>
+
 #include "dense_internal.h"
 #include "gate_kernels.h"
 
@@ -179,11 +181,15 @@ int launch_gate_dense(const Geometry &geo, int i, int j, int kind, bool dag, con
     hipLaunchKernelGGL(k_dense_w<D>, dim3((C::KP * C::KP + kBlock - 1) / kBlock), dim3(kBlock), 0, s, U, kind,
                        dag ? 1 : 0, W);
     const size_t lds = sizeof(float) * ((size_t)C::KP * C::WS + (size_t)64 * C::XS);
-    static bool attr_set = false;  // dynamic LDS beyond 64 kB must be allowed once per kernel
-    if (!attr_set) {
+    // dynamic LDS beyond 64 kB must be allowed once per kernel and device
+    static std::atomic<uint32_t> attr_set{0};
+    int dev = 0;
+    FOCK_HIP(hipGetDevice(&dev));
+    const uint32_t bit = dev < 32 ? (1u << dev) : 0u;
+    if (!bit || !(attr_set.load() & bit)) {
       FOCK_HIP(hipFuncSetAttribute((const void *)k_gate2_dense<D>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                    (int)lds));
-      attr_set = true;
+      attr_set.fetch_or(bit);
     }
     const uint32_t ntile = (gl.nfib + 63) / 64;
     const int grid = (int)(ntile < 256 ? ntile : 256);

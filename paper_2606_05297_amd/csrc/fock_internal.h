@@ -61,7 +61,7 @@ struct PoolPair {
   int16_t pad;
 };
 struct PoolDiag {
-  int16_t r, type, slot, pad;  // KERR / ROT on mode r
+  int16_t r, type, slot, r2;  // KERR / ROT on mode r (r2 = -1), CK on modes (r, r2)
 };
 struct PoolArgs {
   int L, d, nrows, npairs, ndiag, nslots;
@@ -91,10 +91,15 @@ struct GateRec {
 // packed blocks of V (complex double, b x b row-major per block, column m is
 // eigenvector m) and the eigenvalues lambda (b per block) of G = -i A, and the
 // packed blocks of A itself (complex float).
+// Two-mode generator types with eigendata tables: HR, HI, DH, PR, PI and CK.
+constexpr int kTwoModeTypes = 6;
+// Table slot of a two-mode type (FOCK_HR..FOCK_PI -> 0..4, FOCK_CK -> 5).
+__host__ __device__ inline int table_slot(int type) { return type == FOCK_CK ? 5 : type; }
+
 struct EigTables {
-  const double *V[5];
-  const double *lam[5];
-  const float2 *A[5];
+  const double *V[kTwoModeTypes];
+  const double *lam[kTwoModeTypes];
+  const float2 *A[kTwoModeTypes];
   int d, psize;
 };
 
@@ -127,6 +132,9 @@ inline int packed_size(int d) {  // sum of b^2 over blocks (same for SUM and DIF
 void generator_dense(int type, int d, std::vector<double> &m);
 int gate_kind(int type);
 bool is_single_mode(int type);
+// Generators diagonal in the Fock basis (KERR, ROT, CK): pool scoring takes
+// them as -2 f(n) Im(conj(H psi) psi) terms instead of pair terms.
+bool is_pool_diagonal(int type);
 // Library-owned device eigendata for cutoff d (built on first use, per device).
 int get_tables(int d, EigTables *out);
 // Size of one gate's slot in a U buffer (complex entries).

@@ -22,7 +22,7 @@ struct FuseArgs {
   uint32_t tstride[kMaxFuseModes];  // d^m of the tile modes, ascending (tile position 0 = mode 0)
   uint32_t cstride[kMaxL];          // d^m of the other modes, ascending (digits of the tile index)
   int boff[2 * kMaxD];              // offset of block s in a packed two-mode table
-  const float2 *A[5];               // packed generator blocks of the two-mode types (gradients)
+  const float2 *A[kTwoModeTypes];   // packed generator blocks of the two-mode types by table_slot (gradients)
   FuseGate g[kMaxFuseGates];
 };
 

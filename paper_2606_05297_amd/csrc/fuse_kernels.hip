@@ -188,7 +188,7 @@ __global__ __launch_bounds__(kBlock) void k_fuse_adj(FuseArgs a, float2 *__restr
       int li = 1, lj = 1;
       for (int k = 0; k < g.ki; ++k) li *= D;
       for (int k = 0; k < g.kj; ++k) lj *= D;
-      const float2 *A = a.A[g.type];
+      const float2 *A = a.A[table_slot(g.type)];
       const int nf = nt / (D * D);
       for (int blk = wave; blk < NB; blk += kBlock / 64) {
         const int lo = blk_lo(g.kind, D, blk), b = blk_hi(g.kind, D, blk) - lo + 1;

@@ -45,6 +45,7 @@ FastDiv make_fastdiv(uint32_t v) {
 using cd = std::complex<double>;
 
 bool is_single_mode(int type) { return type == FOCK_KERR || type == FOCK_ROT; }
+bool is_pool_diagonal(int type) { return type == FOCK_KERR || type == FOCK_ROT || type == FOCK_CK; }
 int gate_kind(int type) { return (type == FOCK_PR || type == FOCK_PI) ? KIND_DIFF : KIND_SUM; }
 
 // Truncated annihilation operator, a|m> = sqrt(m)|m-1> (Sec. II.A).
@@ -78,6 +79,7 @@ void generator_dense(int type, int d, std::vector<double> &m) {
             case FOCK_DH: im = dh1 + dh2; break;
             case FOCK_PR: re = pr1 - pr2; break;
             case FOCK_PI: im = pr1 + pr2; break;
+            case FOCK_CK: im = (ip == i && jp == j) ? (double)(i * j) : 0.0; break;
             default: break;
           }
           const int r = ip * d + jp, c = i * d + j;
@@ -145,15 +147,17 @@ static std::map<std::pair<int, int>, TableSet> g_tabs;
 
 static int build_tables(int d, TableSet *ts) {
   const int ps = packed_size(d);
-  // layout: [V: 5 * ps complex double][lam: 5 * d*d double][A: 5 * ps float2]
-  const size_t nV = (size_t)5 * ps * 2, nL = (size_t)5 * d * d, nA = (size_t)5 * ps * 2;
+  // layout: [V: NT * ps complex double][lam: NT * d*d double][A: NT * ps float2], NT = kTwoModeTypes
+  constexpr int NT = kTwoModeTypes;
+  const size_t nV = (size_t)NT * ps * 2, nL = (size_t)NT * d * d, nA = (size_t)NT * ps * 2;
   std::vector<double> hv(nV + nL, 0.0);
   std::vector<float> ha(nA, 0.f);
   const int D2 = d * d;
-  for (int t = 0; t < 5; ++t) {
+  for (int t = 0; t < NT; ++t) {
+    const int type = t == table_slot(FOCK_CK) ? FOCK_CK : t;
     std::vector<double> A;
-    generator_dense(t, d, A);
-    const int kind = gate_kind(t);
+    generator_dense(type, d, A);
+    const int kind = gate_kind(type);
     int off = 0, loff = 0;
     double leak = 0.0;
     std::vector<char> covered((size_t)D2 * D2, 0);
@@ -186,7 +190,7 @@ static int build_tables(int d, TableSet *ts) {
           for (int m = 0; m < b; ++m) acc += V[p * b + m] * w[m] * std::conj(V[q * b + m]);
           res = std::max(res, std::abs(acc - G[p * b + q]));
         }
-      if (res > 1e-11) return set_error(FOCK_ERR_HIP, "gate eigendata residual %.3g (type %d, d %d)", res, t, d);
+      if (res > 1e-11) return set_error(FOCK_ERR_HIP, "gate eigendata residual %.3g (type %d, d %d)", res, type, d);
       for (int k = 0; k < b * b; ++k) {
         hv[(size_t)t * ps * 2 + 2 * (off + k)] = V[k].real();
         hv[(size_t)t * ps * 2 + 2 * (off + k) + 1] = V[k].imag();
@@ -197,7 +201,7 @@ static int build_tables(int d, TableSet *ts) {
     }
     for (size_t e = 0; e < (size_t)D2 * D2; ++e)
       if (!covered[e]) leak += std::fabs(A[2 * e]) + std::fabs(A[2 * e + 1]);
-    if (leak != 0.0) return set_error(FOCK_ERR_HIP, "generator type %d has entries outside its blocks", t);
+    if (leak != 0.0) return set_error(FOCK_ERR_HIP, "generator type %d has entries outside its blocks", type);
   }
   const size_t bytesD = (nV + nL) * sizeof(double), bytesA = nA * sizeof(float);
   void *dev = nullptr;
@@ -208,7 +212,7 @@ static int build_tables(int d, TableSet *ts) {
   const double *dV = (const double *)dev;
   const double *dL = dV + nV;
   const float2 *dA = (const float2 *)((const char *)dev + bytesD);
-  for (int t = 0; t < 5; ++t) {
+  for (int t = 0; t < NT; ++t) {
     ts->T.V[t] = dV + (size_t)t * ps * 2;
     ts->T.lam[t] = dL + (size_t)t * D2;
     ts->T.A[t] = dA + (size_t)t * ps;

@@ -50,8 +50,8 @@ __global__ __launch_bounds__(kBlock) void k_gate_build(const double *__restrict_
     loff += b;
   }
   const int p = (e - off) / b, q = (e - off) % b;
-  const double *V = T.V[r.type] + 2 * off;
-  const double *lam = T.lam[r.type] + loff;
+  const double *V = T.V[table_slot(r.type)] + 2 * off;
+  const double *lam = T.lam[table_slot(r.type)] + loff;
   double ur = 0.0, ui = 0.0;
   for (int m = 0; m < b; ++m) {
     double sn, cs;

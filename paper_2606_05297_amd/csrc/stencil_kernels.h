@@ -803,16 +803,17 @@ __device__ __forceinline__ void pool_block(int vb, const float2 *__restrict__ ps
       if (lrs[k] < 0) continue;
       float2 own[D];
       prow<D>(tile, lrs[k], own);
-      // -2 f(n_r) Im(conj(h) psi), f = n^2 (KERR) or n (ROT)
+      // -2 f(n) Im(conj(h) psi), f = n_r^2 (KERR), n_r (ROT) or n_r n_r2 (CK, r < r2)
+      const int m2 = pd.type == FOCK_CK ? digit_of(lo[k], hi[k], pd.r2) : 1;  // r2 >= 1: a row digit
       if (pd.r == 0) {
 #pragma unroll
         for (int q = 0; q < D; ++q) {
-          const float f = pd.type == FOCK_KERR ? (float)(q * q) : (float)q;
+          const float f = pd.type == FOCK_KERR ? (float)(q * q) : (float)(q * m2);
           v = fmaf(f, h[k][q].x * own[q].y - h[k][q].y * own[q].x, v);
         }
       } else {
         const int n = digit_of(lo[k], hi[k], pd.r);
-        const float f = pd.type == FOCK_KERR ? (float)(n * n) : (float)n;
+        const float f = pd.type == FOCK_KERR ? (float)(n * n) : (float)(n * m2);
         float s = 0.f;
 #pragma unroll
         for (int q = 0; q < D; ++q) s = fmaf(h[k][q].x, own[q].y, fmaf(-h[k][q].y, own[q].x, s));

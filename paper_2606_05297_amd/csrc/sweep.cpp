@@ -139,7 +139,7 @@ void build_lists(fock_sweep *sw, const std::vector<char> &sel, bool grad, Lists 
         it.variant = op.i == 0 ? 1 : 0;
         it.kind = gate_kind(op.type);
         it.gl = gate_launch_params(P.g, op.i, op.j);
-        it.A = G.T.A[op.type];
+        it.A = G.T.A[table_slot(op.type)];
         nb = sweep_gate_blocks(P.g.d, (int)P.g.n_amp, op.i);
       }
       const int li = 2 * P.group + (it.variant == 1 && sweep_split_classes(P.g.d) ? 1 : 0);  // item class list
@@ -661,8 +661,8 @@ int fock_sweep_create(const fock_sweep_point_t *pts, int npts, const fock_adapt_
     std::map<std::pair<int, int>, int> pidx;
     for (int k = 0; k < P.P && !rc; ++k) {
       const fock_op_t &op = P.pool[k];
-      if (is_single_mode(op.type)) {
-        diags.push_back({(int16_t)op.i, (int16_t)op.type, (int16_t)k, 0});
+      if (is_pool_diagonal(op.type)) {
+        diags.push_back({(int16_t)op.i, (int16_t)op.type, (int16_t)k, (int16_t)(op.type == FOCK_CK ? op.j : -1)});
         continue;
       }
       auto key = std::make_pair(op.i, op.j);

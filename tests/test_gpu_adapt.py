@@ -68,6 +68,31 @@ def test_adapt_bose_hubbard_l3_d4_replay():
     ad.close()
 
 
+def test_adapt_bose_hubbard_cross_kerr_pool_replay():
+    """Bose-Hubbard L=4 d=5 ring with the paper's number-conserving pool
+    (beam splitters HR/HI, cross-Kerr CK on nearest-neighbour pairs, Kerr K on
+    every site) after the warm-up layer: every step replayed by the oracle."""
+    L, d = 4, 5
+    ho, hl = O.Ham(L, d, True, J=1.0, U=3.0), lib.ham(L, d, True, 1.0, 3.0)
+    pool = W.pool(L, "nn", True, ("HR", "HI", "CK")) + W.site_ops(L, ("KERR",))
+    psi0 = O.fock_state(L, d, [1] * L)
+    wops = W.warmup_ops(L, True)
+    th0 = W.warmup_theta0(len(wops), 5)
+    say("adapt bh L4 d5 CK pool")
+    ad = lib.Adapt(hl, pool, dev(psi0), max_iters=8, warm_ops=wops, warm_theta0=th0)
+    ops, th = ad.ansatz()
+    types = set()
+    for _ in range(8):
+        rep = ad.step()
+        ops, th = replay_check(ad, ho, psi0, ops, th, rep, pool)
+        if rep["k_sel"] >= 0:
+            types.add(pool[rep["k_sel"]][0])
+        if rep["converged"] or rep["capped"]:
+            break
+    ad.close()
+    say("selected types", sorted(types))
+
+
 def test_adapt_kitaev_small_replay_and_modes():
     L, d = 4, 5
     c = dict(L=L, d=d, periodic=False, J=1.0, U=0.0, mu=0.0, Delta=0.5, K=0.2)

@@ -152,8 +152,8 @@ POOL_CASES = [
     (3, 4, False, 1.0, 2.0, 0.0, 0.0, 0.0, "all", ("HR", "HI", "DH", "PR", "PI")),
     (4, 5, True, 1.0, 0.7, 0.2, 0.5, 0.2, "nn+nnn", ("HR", "HI", "DH", "PR", "PI")),
     (5, 4, False, 1.0, 0.0, 0.0, 0.5, 0.2, "all", W.KITAEV_TYPES),
-    (4, 7, True, 1.0, 3.0, 0.0, 0.0, 0.0, "nn+nnn", W.BH_TYPES),
-    (6, 8, False, 1.0, 0.0, 0.0, 0.5, 0.2, "nn", W.KITAEV_TYPES),
+    (4, 7, True, 1.0, 3.0, 0.0, 0.0, 0.0, "nn+nnn", W.BH_TYPES + ("CK",)),
+    (6, 8, False, 1.0, 0.0, 0.0, 0.5, 0.2, "nn", W.KITAEV_TYPES + ("CK",)),
     (2, 6, False, 1.0, 1.0, 0.3, 0.3, 0.1, "all", ("HR", "HI", "DH", "PR", "PI")),
 ]
 
@@ -179,8 +179,8 @@ def test_pool_grads_large_pool_chunks():
     """More than 256 entries and duplicates force several launches."""
     L, d = 5, 3
     ho, hl = ham_pair(L, d, True, 1.0, 0.5, 0.1, 0.4, 0.1)
-    base = W.pool(L, "all", True, ("HR", "HI", "DH", "PR", "PI"))
-    pool = base * 6 + [("KERR", 1, -1)]
+    base = W.pool(L, "all", True, ("HR", "HI", "DH", "PR", "PI", "CK"))
+    pool = base * 5 + [("KERR", 1, -1), ("CK", 0, 4)]
     say("pool_grads chunks", len(pool))
     psi = W.random_state(L, d, seed=3)
     x, y = dev(psi), torch.empty(d**L, dtype=torch.complex64, device="cuda")
@@ -192,7 +192,7 @@ def test_pool_grads_large_pool_chunks():
 
 
 GATE_OPS = [("HR", 0, 1), ("HI", 1, 3), ("DH", 0, 2), ("DH", 2, 3), ("PR", 0, 3), ("PI", 1, 2), ("KERR", 0, -1),
-            ("KERR", 2, -1), ("ROT", 3, -1), ("ROT", 0, -1)]
+            ("KERR", 2, -1), ("ROT", 3, -1), ("ROT", 0, -1), ("CK", 0, 2), ("CK", 1, 3)]
 
 
 @pytest.mark.parametrize("d", [2, 3, 5, 8, 12, 16])
@@ -225,7 +225,7 @@ def test_gate_then_adjoint_is_identity_ragged():
     psi = W.random_state(L, d, seed=2)
     x = dev(psi)
     ws = lib.workspace(lib.ham(L, d), 0, 1)
-    for o in [("HR", 1, 4), ("PR", 0, 4), ("DH", 3, 4), ("KERR", 4, -1)]:
+    for o in [("HR", 1, 4), ("PR", 0, 4), ("DH", 3, 4), ("KERR", 4, -1), ("CK", 0, 3)]:
         say("gate roundtrip", o)
         lib.apply_gate2(L, d, o, 1.1, x, ws)
         lib.apply_gate2(L, d, o, 1.1, x, ws, adjoint=True)
@@ -236,6 +236,7 @@ ADJ_CASES = [
     (3, 4, False, 1.0, 2.0, 0.0, 0.0, 0.0, W.BH_TYPES, ("N", 3), 8),
     (4, 5, False, 1.0, 0.0, 0.0, 0.5, 0.2, W.KITAEV_TYPES, ("parity", 0), 12),
     (5, 4, True, 1.0, 1.2, 0.1, 0.3, 0.1, ("HR", "HI", "DH", "PR", "PI"), None, 10),
+    (5, 5, True, 1.0, 2.0, 0.0, 0.0, 0.0, W.BH_TYPES + ("CK",), ("N", 5), 10),
     (6, 8, False, 1.0, 0.0, 0.0, 0.5, 0.2, W.KITAEV_TYPES, ("parity", 0), 6),
 ]
 
@@ -415,7 +416,7 @@ FUSE_CASES = [
     # (L, d, periodic, J, U, mu, Delta, K, ops as (type, i, j))
     (5, 4, True, 1.0, 0.7, 0.1, 0.4, 0.2,
      [("HR", 0, 1), ("PR", 1, 2), ("HI", 2, 3), ("KERR", 2, -1), ("DH", 0, 1), ("PI", 3, 4), ("ROT", 0, -1),
-      ("HR", 0, 4), ("PR", 3, 4), ("HR", 0, 1)]),
+      ("HR", 0, 4), ("CK", 1, 2), ("PR", 3, 4), ("CK", 0, 1), ("HR", 0, 1)]),
     (6, 6, True, 1.0, 4.0, 0.0, 0.0, 0.0,
      [("HR", 0, 1), ("HR", 1, 2), ("HR", 2, 3), ("HR", 3, 4), ("HR", 4, 5), ("HR", 0, 5), ("KERR", 5, -1),
       ("ROT", 5, -1), ("DH", 4, 5), ("HI", 1, 2), ("HR", 0, 1)]),
@@ -471,7 +472,7 @@ def test_dense_mfma_gate_variant(d):
     ws = lib.workspace(lib.ham(L, d), 0, 1)
     prev = lib.get_gate_variant()
     try:
-        for o in [("HR", 0, 1), ("PR", 1, 3), ("DH", L - 2, L - 1), ("PI", 0, L - 1), ("HI", 2, 3)]:
+        for o in [("HR", 0, 1), ("PR", 1, 3), ("DH", L - 2, L - 1), ("PI", 0, L - 1), ("HI", 2, 3), ("CK", 0, 2)]:
             for adj in (False, True):
                 th = 0.41 if not adj else -0.23
                 out = {}

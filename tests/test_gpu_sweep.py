@@ -92,6 +92,36 @@ def test_sweep_equals_unbatched_and_oracle(tmp_path, unfused):
     sw.close()
 
 
+def test_sweep_with_cross_kerr_and_kerr_pool_entries(unfused):
+    """Pools extended by the paper's cross-Kerr (CK on every pool pair) and Kerr
+    (K on every site) generators: the batched sweep still equals the per-point
+    path bit for bit, and the oracle re-evaluates each point's final ansatz."""
+    pts = [dict(p) for p in small_points()[:4]]
+    for p in pts:
+        types = W.BH_TYPES if p["model"] == "bh" else W.KITAEV_TYPES
+        p["pool"] = W.pool(p["L"], "nn", p["periodic"], types + ("CK",)) + W.site_ops(p["L"], ("KERR",))
+    say("sweep CK", [(p["model"], p["L"], p["d"], len(p["pool"])) for p in pts])
+    entries = [entry(p) for p in pts]
+    singles = [lib.Adapt(e["ham"], e["pool"], e["psi0"], max_iters=4, warm_ops=e["warm_ops"],
+                         warm_theta0=e["warm_theta0"]) for e in entries]
+    sw = lib.Sweep(entries, max_iters=4)
+    last = [None] * len(pts)
+    for it in range(3):
+        reps, _ = sw.step()
+        for k, a in enumerate(singles):
+            r = a.step()
+            assert reps[k]["k_sel"] == r["k_sel"] and reps[k]["E"] == r["E"], (k, it)
+            last[k] = r
+    for a in singles:
+        a.close()
+    for k, p in enumerate(pts):
+        ops, th = sw.ansatz(k)
+        ho = O.Ham(p["L"], p["d"], p["periodic"], p["J"], p["U"], p["mu"], p["Delta"], p["K"])
+        E = O.energy_of(ho, O.fock_state(p["L"], p["d"], p["occ"]), ops, th)
+        assert abs(last[k]["E"] - E) <= 1e-5 * max(1.0, abs(E)), (k, last[k]["E"], E)
+    sw.close()
+
+
 def test_sweep_rejects_unsupported_cutoff():
     p = dict(W.sweep_points()[0])
     e = entry(p)

@@ -185,6 +185,25 @@ def test_generator_matrix_elements_by_hand():
     assert PR[li(3, 3), li(2, 3)] == 0.0   # truncation kills a^+ |3>
 
 
+def test_cross_kerr_closed_forms():
+    """CK = i N_i N_j: diagonal with entries i n_i n_j (local index n_i d + n_j);
+    exp(theta CK) multiplies each amplitude by exp(i theta n_i n_j), checked on a
+    random three-mode state with the digits read off the flat index."""
+    d = 4
+    CK = O.generator_local("CK", d)
+    assert CK[2 * d + 3, 2 * d + 3] == pytest.approx(6j)
+    assert np.count_nonzero(CK - np.diag(np.diag(CK))) == 0
+    L, th = 3, 0.61
+    psi = rand_c(d**L, 11)
+    for (i, j) in [(0, 1), (0, 2), (1, 2)]:
+        out = O.apply_gate(("CK", i, j), th, psi, L, d)
+        want = psi.copy()
+        for k in range(d**L):
+            n = [(k // d**r) % d for r in range(L)]
+            want[k] *= np.exp(1j * th * n[i] * n[j])
+        assert np.abs(out - want).max() < 1e-13
+
+
 def test_beam_splitter_binomial_closed_form():
     """exp(theta HR)|n, 0> = sum_k sqrt(C(n,k)) cos^(n-k) (-sin)^k |n-k, k> (exact for n <= d-1)."""
     L, d, th = 2, 6, 0.41
@@ -208,7 +227,8 @@ def test_two_mode_squeezed_vacuum():
 
 @pytest.mark.parametrize("g,sector", [("HR", ("N", 3)), ("HI", ("N", 3)), ("DH", ("N", 3)),
                                       ("PR", ("parity", 0)), ("PI", ("parity", 0)),
-                                      ("KERR", ("N", 3)), ("ROT", ("parity", 1))])
+                                      ("KERR", ("N", 3)), ("ROT", ("parity", 1)),
+                                      ("CK", ("N", 3)), ("CK", ("parity", 1))])
 def test_gates_preserve_sector(g, sector):
     L, d = 3, 4
     psi = W.random_state(L, d, 7, sector=sector, dtype=np.complex128)
@@ -228,7 +248,7 @@ def test_pool_gradient_fock_state_closed_form():
     h = O.Ham(L, d, False, J=J, U=1.1)
     occ = [3, 0, 2, 1]
     psi = O.fock_state(L, d, occ)
-    pool = W.pool(L, "all", False, W.BH_TYPES)
+    pool = W.pool(L, "all", False, W.BH_TYPES + ("CK",))
     g = O.pool_gradients(h, psi, pool)
     for k, (t, i, j) in enumerate(pool):
         if t == "HR" and j == i + 1:
@@ -255,7 +275,7 @@ def test_pool_gradient_equals_commutator_and_fd():
     h = O.Ham(L, d, True, J=1.0, U=0.8, Delta=0.4, K=0.1, mu=0.2)
     psi = rand_c(d**L, 3)
     psi /= np.linalg.norm(psi)
-    pool = W.pool(L, "all", True, ("HR", "HI", "DH", "PR", "PI")) + [("KERR", 1, -1), ("ROT", 2, -1)]
+    pool = W.pool(L, "all", True, ("HR", "HI", "DH", "PR", "PI", "CK")) + [("KERR", 1, -1), ("ROT", 2, -1)]
     g = O.pool_gradients(h, psi, pool)
     assert np.allclose(g, O.commutator_gradients(h, psi, pool), atol=1e-12)
     for k, op in enumerate(pool):
@@ -280,7 +300,8 @@ def test_real_state_imaginary_generators_vanish():
 def test_adjoint_matches_finite_differences():
     L, d = 3, 4
     h = O.Ham(L, d, False, J=1.0, Delta=0.5, K=0.2)
-    pool = W.pool(L, "nn", False, W.KITAEV_TYPES) + [("KERR", 0, -1), ("ROT", 2, -1), ("DH", 0, 2)]
+    pool = W.pool(L, "nn", False, W.KITAEV_TYPES) + [("KERR", 0, -1), ("ROT", 2, -1), ("DH", 0, 2), ("CK", 0, 2),
+                                                     ("CK", 1, 2)]
     ops, th = W.random_circuit(pool, 9, 4)
     psi0 = O.fock_state(L, d, [0] * L)
     E, g, n2 = O.energy_and_grad_adjoint(h, psi0, ops, th)

@@ -11,8 +11,8 @@ from __future__ import annotations
 import numpy as np
 
 # Generator type codes (same order on every side of the boundary).
-HR, HI, DH, PR, PI, KERR, ROT = range(7)
-TYPE_NAMES = ("HR", "HI", "DH", "PR", "PI", "KERR", "ROT")
+HR, HI, DH, PR, PI, KERR, ROT, CK = range(8)
+TYPE_NAMES = ("HR", "HI", "DH", "PR", "PI", "KERR", "ROT", "CK")
 
 
 def pairs(L: int, kind: str, periodic: bool) -> list[tuple[int, int]]:
@@ -43,6 +43,11 @@ def pool(L: int, kind: str, periodic: bool, types) -> list[tuple[str, int, int]]
 
 
 BH_TYPES = ("HR", "HI", "DH")
+
+
+def site_ops(L: int, types) -> list[tuple[str, int, int]]:
+    """Single-mode pool entries (j = -1): every site x types, sites in order."""
+    return [(t, r, -1) for r in range(L) for t in types]
 KITAEV_TYPES = ("HR", "HI", "PI", "PR")
 
 
