@@ -64,8 +64,8 @@ class Ham:
     K: float = 0.0
 
 
-GEN_TYPES = ("HR", "HI", "DH", "PR", "PI", "KERR", "ROT", "CK")
-SINGLE_MODE = ("KERR", "ROT")
+GEN_TYPES = ("HR", "HI", "DH", "PR", "PI", "KERR", "ROT", "CK", "SR", "SI")
+SINGLE_MODE = ("KERR", "ROT", "SR", "SI")
 
 
 def bonds(L: int, periodic: bool) -> list[tuple[int, int]]:
@@ -256,7 +256,10 @@ def generator_local(gtype: str, d: int) -> np.ndarray:
       PR = a_i a_j - a_i^+ a_j^+          (two-mode squeezer, phi = 0)
       PI = i (a_i a_j + a_i^+ a_j^+)      (two-mode squeezer, phi = pi/2)
       CK = i N_i N_j                      (cross-Kerr, Sec. II.B)
-    Single-mode: KERR = i N^2, ROT = i N.
+    Single-mode: KERR = i N^2, ROT = i N, and the squeezer's generator
+    (theta/2)(e^{-i phi} a^2 - e^{i phi} a^+2) / theta at two phases:
+      SR = (a^2 - a^+2) / 2               (phi = 0)
+      SI = i (a^2 + a^+2) / 2             (phi = -pi/2)
     """
     a = ladder(d)
     ad = a.T
@@ -273,6 +276,10 @@ def generator_local(gtype: str, d: int) -> np.ndarray:
         return 1j * (np.kron(a, a) + np.kron(ad, ad))
     if gtype == "CK":
         return 1j * np.kron(N, N)
+    if gtype == "SR":
+        return 0.5 * (a @ a - ad @ ad)
+    if gtype == "SI":
+        return 0.5j * (a @ a + ad @ ad)
     if gtype == "KERR":
         return 1j * (N @ N)
     if gtype == "ROT":

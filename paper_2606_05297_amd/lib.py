@@ -14,7 +14,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libfock.so")
 
-TYPES = {"HR": 0, "HI": 1, "DH": 2, "PR": 3, "PI": 4, "KERR": 5, "ROT": 6, "CK": 7}
+TYPES = {"HR": 0, "HI": 1, "DH": 2, "PR": 3, "PI": 4, "KERR": 5, "ROT": 6, "CK": 7, "SR": 8, "SI": 9}
 TYPE_NAMES = {v: k for k, v in TYPES.items()}
 
 FOCK_OK = 0

@@ -204,6 +204,20 @@ def test_cross_kerr_closed_forms():
         assert np.abs(out - want).max() < 1e-13
 
 
+@pytest.mark.parametrize("g,phase", [("SR", 1.0), ("SI", 1j)])
+def test_single_mode_squeezed_vacuum(g, phase):
+    """exp(theta A)|0> with A = (e^{-i phi} a^2 - e^{i phi} a^+2)/2 is the squeezed
+    vacuum sum_n (-e^{i phi} tanh theta)^n sqrt((2n)!)/(2^n n!) / sqrt(cosh theta) |2n>
+    as d grows; SR has phi = 0, SI phi = -pi/2 (so -e^{i phi} = i)."""
+    L, d, th = 1, 48, 0.3
+    psi = O.apply_gate((g, 0, -1), th, O.fock_state(L, d, [0]), L, d)
+    want = np.zeros(d, dtype=complex)
+    for n in range(d // 2):
+        want[2 * n] = ((-1.0 if g == "SR" else phase) * math.tanh(th)) ** n * \
+            math.sqrt(math.factorial(2 * n)) / (2**n * math.factorial(n)) / math.sqrt(math.cosh(th))
+    assert np.abs(psi - want).max() < 1e-10
+
+
 def test_beam_splitter_binomial_closed_form():
     """exp(theta HR)|n, 0> = sum_k sqrt(C(n,k)) cos^(n-k) (-sin)^k |n-k, k> (exact for n <= d-1)."""
     L, d, th = 2, 6, 0.41
@@ -228,7 +242,8 @@ def test_two_mode_squeezed_vacuum():
 @pytest.mark.parametrize("g,sector", [("HR", ("N", 3)), ("HI", ("N", 3)), ("DH", ("N", 3)),
                                       ("PR", ("parity", 0)), ("PI", ("parity", 0)),
                                       ("KERR", ("N", 3)), ("ROT", ("parity", 1)),
-                                      ("CK", ("N", 3)), ("CK", ("parity", 1))])
+                                      ("CK", ("N", 3)), ("CK", ("parity", 1)),
+                                      ("SR", ("parity", 0)), ("SI", ("parity", 1))])
 def test_gates_preserve_sector(g, sector):
     L, d = 3, 4
     psi = W.random_state(L, d, 7, sector=sector, dtype=np.complex128)
@@ -263,7 +278,7 @@ def test_pool_gradient_kitaev_vacuum():
     """Vacuum: only the two-mode squeezer PR on bonds has a gradient, -2 Delta."""
     L, d, Dl = 4, 4, 0.35
     h = O.Ham(L, d, False, J=1.0, Delta=Dl, K=0.2)
-    pool = W.pool(L, "all", False, W.KITAEV_TYPES)
+    pool = W.pool(L, "all", False, W.KITAEV_TYPES) + W.site_ops(L, ("SR", "SI", "KERR"))
     g = O.pool_gradients(h, O.fock_state(L, d, [0] * L), pool)
     for k, (t, i, j) in enumerate(pool):
         want = -2 * Dl if (t == "PR" and j == i + 1) else 0.0
@@ -275,7 +290,8 @@ def test_pool_gradient_equals_commutator_and_fd():
     h = O.Ham(L, d, True, J=1.0, U=0.8, Delta=0.4, K=0.1, mu=0.2)
     psi = rand_c(d**L, 3)
     psi /= np.linalg.norm(psi)
-    pool = W.pool(L, "all", True, ("HR", "HI", "DH", "PR", "PI", "CK")) + [("KERR", 1, -1), ("ROT", 2, -1)]
+    pool = W.pool(L, "all", True, ("HR", "HI", "DH", "PR", "PI", "CK")) + [("KERR", 1, -1), ("ROT", 2, -1),
+                                                                          ("SR", 0, -1), ("SI", 2, -1)]
     g = O.pool_gradients(h, psi, pool)
     assert np.allclose(g, O.commutator_gradients(h, psi, pool), atol=1e-12)
     for k, op in enumerate(pool):
@@ -301,7 +317,7 @@ def test_adjoint_matches_finite_differences():
     L, d = 3, 4
     h = O.Ham(L, d, False, J=1.0, Delta=0.5, K=0.2)
     pool = W.pool(L, "nn", False, W.KITAEV_TYPES) + [("KERR", 0, -1), ("ROT", 2, -1), ("DH", 0, 2), ("CK", 0, 2),
-                                                     ("CK", 1, 2)]
+                                                     ("CK", 1, 2), ("SR", 1, -1), ("SI", 0, -1)]
     ops, th = W.random_circuit(pool, 9, 4)
     psi0 = O.fock_state(L, d, [0] * L)
     E, g, n2 = O.energy_and_grad_adjoint(h, psi0, ops, th)

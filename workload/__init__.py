@@ -11,8 +11,8 @@ from __future__ import annotations
 import numpy as np
 
 # Generator type codes (same order on every side of the boundary).
-HR, HI, DH, PR, PI, KERR, ROT, CK = range(8)
-TYPE_NAMES = ("HR", "HI", "DH", "PR", "PI", "KERR", "ROT", "CK")
+HR, HI, DH, PR, PI, KERR, ROT, CK, SR, SI = range(10)
+TYPE_NAMES = ("HR", "HI", "DH", "PR", "PI", "KERR", "ROT", "CK", "SR", "SI")
 
 
 def pairs(L: int, kind: str, periodic: bool) -> list[tuple[int, int]]:
