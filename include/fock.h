@@ -72,8 +72,15 @@ typedef struct {
  *   FOCK_KERR i N_i^2   (single mode, j = -1)    (Kerr gate)
  *   FOCK_ROT  i N_i     (single mode, j = -1)    (phase rotation)
  *   FOCK_CK   i N_i N_j                          (cross-Kerr gate)
- * Two-mode ops need 0 <= i < j < L. */
-enum { FOCK_HR = 0, FOCK_HI = 1, FOCK_DH = 2, FOCK_PR = 3, FOCK_PI = 4, FOCK_KERR = 5, FOCK_ROT = 6, FOCK_CK = 7 };
+ *   FOCK_SR   (a_i^2 - a_i^+2) / 2   (single mode, j = -1)  (squeezer, phi = 0)
+ *   FOCK_SI   i (a_i^2 + a_i^+2) / 2 (single mode, j = -1)  (squeezer, phi = -pi/2)
+ * Two-mode ops need 0 <= i < j < L.  The batched sweep (fock_sweep_*) and
+ * fused gate runs do not take SR / SI (FOCK_ERR_UNSUPPORTED, resp. the
+ * per-gate kernels run). */
+enum {
+  FOCK_HR = 0, FOCK_HI = 1, FOCK_DH = 2, FOCK_PR = 3, FOCK_PI = 4, FOCK_KERR = 5, FOCK_ROT = 6, FOCK_CK = 7,
+  FOCK_SR = 8, FOCK_SI = 9
+};
 
 typedef struct {
   int32_t type, i, j;
@@ -100,8 +107,8 @@ int fock_apply_H(const fock_ham_t *ham, const void *psi, void *hpsi, double *E, 
 /* psi <- exp(theta A_op) psi in place (or its adjoint exp(-theta A_op) when
  * adjoint != 0), Sec. II.B.  The gate is exp of the truncated generator, hence
  * exactly unitary; its conserved blocks (n_i + n_j for HR/HI/DH/CK, n_i - n_j
- * for PR/PI, single levels for KERR/ROT) keep boson number or parity leakage
- * at 0. */
+ * for PR/PI, single levels for KERR/ROT, the parity of n_i for SR/SI) keep
+ * boson number or parity leakage at 0. */
 int fock_apply_gate2(int L, int d, fock_op_t op, double theta, int adjoint, void *psi,
                      void *ws, size_t ws_bytes, fock_stream_t stream);
 

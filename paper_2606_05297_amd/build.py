@@ -37,6 +37,7 @@ SOURCES = [
     "adapt.cpp",
     "bfgs.cpp",
     "fuse_kernels.hip",
+    "gate1_kernels.hip",
     "dense_gate.hip",
     "mlp_kernels.hip",
     "mlp.cpp",

@@ -38,7 +38,7 @@ int check_ham(const fock_ham_t *h, uint32_t *namp) {
 }
 
 int check_op(const fock_op_t &op, int L) {
-  if (op.type < FOCK_HR || op.type > FOCK_CK) return set_error(FOCK_ERR_ARG, "unknown op type %d", op.type);
+  if (op.type < FOCK_HR || op.type > FOCK_SI) return set_error(FOCK_ERR_ARG, "unknown op type %d", op.type);
   if (is_single_mode(op.type)) {
     if (op.i < 0 || op.i >= L) return set_error(FOCK_ERR_ARG, "mode %d out of range for L=%d", op.i, L);
     return FOCK_OK;
@@ -148,6 +148,7 @@ int make_ctx(const fock_ham_t &ham, uint32_t namp, int P, int n, void *ws, size_
                     Ctx *c) {
   c->g = {ham.L, ham.d, namp};
   c->h = make_ham_args(ham);
+  memset(&c->T, 0, sizeof(c->T));  // eigendata loaded below when the call applies gates
   {
     int rc = stencil_order_table(ham.L, ham.d, apply_h_blocks(c->h), &c->h.order);
     if (rc) return rc;
@@ -207,6 +208,7 @@ int forward_gate(Ctx &c, const fock_op_t &op, int k, bool dag, const float2 *src
                              c.s);
   }
   ProfScope ps(is_single_mode(op.type) ? FOCK_K_DIAG : FOCK_K_GATE, c.s, 16.0 * c.g.n_amp);
+  if (is_squeeze(op.type)) return launch_gate1(c.g, op.i, dag, U, src, psi, c.s);
   if (is_single_mode(op.type)) return launch_diag(c.g, op.i, op.type, dag, U, src, psi, c.s);
   return launch_gate(c.g, op.i, op.j, gate_kind(op.type), dag, U, src, psi, c.s);
 }
@@ -262,7 +264,8 @@ static void plan_gate_groups(const Ctx &c, const fock_op_t *ops, int n, std::vec
       auto modes = [&](const fock_op_t &o) { return is_single_mode(o.type) ? (1u << o.i) : ((1u << o.i) | (1u << o.j)); };
       mask |= modes(ops[k]);
       int k1 = k + 1;
-      while (k1 < n && k1 - k < kMaxFuseGates) {
+      // squeezer gates are not fused: they run alone on the per-gate kernels
+      while (!is_squeeze(ops[k].type) && k1 < n && k1 - k < kMaxFuseGates && !is_squeeze(ops[k1].type)) {
         const unsigned nm = mask | modes(ops[k1]);
         if (__builtin_popcount(nm) > smax) break;
         mask = nm;
@@ -379,7 +382,9 @@ int run_circuit(Ctx &c, const fock_op_t *ops, const double *theta, int n, const 
       const float2 *U = U0 + (size_t)k * stride;
       double *pk = part + (size_t)k * c.L.rs;
       ProfScope ps(is_single_mode(op.type) ? FOCK_K_DIAG : FOCK_K_ADJ, c.s, 32.0 * c.g.n_amp);
-      if (is_single_mode(op.type)) rc = launch_diag_adj(c.g, op.i, op.type, U, phi, lam, pk, c.s);
+      if (is_squeeze(op.type))
+        rc = launch_gate1_adj(c.g, op.i, U, c.T.A1[op.type == FOCK_SR ? 0 : 1], phi, lam, pk, c.s);
+      else if (is_single_mode(op.type)) rc = launch_diag_adj(c.g, op.i, op.type, U, phi, lam, pk, c.s);
       else rc = launch_gate_adj(c.g, op.i, op.j, gate_kind(op.type), U, c.T.A[table_slot(op.type)], phi, lam, pk,
                                 c.s);
       if (rc) return rc;
@@ -413,16 +418,27 @@ int pool_dev(Ctx &c, const fock_op_t *pool, int P, const float2 *psi, const floa
   for (int k = 0; k <= kMaxD; ++k) a.sq[k] = c.h.sq[k];
   a.order = c.h.order;  // same tiles as the Hamiltonian stencil
   double *part = (double *)(c.ws + c.L.partial);
+  for (int k = 0; k < P; ++k)
+    if (is_squeeze(pool[k].type) && c.T.d != c.g.d) {  // squeezer scoring reads the generator table
+      int rc = get_tables(c.g.d, &c.T);
+      if (rc) return rc;
+      break;
+    }
   int k0 = 0;
   while (k0 < P) {
     // chunk: up to kMaxSlots entries, kMaxPairs pairs, kMaxDiagOps single-mode ops
     std::vector<PoolPair> pairs;
     std::vector<PoolDiag> diags;
     std::map<std::pair<int, int>, int> pidx;
+    std::vector<int> sq;  // squeezer entries: scored by their own pass after the chunk
     int k1 = k0;
     for (; k1 < P && k1 - k0 < kMaxSlots; ++k1) {
       const fock_op_t &op = pool[k1];
       const int slot = k1 - k0;
+      if (is_squeeze(op.type)) {
+        sq.push_back(k1);
+        continue;
+      }
       if (is_pool_diagonal(op.type)) {
         if ((int)diags.size() >= kMaxDiagOps) break;
         diags.push_back({(int16_t)op.i, (int16_t)op.type, (int16_t)slot, (int16_t)(op.type == FOCK_CK ? op.j : -1)});
@@ -461,15 +477,28 @@ int pool_dev(Ctx &c, const fock_op_t *pool, int P, const float2 *psi, const floa
                             hipMemcpyHostToDevice, c.s));
     rc = tl_in.mark(c.s);
     if (rc) return rc;
-    int G = 0;
-    {
-      ProfScope ps(FOCK_K_POOL, c.s, 16.0 * c.g.n_amp);
-      rc = launch_pool(a, (const PoolPair *)(c.ws + c.L.pairs), (const PoolDiag *)(c.ws + c.L.diags), psi, hpsi,
-                       part, &G, c.s);
+    if (!pairs.empty() || !diags.empty()) {  // a chunk of squeezer entries only needs no stencil pass
+      int G = 0;
+      {
+        ProfScope ps(FOCK_K_POOL, c.s, 16.0 * c.g.n_amp);
+        rc = launch_pool(a, (const PoolPair *)(c.ws + c.L.pairs), (const PoolDiag *)(c.ws + c.L.diags), psi, hpsi,
+                         part, &G, c.s);
+        if (rc) return rc;
+      }
+      rc = launch_reduce(part, G, a.nslots, res + k0, c.s);
       if (rc) return rc;
     }
-    rc = launch_reduce(part, G, a.nslots, res + k0, c.s);
-    if (rc) return rc;
+    for (int k : sq) {  // stream order: after the chunk's reduction has read the partials
+      const fock_op_t &op = pool[k];
+      int G1 = 0;
+      {
+        ProfScope ps(FOCK_K_POOL, c.s, 16.0 * c.g.n_amp);
+        rc = launch_pool1(c.g, op.i, c.T.A1[op.type == FOCK_SR ? 0 : 1], psi, hpsi, part, &G1, c.s);
+        if (rc) return rc;
+      }
+      rc = launch_reduce(part, G1, 1, res + k, c.s);
+      if (rc) return rc;
+    }
     k0 = k1;
   }
   return FOCK_OK;

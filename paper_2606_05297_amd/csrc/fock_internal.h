@@ -100,6 +100,11 @@ struct EigTables {
   const double *V[kTwoModeTypes];
   const double *lam[kTwoModeTypes];
   const float2 *A[kTwoModeTypes];
+  // single-mode squeezers SR (0), SI (1): d x d eigenvectors of G = -i A, its
+  // eigenvalues, and A itself (dense d x d, row-major)
+  const double *V1[2];
+  const double *lam1[2];
+  const float2 *A1[2];
   int d, psize;
 };
 
@@ -135,6 +140,8 @@ bool is_single_mode(int type);
 // Generators diagonal in the Fock basis (KERR, ROT, CK): pool scoring takes
 // them as -2 f(n) Im(conj(H psi) psi) terms instead of pair terms.
 bool is_pool_diagonal(int type);
+// Single-mode squeezers (SR, SI): dense d x d gate on each fibre of one mode.
+bool is_squeeze(int type);
 // Library-owned device eigendata for cutoff d (built on first use, per device).
 int get_tables(int d, EigTables *out);
 // Size of one gate's slot in a U buffer (complex entries).
@@ -168,6 +175,15 @@ int launch_diag(const Geometry &g, int r, int type, bool dag, const float2 *ph, 
 int launch_diag_adj(const Geometry &g, int r, int type, const float2 *ph, float2 *phi, float2 *lam,
                     double *partial, hipStream_t s);
 int diag_blocks_count(const Geometry &g);
+// Squeezer gates (gate1_kernels.hip): U, A are d x d row-major; the reverse
+// step and the pool scoring write one partial per workgroup
+// (diag_blocks_count(g) of them).
+int launch_gate1(const Geometry &g, int r, bool dag, const float2 *U, const float2 *src, float2 *psi,
+                 hipStream_t s);
+int launch_gate1_adj(const Geometry &g, int r, const float2 *U, const float2 *A, float2 *phi, float2 *lam,
+                     double *partial, hipStream_t s);
+int launch_pool1(const Geometry &g, int r, const float2 *A, const float2 *psi, const float2 *hpsi, double *partial,
+                 int *nblocks, hipStream_t s);
 // out[c] = sum_b partial[b * ncols + c] for c < ncols, in a fixed order.
 int launch_reduce(const double *partial, int nblocks, int ncols, double *out, hipStream_t s);
 // out[k] = sum_{b < recs[k].nblk} partial[k * row_stride + b] for k < n, in a fixed order.

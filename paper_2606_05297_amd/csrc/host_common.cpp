@@ -44,7 +44,8 @@ FastDiv make_fastdiv(uint32_t v) {
 // ---------------------------------------------------------------- local generators
 using cd = std::complex<double>;
 
-bool is_single_mode(int type) { return type == FOCK_KERR || type == FOCK_ROT; }
+bool is_single_mode(int type) { return type == FOCK_KERR || type == FOCK_ROT || type == FOCK_SR || type == FOCK_SI; }
+bool is_squeeze(int type) { return type == FOCK_SR || type == FOCK_SI; }
 bool is_pool_diagonal(int type) { return type == FOCK_KERR || type == FOCK_ROT || type == FOCK_CK; }
 int gate_kind(int type) { return (type == FOCK_PR || type == FOCK_PI) ? KIND_DIFF : KIND_SUM; }
 
@@ -53,6 +54,21 @@ static double lad(int d, int row, int col) { return (col >= 1 && row == col - 1)
 static double cre(int d, int row, int col) { return lad(d, col, row); }
 
 void generator_dense(int type, int d, std::vector<double> &m) {
+  if (is_squeeze(type)) {
+    // SR = (a^2 - a^+2) / 2, SI = i (a^2 + a^+2) / 2; a^2 |n> = sqrt(n (n-1)) |n-2>
+    m.assign(2 * d * d, 0.0);
+    for (int n = 2; n < d; ++n) {
+      const double c = 0.5 * std::sqrt((double)n * (double)(n - 1));
+      if (type == FOCK_SR) {
+        m[2 * ((n - 2) * d + n)] = c;   // a^2: row n-2, column n
+        m[2 * (n * d + (n - 2))] = -c;  // -a^+2: row n, column n-2
+      } else {
+        m[2 * ((n - 2) * d + n) + 1] = c;
+        m[2 * (n * d + (n - 2)) + 1] = c;
+      }
+    }
+    return;
+  }
   if (is_single_mode(type)) {
     m.assign(2 * d * d, 0.0);
     for (int n = 0; n < d; ++n) m[2 * (n * d + n) + 1] = type == FOCK_KERR ? (double)n * n : (double)n;
@@ -203,7 +219,39 @@ static int build_tables(int d, TableSet *ts) {
       if (!covered[e]) leak += std::fabs(A[2 * e]) + std::fabs(A[2 * e + 1]);
     if (leak != 0.0) return set_error(FOCK_ERR_HIP, "generator type %d has entries outside its blocks", type);
   }
-  const size_t bytesD = (nV + nL) * sizeof(double), bytesA = nA * sizeof(float);
+  // single-mode squeezers: dense d x d eigendata of G = -i A, appended as
+  // [V1: 2 * d*d complex double][lam1: 2 * d double] and [A1: 2 * d*d float2]
+  const size_t nV1 = (size_t)2 * D2 * 2, nL1 = (size_t)2 * d, nA1 = (size_t)2 * D2 * 2;
+  hv.resize(nV + nL + nV1 + nL1, 0.0);
+  ha.resize(nA + nA1, 0.f);
+  for (int t = 0; t < 2; ++t) {
+    const int type = t == 0 ? FOCK_SR : FOCK_SI;
+    std::vector<double> A;
+    generator_dense(type, d, A);
+    std::vector<cd> G(D2);
+    for (int e = 0; e < D2; ++e) {
+      G[e] = cd(0.0, -1.0) * cd(A[2 * e], A[2 * e + 1]);  // Hermitian
+      ha[nA + (size_t)t * D2 * 2 + 2 * e] = (float)A[2 * e];
+      ha[nA + (size_t)t * D2 * 2 + 2 * e + 1] = (float)A[2 * e + 1];
+    }
+    std::vector<double> w;
+    std::vector<cd> V;
+    herm_jacobi(d, G, w, V);
+    double res = 0.0;
+    for (int p = 0; p < d; ++p)
+      for (int q = 0; q < d; ++q) {
+        cd acc = 0.0;
+        for (int m = 0; m < d; ++m) acc += V[p * d + m] * w[m] * std::conj(V[q * d + m]);
+        res = std::max(res, std::abs(acc - G[p * d + q]));
+      }
+    if (res > 1e-11) return set_error(FOCK_ERR_HIP, "squeezer eigendata residual %.3g (type %d, d %d)", res, type, d);
+    for (int e = 0; e < D2; ++e) {
+      hv[nV + nL + (size_t)t * D2 * 2 + 2 * e] = V[e].real();
+      hv[nV + nL + (size_t)t * D2 * 2 + 2 * e + 1] = V[e].imag();
+    }
+    for (int m = 0; m < d; ++m) hv[nV + nL + nV1 + (size_t)t * d + m] = w[m];
+  }
+  const size_t bytesD = (nV + nL + nV1 + nL1) * sizeof(double), bytesA = (nA + nA1) * sizeof(float);
   void *dev = nullptr;
   FOCK_HIP(hipMalloc(&dev, bytesD + bytesA));
   FOCK_HIP(hipMemcpy(dev, hv.data(), bytesD, hipMemcpyHostToDevice));
@@ -216,6 +264,11 @@ static int build_tables(int d, TableSet *ts) {
     ts->T.V[t] = dV + (size_t)t * ps * 2;
     ts->T.lam[t] = dL + (size_t)t * D2;
     ts->T.A[t] = dA + (size_t)t * ps;
+  }
+  for (int t = 0; t < 2; ++t) {
+    ts->T.V1[t] = dV + nV + nL + (size_t)t * D2 * 2;
+    ts->T.lam1[t] = dV + nV + nL + nV1 + (size_t)t * d;
+    ts->T.A1[t] = dA + (nA / 2) + (size_t)t * D2;
   }
   ts->T.d = d;
   ts->T.psize = ps;

@@ -41,6 +41,26 @@ __global__ __launch_bounds__(kBlock) void k_gate_build(const double *__restrict_
     }
     return;
   }
+  if (r.type == FOCK_SR || r.type == FOCK_SI) {
+    // dense d x d: U[p][q] = sum_m V[p][m] e^{i th lam_m} conj(V[q][m])
+    if (e >= d * d) return;
+    const int t = r.type == FOCK_SR ? 0 : 1;
+    const int p = e / d, q = e % d;
+    const double *V = T.V1[t];
+    const double *lam = T.lam1[t];
+    double ur = 0.0, ui = 0.0;
+    for (int m = 0; m < d; ++m) {
+      double sn, cs;
+      sincos(th * lam[m], &sn, &cs);
+      const double pr = V[2 * (p * d + m)], pi = V[2 * (p * d + m) + 1];
+      const double qr = V[2 * (q * d + m)], qi = V[2 * (q * d + m) + 1];
+      const double tr = pr * cs - pi * sn, ti = pr * sn + pi * cs;
+      ur += tr * qr + ti * qi;
+      ui += ti * qr - tr * qi;
+    }
+    utab[r.u_off + e] = make_float2((float)ur, (float)ui);
+    return;
+  }
   if (e >= T.psize) return;
   int off = 0, loff = 0, b = 1;
   for (int s = 0; s <= 2 * d - 2; ++s) {

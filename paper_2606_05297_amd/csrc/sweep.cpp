@@ -546,12 +546,19 @@ int fock_sweep_create(const fock_sweep_point_t *pts, int npts, const fock_adapt_
     if (!pts[p].pool || pts[p].P < 1 || pts[p].P > kMaxSlots)
       return set_error(FOCK_ERR_ARG, "point %d: pool must hold 1..%d ops", p, kMaxSlots);
     if ((rc = check_ptr(pts[p].psi0, "psi0"))) return rc;
-    for (int k = 0; k < pts[p].P; ++k)
+    for (int k = 0; k < pts[p].P; ++k) {
       if ((rc = check_op(pts[p].pool[k], pts[p].ham.L))) return rc;
+      if (is_squeeze(pts[p].pool[k].type))
+        return set_error(FOCK_ERR_UNSUPPORTED, "point %d: the sweep kernels do not take squeezer ops (pool %d)", p, k);
+    }
     if (pts[p].n_warm < 0 || (pts[p].n_warm > 0 && (!pts[p].warm_ops || !pts[p].warm_theta0)))
       return set_error(FOCK_ERR_ARG, "point %d: warm-up arrays missing", p);
-    for (int k = 0; k < pts[p].n_warm; ++k)
+    for (int k = 0; k < pts[p].n_warm; ++k) {
       if ((rc = check_op(pts[p].warm_ops[k], pts[p].ham.L))) return rc;
+      if (is_squeeze(pts[p].warm_ops[k].type))
+        return set_error(FOCK_ERR_UNSUPPORTED, "point %d: the sweep kernels do not take squeezer ops (warm-up %d)", p,
+                         k);
+    }
   }
   // the caller's psi0 buffers must be ready before the private stream reads them
   if (hipStreamSynchronize((hipStream_t)stream) != hipSuccess) return set_error(FOCK_ERR_HIP, "caller stream error");

@@ -61,9 +61,10 @@ def test_argument_validation_before_device_work():
     # out-of-range mode
     rc = L.fock_apply_gate2(3, 4, lib.op("PR", 0, 3), 0.1, 0, big, big, 1 << 20, None)
     assert rc == -1
-    # unknown type
-    rc = L.fock_apply_gate2(3, 4, lib.Op(9, 0, 1), 0.1, 0, big, big, 1 << 20, None)
-    assert rc == -1 and "unknown" in lib.last_error()
+    # unknown types (the last known one is FOCK_SI = 9)
+    for t in (10, 99, -1):
+        rc = L.fock_apply_gate2(3, 4, lib.Op(t, 0, 1), 0.1, 0, big, big, 1 << 20, None)
+        assert rc == -1 and "unknown" in lib.last_error()
     # non-finite theta
     rc = L.fock_apply_gate2(3, 4, lib.op("HR", 0, 1), float("nan"), 0, big, big, 1 << 20, None)
     assert rc == -4

@@ -93,6 +93,26 @@ def test_adapt_bose_hubbard_cross_kerr_pool_replay():
     say("selected types", sorted(types))
 
 
+def test_adapt_kitaev_squeezer_pool_replay():
+    """Kitaev-Kerr L=4 d=6 from a one-boson-per-site state with the paper's
+    parity-preserving pool (beam splitters, two-mode squeezers, cross-Kerr,
+    single-mode squeezers and Kerr on every site): every step replayed by the
+    oracle, including the squeezers' pool gradients."""
+    L, d = 4, 6
+    ho, hl = O.Ham(L, d, False, J=1.0, Delta=0.5, K=0.2), lib.ham(L, d, False, 1.0, 0.0, 0.0, 0.5, 0.2)
+    pool = W.pool(L, "nn", False, W.KITAEV_TYPES + ("CK",)) + W.site_ops(L, ("SR", "SI", "KERR"))
+    psi0 = O.fock_state(L, d, [1] * L)
+    say("adapt kk L4 d6 squeezer pool")
+    ad = lib.Adapt(hl, pool, dev(psi0), max_iters=8)
+    ops, th = [], np.zeros(0)
+    for _ in range(8):
+        rep = ad.step()
+        ops, th = replay_check(ad, ho, psi0, ops, th, rep, pool)
+        if rep["converged"] or rep["capped"]:
+            break
+    ad.close()
+
+
 def test_adapt_kitaev_small_replay_and_modes():
     L, d = 4, 5
     c = dict(L=L, d=d, periodic=False, J=1.0, U=0.0, mu=0.0, Delta=0.5, K=0.2)

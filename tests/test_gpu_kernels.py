@@ -148,6 +148,46 @@ def test_apply_H_lane_split_parity(case):
         lib.set_stencil_variant(prev)
 
 
+SQ_CASES = [
+    # (L, d, J, U, mu, Delta, K): open chains, squeezers on every site
+    (5, 6, 1.0, 0.0, 0.1, 0.5, 0.2),
+    (4, 8, 0.8, 0.5, 0.0, 0.4, 0.1),
+    (5, 7, 1.0, 0.0, 0.0, 0.5, 0.25),   # ragged: 2401 fibres per mode
+]
+
+
+@pytest.mark.parametrize("case", SQ_CASES, ids=lambda c: f"L{c[0]}d{c[1]}")
+def test_squeezer_energy_adjoint_and_pool_parity(case):
+    """Circuits and pools with the single-mode squeezers SR, SI (with the
+    Kitaev generators, CK and K): energy, adjoint gradient and pool gradients
+    against the oracle; a chunk of squeezer entries alone is scored too."""
+    L, d, J, U, mu, Dl, K = case
+    say("squeezers", case)
+    ho, hl = ham_pair(L, d, False, J, U, mu, Dl, K)
+    pool = W.pool(L, "nn", False, W.KITAEV_TYPES + ("CK",)) + W.site_ops(L, ("SR", "SI", "KERR"))
+    ops, th = W.random_circuit(pool, 12, seed=L * 7 + d)
+    ops = ops[:10] + [("SR", 0, -1), ("SI", L - 1, -1)]
+    th = np.concatenate([th[:10], [0.31, -0.27]])
+    psi0 = W.random_state(L, d, seed=3, sector=("parity", 0))
+    x0 = dev(psi0)
+    a, b = torch.empty_like(x0), torch.empty_like(x0)
+    ws = lib.workspace(hl, len(pool), len(ops))
+    E, _, g = lib.energy_grad_adjoint(hl, ops, th, x0, a, b, ws)
+    Eo, go, _ = O.energy_and_grad_adjoint(ho, psi0.astype(np.complex128), ops, th)
+    assert abs(E - Eo) <= 1e-5 * max(1.0, abs(Eo))
+    assert np.abs(g - go).max() <= 1e-4 * max(1.0, np.abs(go).max())
+    psi = W.random_state(L, d, seed=9)
+    x, y = dev(psi), torch.empty(d**L, dtype=torch.complex64, device="cuda")
+    lib.apply_H(hl, x, y, ws)
+    gp = lib.pool_grads(hl, pool, x, y, ws)
+    ref = O.pool_gradients(ho, psi.astype(np.complex128), pool)
+    assert np.abs(gp - ref).max() <= 1e-4 * max(1.0, np.abs(ref).max())
+    only = W.site_ops(L, ("SI", "SR"))
+    gs = lib.pool_grads(hl, only, x, y, ws)
+    refs = O.pool_gradients(ho, psi.astype(np.complex128), only)
+    assert np.abs(gs - refs).max() <= 1e-4 * max(1.0, np.abs(refs).max())
+
+
 POOL_CASES = [
     (3, 4, False, 1.0, 2.0, 0.0, 0.0, 0.0, "all", ("HR", "HI", "DH", "PR", "PI")),
     (4, 5, True, 1.0, 0.7, 0.2, 0.5, 0.2, "nn+nnn", ("HR", "HI", "DH", "PR", "PI")),
@@ -192,7 +232,8 @@ def test_pool_grads_large_pool_chunks():
 
 
 GATE_OPS = [("HR", 0, 1), ("HI", 1, 3), ("DH", 0, 2), ("DH", 2, 3), ("PR", 0, 3), ("PI", 1, 2), ("KERR", 0, -1),
-            ("KERR", 2, -1), ("ROT", 3, -1), ("ROT", 0, -1), ("CK", 0, 2), ("CK", 1, 3)]
+            ("KERR", 2, -1), ("ROT", 3, -1), ("ROT", 0, -1), ("CK", 0, 2), ("CK", 1, 3), ("SR", 0, -1), ("SI", 2, -1),
+            ("SR", 3, -1)]
 
 
 @pytest.mark.parametrize("d", [2, 3, 5, 8, 12, 16])
@@ -209,7 +250,7 @@ def test_gate_parity_and_leakage(opx, d):
         ref = O.apply_gate(opx, 0.37, psi.astype(np.complex128), L, d, adjoint=adj)
         assert np.abs(got - ref).max() <= 1e-5 * np.abs(psi).max()
     # exact zero leakage from a conserved sector
-    sector = ("parity", 0) if opx[0] in ("PR", "PI") else ("N", 3)
+    sector = ("parity", 0) if opx[0] in ("PR", "PI", "SR", "SI") else ("N", 3)
     ps = W.random_state(L, d, seed=5, sector=sector)
     x = dev(ps)
     lib.apply_gate2(L, d, opx, 0.9, x, ws)
@@ -225,7 +266,7 @@ def test_gate_then_adjoint_is_identity_ragged():
     psi = W.random_state(L, d, seed=2)
     x = dev(psi)
     ws = lib.workspace(lib.ham(L, d), 0, 1)
-    for o in [("HR", 1, 4), ("PR", 0, 4), ("DH", 3, 4), ("KERR", 4, -1), ("CK", 0, 3)]:
+    for o in [("HR", 1, 4), ("PR", 0, 4), ("DH", 3, 4), ("KERR", 4, -1), ("CK", 0, 3), ("SR", 2, -1), ("SI", 0, -1)]:
         say("gate roundtrip", o)
         lib.apply_gate2(L, d, o, 1.1, x, ws)
         lib.apply_gate2(L, d, o, 1.1, x, ws, adjoint=True)
@@ -416,7 +457,7 @@ FUSE_CASES = [
     # (L, d, periodic, J, U, mu, Delta, K, ops as (type, i, j))
     (5, 4, True, 1.0, 0.7, 0.1, 0.4, 0.2,
      [("HR", 0, 1), ("PR", 1, 2), ("HI", 2, 3), ("KERR", 2, -1), ("DH", 0, 1), ("PI", 3, 4), ("ROT", 0, -1),
-      ("HR", 0, 4), ("CK", 1, 2), ("PR", 3, 4), ("CK", 0, 1), ("HR", 0, 1)]),
+      ("HR", 0, 4), ("CK", 1, 2), ("SR", 1, -1), ("PR", 3, 4), ("CK", 0, 1), ("HR", 0, 1), ("SI", 0, -1)]),
     (6, 6, True, 1.0, 4.0, 0.0, 0.0, 0.0,
      [("HR", 0, 1), ("HR", 1, 2), ("HR", 2, 3), ("HR", 3, 4), ("HR", 4, 5), ("HR", 0, 5), ("KERR", 5, -1),
       ("ROT", 5, -1), ("DH", 4, 5), ("HI", 1, 2), ("HR", 0, 1)]),

@@ -122,6 +122,16 @@ def test_sweep_with_cross_kerr_and_kerr_pool_entries(unfused):
     sw.close()
 
 
+def test_sweep_rejects_squeezer_ops():
+    """Squeezer generators run on the single-point path only: a sweep point
+    whose pool holds one is refused at creation."""
+    p = dict(W.sweep_points()[48])
+    e = entry(p)
+    e["pool"] = list(e["pool"]) + [("SR", 0, -1)]
+    with pytest.raises(lib.FockError):
+        lib.Sweep([e], max_iters=2)
+
+
 def test_sweep_rejects_unsupported_cutoff():
     p = dict(W.sweep_points()[0])
     e = entry(p)
