@@ -147,7 +147,8 @@ typedef struct {
   double fd_step;         /* finite-difference step for grad_mode 1 */
   int32_t recycle_hessian;/* 1: seed each BFGS with the previous inverse Hessian (Appendix D) */
   int32_t reserved;
-  double noise_rel;       /* BFGS also stops once the predicted decrease < noise_rel*max(1,|E|) (FP32 noise) */
+  double noise_rel;       /* BFGS also stops once the predicted decrease < noise_rel*max(1,|E|) (FP32 noise),
+                             from its second iteration on */
 } fock_adapt_opts_t;
 
 typedef struct {

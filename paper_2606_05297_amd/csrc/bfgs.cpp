@@ -82,7 +82,12 @@ int bfgs_minimize(std::vector<double> &x, const ObjFn &fn, double gtol, int maxi
       dphi0 = dot(g, p);
       scaled = false;
     }
-    if (noise_rel > 0.0 && -0.5 * dphi0 < noise_rel * std::max(1.0, std::fabs(f))) {
+    // Noise floor: stop once the predicted decrease is below the energy's
+    // resolution.  Not before the first line search: until then the inverse
+    // Hessian holds no curvature of the new direction (identity or a padded
+    // recycled matrix) and its prediction g^2 / 2 can be far below the decrease
+    // available along a soft direction.
+    if (noise_rel > 0.0 && it > 0 && -0.5 * dphi0 < noise_rel * std::max(1.0, std::fabs(f))) {
       o.noise_stop = 1;
       break;
     }

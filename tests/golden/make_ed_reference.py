@@ -4,6 +4,7 @@ oracle only (dense eigh for small sectors, Lanczos otherwise).
 
     python tests/golden/make_ed_reference.py [names...]
     python tests/golden/make_ed_reference.py --warmstart-held [--jobs N]
+    python tests/golden/make_ed_reference.py --paper-cases
 
 The second form writes tests/golden/warmstart_held_ed.json: the even-parity
 ground energies of the 64 held-out Kitaev-Kerr L=6 d=8 warm-start points (in
@@ -22,6 +23,21 @@ import workload as W  # noqa: E402
 
 OUT = os.path.join(HERE, "ed_reference.json")
 OUT_HELD = os.path.join(HERE, "warmstart_held_ed.json")
+OUT_PAPER = os.path.join(HERE, "paper_cases_ed.json")
+
+
+def paper_cases():
+    """Ground energies of workload.paper_cases() in their sectors (dense eigh)."""
+    res = {}
+    for p in W.paper_cases():
+        h = O.Ham(p["L"], p["d"], p["periodic"], p["J"], p["U"], p["mu"], p["Delta"], p["K"])
+        t = time.time()
+        gs = O.ground_state(h, p["sector"], want_vector=False, tol=1e-12)
+        res[p["name"]] = dict(E0=gs["E0"], sector=list(p["sector"]), dim=int(gs["dim"]),
+                              method="eigh" if gs["dim"] <= 20000 else "eigsh", seconds=round(time.time() - t, 1))
+        print(p["name"], res[p["name"]], flush=True)
+    with open(OUT_PAPER, "w") as f:
+        json.dump(res, f, indent=1)
 
 
 def held_one(k):
@@ -75,7 +91,9 @@ def main(names):
 
 
 if __name__ == "__main__":
-    if "--warmstart-held" in sys.argv:
+    if "--paper-cases" in sys.argv:
+        paper_cases()
+    elif "--warmstart-held" in sys.argv:
         j = sys.argv.index("--jobs") if "--jobs" in sys.argv else -1
         held(int(sys.argv[j + 1]) if j >= 0 else 4)
     else:

@@ -175,6 +175,37 @@ def warmstart_points(split: str) -> list[dict]:
     return out
 
 
+def paper_cases() -> list[dict]:
+    """The paper's own ADAPT runs (Sec. V), in this library's sign conventions.
+
+    Kitaev chain (BKC): periodic, d = 6, J = 1, Delta = 0.5, mu in {-3.1, -2.7},
+    N_S in {3, 4, 5}, vacuum; pool: beam splitters and two-mode squeezers on all
+    pairs, single-mode squeezers and rotations on every site.
+    BKC + Kerr: the paper's -(U/2) N(N-1) with U = -1 is K = 0.5 here; mu = -2.7,
+    N_S in {3, 4, 5}; the pool adds cross-Kerr on all pairs and Kerr on every site.
+    Bose-Hubbard: periodic, N_S = 4, 12 bosons, d = 13, Lambda = N U / J = +-4
+    in the paper's sign, i.e. U = -Lambda / 12 here; |3,3,3,3> for Lambda < 0
+    and |6,0,6,0> for Lambda > 0; nearest-neighbour beam splitters and cross-Kerr,
+    Kerr and rotations on every site, after the warm-up layer."""
+    out = []
+    gauss = ("HR", "HI", "PR", "PI")
+    for mu in (-3.1, -2.7):
+        for L in (3, 4, 5):
+            out.append(dict(name=f"bkc_N{L}_mu{mu:g}", model="kk", L=L, d=6, periodic=True, J=1.0, U=0.0, mu=mu,
+                            Delta=0.5, K=0.0, occ=[0] * L, sector=("parity", 0), warm=False, warm_seed=0,
+                            pool=pool(L, "all", True, gauss) + site_ops(L, ("SR", "SI", "ROT"))))
+    for L in (3, 4, 5):
+        out.append(dict(name=f"bkck_N{L}_mu-2.7", model="kk", L=L, d=6, periodic=True, J=1.0, U=0.0, mu=-2.7,
+                        Delta=0.5, K=0.5, occ=[0] * L, sector=("parity", 0), warm=False, warm_seed=0,
+                        pool=pool(L, "all", True, gauss + ("CK",)) + site_ops(L, ("SR", "SI", "ROT", "KERR"))))
+    for lam in (4.0, -4.0):
+        occ = [3, 3, 3, 3] if lam < 0 else [6, 0, 6, 0]
+        out.append(dict(name=f"bh_N4_lam{lam:+g}", model="bh", L=4, d=13, periodic=True, J=1.0, U=-lam / 12.0,
+                        mu=0.0, Delta=0.0, K=0.0, occ=occ, sector=("N", 12), warm=True, warm_seed=7,
+                        pool=pool(4, "nn", True, ("HR", "HI", "CK")) + site_ops(4, ("KERR", "ROT"))))
+    return out
+
+
 # ---------------------------------------------------------------- warm-start network inputs
 
 MLP_SHAPES = [((128, 4), 4), ((128,), 4), ((128, 128), 128), ((128,), 128), ((64, 128), 128), ((64,), 128)]
