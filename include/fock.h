@@ -339,6 +339,33 @@ enum { FOCK_STENCIL_ROWS = 0, FOCK_STENCIL_LANES = 1 };
 int fock_set_stencil_variant(int variant);
 int fock_get_stencil_variant(void);
 
+/* ------------------------------------------------------------------ FP64 states */
+
+/* CV-ADAPT-VQE (Sec. IV.B) on complex128 states, for runs that resolve energy
+ * differences far below the complex64 state's ~1e-7 relative rounding (the
+ * paper runs to |E - E0| ~ 1e-10, Sec. V).  Same loop as adapt_step: pool
+ * scoring, tie band, append at theta = 0, BFGS with the L-inf tolerance and
+ * optional Hessian recycling (no noise-floor stop).  Plain kernels (one thread
+ * per amplitude for H psi; one workgroup per group of fibres with a dense
+ * local gate matrix of d^2 x d^2 or d x d), meant for lattices of up to ~1e6
+ * amplitudes.  psi0: device, d^L complex128 (copied); opts: as adapt_create,
+ * except that warm-up layers and finite-difference gradients are refused
+ * (FOCK_ERR_UNSUPPORTED).  The handle owns its buffers and a private stream;
+ * `stream` is synchronised once at creation. */
+typedef struct fock_adapt64 fock_adapt64_t;
+int adapt64_create(const fock_ham_t *ham, const fock_op_t *pool, int P, const void *psi0,
+                   const fock_adapt_opts_t *opts, fock_stream_t stream, fock_adapt64_t **out);
+/* One ADAPT iteration; FOCK_ERR_STATE once converged or capped. */
+int adapt64_step(fock_adapt64_t *st, fock_adapt_report_t *rep);
+/* Current ansatz (see adapt_get_ansatz). */
+int adapt64_get_ansatz(fock_adapt64_t *st, fock_op_t *ops, double *theta, int cap, int *n);
+/* E (Rayleigh quotient) and, if dEdtheta is non-NULL, all dE/dtheta_k of the
+ * ansatz ops/theta (n <= max_iters + 1, ops no wider than the pool's) on the
+ * handle's psi0, by the FP64 forward pass and reverse sweep. */
+int adapt64_energy_grad(fock_adapt64_t *st, const fock_op_t *ops, const double *theta, int n, double *E,
+                        double *dEdtheta);
+int adapt64_destroy(fock_adapt64_t *st);
+
 /* ------------------------------------------------------------------ warm-start network */
 
 /* A small network proposes the initial angles of an ADAPT step from the

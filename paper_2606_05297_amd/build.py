@@ -38,6 +38,8 @@ SOURCES = [
     "bfgs.cpp",
     "fuse_kernels.hip",
     "gate1_kernels.hip",
+    "f64_kernels.hip",
+    "adapt64.cpp",
     "dense_gate.hip",
     "mlp_kernels.hip",
     "mlp.cpp",

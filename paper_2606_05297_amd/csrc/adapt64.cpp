@@ -1,0 +1,323 @@
+// CV-ADAPT-VQE (Sec. IV.B) on complex128 states: the same loop as adapt_step
+// (pool scoring, tie band, append at theta = 0, BFGS re-optimisation with the
+// L-inf tolerance and optional Hessian recycling), with every evaluation on
+// the FP64 kernels of f64_kernels.hip.  For the small lattices whose runs
+// must resolve energy differences far below the complex64 state's rounding.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <vector>
+
+#include "bfgs.h"
+#include "f64_internal.h"
+#include "pipeline.h"
+
+struct fock_adapt64 {
+  fock::H64 h;
+  int L = 0, d = 0;
+  uint32_t namp = 0;
+  std::vector<fock_op_t> pool, ops;
+  std::vector<double> theta, Hinv;
+  fock_adapt_opts_t opt;
+  hipStream_t s = nullptr;
+  fock::EigTables T;
+  int cap = 0, Mmax = 0;  // gate capacity, largest local dimension
+  // device buffers
+  double2 *psi0 = nullptr, *phi = nullptr, *lam = nullptr, *utab = nullptr;
+  double *partial = nullptr, *res = nullptr, *th_dev = nullptr;
+  fock::GateRec *recs = nullptr;
+  std::map<int, double2 *> A;  // dense generator per type
+  int maxblk = 0;
+  int iter = 0;
+  bool done = false;
+};
+
+namespace fock {
+namespace {
+
+int local_dim(int d, int type) { return is_single_mode(type) ? d : d * d; }
+
+int generator64(fock_adapt64 *st, int type, const double2 **out) {
+  auto it = st->A.find(type);
+  if (it == st->A.end()) {
+    std::vector<double> m;
+    generator_dense(type, st->d, m);
+    double2 *p = nullptr;
+    FOCK_HIP(hipMalloc(&p, sizeof(double2) * m.size() / 2));
+    FOCK_HIP(hipMemcpy(p, m.data(), sizeof(double) * m.size(), hipMemcpyHostToDevice));
+    it = st->A.emplace(type, p).first;
+  }
+  *out = it->second;
+  return FOCK_OK;
+}
+
+int fetch(fock_adapt64 *st, int n, double *host) {
+  FOCK_HIP(hipMemcpyAsync(host, st->res, sizeof(double) * n, hipMemcpyDeviceToHost, st->s));
+  FOCK_HIP(hipStreamSynchronize(st->s));
+  return FOCK_OK;
+}
+
+// E(theta) (Rayleigh quotient), <psi|psi>, and dE/dtheta when g != nullptr.
+// Leaves phi = psi(theta) and lam = H psi when no gradient is asked for.
+int eval64(fock_adapt64 *st, const std::vector<double> &th, double *E, double *n2, std::vector<double> *g) {
+  const int n = (int)st->ops.size();
+  if (n > st->cap) return set_error(FOCK_ERR_SIZE, "more gates (%d) than the run's capacity (%d)", n, st->cap);
+  for (int k = 0; k < n; ++k)
+    if (!std::isfinite(th[k])) return set_error(FOCK_ERR_NONFINITE, "theta[%d] is not finite", k);
+  if (n > 0) {
+    std::vector<GateRec> rec(n);
+    for (int k = 0; k < n; ++k) rec[k] = GateRec{st->ops[k].type, k * st->Mmax * st->Mmax, 0, 0};
+    FOCK_HIP(hipMemcpyAsync(st->th_dev, th.data(), sizeof(double) * n, hipMemcpyHostToDevice, st->s));
+    FOCK_HIP(hipMemcpyAsync(st->recs, rec.data(), sizeof(GateRec) * n, hipMemcpyHostToDevice, st->s));
+    int rc = launch64_build(st->th_dev, st->recs, n, st->T, st->Mmax, st->utab, st->s);
+    if (rc) return rc;
+  }
+  FOCK_HIP(hipMemcpyAsync(st->phi, st->psi0, sizeof(double2) * st->namp, hipMemcpyDeviceToDevice, st->s));
+  for (int k = 0; k < n; ++k) {
+    const Fib64 a = make_fib64(st->L, st->d, st->ops[k]);
+    int rc = launch64_fib_apply(a, st->phi, st->phi, st->utab + (size_t)k * st->Mmax * st->Mmax, false, st->s);
+    if (rc) return rc;
+  }
+  int G = 0;
+  int rc = launch64_apply_h(st->h, st->phi, st->lam, st->partial, &G, st->s);
+  if (rc) return rc;
+  rc = launch_reduce(st->partial, G, 2, st->res, st->s);
+  if (rc) return rc;
+  if (g) {
+    for (int k = n - 1; k >= 0; --k) {
+      const Fib64 a = make_fib64(st->L, st->d, st->ops[k]);
+      const double2 *A = nullptr;
+      rc = generator64(st, st->ops[k].type, &A);
+      if (rc) return rc;
+      double *pk = st->partial + (size_t)(2 + k) * st->maxblk;
+      rc = launch64_fib_adj(a, st->phi, st->lam, st->utab + (size_t)k * st->Mmax * st->Mmax, A, pk, st->s);
+      if (rc) return rc;
+      rc = launch_reduce(pk, fib64_blocks(a), 1, st->res + 2 + k, st->s);
+      if (rc) return rc;
+    }
+  }
+  std::vector<double> host(2 + (g ? n : 0));
+  rc = fetch(st, (int)host.size(), host.data());
+  if (rc) return rc;
+  if (!std::isfinite(host[0]) || !(host[1] > 0.0))
+    return set_error(FOCK_ERR_NONFINITE, "non-finite energy or zero norm (E=%g, norm2=%g)", host[0], host[1]);
+  *E = host[0] / host[1];
+  if (n2) *n2 = host[1];
+  if (g) {
+    g->resize(n);
+    for (int k = 0; k < n; ++k) (*g)[k] = 2.0 * host[2 + k] / host[1];
+  }
+  return FOCK_OK;
+}
+
+// 2 Re<H psi|A_k psi> for the whole pool on phi = psi, lam = H psi.
+int pool64(fock_adapt64 *st, std::vector<double> *g) {
+  const int P = (int)st->pool.size();
+  for (int k = 0; k < P; ++k) {
+    const Fib64 a = make_fib64(st->L, st->d, st->pool[k]);
+    const double2 *A = nullptr;
+    int rc = generator64(st, st->pool[k].type, &A);
+    if (rc) return rc;
+    double *pk = st->partial + (size_t)k * st->maxblk;
+    rc = launch64_fib_pool(a, st->phi, st->lam, A, pk, st->s);
+    if (rc) return rc;
+    rc = launch_reduce(pk, fib64_blocks(a), 1, st->res + k, st->s);
+    if (rc) return rc;
+  }
+  g->resize(P);
+  return fetch(st, P, g->data());
+}
+
+void release(fock_adapt64 *st) {
+  if (st->s) (void)hipStreamSynchronize(st->s);
+  for (void *p : {(void *)st->psi0, (void *)st->phi, (void *)st->lam, (void *)st->utab, (void *)st->partial,
+                  (void *)st->res, (void *)st->th_dev, (void *)st->recs})
+    if (p) (void)hipFree(p);
+  for (auto &kv : st->A) (void)hipFree(kv.second);
+  if (st->s) (void)hipStreamDestroy(st->s);
+}
+
+}  // namespace
+}  // namespace fock
+
+using namespace fock;
+
+extern "C" {
+
+int adapt64_create(const fock_ham_t *ham, const fock_op_t *pool, int P, const void *psi0,
+                   const fock_adapt_opts_t *opts, fock_stream_t stream, fock_adapt64_t **out) {
+  if (!out) return set_error(FOCK_ERR_ARG, "out is NULL");
+  *out = nullptr;
+  uint32_t namp = 0;
+  int rc = check_ham(ham, &namp);
+  if (rc) return rc;
+  if (!pool || P < 1 || P > 4096) return set_error(FOCK_ERR_ARG, "pool must hold 1..4096 ops");
+  for (int k = 0; k < P; ++k)
+    if ((rc = check_op(pool[k], ham->L))) return rc;
+  if ((rc = check_ptr(psi0, "psi0"))) return rc;
+  fock_adapt_opts_t o;
+  adapt_default_opts(&o);
+  if (opts) o = *opts;
+  if (o.n_warm != 0) return set_error(FOCK_ERR_UNSUPPORTED, "the FP64 driver takes no warm-up layer");
+  if (o.grad_mode != 0) return set_error(FOCK_ERR_UNSUPPORTED, "the FP64 driver uses adjoint gradients only");
+  if (o.max_iters < 0 || o.max_iters > 4000) return set_error(FOCK_ERR_ARG, "max_iters out of range");
+  if (hipStreamSynchronize((hipStream_t)stream) != hipSuccess) return set_error(FOCK_ERR_HIP, "caller stream error");
+  fock_adapt64 *st = new fock_adapt64();
+  st->L = ham->L;
+  st->d = ham->d;
+  st->namp = namp;
+  st->h = H64{ham->L, ham->d, (ham->periodic && ham->L >= 3) ? 1 : 0, namp, ham->J, ham->Delta,
+              0.5 * ham->U + ham->K, ham->mu};
+  st->pool.assign(pool, pool + P);
+  st->opt = o;
+  st->cap = o.max_iters + 1;
+  st->Mmax = 0;
+  for (int k = 0; k < P; ++k) st->Mmax = std::max(st->Mmax, local_dim(ham->d, pool[k].type));
+  // partial rows: the most workgroups of any launch (H psi, or fibres of d or d^2 amplitudes)
+  st->maxblk = (int)((namp + kBlock - 1) / kBlock);
+  for (int M : {ham->d, ham->d * ham->d}) {
+    const uint32_t fpw = (uint32_t)std::max(1, kBlock / M), nf = namp / (uint32_t)M;
+    st->maxblk = std::max(st->maxblk, (int)((nf + fpw - 1) / fpw));
+  }
+  const int rows = std::max(2 + st->cap, P) + 2;
+  auto fail = [&](int code) {
+    release(st);
+    delete st;
+    return code;
+  };
+  if (hipStreamCreateWithFlags(&st->s, hipStreamNonBlocking) != hipSuccess)
+    return fail(set_error(FOCK_ERR_HIP, "stream creation failed"));
+  const size_t bs = sizeof(double2) * namp;
+  if (hipMalloc(&st->psi0, bs) != hipSuccess || hipMalloc(&st->phi, bs) != hipSuccess ||
+      hipMalloc(&st->lam, bs) != hipSuccess ||
+      hipMalloc(&st->utab, sizeof(double2) * (size_t)st->cap * st->Mmax * st->Mmax) != hipSuccess ||
+      hipMalloc(&st->partial, sizeof(double) * (size_t)rows * st->maxblk) != hipSuccess ||
+      hipMalloc(&st->res, sizeof(double) * rows) != hipSuccess ||
+      hipMalloc(&st->th_dev, sizeof(double) * st->cap) != hipSuccess ||
+      hipMalloc(&st->recs, sizeof(GateRec) * st->cap) != hipSuccess)
+    return fail(set_error(FOCK_ERR_HIP, "device allocation failed"));
+  if (hipMemcpy(st->psi0, psi0, bs, hipMemcpyDeviceToDevice) != hipSuccess)
+    return fail(set_error(FOCK_ERR_HIP, "copy of psi0 failed"));
+  if ((rc = get_tables(ham->d, &st->T))) return fail(rc);
+  *out = st;
+  return FOCK_OK;
+}
+
+int adapt64_step(fock_adapt64_t *st, fock_adapt_report_t *rep) {
+  if (!st || !rep) return set_error(FOCK_ERR_ARG, "NULL argument");
+  if (st->done) return set_error(FOCK_ERR_STATE, "ADAPT run already finished");
+  memset(rep, 0, sizeof(*rep));
+  st->iter += 1;
+  rep->iter = st->iter;
+  rep->k_sel = -1;
+  double E = 0.0, n2 = 0.0;
+  int rc = eval64(st, st->theta, &E, &n2, nullptr);
+  if (rc) return rc;
+  std::vector<double> g;
+  rc = pool64(st, &g);
+  if (rc) return rc;
+  double gn2 = 0.0, ginf = 0.0;
+  for (auto &v : g) {
+    v /= n2;
+    gn2 += v * v;
+    ginf = std::max(ginf, std::fabs(v));
+  }
+  gn2 = std::sqrt(gn2);
+  rep->g_norm2 = gn2;
+  rep->g_inf = ginf;
+  rep->E = rep->E_init = E;
+  rep->norm2 = n2;
+  rep->n_params = (int)st->theta.size();
+  if (gn2 < st->opt.grad_tol) {
+    rep->converged = 1;
+    st->done = true;
+    return FOCK_OK;
+  }
+  if (st->iter > st->opt.max_iters) {
+    rep->capped = 1;
+    st->done = true;
+    return FOCK_OK;
+  }
+  int ks = 0;
+  for (int k = 0; k < (int)g.size(); ++k)
+    if (std::fabs(g[k]) >= (1.0 - st->opt.tie_tau) * ginf) {
+      ks = k;
+      break;
+    }
+  rep->k_sel = ks;
+  rep->g_sel = std::fabs(g[ks]);
+  st->ops.push_back(st->pool[ks]);
+  st->theta.push_back(0.0);
+  const int n = (int)st->theta.size();
+  std::vector<double> *H = nullptr;
+  if (st->opt.recycle_hessian) {
+    const int m = (int)std::lround(std::sqrt((double)st->Hinv.size()));
+    std::vector<double> Hn((size_t)n * n, 0.0);
+    for (int r = 0; r < n; ++r) Hn[(size_t)r * n + r] = 1.0;
+    if (m == n - 1)
+      for (int r = 0; r < m; ++r)
+        for (int c = 0; c < m; ++c) Hn[(size_t)r * n + c] = st->Hinv[(size_t)r * m + c];
+    st->Hinv.swap(Hn);
+    H = &st->Hinv;
+  }
+  const double gtol = std::max(std::min(1e-6, 1e-5 * rep->g_sel), st->opt.gtol_floor_rel * std::max(1.0, std::fabs(E)));
+  ObjFn fn = [st](const std::vector<double> &x, double *f, std::vector<double> *gx) {
+    return eval64(st, x, f, nullptr, gx);
+  };
+  BfgsOut bo;
+  rc = bfgs_minimize(st->theta, fn, gtol, st->opt.bfgs_maxiter, H, &bo, 0.0);
+  if (rc) return rc;
+  double Ef = 0.0, nf = 0.0;
+  rc = eval64(st, st->theta, &Ef, &nf, nullptr);
+  if (rc) return rc;
+  rep->bfgs_iters = bo.iters;
+  rep->bfgs_evals = bo.evals + 1;
+  rep->status = bo.status;
+  rep->E = Ef;
+  rep->norm2 = nf;
+  rep->E_init = bo.f0;
+  rep->n_params = n;
+  return FOCK_OK;
+}
+
+int adapt64_get_ansatz(fock_adapt64_t *st, fock_op_t *ops, double *theta, int cap, int *n) {
+  if (!st || !n) return set_error(FOCK_ERR_ARG, "NULL argument");
+  *n = (int)st->ops.size();
+  const int m = std::min(cap, *n);
+  for (int k = 0; k < m; ++k) {
+    if (ops) ops[k] = st->ops[k];
+    if (theta) theta[k] = st->theta[k];
+  }
+  return FOCK_OK;
+}
+
+int adapt64_energy_grad(fock_adapt64_t *st, const fock_op_t *ops, const double *theta, int n, double *E,
+                        double *dEdtheta) {
+  if (!st || !E || (n > 0 && (!ops || !theta))) return set_error(FOCK_ERR_ARG, "NULL argument");
+  if (n < 0 || n > st->cap) return set_error(FOCK_ERR_SIZE, "n = %d outside the run's capacity %d", n, st->cap);
+  for (int k = 0; k < n; ++k) {
+    int rc = check_op(ops[k], st->L);
+    if (rc) return rc;
+    if (local_dim(st->d, ops[k].type) > st->Mmax)
+      return set_error(FOCK_ERR_ARG, "op %d needs a larger gate table than the pool's", k);
+  }
+  const std::vector<fock_op_t> keep = st->ops;
+  st->ops.assign(ops, ops + n);
+  std::vector<double> th(theta, theta + n), g;
+  const int rc = eval64(st, th, E, nullptr, dEdtheta ? &g : nullptr);
+  st->ops = keep;
+  if (rc) return rc;
+  if (dEdtheta)
+    for (int k = 0; k < n; ++k) dEdtheta[k] = g[k];
+  return FOCK_OK;
+}
+
+int adapt64_destroy(fock_adapt64_t *st) {
+  if (!st) return FOCK_OK;
+  release(st);
+  delete st;
+  return FOCK_OK;
+}
+
+}  // extern "C"

@@ -107,6 +107,12 @@ def load(path: str = LIB_PATH):
     L.adapt_propose.argtypes = [vp, dp, C.c_int]
     L.adapt_last_proposal.argtypes = [vp, ip, dp, dp]
     L.adapt_destroy.argtypes = [vp]
+    L.adapt64_create.argtypes = [C.POINTER(Ham), C.POINTER(Op), C.c_int, vp, C.POINTER(AdaptOpts), vp,
+                                 C.POINTER(vp)]
+    L.adapt64_step.argtypes = [vp, C.POINTER(AdaptReport)]
+    L.adapt64_get_ansatz.argtypes = [vp, C.POINTER(Op), dp, C.c_int, ip]
+    L.adapt64_energy_grad.argtypes = [vp, C.POINTER(Op), dp, C.c_int, dp, dp]
+    L.adapt64_destroy.argtypes = [vp]
     L.fock_sweep_create.argtypes = [C.POINTER(SweepPoint), C.c_int, C.POINTER(AdaptOpts), vp, C.POINTER(vp)]
     L.fock_sweep_step.argtypes = [vp, C.POINTER(AdaptReport), C.POINTER(C.c_int)]
     L.fock_sweep_warm_reports.argtypes = [vp, C.POINTER(AdaptReport)]
@@ -308,6 +314,66 @@ class Adapt:
     def close(self):
         if self._st:
             self._L.adapt_destroy(self._st)
+            self._st = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Adapt64:
+    """CV-ADAPT-VQE on complex128 states (adapt64_create / adapt64_step): psi0
+    is a device complex128 tensor; no warm-up layer, adjoint gradients, no
+    noise-floor stop."""
+
+    def __init__(self, h: Ham, pool, psi0, max_iters=60, grad_tol=1e-3, recycle_hessian=False, bfgs_maxiter=1000,
+                 tie_tau=1e-4, gtol_floor_rel=1e-5, stream=None):
+        L = load()
+        self._L = L
+        o = AdaptOpts()
+        L.adapt_default_opts(C.byref(o))
+        o.max_iters = int(max_iters)
+        o.grad_tol = float(grad_tol)
+        o.recycle_hessian = int(bool(recycle_hessian))
+        o.bfgs_maxiter = int(bfgs_maxiter)
+        o.tie_tau = float(tie_tau)
+        o.gtol_floor_rel = float(gtol_floor_rel)
+        self.pool = list(pool)
+        self._pool = ops_array(self.pool)
+        self.h = h
+        self._st = C.c_void_p()
+        _check(L.adapt64_create(C.byref(h), self._pool, len(self.pool), _ptr(psi0), C.byref(o), _stream(stream),
+                                C.byref(self._st)))
+
+    def step(self) -> dict:
+        r = AdaptReport()
+        _check(self._L.adapt64_step(self._st, C.byref(r)))
+        return r.as_dict()
+
+    def ansatz(self):
+        n = C.c_int(0)
+        _check(self._L.adapt64_get_ansatz(self._st, None, None, 0, C.byref(n)))
+        m = n.value
+        ops = (Op * max(1, m))()
+        th = np.zeros(max(1, m))
+        _check(self._L.adapt64_get_ansatz(self._st, ops, th.ctypes.data_as(C.POINTER(C.c_double)), m, C.byref(n)))
+        return [(TYPE_NAMES[ops[k].type], ops[k].i, ops[k].j) for k in range(m)], th[:m].copy()
+
+    def energy_grad(self, ops, theta, grad=True):
+        """(E, dE/dtheta or None) of an ansatz on this run's psi0, in FP64."""
+        n = len(ops)
+        th = np.ascontiguousarray(theta, dtype=np.float64)
+        E = C.c_double(0)
+        g = np.zeros(max(n, 1))
+        _check(self._L.adapt64_energy_grad(self._st, ops_array(list(ops)), th.ctypes.data_as(C.POINTER(C.c_double)), n,
+                                           C.byref(E), g.ctypes.data_as(C.POINTER(C.c_double)) if grad else None))
+        return E.value, (g[:n].copy() if grad else None)
+
+    def close(self):
+        if self._st:
+            self._L.adapt64_destroy(self._st)
             self._st = C.c_void_p()
 
     def __del__(self):
