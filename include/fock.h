@@ -81,6 +81,15 @@ enum {
   FOCK_HR = 0, FOCK_HI = 1, FOCK_DH = 2, FOCK_PR = 3, FOCK_PI = 4, FOCK_KERR = 5, FOCK_ROT = 6, FOCK_CK = 7,
   FOCK_SR = 8, FOCK_SI = 9
 };
+/* Two-parameter gates exp(theta A(phi)) of Sec. II.B, pool entries of the
+ * complex128 driver (adapt64_*) only:
+ *   FOCK_BS   beam splitter, A = e^{i phi} a_i a_j^+ - e^{-i phi} a_i^+ a_j
+ *   FOCK_TMS  two-mode squeezer, A = e^{i phi} a_i a_j - e^{-i phi} a_i^+ a_j^+
+ *   FOCK_SQ   single-mode squeezer (j = -1), A = (e^{-i phi} a_i^2 - e^{i phi} a_i^+2) / 2
+ * Each is R(c phi) exp(theta A(0)) R(-c phi) with phase rotations R on mode j
+ * (BS: c = 1, TMS: c = -1) or i (SQ: c = 1/2), and is expanded to those three
+ * gates (adapt64_get_ansatz returns the expanded circuit). */
+enum { FOCK_BS = 10, FOCK_TMS = 11, FOCK_SQ = 12 };
 
 typedef struct {
   int32_t type, i, j;
@@ -350,18 +359,23 @@ int fock_get_stencil_variant(void);
  * local gate matrix of d^2 x d^2 or d x d), meant for lattices of up to ~1e6
  * amplitudes.  psi0: device, d^L complex128 (copied); opts: as adapt_create,
  * except that warm-up layers and finite-difference gradients are refused
- * (FOCK_ERR_UNSUPPORTED).  The handle owns its buffers and a private stream;
+ * (FOCK_ERR_UNSUPPORTED); gtol_floor_rel is taken as given, and its default
+ * (1e-5, the complex64 resolution) stops BFGS once ||g||_inf < 1e-5 |E|, which
+ * caps the energy error near 1e-6 |E|: complex128 runs pass ~1e-11.  The handle owns its buffers and a private stream;
  * `stream` is synchronised once at creation. */
 typedef struct fock_adapt64 fock_adapt64_t;
 int adapt64_create(const fock_ham_t *ham, const fock_op_t *pool, int P, const void *psi0,
                    const fock_adapt_opts_t *opts, fock_stream_t stream, fock_adapt64_t **out);
 /* One ADAPT iteration; FOCK_ERR_STATE once converged or capped. */
 int adapt64_step(fock_adapt64_t *st, fock_adapt_report_t *rep);
-/* Current ansatz (see adapt_get_ansatz). */
+/* Current ansatz as gates and gate angles (see adapt_get_ansatz); a
+ * two-parameter op appears as its three gates.  The report's n_params counts
+ * the logical parameters (two per two-parameter op). */
 int adapt64_get_ansatz(fock_adapt64_t *st, fock_op_t *ops, double *theta, int cap, int *n);
 /* E (Rayleigh quotient) and, if dEdtheta is non-NULL, all dE/dtheta_k of the
- * ansatz ops/theta (n <= max_iters + 1, ops no wider than the pool's) on the
- * handle's psi0, by the FP64 forward pass and reverse sweep. */
+ * ansatz ops/theta (ops no wider than the pool's) on the
+ * handle's psi0, by the FP64 forward pass and reverse sweep.  ops are gates
+ * (no two-parameter types), n <= 3 (max_iters + 1). */
 int adapt64_energy_grad(fock_adapt64_t *st, const fock_op_t *ops, const double *theta, int n, double *E,
                         double *dEdtheta);
 int adapt64_destroy(fock_adapt64_t *st);

@@ -3,6 +3,17 @@
 // L-inf tolerance and optional Hessian recycling), with every evaluation on
 // the FP64 kernels of f64_kernels.hip.  For the small lattices whose runs
 // must resolve energy differences far below the complex64 state's rounding.
+//
+// Two-parameter gates (Sec. II.B; FOCK_BS, FOCK_TMS, FOCK_SQ): the phase phi of
+// the beam splitter, two-mode squeezer and squeezer is a conjugation by phase
+// rotations R(a) = exp(i a N) of the phi = 0 gate,
+//   BS(theta, phi)  = R_j(phi) exp(-theta HR) R_j(-phi)
+//   TMS(theta, phi) = R_j(-phi) exp(theta PR) R_j(phi)
+//   SQ(theta, phi)  = R_i(phi/2) exp(theta SR) R_i(-phi/2),
+// so each expands to three gates with tied angles; dE/dtheta and dE/dphi
+// follow by the chain rule from the three gates' adjoint gradients.  They are
+// scored by |dE/dtheta| at theta = phi = 0 (dE/dphi vanishes there, Sec. IV.B)
+// and enter the ansatz at (0, 0).
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -17,8 +28,9 @@ struct fock_adapt64 {
   fock::H64 h;
   int L = 0, d = 0;
   uint32_t namp = 0;
-  std::vector<fock_op_t> pool, ops;
-  std::vector<double> theta, Hinv;
+  std::vector<fock_op_t> pool, ops;  // ops: the ansatz's logical ops (two-parameter ones unexpanded)
+  std::vector<double> theta, Hinv;   // theta: logical parameters (two per two-parameter op)
+  std::vector<fock_op_t> gops;       // gates of the last evaluation
   fock_adapt_opts_t opt;
   hipStream_t s = nullptr;
   fock::EigTables T;
@@ -36,7 +48,60 @@ struct fock_adapt64 {
 namespace fock {
 namespace {
 
-int local_dim(int d, int type) { return is_single_mode(type) ? d : d * d; }
+bool two_param(int t) { return t == FOCK_BS || t == FOCK_TMS || t == FOCK_SQ; }
+int fixed_type(int t) { return t == FOCK_BS ? FOCK_HR : t == FOCK_TMS ? FOCK_PR : t == FOCK_SQ ? FOCK_SR : t; }
+int local_dim(int d, int type) { return is_single_mode(fixed_type(type)) ? d : d * d; }
+
+// Logical ansatz (ops, x) -> gates and gate angles.
+void expand(const std::vector<fock_op_t> &lops, const std::vector<double> &x, std::vector<fock_op_t> *g,
+            std::vector<double> *a) {
+  g->clear();
+  a->clear();
+  size_t p = 0;
+  for (const fock_op_t &op : lops) {
+    if (!two_param(op.type)) {
+      g->push_back(op);
+      a->push_back(x[p++]);
+      continue;
+    }
+    const double th = x[p], ph = x[p + 1];
+    p += 2;
+    const fock_op_t rot{FOCK_ROT, op.type == FOCK_SQ ? op.i : op.j, -1};
+    const fock_op_t fix{fixed_type(op.type), op.i, op.type == FOCK_SQ ? -1 : op.j};
+    const double r1 = op.type == FOCK_BS ? -ph : op.type == FOCK_TMS ? ph : -0.5 * ph;
+    const double c = op.type == FOCK_BS ? -1.0 : 1.0;
+    g->push_back(rot);
+    a->push_back(r1);
+    g->push_back(fix);
+    a->push_back(c * th);
+    g->push_back(rot);
+    a->push_back(-r1);
+  }
+}
+
+// Gate gradients -> logical gradients (chain rule through expand).
+void contract(const std::vector<fock_op_t> &lops, const std::vector<double> &gg, std::vector<double> *gx) {
+  gx->clear();
+  size_t q = 0;
+  for (const fock_op_t &op : lops) {
+    if (!two_param(op.type)) {
+      gx->push_back(gg[q++]);
+      continue;
+    }
+    const double g1 = gg[q], g2 = gg[q + 1], g3 = gg[q + 2];
+    q += 3;
+    if (op.type == FOCK_BS) {
+      gx->push_back(-g2);
+      gx->push_back(g3 - g1);
+    } else if (op.type == FOCK_TMS) {
+      gx->push_back(g2);
+      gx->push_back(g1 - g3);
+    } else {
+      gx->push_back(g2);
+      gx->push_back(0.5 * (g3 - g1));
+    }
+  }
+}
 
 int generator64(fock_adapt64 *st, int type, const double2 **out) {
   auto it = st->A.find(type);
@@ -58,16 +123,17 @@ int fetch(fock_adapt64 *st, int n, double *host) {
   return FOCK_OK;
 }
 
-// E(theta) (Rayleigh quotient), <psi|psi>, and dE/dtheta when g != nullptr.
-// Leaves phi = psi(theta) and lam = H psi when no gradient is asked for.
-int eval64(fock_adapt64 *st, const std::vector<double> &th, double *E, double *n2, std::vector<double> *g) {
-  const int n = (int)st->ops.size();
+// E (Rayleigh quotient), <psi|psi>, and the gate gradients when g != nullptr,
+// for the gates st->gops at angles th.  Leaves phi = psi and lam = H psi when
+// no gradient is asked for.
+int eval_gates(fock_adapt64 *st, const std::vector<double> &th, double *E, double *n2, std::vector<double> *g) {
+  const int n = (int)st->gops.size();
   if (n > st->cap) return set_error(FOCK_ERR_SIZE, "more gates (%d) than the run's capacity (%d)", n, st->cap);
   for (int k = 0; k < n; ++k)
     if (!std::isfinite(th[k])) return set_error(FOCK_ERR_NONFINITE, "theta[%d] is not finite", k);
   if (n > 0) {
     std::vector<GateRec> rec(n);
-    for (int k = 0; k < n; ++k) rec[k] = GateRec{st->ops[k].type, k * st->Mmax * st->Mmax, 0, 0};
+    for (int k = 0; k < n; ++k) rec[k] = GateRec{st->gops[k].type, k * st->Mmax * st->Mmax, 0, 0};
     FOCK_HIP(hipMemcpyAsync(st->th_dev, th.data(), sizeof(double) * n, hipMemcpyHostToDevice, st->s));
     FOCK_HIP(hipMemcpyAsync(st->recs, rec.data(), sizeof(GateRec) * n, hipMemcpyHostToDevice, st->s));
     int rc = launch64_build(st->th_dev, st->recs, n, st->T, st->Mmax, st->utab, st->s);
@@ -75,7 +141,7 @@ int eval64(fock_adapt64 *st, const std::vector<double> &th, double *E, double *n
   }
   FOCK_HIP(hipMemcpyAsync(st->phi, st->psi0, sizeof(double2) * st->namp, hipMemcpyDeviceToDevice, st->s));
   for (int k = 0; k < n; ++k) {
-    const Fib64 a = make_fib64(st->L, st->d, st->ops[k]);
+    const Fib64 a = make_fib64(st->L, st->d, st->gops[k]);
     int rc = launch64_fib_apply(a, st->phi, st->phi, st->utab + (size_t)k * st->Mmax * st->Mmax, false, st->s);
     if (rc) return rc;
   }
@@ -86,9 +152,9 @@ int eval64(fock_adapt64 *st, const std::vector<double> &th, double *E, double *n
   if (rc) return rc;
   if (g) {
     for (int k = n - 1; k >= 0; --k) {
-      const Fib64 a = make_fib64(st->L, st->d, st->ops[k]);
+      const Fib64 a = make_fib64(st->L, st->d, st->gops[k]);
       const double2 *A = nullptr;
-      rc = generator64(st, st->ops[k].type, &A);
+      rc = generator64(st, st->gops[k].type, &A);
       if (rc) return rc;
       double *pk = st->partial + (size_t)(2 + k) * st->maxblk;
       rc = launch64_fib_adj(a, st->phi, st->lam, st->utab + (size_t)k * st->Mmax * st->Mmax, A, pk, st->s);
@@ -111,13 +177,28 @@ int eval64(fock_adapt64 *st, const std::vector<double> &th, double *E, double *n
   return FOCK_OK;
 }
 
-// 2 Re<H psi|A_k psi> for the whole pool on phi = psi, lam = H psi.
+// E, <psi|psi> and the logical gradient of the ansatz ops at logical parameters x.
+int eval64(fock_adapt64 *st, const std::vector<fock_op_t> &lops, const std::vector<double> &x, double *E, double *n2,
+           std::vector<double> *gx) {
+  std::vector<double> a, gg;
+  expand(lops, x, &st->gops, &a);
+  int rc = eval_gates(st, a, E, n2, gx ? &gg : nullptr);
+  if (rc || !gx) return rc;
+  contract(lops, gg, gx);
+  return FOCK_OK;
+}
+
+// 2 Re<H psi|A_k psi> for the whole pool on phi = psi, lam = H psi (the phi = 0
+// generator of a two-parameter entry, with its sign in the expansion).
 int pool64(fock_adapt64 *st, std::vector<double> *g) {
   const int P = (int)st->pool.size();
   for (int k = 0; k < P; ++k) {
-    const Fib64 a = make_fib64(st->L, st->d, st->pool[k]);
+    fock_op_t op = st->pool[k];
+    if (op.type == FOCK_SQ) op.j = -1;
+    op.type = fixed_type(op.type);
+    const Fib64 a = make_fib64(st->L, st->d, op);
     const double2 *A = nullptr;
-    int rc = generator64(st, st->pool[k].type, &A);
+    int rc = generator64(st, op.type, &A);
     if (rc) return rc;
     double *pk = st->partial + (size_t)k * st->maxblk;
     rc = launch64_fib_pool(a, st->phi, st->lam, A, pk, st->s);
@@ -126,7 +207,11 @@ int pool64(fock_adapt64 *st, std::vector<double> *g) {
     if (rc) return rc;
   }
   g->resize(P);
-  return fetch(st, P, g->data());
+  int rc = fetch(st, P, g->data());
+  if (rc) return rc;
+  for (int k = 0; k < P; ++k)
+    if (st->pool[k].type == FOCK_BS) (*g)[k] = -(*g)[k];
+  return FOCK_OK;
 }
 
 void release(fock_adapt64 *st) {
@@ -153,8 +238,17 @@ int adapt64_create(const fock_ham_t *ham, const fock_op_t *pool, int P, const vo
   int rc = check_ham(ham, &namp);
   if (rc) return rc;
   if (!pool || P < 1 || P > 4096) return set_error(FOCK_ERR_ARG, "pool must hold 1..4096 ops");
-  for (int k = 0; k < P; ++k)
-    if ((rc = check_op(pool[k], ham->L))) return rc;
+  for (int k = 0; k < P; ++k) {
+    const fock_op_t &op = pool[k];
+    if (two_param(op.type)) {
+      fock_op_t f = op;
+      f.type = fixed_type(op.type);
+      if (op.type == FOCK_SQ) f.j = -1;
+      if ((rc = check_op(f, ham->L))) return rc;
+    } else if ((rc = check_op(op, ham->L))) {
+      return rc;
+    }
+  }
   if ((rc = check_ptr(psi0, "psi0"))) return rc;
   fock_adapt_opts_t o;
   adapt_default_opts(&o);
@@ -171,7 +265,7 @@ int adapt64_create(const fock_ham_t *ham, const fock_op_t *pool, int P, const vo
               0.5 * ham->U + ham->K, ham->mu};
   st->pool.assign(pool, pool + P);
   st->opt = o;
-  st->cap = o.max_iters + 1;
+  st->cap = 3 * (o.max_iters + 1);  // gates: a two-parameter op expands to three
   st->Mmax = 0;
   for (int k = 0; k < P; ++k) st->Mmax = std::max(st->Mmax, local_dim(ham->d, pool[k].type));
   // partial rows: the most workgroups of any launch (H psi, or fibres of d or d^2 amplitudes)
@@ -212,7 +306,7 @@ int adapt64_step(fock_adapt64_t *st, fock_adapt_report_t *rep) {
   rep->iter = st->iter;
   rep->k_sel = -1;
   double E = 0.0, n2 = 0.0;
-  int rc = eval64(st, st->theta, &E, &n2, nullptr);
+  int rc = eval64(st, st->ops, st->theta, &E, &n2, nullptr);
   if (rc) return rc;
   std::vector<double> g;
   rc = pool64(st, &g);
@@ -248,14 +342,16 @@ int adapt64_step(fock_adapt64_t *st, fock_adapt_report_t *rep) {
   rep->k_sel = ks;
   rep->g_sel = std::fabs(g[ks]);
   st->ops.push_back(st->pool[ks]);
-  st->theta.push_back(0.0);
+  if (st->ops.back().type == FOCK_SQ) st->ops.back().j = -1;
+  const int added = two_param(st->pool[ks].type) ? 2 : 1;
+  for (int k = 0; k < added; ++k) st->theta.push_back(0.0);
   const int n = (int)st->theta.size();
   std::vector<double> *H = nullptr;
   if (st->opt.recycle_hessian) {
     const int m = (int)std::lround(std::sqrt((double)st->Hinv.size()));
     std::vector<double> Hn((size_t)n * n, 0.0);
     for (int r = 0; r < n; ++r) Hn[(size_t)r * n + r] = 1.0;
-    if (m == n - 1)
+    if (m == n - added)
       for (int r = 0; r < m; ++r)
         for (int c = 0; c < m; ++c) Hn[(size_t)r * n + c] = st->Hinv[(size_t)r * m + c];
     st->Hinv.swap(Hn);
@@ -263,13 +359,13 @@ int adapt64_step(fock_adapt64_t *st, fock_adapt_report_t *rep) {
   }
   const double gtol = std::max(std::min(1e-6, 1e-5 * rep->g_sel), st->opt.gtol_floor_rel * std::max(1.0, std::fabs(E)));
   ObjFn fn = [st](const std::vector<double> &x, double *f, std::vector<double> *gx) {
-    return eval64(st, x, f, nullptr, gx);
+    return eval64(st, st->ops, x, f, nullptr, gx);
   };
   BfgsOut bo;
   rc = bfgs_minimize(st->theta, fn, gtol, st->opt.bfgs_maxiter, H, &bo, 0.0);
   if (rc) return rc;
   double Ef = 0.0, nf = 0.0;
-  rc = eval64(st, st->theta, &Ef, &nf, nullptr);
+  rc = eval64(st, st->ops, st->theta, &Ef, &nf, nullptr);
   if (rc) return rc;
   rep->bfgs_iters = bo.iters;
   rep->bfgs_evals = bo.evals + 1;
@@ -283,11 +379,14 @@ int adapt64_step(fock_adapt64_t *st, fock_adapt_report_t *rep) {
 
 int adapt64_get_ansatz(fock_adapt64_t *st, fock_op_t *ops, double *theta, int cap, int *n) {
   if (!st || !n) return set_error(FOCK_ERR_ARG, "NULL argument");
-  *n = (int)st->ops.size();
+  std::vector<fock_op_t> g;
+  std::vector<double> a;
+  expand(st->ops, st->theta, &g, &a);
+  *n = (int)g.size();
   const int m = std::min(cap, *n);
   for (int k = 0; k < m; ++k) {
-    if (ops) ops[k] = st->ops[k];
-    if (theta) theta[k] = st->theta[k];
+    if (ops) ops[k] = g[k];
+    if (theta) theta[k] = a[k];
   }
   return FOCK_OK;
 }
@@ -302,11 +401,9 @@ int adapt64_energy_grad(fock_adapt64_t *st, const fock_op_t *ops, const double *
     if (local_dim(st->d, ops[k].type) > st->Mmax)
       return set_error(FOCK_ERR_ARG, "op %d needs a larger gate table than the pool's", k);
   }
-  const std::vector<fock_op_t> keep = st->ops;
-  st->ops.assign(ops, ops + n);
+  st->gops.assign(ops, ops + n);
   std::vector<double> th(theta, theta + n), g;
-  const int rc = eval64(st, th, E, nullptr, dEdtheta ? &g : nullptr);
-  st->ops = keep;
+  const int rc = eval_gates(st, th, E, nullptr, dEdtheta ? &g : nullptr);
   if (rc) return rc;
   if (dEdtheta)
     for (int k = 0; k < n; ++k) dEdtheta[k] = g[k];

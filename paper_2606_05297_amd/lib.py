@@ -14,7 +14,8 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libfock.so")
 
-TYPES = {"HR": 0, "HI": 1, "DH": 2, "PR": 3, "PI": 4, "KERR": 5, "ROT": 6, "CK": 7, "SR": 8, "SI": 9}
+TYPES = {"HR": 0, "HI": 1, "DH": 2, "PR": 3, "PI": 4, "KERR": 5, "ROT": 6, "CK": 7, "SR": 8, "SI": 9,
+         "BS": 10, "TMS": 11, "SQ": 12}
 TYPE_NAMES = {v: k for k, v in TYPES.items()}
 
 FOCK_OK = 0
@@ -326,10 +327,11 @@ class Adapt:
 class Adapt64:
     """CV-ADAPT-VQE on complex128 states (adapt64_create / adapt64_step): psi0
     is a device complex128 tensor; no warm-up layer, adjoint gradients, no
-    noise-floor stop."""
+    noise-floor stop.  The BFGS tolerance floor defaults to 1e-11 |E| (FP64
+    gradients), not the complex64 path's 1e-5 |E|."""
 
     def __init__(self, h: Ham, pool, psi0, max_iters=60, grad_tol=1e-3, recycle_hessian=False, bfgs_maxiter=1000,
-                 tie_tau=1e-4, gtol_floor_rel=1e-5, stream=None):
+                 tie_tau=1e-4, gtol_floor_rel=1e-11, stream=None):
         L = load()
         self._L = L
         o = AdaptOpts()

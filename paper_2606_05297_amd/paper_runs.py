@@ -1,7 +1,7 @@
 """CV-ADAPT-VQE at the paper's own parameters (Sec. V): energy error against
 exact diagonalisation as a function of the number of ADAPT gates.
 
-    python -m paper_2606_05297_amd.paper_runs [--gates 160] [--cases name,...] [--out file]
+    python -m paper_2606_05297_amd.paper_runs [--gates 160] [--cases name,...] [--fp64 [--two-param]] [--out file]
 
 Cases: workload.paper_cases() (Kitaev chain N_S = 3..5 at mu = -3.1 and -2.7,
 Kitaev chain with Kerr term, Bose-Hubbard N_S = 4 with 12 bosons at
@@ -9,9 +9,13 @@ Lambda = +-4).  Each run appends operators until `gates` have been added or
 the energy error drops below 1e-10 (the paper's stopping rule; the gradient
 threshold is disabled), with the inverse Hessian recycled across steps.
 Exact ground energies: tests/golden/paper_cases_ed.json (written from the FP64
-oracle by tests/golden/make_ed_reference.py --paper-cases).  States are
-complex64, so the energy error levels off near 1e-6 |E0| instead of the
-paper's 1e-10.  Prints one JSON line per case.
+oracle by tests/golden/make_ed_reference.py --paper-cases).  complex64 states
+(default) stop resolving the per-iteration BFGS gains near 1e-7 |E|; --fp64
+runs the complex128 driver (adapt64_*), which follows the paper's convergence.
+--two-param (with --fp64) takes the paper's two-parameter pool (beam splitter
+and two-mode squeezer on every pair, single-mode squeezer and rotation on
+every site, plus the Kerr-type terms where the Hamiltonian has them).
+Prints one JSON line per case.
 """
 from __future__ import annotations
 
@@ -28,34 +32,40 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 
-def fock_vector(L, d, occ):
+def fock_vector(L, d, occ, dtype="complex64"):
     import torch
 
     import workload as W
 
-    x = torch.zeros(d**L, dtype=torch.complex64)
+    x = torch.zeros(d**L, dtype=getattr(torch, dtype))
     x[W.fock_index(L, d, occ)] = 1.0
     return x.to("cuda")
 
 
-def run_case(p, E0, gates, log):
+def run_case(p, E0, gates, log, fp64=False, two_param=False):
     import workload as W
     from paper_2606_05297_amd import lib
 
     h = lib.ham(p["L"], p["d"], p["periodic"], p["J"], p["U"], p["mu"], p["Delta"], p["K"])
     wops = W.warmup_ops(p["L"], p["periodic"]) if p["warm"] else []
     wth = W.warmup_theta0(len(wops), p["warm_seed"]) if p["warm"] else np.zeros(0)
-    ad = lib.Adapt(h, p["pool"], fock_vector(p["L"], p["d"], p["occ"]), max_iters=gates, grad_tol=1e-14,
-                   warm_ops=wops, warm_theta0=wth, recycle_hessian=True)
-    dE, iters, sel = [], [], []
+    pool = p["pool2"] if two_param else p["pool"]
+    if fp64:
+        ad = lib.Adapt64(h, pool, fock_vector(p["L"], p["d"], p["occ"], dtype="complex128"), max_iters=gates,
+                         grad_tol=1e-14, recycle_hessian=True)
+    else:
+        ad = lib.Adapt(h, p["pool"], fock_vector(p["L"], p["d"], p["occ"]), max_iters=gates, grad_tol=1e-14,
+                       warm_ops=wops, warm_theta0=wth, recycle_hessian=True)
+    dE, iters, sel, npar = [], [], [], 0
     t0 = time.perf_counter()
     for k in range(gates):
         r = ad.step()
         dE.append(abs(r["E"] - E0))
         iters.append(int(r["bfgs_iters"]))
+        npar = int(r["n_params"])
         if r["k_sel"] >= 0:
-            sel.append(p["pool"][r["k_sel"]][0])
-        if log and (k + 1) % 20 == 0:
+            sel.append(pool[r["k_sel"]][0])
+        if log and (k + 1) % 5 == 0:
             log(f"{p['name']}: {k + 1} gates, dE = {dE[-1]:.3e}")
         if r["converged"] or r["capped"] or dE[-1] < 1e-10:
             break
@@ -67,8 +77,10 @@ def run_case(p, E0, gates, log):
         k = np.nonzero(dE < t * abs(E0))[0]
         return int(k[0]) + 1 if k.size else None
 
-    return {"case": p["name"], "L": p["L"], "d": p["d"], "E0": E0, "warmup_gates": len(wops),
-            "pool_size": len(p["pool"]), "gates": int(dE.size), "dE": [float(x) for x in dE],
+    return {"case": p["name"], "state": "complex128" if fp64 else "complex64", "L": p["L"], "d": p["d"], "E0": E0,
+            "warmup_gates": len(wops),
+            "pool": "two-parameter" if two_param else "one-parameter", "pool_size": len(pool), "gates": int(dE.size),
+            "params": npar, "dE": [float(x) for x in dE],
             "dE_min": float(dE.min()), "gates_to_rel_1e-3": first_below(1e-3), "gates_to_rel_1e-5": first_below(1e-5),
             "bfgs_iters": iters, "selected_types": {t: sel.count(t) for t in sorted(set(sel))}, "seconds": dt}
 
@@ -79,7 +91,12 @@ def main():
     ap.add_argument("--cases", default=None, help="comma-separated case names (default: all)")
     ap.add_argument("--ed", default=os.path.join(ROOT, "tests", "golden", "paper_cases_ed.json"))
     ap.add_argument("--out", default=None)
+    ap.add_argument("--fp64", action="store_true",
+                    help="complex128 states (adapt64_*); cases with a warm-up layer are skipped")
+    ap.add_argument("--two-param", action="store_true", help="the two-parameter pool (needs --fp64)")
     args = ap.parse_args()
+    if args.two_param and not args.fp64:
+        ap.error("--two-param needs --fp64")
     import torch
 
     import workload as W
@@ -95,7 +112,13 @@ def main():
     for p in W.paper_cases():
         if want and p["name"] not in want:
             continue
-        res = run_case(p, ed[p["name"]]["E0"], args.gates, log)
+        if args.fp64 and p["warm"]:
+            log(f"{p['name']}: skipped (the complex128 driver takes no warm-up layer)")
+            continue
+        if args.two_param and "pool2" not in p:
+            log(f"{p['name']}: skipped (no two-parameter pool)")
+            continue
+        res = run_case(p, ed[p["name"]]["E0"], args.gates, log, fp64=args.fp64, two_param=args.two_param)
         line = json.dumps(res)
         print(line, flush=True)
         lines.append(line)

@@ -11,8 +11,8 @@ from __future__ import annotations
 import numpy as np
 
 # Generator type codes (same order on every side of the boundary).
-HR, HI, DH, PR, PI, KERR, ROT, CK, SR, SI = range(10)
-TYPE_NAMES = ("HR", "HI", "DH", "PR", "PI", "KERR", "ROT", "CK", "SR", "SI")
+HR, HI, DH, PR, PI, KERR, ROT, CK, SR, SI, BS, TMS, SQ = range(13)
+TYPE_NAMES = ("HR", "HI", "DH", "PR", "PI", "KERR", "ROT", "CK", "SR", "SI", "BS", "TMS", "SQ")
 
 
 def pairs(L: int, kind: str, periodic: bool) -> list[tuple[int, int]]:
@@ -198,6 +198,11 @@ def paper_cases() -> list[dict]:
         out.append(dict(name=f"bkck_N{L}_mu-2.7", model="kk", L=L, d=6, periodic=True, J=1.0, U=0.0, mu=-2.7,
                         Delta=0.5, K=0.5, occ=[0] * L, sector=("parity", 0), warm=False, warm_seed=0,
                         pool=pool(L, "all", True, gauss + ("CK",)) + site_ops(L, ("SR", "SI", "ROT", "KERR"))))
+    # the same Kitaev pools with the paper's two-parameter gates (one BS, TMS, SQ entry per pair or site)
+    for p in out:
+        tp = ("BS", "TMS") + (("CK",) if p["K"] else ())
+        sp = ("SQ", "ROT") + (("KERR",) if p["K"] else ())
+        p["pool2"] = pool(p["L"], "all", True, tp) + site_ops(p["L"], sp)
     for lam in (4.0, -4.0):
         occ = [3, 3, 3, 3] if lam < 0 else [6, 0, 6, 0]
         out.append(dict(name=f"bh_N4_lam{lam:+g}", model="bh", L=4, d=13, periodic=True, J=1.0, U=-lam / 12.0,
