@@ -108,7 +108,8 @@ def main():
     def log(m):
         print(f"[paper_runs] {m}", file=sys.stderr, flush=True)
 
-    lines = []
+    if args.out:
+        open(args.out, "w").close()
     for p in W.paper_cases():
         if want and p["name"] not in want:
             continue
@@ -121,10 +122,9 @@ def main():
         res = run_case(p, ed[p["name"]]["E0"], args.gates, log, fp64=args.fp64, two_param=args.two_param)
         line = json.dumps(res)
         print(line, flush=True)
-        lines.append(line)
-    if args.out:
-        with open(args.out, "w") as fh:
-            fh.write("\n".join(lines) + "\n")
+        if args.out:  # one line per finished case, so a cut-off run keeps what it finished
+            with open(args.out, "a") as fh:
+                fh.write(line + "\n")
 
 
 if __name__ == "__main__":
