@@ -357,9 +357,11 @@ int fock_get_stencil_variant(void);
  * optional Hessian recycling (no noise-floor stop).  Plain kernels (one thread
  * per amplitude for H psi; one workgroup per group of fibres with a dense
  * local gate matrix of d^2 x d^2 or d x d), meant for lattices of up to ~1e6
- * amplitudes.  psi0: device, d^L complex128 (copied); opts: as adapt_create,
- * except that warm-up layers and finite-difference gradients are refused
- * (FOCK_ERR_UNSUPPORTED); gtol_floor_rel is taken as given, and its default
+ * amplitudes.  psi0: device, d^L complex128 (copied); opts: as adapt_create
+ * (a warm-up layer of one-parameter ops leads the ansatz, is BFGS-optimised
+ * here with tolerance max(warm_gtol, gtol_floor_rel max(1,|E|)) and re-optimised
+ * with every step, Appendix C), except that finite-difference gradients are
+ * refused (FOCK_ERR_UNSUPPORTED); gtol_floor_rel is taken as given, and its default
  * (1e-5, the complex64 resolution) stops BFGS once ||g||_inf < 1e-5 |E|, which
  * caps the energy error near 1e-6 |E|: complex128 runs pass ~1e-11.  The handle owns its buffers and a private stream;
  * `stream` is synchronised once at creation. */
@@ -368,6 +370,9 @@ int adapt64_create(const fock_ham_t *ham, const fock_op_t *pool, int P, const vo
                    const fock_adapt_opts_t *opts, fock_stream_t stream, fock_adapt64_t **out);
 /* One ADAPT iteration; FOCK_ERR_STATE once converged or capped. */
 int adapt64_step(fock_adapt64_t *st, fock_adapt_report_t *rep);
+/* Report of the warm-up optimisation done in adapt64_create (iter 0; without
+ * a warm-up layer: the energy of psi0, no BFGS iterations). */
+int adapt64_warm_report(fock_adapt64_t *st, fock_adapt_report_t *rep);
 /* Current ansatz as gates and gate angles (see adapt_get_ansatz); a
  * two-parameter op appears as its three gates.  The report's n_params counts
  * the logical parameters (two per two-parameter op). */
@@ -375,7 +380,7 @@ int adapt64_get_ansatz(fock_adapt64_t *st, fock_op_t *ops, double *theta, int ca
 /* E (Rayleigh quotient) and, if dEdtheta is non-NULL, all dE/dtheta_k of the
  * ansatz ops/theta (ops no wider than the pool's) on the
  * handle's psi0, by the FP64 forward pass and reverse sweep.  ops are gates
- * (no two-parameter types), n <= 3 (max_iters + 1). */
+ * (no two-parameter types), n <= n_warm + 3 (max_iters + 1). */
 int adapt64_energy_grad(fock_adapt64_t *st, const fock_op_t *ops, const double *theta, int n, double *E,
                         double *dEdtheta);
 int adapt64_destroy(fock_adapt64_t *st);

@@ -43,6 +43,7 @@ struct fock_adapt64 {
   int maxblk = 0;
   int iter = 0;
   bool done = false;
+  fock_adapt_report_t warm{};  // warm-up optimisation done at creation (iter 0)
 };
 
 namespace fock {
@@ -253,7 +254,10 @@ int adapt64_create(const fock_ham_t *ham, const fock_op_t *pool, int P, const vo
   fock_adapt_opts_t o;
   adapt_default_opts(&o);
   if (opts) o = *opts;
-  if (o.n_warm != 0) return set_error(FOCK_ERR_UNSUPPORTED, "the FP64 driver takes no warm-up layer");
+  if (o.n_warm < 0 || o.n_warm > 4096 || (o.n_warm > 0 && (!o.warm_ops || !o.warm_theta0)))
+    return set_error(FOCK_ERR_ARG, "warm-up layer arrays missing or too long");
+  for (int k = 0; k < o.n_warm; ++k)  // one-parameter generators only (check_op refuses BS, TMS, SQ)
+    if ((rc = check_op(o.warm_ops[k], ham->L))) return rc;
   if (o.grad_mode != 0) return set_error(FOCK_ERR_UNSUPPORTED, "the FP64 driver uses adjoint gradients only");
   if (o.max_iters < 0 || o.max_iters > 4000) return set_error(FOCK_ERR_ARG, "max_iters out of range");
   if (hipStreamSynchronize((hipStream_t)stream) != hipSuccess) return set_error(FOCK_ERR_HIP, "caller stream error");
@@ -265,9 +269,16 @@ int adapt64_create(const fock_ham_t *ham, const fock_op_t *pool, int P, const vo
               0.5 * ham->U + ham->K, ham->mu};
   st->pool.assign(pool, pool + P);
   st->opt = o;
-  st->cap = 3 * (o.max_iters + 1);  // gates: a two-parameter op expands to three
+  st->opt.warm_ops = nullptr;
+  st->opt.warm_theta0 = nullptr;
+  for (int k = 0; k < o.n_warm; ++k) {  // the warm-up layer leads the ansatz and is re-optimised every step
+    st->ops.push_back(o.warm_ops[k]);
+    st->theta.push_back(o.warm_theta0[k]);
+  }
+  st->cap = o.n_warm + 3 * (o.max_iters + 1);  // gates: a two-parameter op expands to three
   st->Mmax = 0;
   for (int k = 0; k < P; ++k) st->Mmax = std::max(st->Mmax, local_dim(ham->d, pool[k].type));
+  for (int k = 0; k < o.n_warm; ++k) st->Mmax = std::max(st->Mmax, local_dim(ham->d, o.warm_ops[k].type));
   // partial rows: the most workgroups of any launch (H psi, or fibres of d or d^2 amplitudes)
   st->maxblk = (int)((namp + kBlock - 1) / kBlock);
   for (int M : {ham->d, ham->d * ham->d}) {
@@ -294,7 +305,35 @@ int adapt64_create(const fock_ham_t *ham, const fock_op_t *pool, int P, const vo
   if (hipMemcpy(st->psi0, psi0, bs, hipMemcpyDeviceToDevice) != hipSuccess)
     return fail(set_error(FOCK_ERR_HIP, "copy of psi0 failed"));
   if ((rc = get_tables(ham->d, &st->T))) return fail(rc);
+  st->warm.iter = 0;
+  st->warm.k_sel = -1;
+  double E0 = 0.0, n2 = 0.0;
+  if ((rc = eval64(st, st->ops, st->theta, &E0, &n2, nullptr))) return fail(rc);
+  st->warm.E = st->warm.E_init = E0;
+  st->warm.norm2 = n2;
+  st->warm.n_params = (int)st->theta.size();
+  if (o.n_warm > 0) {
+    const double gtol = std::max(o.warm_gtol, o.gtol_floor_rel * std::max(1.0, std::fabs(E0)));
+    ObjFn fn = [st](const std::vector<double> &x, double *f, std::vector<double> *gx) {
+      return eval64(st, st->ops, x, f, nullptr, gx);
+    };
+    BfgsOut bo;
+    if ((rc = bfgs_minimize(st->theta, fn, gtol, o.bfgs_maxiter, nullptr, &bo, 0.0))) return fail(rc);
+    if ((rc = eval64(st, st->ops, st->theta, &E0, &n2, nullptr))) return fail(rc);
+    st->warm.bfgs_iters = bo.iters;
+    st->warm.bfgs_evals = bo.evals + 1;
+    st->warm.status = bo.status;
+    st->warm.E = E0;
+    st->warm.E_init = bo.f0;
+    st->warm.norm2 = n2;
+  }
   *out = st;
+  return FOCK_OK;
+}
+
+int adapt64_warm_report(fock_adapt64_t *st, fock_adapt_report_t *rep) {
+  if (!st || !rep) return set_error(FOCK_ERR_ARG, "NULL argument");
+  *rep = st->warm;
   return FOCK_OK;
 }
 

@@ -111,6 +111,7 @@ def load(path: str = LIB_PATH):
     L.adapt64_create.argtypes = [C.POINTER(Ham), C.POINTER(Op), C.c_int, vp, C.POINTER(AdaptOpts), vp,
                                  C.POINTER(vp)]
     L.adapt64_step.argtypes = [vp, C.POINTER(AdaptReport)]
+    L.adapt64_warm_report.argtypes = [vp, C.POINTER(AdaptReport)]
     L.adapt64_get_ansatz.argtypes = [vp, C.POINTER(Op), dp, C.c_int, ip]
     L.adapt64_energy_grad.argtypes = [vp, C.POINTER(Op), dp, C.c_int, dp, dp]
     L.adapt64_destroy.argtypes = [vp]
@@ -326,12 +327,12 @@ class Adapt:
 
 class Adapt64:
     """CV-ADAPT-VQE on complex128 states (adapt64_create / adapt64_step): psi0
-    is a device complex128 tensor; no warm-up layer, adjoint gradients, no
-    noise-floor stop.  The BFGS tolerance floor defaults to 1e-11 |E| (FP64
-    gradients), not the complex64 path's 1e-5 |E|."""
+    is a device complex128 tensor; optional warm-up layer of one-parameter ops,
+    adjoint gradients, no noise-floor stop.  The BFGS tolerance floor defaults
+    to 1e-11 |E| (FP64 gradients), not the complex64 path's 1e-5 |E|."""
 
     def __init__(self, h: Ham, pool, psi0, max_iters=60, grad_tol=1e-3, recycle_hessian=False, bfgs_maxiter=1000,
-                 tie_tau=1e-4, gtol_floor_rel=1e-11, stream=None):
+                 tie_tau=1e-4, gtol_floor_rel=1e-11, warm_ops=(), warm_theta0=(), warm_gtol=1e-6, stream=None):
         L = load()
         self._L = L
         o = AdaptOpts()
@@ -342,12 +343,26 @@ class Adapt64:
         o.bfgs_maxiter = int(bfgs_maxiter)
         o.tie_tau = float(tie_tau)
         o.gtol_floor_rel = float(gtol_floor_rel)
+        o.warm_gtol = float(warm_gtol)
+        self._warm = ops_array(list(warm_ops))
+        self._warm_th = np.ascontiguousarray(warm_theta0, dtype=np.float64)
+        if len(self._warm_th) != len(warm_ops):
+            raise ValueError("warm_theta0 needs one angle per warm-up op")
+        o.n_warm = len(warm_ops)
+        if len(warm_ops):
+            o.warm_ops = C.cast(self._warm, C.POINTER(Op))
+            o.warm_theta0 = self._warm_th.ctypes.data_as(C.POINTER(C.c_double))
         self.pool = list(pool)
         self._pool = ops_array(self.pool)
         self.h = h
         self._st = C.c_void_p()
         _check(L.adapt64_create(C.byref(h), self._pool, len(self.pool), _ptr(psi0), C.byref(o), _stream(stream),
                                 C.byref(self._st)))
+
+    def warm_report(self) -> dict:
+        r = AdaptReport()
+        _check(self._L.adapt64_warm_report(self._st, C.byref(r)))
+        return r.as_dict()
 
     def step(self) -> dict:
         r = AdaptReport()

@@ -1,7 +1,8 @@
 """CV-ADAPT-VQE at the paper's own parameters (Sec. V): energy error against
 exact diagonalisation as a function of the number of ADAPT gates.
 
-    python -m paper_2606_05297_amd.paper_runs [--gates 160] [--cases name,...] [--fp64 [--two-param]] [--out file]
+    python -m paper_2606_05297_amd.paper_runs [--gates 160] [--cases name,...] [--fp64 [--two-param]]
+        [--warm-seeds 0,1,...] [--out file]
 
 Cases: workload.paper_cases() (Kitaev chain N_S = 3..5 at mu = -3.1 and -2.7,
 Kitaev chain with Kerr term, Bose-Hubbard N_S = 4 with 12 bosons at
@@ -15,7 +16,9 @@ runs the complex128 driver (adapt64_*), which follows the paper's convergence.
 --two-param (with --fp64) takes the paper's two-parameter pool (beam splitter
 and two-mode squeezer on every pair, single-mode squeezer and rotation on
 every site, plus the Kerr-type terms where the Hamiltonian has them).
-Prints one JSON line per case.
+--warm-seeds 0,1,... runs each case with a warm-up layer once per seed of its
+initial warm-up angles (the paper keeps the best seed per configuration,
+Appendix C).  Prints one JSON line per run.
 """
 from __future__ import annotations
 
@@ -52,10 +55,11 @@ def run_case(p, E0, gates, log, fp64=False, two_param=False):
     pool = p["pool2"] if two_param else p["pool"]
     if fp64:
         ad = lib.Adapt64(h, pool, fock_vector(p["L"], p["d"], p["occ"], dtype="complex128"), max_iters=gates,
-                         grad_tol=1e-14, recycle_hessian=True)
+                         grad_tol=1e-14, recycle_hessian=True, warm_ops=wops, warm_theta0=wth)
     else:
         ad = lib.Adapt(h, p["pool"], fock_vector(p["L"], p["d"], p["occ"]), max_iters=gates, grad_tol=1e-14,
                        warm_ops=wops, warm_theta0=wth, recycle_hessian=True)
+    ad_warm = ad.warm_report()
     dE, iters, sel, npar = [], [], [], 0
     t0 = time.perf_counter()
     for k in range(gates):
@@ -66,7 +70,7 @@ def run_case(p, E0, gates, log, fp64=False, two_param=False):
         if r["k_sel"] >= 0:
             sel.append(pool[r["k_sel"]][0])
         if log and (k + 1) % 5 == 0:
-            log(f"{p['name']}: {k + 1} gates, dE = {dE[-1]:.3e}")
+            log(f"{p['name']} (warm-up seed {p['warm_seed']}): {k + 1} gates, dE = {dE[-1]:.3e}")
         if r["converged"] or r["capped"] or dE[-1] < 1e-10:
             break
     dt = time.perf_counter() - t0
@@ -78,7 +82,8 @@ def run_case(p, E0, gates, log, fp64=False, two_param=False):
         return int(k[0]) + 1 if k.size else None
 
     return {"case": p["name"], "state": "complex128" if fp64 else "complex64", "L": p["L"], "d": p["d"], "E0": E0,
-            "warmup_gates": len(wops),
+            "warmup_gates": len(wops), "warm_seed": p["warm_seed"] if p["warm"] else None,
+            "E_after_warmup": float(ad_warm["E"]),
             "pool": "two-parameter" if two_param else "one-parameter", "pool_size": len(pool), "gates": int(dE.size),
             "params": npar, "dE": [float(x) for x in dE],
             "dE_min": float(dE.min()), "gates_to_rel_1e-3": first_below(1e-3), "gates_to_rel_1e-5": first_below(1e-5),
@@ -92,8 +97,11 @@ def main():
     ap.add_argument("--ed", default=os.path.join(ROOT, "tests", "golden", "paper_cases_ed.json"))
     ap.add_argument("--out", default=None)
     ap.add_argument("--fp64", action="store_true",
-                    help="complex128 states (adapt64_*); cases with a warm-up layer are skipped")
+                    help="complex128 states (adapt64_*)")
     ap.add_argument("--two-param", action="store_true", help="the two-parameter pool (needs --fp64)")
+    ap.add_argument("--warm-seeds", default=None,
+                    help="comma-separated seeds of the warm-up angles, one run each (cases with a warm-up layer; "
+                         "default: the case's own seed)")
     args = ap.parse_args()
     if args.two_param and not args.fp64:
         ap.error("--two-param needs --fp64")
@@ -113,18 +121,20 @@ def main():
     for p in W.paper_cases():
         if want and p["name"] not in want:
             continue
-        if args.fp64 and p["warm"]:
-            log(f"{p['name']}: skipped (the complex128 driver takes no warm-up layer)")
-            continue
         if args.two_param and "pool2" not in p:
             log(f"{p['name']}: skipped (no two-parameter pool)")
             continue
-        res = run_case(p, ed[p["name"]]["E0"], args.gates, log, fp64=args.fp64, two_param=args.two_param)
-        line = json.dumps(res)
-        print(line, flush=True)
-        if args.out:  # one line per finished case, so a cut-off run keeps what it finished
-            with open(args.out, "a") as fh:
-                fh.write(line + "\n")
+        seeds = [p["warm_seed"]]
+        if p["warm"] and args.warm_seeds:
+            seeds = [int(x) for x in args.warm_seeds.split(",")]
+        for seed in seeds:
+            q = dict(p, warm_seed=seed)
+            res = run_case(q, ed[p["name"]]["E0"], args.gates, log, fp64=args.fp64, two_param=args.two_param)
+            line = json.dumps(res)
+            print(line, flush=True)
+            if args.out:  # one line per finished run, so a cut-off call keeps what it finished
+                with open(args.out, "a") as fh:
+                    fh.write(line + "\n")
 
 
 if __name__ == "__main__":

@@ -170,3 +170,46 @@ def test_fp64_adapt_two_parameter_pool_replay():
     ad.close()
     assert all(b <= a + 1e-12 for a, b in zip(dE, dE[1:]))
     assert dE[-1] < 2.7e-4
+
+
+def test_fp64_warmup_layer_bose_hubbard_replay():
+    """The paper's attractive Bose-Hubbard ring (N_S = 4, 12 bosons, d = 13,
+    Lambda = +4, start |6,0,6,0>) with the HVA warm-up layer: the warm-up
+    optimisation's energy equals the oracle's on the optimised layer and the
+    complex64 driver's (same seed) to its precision; every checked step equals
+    the oracle's replay of the GPU's ansatz (warm-up layer first); the energy
+    never rises."""
+    p = [c for c in W.paper_cases() if c["name"] == "bh_N4_lam+4"][0]
+    ho = O.Ham(p["L"], p["d"], p["periodic"], p["J"], p["U"], p["mu"], p["Delta"], p["K"])
+    hl = lib.ham(p["L"], p["d"], p["periodic"], p["J"], p["U"], p["mu"], p["Delta"], p["K"])
+    psi0 = O.fock_state(p["L"], p["d"], p["occ"])
+    wops = W.warmup_ops(p["L"], p["periodic"])
+    wth = W.warmup_theta0(len(wops), 0)
+    say("fp64 warm-up layer", p["name"], len(wops))
+    ad = lib.Adapt64(hl, p["pool"], dev128(psi0), max_iters=12, grad_tol=1e-14, recycle_hessian=True,
+                     warm_ops=wops, warm_theta0=wth)
+    w = ad.warm_report()
+    ops, th = ad.ansatz()
+    assert ops == wops and w["bfgs_iters"] > 0
+    Eo = O.energy_of(ho, psi0, ops, th)
+    assert abs(w["E"] - Eo) <= 1e-11 * abs(Eo), (w["E"], Eo)
+    assert w["E"] <= w["E_init"]
+    a32 = lib.Adapt(hl, p["pool"], dev128(psi0).to(torch.complex64), max_iters=2, warm_ops=wops, warm_theta0=wth)
+    w32 = a32.warm_report()
+    a32.close()
+    say("warm-up E fp64", w["E"], "complex64", w32["E"])
+    assert abs(w["E"] - w32["E"]) <= 1e-4 * abs(w["E"])
+    Es = [w["E"]]
+    for k in range(12):
+        r = ad.step()
+        Es.append(r["E"])
+        if (k + 1) % 4 == 0:
+            ops, th = ad.ansatz()
+            assert ops[: len(wops)] == wops and len(ops) == len(wops) + k + 1
+            Eo = O.energy_of(ho, psi0, ops, th)
+            assert abs(r["E"] - Eo) <= 1e-10 * abs(Eo), (k, r["E"], Eo)
+            say("gate", k + 1, "E", r["E"])
+        if r["converged"] or r["capped"]:
+            break
+    ad.close()
+    assert all(b <= a + 1e-9 for a, b in zip(Es, Es[1:]))

@@ -52,12 +52,14 @@ KITAEV_TYPES = ("HR", "HI", "PI", "PR")
 
 
 def warmup_ops(L: int, periodic: bool) -> list[tuple[str, int, int]]:
-    """One Hamiltonian-variational layer for the Bose-Hubbard chain: a hopping
-    rotation on every bond, then a Kerr phase and a rotation on every site."""
+    """One Hamiltonian-variational layer for the Bose-Hubbard chain, built from
+    exp(-i theta H_k) of the Hamiltonian's own terms (Sec. IV.A): the hopping
+    term's generator i(a_i^+ a_j + h.c.) (HI) on every bond, then a Kerr phase
+    and a rotation on every site (the on-site interaction and number terms)."""
     bl = [(r, r + 1) for r in range(L - 1)]
     if periodic and L >= 3:
         bl.append((0, L - 1))
-    ops = [("HR", i, j) for (i, j) in bl]
+    ops = [("HI", i, j) for (i, j) in bl]
     ops += [("KERR", r, -1) for r in range(L)]
     ops += [("ROT", r, -1) for r in range(L)]
     return ops
