@@ -9,7 +9,10 @@ angles with energy + adjoint-gradient evaluations (gate build, forward gates,
 H psi, fused reverse sweep).  W warm-up steps run on a separate ADAPT instance;
 the K timed steps are steps 1..K of a fresh run from the vacuum.  Per-kernel
 durations come from HIP events recorded on the launch stream inside the timed
-region; the roofline entry is the kernel with the largest total time.  BFGS
+region, around one launch in --prof-sample (default 4) of each kernel family:
+two event records per timed launch lengthen the gap to the next kernel, and
+timing every launch costs about 9% of the step rate.  The roofline entry is
+the kernel with the largest total time.  BFGS
 starts every step from the previous step's inverse Hessian, padded with the
 identity for the new angle (Appendix D); --no-hessian-recycling starts from
 the scaled identity.  After the timed region, "variants" reports the same
@@ -90,6 +93,8 @@ def main():
     ap.add_argument("--no-hessian-recycling", action="store_true",
                     help="start every BFGS from the scaled identity instead of the previous inverse Hessian")
     ap.add_argument("--no-variants", action="store_true", help="skip the FD-gradient and Hessian-recycling lines")
+    ap.add_argument("--prof-sample", type=int, default=4,
+                    help="time one launch in this many per kernel family with HIP events (1: every launch)")
     ap.add_argument("--gate-fusion", type=int, choices=[0, 1, 2], default=None,
                     help="0 per-gate passes (library default), 1 fused forward circuit, 2 fused forward and adjoint")
     args = ap.parse_args()
@@ -121,6 +126,7 @@ def main():
             ad.step()
         ad.close()
     ad = lib.Adapt(hl, cfg["pool"], psi0, max_iters=cfg["max_iters"], grad_mode=gm, recycle_hessian=rh)
+    lib.prof_set_sample(args.prof_sample)
     lib.prof_reset()
     lib.prof_enable(True)
     torch.cuda.synchronize()
@@ -148,6 +154,7 @@ def main():
         gbs = per_launch_bytes / (avg_ms * 1e-3) / 1e9
         return {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS,
                 "traffic": traffic_for(kid), "kernel": KERNEL_NAMES[kid], "launches": p["launches"],
+                "event_sample": args.prof_sample,
                 "avg_us": avg_ms * 1e3, "algorithmic_bytes_per_launch": per_launch_bytes,
                 "total_ms": p["ms"]}
 

@@ -428,8 +428,14 @@ int fock_mlp_destroy(fock_mlp_t *net);
 enum { FOCK_K_APPLY_H = 0, FOCK_K_POOL = 1, FOCK_K_GATE = 2, FOCK_K_ADJ = 3, FOCK_K_DIAG = 4,
        FOCK_K_REDUCE = 5, FOCK_K_MLP_FWD = 6, FOCK_K_MLP_TRAIN = 7, FOCK_K_GATE_DENSE = 8, FOCK_K_NUM = 9 };
 
-/* Enable/disable event timing of every launch (off by default). */
+/* Enable/disable event timing of launches (off by default). */
 int fock_prof_enable(int on);
+/* Time only every `every`-th launch of each kernel id (1, the default: every
+ * launch).  Each timed launch is bracketed by two event records on its
+ * stream, which lengthen the gaps between dependent kernels; sampling keeps
+ * that cost off the untimed launches.  Counting restarts at fock_prof_reset.
+ * FOCK_ERR_ARG for every < 1; process-wide. */
+int fock_prof_set_sample(int every);
 /* Launch count, summed duration (ms) and summed algorithmic bytes (FLOPs for
  * the two network kernels) of kernel id
  * since the last reset (completed launches only; call after a synchronise). */

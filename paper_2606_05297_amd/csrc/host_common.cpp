@@ -426,6 +426,8 @@ struct Pending {
 };
 static std::mutex g_prof_mu;
 static bool g_prof_on = false;
+static int g_prof_every = 1;              // time one launch in g_prof_every per kernel id
+static int64_t g_prof_seen[FOCK_K_NUM];   // launches seen per kernel id while enabled
 static ProfAcc g_prof[FOCK_K_NUM];
 static std::vector<Pending> g_pending;
 static std::vector<hipEvent_t> g_event_pool;
@@ -444,6 +446,7 @@ static hipEvent_t take_event() {
 ProfScope::ProfScope(int id_, hipStream_t s_, double bytes_) : id(id_), s(s_), bytes(bytes_) {
   std::lock_guard<std::mutex> lk(g_prof_mu);
   if (!g_prof_on) return;
+  if (id >= 0 && id < FOCK_K_NUM && (g_prof_seen[id]++ % g_prof_every) != 0) return;
   e0 = take_event();
   e1 = take_event();
   if (e0) hipEventRecord(e0, s);
@@ -488,6 +491,13 @@ int fock_prof_enable(int on) {
   return FOCK_OK;
 }
 
+int fock_prof_set_sample(int every) {
+  if (every < 1) return fock::set_error(FOCK_ERR_ARG, "sampling interval %d < 1", every);
+  std::lock_guard<std::mutex> lk(fock::g_prof_mu);
+  fock::g_prof_every = every;
+  return FOCK_OK;
+}
+
 int fock_prof_query(int id, int64_t *launches, double *total_ms, double *bytes) {
   if (id < 0 || id >= FOCK_K_NUM) return fock::set_error(FOCK_ERR_ARG, "kernel id %d out of range", id);
   fock::prof_harvest();
@@ -502,6 +512,7 @@ int fock_prof_reset(void) {
   fock::prof_harvest();
   std::lock_guard<std::mutex> lk(fock::g_prof_mu);
   for (auto &p : fock::g_prof) p = fock::ProfAcc();
+  for (auto &n : fock::g_prof_seen) n = 0;
   return FOCK_OK;
 }
 

@@ -128,6 +128,7 @@ def load(path: str = LIB_PATH):
     L.fock_prof_enable.argtypes = [C.c_int]
     L.fock_prof_query.argtypes = [C.c_int, C.POINTER(C.c_int64), dp, dp]
     L.fock_prof_reset.argtypes = []
+    L.fock_prof_set_sample.argtypes = [C.c_int]
     _lib = L
     return L
 
@@ -650,6 +651,11 @@ def prof_enable(on=True):
 
 def prof_reset():
     _check(load().fock_prof_reset())
+
+
+def prof_set_sample(every: int):
+    """Time one launch in `every` per kernel id (1: every launch)."""
+    _check(load().fock_prof_set_sample(int(every)))
 
 
 def prof_query(kid: int) -> dict:

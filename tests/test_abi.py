@@ -187,6 +187,18 @@ def test_stencil_variant_setter():
         lib.set_stencil_variant(prev)
 
 
+def test_prof_sample_setter():
+    """Event-timing sampling interval: positive values accepted, zero and
+    negative rejected; no launch is timed while profiling is off."""
+    for v in (4, 1):
+        lib.prof_set_sample(v)
+    for v in (0, -3):
+        with pytest.raises(lib.FockError):
+            lib.prof_set_sample(v)
+    lib.prof_reset()
+    assert lib.prof_query(0)["launches"] == 0
+
+
 def test_mfma_operand_overlap_check():
     """The build rejects matrix instructions whose destination partially
     overlaps the accumulator input (identical or disjoint ranges are fine)."""
