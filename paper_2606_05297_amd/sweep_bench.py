@@ -62,6 +62,9 @@ def main():
             r = a.step()
             E_seq[k, s] = r["E"]
             steps_seq += 1
+            if r["converged"] or r["capped"]:  # finished: its energy stays
+                E_seq[k, s + 1:] = r["E"]
+                break
     torch.cuda.synchronize()
     t_seq = time.perf_counter() - t0
     for a in singles:
@@ -76,11 +79,17 @@ def main():
     E_bat = np.zeros((len(pts), K))
     steps_bat = 0
     t0 = time.perf_counter()
+    done = np.zeros(len(pts), dtype=bool)
     for s in range(K):
+        if done.all():
+            break
         reps, na = sw.step()
         steps_bat += na
         for k in range(len(pts)):
-            E_bat[k, s] = reps[k]["E"]
+            if done[k]:
+                continue
+            E_bat[k, s:] = reps[k]["E"]
+            done[k] = bool(reps[k]["converged"] or reps[k]["capped"])
     torch.cuda.synchronize()
     t_bat = time.perf_counter() - t0
     sw.close()
@@ -88,7 +97,7 @@ def main():
     out = {"points": len(pts), "amplitudes": amps, "steps": K, "sequential_point_steps_per_s": steps_seq / t_seq,
            "batched_point_steps_per_s": steps_bat / t_bat, "speedup": (steps_bat / t_bat) / (steps_seq / t_seq),
            "bitwise_equal": bool(np.array_equal(E_seq, E_bat)), "autotuned_grid": grid,
-           "max_abs_dE": float(np.abs(E_seq - E_bat).max())}
+           "max_abs_dE": float(np.abs(E_seq - E_bat).max()), "points_finished_early": int(done.sum())}
     print(json.dumps(out), flush=True)
 
 
