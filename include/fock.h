@@ -155,7 +155,8 @@ typedef struct {
   const double *warm_theta0;    /* host, n_warm initial angles, copied at create */
   double fd_step;         /* finite-difference step for grad_mode 1 */
   int32_t recycle_hessian;/* 1: seed each BFGS with the previous inverse Hessian (Appendix D) */
-  int32_t reserved;
+  int32_t warm_fixed;     /* 1: the warm-up angles stay at warm_theta0 (never optimised; Appendix D's
+                             fixed warm-up); complex128 driver only, 0 elsewhere */
   double noise_rel;       /* BFGS also stops once the predicted decrease < noise_rel*max(1,|E|) (FP32 noise),
                              from its second iteration on */
 } fock_adapt_opts_t;
@@ -360,7 +361,8 @@ int fock_get_stencil_variant(void);
  * amplitudes.  psi0: device, d^L complex128 (copied); opts: as adapt_create
  * (a warm-up layer of one-parameter ops leads the ansatz, is BFGS-optimised
  * here with tolerance max(warm_gtol, gtol_floor_rel max(1,|E|)) and re-optimised
- * with every step, Appendix C), except that finite-difference gradients are
+ * with every step, Appendix C; with warm_fixed its angles stay at warm_theta0
+ * and BFGS runs over the other angles only, Appendix D), except that finite-difference gradients are
  * refused (FOCK_ERR_UNSUPPORTED); gtol_floor_rel is taken as given, and its default
  * (1e-5, the complex64 resolution) stops BFGS once ||g||_inf < 1e-5 |E|, which
  * caps the energy error near 1e-6 |E|: complex128 runs pass ~1e-11.  The handle owns its buffers and a private stream;

@@ -134,6 +134,8 @@ int adapt_create(const fock_ham_t *ham, const fock_op_t *pool, int P, const void
   if ((rc = check_ptr(psi0, "psi0"))) return rc;
   for (int k = 0; k < P; ++k)
     if ((rc = check_op(pool[k], ham->L))) return rc;
+  if (opts->warm_fixed != 0)
+    return set_error(FOCK_ERR_UNSUPPORTED, "fixed warm-up angles are taken by the complex128 driver only");
   if (opts->n_warm < 0 || (opts->n_warm > 0 && (!opts->warm_ops || !opts->warm_theta0)))
     return set_error(FOCK_ERR_ARG, "warm-up layer arrays missing");
   for (int k = 0; k < opts->n_warm; ++k)

@@ -312,7 +312,7 @@ int adapt64_create(const fock_ham_t *ham, const fock_op_t *pool, int P, const vo
   st->warm.E = st->warm.E_init = E0;
   st->warm.norm2 = n2;
   st->warm.n_params = (int)st->theta.size();
-  if (o.n_warm > 0) {
+  if (o.n_warm > 0 && !o.warm_fixed) {
     const double gtol = std::max(o.warm_gtol, o.gtol_floor_rel * std::max(1.0, std::fabs(E0)));
     ObjFn fn = [st](const std::vector<double> &x, double *f, std::vector<double> *gx) {
       return eval64(st, st->ops, x, f, nullptr, gx);
@@ -385,32 +385,41 @@ int adapt64_step(fock_adapt64_t *st, fock_adapt_report_t *rep) {
   const int added = two_param(st->pool[ks].type) ? 2 : 1;
   for (int k = 0; k < added; ++k) st->theta.push_back(0.0);
   const int n = (int)st->theta.size();
+  // BFGS runs over the free angles: all but a fixed warm-up layer's
+  const int nf = st->opt.warm_fixed ? st->opt.n_warm : 0, nx = n - nf;
   std::vector<double> *H = nullptr;
   if (st->opt.recycle_hessian) {
     const int m = (int)std::lround(std::sqrt((double)st->Hinv.size()));
-    std::vector<double> Hn((size_t)n * n, 0.0);
-    for (int r = 0; r < n; ++r) Hn[(size_t)r * n + r] = 1.0;
-    if (m == n - added)
+    std::vector<double> Hn((size_t)nx * nx, 0.0);
+    for (int r = 0; r < nx; ++r) Hn[(size_t)r * nx + r] = 1.0;
+    if (m == nx - added)
       for (int r = 0; r < m; ++r)
-        for (int c = 0; c < m; ++c) Hn[(size_t)r * n + c] = st->Hinv[(size_t)r * m + c];
+        for (int c = 0; c < m; ++c) Hn[(size_t)r * nx + c] = st->Hinv[(size_t)r * m + c];
     st->Hinv.swap(Hn);
     H = &st->Hinv;
   }
   const double gtol = std::max(std::min(1e-6, 1e-5 * rep->g_sel), st->opt.gtol_floor_rel * std::max(1.0, std::fabs(E)));
-  ObjFn fn = [st](const std::vector<double> &x, double *f, std::vector<double> *gx) {
-    return eval64(st, st->ops, x, f, nullptr, gx);
+  ObjFn fn = [st, nf](const std::vector<double> &x, double *f, std::vector<double> *gx) {
+    if (nf == 0) return eval64(st, st->ops, x, f, nullptr, gx);
+    std::vector<double> full(st->theta.begin(), st->theta.begin() + nf), g;
+    full.insert(full.end(), x.begin(), x.end());
+    const int r = eval64(st, st->ops, full, f, nullptr, gx ? &g : nullptr);
+    if (!r && gx) gx->assign(g.begin() + nf, g.end());
+    return r;
   };
+  std::vector<double> x(st->theta.begin() + nf, st->theta.end());
   BfgsOut bo;
-  rc = bfgs_minimize(st->theta, fn, gtol, st->opt.bfgs_maxiter, H, &bo, 0.0);
+  rc = bfgs_minimize(x, fn, gtol, st->opt.bfgs_maxiter, H, &bo, 0.0);
   if (rc) return rc;
-  double Ef = 0.0, nf = 0.0;
-  rc = eval64(st, st->ops, st->theta, &Ef, &nf, nullptr);
+  std::copy(x.begin(), x.end(), st->theta.begin() + nf);
+  double Ef = 0.0, n2f = 0.0;
+  rc = eval64(st, st->ops, st->theta, &Ef, &n2f, nullptr);
   if (rc) return rc;
   rep->bfgs_iters = bo.iters;
   rep->bfgs_evals = bo.evals + 1;
   rep->status = bo.status;
   rep->E = Ef;
-  rep->norm2 = nf;
+  rep->norm2 = n2f;
   rep->E_init = bo.f0;
   rep->n_params = n;
   return FOCK_OK;

@@ -536,6 +536,8 @@ int fock_sweep_create(const fock_sweep_point_t *pts, int npts, const fock_adapt_
   *out = nullptr;
   if (!pts || npts < 1 || npts > 4096) return set_error(FOCK_ERR_ARG, "npts must be in [1, 4096]");
   if (!opts) return set_error(FOCK_ERR_ARG, "opts is NULL");
+  if (opts->warm_fixed != 0)
+    return set_error(FOCK_ERR_UNSUPPORTED, "fixed warm-up angles are taken by the complex128 driver only");
   int rc = 0;
   for (int p = 0; p < npts; ++p) {
     uint32_t namp = 0;

@@ -39,7 +39,7 @@ class AdaptOpts(C.Structure):
                 ("tie_tau", C.c_double), ("gtol_floor_rel", C.c_double), ("warm_gtol", C.c_double),
                 ("n_warm", C.c_int32), ("grad_mode", C.c_int32), ("warm_ops", C.POINTER(Op)),
                 ("warm_theta0", C.POINTER(C.c_double)), ("fd_step", C.c_double),
-                ("recycle_hessian", C.c_int32), ("reserved", C.c_int32), ("noise_rel", C.c_double)]
+                ("recycle_hessian", C.c_int32), ("warm_fixed", C.c_int32), ("noise_rel", C.c_double)]
 
 
 class AdaptReport(C.Structure):
@@ -328,12 +328,14 @@ class Adapt:
 
 class Adapt64:
     """CV-ADAPT-VQE on complex128 states (adapt64_create / adapt64_step): psi0
-    is a device complex128 tensor; optional warm-up layer of one-parameter ops,
-    adjoint gradients, no noise-floor stop.  The BFGS tolerance floor defaults
+    is a device complex128 tensor; optional warm-up layer of one-parameter ops
+    (optimised, or with warm_fixed kept at warm_theta0), adjoint gradients, no
+    noise-floor stop.  The BFGS tolerance floor defaults
     to 1e-11 |E| (FP64 gradients), not the complex64 path's 1e-5 |E|."""
 
     def __init__(self, h: Ham, pool, psi0, max_iters=60, grad_tol=1e-3, recycle_hessian=False, bfgs_maxiter=1000,
-                 tie_tau=1e-4, gtol_floor_rel=1e-11, warm_ops=(), warm_theta0=(), warm_gtol=1e-6, stream=None):
+                 tie_tau=1e-4, gtol_floor_rel=1e-11, warm_ops=(), warm_theta0=(), warm_gtol=1e-6, warm_fixed=False,
+                 stream=None):
         L = load()
         self._L = L
         o = AdaptOpts()
@@ -345,6 +347,7 @@ class Adapt64:
         o.tie_tau = float(tie_tau)
         o.gtol_floor_rel = float(gtol_floor_rel)
         o.warm_gtol = float(warm_gtol)
+        o.warm_fixed = int(bool(warm_fixed))
         self._warm = ops_array(list(warm_ops))
         self._warm_th = np.ascontiguousarray(warm_theta0, dtype=np.float64)
         if len(self._warm_th) != len(warm_ops):

@@ -2,7 +2,7 @@
 exact diagonalisation as a function of the number of ADAPT gates.
 
     python -m paper_2606_05297_amd.paper_runs [--gates 160] [--cases name,...] [--fp64 [--two-param]]
-        [--warm-seeds 0,1,...] [--out file]
+        [--warm-seeds 0,1,...] [--warm-fixed] [--out file]
 
 Cases: workload.paper_cases() (Kitaev chain N_S = 3..5 at mu = -3.1 and -2.7,
 Kitaev chain with Kerr term, Bose-Hubbard N_S = 4 with 12 bosons at
@@ -18,7 +18,8 @@ and two-mode squeezer on every pair, single-mode squeezer and rotation on
 every site, plus the Kerr-type terms where the Hamiltonian has them).
 --warm-seeds 0,1,... runs each case with a warm-up layer once per seed of its
 initial warm-up angles (the paper keeps the best seed per configuration,
-Appendix C).  Prints one JSON line per run.
+Appendix C); --warm-fixed (with --fp64) keeps those angles fixed instead of
+optimising them (Appendix D compares both).  Prints one JSON line per run.
 """
 from __future__ import annotations
 
@@ -45,7 +46,7 @@ def fock_vector(L, d, occ, dtype="complex64"):
     return x.to("cuda")
 
 
-def run_case(p, E0, gates, log, fp64=False, two_param=False):
+def run_case(p, E0, gates, log, fp64=False, two_param=False, warm_fixed=False):
     import workload as W
     from paper_2606_05297_amd import lib
 
@@ -55,7 +56,8 @@ def run_case(p, E0, gates, log, fp64=False, two_param=False):
     pool = p["pool2"] if two_param else p["pool"]
     if fp64:
         ad = lib.Adapt64(h, pool, fock_vector(p["L"], p["d"], p["occ"], dtype="complex128"), max_iters=gates,
-                         grad_tol=1e-14, recycle_hessian=True, warm_ops=wops, warm_theta0=wth)
+                         grad_tol=1e-14, recycle_hessian=True, warm_ops=wops, warm_theta0=wth,
+                         warm_fixed=warm_fixed and bool(wops))
     else:
         ad = lib.Adapt(h, p["pool"], fock_vector(p["L"], p["d"], p["occ"]), max_iters=gates, grad_tol=1e-14,
                        warm_ops=wops, warm_theta0=wth, recycle_hessian=True)
@@ -83,6 +85,7 @@ def run_case(p, E0, gates, log, fp64=False, two_param=False):
 
     return {"case": p["name"], "state": "complex128" if fp64 else "complex64", "L": p["L"], "d": p["d"], "E0": E0,
             "warmup_gates": len(wops), "warm_seed": p["warm_seed"] if p["warm"] else None,
+            "warmup": ("fixed" if warm_fixed else "optimised") if wops else None,
             "E_after_warmup": float(ad_warm["E"]),
             "pool": "two-parameter" if two_param else "one-parameter", "pool_size": len(pool), "gates": int(dE.size),
             "params": npar, "dE": [float(x) for x in dE],
@@ -99,12 +102,14 @@ def main():
     ap.add_argument("--fp64", action="store_true",
                     help="complex128 states (adapt64_*)")
     ap.add_argument("--two-param", action="store_true", help="the two-parameter pool (needs --fp64)")
+    ap.add_argument("--warm-fixed", action="store_true",
+                    help="keep the warm-up angles at their seeded initial values (needs --fp64)")
     ap.add_argument("--warm-seeds", default=None,
                     help="comma-separated seeds of the warm-up angles, one run each (cases with a warm-up layer; "
                          "default: the case's own seed)")
     args = ap.parse_args()
-    if args.two_param and not args.fp64:
-        ap.error("--two-param needs --fp64")
+    if (args.two_param or args.warm_fixed) and not args.fp64:
+        ap.error("--two-param and --warm-fixed need --fp64")
     import torch
 
     import workload as W
@@ -129,7 +134,8 @@ def main():
             seeds = [int(x) for x in args.warm_seeds.split(",")]
         for seed in seeds:
             q = dict(p, warm_seed=seed)
-            res = run_case(q, ed[p["name"]]["E0"], args.gates, log, fp64=args.fp64, two_param=args.two_param)
+            res = run_case(q, ed[p["name"]]["E0"], args.gates, log, fp64=args.fp64, two_param=args.two_param,
+                           warm_fixed=args.warm_fixed)
             line = json.dumps(res)
             print(line, flush=True)
             if args.out:  # one line per finished run, so a cut-off call keeps what it finished

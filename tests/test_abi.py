@@ -104,6 +104,10 @@ def test_adapt_create_validation():
     o.n_warm = 2  # arrays missing
     assert L.adapt_create(C.byref(h), lib.ops_array([("HR", 0, 1)]), 1, C.c_void_p(1 << 20), C.byref(o), None,
                           C.byref(st)) == -1
+    o.n_warm = 0
+    o.warm_fixed = 1  # fixed warm-up angles: the complex128 driver only
+    assert L.adapt_create(C.byref(h), lib.ops_array([("HR", 0, 1)]), 1, C.c_void_p(1 << 20), C.byref(o), None,
+                          C.byref(st)) == -3
     assert not st.value
 
 
