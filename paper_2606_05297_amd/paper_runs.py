@@ -2,13 +2,14 @@
 exact diagonalisation as a function of the number of ADAPT gates.
 
     python -m paper_2606_05297_amd.paper_runs [--gates 160] [--cases name,...] [--fp64 [--two-param]]
-        [--warm-seeds 0,1,...] [--warm-fixed] [--out file]
+        [--warm-seeds 0,1,...] [--warm-fixed] [--no-hessian-recycling] [--out file]
 
 Cases: workload.paper_cases() (Kitaev chain N_S = 3..5 at mu = -3.1 and -2.7,
 Kitaev chain with Kerr term, Bose-Hubbard N_S = 4 with 12 bosons at
 Lambda = +-4).  Each run appends operators until `gates` have been added or
 the energy error drops below 1e-10 (the paper's stopping rule; the gradient
-threshold is disabled), with the inverse Hessian recycled across steps.
+threshold is disabled), with the inverse Hessian recycled across steps
+(--no-hessian-recycling: every BFGS starts from the identity).
 Exact ground energies: tests/golden/paper_cases_ed.json (written from the FP64
 oracle by tests/golden/make_ed_reference.py --paper-cases).  complex64 states
 (default) stop resolving the per-iteration BFGS gains near 1e-7 |E|; --fp64
@@ -46,7 +47,7 @@ def fock_vector(L, d, occ, dtype="complex64"):
     return x.to("cuda")
 
 
-def run_case(p, E0, gates, log, fp64=False, two_param=False, warm_fixed=False):
+def run_case(p, E0, gates, log, fp64=False, two_param=False, warm_fixed=False, recycle=True):
     import workload as W
     from paper_2606_05297_amd import lib
 
@@ -56,11 +57,11 @@ def run_case(p, E0, gates, log, fp64=False, two_param=False, warm_fixed=False):
     pool = p["pool2"] if two_param else p["pool"]
     if fp64:
         ad = lib.Adapt64(h, pool, fock_vector(p["L"], p["d"], p["occ"], dtype="complex128"), max_iters=gates,
-                         grad_tol=1e-14, recycle_hessian=True, warm_ops=wops, warm_theta0=wth,
+                         grad_tol=1e-14, recycle_hessian=recycle, warm_ops=wops, warm_theta0=wth,
                          warm_fixed=warm_fixed and bool(wops))
     else:
         ad = lib.Adapt(h, p["pool"], fock_vector(p["L"], p["d"], p["occ"]), max_iters=gates, grad_tol=1e-14,
-                       warm_ops=wops, warm_theta0=wth, recycle_hessian=True)
+                       warm_ops=wops, warm_theta0=wth, recycle_hessian=recycle)
     ad_warm = ad.warm_report()
     dE, iters, sel, npar = [], [], [], 0
     t0 = time.perf_counter()
@@ -85,7 +86,7 @@ def run_case(p, E0, gates, log, fp64=False, two_param=False, warm_fixed=False):
 
     return {"case": p["name"], "state": "complex128" if fp64 else "complex64", "L": p["L"], "d": p["d"], "E0": E0,
             "warmup_gates": len(wops), "warm_seed": p["warm_seed"] if p["warm"] else None,
-            "warmup": ("fixed" if warm_fixed else "optimised") if wops else None,
+            "warmup": ("fixed" if warm_fixed else "optimised") if wops else None, "hessian_recycling": recycle,
             "E_after_warmup": float(ad_warm["E"]),
             "pool": "two-parameter" if two_param else "one-parameter", "pool_size": len(pool), "gates": int(dE.size),
             "params": npar, "dE": [float(x) for x in dE],
@@ -104,6 +105,8 @@ def main():
     ap.add_argument("--two-param", action="store_true", help="the two-parameter pool (needs --fp64)")
     ap.add_argument("--warm-fixed", action="store_true",
                     help="keep the warm-up angles at their seeded initial values (needs --fp64)")
+    ap.add_argument("--no-hessian-recycling", action="store_true",
+                    help="start every BFGS from the identity instead of the previous inverse Hessian")
     ap.add_argument("--warm-seeds", default=None,
                     help="comma-separated seeds of the warm-up angles, one run each (cases with a warm-up layer; "
                          "default: the case's own seed)")
@@ -135,7 +138,7 @@ def main():
         for seed in seeds:
             q = dict(p, warm_seed=seed)
             res = run_case(q, ed[p["name"]]["E0"], args.gates, log, fp64=args.fp64, two_param=args.two_param,
-                           warm_fixed=args.warm_fixed)
+                           warm_fixed=args.warm_fixed, recycle=not args.no_hessian_recycling)
             line = json.dumps(res)
             print(line, flush=True)
             if args.out:  # one line per finished run, so a cut-off call keeps what it finished
