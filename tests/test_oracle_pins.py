@@ -387,3 +387,36 @@ def test_product_state_oracle_functions():
             out = O.apply_gate(op, 0.37, psi, L, d)
             for k in range(d**L):
                 assert abs(O.product_gate_at(op, 0.37, fac, L, d, k) - out[k]) < 1e-12
+
+
+@pytest.mark.parametrize("t", ["BS", "TMS", "SQ"])
+def test_two_parameter_gates_are_rotation_conjugated_fixed_phase_gates(t):
+    """The paper's two-parameter gates (Sec. II.B), built directly as
+    exp(theta A(phi)), equal the phi = 0 gate conjugated by phase rotations
+    R(a) = exp(i a N): BS(theta, phi) = R_2(phi) exp(-theta HR) R_2(-phi),
+    S2(theta, phi) = R_2(-phi) exp(theta PR) R_2(phi) and
+    S(theta, phi) = R(phi/2) exp(theta SR) R(-phi/2), on the truncated space,
+    for several angles (a wrong sign of phi, a missing factor 1/2 or a
+    transposed mode order fails)."""
+    import scipy.linalg
+
+    d = 5
+    a = O.ladder(d)
+    ad = a.T
+    I = np.eye(d)
+    rng = np.random.default_rng(7)
+    for _ in range(4):
+        th, ph = rng.uniform(-1.5, 1.5, 2)
+        if t == "BS":
+            A = np.exp(1j * ph) * np.kron(a, ad) - np.exp(-1j * ph) * np.kron(ad, a)
+            R = lambda x: np.kron(I, O.gate_local("ROT", d, x))  # noqa: E731  (rotation of mode 2)
+            M = R(ph) @ O.gate_local("HR", d, -th) @ R(-ph)
+        elif t == "TMS":
+            A = np.exp(1j * ph) * np.kron(a, a) - np.exp(-1j * ph) * np.kron(ad, ad)
+            R = lambda x: np.kron(I, O.gate_local("ROT", d, x))  # noqa: E731
+            M = R(-ph) @ O.gate_local("PR", d, th) @ R(ph)
+        else:
+            A = 0.5 * (np.exp(-1j * ph) * a @ a - np.exp(1j * ph) * ad @ ad)
+            M = O.gate_local("ROT", d, ph / 2) @ O.gate_local("SR", d, th) @ O.gate_local("ROT", d, -ph / 2)
+        U = scipy.linalg.expm(th * A)
+        assert np.abs(U - M).max() < 1e-12
