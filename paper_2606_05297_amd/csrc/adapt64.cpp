@@ -31,6 +31,7 @@ struct fock_adapt64 {
   std::vector<fock_op_t> pool, ops;  // ops: the ansatz's logical ops (two-parameter ones unexpanded)
   std::vector<double> theta, Hinv;   // theta: logical parameters (two per two-parameter op)
   std::vector<fock_op_t> gops;       // gates of the last evaluation
+  std::vector<fock_op_t> rec_ops;    // gates whose records are on the device (recs)
   fock_adapt_opts_t opt;
   hipStream_t s = nullptr;
   fock::EigTables T;
@@ -133,17 +134,29 @@ int eval_gates(fock_adapt64 *st, const std::vector<double> &th, double *E, doubl
   for (int k = 0; k < n; ++k)
     if (!std::isfinite(th[k])) return set_error(FOCK_ERR_NONFINITE, "theta[%d] is not finite", k);
   if (n > 0) {
-    std::vector<GateRec> rec(n);
-    for (int k = 0; k < n; ++k) rec[k] = GateRec{st->gops[k].type, k * st->Mmax * st->Mmax, 0, 0};
+    // gate records (table offset, reverse-step workgroups) change only with the gate list
+    bool same = st->rec_ops.size() == st->gops.size();
+    for (int k = 0; same && k < n; ++k)
+      same = st->rec_ops[k].type == st->gops[k].type && st->rec_ops[k].i == st->gops[k].i &&
+             st->rec_ops[k].j == st->gops[k].j;
+    if (!same) {
+      std::vector<GateRec> rec(n);
+      for (int k = 0; k < n; ++k)
+        rec[k] = GateRec{st->gops[k].type, k * st->Mmax * st->Mmax,
+                         fib64_blocks(make_fib64(st->L, st->d, st->gops[k])), 0};
+      FOCK_HIP(hipMemcpyAsync(st->recs, rec.data(), sizeof(GateRec) * n, hipMemcpyHostToDevice, st->s));
+      st->rec_ops = st->gops;
+    }
     FOCK_HIP(hipMemcpyAsync(st->th_dev, th.data(), sizeof(double) * n, hipMemcpyHostToDevice, st->s));
-    FOCK_HIP(hipMemcpyAsync(st->recs, rec.data(), sizeof(GateRec) * n, hipMemcpyHostToDevice, st->s));
     int rc = launch64_build(st->th_dev, st->recs, n, st->T, st->Mmax, st->utab, st->s);
     if (rc) return rc;
+  } else {
+    FOCK_HIP(hipMemcpyAsync(st->phi, st->psi0, sizeof(double2) * st->namp, hipMemcpyDeviceToDevice, st->s));
   }
-  FOCK_HIP(hipMemcpyAsync(st->phi, st->psi0, sizeof(double2) * st->namp, hipMemcpyDeviceToDevice, st->s));
-  for (int k = 0; k < n; ++k) {
+  for (int k = 0; k < n; ++k) {  // the first gate reads psi0 and writes phi
     const Fib64 a = make_fib64(st->L, st->d, st->gops[k]);
-    int rc = launch64_fib_apply(a, st->phi, st->phi, st->utab + (size_t)k * st->Mmax * st->Mmax, false, st->s);
+    int rc = launch64_fib_apply(a, k == 0 ? st->psi0 : st->phi, st->phi,
+                                st->utab + (size_t)k * st->Mmax * st->Mmax, false, st->s);
     if (rc) return rc;
   }
   int G = 0;
@@ -160,9 +173,10 @@ int eval_gates(fock_adapt64 *st, const std::vector<double> &th, double *E, doubl
       double *pk = st->partial + (size_t)(2 + k) * st->maxblk;
       rc = launch64_fib_adj(a, st->phi, st->lam, st->utab + (size_t)k * st->Mmax * st->Mmax, A, pk, st->s);
       if (rc) return rc;
-      rc = launch_reduce(pk, fib64_blocks(a), 1, st->res + 2 + k, st->s);
-      if (rc) return rc;
     }
+    // one launch sums every gate's row of partials (nblk of its record)
+    rc = launch_reduce_rows(st->partial + (size_t)2 * st->maxblk, st->maxblk, st->recs, n, st->res + 2, st->s);
+    if (rc) return rc;
   }
   std::vector<double> host(2 + (g ? n : 0));
   rc = fetch(st, (int)host.size(), host.data());
