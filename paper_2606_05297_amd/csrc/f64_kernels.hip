@@ -7,7 +7,8 @@
 //                   partials per workgroup;
 //   k64_fib_apply   psi <- U psi (U^+ psi) with a dense M x M local matrix on
 //                   every fibre (M = d^2 amplitudes over (n_i, n_j), or d over
-//                   one mode), fibres staged in LDS, one thread per output;
+//                   one mode), fibres (and matrices up to 36 x 36) staged in
+//                   LDS, one thread per output;
 //   k64_fib_adj     reverse step: Re<lam|A phi> per workgroup, then U^+ on
 //                   phi and lam;
 //   k64_fib_pool    2 Re<hpsi|A psi> per workgroup for one pool entry;
@@ -92,13 +93,23 @@ __device__ __forceinline__ uint32_t fib_off(int m, const Fib64 &a) {
   return a.j >= 0 ? (uint32_t)(m / a.d) * a.si + (uint32_t)(m % a.d) * a.sj : (uint32_t)m * a.si;
 }
 
+// Local matrices of up to kStage entries (M <= 36: every one-mode gate at
+// d <= 36 and two-mode gates at d <= 6) are staged in LDS once per workgroup,
+// so the per-thread loops below read LDS; larger ones are read from global
+// memory (L2) as they are.
+constexpr int kStage = 36 * 36;
+
+template <bool STAGE>
 __global__ __launch_bounds__(kBlock) void k64_fib_apply(const double2 *src, double2 *dst,
                                                         const double2 *__restrict__ U, Fib64 a, int dag) {
   __shared__ double2 x[kBlock];
+  __shared__ double2 Us[STAGE ? kStage : 1];
   const int M = a.M, fpw = a.fpw;
   const int fl = threadIdx.x / M, p = threadIdx.x % M;
   const uint32_t f = blockIdx.x * (uint32_t)fpw + (uint32_t)fl;
   const bool on = fl < fpw && f < a.nfib;
+  if constexpr (STAGE)
+    for (int e = threadIdx.x; e < M * M; e += kBlock) Us[e] = U[e];
   uint32_t base = 0;
   if (on) {
     base = fib_base(f, a);
@@ -109,7 +120,10 @@ __global__ __launch_bounds__(kBlock) void k64_fib_apply(const double2 *src, doub
     const double2 *xf = x + fl * M;
     double yr = 0.0, yi = 0.0;
     for (int q = 0; q < M; ++q) {
-      double2 u = dag ? U[(size_t)q * M + p] : U[(size_t)p * M + q];
+      const int e = dag ? q * M + p : p * M + q;
+      double2 u;
+      if constexpr (STAGE) u = Us[e];
+      else u = U[e];
       if (dag) u.y = -u.y;
       yr += u.x * xf[q].x - u.y * xf[q].y;
       yi += u.x * xf[q].y + u.y * xf[q].x;
@@ -118,15 +132,22 @@ __global__ __launch_bounds__(kBlock) void k64_fib_apply(const double2 *src, doub
   }
 }
 
+template <bool STAGE>
 __global__ __launch_bounds__(kBlock) void k64_fib_adj(double2 *__restrict__ phi, double2 *__restrict__ lam,
                                                       const double2 *__restrict__ U, const double2 *__restrict__ A,
                                                       double *__restrict__ partial, Fib64 a) {
   __shared__ double2 x[kBlock], l[kBlock];
+  __shared__ double2 Us[STAGE ? kStage : 1], As[STAGE ? kStage : 1];
   __shared__ double red[4];
   const int M = a.M, fpw = a.fpw;
   const int fl = threadIdx.x / M, p = threadIdx.x % M;
   const uint32_t f = blockIdx.x * (uint32_t)fpw + (uint32_t)fl;
   const bool on = fl < fpw && f < a.nfib;
+  if constexpr (STAGE)
+    for (int e = threadIdx.x; e < M * M; e += kBlock) {
+      Us[e] = U[e];
+      As[e] = A[e];
+    }
   uint32_t base = 0;
   if (on) {
     base = fib_base(f, a);
@@ -139,10 +160,16 @@ __global__ __launch_bounds__(kBlock) void k64_fib_adj(double2 *__restrict__ phi,
     const double2 *xf = x + fl * M, *lf = l + fl * M;
     double ar = 0.0, ai = 0.0, pr = 0.0, pi = 0.0, qr = 0.0, qi = 0.0;
     for (int q = 0; q < M; ++q) {
-      const double2 av = A[(size_t)p * M + q];
+      double2 av, u;  // u = U[q][p]: (U^+)[p][q] = conj(U[q][p])
+      if constexpr (STAGE) {
+        av = As[p * M + q];
+        u = Us[q * M + p];
+      } else {
+        av = A[(size_t)p * M + q];
+        u = U[(size_t)q * M + p];
+      }
       ar += av.x * xf[q].x - av.y * xf[q].y;
       ai += av.x * xf[q].y + av.y * xf[q].x;
-      const double2 u = U[(size_t)q * M + p];  // (U^+)[p][q] = conj(U[q][p])
       pr += u.x * xf[q].x + u.y * xf[q].y;
       pi += u.x * xf[q].y - u.y * xf[q].x;
       qr += u.x * lf[q].x + u.y * lf[q].y;
@@ -156,16 +183,20 @@ __global__ __launch_bounds__(kBlock) void k64_fib_adj(double2 *__restrict__ phi,
   if (threadIdx.x == 0) partial[blockIdx.x] = s;
 }
 
+template <bool STAGE>
 __global__ __launch_bounds__(kBlock) void k64_fib_pool(const double2 *__restrict__ psi,
                                                        const double2 *__restrict__ hpsi,
                                                        const double2 *__restrict__ A, double *__restrict__ partial,
                                                        Fib64 a) {
   __shared__ double2 x[kBlock];
+  __shared__ double2 As[STAGE ? kStage : 1];
   __shared__ double red[4];
   const int M = a.M, fpw = a.fpw;
   const int fl = threadIdx.x / M, p = threadIdx.x % M;
   const uint32_t f = blockIdx.x * (uint32_t)fpw + (uint32_t)fl;
   const bool on = fl < fpw && f < a.nfib;
+  if constexpr (STAGE)
+    for (int e = threadIdx.x; e < M * M; e += kBlock) As[e] = A[e];
   uint32_t base = 0;
   double2 h = make_double2(0.0, 0.0);
   if (on) {
@@ -179,7 +210,9 @@ __global__ __launch_bounds__(kBlock) void k64_fib_pool(const double2 *__restrict
     const double2 *xf = x + fl * M;
     double ar = 0.0, ai = 0.0;
     for (int q = 0; q < M; ++q) {
-      const double2 av = A[(size_t)p * M + q];
+      double2 av;
+      if constexpr (STAGE) av = As[p * M + q];
+      else av = A[(size_t)p * M + q];
       ar += av.x * xf[q].x - av.y * xf[q].y;
       ai += av.x * xf[q].y + av.y * xf[q].x;
     }
@@ -283,21 +316,30 @@ int launch64_apply_h(const H64 &h, const double2 *psi, double2 *hpsi, double *pa
 }
 
 int launch64_fib_apply(const Fib64 &a, const double2 *src, double2 *dst, const double2 *U, bool dag, hipStream_t s) {
-  hipLaunchKernelGGL(k64_fib_apply, dim3(fib64_blocks(a)), dim3(kBlock), 0, s, src, dst, U, a, dag ? 1 : 0);
+  if (a.M * a.M <= kStage)
+    hipLaunchKernelGGL(k64_fib_apply<true>, dim3(fib64_blocks(a)), dim3(kBlock), 0, s, src, dst, U, a, dag ? 1 : 0);
+  else
+    hipLaunchKernelGGL(k64_fib_apply<false>, dim3(fib64_blocks(a)), dim3(kBlock), 0, s, src, dst, U, a, dag ? 1 : 0);
   FOCK_HIP(hipGetLastError());
   return FOCK_OK;
 }
 
 int launch64_fib_adj(const Fib64 &a, double2 *phi, double2 *lam, const double2 *U, const double2 *A,
                      double *partial, hipStream_t s) {
-  hipLaunchKernelGGL(k64_fib_adj, dim3(fib64_blocks(a)), dim3(kBlock), 0, s, phi, lam, U, A, partial, a);
+  if (a.M * a.M <= kStage)
+    hipLaunchKernelGGL(k64_fib_adj<true>, dim3(fib64_blocks(a)), dim3(kBlock), 0, s, phi, lam, U, A, partial, a);
+  else
+    hipLaunchKernelGGL(k64_fib_adj<false>, dim3(fib64_blocks(a)), dim3(kBlock), 0, s, phi, lam, U, A, partial, a);
   FOCK_HIP(hipGetLastError());
   return FOCK_OK;
 }
 
 int launch64_fib_pool(const Fib64 &a, const double2 *psi, const double2 *hpsi, const double2 *A, double *partial,
                       hipStream_t s) {
-  hipLaunchKernelGGL(k64_fib_pool, dim3(fib64_blocks(a)), dim3(kBlock), 0, s, psi, hpsi, A, partial, a);
+  if (a.M * a.M <= kStage)
+    hipLaunchKernelGGL(k64_fib_pool<true>, dim3(fib64_blocks(a)), dim3(kBlock), 0, s, psi, hpsi, A, partial, a);
+  else
+    hipLaunchKernelGGL(k64_fib_pool<false>, dim3(fib64_blocks(a)), dim3(kBlock), 0, s, psi, hpsi, A, partial, a);
   FOCK_HIP(hipGetLastError());
   return FOCK_OK;
 }
