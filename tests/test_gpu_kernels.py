@@ -563,3 +563,31 @@ def test_maximum_size_product_state_apply_H_gate_energy():
         ref = np.array([O.product_gate_at(o, 0.3, fac, L, d, int(k)) for k in idx])
         assert np.abs(got - ref).max() <= 1e-5 * np.abs(ref).max(), o
         del x
+
+
+def test_event_timing_samples_one_launch_in_k():
+    """Event timing with a sampling interval k times launches 0, k, 2k, ... of
+    each kernel family: 8 gate launches give 2 timed ones at k = 4 and 8 at
+    k = 1, each with a positive duration; nothing is timed while disabled."""
+    L, d = 6, 4
+    x = dev(W.random_state(L, d, seed=3))
+    ws = lib.workspace(lib.ham(L, d), 0, 1)
+    say("event sampling")
+    try:
+        for k, want in ((4, 2), (1, 8)):
+            lib.prof_set_sample(k)
+            lib.prof_reset()
+            lib.prof_enable(True)
+            for _ in range(8):
+                lib.apply_gate2(L, d, ("HR", 2, 3), 0.3, x, ws)
+            torch.cuda.synchronize()
+            lib.prof_enable(False)
+            p = lib.prof_query(2)  # FOCK_K_GATE
+            assert p["launches"] == want and p["ms"] > 0.0, (k, p)
+        lib.prof_reset()
+        lib.apply_gate2(L, d, ("HR", 2, 3), 0.3, x, ws)
+        torch.cuda.synchronize()
+        assert lib.prof_query(2)["launches"] == 0
+    finally:
+        lib.prof_enable(False)
+        lib.prof_set_sample(1)
