@@ -316,7 +316,10 @@ int adapt64_create(const fock_ham_t *ham, const fock_op_t *pool, int P, const vo
       hipMalloc(&st->th_dev, sizeof(double) * st->cap) != hipSuccess ||
       hipMalloc(&st->recs, sizeof(GateRec) * st->cap) != hipSuccess)
     return fail(set_error(FOCK_ERR_HIP, "device allocation failed"));
-  if (hipMemcpy(st->psi0, psi0, bs, hipMemcpyDeviceToDevice) != hipSuccess)
+  // On the handle's own (non-blocking) stream, so that every later kernel is
+  // ordered after it; the evaluation below synchronises that stream before
+  // create returns, after which the caller may release psi0.
+  if (hipMemcpyAsync(st->psi0, psi0, bs, hipMemcpyDeviceToDevice, st->s) != hipSuccess)
     return fail(set_error(FOCK_ERR_HIP, "copy of psi0 failed"));
   if ((rc = get_tables(ham->d, &st->T))) return fail(rc);
   st->warm.iter = 0;

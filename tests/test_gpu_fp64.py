@@ -249,3 +249,23 @@ def test_fp64_fixed_warmup_bose_hubbard_repulsive():
     ad.close()
     assert all(b <= a + 1e-9 for a, b in zip(Es, Es[1:]))
     assert Es[-1] - E0 < 5.0
+
+
+def test_fp64_create_orders_psi0_copy_before_first_evaluation():
+    """Regression: the creation-time evaluation (warm report without a warm-up
+    layer) must see the whole copied psi0.  Handles of different sizes are
+    created back to back from fresh random states; each reports the oracle's
+    energy of its psi0, and the first step's starting energy equals it too."""
+    for L, d in ((3, 6), (4, 6), (5, 6), (4, 6), (5, 5)):
+        ho = O.Ham(L, d, True, J=1.0, mu=-3.1, Delta=0.5)
+        hl = lib.ham(L, d, True, 1.0, 0.0, -3.1, 0.5, 0.0)
+        psi0 = W.random_state(L, d, seed=L * d, sector=("parity", 0), dtype=np.complex128)
+        pool = W.pool(L, "all", True, ("HR", "PR")) + W.site_ops(L, ("SR",))
+        say("fp64 create", L, d)
+        ad = lib.Adapt64(hl, pool, dev128(psi0), max_iters=4, grad_tol=1e-14)
+        w = ad.warm_report()
+        Eo = O.energy(ho, psi0)[0]
+        assert abs(w["E"] - Eo) <= 1e-12 * max(1.0, abs(Eo)), (L, d, w["E"], Eo)
+        r = ad.step()
+        assert abs(r["E_init"] - Eo) <= 1e-10 * max(1.0, abs(Eo))
+        ad.close()
