@@ -209,7 +209,9 @@ def paper_cases() -> list[dict]:
         occ = [3, 3, 3, 3] if lam < 0 else [6, 0, 6, 0]
         out.append(dict(name=f"bh_N4_lam{lam:+g}", model="bh", L=4, d=13, periodic=True, J=1.0, U=-lam / 12.0,
                         mu=0.0, Delta=0.0, K=0.0, occ=occ, sector=("N", 12), warm=True, warm_seed=7,
-                        pool=pool(4, "nn", True, ("HR", "HI", "CK")) + site_ops(4, ("KERR", "ROT"))))
+                        pool=pool(4, "nn", True, ("HR", "HI", "CK")) + site_ops(4, ("KERR", "ROT")),
+                        # the paper's number-conserving pool with its two-parameter beam splitter
+                        pool2=pool(4, "nn", True, ("BS", "CK")) + site_ops(4, ("KERR", "ROT"))))
     return out
 
 
