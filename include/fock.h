@@ -140,6 +140,19 @@ int fock_energy_grad_adjoint(const fock_ham_t *ham, const fock_op_t *ops, const 
                              double *norm2, double *dEdtheta, void *ws, size_t ws_bytes,
                              fock_stream_t stream);
 
+/* The reverse sweep of fock_energy_grad_adjoint on its own (the adjoint
+ * gradient identity of Sec. IV.B applied to every parameter): given
+ * psi_work = psi_n and lam_work = H psi_n as left by an energy-only call
+ * (dEdtheta == NULL) of the same ops/theta, and that call's norm2, writes all
+ * dE/dtheta_k = 2 Re <lambda_k| A_k phi_k> / norm2 into dEdtheta (host, n).
+ * psi_work and lam_work are overwritten (they end as psi0 and
+ * O_1^+..O_n^+ H psi_n up to rounding).  Lets a caller run the forward pass
+ * and the gradient pass separately (e.g. an autograd backward).  Same
+ * workspace as fock_energy_grad_adjoint for n gates. */
+int fock_adjoint_sweep(const fock_ham_t *ham, const fock_op_t *ops, const double *theta, int n, void *psi_work,
+                       void *lam_work, double norm2, double *dEdtheta, void *ws, size_t ws_bytes,
+                       fock_stream_t stream);
+
 /* ------------------------------------------------------------------ ADAPT */
 
 typedef struct {

@@ -327,10 +327,11 @@ def energy(ham: Ham, psi: np.ndarray) -> tuple[float, float]:
     return float(np.vdot(psi, h).real), float(np.vdot(psi, psi).real)
 
 
-def pool_gradients(ham: Ham, psi: np.ndarray, pool: Sequence) -> np.ndarray:
-    """g_k = <psi|[H, A_k]|psi> = 2 Re <H psi|A_k psi> for anti-Hermitian A_k (Eq. grad)."""
+def pool_gradients(ham: Ham, psi: np.ndarray, pool: Sequence, apply_h=None) -> np.ndarray:
+    """g_k = <psi|[H, A_k]|psi> = 2 Re <H psi|A_k psi> for anti-Hermitian A_k (Eq. grad).
+    apply_h: as in energy_and_grad_adjoint (apply_H by default)."""
     L, d = ham.L, ham.d
-    h = apply_H(ham, psi)
+    h = (apply_h or apply_H)(ham, psi)
     return np.array([2.0 * np.vdot(h, apply_generator(op, psi, L, d)).real for op in pool])
 
 
@@ -351,13 +352,16 @@ def commutator_gradients(ham: Ham, psi: np.ndarray, pool: Sequence) -> np.ndarra
     return np.array(out)
 
 
-def energy_and_grad_adjoint(ham: Ham, psi0: np.ndarray, ops: Sequence, thetas: Sequence[float]):
+def energy_and_grad_adjoint(ham: Ham, psi0: np.ndarray, ops: Sequence, thetas: Sequence[float], apply_h=None):
     """E(theta) = <psi|H|psi> and dE/dtheta_k = 2 Re <lambda_k|A_k phi_k> by one
     reverse sweep, with phi_k = O_k ... O_1 psi0 and
-    lambda_k = O_{k+1}^+ ... O_n^+ H psi_n (uses dO_k/dtheta_k = A_k O_k)."""
+    lambda_k = O_{k+1}^+ ... O_n^+ H psi_n (uses dO_k/dtheta_k = A_k O_k).
+    apply_h: which of the oracle's H psi constructions to use (apply_H by
+    default; apply_H_slices is the same operator, several times faster on
+    large lattices, and pinned against apply_H and the dense matrix)."""
     L, d = ham.L, ham.d
     phi = ansatz_state(psi0, ops, thetas, L, d)
-    lam = apply_H(ham, phi)
+    lam = (apply_h or apply_H)(ham, phi)
     E = float(np.vdot(phi, lam).real)
     n2 = float(np.vdot(phi, phi).real)
     g = np.zeros(len(ops))

@@ -136,12 +136,12 @@ int adapt_create(const fock_ham_t *ham, const fock_op_t *pool, int P, const void
     if ((rc = check_op(pool[k], ham->L))) return rc;
   if (opts->warm_fixed != 0)
     return set_error(FOCK_ERR_UNSUPPORTED, "fixed warm-up angles are taken by the complex128 driver only");
-  if (opts->n_warm < 0 || (opts->n_warm > 0 && (!opts->warm_ops || !opts->warm_theta0)))
-    return set_error(FOCK_ERR_ARG, "warm-up layer arrays missing");
+  if (opts->n_warm < 0 || opts->n_warm > 4096 || (opts->n_warm > 0 && (!opts->warm_ops || !opts->warm_theta0)))
+    return set_error(FOCK_ERR_ARG, "warm-up layer: 0..4096 ops with both arrays given");
   for (int k = 0; k < opts->n_warm; ++k)
     if ((rc = check_op(opts->warm_ops[k], ham->L))) return rc;
-  if (opts->max_iters < 0 || opts->bfgs_maxiter < 0 || !(opts->grad_tol >= 0.0))
-    return set_error(FOCK_ERR_ARG, "invalid iteration caps or tolerance");
+  if (opts->max_iters < 0 || opts->max_iters > 4000 || opts->bfgs_maxiter < 0 || !(opts->grad_tol >= 0.0))
+    return set_error(FOCK_ERR_ARG, "invalid iteration caps (max_iters in 0..4000) or tolerance");
   if (opts->grad_mode == 1 && !(opts->fd_step > 0.0)) return set_error(FOCK_ERR_ARG, "fd_step must be > 0");
 
   fock_adapt *st = new fock_adapt();

@@ -330,24 +330,63 @@ static FuseArgs make_fuse_args(const Ctx &c, const GateGroup &gr, const fock_op_
   return a;
 }
 
+// Stage the gate tables of a circuit (with the per-gate partial counts of the
+// reverse step, which depend on how the gates are grouped) and plan its groups.
+static int stage_circuit(Ctx &c, const fock_op_t *ops, const double *theta, int n, std::vector<GateGroup> *groups) {
+  if (n > c.L.nmax) return set_error(FOCK_ERR_SIZE, "circuit of %d gates exceeds the workspace's %d", n, c.L.nmax);
+  plan_gate_groups(c, ops, n, groups);
+  if (n == 0) return FOCK_OK;
+  const bool fuse_rev = g_fuse.load() == FOCK_FUSE_ALL;
+  std::vector<int> nblk(n, 0);
+  for (const GateGroup &gr : *groups)
+    if (gr.s > 0 && fuse_rev) {
+      int nt = 1;
+      for (int r = 0; r < c.g.L - gr.s; ++r) nt *= c.g.d;
+      for (int k = gr.k0; k < gr.k1; ++k) nblk[k] = nt;
+    }
+  return stage_gates(c, ops, theta, n, nblk.data());
+}
+
+// Reverse sweep from phi = psi_n, lam = H psi_n (both overwritten): per-gate
+// sums of Re<lam|A_k phi> reduced into res[0..n) (device), in stream order.
+static int reverse_sweep(Ctx &c, const fock_op_t *ops, int n, const std::vector<GateGroup> &groups, float2 *phi,
+                         float2 *lam, double *res) {
+  if (n == 0) return FOCK_OK;
+  int rc = FOCK_OK;
+  const bool fuse_rev = g_fuse.load() == FOCK_FUSE_ALL;
+  const float2 *utab = (const float2 *)(c.ws + c.L.utab);
+  double *part = (double *)(c.ws + c.L.partial);
+  const int stride = gate_stride(c.g.d);
+  for (int gi = (int)groups.size() - 1; gi >= 0; --gi) {
+    const GateGroup &gr = groups[gi];
+    if (gr.s > 0 && fuse_rev) {
+      ProfScope ps(FOCK_K_ADJ, c.s, 32.0 * c.g.n_amp);
+      rc = launch_fuse_adj(c.g.d, make_fuse_args(c, gr, ops), phi, lam, utab, part, c.L.rs, c.s);
+      if (rc) return rc;
+      continue;
+    }
+    for (int k = gr.k1 - 1; k >= gr.k0; --k) {
+      const fock_op_t &op = ops[k];
+      const float2 *U = utab + (size_t)k * stride;
+      double *pk = part + (size_t)k * c.L.rs;
+      ProfScope ps(is_single_mode(op.type) ? FOCK_K_DIAG : FOCK_K_ADJ, c.s, 32.0 * c.g.n_amp);
+      if (is_squeeze(op.type))
+        rc = launch_gate1_adj(c.g, op.i, U, c.T.A1[op.type == FOCK_SR ? 0 : 1], phi, lam, pk, c.s);
+      else if (is_single_mode(op.type)) rc = launch_diag_adj(c.g, op.i, op.type, U, phi, lam, pk, c.s);
+      else rc = launch_gate_adj(c.g, op.i, op.j, gate_kind(op.type), U, c.T.A[table_slot(op.type)], phi, lam, pk,
+                                c.s);
+      if (rc) return rc;
+    }
+  }
+  return launch_reduce_rows(part, c.L.rs, (const GateRec *)(c.ws + c.L.recs), n, res, c.s);
+}
+
 // Energy and (optionally) all dE/dtheta of a circuit; see fock_energy_grad_adjoint.
 int run_circuit(Ctx &c, const fock_op_t *ops, const double *theta, int n, const void *psi0, float2 *phi,
                        float2 *lam, bool grad, double *E, double *norm2, double *dE) {
-  int rc = FOCK_OK;
   std::vector<GateGroup> groups;
-  plan_gate_groups(c, ops, n, &groups);
-  const bool fuse_rev = g_fuse.load() == FOCK_FUSE_ALL;
-  if (n > 0) {
-    std::vector<int> nblk(n, 0);
-    for (const GateGroup &gr : groups)
-      if (gr.s > 0 && fuse_rev) {
-        int nt = 1;
-        for (int r = 0; r < c.g.L - gr.s; ++r) nt *= c.g.d;
-        for (int k = gr.k0; k < gr.k1; ++k) nblk[k] = nt;
-      }
-    rc = stage_gates(c, ops, theta, n, nblk.data());
-    if (rc) return rc;
-  }
+  int rc = stage_circuit(c, ops, theta, n, &groups);
+  if (rc) return rc;
   const float2 *utab = (const float2 *)(c.ws + c.L.utab);
   // the first gate reads psi0 and writes phi (no separate copy)
   if (n == 0)
@@ -366,31 +405,7 @@ int run_circuit(Ctx &c, const fock_op_t *ops, const double *theta, int n, const 
   rc = apply_h_dev(c, phi, lam, res);
   if (rc) return rc;
   if (grad && n > 0) {
-    double *part = (double *)(c.ws + c.L.partial);
-    const int stride = gate_stride(c.g.d);
-    const float2 *U0 = (const float2 *)(c.ws + c.L.utab);
-    for (int gi = (int)groups.size() - 1; gi >= 0; --gi) {
-      const GateGroup &gr = groups[gi];
-      if (gr.s > 0 && fuse_rev) {
-        ProfScope ps(FOCK_K_ADJ, c.s, 32.0 * c.g.n_amp);
-        rc = launch_fuse_adj(c.g.d, make_fuse_args(c, gr, ops), phi, lam, utab, part, c.L.rs, c.s);
-        if (rc) return rc;
-        continue;
-      }
-      for (int k = gr.k1 - 1; k >= gr.k0; --k) {
-      const fock_op_t &op = ops[k];
-      const float2 *U = U0 + (size_t)k * stride;
-      double *pk = part + (size_t)k * c.L.rs;
-      ProfScope ps(is_single_mode(op.type) ? FOCK_K_DIAG : FOCK_K_ADJ, c.s, 32.0 * c.g.n_amp);
-      if (is_squeeze(op.type))
-        rc = launch_gate1_adj(c.g, op.i, U, c.T.A1[op.type == FOCK_SR ? 0 : 1], phi, lam, pk, c.s);
-      else if (is_single_mode(op.type)) rc = launch_diag_adj(c.g, op.i, op.type, U, phi, lam, pk, c.s);
-      else rc = launch_gate_adj(c.g, op.i, op.j, gate_kind(op.type), U, c.T.A[table_slot(op.type)], phi, lam, pk,
-                                c.s);
-      if (rc) return rc;
-      }
-    }
-    rc = launch_reduce_rows(part, c.L.rs, (const GateRec *)(c.ws + c.L.recs), n, res + 2, c.s);
+    rc = reverse_sweep(c, ops, n, groups, phi, lam, res + 2);
     if (rc) return rc;
   }
   const int cnt = 2 + ((grad && n > 0) ? n : 0);
@@ -404,6 +419,27 @@ int run_circuit(Ctx &c, const fock_op_t *ops, const double *theta, int n, const 
   if (norm2) *norm2 = nrm;
   if (grad && dE)
     for (int k = 0; k < n; ++k) dE[k] = 2.0 * host[2 + k] / nrm;
+  return FOCK_OK;
+}
+
+// All dE/dtheta by the reverse sweep alone, from phi = psi_n and lam = H psi_n
+// left by an energy-only evaluation of the same circuit; see fock_adjoint_sweep.
+int run_reverse(Ctx &c, const fock_op_t *ops, const double *theta, int n, float2 *phi, float2 *lam, double norm2,
+                double *dE) {
+  if (!(norm2 > 0.0) || !std::isfinite(norm2)) return set_error(FOCK_ERR_ARG, "norm2 must be finite and > 0");
+  std::vector<GateGroup> groups;
+  int rc = stage_circuit(c, ops, theta, n, &groups);
+  if (rc || n == 0) return rc;
+  double *res = (double *)(c.ws + c.L.result);
+  rc = reverse_sweep(c, ops, n, groups, phi, lam, res);
+  if (rc) return rc;
+  std::vector<double> host(n);
+  rc = fetch_results(c, n, host.data());
+  if (rc) return rc;
+  for (int k = 0; k < n; ++k) {
+    if (!std::isfinite(host[k])) return set_error(FOCK_ERR_NONFINITE, "non-finite gradient entry %d", k);
+    dE[k] = 2.0 * host[k] / norm2;
+  }
   return FOCK_OK;
 }
 
@@ -697,6 +733,25 @@ int fock_energy_grad_adjoint(const fock_ham_t *ham, const fock_op_t *ops, const 
   if (rc) return rc;
   return run_circuit(c, ops, theta, n, psi0, (float2 *)psi_work, (float2 *)lam_work, dEdtheta != nullptr, E, norm2,
                      dEdtheta);
+}
+
+int fock_adjoint_sweep(const fock_ham_t *ham, const fock_op_t *ops, const double *theta, int n, void *psi_work,
+                       void *lam_work, double norm2, double *dEdtheta, void *ws, size_t ws_bytes,
+                       fock_stream_t stream) {
+  uint32_t namp = 0;
+  int rc = check_ham(ham, &namp);
+  if (rc) return rc;
+  if (n < 0 || n > 4096) return set_error(FOCK_ERR_ARG, "n=%d out of range", n);
+  if (n > 0 && (!ops || !theta || !dEdtheta)) return set_error(FOCK_ERR_ARG, "ops/theta/dEdtheta is NULL");
+  if ((rc = check_ptr(psi_work, "psi_work")) || (rc = check_ptr(lam_work, "lam_work"))) return rc;
+  if (psi_work == lam_work) return set_error(FOCK_ERR_ARG, "psi_work and lam_work must be distinct");
+  if (!(norm2 > 0.0) || !std::isfinite(norm2)) return set_error(FOCK_ERR_ARG, "norm2 must be finite and > 0");
+  for (int k = 0; k < n; ++k)
+    if ((rc = check_op(ops[k], ham->L))) return rc;
+  Ctx c;
+  rc = make_ctx(*ham, namp, 0, n, ws, ws_bytes, (hipStream_t)stream, &c);
+  if (rc) return rc;
+  return run_reverse(c, ops, theta, n, (float2 *)psi_work, (float2 *)lam_work, norm2, dEdtheta);
 }
 
 }  // extern "C"

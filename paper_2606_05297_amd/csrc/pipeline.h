@@ -37,6 +37,9 @@ int fetch_results(Ctx &c, int count, double *host);
 // Energy (Rayleigh quotient) and optionally all dE/dtheta of ops/theta applied to psi0.
 int run_circuit(Ctx &c, const fock_op_t *ops, const double *theta, int n, const void *psi0, float2 *phi,
                 float2 *lam, bool grad, double *E, double *norm2, double *dE);
+// All dE/dtheta from phi = psi_n, lam = H psi_n (overwritten) by the reverse sweep alone.
+int run_reverse(Ctx &c, const fock_op_t *ops, const double *theta, int n, float2 *phi, float2 *lam, double norm2,
+                double *dE);
 // 2 Re <hpsi|A_k psi> for the pool into res[0..P) (device).
 int pool_dev(Ctx &c, const fock_op_t *pool, int P, const float2 *psi, const float2 *hpsi, double *res);
 

@@ -538,6 +538,7 @@ int fock_sweep_create(const fock_sweep_point_t *pts, int npts, const fock_adapt_
   if (!opts) return set_error(FOCK_ERR_ARG, "opts is NULL");
   if (opts->warm_fixed != 0)
     return set_error(FOCK_ERR_UNSUPPORTED, "fixed warm-up angles are taken by the complex128 driver only");
+  if (opts->max_iters < 0 || opts->max_iters > 4000) return set_error(FOCK_ERR_ARG, "max_iters out of range 0..4000");
   int rc = 0;
   for (int p = 0; p < npts; ++p) {
     uint32_t namp = 0;
@@ -553,8 +554,8 @@ int fock_sweep_create(const fock_sweep_point_t *pts, int npts, const fock_adapt_
       if (is_squeeze(pts[p].pool[k].type))
         return set_error(FOCK_ERR_UNSUPPORTED, "point %d: the sweep kernels do not take squeezer ops (pool %d)", p, k);
     }
-    if (pts[p].n_warm < 0 || (pts[p].n_warm > 0 && (!pts[p].warm_ops || !pts[p].warm_theta0)))
-      return set_error(FOCK_ERR_ARG, "point %d: warm-up arrays missing", p);
+    if (pts[p].n_warm < 0 || pts[p].n_warm > 4096 || (pts[p].n_warm > 0 && (!pts[p].warm_ops || !pts[p].warm_theta0)))
+      return set_error(FOCK_ERR_ARG, "point %d: warm-up layer needs 0..4096 ops with both arrays given", p);
     for (int k = 0; k < pts[p].n_warm; ++k) {
       if ((rc = check_op(pts[p].warm_ops[k], pts[p].ham.L))) return rc;
       if (is_squeeze(pts[p].warm_ops[k].type))

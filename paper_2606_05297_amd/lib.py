@@ -98,6 +98,7 @@ def load(path: str = LIB_PATH):
     L.fock_pool_grads.argtypes = [C.POINTER(Ham), C.POINTER(Op), C.c_int, vp, vp, dp, vp, sz, vp]
     L.fock_energy_grad_adjoint.argtypes = [C.POINTER(Ham), C.POINTER(Op), dp, C.c_int, vp, vp, vp, dp, dp, dp, vp,
                                            sz, vp]
+    L.fock_adjoint_sweep.argtypes = [C.POINTER(Ham), C.POINTER(Op), dp, C.c_int, vp, vp, C.c_double, dp, vp, sz, vp]
     L.adapt_default_opts.argtypes = [C.POINTER(AdaptOpts)]
     L.adapt_default_opts.restype = None
     L.adapt_create.argtypes = [C.POINTER(Ham), C.POINTER(Op), C.c_int, vp, C.POINTER(AdaptOpts), vp,
@@ -186,11 +187,49 @@ def workspace(h: Ham, n_pool: int = 0, n_ops: int = 0, device="cuda"):
     return torch.empty(workspace_bytes(h, n_pool, n_ops), dtype=torch.uint8, device=device)
 
 
+def _state_arg(t, L_, d, name, dtype="c64"):
+    """Reject a state tensor the kernels cannot take: not a contiguous complex64
+    (complex128 for the FP64 driver) tensor on the current GPU, or not holding
+    exactly d^L amplitudes.  Raised before any launch, so a wrong buffer never
+    reaches a kernel that would read or write past it."""
+    import torch
+    want = torch.complex64 if dtype == "c64" else torch.complex128
+    if not isinstance(t, torch.Tensor):
+        raise FockError(-1, f"{name} must be a torch tensor, got {type(t).__name__}")
+    if t.dtype != want or not t.is_contiguous():
+        raise FockError(-1, f"{name} must be a contiguous {want} tensor (got {t.dtype}, "
+                            f"contiguous={t.is_contiguous()})")
+    n = int(d) ** int(L_)
+    if t.numel() != n:
+        raise FockError(-2, f"{name} must hold d^L = {d}^{L_} = {n} amplitudes, got {t.numel()}")
+    if not t.is_cuda:
+        raise FockError(-1, f"{name} must live on the GPU, got {t.device}")
+    if t.device.index != torch.cuda.current_device():
+        raise FockError(-1, f"{name} lives on {t.device}, not on the current device cuda:{torch.cuda.current_device()}")
+
+
+def _ws_arg(ws, name="ws"):
+    import torch
+    if not isinstance(ws, torch.Tensor) or not ws.is_cuda or ws.dtype != torch.uint8 or not ws.is_contiguous():
+        raise FockError(-1, f"{name} must be a contiguous CUDA uint8 tensor")
+
+
+def _disjoint(a, b, na, nb):
+    pa, pb = a.data_ptr(), b.data_ptr()
+    ea, eb = pa + a.numel() * a.element_size(), pb + b.numel() * b.element_size()
+    if pa < eb and pb < ea:
+        raise FockError(-1, f"{na} and {nb} must not overlap")
+
+
 # ---------------------------------------------------------------- entry points
 
 def apply_H(h: Ham, psi, hpsi, ws, energy=True, stream=None):
     """hpsi = H psi; returns (<psi|H|psi>, <psi|psi>) when energy is True."""
     L = load()
+    _state_arg(psi, h.L, h.d, "psi")
+    _state_arg(hpsi, h.L, h.d, "hpsi")
+    _disjoint(psi, hpsi, "psi", "hpsi")
+    _ws_arg(ws)
     E, n2 = C.c_double(0), C.c_double(0)
     _check(L.fock_apply_H(C.byref(h), _ptr(psi), _ptr(hpsi), C.byref(E) if energy else None,
                           C.byref(n2) if energy else None, _ptr(ws), ws.numel(), _stream(stream)))
@@ -199,12 +238,17 @@ def apply_H(h: Ham, psi, hpsi, ws, energy=True, stream=None):
 
 def apply_gate2(L_, d, o, theta, psi, ws, adjoint=False, stream=None):
     L = load()
+    _state_arg(psi, L_, d, "psi")
+    _ws_arg(ws)
     _check(L.fock_apply_gate2(int(L_), int(d), op(*o), float(theta), int(bool(adjoint)), _ptr(psi), _ptr(ws),
                               ws.numel(), _stream(stream)))
 
 
 def pool_grads(h: Ham, pool, psi, hpsi, ws, stream=None) -> np.ndarray:
     L = load()
+    _state_arg(psi, h.L, h.d, "psi")
+    _state_arg(hpsi, h.L, h.d, "hpsi")
+    _ws_arg(ws)
     P = len(pool)
     out = np.zeros(P, dtype=np.float64)
     _check(L.fock_pool_grads(C.byref(h), ops_array(pool), P, _ptr(psi), _ptr(hpsi),
@@ -216,7 +260,15 @@ def energy_grad_adjoint(h: Ham, ops, theta, psi0, psi_work, lam_work, ws, grad=T
     """Returns (E, norm2, dE/dtheta or None) for the ansatz ops/theta on psi0."""
     L = load()
     n = len(ops)
+    for t, nm in ((psi0, "psi0"), (psi_work, "psi_work"), (lam_work, "lam_work")):
+        _state_arg(t, h.L, h.d, nm)
+    _disjoint(psi0, psi_work, "psi0", "psi_work")
+    _disjoint(psi0, lam_work, "psi0", "lam_work")
+    _disjoint(psi_work, lam_work, "psi_work", "lam_work")
+    _ws_arg(ws)
     th = np.ascontiguousarray(theta, dtype=np.float64)
+    if th.shape != (n,):
+        raise FockError(-1, f"theta must have shape ({n},), got {th.shape}")
     E, n2 = C.c_double(0), C.c_double(0)
     g = np.zeros(max(n, 1), dtype=np.float64)
     _check(L.fock_energy_grad_adjoint(C.byref(h), ops_array(ops), th.ctypes.data_as(C.POINTER(C.c_double)), n,
@@ -224,6 +276,26 @@ def energy_grad_adjoint(h: Ham, ops, theta, psi0, psi_work, lam_work, ws, grad=T
                                       g.ctypes.data_as(C.POINTER(C.c_double)) if grad else None, _ptr(ws),
                                       ws.numel(), _stream(stream)))
     return E.value, n2.value, (g[:n].copy() if grad else None)
+
+
+def adjoint_sweep(h: Ham, ops, theta, psi_work, lam_work, norm2, ws, stream=None) -> np.ndarray:
+    """dE/dtheta by the reverse sweep alone, from psi_work = psi_n and
+    lam_work = H psi_n left by energy_grad_adjoint(..., grad=False) on the same
+    ops/theta (both buffers are overwritten); norm2 is that call's <psi|psi>."""
+    L = load()
+    n = len(ops)
+    _state_arg(psi_work, h.L, h.d, "psi_work")
+    _state_arg(lam_work, h.L, h.d, "lam_work")
+    _disjoint(psi_work, lam_work, "psi_work", "lam_work")
+    _ws_arg(ws)
+    th = np.ascontiguousarray(theta, dtype=np.float64)
+    if th.shape != (n,):
+        raise FockError(-1, f"theta must have shape ({n},), got {th.shape}")
+    g = np.zeros(max(n, 1), dtype=np.float64)
+    _check(L.fock_adjoint_sweep(C.byref(h), ops_array(ops), th.ctypes.data_as(C.POINTER(C.c_double)), n,
+                                _ptr(psi_work), _ptr(lam_work), float(norm2), g.ctypes.data_as(C.POINTER(C.c_double)),
+                                _ptr(ws), ws.numel(), _stream(stream)))
+    return g[:n].copy()
 
 
 def bfgs_minimize(fun, x0, gtol=1e-8, maxiter=1000, hinv=None):
@@ -261,6 +333,7 @@ class Adapt:
                  gtol_floor_rel=1e-5, warm_gtol=1e-6, noise_rel=1e-7, stream=None):
         L = load()
         self._L = L
+        _state_arg(psi0, h.L, h.d, "psi0")
         o = AdaptOpts()
         L.adapt_default_opts(C.byref(o))
         o.max_iters = int(max_iters)
@@ -275,6 +348,8 @@ class Adapt:
         o.noise_rel = float(noise_rel)
         self._warm = ops_array(list(warm_ops))
         self._warm_th = np.ascontiguousarray(warm_theta0, dtype=np.float64)
+        if len(self._warm_th) != len(warm_ops):
+            raise ValueError("warm_theta0 needs one angle per warm-up op")
         o.n_warm = len(warm_ops)
         if len(warm_ops):
             o.warm_ops = C.cast(self._warm, C.POINTER(Op))
@@ -338,6 +413,7 @@ class Adapt64:
                  stream=None):
         L = load()
         self._L = L
+        _state_arg(psi0, h.L, h.d, "psi0", dtype="c128")
         o = AdaptOpts()
         L.adapt_default_opts(C.byref(o))
         o.max_iters = int(max_iters)
@@ -427,6 +503,7 @@ class Sweep:
         self._keep = []
         arr = (SweepPoint * self.n)()
         for k, p in enumerate(points):
+            _state_arg(p["psi0"], p["ham"].L, p["ham"].d, f"points[{k}].psi0")
             pool = ops_array(p["pool"])
             wo = p.get("warm_ops", ())
             wops = ops_array(list(wo))

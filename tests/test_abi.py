@@ -218,3 +218,72 @@ def test_mfma_operand_overlap_check():
     assert n == 5
     assert bad == ["v_mfma_f32_16x16x4_f32 a[26:29], v16, v12, a[28:31]",
                    "v_mfma_f32_16x16x32_bf16 v[4:7], v[0:3], v[8:11], v[2:5]"]
+
+
+# ---------------------------------------------------------------- binding argument checks
+
+def test_state_arguments_rejected_before_any_launch():
+    """The Python entry points refuse state tensors of the wrong dtype, length
+    or device before calling the library (a short or complex128 buffer would
+    otherwise be read or written past its end by the kernels)."""
+    import torch
+    h = lib.ham(3, 4, False, 1, 2)
+    good_len = 4 ** 3
+    ws = torch.empty(16, dtype=torch.uint8)
+    with pytest.raises(lib.FockError, match="complex64"):
+        lib.apply_H(h, torch.zeros(good_len, dtype=torch.complex128), torch.zeros(good_len, dtype=torch.complex64), ws)
+    with pytest.raises(lib.FockError, match="amplitudes"):
+        lib.apply_H(h, torch.zeros(good_len - 1, dtype=torch.complex64), torch.zeros(good_len, dtype=torch.complex64),
+                    ws)
+    with pytest.raises(lib.FockError, match="GPU"):
+        lib.apply_H(h, torch.zeros(good_len, dtype=torch.complex64), torch.zeros(good_len, dtype=torch.complex64), ws)
+    with pytest.raises(lib.FockError, match="contiguous"):
+        lib.pool_grads(h, [("HR", 0, 1)], torch.zeros(2 * good_len, dtype=torch.complex64)[::2],
+                       torch.zeros(good_len, dtype=torch.complex64), ws)
+    with pytest.raises(lib.FockError, match="amplitudes"):
+        lib.apply_gate2(3, 4, ("HR", 0, 1), 0.1, torch.zeros(good_len + 1, dtype=torch.complex64), ws)
+    with pytest.raises(lib.FockError, match="amplitudes"):
+        lib.energy_grad_adjoint(h, [("HR", 0, 1)], [0.1], torch.zeros(3, dtype=torch.complex64),
+                                torch.zeros(good_len, dtype=torch.complex64), torch.zeros(good_len, dtype=torch.complex64),
+                                ws)
+    with pytest.raises(lib.FockError, match="complex128"):
+        lib.Adapt64(h, [("HR", 0, 1)], torch.zeros(good_len, dtype=torch.complex64))
+    with pytest.raises(lib.FockError, match="amplitudes"):
+        lib.Adapt(h, [("HR", 0, 1)], torch.zeros(good_len * 4, dtype=torch.complex64))
+    with pytest.raises(lib.FockError, match="amplitudes"):
+        lib.Sweep([dict(ham=h, pool=[("HR", 0, 1)], psi0=torch.zeros(5, dtype=torch.complex64))])
+
+
+def test_adapt_create_rejects_oversized_caps():
+    L = lib.load()
+    o = lib.AdaptOpts()
+    L.adapt_default_opts(C.byref(o))
+    st = C.c_void_p()
+    h = lib.ham(3, 4, False, 1, 2)
+    o.max_iters = 1 << 30  # would overflow the workspace's gate count
+    assert L.adapt_create(C.byref(h), lib.ops_array([("HR", 0, 1)]), 1, C.c_void_p(1 << 20), C.byref(o), None,
+                          C.byref(st)) == -1
+    assert "max_iters" in lib.last_error()
+    o.max_iters = 60
+    o.n_warm = 5000
+    wops = lib.ops_array([("HR", 0, 1)] * 5000)
+    wth = (C.c_double * 5000)()
+    o.warm_ops = C.cast(wops, C.POINTER(lib.Op))
+    o.warm_theta0 = C.cast(wth, C.POINTER(C.c_double))
+    assert L.adapt_create(C.byref(h), lib.ops_array([("HR", 0, 1)]), 1, C.c_void_p(1 << 20), C.byref(o), None,
+                          C.byref(st)) == -1
+    assert not st.value
+
+
+def test_adjoint_sweep_argument_checks():
+    L = lib.load()
+    h = lib.ham(3, 4, False, 1, 2)
+    big = C.c_void_p(1 << 20)
+    g = (C.c_double * 2)()
+    th = (C.c_double * 2)(0.1, 0.2)
+    rc = L.fock_adjoint_sweep(C.byref(h), lib.ops_array([("HR", 0, 1), ("PR", 1, 2)]), th, 2, big, big, 1.0, g, big,
+                              1 << 20, None)
+    assert rc == -1 and "distinct" in lib.last_error()
+    rc = L.fock_adjoint_sweep(C.byref(h), lib.ops_array([("HR", 0, 1), ("PR", 1, 2)]), th, 2, big,
+                              C.c_void_p(2 << 20), 0.0, g, C.c_void_p(3 << 20), 1 << 24, None)
+    assert rc == -1 and "norm2" in lib.last_error()

@@ -370,23 +370,55 @@ def test_full_kitaev_l8_d8_pool_grads(kk_full):
     g = lib.pool_grads(hl, c["pool"], x, y, ws)
     p128 = psi.astype(np.complex128)
     h128 = O.apply_H_slices(ho, p128)
-    sub = [0, 3, 5, 10, 13, 18, 22, 24, 27]
-    ref = np.array([2 * np.vdot(h128, O.apply_generator(c["pool"][k], p128, 8, 8)).real for k in sub])
-    assert np.abs(g[sub] - ref).max() <= 1e-4 * max(1.0, np.abs(ref).max())
+    assert len(c["pool"]) == 28
+    ref = np.array([2 * np.vdot(h128, O.apply_generator(op, p128, 8, 8)).real for op in c["pool"]])
+    assert np.abs(g - ref).max() <= 1e-4 * max(1.0, np.abs(ref).max())
 
 
 def test_full_kitaev_l8_d8_adjoint(kk_full):
+    """Adjoint gradients at the benchmark's size and depth: a 24-gate circuit
+    drawn from the 28-entry pool (every generator type, all seven bonds) on
+    L=8 d=8; energy to 1e-5 |E| and every dE/dtheta_k to 1e-4 max(1, |g|_inf)
+    against the oracle's FP64 reverse sweep."""
     c, ho, hl, psi = kk_full
-    say("full kk adjoint")
-    ops, th = W.random_circuit(c["pool"], 3, seed=3)
+    say("full kk adjoint, 24 gates")
+    ops, th = W.random_circuit(c["pool"], 24, seed=3)
+    assert {o[0] for o in ops} == {"HR", "HI", "PI", "PR"}
     psi0 = W.random_state(8, 8, seed=0, sector=("parity", 0))
     x0 = dev(psi0)
     a, b = torch.empty_like(x0), torch.empty_like(x0)
     ws = lib.workspace(hl, len(c["pool"]), 64)
     E, n2, g = lib.energy_grad_adjoint(hl, ops, th, x0, a, b, ws)
-    Eref, gref, n2ref = O.energy_and_grad_adjoint(ho, psi0.astype(np.complex128), ops, th)
+    Eref, gref, n2ref = O.energy_and_grad_adjoint(ho, psi0.astype(np.complex128), ops, th, apply_h=O.apply_H_slices)
     assert abs(E - Eref) <= 1e-5 * abs(Eref)
     assert np.abs(g - gref).max() <= 1e-4 * max(1.0, np.abs(gref).max())
+
+
+def test_full_kitaev_l8_d8_adjoint_vs_fp64_finite_differences(kk_full):
+    """The GPU adjoint gradient of a 3-gate circuit at L=8 d=8 against FP64
+    central differences of the oracle's energy with the step 1e-4 of the
+    Kitaev-Kerr workload (no FP32 noise in the difference quotient)."""
+    c, ho, hl, psi = kk_full
+    ops, th = W.random_circuit(c["pool"], 3, seed=5)
+    psi0 = W.random_state(8, 8, seed=2, sector=("parity", 0))
+    x0 = dev(psi0)
+    a, b = torch.empty_like(x0), torch.empty_like(x0)
+    ws = lib.workspace(hl, len(c["pool"]), 64)
+    E, n2, g = lib.energy_grad_adjoint(hl, ops, th, x0, a, b, ws)
+    p0 = psi0.astype(np.complex128)
+
+    def e64(t):
+        s = O.ansatz_state(p0, ops, t, 8, 8)
+        return np.vdot(s, O.apply_H_slices(ho, s)).real / np.vdot(s, s).real
+
+    h = 1e-4
+    for k in range(len(ops)):
+        say("fp64 fd parameter", k)
+        tp, tm = th.copy(), th.copy()
+        tp[k] += h
+        tm[k] -= h
+        fd = (e64(tp) - e64(tm)) / (2 * h)
+        assert abs(fd - g[k]) <= 1e-4 * max(1.0, abs(fd)), (k, fd, g[k])
 
 
 def test_full_bose_hubbard_l8_d6_sampled():

@@ -325,6 +325,18 @@ def test_adjoint_matches_finite_differences():
     assert abs(n2 - 1) < 1e-13
     assert np.abs(g - fd).max() <= 1e-6 * max(1.0, np.abs(g).max())
     assert abs(E - O.energy_of(h, psi0, ops, th)) < 1e-13
+    # the sliced H psi gives the same sweep (open and ring lattices)
+    E2, g2, _ = O.energy_and_grad_adjoint(h, psi0, ops, th, apply_h=O.apply_H_slices)
+    assert abs(E2 - E) < 1e-12 and np.abs(g2 - g).max() < 1e-12
+    hr = O.Ham(4, 3, True, J=1.0, U=0.7, mu=0.2, Delta=0.3, K=0.1)
+    opr, thr = W.random_circuit(W.pool(4, "nn", True, W.KITAEV_TYPES), 6, 8)
+    p0 = W.random_state(4, 3, seed=1, sector=("parity", 0)).astype(complex)
+    Ea, ga, _ = O.energy_and_grad_adjoint(hr, p0, opr, thr)
+    Eb, gb, _ = O.energy_and_grad_adjoint(hr, p0, opr, thr, apply_h=O.apply_H_slices)
+    assert abs(Ea - Eb) < 1e-12 and np.abs(ga - gb).max() < 1e-12
+    pr = W.pool(4, "nn", True, W.KITAEV_TYPES)
+    psr = O.ansatz_state(p0, opr, thr, 4, 3)
+    assert np.abs(O.pool_gradients(hr, psr, pr) - O.pool_gradients(hr, psr, pr, apply_h=O.apply_H_slices)).max() < 1e-12
 
 
 # ---------------------------------------------------------------- ADAPT
