@@ -348,17 +348,23 @@ int fock_stencil_schedule_table(int L, int d, int scheme, int *order, int n);
 int fock_autotune_stencil(const fock_ham_t *ham, const void *psi, void *hpsi, void *ws, size_t ws_bytes,
                           fock_stream_t stream, const char *cache_path, int *best_scheme);
 
-/* Work split of the H psi kernel (same operator, Sec. III; same output and
- * energy/norm partials per tile):
+/* Work split of the H psi kernel (same operator, Sec. III):
  *   FOCK_STENCIL_ROWS  - one thread per row of d amplitudes (every d, L, boundary);
  *   FOCK_STENCIL_LANES - four lanes per row, two amplitudes each, with the bonds
  *      beyond the LDS tile read as 1 kB blocks at wavefront-uniform offsets.
  *      Used where d = 8, 4 <= L <= 10, the chain is open and the schedule is
  *      single-pass; elsewhere the row split runs.
- * The two sum a row's terms in different orders (FP32 rounding level).  Takes
- * effect for handles (ADAPT runs, sweeps) created after the call and for the
- * direct fock_apply_H calls; process-wide. */
-enum { FOCK_STENCIL_ROWS = 0, FOCK_STENCIL_LANES = 1 };
+ *   FOCK_STENCIL_SLAB  - (the default) two LDS-resident passes for L = 8, d = 8,
+ *      open or ring: a column pass applies the bonds among modes 4..7 (and the
+ *      ring bond) streaming mode 7 over 128-byte segments of the low modes and
+ *      writes them to hpsi; a row pass applies the bonds among modes 0..4
+ *      streaming mode 4 over contiguous 32 kB slices and adds them in place.
+ *      Every neighbour comes from LDS or registers; 40 B/amplitude of traffic
+ *      in long contiguous runs.  Elsewhere (and with schedule 4) the row split runs.
+ * The variants sum an amplitude's terms in different orders (FP32 rounding
+ * level).  Takes effect for handles (ADAPT runs, sweeps) created after the
+ * call and for the direct fock_apply_H calls; process-wide. */
+enum { FOCK_STENCIL_ROWS = 0, FOCK_STENCIL_LANES = 1, FOCK_STENCIL_SLAB = 2 };
 int fock_set_stencil_variant(int variant);
 int fock_get_stencil_variant(void);
 

@@ -22,6 +22,7 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 SOURCES = [
     "kernels_h.hip",
+    "stencil2.hip",
     "kernels_pool.hip",
     "kernels_gate.hip",
     "kernels_gate_da.hip",

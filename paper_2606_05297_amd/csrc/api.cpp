@@ -156,6 +156,7 @@ int make_ctx(const fock_ham_t &ham, uint32_t namp, int P, int n, void *ws, size_
       c->h.hi_m = apply_h_hi_modes(ham.L, ham.d, c->h.periodic_wrap);
     c->h.lanes = (stencil_variant() == FOCK_STENCIL_LANES && c->h.hi_m == 0 &&
                   lanes_stencil_ok(ham.L, ham.d, c->h.periodic_wrap)) ? 1 : 0;
+    c->h.slab = (stencil_variant() == FOCK_STENCIL_SLAB && c->h.hi_m == 0 && slab_stencil_ok(ham.L, ham.d)) ? 1 : 0;
   }
   c->s = s;
   c->ws = (char *)ws;
@@ -217,7 +218,8 @@ int apply_h_dev(Ctx &c, const float2 *psi, float2 *hpsi, double *res2) {
   int G = 0;
   {
     ProfScope ps(FOCK_K_APPLY_H, c.s, 16.0 * c.g.n_amp);
-    int rc = launch_apply_h(c.h, psi, hpsi, (double *)(c.ws + c.L.partial), &G, c.s);
+    int rc = c.h.slab ? launch_apply_h2(c.h, psi, hpsi, (double *)(c.ws + c.L.partial), &G, c.s)
+                      : launch_apply_h(c.h, psi, hpsi, (double *)(c.ws + c.L.partial), &G, c.s);
     if (rc) return rc;
   }
   return launch_reduce((const double *)(c.ws + c.L.partial), G, 2, res2, c.s);

@@ -52,6 +52,7 @@ struct HamArgs {
   int hi_m;           // two-pass stencil: bonds among the top hi_m modes (and the ring bond) are applied
                       // by a first pass that stages those modes in LDS; 0 = single pass
   int lanes;          // 1: lane-split stencil (d = 8, 4 <= L <= 10, open chain, single pass)
+  int slab;           // 1: two-pass slab stencil (L = 8, d = 8; stencil2.hip)
 };
 
 // ---------------------------------------------------------------- pool gradients
@@ -202,6 +203,12 @@ int stencil_schedule();
 // split covers (L, d, ring bond).
 int stencil_variant();
 bool lanes_stencil_ok(int L, int d, int periodic_wrap);
+bool slab_stencil_ok(int L, int d);
+// Two-pass slab H psi (stencil2.hip): column pass writes the bonds among modes
+// 4..7 into hpsi, row pass adds the rest in place; *nblocks pencils of
+// (<psi|H psi>, <psi|psi>) partials.
+int launch_apply_h2(const HamArgs &h, const float2 *psi, float2 *hpsi, double *partial, int *nblocks,
+                    hipStream_t s);
 
 struct ProfScope {
   int id;

@@ -351,9 +351,10 @@ static bool build_tile_order(int d, int ntiles, int scheme, std::vector<int> *ou
 
 int stencil_schedule() { return g_sched.load(); }
 
-static std::atomic<int> g_stencil_variant{FOCK_STENCIL_ROWS};
+static std::atomic<int> g_stencil_variant{FOCK_STENCIL_SLAB};
 int stencil_variant() { return g_stencil_variant.load(); }
 bool lanes_stencil_ok(int L, int d, int periodic_wrap) { return d == 8 && L >= 4 && L <= 10 && !periodic_wrap; }
+bool slab_stencil_ok(int L, int d) { return L == 8 && d == 8; }
 
 int stencil_order_table(int L, int d, int ntiles, const int **order) {
   *order = nullptr;
@@ -389,8 +390,8 @@ extern "C" int fock_set_stencil_schedule(int scheme) {
 extern "C" int fock_get_stencil_schedule(void) { return fock::g_sched.load(); }
 
 extern "C" int fock_set_stencil_variant(int variant) {
-  if (variant != FOCK_STENCIL_ROWS && variant != FOCK_STENCIL_LANES)
-    return fock::set_error(FOCK_ERR_ARG, "stencil variant %d is neither ROWS (0) nor LANES (1)", variant);
+  if (variant != FOCK_STENCIL_ROWS && variant != FOCK_STENCIL_LANES && variant != FOCK_STENCIL_SLAB)
+    return fock::set_error(FOCK_ERR_ARG, "stencil variant %d is not ROWS (0), LANES (1) or SLAB (2)", variant);
   fock::g_stencil_variant.store(variant);
   return FOCK_OK;
 }

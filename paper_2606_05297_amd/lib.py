@@ -703,12 +703,13 @@ def get_stencil_schedule() -> int:
     return int(load().fock_get_stencil_schedule())
 
 
-STENCIL_ROWS, STENCIL_LANES = 0, 1
+STENCIL_ROWS, STENCIL_LANES, STENCIL_SLAB = 0, 1, 2
 
 
 def set_stencil_variant(variant: int):
     """Work split of the H psi kernel: 0 = one thread per row, 1 = four lanes per
-    row (d = 8, 4 <= L <= 10, open chains; elsewhere the row split runs)."""
+    row (d = 8, 4 <= L <= 10, open chains), 2 = two-pass slab stencil (the
+    default; L = 8, d = 8); elsewhere the row split runs."""
     _check(load().fock_set_stencil_variant(int(variant)))
 
 

@@ -177,15 +177,18 @@ def test_stencil_schedules_are_permutations():
 
 
 def test_stencil_variant_setter():
-    """The H psi work split is a process-wide setting: both values round-trip,
-    anything else is rejected and leaves the setting unchanged."""
+    """The H psi work split is a process-wide setting: the three values
+    round-trip, anything else is rejected and leaves the setting unchanged; the
+    two-pass slab stencil is the default."""
     prev = lib.get_stencil_variant()
+    assert prev == lib.STENCIL_SLAB
     try:
-        for v in (lib.STENCIL_LANES, lib.STENCIL_ROWS):
+        for v in (lib.STENCIL_LANES, lib.STENCIL_SLAB, lib.STENCIL_ROWS):
             lib.set_stencil_variant(v)
             assert lib.get_stencil_variant() == v
-        with pytest.raises(lib.FockError):
-            lib.set_stencil_variant(2)
+        for bad in (3, -1):
+            with pytest.raises(lib.FockError):
+                lib.set_stencil_variant(bad)
         assert lib.get_stencil_variant() == lib.STENCIL_ROWS
     finally:
         lib.set_stencil_variant(prev)

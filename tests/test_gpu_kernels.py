@@ -340,7 +340,51 @@ def kk_full():
     return c, ho, hl, psi
 
 
-@pytest.mark.parametrize("stencil", [0, 1], indirect=True, ids=["rows", "lanes"])
+SLAB_CASES = [
+    # (periodic, J, U, mu, Delta, K, state sector): the benchmark's chain, and a ring with every term on
+    (False, 1.0, 0.0, 0.0, 0.5, 0.2, ("parity", 0)),
+    (True, 0.8, 1.1, 0.3, 0.45, 0.15, None),
+]
+
+
+@pytest.mark.parametrize("case", SLAB_CASES, ids=["kk_open", "ring_all_terms"])
+def test_slab_stencil_full_vector_l8_d8(case):
+    """The two-pass slab H psi (default at L=8, d=8) against the oracle on all
+    16,777,216 amplitudes: open Kitaev-Kerr chain on an even-parity state, and
+    a ring with hopping, pairing, on-site U, K and mu on a state with every
+    amplitude non-zero (all boundary digits n_r = 0, 7 exercised).  Also the
+    energy, the norm, and agreement with the one-pass row kernel."""
+    per, J, U, mu, Dl, K, sector = case
+    ho, hl = ham_pair(8, 8, per, J, U, mu, Dl, K)
+    say("slab full vector", case)
+    assert lib.get_stencil_variant() == lib.STENCIL_SLAB
+    psi = W.random_state(8, 8, seed=7, sector=sector)
+    x, y = dev(psi), torch.empty(8**8, dtype=torch.complex64, device="cuda")
+    ws = lib.workspace(hl, 0, 0)
+    y.fill_(float("nan"))  # every output amplitude must be written
+    E, n2 = lib.apply_H(hl, x, y, ws)
+    got = host(y)
+    p128 = psi.astype(np.complex128)
+    ref = O.apply_H_slices(ho, p128)
+    assert np.isfinite(got).all()
+    assert np.abs(got - ref).max() <= 2e-5 * np.abs(ref).max()
+    Eref = np.vdot(p128, ref).real
+    assert abs(E - Eref) <= 1e-5 * max(1.0, abs(Eref))
+    assert abs(n2 - np.vdot(p128, p128).real) <= 1e-6
+    if sector is not None:  # H keeps the parity sector: odd amplitudes exactly zero
+        odd = O.sector_indices(8, 8, ("parity", 1))
+        assert np.count_nonzero(got[odd]) == 0
+    lib.set_stencil_variant(lib.STENCIL_ROWS)
+    try:
+        y2 = torch.empty_like(y)
+        E2, _ = lib.apply_H(hl, x, y2, ws)
+    finally:
+        lib.set_stencil_variant(lib.STENCIL_SLAB)
+    assert np.abs(host(y2) - got).max() <= 2e-5 * np.abs(ref).max()
+    assert abs(E2 - E) <= 1e-5 * max(1.0, abs(E))
+
+
+@pytest.mark.parametrize("stencil", [0, 1, 2], indirect=True, ids=["rows", "lanes", "slab"])
 def test_full_kitaev_l8_d8_apply_H_sampled_and_energy(kk_full, stencil):
     c, ho, hl, psi = kk_full
     say("full kk apply_H, stencil", stencil)
