@@ -503,6 +503,50 @@ int pool_dev(Ctx &c, const fock_op_t *pool, int P, const float2 *psi, const floa
       pp.slot[op.type] = (int16_t)slot;
     }
     if (k1 == k0) return set_error(FOCK_ERR_ARG, "cannot schedule pool entry %d", k0);
+    // slab kernels (L = 8, d = 8): nearest-neighbour pairs, the ring pair and diagonal entries
+    if (c.h.slab && (!pairs.empty() || !diags.empty())) {
+      SlabPool sp;
+      memset(&sp, 0, sizeof(sp));
+      for (int p = 0; p < 8; ++p)
+        for (int t = 0; t < 5; ++t) sp.slot[p][t] = -1;
+      bool ok = (int)diags.size() <= kSlabDiag;
+      for (const PoolPair &pp : pairs) {
+        int p = -1;
+        if (pp.j == pp.i + 1 && pp.i <= 6) p = pp.i;
+        else if (pp.i == 0 && pp.j == 7 && c.h.periodic_wrap) p = 7;
+        if (p < 0) {
+          ok = false;
+          break;
+        }
+        for (int t = 0; t < 5; ++t) sp.slot[p][t] = pp.slot[t];
+      }
+      if (ok) {
+        sp.ndiag = (int)diags.size();
+        for (int q = 0; q < sp.ndiag; ++q) sp.diag[q] = diags[q];
+        sp.nslots = k1 - k0;
+        int G = 0;
+        {
+          ProfScope ps(FOCK_K_POOL, c.s, 16.0 * c.g.n_amp);
+          int rc = launch_pool_slab(sp, c.h, psi, hpsi, part, &G, c.s);
+          if (rc) return rc;
+        }
+        int rc = launch_reduce(part, G, sp.nslots, res + k0, c.s);
+        if (rc) return rc;
+        for (int k : sq) {
+          const fock_op_t &op = pool[k];
+          int G1 = 0;
+          {
+            ProfScope ps(FOCK_K_POOL, c.s, 16.0 * c.g.n_amp);
+            rc = launch_pool1(c.g, op.i, c.T.A1[op.type == FOCK_SR ? 0 : 1], psi, hpsi, part, &G1, c.s);
+            if (rc) return rc;
+          }
+          rc = launch_reduce(part, G1, 1, res + k, c.s);
+          if (rc) return rc;
+        }
+        k0 = k1;
+        continue;
+      }
+    }
     a.npairs = (int)pairs.size();
     a.ndiag = (int)diags.size();
     a.nslots = k1 - k0;

@@ -64,6 +64,16 @@ struct PoolPair {
 struct PoolDiag {
   int16_t r, type, slot, r2;  // KERR / ROT on mode r (r2 = -1), CK on modes (r, r2)
 };
+// Pool entries scored by the slab kernels (L = 8, d = 8): slot[p][type] for
+// the pairs p = 0..6 ~ (p, p + 1) and p = 7 ~ the ring pair (0, 7), types
+// HR..PI (-1 = absent); up to kSlabDiag diagonal entries (KERR, ROT, CK).
+constexpr int kSlabDiag = 16;
+struct SlabPool {
+  int16_t slot[8][5];
+  PoolDiag diag[kSlabDiag];
+  int ndiag, nslots;
+};
+
 struct PoolArgs {
   int L, d, nrows, npairs, ndiag, nslots;
   int srow[kMaxL];
@@ -209,6 +219,11 @@ bool slab_stencil_ok(int L, int d);
 // (<psi|H psi>, <psi|psi>) partials.
 int launch_apply_h2(const HamArgs &h, const float2 *psi, float2 *hpsi, double *partial, int *nblocks,
                     hipStream_t s);
+// Slab pool scoring (stencil2.hip): one FP64 partial per (workgroup, slot),
+// pool_slab_blocks() workgroups, slot values already doubled.
+int launch_pool_slab(const SlabPool &sp, const HamArgs &h, const float2 *psi, const float2 *hpsi, double *partial,
+                     int *nblocks, hipStream_t s);
+int pool_slab_blocks();
 
 struct ProfScope {
   int id;

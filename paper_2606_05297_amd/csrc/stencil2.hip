@@ -355,6 +355,349 @@ __global__ __launch_bounds__(kRowThreads) void k_h8_row(const float2 *__restrict
   }
 }
 
+// ---------------------------------------------------------------- pool scoring
+//
+// Eq. (grad), g_k = 2 Re <H psi | A_k psi>, on the same two slab shapes: the
+// row shape scores the pairs (0,1), (1,2), (2,3), (3,4) and every diagonal
+// entry (KERR, ROT, CK), the column shape the pairs (4,5), (5,6), (6,7) and
+// the ring pair (0,7).  For a pair (i, j) the four ladder neighbours of psi,
+//   u1 = dn(n_i) up(n_j) psi[n - e_i + e_j]   (a_i^+ a_j)
+//   u2 = up(n_i) dn(n_j) psi[n + e_i - e_j]   (a_j^+ a_i)
+//   w1 = up(n_i) up(n_j) psi[n + e_i + e_j]   (a_i a_j)
+//   w2 = dn(n_i) dn(n_j) psi[n - e_i - e_j]   (a_i^+ a_j^+)
+// give (with c = conj(h[n]) x, h = H psi)
+//   HR: Re(c(u1) - c(u2)),  HI: -Im(c(u1) + c(u2)),  DH: -Im(n_i c(u1) + (n_i + 1) c(u2)),
+//   PR: Re(c(w1) - c(w2)),  PI: -Im(c(w1) + c(w2)),
+// summed over n and doubled; a diagonal generator i f(N) gives -2 f(n) Im(conj(h) psi).
+// Only psi needs neighbours (LDS slice and registers); H psi is read at each
+// thread's own amplitudes.  The streamed pair's terms couple slice k with
+// k - 1: at step k the thread pairs its own H psi of slice k with its psi of
+// slice k - 1 and its H psi of slice k - 1 with its psi of slice k.
+
+struct PairSums {  // per-thread sums of one pair, one per generator type
+  float hr = 0.f, hi = 0.f, dh = 0.f, pr = 0.f, pi = 0.f;
+};
+
+// Accumulate one amplitude's four neighbour terms (already multiplied by their
+// ladder factors) against h; ni = n_i of the amplitude.
+__device__ __forceinline__ void pair_terms(PairSums &S, const float2 &h, const float2 &u1, const float2 &u2,
+                                           const float2 &w1, const float2 &w2, float ni, bool X, bool Y, bool Dh) {
+  if (X || Dh) {
+    const float r1 = h.x * u1.x + h.y * u1.y, i1 = h.x * u1.y - h.y * u1.x;
+    const float r2 = h.x * u2.x + h.y * u2.y, i2 = h.x * u2.y - h.y * u2.x;
+    if (X) {
+      S.hr += r1 - r2;
+      S.hi -= i1 + i2;
+    }
+    if (Dh) S.dh -= ni * i1 + (ni + 1.f) * i2;
+  }
+  if (Y) {
+    const float r1 = h.x * w1.x + h.y * w1.y, i1 = h.x * w1.y - h.y * w1.x;
+    const float r2 = h.x * w2.x + h.y * w2.y, i2 = h.x * w2.y - h.y * w2.x;
+    S.pr += r1 - r2;
+    S.pi -= i1 + i2;
+  }
+}
+
+__device__ __forceinline__ float2 cmul(float c, float2 v) { return make_float2(c * v.x, c * v.y); }
+__device__ __forceinline__ float2 lo2(const float4 &v) { return make_float2(v.x, v.y); }
+__device__ __forceinline__ float2 hi2(const float4 &v) { return make_float2(v.z, v.w); }
+
+__device__ __forceinline__ bool want_x(const SlabPool &sp, int p) {
+  return sp.slot[p][FOCK_HR] >= 0 || sp.slot[p][FOCK_HI] >= 0;
+}
+__device__ __forceinline__ bool want_y(const SlabPool &sp, int p) {
+  return sp.slot[p][FOCK_PR] >= 0 || sp.slot[p][FOCK_PI] >= 0;
+}
+__device__ __forceinline__ bool want_d(const SlabPool &sp, int p) { return sp.slot[p][FOCK_DH] >= 0; }
+__device__ __forceinline__ bool want_any(const SlabPool &sp, int p) {
+  return want_x(sp, p) || want_y(sp, p) || want_d(sp, p);
+}
+
+// Block reduction of per-thread slot values: red[w][slot] per wavefront (FP64
+// over the lanes), then one FP64 partial per slot in a fixed order.
+template <int NT>
+__device__ __forceinline__ void slot_add(double (*red)[kMaxSlots], int slot, float v) {
+  if (slot < 0) return;
+  const double s = wave_sum_d((double)v);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6][slot] += s;
+}
+__device__ __forceinline__ void pair_slots(double (*red)[kMaxSlots], const SlabPool &sp, int p, const PairSums &S) {
+  slot_add<0>(red, sp.slot[p][FOCK_HR], S.hr);
+  slot_add<0>(red, sp.slot[p][FOCK_HI], S.hi);
+  slot_add<0>(red, sp.slot[p][FOCK_DH], S.dh);
+  slot_add<0>(red, sp.slot[p][FOCK_PR], S.pr);
+  slot_add<0>(red, sp.slot[p][FOCK_PI], S.pi);
+}
+template <int NT>
+__device__ __forceinline__ void write_slots(double (*red)[kMaxSlots], int nslots, double *__restrict__ out) {
+  __syncthreads();
+  for (int s = threadIdx.x; s < nslots; s += NT) {
+    double r = 0.0;
+#pragma unroll
+    for (int w = 0; w < NT / 64; ++w) r += red[w][s];
+    out[s] = 2.0 * r;
+  }
+}
+
+// Row shape: pencil (n5, n6, n7) streaming n4; thread (n0, n1, n2), registers n3.
+__global__ __launch_bounds__(kRowThreads) void k_pool8_row(const float2 *__restrict__ psi,
+                                                           const float2 *__restrict__ hpsi,
+                                                           double *__restrict__ partial, SlabPool sp, HamArgs hcoef) {
+  __shared__ float2 tile[4096];
+  __shared__ double red[kRowThreads / 64][kMaxSlots];
+  const int t = threadIdx.x;
+  for (int e = t; e < (kRowThreads / 64) * kMaxSlots; e += kRowThreads) (&red[0][0])[e] = 0.0;
+  const Coef C = make_coef(hcoef);
+  const int b = blockIdx.x;
+  const int p = (b & 7) * (kPencils / 8) + (b >> 3);
+  const int n0 = t & 7, n1 = (t >> 3) & 7, n2 = t >> 6;
+  const int n5 = p & 7, n6 = (p >> 3) & 7, n7 = p >> 6;
+  const size_t base = (size_t)t + (size_t)p * 8 * kS4;
+  auto ti = [&](int a0, int a1, int a2, int a3) { return (a0 & 7) + 8 * (a1 & 7) + 64 * (a2 & 7) + 512 * a3; };
+  const bool on01 = want_any(sp, 0), on12 = want_any(sp, 1), on23 = want_any(sp, 2), on34 = want_any(sp, 3);
+  PairSums S[4];
+  float dsum[kSlabDiag];
+#pragma unroll
+  for (int q = 0; q < kSlabDiag; ++q) dsum[q] = 0.f;
+  float2 own[8], prev[8], h[8], hp[8], nxt[8], hn[8];
+#pragma unroll
+  for (int a = 0; a < 8; ++a) {
+    own[a] = psi[base + (size_t)a * 512];
+    h[a] = hpsi[base + (size_t)a * 512];
+  }
+  __syncthreads();  // red cleared
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    if (k > 0) __syncthreads();
+#pragma unroll
+    for (int a = 0; a < 8; ++a) tile[t + 512 * a] = own[a];
+    if (k < 7) {
+#pragma unroll
+      for (int a = 0; a < 8; ++a) {
+        nxt[a] = psi[base + (size_t)a * 512 + (size_t)(k + 1) * kS4];
+        hn[a] = hpsi[base + (size_t)a * 512 + (size_t)(k + 1) * kS4];
+      }
+    }
+    __syncthreads();
+    if (on01) {
+      const bool X = want_x(sp, 0), Y = want_y(sp, 0), Dh = want_d(sp, 0);
+      const float ca = C.dn(n0) * C.up(n1), cb = C.up(n0) * C.dn(n1), cc = C.up(n0) * C.up(n1),
+                  cd = C.dn(n0) * C.dn(n1);
+#pragma unroll
+      for (int a = 0; a < 8; ++a) {
+        const float2 u = tile[ti(n0, n1 + 1, n2, a)], v = tile[ti(n0, n1 - 1, n2, a)];
+        const float2 ul = make_float2(dpp_from_left(u.x), dpp_from_left(u.y));
+        const float2 ur = make_float2(dpp_from_right(u.x), dpp_from_right(u.y));
+        const float2 vl = make_float2(dpp_from_left(v.x), dpp_from_left(v.y));
+        const float2 vr = make_float2(dpp_from_right(v.x), dpp_from_right(v.y));
+        pair_terms(S[0], h[a], cmul(ca, ul), cmul(cb, vr), cmul(cc, ur), cmul(cd, vl), (float)n0, X, Y, Dh);
+      }
+    }
+    if (on12) {
+      const bool X = want_x(sp, 1), Y = want_y(sp, 1), Dh = want_d(sp, 1);
+      const float ca = C.dn(n1) * C.up(n2), cb = C.up(n1) * C.dn(n2), cc = C.up(n1) * C.up(n2),
+                  cd = C.dn(n1) * C.dn(n2);
+#pragma unroll
+      for (int a = 0; a < 8; ++a)
+        pair_terms(S[1], h[a], cmul(ca, tile[ti(n0, n1 - 1, n2 + 1, a)]), cmul(cb, tile[ti(n0, n1 + 1, n2 - 1, a)]),
+                   cmul(cc, tile[ti(n0, n1 + 1, n2 + 1, a)]), cmul(cd, tile[ti(n0, n1 - 1, n2 - 1, a)]), (float)n1,
+                   X, Y, Dh);
+    }
+    if (on23) {
+      const bool X = want_x(sp, 2), Y = want_y(sp, 2), Dh = want_d(sp, 2);
+      float2 vm[8], vp[8];
+#pragma unroll
+      for (int a = 0; a < 8; ++a) {
+        vm[a] = tile[ti(n0, n1, n2 - 1, a)];
+        vp[a] = tile[ti(n0, n1, n2 + 1, a)];
+      }
+      const float dm = C.dn(n2), um = C.up(n2);
+      const float2 z = make_float2(0.f, 0.f);
+#pragma unroll
+      for (int a = 0; a < 8; ++a) {
+        const float2 u1 = a < 7 ? cmul(dm * C.up(a), vm[a + 1]) : z;  // reads (n2 - 1, n3 + 1)
+        const float2 u2 = a > 0 ? cmul(um * C.dn(a), vp[a - 1]) : z;  // reads (n2 + 1, n3 - 1)
+        const float2 w1 = a < 7 ? cmul(um * C.up(a), vp[a + 1]) : z;  // reads (n2 + 1, n3 + 1)
+        const float2 w2 = a > 0 ? cmul(dm * C.dn(a), vm[a - 1]) : z;  // reads (n2 - 1, n3 - 1)
+        pair_terms(S[2], h[a], u1, u2, w1, w2, (float)n2, X, Y, Dh);
+      }
+    }
+    if (on34 && k > 0) {
+      const bool X = want_x(sp, 3), Y = want_y(sp, 3), Dh = want_d(sp, 3);
+      const float2 z = make_float2(0.f, 0.f);
+#pragma unroll
+      for (int a = 0; a < 8; ++a) {
+        // amplitudes of slice k read slice k - 1: a4^+ a3 (n3 + 1, n4 - 1), a3^+ a4^+ (n3 - 1, n4 - 1)
+        const float2 u2 = a < 7 ? cmul(C.up(a) * C.dn(k), prev[a + 1]) : z;
+        const float2 w2 = a > 0 ? cmul(C.dn(a) * C.dn(k), prev[a - 1]) : z;
+        pair_terms(S[3], h[a], z, u2, z, w2, (float)a, X, Y, Dh);
+        // amplitudes of slice k - 1 read slice k: a3^+ a4 (n3 - 1, n4 + 1), a3 a4 (n3 + 1, n4 + 1)
+        const float2 u1 = a > 0 ? cmul(C.dn(a) * C.up(k - 1), own[a - 1]) : z;
+        const float2 w1 = a < 7 ? cmul(C.up(a) * C.up(k - 1), own[a + 1]) : z;
+        pair_terms(S[3], hp[a], u1, z, w1, z, (float)a, X, Y, Dh);
+      }
+    }
+    // diagonal entries: -2 f(n) Im(conj(h) psi) (the factor 2 is applied at the end)
+#pragma unroll
+    for (int q = 0; q < kSlabDiag; ++q) {
+      if (q >= sp.ndiag) break;
+      const PoolDiag dq = sp.diag[q];
+      auto dig = [&](int r, int a) -> float {
+        const int v = r == 0 ? n0 : r == 1 ? n1 : r == 2 ? n2 : r == 3 ? a : r == 4 ? k : r == 5 ? n5 : r == 6 ? n6 : n7;
+        return (float)v;
+      };
+#pragma unroll
+      for (int a = 0; a < 8; ++a) {
+        const float nr = dig(dq.r, a);
+        const float f = dq.type == FOCK_KERR ? nr * nr : dq.type == FOCK_ROT ? nr : nr * dig(dq.r2, a);
+        dsum[q] -= f * (h[a].x * own[a].y - h[a].y * own[a].x);
+      }
+    }
+#pragma unroll
+    for (int a = 0; a < 8; ++a) {
+      prev[a] = own[a];
+      hp[a] = h[a];
+      if (k < 7) {
+        own[a] = nxt[a];
+        h[a] = hn[a];
+      }
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < 4; ++q) pair_slots(red, sp, q, S[q]);
+#pragma unroll
+  for (int q = 0; q < kSlabDiag; ++q)
+    if (q < sp.ndiag) slot_add<0>(red, sp.diag[q].slot, dsum[q]);
+  write_slots<kRowThreads>(red, sp.nslots, partial + (size_t)p * sp.nslots);
+}
+
+// Column shape: chunk j streaming n7; thread (l, n4, n5) with amplitudes 2l,
+// 2l + 1 of the chunk, registers n6.  The streamed pairs couple slices k and
+// k + 1 through the prefetched slice k + 1 (psi and H psi), so no registers
+// of slice k - 1 are kept.
+template <bool RING>
+__global__ __launch_bounds__(kColThreads) void k_pool8_col(const float4 *__restrict__ psi,
+                                                           const float4 *__restrict__ hpsi,
+                                                           double *__restrict__ partial, SlabPool sp, HamArgs hcoef) {
+  __shared__ float4 sl[4096];
+  __shared__ double red[kColThreads / 64][kMaxSlots];
+  const int t = threadIdx.x;
+  for (int e = t; e < (kColThreads / 64) * kMaxSlots; e += kColThreads) (&red[0][0])[e] = 0.0;
+  const Coef C = make_coef(hcoef);
+  const int b = blockIdx.x;
+  const int j = (b & 7) * (kCols / 8) + (b >> 3);
+  const int l = t & 7, n4 = (t >> 3) & 7, n5 = t >> 6;
+  constexpr int S6 = kS4 / 2 * 64, S7 = kS4 / 2 * 512;
+  const size_t base = (size_t)(8 * j + l) + (size_t)(kS4 / 2) * (n4 + 8 * n5);
+  auto li = [&](int a4, int a5, int a6) { return (((a6 * 8) + (a5 & 7)) * 8 + (a4 & 7)) * 8 + l; };
+  const bool on45 = want_any(sp, 4), on56 = want_any(sp, 5), on67 = want_any(sp, 6), on07 = RING && want_any(sp, 7);
+  const float q0 = (float)(2 * (l & 3)), q1 = q0 + 1.f;  // n0 of the two amplitudes
+  const int iq0 = 2 * (l & 3), iq1 = iq0 + 1;
+  const float2 z = make_float2(0.f, 0.f);
+  PairSums S[4];
+  float4 own[8], h[8], nxt[8], hn[8];
+#pragma unroll
+  for (int a = 0; a < 8; ++a) {
+    own[a] = psi[base + (size_t)a * S6];
+    h[a] = hpsi[base + (size_t)a * S6];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    if (k > 0) __syncthreads();
+#pragma unroll
+    for (int a = 0; a < 8; ++a) sl[li(n4, n5, a)] = own[a];
+    if (k < 7) {
+#pragma unroll
+      for (int a = 0; a < 8; ++a) {
+        nxt[a] = psi[base + (size_t)a * S6 + (size_t)(k + 1) * S7];
+        hn[a] = hpsi[base + (size_t)a * S6 + (size_t)(k + 1) * S7];
+      }
+    }
+    __syncthreads();
+    if (on45) {
+      const bool X = want_x(sp, 4), Y = want_y(sp, 4), Dh = want_d(sp, 4);
+      const float ca = C.dn(n4) * C.up(n5), cb = C.up(n4) * C.dn(n5), cc = C.up(n4) * C.up(n5),
+                  cd = C.dn(n4) * C.dn(n5);
+#pragma unroll
+      for (int a = 0; a < 8; ++a) {
+        const float4 va = sl[li(n4 - 1, n5 + 1, a)], vb = sl[li(n4 + 1, n5 - 1, a)], vc = sl[li(n4 + 1, n5 + 1, a)],
+                     vd = sl[li(n4 - 1, n5 - 1, a)];
+        pair_terms(S[0], lo2(h[a]), cmul(ca, lo2(va)), cmul(cb, lo2(vb)), cmul(cc, lo2(vc)), cmul(cd, lo2(vd)),
+                   (float)n4, X, Y, Dh);
+        pair_terms(S[0], hi2(h[a]), cmul(ca, hi2(va)), cmul(cb, hi2(vb)), cmul(cc, hi2(vc)), cmul(cd, hi2(vd)),
+                   (float)n4, X, Y, Dh);
+      }
+    }
+    if (on56) {
+      const bool X = want_x(sp, 5), Y = want_y(sp, 5), Dh = want_d(sp, 5);
+      const float dm = C.dn(n5), um = C.up(n5);
+#pragma unroll
+      for (int a = 0; a < 8; ++a) {
+        const float cu1 = a < 7 ? dm * C.up(a) : 0.f, cu2 = a > 0 ? um * C.dn(a) : 0.f;
+        const float cw1 = a < 7 ? um * C.up(a) : 0.f, cw2 = a > 0 ? dm * C.dn(a) : 0.f;
+        const float4 vmn = sl[li(n4, n5 - 1, a < 7 ? a + 1 : a)];  // (n5 - 1, n6 + 1)
+        const float4 vpp = sl[li(n4, n5 + 1, a > 0 ? a - 1 : a)];  // (n5 + 1, n6 - 1)
+        const float4 vpn = sl[li(n4, n5 + 1, a < 7 ? a + 1 : a)];  // (n5 + 1, n6 + 1)
+        const float4 vmp = sl[li(n4, n5 - 1, a > 0 ? a - 1 : a)];  // (n5 - 1, n6 - 1)
+        pair_terms(S[1], lo2(h[a]), cmul(cu1, lo2(vmn)), cmul(cu2, lo2(vpp)), cmul(cw1, lo2(vpn)),
+                   cmul(cw2, lo2(vmp)), (float)n5, X, Y, Dh);
+        pair_terms(S[1], hi2(h[a]), cmul(cu1, hi2(vmn)), cmul(cu2, hi2(vpp)), cmul(cw1, hi2(vpn)),
+                   cmul(cw2, hi2(vmp)), (float)n5, X, Y, Dh);
+      }
+    }
+    if (on67 && k < 7) {
+      const bool X = want_x(sp, 6), Y = want_y(sp, 6), Dh = want_d(sp, 6);
+#pragma unroll
+      for (int a = 0; a < 8; ++a) {
+        // slice k reads slice k + 1: a6^+ a7 (n6 - 1, n7 + 1), a6 a7 (n6 + 1, n7 + 1)
+        const float cu1 = a > 0 ? C.dn(a) * C.up(k) : 0.f, cw1 = a < 7 ? C.up(a) * C.up(k) : 0.f;
+        const float4 xu = nxt[a > 0 ? a - 1 : a], xw = nxt[a < 7 ? a + 1 : a];
+        pair_terms(S[2], lo2(h[a]), cmul(cu1, lo2(xu)), z, cmul(cw1, lo2(xw)), z, (float)a, X, Y, Dh);
+        pair_terms(S[2], hi2(h[a]), cmul(cu1, hi2(xu)), z, cmul(cw1, hi2(xw)), z, (float)a, X, Y, Dh);
+        // slice k + 1 reads slice k: a7^+ a6 (n6 + 1, n7 - 1), a6^+ a7^+ (n6 - 1, n7 - 1)
+        const float cu2 = a < 7 ? C.up(a) * C.dn(k + 1) : 0.f, cw2 = a > 0 ? C.dn(a) * C.dn(k + 1) : 0.f;
+        const float4 ou = own[a < 7 ? a + 1 : a], ow = own[a > 0 ? a - 1 : a];
+        pair_terms(S[2], lo2(hn[a]), z, cmul(cu2, lo2(ou)), z, cmul(cw2, lo2(ow)), (float)a, X, Y, Dh);
+        pair_terms(S[2], hi2(hn[a]), z, cmul(cu2, hi2(ou)), z, cmul(cw2, hi2(ow)), (float)a, X, Y, Dh);
+      }
+    }
+    if (on07 && k < 7) {
+      const bool X = want_x(sp, 7), Y = want_y(sp, 7), Dh = want_d(sp, 7);
+      const float uk = C.up(k), dk = C.dn(k + 1);
+#pragma unroll
+      for (int a = 0; a < 8; ++a) {
+        // n0 -+ 1 inside the chunk: the thread's other amplitude or lanes l -+ 1 (weight 0 past n0 = 0, 7)
+        const float2 xl = make_float2(dpp_from_left(nxt[a].z), dpp_from_left(nxt[a].w));
+        const float2 xr = make_float2(dpp_from_right(nxt[a].x), dpp_from_right(nxt[a].y));
+        const float2 ol = make_float2(dpp_from_left(own[a].z), dpp_from_left(own[a].w));
+        const float2 orr = make_float2(dpp_from_right(own[a].x), dpp_from_right(own[a].y));
+        // slice k reads slice k + 1: a0^+ a7 (n0 - 1, n7 + 1), a0 a7 (n0 + 1, n7 + 1)
+        pair_terms(S[3], lo2(h[a]), cmul(C.dn(iq0) * uk, xl), z, cmul(C.up(iq0) * uk, hi2(nxt[a])), z, q0, X, Y,
+                   Dh);
+        pair_terms(S[3], hi2(h[a]), cmul(C.dn(iq1) * uk, lo2(nxt[a])), z, cmul(C.up(iq1) * uk, xr), z, q1, X, Y,
+                   Dh);
+        // slice k + 1 reads slice k: a7^+ a0 (n0 + 1, n7 - 1), a0^+ a7^+ (n0 - 1, n7 - 1)
+        pair_terms(S[3], lo2(hn[a]), z, cmul(C.up(iq0) * dk, hi2(own[a])), z, cmul(C.dn(iq0) * dk, ol), q0, X, Y,
+                   Dh);
+        pair_terms(S[3], hi2(hn[a]), z, cmul(C.up(iq1) * dk, orr), z, cmul(C.dn(iq1) * dk, lo2(own[a])), q1, X, Y,
+                   Dh);
+      }
+    }
+    if (k < 7) {
+#pragma unroll
+      for (int a = 0; a < 8; ++a) {
+        own[a] = nxt[a];
+        h[a] = hn[a];
+      }
+    }
+  }
+#pragma unroll
+  for (int p4 = 0; p4 < 4; ++p4) pair_slots(red, sp, 4 + p4, S[p4]);
+  write_slots<kColThreads>(red, sp.nslots, partial + (size_t)(kPencils + j) * sp.nslots);
+}
+
 }  // namespace
 
 bool apply_h2_supported(const HamArgs &h) { return slab_stencil_ok(h.L, h.d); }
@@ -372,6 +715,25 @@ int launch_apply_h2(const HamArgs &h, const float2 *psi, float2 *hpsi, double *p
   hipLaunchKernelGGL(k_h8_row, dim3(kPencils), dim3(kRowThreads), 0, s, psi, hpsi, partial, h);
   FOCK_HIP(hipGetLastError());
   *nblocks = apply_h2_blocks();
+  return FOCK_OK;
+}
+
+int pool_slab_blocks() { return kPencils + kCols; }
+
+int launch_pool_slab(const SlabPool &sp, const HamArgs &h, const float2 *psi, const float2 *hpsi, double *partial,
+                     int *nblocks, hipStream_t s) {
+  if (!apply_h2_supported(h)) return set_error(FOCK_ERR_UNSUPPORTED, "slab pool scoring needs L = 8, d = 8");
+  if (sp.nslots < 1 || sp.nslots > kMaxSlots || sp.ndiag < 0 || sp.ndiag > kSlabDiag)
+    return set_error(FOCK_ERR_ARG, "slab pool: %d slots, %d diagonal entries", sp.nslots, sp.ndiag);
+  hipLaunchKernelGGL(k_pool8_row, dim3(kPencils), dim3(kRowThreads), 0, s, psi, hpsi, partial, sp, h);
+  if (h.periodic_wrap)
+    hipLaunchKernelGGL(k_pool8_col<true>, dim3(kCols), dim3(kColThreads), 0, s, (const float4 *)psi,
+                       (const float4 *)hpsi, partial, sp, h);
+  else
+    hipLaunchKernelGGL(k_pool8_col<false>, dim3(kCols), dim3(kColThreads), 0, s, (const float4 *)psi,
+                       (const float4 *)hpsi, partial, sp, h);
+  FOCK_HIP(hipGetLastError());
+  *nblocks = pool_slab_blocks();
   return FOCK_OK;
 }
 

@@ -384,6 +384,37 @@ def test_slab_stencil_full_vector_l8_d8(case):
     assert abs(E2 - E) <= 1e-5 * max(1.0, abs(E))
 
 
+def test_slab_pool_ring_all_types_l8_d8():
+    """Slab pool scoring (default at L=8, d=8) on a ring with hopping, pairing,
+    U, K and mu: every two-mode generator type (HR, HI, DH, PR, PI) on all
+    eight nearest-neighbour pairs including the ring pair (0, 7), plus Kerr,
+    rotation and cross-Kerr entries on several modes, on a state with every
+    amplitude non-zero; against the oracle's 2 Re <H psi|A_k psi> (FP64) and
+    against the one-pass pool kernel."""
+    per, J, U, mu, Dl, K = True, 0.8, 1.1, 0.3, 0.45, 0.15
+    ho, hl = ham_pair(8, 8, per, J, U, mu, Dl, K)
+    pool = W.pool(8, "nn", True, ("HR", "HI", "DH", "PR", "PI"))
+    pool += [("KERR", 0, -1), ("ROT", 3, -1), ("KERR", 7, -1), ("CK", 0, 7), ("CK", 2, 5), ("ROT", 5, -1)]
+    assert ("HR", 0, 7) in pool
+    say("slab pool ring, all types")
+    psi = W.random_state(8, 8, seed=11, sector=None)
+    x, y = dev(psi), torch.empty(8**8, dtype=torch.complex64, device="cuda")
+    ws = lib.workspace(hl, len(pool), 0)
+    lib.apply_H(hl, x, y, ws)
+    g = lib.pool_grads(hl, pool, x, y, ws)
+    p128 = psi.astype(np.complex128)
+    ref = O.pool_gradients(ho, p128, pool, apply_h=O.apply_H_slices)
+    assert np.abs(g - ref).max() <= 1e-4 * max(1.0, np.abs(ref).max()), np.abs(g - ref).max()
+    lib.set_stencil_variant(lib.STENCIL_ROWS)
+    try:
+        y2 = torch.empty_like(y)
+        lib.apply_H(hl, x, y2, ws)
+        g2 = lib.pool_grads(hl, pool, x, y2, ws)
+    finally:
+        lib.set_stencil_variant(lib.STENCIL_SLAB)
+    assert np.abs(g2 - g).max() <= 1e-4 * max(1.0, np.abs(ref).max())
+
+
 @pytest.mark.parametrize("stencil", [0, 1, 2], indirect=True, ids=["rows", "lanes", "slab"])
 def test_full_kitaev_l8_d8_apply_H_sampled_and_energy(kk_full, stencil):
     c, ho, hl, psi = kk_full
