@@ -153,6 +153,22 @@ int fock_adjoint_sweep(const fock_ham_t *ham, const fock_op_t *ops, const double
                        void *lam_work, double norm2, double *dEdtheta, void *ws, size_t ws_bytes,
                        fock_stream_t stream);
 
+/* fock_apply_H without any allocation, for callers that cannot allocate
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): hpsi = H psi as fock_apply_H, with the per-workgroup energy and
+ * norm partials in a fixed 1 MiB device array owned by the library (one per
+ * GPU, kept until the process ends) instead of a caller workspace, and the
+ * reduced pair written to DEVICE memory: res_dev[0] = <psi|H|psi>,
+ * res_dev[1] = <psi|psi> (double; res_dev nullable, 8-byte aligned).  No host
+ * synchronisation and no pinned staging; the work is only enqueued on stream.
+ * Same kernels and reduction order as fock_apply_H (bit-identical results).
+ * Limit: at most 65,536 workgroup partials (every L=8 lattice with d <= 8 and
+ * any d^L <= 2^28 fits); larger lattices return FOCK_ERR_SIZE.  Calls that
+ * overlap on one GPU (concurrent streams or threads) share the array and race;
+ * serialise them.  Tile schedules 1-3 (fock_set_stencil_schedule) are taken
+ * as schedule 0 here, since their order tables are allocated on first use. */
+int fock_apply_H_noalloc(const fock_ham_t *ham, const void *psi, void *hpsi, double *res_dev, fock_stream_t stream);
+
 /* ------------------------------------------------------------------ ADAPT */
 
 typedef struct {

@@ -23,6 +23,7 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 SOURCES = [
     "kernels_h.hip",
     "stencil2.hip",
+    "noalloc.hip",
     "kernels_pool.hip",
     "kernels_gate.hip",
     "kernels_gate_da.hip",

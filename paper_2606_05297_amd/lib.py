@@ -98,6 +98,7 @@ def load(path: str = LIB_PATH):
     L.fock_pool_grads.argtypes = [C.POINTER(Ham), C.POINTER(Op), C.c_int, vp, vp, dp, vp, sz, vp]
     L.fock_energy_grad_adjoint.argtypes = [C.POINTER(Ham), C.POINTER(Op), dp, C.c_int, vp, vp, vp, dp, dp, dp, vp,
                                            sz, vp]
+    L.fock_apply_H_noalloc.argtypes = [C.POINTER(Ham), vp, vp, vp, vp]
     L.fock_adjoint_sweep.argtypes = [C.POINTER(Ham), C.POINTER(Op), dp, C.c_int, vp, vp, C.c_double, dp, vp, sz, vp]
     L.adapt_default_opts.argtypes = [C.POINTER(AdaptOpts)]
     L.adapt_default_opts.restype = None
@@ -234,6 +235,23 @@ def apply_H(h: Ham, psi, hpsi, ws, energy=True, stream=None):
     _check(L.fock_apply_H(C.byref(h), _ptr(psi), _ptr(hpsi), C.byref(E) if energy else None,
                           C.byref(n2) if energy else None, _ptr(ws), ws.numel(), _stream(stream)))
     return (E.value, n2.value) if energy else None
+
+
+def apply_H_noalloc(h: Ham, psi, hpsi, res=None, stream=None):
+    """hpsi = H psi through the allocation-free entry point; res (optional): a
+    CUDA float64 tensor of 2 entries receiving (<psi|H|psi>, <psi|psi>) on the
+    device, without a host synchronisation."""
+    L = load()
+    _state_arg(psi, h.L, h.d, "psi")
+    _state_arg(hpsi, h.L, h.d, "hpsi")
+    _disjoint(psi, hpsi, "psi", "hpsi")
+    if res is not None:
+        import torch
+        if not (isinstance(res, torch.Tensor) and res.is_cuda and res.dtype == torch.float64 and res.numel() >= 2
+                and res.is_contiguous()):
+            raise FockError(-1, "res must be a contiguous CUDA float64 tensor of at least 2 entries")
+    _check(L.fock_apply_H_noalloc(C.byref(h), _ptr(psi), _ptr(hpsi), _ptr(res) if res is not None else None,
+                                  _stream(stream)))
 
 
 def apply_gate2(L_, d, o, theta, psi, ws, adjoint=False, stream=None):

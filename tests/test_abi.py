@@ -290,3 +290,18 @@ def test_adjoint_sweep_argument_checks():
     rc = L.fock_adjoint_sweep(C.byref(h), lib.ops_array([("HR", 0, 1), ("PR", 1, 2)]), th, 2, big,
                               C.c_void_p(2 << 20), 0.0, g, C.c_void_p(3 << 20), 1 << 24, None)
     assert rc == -1 and "norm2" in lib.last_error()
+
+
+def test_apply_H_noalloc_rejects_before_device_work():
+    """The allocation-free H psi refuses lattices whose workgroup partials
+    exceed its fixed scratch array (L=10, d=8: 262,144 partials) and bad
+    pointers, before touching the device."""
+    L = lib.load()
+    big = lib.ham(10, 8, False, 1.0, 0.0, 0.0, 0.5, 0.2)
+    a, b = C.c_void_p(1 << 20), C.c_void_p(2 << 20)
+    assert L.fock_apply_H_noalloc(C.byref(big), a, b, None, None) == -2
+    assert "scratch" in lib.last_error()
+    h = lib.ham(8, 8, False, 1.0, 0.0, 0.0, 0.5, 0.2)
+    assert L.fock_apply_H_noalloc(C.byref(h), a, a, None, None) == -1 and "overlap" in lib.last_error()
+    assert L.fock_apply_H_noalloc(C.byref(h), None, b, None, None) == -1
+    assert L.fock_apply_H_noalloc(C.byref(h), a, b, C.c_void_p((3 << 20) + 4), None) == -1
