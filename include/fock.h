@@ -238,6 +238,31 @@ int adapt_last_proposal(fock_adapt_t *st, int *accepted, double *E_prop, double 
 
 int adapt_destroy(fock_adapt_t *st);
 
+/* ------------------------------------------------------------------ HVA-CV-VQE */
+
+/* The paper's fixed-structure baseline (Sec. IV.A, Eq. (HVA_ansatz)): the
+ * ansatz repeats one layer of gates exp(theta A_k), the generators being the
+ * Hamiltonian's own terms (hopping HI, pairing PI, Kerr, rotation; layer ops
+ * given by the caller, host, copied), and grows one layer at a time (Sec. V.A):
+ * hva_add_layer appends a layer whose angles start at theta_new (host, layer
+ * size; the paper draws them uniformly in [-0.05, 0.05]), keeps the earlier
+ * angles at their previous optimum and BFGS-re-optimises all of them (opts:
+ * bfgs_maxiter, gtol_floor_rel, noise_rel as for adapt_create; L-infinity
+ * tolerance max(gtol, gtol_floor_rel max(1, |E|)), the paper's gtol being
+ * 1e-9).  The report carries the layer count (iter), E, BFGS iterations and
+ * evaluations, the parameter count and the final ||g||_inf.  Same evaluation
+ * pipeline as adapt_step.  psi0: device complex64 (copied once `stream` is
+ * synchronised); the handle owns its buffers.  max_layers * layer size <= 4096. */
+typedef struct fock_hva fock_hva_t;
+int hva_create(const fock_ham_t *ham, const fock_op_t *layer, int n_layer, int max_layers, const void *psi0,
+               const fock_adapt_opts_t *opts, double gtol, fock_stream_t stream, fock_hva_t **out);
+int hva_add_layer(fock_hva_t *st, const double *theta_new, fock_adapt_report_t *rep);
+/* Energy of psi0 (no layer). */
+int hva_initial_report(fock_hva_t *st, fock_adapt_report_t *rep);
+/* Current ansatz (all layers' gates and angles), as adapt_get_ansatz. */
+int hva_get_ansatz(fock_hva_t *st, fock_op_t *ops, double *theta, int cap, int *n);
+int hva_destroy(fock_hva_t *st);
+
 /* ------------------------------------------------------------------ batched sweep */
 
 /* One point of a parameter sweep: its Hamiltonian, pool (P <= 256 ops, host,

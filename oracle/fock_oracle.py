@@ -578,6 +578,22 @@ def adapt(ham: Ham, psi0, pool, max_iters: int, grad_tol: float = 1e-3, warm_ops
     return records
 
 
+def hva(ham: Ham, psi0, layer_ops, layer_inits, gtol: float = 1e-9, maxiter: int = 1000):
+    """HVA-CV-VQE (Sec. IV.A, Eq. (HVA_ansatz)): psi = prod_l prod_k exp(theta_lk A_k) psi0
+    with the same layer of generators A_k (the Hamiltonian's own terms) repeated.
+    Grown one layer at a time (Sec. V.A): layer l enters with the angles
+    layer_inits[l-1], the earlier layers start from their previous optimum, and
+    BFGS (L-infinity tolerance gtol, at most maxiter iterations) re-optimises all
+    angles.  Returns one record per layer."""
+    ops, theta, out = [], np.zeros(0), []
+    for l, init in enumerate(layer_inits):
+        ops = ops + list(layer_ops)
+        theta = np.concatenate([theta, np.asarray(init, dtype=float)])
+        theta, E, nit, nev = bfgs(ham, psi0, ops, theta, gtol=gtol, maxiter=maxiter)
+        out.append(dict(layers=l + 1, E=E, theta=theta.copy(), ops=list(ops), bfgs_iters=nit, bfgs_evals=nev))
+    return out
+
+
 # --------------------------------------------------------------------------
 # Single matrix rows (sampled checks on states too large for the full oracle)
 # --------------------------------------------------------------------------

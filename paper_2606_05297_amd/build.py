@@ -37,6 +37,7 @@ SOURCES = [
     "host_common.cpp",
     "api.cpp",
     "adapt.cpp",
+    "hva.cpp",
     "bfgs.cpp",
     "fuse_kernels.hip",
     "gate1_kernels.hip",

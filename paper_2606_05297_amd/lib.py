@@ -117,6 +117,12 @@ def load(path: str = LIB_PATH):
     L.adapt64_get_ansatz.argtypes = [vp, C.POINTER(Op), dp, C.c_int, ip]
     L.adapt64_energy_grad.argtypes = [vp, C.POINTER(Op), dp, C.c_int, dp, dp]
     L.adapt64_destroy.argtypes = [vp]
+    L.hva_create.argtypes = [C.POINTER(Ham), C.POINTER(Op), C.c_int, C.c_int, vp, C.POINTER(AdaptOpts), C.c_double,
+                             vp, C.POINTER(vp)]
+    L.hva_add_layer.argtypes = [vp, dp, C.POINTER(AdaptReport)]
+    L.hva_initial_report.argtypes = [vp, C.POINTER(AdaptReport)]
+    L.hva_get_ansatz.argtypes = [vp, C.POINTER(Op), dp, C.c_int, ip]
+    L.hva_destroy.argtypes = [vp]
     L.fock_sweep_create.argtypes = [C.POINTER(SweepPoint), C.c_int, C.POINTER(AdaptOpts), vp, C.POINTER(vp)]
     L.fock_sweep_step.argtypes = [vp, C.POINTER(AdaptReport), C.POINTER(C.c_int)]
     L.fock_sweep_warm_reports.argtypes = [vp, C.POINTER(AdaptReport)]
@@ -489,6 +495,58 @@ class Adapt64:
     def close(self):
         if self._st:
             self._L.adapt64_destroy(self._st)
+            self._st = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Hva:
+    """HVA-CV-VQE on the device (hva_create / hva_add_layer): the layer of
+    gates `layer` repeated up to max_layers times, grown one layer at a time."""
+
+    def __init__(self, h: Ham, layer, psi0, max_layers, gtol=1e-9, bfgs_maxiter=1000, gtol_floor_rel=1e-5,
+                 noise_rel=1e-7, stream=None):
+        L = load()
+        self._L = L
+        _state_arg(psi0, h.L, h.d, "psi0")
+        o = AdaptOpts()
+        L.adapt_default_opts(C.byref(o))
+        o.bfgs_maxiter, o.gtol_floor_rel, o.noise_rel = int(bfgs_maxiter), float(gtol_floor_rel), float(noise_rel)
+        self.layer = list(layer)
+        self._layer = ops_array(self.layer)
+        self._st = C.c_void_p()
+        _check(L.hva_create(C.byref(h), self._layer, len(self.layer), int(max_layers), _ptr(psi0), C.byref(o),
+                            float(gtol), _stream(stream), C.byref(self._st)))
+
+    def initial_report(self) -> dict:
+        r = AdaptReport()
+        _check(self._L.hva_initial_report(self._st, C.byref(r)))
+        return r.as_dict()
+
+    def add_layer(self, theta_new) -> dict:
+        th = np.ascontiguousarray(theta_new, dtype=np.float64)
+        if th.shape != (len(self.layer),):
+            raise FockError(-1, f"theta_new must have shape ({len(self.layer)},), got {th.shape}")
+        r = AdaptReport()
+        _check(self._L.hva_add_layer(self._st, th.ctypes.data_as(C.POINTER(C.c_double)), C.byref(r)))
+        return r.as_dict()
+
+    def ansatz(self):
+        n = C.c_int(0)
+        _check(self._L.hva_get_ansatz(self._st, None, None, 0, C.byref(n)))
+        m = n.value
+        ops = (Op * max(1, m))()
+        th = np.zeros(max(1, m))
+        _check(self._L.hva_get_ansatz(self._st, ops, th.ctypes.data_as(C.POINTER(C.c_double)), m, C.byref(n)))
+        return [(TYPE_NAMES[ops[k].type], ops[k].i, ops[k].j) for k in range(m)], th[:m].copy()
+
+    def close(self):
+        if self._st:
+            self._L.hva_destroy(self._st)
             self._st = C.c_void_p()
 
     def __del__(self):

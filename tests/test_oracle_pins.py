@@ -432,3 +432,46 @@ def test_two_parameter_gates_are_rotation_conjugated_fixed_phase_gates(t):
             M = O.gate_local("ROT", d, ph / 2) @ O.gate_local("SR", d, th) @ O.gate_local("ROT", d, -ph / 2)
         U = scipy.linalg.expm(th * A)
         assert np.abs(U - M).max() < 1e-12
+
+
+# ---------------------------------------------------------------- HVA-CV-VQE baseline
+
+def test_hva_single_boson_two_sites_reaches_hopping_ground_state():
+    """One HVA layer (Sec. IV.A) on two sites holding one boson: HI(0,1), Kerr
+    and rotation phases give cos t e^{ia}|1,0> + i sin t e^{ib}|0,1>, whose
+    energy 2J cos t sin t sin(b - a) has the closed-form minimum -J (t = pi/4,
+    b - a = -pi/2), the exact ground energy."""
+    h = O.Ham(2, 3, False, J=1.0)
+    layer = W.hva_layer(2, False, "bh")
+    assert layer == [("HI", 0, 1), ("KERR", 0, -1), ("KERR", 1, -1), ("ROT", 0, -1), ("ROT", 1, -1)]
+    recs = O.hva(h, O.fock_state(2, 3, [1, 0]), layer, W.hva_inits(len(layer), 1, seed=0), gtol=1e-10)
+    assert abs(recs[0]["E"] - (-1.0)) < 1e-9
+
+
+def test_hva_pairing_two_modes_reaches_bogoliubov_energy():
+    """Two modes with pairing only (J = 0, mu < 0): H = eps (n_0 + n_1) +
+    Delta (a_0 a_1 + h.c.) with eps = -mu has the Bogoliubov ground energy
+    sqrt(eps^2 - Delta^2) - eps (a two-mode squeezed vacuum); one Kitaev HVA
+    layer (PI, HI, rotations) from the vacuum reaches it at d = 16, where the
+    truncation is negligible."""
+    eps, dl = 2.0, 0.5
+    h = O.Ham(2, 16, False, J=0.0, mu=-eps, Delta=dl)
+    layer = W.hva_layer(2, False, "bkc")
+    assert layer == [("PI", 0, 1), ("HI", 0, 1), ("ROT", 0, -1), ("ROT", 1, -1)]
+    recs = O.hva(h, O.fock_state(2, 16, [0, 0]), layer, W.hva_inits(len(layer), 1, seed=3), gtol=1e-10)
+    assert abs(recs[0]["E"] - (np.sqrt(eps**2 - dl**2) - eps)) < 1e-9
+
+
+def test_hva_zero_start_is_stationary_and_layers_repeat():
+    """All-zero angles leave a Fock start unchanged (every gradient vanishes
+    there: the HVA generators are off-diagonal or diagonal phases), so BFGS stops
+    at once with the start's diagonal energy; each layer repeats the same gates."""
+    h = O.Ham(3, 4, True, J=1.0, U=2.0)
+    layer = W.hva_layer(3, True, "bh")
+    assert len(layer) == 9
+    recs = O.hva(h, O.fock_state(3, 4, [2, 1, 0]), layer, [np.zeros(9), np.zeros(9)], gtol=1e-10)
+    assert abs(recs[-1]["E"] - (2.0 / 2 * 2 * 1)) < 1e-12  # (U/2) n(n-1) at n = 2
+    assert recs[-1]["ops"] == layer + layer and np.all(recs[-1]["theta"] == 0.0)
+    assert W.hva_layer(4, True, "bkck") == ([("PI", i, j) for i, j in [(0, 1), (1, 2), (2, 3), (0, 3)]] +
+                                            [("HI", i, j) for i, j in [(0, 1), (1, 2), (2, 3), (0, 3)]] +
+                                            [("KERR", r, -1) for r in range(4)] + [("ROT", r, -1) for r in range(4)])

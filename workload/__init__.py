@@ -65,6 +65,36 @@ def warmup_ops(L: int, periodic: bool) -> list[tuple[str, int, int]]:
     return ops
 
 
+def hva_layer(L: int, periodic: bool, model: str) -> list[tuple[str, int, int]]:
+    """One layer of the Hamiltonian variational ansatz (Sec. IV.A, Table I and
+    the HVA circuit figure): exp(-i theta H_k) for each of the Hamiltonian's
+    terms, one angle per gate, in the figure's order.  The hopping term gives the
+    generator i(a_i^+ a_j + h.c.) (HI), the pairing term i(a_i a_j + h.c.) (PI),
+    the on-site terms Kerr (i N^2) and rotation (i N) phases.
+      "bh":  HI on every bond, KERR and ROT on every site        (3 N_S gates)
+      "bkc": PI on every bond, HI on every bond, ROT on every site (3 N_S gates)
+      "bkck": as "bkc" with KERR on every site before the rotations (4 N_S gates)
+    Bonds in order (r, r+1), then the ring bond (0, L-1) when periodic."""
+    bl = [(r, r + 1) for r in range(L - 1)]
+    if periodic and L >= 3:
+        bl.append((0, L - 1))
+    sites = range(L)
+    if model == "bh":
+        return [("HI", i, j) for (i, j) in bl] + [("KERR", r, -1) for r in sites] + [("ROT", r, -1) for r in sites]
+    if model in ("bkc", "bkck"):
+        ops = [("PI", i, j) for (i, j) in bl] + [("HI", i, j) for (i, j) in bl]
+        if model == "bkck":
+            ops += [("KERR", r, -1) for r in sites]
+        return ops + [("ROT", r, -1) for r in sites]
+    raise ValueError(model)
+
+
+def hva_inits(n_layer: int, layers: int, seed: int) -> list[np.ndarray]:
+    """Initial angles of each new HVA layer, uniform in [-0.05, 0.05] (Sec. V.A)."""
+    rng = np.random.default_rng(seed)
+    return [rng.uniform(-0.05, 0.05, size=n_layer) for _ in range(layers)]
+
+
 def warmup_theta0(n: int, seed: int) -> np.ndarray:
     """Initial warm-up angles uniform in [-0.05, 0.05]."""
     return np.random.default_rng(seed).uniform(-0.05, 0.05, size=n)
