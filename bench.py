@@ -38,7 +38,7 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0
 METRIC = "ADAPT steps/s, Kitaev-Kerr L=8 d=8, |ΔE|<1e-5 vs ED; apply-H GB/s vs peak"
-KERNEL_NAMES = {0: "apply_h", 1: "pool_grads", 2: "gate2", 3: "gate2_adjoint", 4: "diag_gate"}
+KERNEL_NAMES = {0: "apply_h", 1: "pool_grads", 2: "gate2", 3: "gate2_adjoint", 4: "diag_gate", 9: "score"}
 
 
 def traffic_for(kid: int):

@@ -127,6 +127,19 @@ int fock_apply_gate2(int L, int d, fock_op_t op, double theta, int adjoint, void
 int fock_pool_grads(const fock_ham_t *ham, const fock_op_t *pool, int P, const void *psi,
                     const void *hpsi, double *grads, void *ws, size_t ws_bytes, fock_stream_t stream);
 
+/* Pool scoring with H psi in one call (Eq. (grad) on the Hamiltonian of
+ * Sec. III): hpsi = H psi, E = <psi|H|psi>, norm2 = <psi|psi> (both nullable)
+ * and grads[k] = 2 Re <H psi| A_k psi> for k < P (host, P doubles), the stream
+ * synchronised once.  Where L = 8, d = 8 (the slab stencil variant) and every
+ * entry is a two-mode generator on a nearest-neighbour pair (or the ring pair
+ * (0, 7) of a ring) or a diagonal generator (at most 16), with no duplicates
+ * and P <= 256, the scoring is fused: the row pass that completes H psi also
+ * scores the entries of modes 0..4 against it from the same LDS slices, and
+ * one column-shape pass scores the rest; otherwise fock_apply_H then
+ * fock_pool_grads run.  Same results as those two calls to FP32 rounding. */
+int fock_score(const fock_ham_t *ham, const fock_op_t *pool, int P, const void *psi, void *hpsi, double *E,
+               double *norm2, double *grads, void *ws, size_t ws_bytes, fock_stream_t stream);
+
 /* Energy of the ansatz psi = O_n(theta_n) ... O_1(theta_1) psi0 (newest gate
  * acts last, Sec. IV.B) and, when dEdtheta is non-NULL, all dE/dtheta_k by one
  * reverse sweep: dE/dtheta_k = 2 Re <lambda_k| A_k phi_k> / <psi|psi> with
@@ -488,7 +501,8 @@ int fock_mlp_destroy(fock_mlp_t *net);
 
 /* Kernel ids for per-kernel timing by HIP events recorded on the launch stream. */
 enum { FOCK_K_APPLY_H = 0, FOCK_K_POOL = 1, FOCK_K_GATE = 2, FOCK_K_ADJ = 3, FOCK_K_DIAG = 4,
-       FOCK_K_REDUCE = 5, FOCK_K_MLP_FWD = 6, FOCK_K_MLP_TRAIN = 7, FOCK_K_GATE_DENSE = 8, FOCK_K_NUM = 9 };
+       FOCK_K_REDUCE = 5, FOCK_K_MLP_FWD = 6, FOCK_K_MLP_TRAIN = 7, FOCK_K_GATE_DENSE = 8,
+       FOCK_K_SCORE = 9 /* fused scoring: H psi and pool partials, fock_score / adapt_step */, FOCK_K_NUM = 10 };
 
 /* Enable/disable event timing of launches (off by default). */
 int fock_prof_enable(int on);

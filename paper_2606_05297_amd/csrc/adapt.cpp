@@ -211,16 +211,13 @@ int adapt_step(fock_adapt_t *st, fock_adapt_report_t *rep) {
   st->iter += 1;
   rep->iter = st->iter;
   rep->k_sel = -1;
-  // 1. state and energy at the current optimum
+  // 1-2. state, energy and pool scoring at the current optimum (H psi and the
+  // pool gradients from one fused pass where the pool allows it)
   double E = 0.0, n2 = 0.0;
-  int rc = eval_energy(st, st->theta, &E, &n2, nullptr);
-  if (rc) return rc;
-  // 2. pool scoring on (phi = psi, lam = H psi)
   const int P = (int)st->pool.size();
   std::vector<double> g(P);
-  rc = pool_dev(st->ctx, st->pool.data(), P, st->phi, st->lam, (double *)(st->ctx.ws + st->ctx.L.result));
-  if (rc) return rc;
-  rc = fetch_results(st->ctx, P, g.data());
+  int rc = run_score(st->ctx, st->ops.data(), st->theta.data(), (int)st->ops.size(), st->psi0, st->phi, st->lam,
+                     st->pool.data(), P, &E, &n2, g.data());
   if (rc) return rc;
   double gn2 = 0.0, ginf = 0.0;
   for (auto &v : g) {

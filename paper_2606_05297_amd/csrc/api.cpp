@@ -383,18 +383,15 @@ static int reverse_sweep(Ctx &c, const fock_op_t *ops, int n, const std::vector<
   return launch_reduce_rows(part, c.L.rs, (const GateRec *)(c.ws + c.L.recs), n, res, c.s);
 }
 
-// Energy and (optionally) all dE/dtheta of a circuit; see fock_energy_grad_adjoint.
-int run_circuit(Ctx &c, const fock_op_t *ops, const double *theta, int n, const void *psi0, float2 *phi,
-                       float2 *lam, bool grad, double *E, double *norm2, double *dE) {
-  std::vector<GateGroup> groups;
-  int rc = stage_circuit(c, ops, theta, n, &groups);
-  if (rc) return rc;
+// phi = O_n..O_1 psi0 for a staged circuit (the first gate reads psi0 directly).
+static int forward_circuit(Ctx &c, const fock_op_t *ops, int n, const std::vector<GateGroup> &groups,
+                           const void *psi0, float2 *phi) {
   const float2 *utab = (const float2 *)(c.ws + c.L.utab);
-  // the first gate reads psi0 and writes phi (no separate copy)
   if (n == 0)
     FOCK_HIP(hipMemcpyAsync(phi, psi0, sizeof(float2) * (size_t)c.g.n_amp, hipMemcpyDeviceToDevice, c.s));
   for (const GateGroup &gr : groups) {
     const float2 *src = gr.k0 == 0 ? (const float2 *)psi0 : phi;
+    int rc;
     if (gr.s == 0) {
       rc = forward_gate(c, ops[gr.k0], gr.k0, false, src, phi);
     } else {
@@ -403,6 +400,37 @@ int run_circuit(Ctx &c, const fock_op_t *ops, const double *theta, int n, const 
     }
     if (rc) return rc;
   }
+  return FOCK_OK;
+}
+
+// State of a circuit, its energy and the pool gradients there, with the
+// scoring fused where possible; g receives the raw 2 Re <H psi|A_k psi>.
+int run_score(Ctx &c, const fock_op_t *ops, const double *theta, int n, const void *psi0, float2 *phi,
+              float2 *lam, const fock_op_t *pool, int P, double *E, double *norm2, double *g) {
+  std::vector<GateGroup> groups;
+  int rc = stage_circuit(c, ops, theta, n, &groups);
+  if (rc) return rc;
+  if ((rc = forward_circuit(c, ops, n, groups, psi0, phi))) return rc;
+  double *res = (double *)(c.ws + c.L.result);
+  if ((rc = score_dev(c, pool, P, phi, lam, res))) return rc;
+  std::vector<double> host(2 + P);
+  if ((rc = fetch_results(c, 2 + P, host.data()))) return rc;
+  const double nrm = host[1];
+  if (!std::isfinite(host[0]) || !std::isfinite(nrm) || nrm <= 0.0)
+    return set_error(FOCK_ERR_NONFINITE, "non-finite energy or zero norm (E=%g, norm2=%g)", host[0], nrm);
+  *E = host[0] / nrm;
+  if (norm2) *norm2 = nrm;
+  for (int k = 0; k < P; ++k) g[k] = host[2 + k];
+  return FOCK_OK;
+}
+
+// Energy and (optionally) all dE/dtheta of a circuit; see fock_energy_grad_adjoint.
+int run_circuit(Ctx &c, const fock_op_t *ops, const double *theta, int n, const void *psi0, float2 *phi,
+                       float2 *lam, bool grad, double *E, double *norm2, double *dE) {
+  std::vector<GateGroup> groups;
+  int rc = stage_circuit(c, ops, theta, n, &groups);
+  if (rc) return rc;
+  if ((rc = forward_circuit(c, ops, n, groups, psi0, phi))) return rc;
   double *res = (double *)(c.ws + c.L.result);
   rc = apply_h_dev(c, phi, lam, res);
   if (rc) return rc;
@@ -443,6 +471,55 @@ int run_reverse(Ctx &c, const fock_op_t *ops, const double *theta, int n, float2
     dE[k] = 2.0 * host[k] / norm2;
   }
   return FOCK_OK;
+}
+
+// The whole pool as one slab-kernel chunk, when every entry is a two-mode
+// generator (HR..PI) on a nearest-neighbour pair (p, p + 1), or on the ring pair
+// (0, L - 1) of a ring, or a diagonal generator (at most kSlabDiag), with no
+// duplicates and at most kMaxSlots entries; false otherwise.
+static bool slab_pool_of(const Ctx &c, const fock_op_t *pool, int P, SlabPool *sp) {
+  if (!c.h.slab || P < 1 || P > kMaxSlots) return false;
+  memset(sp, 0, sizeof(*sp));
+  for (int p = 0; p < 8; ++p)
+    for (int t = 0; t < 5; ++t) sp->slot[p][t] = -1;
+  for (int k = 0; k < P; ++k) {
+    const fock_op_t &op = pool[k];
+    if (is_pool_diagonal(op.type)) {
+      if (sp->ndiag >= kSlabDiag) return false;
+      sp->diag[sp->ndiag++] = {(int16_t)op.i, (int16_t)op.type, (int16_t)k, (int16_t)(op.type == FOCK_CK ? op.j : -1)};
+      continue;
+    }
+    if (op.type > FOCK_PI) return false;  // squeezers
+    int p = -1;
+    if (op.j == op.i + 1 && op.i <= 6) p = op.i;
+    else if (op.i == 0 && op.j == 7 && c.h.periodic_wrap) p = 7;
+    if (p < 0 || sp->slot[p][op.type] >= 0) return false;
+    sp->slot[p][op.type] = (int16_t)k;
+  }
+  sp->nslots = P;
+  return true;
+}
+
+// H psi, (<psi|H psi>, <psi|psi>) into res[0..1] and the pool gradients
+// 2 Re <H psi|A_k psi> into res[2..2+P), on the device: fused slab scoring when
+// the pool fits it, else H psi followed by the pool pass.
+int score_dev(Ctx &c, const fock_op_t *pool, int P, const float2 *psi, float2 *hpsi, double *res) {
+  SlabPool sp;
+  if (slab_pool_of(c, pool, P, &sp)) {
+    double *ppart = (double *)(c.ws + c.L.partial);
+    double *hpart = ppart + (size_t)pool_slab_blocks() * P;
+    {
+      ProfScope ps(FOCK_K_SCORE, c.s, 16.0 * c.g.n_amp);
+      int rc = launch_score_slab(sp, c.h, psi, hpsi, hpart, ppart, c.s);
+      if (rc) return rc;
+    }
+    int rc = launch_reduce(hpart, 512, 2, res, c.s);
+    if (rc) return rc;
+    return launch_reduce(ppart, pool_slab_blocks(), P, res + 2, c.s);
+  }
+  int rc = apply_h_dev(c, psi, hpsi, res);
+  if (rc) return rc;
+  return pool_dev(c, pool, P, psi, hpsi, res + 2);
 }
 
 // Pool gradients 2 Re <hpsi|A_k psi> into res[0..P) on the device.
@@ -779,6 +856,38 @@ int fock_energy_grad_adjoint(const fock_ham_t *ham, const fock_op_t *ops, const 
   if (rc) return rc;
   return run_circuit(c, ops, theta, n, psi0, (float2 *)psi_work, (float2 *)lam_work, dEdtheta != nullptr, E, norm2,
                      dEdtheta);
+}
+
+int fock_score(const fock_ham_t *ham, const fock_op_t *pool, int P, const void *psi, void *hpsi, double *E,
+               double *norm2, double *grads, void *ws, size_t ws_bytes, fock_stream_t stream) {
+  uint32_t namp = 0;
+  int rc = check_ham(ham, &namp);
+  if (rc) return rc;
+  if (P < 1 || P > 4096) return set_error(FOCK_ERR_ARG, "P=%d out of range", P);
+  if (!pool || !grads) return set_error(FOCK_ERR_ARG, "pool/grads is NULL");
+  if ((rc = check_ptr(psi, "psi")) || (rc = check_ptr(hpsi, "hpsi"))) return rc;
+  if (psi == hpsi) return set_error(FOCK_ERR_ARG, "psi and hpsi must not overlap");
+  for (int k = 0; k < P; ++k)
+    if ((rc = check_op(pool[k], ham->L))) return rc;
+  Ctx c;
+  rc = make_ctx(*ham, namp, P, 0, ws, ws_bytes, (hipStream_t)stream, &c);
+  if (rc) return rc;
+  for (int k = 0; k < P; ++k)
+    if (is_squeeze(pool[k].type) && c.T.d != c.g.d) {  // squeezer scoring reads the generator table
+      rc = get_tables(c.g.d, &c.T);
+      if (rc) return rc;
+      break;
+    }
+  double *res = (double *)(c.ws + c.L.result);
+  rc = score_dev(c, pool, P, (const float2 *)psi, (float2 *)hpsi, res);
+  if (rc) return rc;
+  std::vector<double> host(2 + P);
+  rc = fetch_results(c, 2 + P, host.data());
+  if (rc) return rc;
+  if (E) *E = host[0];
+  if (norm2) *norm2 = host[1];
+  for (int k = 0; k < P; ++k) grads[k] = host[2 + k];
+  return FOCK_OK;
 }
 
 int fock_adjoint_sweep(const fock_ham_t *ham, const fock_op_t *ops, const double *theta, int n, void *psi_work,

@@ -224,6 +224,13 @@ int launch_apply_h2(const HamArgs &h, const float2 *psi, float2 *hpsi, double *p
 int launch_pool_slab(const SlabPool &sp, const HamArgs &h, const float2 *psi, const float2 *hpsi, double *partial,
                      int *nblocks, hipStream_t s);
 int pool_slab_blocks();
+// Fused scoring (stencil2.hip): H psi into hpsi with (<psi|H psi>, <psi|psi>)
+// partials per pencil in hpart (apply_h2 layout), and the pool partials of
+// every slot in ppart (launch_pool_slab layout), from one column pass, one row
+// pass that scores the row-shape entries as it completes H psi, and the
+// column-shape pool pass.
+int launch_score_slab(const SlabPool &sp, const HamArgs &h, const float2 *psi, float2 *hpsi, double *hpart,
+                      double *ppart, hipStream_t s);
 
 struct ProfScope {
   int id;

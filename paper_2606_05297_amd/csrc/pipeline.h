@@ -40,6 +40,13 @@ int run_circuit(Ctx &c, const fock_op_t *ops, const double *theta, int n, const 
 // All dE/dtheta from phi = psi_n, lam = H psi_n (overwritten) by the reverse sweep alone.
 int run_reverse(Ctx &c, const fock_op_t *ops, const double *theta, int n, float2 *phi, float2 *lam, double norm2,
                 double *dE);
+// psi = circuit(psi0) into phi, its Rayleigh energy, norm and the raw pool
+// gradients 2 Re <H psi|A_k psi> (g, host, P), with H psi left in lam.
+int run_score(Ctx &c, const fock_op_t *ops, const double *theta, int n, const void *psi0, float2 *phi,
+              float2 *lam, const fock_op_t *pool, int P, double *E, double *norm2, double *g);
+// H psi, (<psi|H psi>, <psi|psi>) into res[0..1] and the pool gradients into
+// res[2..2+P) (device); fused slab scoring where the pool allows it.
+int score_dev(Ctx &c, const fock_op_t *pool, int P, const float2 *psi, float2 *hpsi, double *res);
 // 2 Re <hpsi|A_k psi> for the pool into res[0..P) (device).
 int pool_dev(Ctx &c, const fock_op_t *pool, int P, const float2 *psi, const float2 *hpsi, double *res);
 

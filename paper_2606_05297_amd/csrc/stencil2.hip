@@ -414,6 +414,30 @@ __device__ __forceinline__ bool want_any(const SlabPool &sp, int p) {
   return want_x(sp, p) || want_y(sp, p) || want_d(sp, p);
 }
 
+// Diagonal entries on the row shape.  Each f(n) (KERR n_r^2, ROT n_r, CK
+// n_r n_r2) is a polynomial of degree <= 2 in the register mode n3 whose
+// coefficients depend only on the other modes, so with the slice sums
+// m0 = sum_a Im(conj(h) psi), m1 = sum_a a Im(..), m2 = sum_a a^2 Im(..) over
+// n3 = a each entry costs three products.  nv[r] is the thread's n_r (r != 3).
+__device__ __forceinline__ void diag_slice(float *dsum, const SlabPool &sp, const float (&nv)[8], float m0, float m1,
+                                           float m2) {
+#pragma unroll
+  for (int q = 0; q < kSlabDiag; ++q) {
+    if (q >= sp.ndiag) break;
+    const PoolDiag dq = sp.diag[q];
+    const float vr = nv[dq.r & 7], vr2 = nv[dq.r2 & 7];
+    float c0 = 0.f, c1 = 0.f, c2 = 0.f;
+    if (dq.type == FOCK_KERR) {
+      if (dq.r == 3) c2 = 1.f; else c0 = vr * vr;
+    } else if (dq.type == FOCK_ROT) {
+      if (dq.r == 3) c1 = 1.f; else c0 = vr;
+    } else {  // CK on (r, r2), r != r2
+      if (dq.r == 3) c1 = vr2; else if (dq.r2 == 3) c1 = vr; else c0 = vr * vr2;
+    }
+    dsum[q] -= c0 * m0 + c1 * m1 + c2 * m2;
+  }
+}
+
 // Block reduction of per-thread slot values: red[w][slot] per wavefront (FP64
 // over the lanes), then one FP64 partial per slot in a fixed order.
 template <int NT>
@@ -467,7 +491,7 @@ __global__ __launch_bounds__(kRowThreads) void k_pool8_row(const float2 *__restr
     h[a] = hpsi[base + (size_t)a * 512];
   }
   __syncthreads();  // red cleared
-#pragma unroll
+#pragma unroll 1
   for (int k = 0; k < 8; ++k) {
     if (k > 0) __syncthreads();
 #pragma unroll
@@ -539,20 +563,17 @@ __global__ __launch_bounds__(kRowThreads) void k_pool8_row(const float2 *__restr
       }
     }
     // diagonal entries: -2 f(n) Im(conj(h) psi) (the factor 2 is applied at the end)
-#pragma unroll
-    for (int q = 0; q < kSlabDiag; ++q) {
-      if (q >= sp.ndiag) break;
-      const PoolDiag dq = sp.diag[q];
-      auto dig = [&](int r, int a) -> float {
-        const int v = r == 0 ? n0 : r == 1 ? n1 : r == 2 ? n2 : r == 3 ? a : r == 4 ? k : r == 5 ? n5 : r == 6 ? n6 : n7;
-        return (float)v;
-      };
+    if (sp.ndiag > 0) {
+      float m0 = 0.f, m1 = 0.f, m2 = 0.f;
 #pragma unroll
       for (int a = 0; a < 8; ++a) {
-        const float nr = dig(dq.r, a);
-        const float f = dq.type == FOCK_KERR ? nr * nr : dq.type == FOCK_ROT ? nr : nr * dig(dq.r2, a);
-        dsum[q] -= f * (h[a].x * own[a].y - h[a].y * own[a].x);
+        const float im = h[a].x * own[a].y - h[a].y * own[a].x;
+        m0 += im;
+        m1 += (float)a * im;
+        m2 += (float)(a * a) * im;
       }
+      const float nv[8] = {(float)n0, (float)n1, (float)n2, 0.f, (float)k, (float)n5, (float)n6, (float)n7};
+      diag_slice(dsum, sp, nv, m0, m1, m2);
     }
 #pragma unroll
     for (int a = 0; a < 8; ++a) {
@@ -603,7 +624,7 @@ __global__ __launch_bounds__(kColThreads) void k_pool8_col(const float4 *__restr
     h[a] = hpsi[base + (size_t)a * S6];
   }
   __syncthreads();
-#pragma unroll
+#pragma unroll 1
   for (int k = 0; k < 8; ++k) {
     if (k > 0) __syncthreads();
 #pragma unroll
@@ -698,6 +719,233 @@ __global__ __launch_bounds__(kColThreads) void k_pool8_col(const float4 *__restr
   write_slots<kColThreads>(red, sp.nslots, partial + (size_t)(kPencils + j) * sp.nslots);
 }
 
+// Fused scoring, row shape: the row pass of H psi that also scores the pool
+// entries of the row shape against the H psi it has just completed.  Two LDS
+// slices: when slice s = k - 1 is finalised at step k (H psi(s) = column-pass
+// terms + row terms), psi(s) is still in the other buffer, so the pairs
+// (0,1), (1,2), (2,3) read their neighbours there; the streamed pair (3,4)
+// reads psi(s +- 1) from the thread's registers (slices k and k - 2), and the
+// diagonal entries use psi(s) itself.  Writes H psi, the energy/norm partials
+// of its pencil and one partial per pool slot (the column shape's pairs are
+// scored by k_pool8_col afterwards).
+__global__ __launch_bounds__(kRowThreads) void k_h8_row_score(const float2 *__restrict__ psi,
+                                                              float2 *__restrict__ hpsi,
+                                                              double *__restrict__ partial,
+                                                              double *__restrict__ ppart, SlabPool sp, HamArgs h) {
+  __shared__ float2 tile[2][4096];  // psi of slices k (buffer k & 1) and k - 1
+  __shared__ double red[kRowThreads / 64][kMaxSlots];
+  __shared__ double red2[2 * kRowThreads / 64];
+  const int t = threadIdx.x;
+  for (int e = t; e < (kRowThreads / 64) * kMaxSlots; e += kRowThreads) (&red[0][0])[e] = 0.0;
+  const Coef C = make_coef(h);
+  const int b = blockIdx.x;
+  const int p = (b & 7) * (kPencils / 8) + (b >> 3);
+  const int n0 = t & 7, n1 = (t >> 3) & 7, n2 = t >> 6;
+  const int n5 = p & 7, n6 = (p >> 3) & 7, n7 = p >> 6;
+  const size_t base = (size_t)t + (size_t)p * 8 * kS4;
+  const float2 *src = psi + base;
+  float2 *dst = hpsi + base;
+  auto ti = [&](int a0, int a1, int a2, int a3) { return (a0 & 7) + 8 * (a1 & 7) + 64 * (a2 & 7) + 512 * a3; };
+  // H psi coefficients (as k_h8_row)
+  const int r01p = ti(n0, n1 + 1, n2, 0), r01m = ti(n0, n1 - 1, n2, 0);
+  const float c01a = C.dn(n0) * C.up(n1), c01b = C.up(n0) * C.dn(n1);
+  const float c01c = C.up(n0) * C.up(n1), c01d = C.dn(n0) * C.dn(n1);
+  const int o12a = ti(n0, n1 - 1, n2 + 1, 0), o12b = ti(n0, n1 + 1, n2 - 1, 0), o12c = ti(n0, n1 + 1, n2 + 1, 0),
+            o12d = ti(n0, n1 - 1, n2 - 1, 0);
+  const float c12a = C.dn(n1) * C.up(n2), c12b = C.up(n1) * C.dn(n2);
+  const float c12c = C.up(n1) * C.up(n2), c12d = C.dn(n1) * C.dn(n2);
+  const int o23m = ti(n0, n1, n2 - 1, 0), o23p = ti(n0, n1, n2 + 1, 0);
+  const float dg012 = C.dg(n0) + C.dg(n1) + C.dg(n2);
+  const bool on01 = want_any(sp, 0), on12 = want_any(sp, 1), on23 = want_any(sp, 2), on34 = want_any(sp, 3);
+  PairSums S[4];
+  float dsum[kSlabDiag];
+#pragma unroll
+  for (int q = 0; q < kSlabDiag; ++q) dsum[q] = 0.f;
+
+  float2 own[8], nxt[8], prev[8], prev2[8], tv[8];
+  // row-pass sums of slices k - 1 (am), k (a0) and k + 1 (ap), rotated each step
+  float2 am[8], a0[8], ap[8];
+#pragma unroll
+  for (int a = 0; a < 8; ++a) own[a] = src[(size_t)a * 512];
+  float e = 0.f, nn = 0.f;
+  // pool terms of slice s (its H psi in hf, psi(s) in prev, psi(s - 1) in prev2, psi(s + 1) in own)
+  auto score = [&](int s, const float2 (&hf)[8], bool has_next) {
+    const float2 *tl = tile[s & 1];
+    const float2 z = make_float2(0.f, 0.f);
+    if (on01) {
+      const bool X = want_x(sp, 0), Y = want_y(sp, 0), Dh = want_d(sp, 0);
+#pragma unroll
+      for (int a = 0; a < 8; ++a) {
+        const float2 u = tl[r01p + 512 * a], v = tl[r01m + 512 * a];
+        const float2 ul = make_float2(dpp_from_left(u.x), dpp_from_left(u.y));
+        const float2 ur = make_float2(dpp_from_right(u.x), dpp_from_right(u.y));
+        const float2 vl = make_float2(dpp_from_left(v.x), dpp_from_left(v.y));
+        const float2 vr = make_float2(dpp_from_right(v.x), dpp_from_right(v.y));
+        pair_terms(S[0], hf[a], cmul(c01a, ul), cmul(c01b, vr), cmul(c01c, ur), cmul(c01d, vl), (float)n0, X, Y, Dh);
+      }
+    }
+    if (on12) {
+      const bool X = want_x(sp, 1), Y = want_y(sp, 1), Dh = want_d(sp, 1);
+#pragma unroll
+      for (int a = 0; a < 8; ++a)
+        pair_terms(S[1], hf[a], cmul(c12a, tl[o12a + 512 * a]), cmul(c12b, tl[o12b + 512 * a]),
+                   cmul(c12c, tl[o12c + 512 * a]), cmul(c12d, tl[o12d + 512 * a]), (float)n1, X, Y, Dh);
+    }
+    if (on23) {
+      const bool X = want_x(sp, 2), Y = want_y(sp, 2), Dh = want_d(sp, 2);
+      const float dm = C.dn(n2), um = C.up(n2);
+#pragma unroll
+      for (int a = 0; a < 8; ++a) {
+        const float2 u1 = a < 7 ? cmul(dm * C.up(a), tl[o23m + 512 * (a + 1)]) : z;  // (n2 - 1, n3 + 1)
+        const float2 u2 = a > 0 ? cmul(um * C.dn(a), tl[o23p + 512 * (a - 1)]) : z;  // (n2 + 1, n3 - 1)
+        const float2 w1 = a < 7 ? cmul(um * C.up(a), tl[o23p + 512 * (a + 1)]) : z;  // (n2 + 1, n3 + 1)
+        const float2 w2 = a > 0 ? cmul(dm * C.dn(a), tl[o23m + 512 * (a - 1)]) : z;  // (n2 - 1, n3 - 1)
+        pair_terms(S[2], hf[a], u1, u2, w1, w2, (float)n2, X, Y, Dh);
+      }
+    }
+    if (on34) {
+      const bool X = want_x(sp, 3), Y = want_y(sp, 3), Dh = want_d(sp, 3);
+#pragma unroll
+      for (int a = 0; a < 8; ++a) {
+        // slice s reads s + 1: a3^+ a4 (n3 - 1, n4 + 1), a3 a4 (n3 + 1, n4 + 1)
+        const float2 u1 = (has_next && a > 0) ? cmul(C.dn(a) * C.up(s), own[a - 1]) : z;
+        const float2 w1 = (has_next && a < 7) ? cmul(C.up(a) * C.up(s), own[a + 1]) : z;
+        // slice s reads s - 1: a4^+ a3 (n3 + 1, n4 - 1), a3^+ a4^+ (n3 - 1, n4 - 1)
+        const float2 u2 = (s > 0 && a < 7) ? cmul(C.up(a) * C.dn(s), prev2[a + 1]) : z;
+        const float2 w2 = (s > 0 && a > 0) ? cmul(C.dn(a) * C.dn(s), prev2[a - 1]) : z;
+        pair_terms(S[3], hf[a], u1, u2, w1, w2, (float)a, X, Y, Dh);
+      }
+    }
+    if (sp.ndiag > 0) {
+      float m0 = 0.f, m1 = 0.f, m2 = 0.f;
+#pragma unroll
+      for (int a = 0; a < 8; ++a) {
+        const float im = hf[a].x * prev[a].y - hf[a].y * prev[a].x;
+        m0 += im;
+        m1 += (float)a * im;
+        m2 += (float)(a * a) * im;
+      }
+      const float nv[8] = {(float)n0, (float)n1, (float)n2, 0.f, (float)s, (float)n5, (float)n6, (float)n7};
+      diag_slice(dsum, sp, nv, m0, m1, m2);
+    }
+  };
+
+  // Step k (0..8) stages slice k (k < 8), completes and scores slice k - 1
+  // (k > 0) and adds the row terms of slice k.  Kept rolled: unrolled, the
+  // kernel outgrows the instruction cache.
+#pragma unroll
+  for (int a = 0; a < 8; ++a) a0[a] = make_float2(0.f, 0.f);
+#pragma unroll 1
+  for (int k = 0; k <= 8; ++k) {
+    if (k > 0) __syncthreads();
+    if (k < 8) {
+#pragma unroll
+      for (int a = 0; a < 8; ++a) tile[k & 1][t + 512 * a] = own[a];
+    }
+    if (k < 7) {
+#pragma unroll
+      for (int a = 0; a < 8; ++a) nxt[a] = src[(size_t)a * 512 + (size_t)(k + 1) * kS4];
+    }
+    if (k > 0) {
+#pragma unroll
+      for (int a = 0; a < 8; ++a) tv[a] = dst[(size_t)a * 512 + (size_t)(k - 1) * kS4];
+    }
+    __syncthreads();
+    if (k > 0) {  // bond (3,4) of slice k - 1 reading slice k; slice k - 1 complete: write, energy, scoring
+      if (k < 8) {
+        const float u = C.up(k - 1);
+#pragma unroll
+        for (int a = 0; a < 8; ++a) {
+          if (a > 0) fma2(am[a], own[a - 1], -C.J * C.dn(a) * u);
+          if (a < 7) fma2(am[a], own[a + 1], C.Dl * C.up(a) * u);
+        }
+      }
+#pragma unroll
+      for (int a = 0; a < 8; ++a) {
+        am[a] = make_float2(am[a].x + tv[a].x, am[a].y + tv[a].y);
+        e += prev[a].x * am[a].x + prev[a].y * am[a].y;
+        nn += prev[a].x * prev[a].x + prev[a].y * prev[a].y;
+        dst[(size_t)a * 512 + (size_t)(k - 1) * kS4] = am[a];
+      }
+      score(k - 1, am, k < 8);
+    }
+    if (k == 8) break;
+#pragma unroll
+    for (int a = 0; a < 8; ++a) ap[a] = make_float2(0.f, 0.f);
+    if (k < 7) {  // bond (3,4) of slice k + 1 reading slice k
+      const float dnx = C.dn(k + 1);
+#pragma unroll
+      for (int a = 0; a < 8; ++a) {
+        if (a < 7) fma2(ap[a], own[a + 1], -C.J * C.up(a) * dnx);
+        if (a > 0) fma2(ap[a], own[a - 1], C.Dl * C.dn(a) * dnx);
+      }
+    }
+    const float2 *tl = tile[k & 1];
+#pragma unroll
+    for (int a = 0; a < 8; ++a) {
+      fma2(a0[a], own[a], dg012 + C.dg(a));
+      const float2 uu = tl[r01p + 512 * a], vv = tl[r01m + 512 * a];
+      const float2 ul = make_float2(dpp_from_left(uu.x), dpp_from_left(uu.y));
+      const float2 ur = make_float2(dpp_from_right(uu.x), dpp_from_right(uu.y));
+      const float2 vl = make_float2(dpp_from_left(vv.x), dpp_from_left(vv.y));
+      const float2 vr = make_float2(dpp_from_right(vv.x), dpp_from_right(vv.y));
+      fma2(a0[a], ul, -C.J * c01a);
+      fma2(a0[a], vr, -C.J * c01b);
+      fma2(a0[a], ur, C.Dl * c01c);
+      fma2(a0[a], vl, C.Dl * c01d);
+      fma2(a0[a], tl[o12a + 512 * a], -C.J * c12a);
+      fma2(a0[a], tl[o12b + 512 * a], -C.J * c12b);
+      fma2(a0[a], tl[o12c + 512 * a], C.Dl * c12c);
+      fma2(a0[a], tl[o12d + 512 * a], C.Dl * c12d);
+    }
+    {
+      const float hm = -C.J * C.dn(n2), pm = C.Dl * C.dn(n2), hp = -C.J * C.up(n2), pp = C.Dl * C.up(n2);
+#pragma unroll
+      for (int a = 0; a < 8; ++a) {
+        const float2 vm = tl[o23m + 512 * a], vp = tl[o23p + 512 * a];
+        if (a > 0) {
+          fma2(a0[a - 1], vm, hm * C.up(a - 1));
+          fma2(a0[a - 1], vp, pp * C.up(a - 1));
+        }
+        if (a < 7) {
+          fma2(a0[a + 1], vp, hp * C.dn(a + 1));
+          fma2(a0[a + 1], vm, pm * C.dn(a + 1));
+        }
+      }
+    }
+#pragma unroll
+    for (int a = 0; a < 8; ++a) {
+      prev2[a] = prev[a];
+      prev[a] = own[a];
+      if (k < 7) own[a] = nxt[a];
+      am[a] = a0[a];
+      a0[a] = ap[a];
+    }
+  }
+  const double se = wave_sum_d((double)e), sn = wave_sum_d((double)nn);
+  if ((t & 63) == 0) {
+    red2[2 * (t >> 6)] = se;
+    red2[2 * (t >> 6) + 1] = sn;
+  }
+#pragma unroll
+  for (int q = 0; q < 4; ++q) pair_slots(red, sp, q, S[q]);
+#pragma unroll
+  for (int q = 0; q < kSlabDiag; ++q)
+    if (q < sp.ndiag) slot_add<0>(red, sp.diag[q].slot, dsum[q]);
+  __syncthreads();
+  if (t == 0) {
+    double r0 = 0.0, r1 = 0.0;
+#pragma unroll
+    for (int w = 0; w < kRowThreads / 64; ++w) {
+      r0 += red2[2 * w];
+      r1 += red2[2 * w + 1];
+    }
+    partial[2 * p] = r0;
+    partial[2 * p + 1] = r1;
+  }
+  write_slots<kRowThreads>(red, sp.nslots, ppart + (size_t)p * sp.nslots);
+}
+
 }  // namespace
 
 bool apply_h2_supported(const HamArgs &h) { return slab_stencil_ok(h.L, h.d); }
@@ -719,6 +967,26 @@ int launch_apply_h2(const HamArgs &h, const float2 *psi, float2 *hpsi, double *p
 }
 
 int pool_slab_blocks() { return kPencils + kCols; }
+
+int launch_score_slab(const SlabPool &sp, const HamArgs &h, const float2 *psi, float2 *hpsi, double *hpart,
+                      double *ppart, hipStream_t s) {
+  if (!apply_h2_supported(h)) return set_error(FOCK_ERR_UNSUPPORTED, "fused scoring needs L = 8, d = 8");
+  if (sp.nslots < 1 || sp.nslots > kMaxSlots || sp.ndiag < 0 || sp.ndiag > kSlabDiag)
+    return set_error(FOCK_ERR_ARG, "slab pool: %d slots, %d diagonal entries", sp.nslots, sp.ndiag);
+  if (h.periodic_wrap)
+    hipLaunchKernelGGL(k_h8_col<true>, dim3(kCols), dim3(kColThreads), 0, s, (const float4 *)psi, (float4 *)hpsi, h);
+  else
+    hipLaunchKernelGGL(k_h8_col<false>, dim3(kCols), dim3(kColThreads), 0, s, (const float4 *)psi, (float4 *)hpsi, h);
+  hipLaunchKernelGGL(k_h8_row_score, dim3(kPencils), dim3(kRowThreads), 0, s, psi, hpsi, hpart, ppart, sp, h);
+  if (h.periodic_wrap)
+    hipLaunchKernelGGL(k_pool8_col<true>, dim3(kCols), dim3(kColThreads), 0, s, (const float4 *)psi,
+                       (const float4 *)hpsi, ppart, sp, h);
+  else
+    hipLaunchKernelGGL(k_pool8_col<false>, dim3(kCols), dim3(kColThreads), 0, s, (const float4 *)psi,
+                       (const float4 *)hpsi, ppart, sp, h);
+  FOCK_HIP(hipGetLastError());
+  return FOCK_OK;
+}
 
 int launch_pool_slab(const SlabPool &sp, const HamArgs &h, const float2 *psi, const float2 *hpsi, double *partial,
                      int *nblocks, hipStream_t s) {

@@ -22,6 +22,7 @@ FOCK_OK = 0
 ERRORS = {-1: "FOCK_ERR_ARG", -2: "FOCK_ERR_SIZE", -3: "FOCK_ERR_UNSUPPORTED", -4: "FOCK_ERR_NONFINITE",
           -5: "FOCK_ERR_HIP", -6: "FOCK_ERR_LINESEARCH", -7: "FOCK_ERR_STATE"}
 K_APPLY_H, K_POOL, K_GATE, K_ADJ, K_DIAG, K_REDUCE = range(6)
+K_SCORE = 9
 
 
 class Ham(C.Structure):
@@ -99,6 +100,7 @@ def load(path: str = LIB_PATH):
     L.fock_energy_grad_adjoint.argtypes = [C.POINTER(Ham), C.POINTER(Op), dp, C.c_int, vp, vp, vp, dp, dp, dp, vp,
                                            sz, vp]
     L.fock_apply_H_noalloc.argtypes = [C.POINTER(Ham), vp, vp, vp, vp]
+    L.fock_score.argtypes = [C.POINTER(Ham), C.POINTER(Op), C.c_int, vp, vp, dp, dp, dp, vp, sz, vp]
     L.fock_adjoint_sweep.argtypes = [C.POINTER(Ham), C.POINTER(Op), dp, C.c_int, vp, vp, C.c_double, dp, vp, sz, vp]
     L.adapt_default_opts.argtypes = [C.POINTER(AdaptOpts)]
     L.adapt_default_opts.restype = None
@@ -300,6 +302,22 @@ def energy_grad_adjoint(h: Ham, ops, theta, psi0, psi_work, lam_work, ws, grad=T
                                       g.ctypes.data_as(C.POINTER(C.c_double)) if grad else None, _ptr(ws),
                                       ws.numel(), _stream(stream)))
     return E.value, n2.value, (g[:n].copy() if grad else None)
+
+
+def score(h: Ham, pool, psi, hpsi, ws, stream=None):
+    """hpsi = H psi and the pool gradients in one call (fock_score, fused where
+    the pool allows it); returns (grads, <psi|H|psi>, <psi|psi>)."""
+    L = load()
+    _state_arg(psi, h.L, h.d, "psi")
+    _state_arg(hpsi, h.L, h.d, "hpsi")
+    _disjoint(psi, hpsi, "psi", "hpsi")
+    _ws_arg(ws)
+    P = len(pool)
+    out = np.zeros(P, dtype=np.float64)
+    E, n2 = C.c_double(0), C.c_double(0)
+    _check(L.fock_score(C.byref(h), ops_array(pool), P, _ptr(psi), _ptr(hpsi), C.byref(E), C.byref(n2),
+                        out.ctypes.data_as(C.POINTER(C.c_double)), _ptr(ws), ws.numel(), _stream(stream)))
+    return out, E.value, n2.value
 
 
 def adjoint_sweep(h: Ham, ops, theta, psi_work, lam_work, norm2, ws, stream=None) -> np.ndarray:

@@ -394,7 +394,8 @@ def test_slab_pool_ring_all_types_l8_d8():
     per, J, U, mu, Dl, K = True, 0.8, 1.1, 0.3, 0.45, 0.15
     ho, hl = ham_pair(8, 8, per, J, U, mu, Dl, K)
     pool = W.pool(8, "nn", True, ("HR", "HI", "DH", "PR", "PI"))
-    pool += [("KERR", 0, -1), ("ROT", 3, -1), ("KERR", 7, -1), ("CK", 0, 7), ("CK", 2, 5), ("ROT", 5, -1)]
+    pool += [("KERR", 0, -1), ("ROT", 3, -1), ("KERR", 7, -1), ("CK", 0, 7), ("CK", 2, 5), ("ROT", 5, -1),
+             ("KERR", 3, -1), ("CK", 3, 6), ("CK", 1, 3), ("ROT", 4, -1), ("CK", 3, 4)]
     assert ("HR", 0, 7) in pool
     say("slab pool ring, all types")
     psi = W.random_state(8, 8, seed=11, sector=None)
@@ -413,6 +414,47 @@ def test_slab_pool_ring_all_types_l8_d8():
     finally:
         lib.set_stencil_variant(lib.STENCIL_SLAB)
     assert np.abs(g2 - g).max() <= 1e-4 * max(1.0, np.abs(ref).max())
+
+
+SCORE_CASES = [
+    # the benchmark's chain and pool; a ring with every two-mode type and diagonal entries
+    (False, 1.0, 0.0, 0.0, 0.5, 0.2, ("parity", 0), "kk"),
+    (True, 0.8, 1.1, 0.3, 0.45, 0.15, None, "all"),
+]
+
+
+@pytest.mark.parametrize("case", SCORE_CASES, ids=["kk_open_pool28", "ring_all_types"])
+def test_fused_scoring_l8_d8(case):
+    """fock_score (fused H psi + pool scoring at L=8, d=8) against the oracle
+    (H psi on every amplitude, energy, norm, every pool gradient) and against
+    fock_apply_H followed by fock_pool_grads."""
+    per, J, U, mu, Dl, K, sector, kind = case
+    ho, hl = ham_pair(8, 8, per, J, U, mu, Dl, K)
+    if kind == "kk":
+        pool = W.config("kk_l8_d8")["pool"]
+    else:
+        pool = W.pool(8, "nn", True, ("HR", "HI", "DH", "PR", "PI"))
+        pool += [("KERR", 0, -1), ("ROT", 3, -1), ("CK", 0, 7), ("CK", 2, 5), ("KERR", 3, -1), ("CK", 3, 6),
+                 ("CK", 1, 3), ("KERR", 4, -1)]
+    say("fused scoring", kind)
+    psi = W.random_state(8, 8, seed=21, sector=sector)
+    x = dev(psi)
+    y = torch.full((8**8,), float("nan"), dtype=torch.complex64, device="cuda")
+    ws = lib.workspace(hl, len(pool), 0)
+    g, E, n2 = lib.score(hl, pool, x, y, ws)
+    p128 = psi.astype(np.complex128)
+    href = O.apply_H_slices(ho, p128)
+    got = host(y)
+    assert np.abs(got - href).max() <= 2e-5 * np.abs(href).max()
+    Eref = np.vdot(p128, href).real
+    assert abs(E - Eref) <= 1e-5 * max(1.0, abs(Eref)) and abs(n2 - np.vdot(p128, p128).real) <= 1e-6
+    gref = np.array([2 * np.vdot(href, O.apply_generator(op, p128, 8, 8)).real for op in pool])
+    assert np.abs(g - gref).max() <= 1e-4 * max(1.0, np.abs(gref).max()), np.abs(g - gref).max()
+    y2 = torch.empty_like(y)
+    E2, _ = lib.apply_H(hl, x, y2, ws)
+    g2 = lib.pool_grads(hl, pool, x, y2, ws)
+    assert np.abs(g2 - g).max() <= 1e-4 * max(1.0, np.abs(gref).max())
+    assert abs(E2 - E) <= 1e-5 * max(1.0, abs(E))
 
 
 @pytest.mark.parametrize("stencil", [0, 1, 2], indirect=True, ids=["rows", "lanes", "slab"])
