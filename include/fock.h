@@ -499,6 +499,18 @@ int fock_mlp_destroy(fock_mlp_t *net);
 
 /* ------------------------------------------------------------------ profiling */
 
+/* Streaming-bandwidth probe: the measured HBM ceiling the kernel rooflines are
+ * read against.  kind 0 copies `bytes` from a to b, kind 1 reads a (one float
+ * per workgroup is written to b), kind 2 updates b in place (multiplies every
+ * complex64 value by i).  grid workgroups of 256 threads, grid-stride, 16-byte
+ * accesses; one untimed warm-up launch, then *ms = mean duration (ms) of
+ * `iters` launches from HIP events on `stream` (synchronised on return).
+ * Buffers are the caller's (device, 16-byte aligned, `bytes` each; a unused
+ * for kind 2).  FOCK_ERR_ARG on a bad kind, size, grid, count or pointer. */
+int fock_stream_probe(int kind, const void *a, void *b, size_t bytes, int grid, int iters, double *ms,
+                      fock_stream_t stream);
+
+
 /* Kernel ids for per-kernel timing by HIP events recorded on the launch stream. */
 enum { FOCK_K_APPLY_H = 0, FOCK_K_POOL = 1, FOCK_K_GATE = 2, FOCK_K_ADJ = 3, FOCK_K_DIAG = 4,
        FOCK_K_REDUCE = 5, FOCK_K_MLP_FWD = 6, FOCK_K_MLP_TRAIN = 7, FOCK_K_GATE_DENSE = 8,

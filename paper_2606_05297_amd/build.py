@@ -24,6 +24,7 @@ SOURCES = [
     "kernels_h.hip",
     "stencil2.hip",
     "noalloc.hip",
+    "probe.hip",
     "kernels_pool.hip",
     "kernels_gate.hip",
     "kernels_gate_da.hip",

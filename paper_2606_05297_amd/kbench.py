@@ -74,6 +74,21 @@ def main():
         ms = ev0.elapsed_time(ev1) / args.iters
         res["copy"] = {"avg_us": ms * 1e3, "GBs": 16.0 * n / (ms * 1e-3) / 1e9}
         print(f"[kbench] copy done", file=sys.stderr, flush=True)
+    if "stream" in want:
+        # streaming ceiling: 1 GiB buffers (4x the 256 MiB Infinity Cache) and, for
+        # contrast, 128 MiB buffers that stay cache-resident between launches
+        res["stream"] = {}
+        for mib in (1024, 128):
+            a = torch.empty(mib << 18, dtype=torch.float32, device="cuda").fill_(1.0)
+            b = torch.empty_like(a).fill_(2.0)
+            for grid in (1024, 4096, 16384):
+                for kind, name, mult in ((0, "copy", 2), (1, "read", 1), (2, "update", 2)):
+                    ms = lib.stream_probe(kind, a, b, grid=grid, iters=max(5, args.iters // 2))
+                    res["stream"][f"{name}_{mib}MiB_g{grid}"] = {
+                        "avg_us": ms * 1e3, "GBs": mult * (mib << 20) / (ms * 1e-3) / 1e9}
+            del a, b
+        torch.cuda.synchronize()
+        print(f"[kbench] stream done", file=sys.stderr, flush=True)
     if "apply_h" in want:
         for k in range(args.iters):
             j = 0 if args.hot else k % 3

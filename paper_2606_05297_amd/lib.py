@@ -100,6 +100,7 @@ def load(path: str = LIB_PATH):
     L.fock_energy_grad_adjoint.argtypes = [C.POINTER(Ham), C.POINTER(Op), dp, C.c_int, vp, vp, vp, dp, dp, dp, vp,
                                            sz, vp]
     L.fock_apply_H_noalloc.argtypes = [C.POINTER(Ham), vp, vp, vp, vp]
+    L.fock_stream_probe.argtypes = [C.c_int, vp, vp, sz, C.c_int, C.c_int, dp, vp]
     L.fock_score.argtypes = [C.POINTER(Ham), C.POINTER(Op), C.c_int, vp, vp, dp, dp, dp, vp, sz, vp]
     L.fock_adjoint_sweep.argtypes = [C.POINTER(Ham), C.POINTER(Op), dp, C.c_int, vp, vp, C.c_double, dp, vp, sz, vp]
     L.adapt_default_opts.argtypes = [C.POINTER(AdaptOpts)]
@@ -260,6 +261,24 @@ def apply_H_noalloc(h: Ham, psi, hpsi, res=None, stream=None):
             raise FockError(-1, "res must be a contiguous CUDA float64 tensor of at least 2 entries")
     _check(L.fock_apply_H_noalloc(C.byref(h), _ptr(psi), _ptr(hpsi), _ptr(res) if res is not None else None,
                                   _stream(stream)))
+
+
+def stream_probe(kind, a, b, grid=4096, iters=10, stream=None):
+    """Mean duration (ms) of the streaming probe: kind 0 copies a into b, 1
+    reads a, 2 updates b in place (fock_stream_probe).  a and b: contiguous
+    CUDA tensors of the same byte size (a unused for kind 2)."""
+    import torch
+    L = load()
+    if not (isinstance(b, torch.Tensor) and b.is_cuda and b.is_contiguous()):
+        raise FockError(-1, "b must be a contiguous CUDA tensor")
+    nbytes = b.numel() * b.element_size()
+    if kind != 2 and not (isinstance(a, torch.Tensor) and a.is_cuda and a.is_contiguous()
+                          and a.numel() * a.element_size() == nbytes):
+        raise FockError(-1, "a must be a contiguous CUDA tensor of b's byte size")
+    ms = C.c_double(0.0)
+    _check(L.fock_stream_probe(int(kind), _ptr(a) if kind != 2 else None, _ptr(b), nbytes, int(grid), int(iters),
+                               C.byref(ms), _stream(stream)))
+    return ms.value
 
 
 def apply_gate2(L_, d, o, theta, psi, ws, adjoint=False, stream=None):

@@ -305,3 +305,21 @@ def test_apply_H_noalloc_rejects_before_device_work():
     assert L.fock_apply_H_noalloc(C.byref(h), a, a, None, None) == -1 and "overlap" in lib.last_error()
     assert L.fock_apply_H_noalloc(C.byref(h), None, b, None, None) == -1
     assert L.fock_apply_H_noalloc(C.byref(h), a, b, C.c_void_p((3 << 20) + 4), None) == -1
+
+
+def test_stream_probe_rejects_before_device_work():
+    """The streaming probe validates kind, size, grid, count and pointers
+    before it creates events or launches anything."""
+    L = lib.load()
+    a, b = C.c_void_p(1 << 20), C.c_void_p(2 << 20)
+    ms = C.c_double(0.0)
+    assert L.fock_stream_probe(3, a, b, 1 << 20, 64, 1, C.byref(ms), None) == -1 and "kind" in lib.last_error()
+    assert L.fock_stream_probe(0, a, b, 0, 64, 1, C.byref(ms), None) == -1
+    assert L.fock_stream_probe(0, a, b, 24, 64, 1, C.byref(ms), None) == -1
+    assert L.fock_stream_probe(0, a, b, 1 << 20, 0, 1, C.byref(ms), None) == -1
+    assert L.fock_stream_probe(0, a, b, 1 << 20, 64, 0, C.byref(ms), None) == -1
+    assert L.fock_stream_probe(0, None, b, 1 << 20, 64, 1, C.byref(ms), None) == -1
+    assert L.fock_stream_probe(2, None, None, 1 << 20, 64, 1, C.byref(ms), None) == -1
+    assert L.fock_stream_probe(0, C.c_void_p((1 << 20) + 8), b, 1 << 20, 64, 1, C.byref(ms), None) == -1
+    assert L.fock_stream_probe(1, a, b, 64, 64, 1, C.byref(ms), None) == -1 and "too small" in lib.last_error()
+    assert L.fock_stream_probe(0, a, b, 1 << 20, 64, 1, None, None) == -1
