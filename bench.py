@@ -18,7 +18,10 @@ identity for the new angle (Appendix D); --no-hessian-recycling starts from
 the scaled identity.  After the timed region, "variants" reports the same
 workload with central-difference BFGS gradients (the plain method), adjoint
 gradients without and with Hessian recycling, and adjoint gradients through
-the batched engine (persistent kernels, graph-replayed BFGS rounds).  Then,
+the batched engine (persistent kernels, graph-replayed BFGS rounds), and
+"warm_start": the learned warm start trained on 8 nearby points run by the
+batched sweep, proposing angles after each step's selection (see
+warm_start_leg; --no-warm-start skips it).  Then,
 on the host, the FP64 oracle re-evaluates the GPU's ansatz after steps 5, 10,
 15 and 20 ("replay_checked_steps", |dE| <= 1e-5 |E|) and is timed on steps
 1..3 of the same trajectory at all BLAS threads and at one ("cpu_baseline");
@@ -122,6 +125,77 @@ def cpu_leg(cfg, psi0, snaps, reps):
     return base, replay
 
 
+def warm_start_leg(cfg, hl, psi0, k, plain):
+    """Batched + adjoint + learned warm start against the plain GPU method.
+
+    Training data: plain ADAPT (adjoint gradients) for k steps on 8 points
+    around the benchmark point, (Delta, K) scaled by U[0.9, 1.1] (seed 5), all
+    run together by the batched sweep; their steps on the majority operator
+    sequence become samples (J, Delta, K, n / 64) -> angles after step n, and
+    the 4-128-128-64 network is trained on the GPU (bf16 MFMA kernels, Adam).
+    Then steps 1..k of the benchmark point with Hessian recycling, as the
+    headline, where every step selects first and, when the chosen circuit
+    still follows the training sequence, proposes the network's angles
+    (previous angles + predicted shift, predicted new angle); the library
+    keeps a proposal only if its energy is not above the plain start.  The
+    timed part is the k steps including network forwards and proposals;
+    training is reported separately."""
+    import numpy as np
+    import torch
+
+    import workload as W
+    from paper_2606_05297_amd import lib
+    from paper_2606_05297_amd import warmstart as WS
+
+    rng = np.random.default_rng(5)
+    pts = [dict(cfg, Delta=cfg["Delta"] * f1, K=cfg["K"] * f2) for f1, f2 in rng.uniform(0.9, 1.1, (8, 2))]
+    t0 = time.perf_counter()
+    recs, ang = WS.run_sweep(pts, k)
+    t_data = time.perf_counter() - t0
+    seq, agree = WS.consensus(recs)
+    X, T, nv = WS.dataset_agreeing(pts, ang, agree)
+    t0 = time.perf_counter()
+    net, hist = WS.train(X, T, nv, epochs=300, batch=256)
+    t_train = time.perf_counter() - t0
+    Xd = torch.zeros((2, 4), dtype=torch.float32, device="cuda")
+    ad = lib.Adapt(hl, cfg["pool"], psi0, max_iters=cfg["max_iters"], recycle_hessian=True)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    rs, acc, proposed, on_seq = [], [], 0, True
+    for step in range(k):
+        sel = ad.select()
+        if sel["converged"] or sel["capped"]:
+            rs.append(sel)
+            break
+        n = sel["n_params"] - 1
+        on_seq = on_seq and step < len(seq) and sel["k_sel"] == seq[step]
+        if on_seq and n + 1 <= WS.NOUT:
+            Xd.copy_(torch.from_numpy(np.stack([W.mlp_features(cfg["J"], cfg["Delta"], cfg["K"], n + 1),
+                                                W.mlp_features(cfg["J"], cfg["Delta"], cfg["K"], max(n, 1))])))
+            Y = net.forward(Xd).cpu().numpy().astype(np.float64)
+            _, th = ad.ansatz()
+            prop = np.append(th[:n] + Y[0, :n] - Y[1, :n], Y[0, n]) if n > 0 else Y[0, :1]
+            ad.propose(prop)
+            proposed += 1
+        r = ad.finish()
+        if on_seq and n + 1 <= WS.NOUT:
+            acc.append(ad.last_proposal()["accepted"])
+        rs.append(r)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t
+    ad.close()
+    net.close()
+    done = [r for r in rs if r["k_sel"] >= 0]
+    return {"steps": len(done), "steps_per_s": len(done) / dt, "E_final": rs[-1]["E"],
+            "bfgs_evals_per_step": float(np.mean([r["bfgs_evals"] for r in done])),
+            "bfgs_iters_per_step": float(np.mean([r["bfgs_iters"] for r in done])),
+            "proposals": proposed, "accepted": int(sum(acc)),
+            "speedup_vs_plain_adjoint_recycling": (len(done) / dt) / plain["steps_per_s"],
+            "training": {"points": len(pts), "samples": int(len(X)), "sequence_steps": len(seq),
+                         "points_on_sequence_per_step": [int(sum(1 for a in agree if a > s)) for s in range(len(seq))],
+                         "sweep_s": t_data, "train_s": t_train, "loss_first_last": [hist[0][1], hist[-1][1]]}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -132,6 +206,7 @@ def main():
     ap.add_argument("--no-hessian-recycling", action="store_true",
                     help="start every BFGS from the scaled identity instead of the previous inverse Hessian")
     ap.add_argument("--no-variants", action="store_true", help="skip the FD-gradient and Hessian-recycling lines")
+    ap.add_argument("--no-warm-start", action="store_true", help="skip the learned warm-start leg")
     ap.add_argument("--prof-sample", type=int, default=4,
                     help="time one launch in this many per kernel family with HIP events (1: every launch)")
     ap.add_argument("--gate-fusion", type=int, choices=[0, 1, 2], default=None,
@@ -274,6 +349,10 @@ def main():
             "adjoint_hessian_recycling": main if rh else variant(args.steps, recycle_hessian=True),
             "adjoint_graph_replay": variant_graph(args.steps),
         }
+    if not args.no_variants and args.grad_mode == "adjoint" and not args.no_warm_start:
+        print("[bench] warm-start leg: training data from 8 nearby points, network, proposals after selection",
+              file=sys.stderr, flush=True)
+        out["warm_start"] = warm_start_leg(cfg, hl, psi0, args.steps, out["variants"]["adjoint_hessian_recycling"])
     if not args.no_cpu_baseline and 3 in snaps:
         print("[bench] oracle on the host: replay of steps 5/10/15/20 and the steps 1-3 timing sample", file=sys.stderr,
               flush=True)

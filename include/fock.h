@@ -235,6 +235,18 @@ int adapt_create(const fock_ham_t *ham, const fock_op_t *pool, int P, const void
  * angles by BFGS.  Returns FOCK_ERR_STATE once the run has converged/capped. */
 int adapt_step(fock_adapt_t *st, fock_adapt_report_t *rep);
 
+/* adapt_step in two halves, so that a caller can propose starting angles for
+ * the circuit the step has actually chosen (Sec. IV.B: the initial point of
+ * each re-optimisation is {theta_prev, 0}).  adapt_step_select scores the
+ * pool, tests convergence and, unless converged or capped, selects and appends
+ * exp(theta A_k) with theta = 0 (rep: iter, k_sel, g_sel, g_norm2, g_inf, E,
+ * norm2, n_params including the new angle).  adapt_step_finish then starts
+ * BFGS from {theta_prev, 0} or from a pending proposal whose energy is not
+ * higher, and fills the whole report as adapt_step.  FOCK_ERR_STATE for a
+ * select while a step is pending and for a finish without one. */
+int adapt_step_select(fock_adapt_t *st, fock_adapt_report_t *rep);
+int adapt_step_finish(fock_adapt_t *st, fock_adapt_report_t *rep);
+
 /* Report of the warm-up optimisation done in adapt_create. */
 int adapt_warm_report(fock_adapt_t *st, fock_adapt_report_t *rep);
 
@@ -242,10 +254,12 @@ int adapt_warm_report(fock_adapt_t *st, fock_adapt_report_t *rep);
  * *n receives the full length. */
 int adapt_get_ansatz(fock_adapt_t *st, fock_op_t *ops, double *theta, int cap, int *n);
 
-/* Proposal for the angles used as the BFGS start of the next step (full
- * vector of length current n_params + 1).  It is used only if its energy is
- * not above the plain start {theta_prev, 0}; otherwise the plain start is
- * kept.  *accepted (after the step) via adapt_last_proposal. */
+/* Proposal for the angles used as the BFGS start of the next step: the full
+ * vector of length n_params + 1 before adapt_step / adapt_step_select, or of
+ * length n_params (the new angle already appended) between adapt_step_select
+ * and adapt_step_finish.  It is used only if its energy is not above the
+ * plain start {theta_prev, 0}; otherwise the plain start is kept.  *accepted
+ * (after the step) via adapt_last_proposal. */
 int adapt_propose(fock_adapt_t *st, const double *theta, int n);
 int adapt_last_proposal(fock_adapt_t *st, int *accepted, double *E_prop, double *E_plain);
 

@@ -35,6 +35,9 @@ struct fock_adapt {
   bool has_prop = false;
   int prop_acc = 0;
   double prop_E = 0.0, plain_E = 0.0;
+  // a step between adapt_step_select and adapt_step_finish
+  bool pending = false;
+  fock_adapt_report_t pend{};
 };
 
 namespace {
@@ -204,9 +207,10 @@ int adapt_warm_report(fock_adapt_t *st, fock_adapt_report_t *rep) {
   return FOCK_OK;
 }
 
-int adapt_step(fock_adapt_t *st, fock_adapt_report_t *rep) {
+int adapt_step_select(fock_adapt_t *st, fock_adapt_report_t *rep) {
   if (!st || !rep) return set_error(FOCK_ERR_ARG, "NULL argument");
   if (st->done) return set_error(FOCK_ERR_STATE, "ADAPT run already finished");
+  if (st->pending) return set_error(FOCK_ERR_STATE, "a selected step awaits adapt_step_finish");
   memset(rep, 0, sizeof(*rep));
   st->iter += 1;
   rep->iter = st->iter;
@@ -251,11 +255,25 @@ int adapt_step(fock_adapt_t *st, fock_adapt_report_t *rep) {
     }
   rep->k_sel = ks;
   rep->g_sel = std::fabs(g[ks]);
-  // 4. append with theta = 0, or a proposal whose energy is not worse
+  // 4. append with theta = 0 (a proposal may replace the start in adapt_step_finish)
   st->ops.push_back(st->pool[ks]);
   st->theta.push_back(0.0);
+  rep->n_params = (int)st->theta.size();
+  st->pending = true;
+  st->pend = *rep;
+  return FOCK_OK;
+}
+
+int adapt_step_finish(fock_adapt_t *st, fock_adapt_report_t *rep) {
+  if (!st || !rep) return set_error(FOCK_ERR_ARG, "NULL argument");
+  if (!st->pending) return set_error(FOCK_ERR_STATE, "no selected step (call adapt_step_select first)");
+  st->pending = false;
+  const fock_adapt_report_t sel = st->pend;
+  const double E = sel.E;
+  // 4b. start from {theta_prev, 0}, or from a proposal whose energy is not higher
   st->prop_acc = 0;
   st->plain_E = E;
+  int rc = FOCK_OK;
   if (st->has_prop) {
     st->has_prop = false;
     if (st->proposal.size() == st->theta.size()) {
@@ -270,13 +288,21 @@ int adapt_step(fock_adapt_t *st, fock_adapt_report_t *rep) {
     }
   }
   // 5. re-optimise all angles
-  rc = optimise(st, gtol_for(st, rep->g_sel, E), rep);
+  memset(rep, 0, sizeof(*rep));
+  rc = optimise(st, gtol_for(st, sel.g_sel, E), rep);
   if (rc) return rc;
-  rep->iter = st->iter;
-  rep->k_sel = ks;
-  rep->g_norm2 = gn2;
-  rep->g_inf = ginf;
+  rep->iter = sel.iter;
+  rep->k_sel = sel.k_sel;
+  rep->g_sel = sel.g_sel;
+  rep->g_norm2 = sel.g_norm2;
+  rep->g_inf = sel.g_inf;
   return FOCK_OK;
+}
+
+int adapt_step(fock_adapt_t *st, fock_adapt_report_t *rep) {
+  int rc = adapt_step_select(st, rep);
+  if (rc || rep->converged || rep->capped) return rc;
+  return adapt_step_finish(st, rep);
 }
 
 int adapt_get_ansatz(fock_adapt_t *st, fock_op_t *ops, double *theta, int cap, int *n) {
@@ -292,8 +318,9 @@ int adapt_get_ansatz(fock_adapt_t *st, fock_op_t *ops, double *theta, int cap, i
 
 int adapt_propose(fock_adapt_t *st, const double *theta, int n) {
   if (!st || (!theta && n > 0)) return set_error(FOCK_ERR_ARG, "NULL argument");
-  if (n != (int)st->theta.size() + 1)
-    return set_error(FOCK_ERR_ARG, "proposal length %d != current parameters + 1 (%d)", n, (int)st->theta.size() + 1);
+  // before adapt_step_select the new angle is not appended yet; after it, it is
+  const int want = (int)st->theta.size() + (st->pending ? 0 : 1);
+  if (n != want) return set_error(FOCK_ERR_ARG, "proposal length %d != parameters of the step (%d)", n, want);
   for (int k = 0; k < n; ++k)
     if (!std::isfinite(theta[k])) return set_error(FOCK_ERR_NONFINITE, "proposal[%d] not finite", k);
   st->proposal.assign(theta, theta + n);

@@ -108,6 +108,8 @@ def load(path: str = LIB_PATH):
     L.adapt_create.argtypes = [C.POINTER(Ham), C.POINTER(Op), C.c_int, vp, C.POINTER(AdaptOpts), vp,
                                C.POINTER(vp)]
     L.adapt_step.argtypes = [vp, C.POINTER(AdaptReport)]
+    L.adapt_step_select.argtypes = [vp, C.POINTER(AdaptReport)]
+    L.adapt_step_finish.argtypes = [vp, C.POINTER(AdaptReport)]
     L.adapt_warm_report.argtypes = [vp, C.POINTER(AdaptReport)]
     L.adapt_get_ansatz.argtypes = [vp, C.POINTER(Op), dp, C.c_int, ip]
     L.adapt_propose.argtypes = [vp, dp, C.c_int]
@@ -430,6 +432,18 @@ class Adapt:
     def step(self) -> dict:
         r = AdaptReport()
         _check(self._L.adapt_step(self._st, C.byref(r)))
+        return r.as_dict()
+
+    def select(self) -> dict:
+        """First half of a step: score, test, select and append (adapt_step_select)."""
+        r = AdaptReport()
+        _check(self._L.adapt_step_select(self._st, C.byref(r)))
+        return r.as_dict()
+
+    def finish(self) -> dict:
+        """Second half: BFGS from the plain start or a pending proposal (adapt_step_finish)."""
+        r = AdaptReport()
+        _check(self._L.adapt_step_finish(self._st, C.byref(r)))
         return r.as_dict()
 
     def ansatz(self):

@@ -131,6 +131,35 @@ def dataset(points, angles):
     return np.array(X, dtype=np.float32), np.array(T, dtype=np.float32), np.array(n, dtype=np.int32)
 
 
+def consensus(recs):
+    """Majority operator sequence of the training trajectories and, per point,
+    how many of its first steps follow it.  A slot-wise angle regression only
+    means something while the circuits agree, so training keeps those steps."""
+    seq, agree = [], [0] * len(recs)
+    alive = list(range(len(recs)))
+    step = 0
+    while alive:
+        ks = [recs[k][step]["k_sel"] for k in alive if step < len(recs[k]) and recs[k][step]["k_sel"] >= 0]
+        if not ks:
+            break
+        vals, cnt = np.unique(ks, return_counts=True)
+        best = int(vals[np.argmax(cnt)])
+        seq.append(best)
+        nxt = []
+        for k in alive:
+            if step < len(recs[k]) and recs[k][step]["k_sel"] == best:
+                agree[k] = step + 1
+                nxt.append(k)
+        alive = nxt
+        step += 1
+    return seq, agree
+
+
+def dataset_agreeing(points, angles, agree):
+    """dataset() restricted to each point's first agree[k] steps."""
+    return dataset(points, [ang[:a] for ang, a in zip(angles, agree)])
+
+
 def train(X, T, n, epochs=400, batch=1024, lr=2e-3, seed=0, log=None):
     """Adam on the GPU; returns (network, loss history per epoch)."""
     import torch

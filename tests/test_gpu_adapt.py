@@ -167,6 +167,41 @@ def test_adapt_proposal_accept_and_reject():
     ad.close()
 
 
+def test_adapt_select_finish_matches_step_and_takes_late_proposals():
+    """adapt_step_select + adapt_step_finish reproduce adapt_step bit for bit;
+    a proposal made after selection (length n_params, new angle appended) is
+    used when its energy is not higher, and the half-step order is enforced."""
+    L, d = 3, 4
+    c = dict(L=L, d=d, periodic=False, J=1.0, U=0.0, mu=0.0, Delta=0.5, K=0.2)
+    hl = lib.ham_from(c)
+    pool = W.pool(L, "nn", False, W.KITAEV_TYPES)
+    psi0 = O.fock_state(L, d, [0] * L)
+    say("adapt select/finish")
+    a, b = lib.Adapt(hl, pool, dev(psi0), max_iters=6), lib.Adapt(hl, pool, dev(psi0), max_iters=6)
+    for _ in range(3):
+        ra = a.step()
+        sel = b.select()
+        assert sel["k_sel"] == ra["k_sel"] and sel["n_params"] == ra["n_params"]
+        with pytest.raises(lib.FockError):
+            b.select()  # a step is pending
+        rb = b.finish()
+        assert rb == ra
+    with pytest.raises(lib.FockError):
+        b.finish()  # nothing pending
+    sel = b.select()
+    ops, th = b.ansatz()
+    assert len(th) == sel["n_params"] and th[-1] == 0.0
+    with pytest.raises(lib.FockError):
+        b.propose(np.zeros(len(th) + 1))  # the new angle is already appended
+    b.propose(th)  # the plain start itself: accepted (energy not higher)
+    r = b.finish()
+    p = b.last_proposal()
+    assert p["accepted"] and abs(p["E_prop"] - p["E_plain"]) <= 1e-6 * max(1.0, abs(p["E_plain"]))
+    assert r["E"] <= sel["E"] + 1e-9
+    a.close()
+    b.close()
+
+
 def test_adapt_kitaev_kerr_l8_d8_first_steps_replay():
     c = W.config("kk_l8_d8")
     ho, hl = oham(c), lib.ham_from(c)
