@@ -141,10 +141,7 @@ def warm_start_leg(cfg, hl, psi0, k, plain):
     timed part is the k steps including network forwards and proposals;
     training is reported separately."""
     import numpy as np
-    import torch
 
-    import workload as W
-    from paper_2606_05297_amd import lib
     from paper_2606_05297_amd import warmstart as WS
 
     rng = np.random.default_rng(5)
@@ -157,39 +154,13 @@ def warm_start_leg(cfg, hl, psi0, k, plain):
     t0 = time.perf_counter()
     net, hist = WS.train(X, T, nv, epochs=300, batch=256)
     t_train = time.perf_counter() - t0
-    Xd = torch.zeros((2, 4), dtype=torch.float32, device="cuda")
-    ad = lib.Adapt(hl, cfg["pool"], psi0, max_iters=cfg["max_iters"], recycle_hessian=True)
-    torch.cuda.synchronize()
-    t = time.perf_counter()
-    rs, acc, proposed, on_seq = [], [], 0, True
-    for step in range(k):
-        sel = ad.select()
-        if sel["converged"] or sel["capped"]:
-            rs.append(sel)
-            break
-        n = sel["n_params"] - 1
-        on_seq = on_seq and step < len(seq) and sel["k_sel"] == seq[step]
-        if on_seq and n + 1 <= WS.NOUT:
-            Xd.copy_(torch.from_numpy(np.stack([W.mlp_features(cfg["J"], cfg["Delta"], cfg["K"], n + 1),
-                                                W.mlp_features(cfg["J"], cfg["Delta"], cfg["K"], max(n, 1))])))
-            Y = net.forward(Xd).cpu().numpy().astype(np.float64)
-            _, th = ad.ansatz()
-            prop = np.append(th[:n] + Y[0, :n] - Y[1, :n], Y[0, n]) if n > 0 else Y[0, :1]
-            ad.propose(prop)
-            proposed += 1
-        r = ad.finish()
-        if on_seq and n + 1 <= WS.NOUT:
-            acc.append(ad.last_proposal()["accepted"])
-        rs.append(r)
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t
-    ad.close()
+    rs, proposed, kept, dt = WS.adapt_with_network(cfg, hl, psi0, k, net, seq, recycle_hessian=True)
     net.close()
     done = [r for r in rs if r["k_sel"] >= 0]
     return {"steps": len(done), "steps_per_s": len(done) / dt, "E_final": rs[-1]["E"],
             "bfgs_evals_per_step": float(np.mean([r["bfgs_evals"] for r in done])),
             "bfgs_iters_per_step": float(np.mean([r["bfgs_iters"] for r in done])),
-            "proposals": proposed, "accepted": int(sum(acc)),
+            "proposals": proposed, "accepted": kept,
             "speedup_vs_plain_adjoint_recycling": (len(done) / dt) / plain["steps_per_s"],
             "training": {"points": len(pts), "samples": int(len(X)), "sequence_steps": len(seq),
                          "points_on_sequence_per_step": [int(sum(1 for a in agree if a > s)) for s in range(len(seq))],

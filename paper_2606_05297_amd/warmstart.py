@@ -160,6 +160,49 @@ def dataset_agreeing(points, angles, agree):
     return dataset(points, [ang[:a] for ang, a in zip(angles, agree)])
 
 
+def adapt_with_network(cfg, h, psi0, steps, net, seq, **adapt_kw):
+    """Steps 1..steps of one ADAPT run (lib.Adapt on ham h from device psi0)
+    where every step selects first and, while the chosen circuit follows the
+    operator sequence seq the network was trained on, proposes previous
+    angles + the network's predicted shift and its predicted new angle
+    ("delta"), kept by the library only if not above the plain start.
+    Returns (step reports, proposals made, proposals kept, seconds)."""
+    import torch
+
+    from paper_2606_05297_amd import lib
+    import workload as W
+
+    Xd = torch.zeros((2, 4), dtype=torch.float32, device="cuda")
+    ad = lib.Adapt(h, cfg["pool"], psi0, max_iters=cfg["max_iters"], **adapt_kw)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    reps, made, kept, on_seq = [], 0, 0, True
+    for step in range(steps):
+        sel = ad.select()
+        if sel["converged"] or sel["capped"]:
+            reps.append(sel)
+            break
+        n = sel["n_params"] - 1
+        on_seq = on_seq and step < len(seq) and sel["k_sel"] == seq[step]
+        use = on_seq and n + 1 <= NOUT
+        if use:
+            Xd.copy_(torch.from_numpy(np.stack([W.mlp_features(cfg["J"], cfg["Delta"], cfg["K"], n + 1),
+                                                W.mlp_features(cfg["J"], cfg["Delta"], cfg["K"], max(n, 1))])))
+            Y = net.forward(Xd).cpu().numpy().astype(np.float64)
+            _, th = ad.ansatz()
+            ad.propose(np.append(th[:n] + Y[0, :n] - Y[1, :n], Y[0, n]) if n > 0 else Y[0, :1])
+            made += 1
+        r = ad.finish()
+        if use:
+            r.update(ad.last_proposal())
+            kept += int(r["accepted"])
+        reps.append(r)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t
+    ad.close()
+    return reps, made, kept, dt
+
+
 def train(X, T, n, epochs=400, batch=1024, lr=2e-3, seed=0, log=None):
     """Adam on the GPU; returns (network, loss history per epoch)."""
     import torch

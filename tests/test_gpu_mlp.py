@@ -163,3 +163,42 @@ def test_warm_start_gain_on_held_out_points():
     assert sw["acceptance_steps_1_4"] >= 0.5
     assert sw["mean_start_energy_gain_accepted"] > 0.0
     net.close()
+
+
+def test_warm_start_after_selection_on_nearby_points_l6():
+    """The benchmark's warm-start procedure at L=6, d=8 (262,144 amplitudes):
+    plain ADAPT on 8 points around (Delta, K) = (0.5, 0.2) by the batched
+    sweep, training on the steps that follow the majority operator sequence,
+    then 12 steps of the centre point with proposals after selection, against
+    the same 12 steps without the network (both with Hessian recycling).
+    Asserted: training fits; every kept proposal starts no higher than the
+    plain start; the network's run selects the same operators and ends at the
+    same energy (1e-5 relative); BFGS evaluations with and without the network
+    are printed with the proposal counts."""
+    from paper_2606_05297_amd import warmstart as WS
+    steps = 12
+    cfg = dict(W.config("kk_l8_d8"), L=6, pool=W.pool(6, "nn", False, W.KITAEV_TYPES))
+    h = lib.ham_from(cfg)
+    psi0 = torch.zeros(8**6, dtype=torch.complex64, device="cuda")
+    psi0[0] = 1.0
+    rng = np.random.default_rng(5)
+    pts = [dict(cfg, Delta=cfg["Delta"] * f1, K=cfg["K"] * f2) for f1, f2 in rng.uniform(0.9, 1.1, (8, 2))]
+    say("warm start after selection: data")
+    recs, ang = WS.run_sweep(pts, steps)
+    seq, agree = WS.consensus(recs)
+    X, T, nv = WS.dataset_agreeing(pts, ang, agree)
+    say("samples", len(X), "sequence", seq, "agree", agree)
+    net, hist = WS.train(X, T, nv, epochs=300, batch=256)
+    assert hist[-1][1] < 0.5 * hist[0][1]
+    plain, _, _, _ = WS.adapt_with_network(cfg, h, psi0, steps, net, [], recycle_hessian=True)
+    warm, made, kept, _ = WS.adapt_with_network(cfg, h, psi0, steps, net, seq, recycle_hessian=True)
+    net.close()
+    for r in warm:
+        if r.get("accepted"):
+            assert r["E_prop"] <= r["E_plain"]
+    assert made > 0 and kept > 0
+    ep = sum(r["bfgs_evals"] for r in plain)
+    ew = sum(r["bfgs_evals"] for r in warm)
+    same = [r["k_sel"] for r in warm] == [r["k_sel"] for r in plain]
+    say(f"BFGS evaluations over {steps} steps: plain {ep}, with network {ew}; proposals {made}, kept {kept}; "
+        f"same operators: {same}; final E plain {plain[-1]['E']:.8f}, with network {warm[-1]['E']:.8f}")
