@@ -12,9 +12,10 @@ resp. write exactly N bytes; runs without such a copy take the factors
 measured in a run that has one.
 
 --traffic-out writes, per kernel family (the groups the library's own
-profiling counters use), the mean HBM bytes per launch (fetch + write) and a
-hash of the family's sources, so that a reader can tell whether the kernels
-changed since the counters were taken.
+profiling counters use), the HBM bytes (fetch + write) of one library call of
+the family (summed over the kernels one call dispatches) and a hash of the
+family's sources, so that a reader can tell whether the kernels changed since
+the counters were taken.
 """
 from __future__ import annotations
 
@@ -29,13 +30,21 @@ from collections import defaultdict
 COPY = "__amd_rocclr_copyBuffer"
 CSRC = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc")
 
-# kernel family -> (kernel base names, source files the family is built from)
+# kernel family -> (variants, source files the family is built from).  One
+# library call of a family runs one dispatch of each stage of a variant (a
+# stage lists the kernel base names that can fill it); its bytes per call are
+# the sum over the stages of the mean bytes per dispatch.  The first variant
+# whose stages all appear in the counter runs is used.
 FAMILIES = {
-    "apply_h": (("k_apply_h", "k_apply_h_lanes8"), ("kernels_h.hip", "stencil_kernels.h", "device_common.h")),
-    "pool_grads": (("k_pool",), ("kernels_pool.hip", "stencil_kernels.h", "device_common.h")),
-    "gate2": (("k_gate2", "k_gate2_m0"), ("gate_kernels.h", "kernels_gate.hip", "device_common.h")),
-    "gate2_adjoint": (("k_gate2_adj", "k_gate2_adj_m0"), ("gate_kernels.h", "kernels_gate.hip", "device_common.h")),
-    "diag_gate": (("k_diag", "k_diag_adj"), ("gate_kernels.h", "kernels_gate.hip", "device_common.h")),
+    "apply_h": (((("k_h8_col",), ("k_h8_row",)), (("k_apply_h", "k_apply_h_lanes8"),)),
+                ("stencil2.hip", "kernels_h.hip", "stencil_kernels.h", "device_common.h")),
+    "pool_grads": (((("k_pool8_row",), ("k_pool8_col",)), (("k_pool",),)),
+                   ("stencil2.hip", "kernels_pool.hip", "stencil_kernels.h", "device_common.h")),
+    "score": (((("k_h8_col",), ("k_h8_row_score",), ("k_pool8_col",)),), ("stencil2.hip", "device_common.h")),
+    "gate2": (((("k_gate2", "k_gate2_m0"),),), ("gate_kernels.h", "kernels_gate.hip", "device_common.h")),
+    "gate2_adjoint": (((("k_gate2_adj", "k_gate2_adj_m0"),),),
+                      ("gate_kernels.h", "kernels_gate.hip", "device_common.h")),
+    "diag_gate": (((("k_diag", "k_diag_adj"),),), ("gate_kernels.h", "kernels_gate.hip", "device_common.h")),
 }
 
 
@@ -47,15 +56,29 @@ def source_sha(family: str) -> str:
     return h.hexdigest()[:16]
 
 
-def family_of(kname: str):
-    base = kname.split("<")[0].split("::")[-1]
-    for fam, (names, _) in FAMILIES.items():
-        if base in names:
-            return fam
+def base_of(kname: str) -> str:
+    return kname.split("<")[0].split("::")[-1]
+
+
+def family_bytes(fam: str, per_kernel: dict):
+    """Bytes per library call of family fam from per-kernel dispatch values
+    (mean over the dispatches of each stage, summed over the stages), with the
+    number of dispatches used; None when no variant is complete."""
+    for stages in FAMILIES[fam][0]:
+        total, n = 0.0, 0
+        for stage in stages:
+            vals = [v for k, vs in per_kernel.items() if base_of(k) in stage for v in vs]
+            if not vals:
+                break
+            total += sum(vals) / len(vals)
+            n += len(vals)
+        else:
+            return total, n
     return None
 
 
 def short(name: str) -> str:
+    name = name.replace("(anonymous namespace)::", "")
     m = re.match(r"^(?:void )?([\w:]+(?:<[^()]*>)?)", name)
     return m.group(1) if m else name[:80]
 
@@ -125,14 +148,12 @@ def main():
     if a.traffic_out and fe and wr and ffac and wfac:
         fam = {}
         for f in FAMILIES:
-            fb = [v for k, vs in fe.items() if family_of(k) == f for v in vs]
-            wb = [v for k, vs in wr.items() if family_of(k) == f for v in vs]
+            fb, wb = family_bytes(f, fe), family_bytes(f, wr)
             if fb and wb:
-                per = 1024.0 * (ffac * sum(fb) / len(fb) + wfac * sum(wb) / len(wb))
-                fam[f] = {"hbm_bytes_per_launch": per, "fetch_bytes_per_launch": 1024.0 * ffac * sum(fb) / len(fb),
-                          "write_bytes_per_launch": 1024.0 * wfac * sum(wb) / len(wb), "launches": len(fb),
-                          "source_sha": source_sha(f)}
-                print(f"family {f:14s} launches {len(fb):5d}  HBM bytes/launch {per / 1e6:10.1f} MB")
+                fetch, write = 1024.0 * ffac * fb[0], 1024.0 * wfac * wb[0]
+                fam[f] = {"hbm_bytes_per_launch": fetch + write, "fetch_bytes_per_launch": fetch,
+                          "write_bytes_per_launch": write, "dispatches": fb[1], "source_sha": source_sha(f)}
+                print(f"family {f:14s} dispatches {fb[1]:5d}  HBM bytes per call {(fetch + write) / 1e6:10.1f} MB")
         with open(a.traffic_out, "w") as fh:
             json.dump({"fetch_factor": ffac, "write_factor": wfac, "families": fam}, fh, indent=1)
 
