@@ -21,14 +21,14 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 NAMES = {0: "apply_h", 1: "pool_grads", 2: "gate2", 3: "gate2_adjoint", 4: "diag_gate", 6: "mlp_forward",
-         7: "mlp_train_step", 8: "gate2_dense_mfma"}
+         7: "mlp_train_step", 8: "gate2_dense_mfma", 9: "score"}
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--workload", default="kk_l8_d8")
     ap.add_argument("--iters", type=int, default=20)
-    ap.add_argument("--kernels", default="copy,apply_h,pool,gate,adjoint,dense,mlp")
+    ap.add_argument("--kernels", default="copy,apply_h,pool,score,gate,adjoint,dense,mlp")
     ap.add_argument("--mlp-batch", type=int, default=16384)
     ap.add_argument("--lib", default=None, help="path of an alternative libfock.so build")
     ap.add_argument("--schedule", type=int, default=None, help="stencil tile schedule (fock_set_stencil_schedule)")
@@ -100,6 +100,10 @@ def main():
         for k in range(args.iters):
             lib.pool_grads(h, cfg["pool"], states[k % 3], outs[k % 3], ws)
         print(f"[kbench] pool done", file=sys.stderr, flush=True)
+    if "score" in want:
+        for k in range(args.iters):
+            lib.score(h, cfg["pool"], states[k % 3], outs[k % 3], ws)
+        print(f"[kbench] score done", file=sys.stderr, flush=True)
     if "gate" in want:
         pairs = [(0, 1), (3, 4), (L - 2, L - 1), (1, 2)]
         types = ["HR", "PR"] if cfg["Delta"] != 0 else ["HR", "DH"]
