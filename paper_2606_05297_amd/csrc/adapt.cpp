@@ -38,6 +38,7 @@ struct fock_adapt {
   // a step between adapt_step_select and adapt_step_finish
   bool pending = false;
   fock_adapt_report_t pend{};
+  void *store_buf = nullptr;  // forward states of gradient evaluations (may be null)
 };
 
 namespace {
@@ -173,6 +174,7 @@ int adapt_create(const fock_ham_t *ham, const fock_op_t *pool, int P, const void
   st->lam = (float2 *)(b + 2 * sbytes);
   st->ws = b + 3 * sbytes;
   rc = make_ctx(*ham, namp, P, nmax, st->ws, st->ws_bytes, st->s, &st->ctx);
+  if (!rc) rc = attach_state_store(st->ctx, nmax, &st->store_buf);
   if (!rc && hipMemcpyAsync(st->psi0, psi0, sizeof(float2) * namp, hipMemcpyDeviceToDevice, st->s) != hipSuccess)
     rc = set_error(FOCK_ERR_HIP, "copy of psi0 failed");
   if (!rc) {
@@ -193,6 +195,7 @@ int adapt_create(const fock_ham_t *ham, const fock_op_t *pool, int P, const void
   if (rc) {
     (void)hipStreamSynchronize(st->s);
     (void)hipFree(st->dbuf);
+    if (st->store_buf) (void)hipFree(st->store_buf);
     delete st;
     return rc;
   }
@@ -336,10 +339,17 @@ int adapt_last_proposal(fock_adapt_t *st, int *accepted, double *E_prop, double 
   return FOCK_OK;
 }
 
+int adapt_state_store(fock_adapt_t *st, int *nstates) {
+  if (!st || !nstates) return set_error(FOCK_ERR_ARG, "NULL argument");
+  *nstates = st->ctx.nstore;
+  return FOCK_OK;
+}
+
 int adapt_destroy(fock_adapt_t *st) {
   if (!st) return FOCK_OK;
   (void)hipStreamSynchronize(st->s);
   if (st->dbuf) (void)hipFree(st->dbuf);
+  if (st->store_buf) (void)hipFree(st->store_buf);
   delete st;
   return FOCK_OK;
 }

@@ -197,6 +197,42 @@ int stage_gates(Ctx &c, const fock_op_t *ops, const double *theta, int n, const 
                            (float2 *)(c.ws + c.L.utab), c.s);
 }
 
+static std::atomic<int> g_state_store{FOCK_STORE_AUTO};
+
+// States up to this size stay in the 256 MiB Infinity Cache while gates update
+// them in place, which then beats writing each forward state to a fresh buffer
+// (measured: neutral at 134 MB, +10 % steps/s with the store at 1.07 GB).
+constexpr size_t kStoreAutoMinBytes = (size_t)256 << 20;
+
+// A store of nmax forward states for c, when switched on (always, or with
+// FOCK_STORE_AUTO when one state exceeds the Infinity Cache) and the device has
+// room (the store takes at most half of the free device memory); *owner
+// receives the allocation, or nullptr when no store is kept (the in-place
+// reverse sweep then runs).
+int attach_state_store(Ctx &c, int nmax, void **owner) {
+  *owner = nullptr;
+  const int mode = g_state_store.load();
+  const size_t sbytes = (sizeof(float2) * (size_t)c.g.n_amp + 255) & ~(size_t)255;
+  if (mode == FOCK_STORE_OFF || nmax < 1) return FOCK_OK;
+  if (mode == FOCK_STORE_AUTO && sbytes <= kStoreAutoMinBytes) return FOCK_OK;
+  const size_t need = sbytes * (size_t)nmax;
+  size_t fr = 0, tot = 0;
+  if (hipMemGetInfo(&fr, &tot) != hipSuccess || need > fr / 2) {
+    (void)hipGetLastError();
+    return FOCK_OK;
+  }
+  void *p = nullptr;
+  if (hipMalloc(&p, need) != hipSuccess) {
+    (void)hipGetLastError();
+    return FOCK_OK;
+  }
+  c.store = (float2 *)p;
+  c.nstore = nmax;
+  c.sstride = sbytes / sizeof(float2);
+  *owner = p;
+  return FOCK_OK;
+}
+
 static std::atomic<int> g_gate_variant{FOCK_GATE_BLOCK};
 
 int gate_variant() { return g_gate_variant.load(); }
@@ -349,6 +385,42 @@ static int stage_circuit(Ctx &c, const fock_op_t *ops, const double *theta, int 
   return stage_gates(c, ops, theta, n, nblk.data());
 }
 
+// True when a gradient evaluation of this circuit can keep its forward states:
+// a store of at least n states, no fused gate runs and no squeezer gates
+// (their reverse kernels always rewrite phi).
+static bool use_store(const Ctx &c, const fock_op_t *ops, int n, const std::vector<GateGroup> &groups) {
+  if (!c.store || n < 1 || n > c.nstore) return false;
+  for (const GateGroup &gr : groups)
+    if (gr.s > 0) return false;
+  for (int k = 0; k < n; ++k)
+    if (is_squeeze(ops[k].type)) return false;
+  return true;
+}
+
+static float2 *stored_state(const Ctx &c, int k) { return c.store + (size_t)(k - 1) * c.sstride; }
+
+// Reverse sweep with the forward states kept: gate k reads phi_k from the
+// store (read-only) and updates lam <- U_k^+ lam; 24 B per amplitude instead
+// of 32.
+static int reverse_sweep_stored(Ctx &c, const fock_op_t *ops, int n, float2 *lam, double *res) {
+  const float2 *utab = (const float2 *)(c.ws + c.L.utab);
+  double *part = (double *)(c.ws + c.L.partial);
+  const int stride = gate_stride(c.g.d);
+  for (int k = n - 1; k >= 0; --k) {
+    const fock_op_t &op = ops[k];
+    const float2 *U = utab + (size_t)k * stride;
+    double *pk = part + (size_t)k * c.L.rs;
+    float2 *phik = stored_state(c, k + 1);
+    ProfScope ps(is_single_mode(op.type) ? FOCK_K_DIAG : FOCK_K_ADJ, c.s, 24.0 * c.g.n_amp);
+    const int rc = is_single_mode(op.type)
+                       ? launch_diag_adj(c.g, op.i, op.type, U, phik, lam, pk, c.s, false)
+                       : launch_gate_adj(c.g, op.i, op.j, gate_kind(op.type), U, c.T.A[table_slot(op.type)], phik, lam,
+                                         pk, c.s, false);
+    if (rc) return rc;
+  }
+  return launch_reduce_rows(part, c.L.rs, (const GateRec *)(c.ws + c.L.recs), n, res, c.s);
+}
+
 // Reverse sweep from phi = psi_n, lam = H psi_n (both overwritten): per-gate
 // sums of Re<lam|A_k phi> reduced into res[0..n) (device), in stream order.
 static int reverse_sweep(Ctx &c, const fock_op_t *ops, int n, const std::vector<GateGroup> &groups, float2 *phi,
@@ -381,6 +453,16 @@ static int reverse_sweep(Ctx &c, const fock_op_t *ops, int n, const std::vector<
     }
   }
   return launch_reduce_rows(part, c.L.rs, (const GateRec *)(c.ws + c.L.recs), n, res, c.s);
+}
+
+// phi_k = O_k phi_{k-1} into store buffer k - 1 for k = 1..n (phi_0 = psi0).
+static int forward_stored(Ctx &c, const fock_op_t *ops, int n, const void *psi0) {
+  for (int k = 0; k < n; ++k) {
+    const float2 *src = k == 0 ? (const float2 *)psi0 : stored_state(c, k);
+    const int rc = forward_gate(c, ops[k], k, false, src, stored_state(c, k + 1));
+    if (rc) return rc;
+  }
+  return FOCK_OK;
 }
 
 // phi = O_n..O_1 psi0 for a staged circuit (the first gate reads psi0 directly).
@@ -430,13 +512,20 @@ int run_circuit(Ctx &c, const fock_op_t *ops, const double *theta, int n, const 
   std::vector<GateGroup> groups;
   int rc = stage_circuit(c, ops, theta, n, &groups);
   if (rc) return rc;
-  if ((rc = forward_circuit(c, ops, n, groups, psi0, phi))) return rc;
   double *res = (double *)(c.ws + c.L.result);
-  rc = apply_h_dev(c, phi, lam, res);
-  if (rc) return rc;
-  if (grad && n > 0) {
-    rc = reverse_sweep(c, ops, n, groups, phi, lam, res + 2);
+  if (grad && use_store(c, ops, n, groups)) {
+    // forward states kept: H psi_n reads the last one; phi is not touched
+    if ((rc = forward_stored(c, ops, n, psi0))) return rc;
+    if ((rc = apply_h_dev(c, stored_state(c, n), lam, res))) return rc;
+    if ((rc = reverse_sweep_stored(c, ops, n, lam, res + 2))) return rc;
+  } else {
+    if ((rc = forward_circuit(c, ops, n, groups, psi0, phi))) return rc;
+    rc = apply_h_dev(c, phi, lam, res);
     if (rc) return rc;
+    if (grad && n > 0) {
+      rc = reverse_sweep(c, ops, n, groups, phi, lam, res + 2);
+      if (rc) return rc;
+    }
   }
   const int cnt = 2 + ((grad && n > 0) ? n : 0);
   std::vector<double> host(cnt);
@@ -889,6 +978,15 @@ int fock_score(const fock_ham_t *ham, const fock_op_t *pool, int P, const void *
   for (int k = 0; k < P; ++k) grads[k] = host[2 + k];
   return FOCK_OK;
 }
+
+int fock_set_state_store(int mode) {
+  if (mode != FOCK_STORE_OFF && mode != FOCK_STORE_ON && mode != FOCK_STORE_AUTO)
+    return set_error(FOCK_ERR_ARG, "state store mode %d is not OFF (0), ON (1) or AUTO (2)", mode);
+  g_state_store.store(mode);
+  return FOCK_OK;
+}
+
+int fock_get_state_store(void) { return g_state_store.load(); }
 
 int fock_adjoint_sweep(const fock_ham_t *ham, const fock_op_t *ops, const double *theta, int n, void *psi_work,
                        void *lam_work, double norm2, double *dEdtheta, void *ws, size_t ws_bytes,

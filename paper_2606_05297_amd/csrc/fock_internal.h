@@ -175,16 +175,17 @@ int launch_gate_build(const double *theta, const GateRec *recs, int n, const Eig
 int launch_gate(const Geometry &g, int i, int j, int kind, bool dag, const float2 *U, const float2 *src, float2 *psi,
                 hipStream_t s);
 // Fused reverse step: partial[blk] = per-block sum of Re<lam|A phi>, then
-// phi <- U^+ phi, lam <- U^+ lam.
+// phi <- U^+ phi (unless write_phi is false: phi is then only read) and
+// lam <- U^+ lam.
 int launch_gate_adj(const Geometry &g, int i, int j, int kind, const float2 *U, const float2 *A, float2 *phi,
-                    float2 *lam, double *partial, hipStream_t s);
+                    float2 *lam, double *partial, hipStream_t s, bool write_phi = true);
 int gate_blocks_count(const Geometry &g, int i);  // workgroups of a gate on (i, j)
 int gate_blocks_max(const Geometry &g);
 // Single-mode diagonal gate with device phase table ph[d].
 int launch_diag(const Geometry &g, int r, int type, bool dag, const float2 *ph, const float2 *src, float2 *psi,
                 hipStream_t s);
 int launch_diag_adj(const Geometry &g, int r, int type, const float2 *ph, float2 *phi, float2 *lam,
-                    double *partial, hipStream_t s);
+                    double *partial, hipStream_t s, bool write_phi = true);
 int diag_blocks_count(const Geometry &g);
 // Squeezer gates (gate1_kernels.hip): U, A are d x d row-major; the reverse
 // step and the pool scoring write one partial per workgroup

@@ -140,9 +140,10 @@ __device__ __forceinline__ void gate_group(CPtr src, Ptr base, uint32_t si, uint
 }
 
 // Fused reverse step on group G: returns sum Re(conj(lam) A phi) over the
-// group's members, then phi <- U^+ phi, lam <- U^+ lam.  A's blocks are
-// tridiagonal in the member order (the generators move n_i by one).
-template <int D, int KIND, int NG, int G, class Ptr>
+// group's members, then phi <- U^+ phi (only when WPHI: with the forward
+// states kept, phi is read-only), lam <- U^+ lam.  A's blocks are tridiagonal
+// in the member order (the generators move n_i by one).
+template <int D, int KIND, int NG, int G, bool WPHI = true, class Ptr>
 __device__ __forceinline__ float adj_group_blockwise(Ptr pb, Ptr lb, uint32_t si, uint32_t sj,
                                                      const float2 *__restrict__ U, const float2 *__restrict__ A) {
   constexpr Groups<D, NG> P{};
@@ -177,11 +178,11 @@ __device__ __forceinline__ float adj_group_blockwise(Ptr pb, Ptr lb, uint32_t si
           for (int q = 0; q < D; ++q)
             if (q < b) {
               const float2 u = U[off + q * b + p];
-              cmac_conj(np, u, pv[q]);
+              if (WPHI) cmac_conj(np, u, pv[q]);
               cmac_conj(nl, u, lv[q]);
             }
           const uint32_t o = member_off<D, KIND>(s, lo + p, si, sj);
-          pb[o] = np;
+          if (WPHI) pb[o] = np;
           lb[o] = nl;
         }
     }
@@ -190,10 +191,10 @@ __device__ __forceinline__ float adj_group_blockwise(Ptr pb, Ptr lb, uint32_t si
   return gacc;
 }
 
-template <int D, int KIND, int NG, int G, class Ptr>
+template <int D, int KIND, int NG, int G, bool WPHI = true, class Ptr>
 __device__ __forceinline__ float adj_group(Ptr pb, Ptr lb, uint32_t si, uint32_t sj, const float2 *__restrict__ U,
                                            const float2 *__restrict__ A) {
-  if constexpr (D > 8) return adj_group_blockwise<D, KIND, NG, G>(pb, lb, si, sj, U, A);
+  if constexpr (D > 8) return adj_group_blockwise<D, KIND, NG, G, WPHI>(pb, lb, si, sj, U, A);
   constexpr Groups<D, NG> P{};
   float2 pv[D * D], lv[D * D];
   int m = 0;
@@ -234,11 +235,11 @@ __device__ __forceinline__ float adj_group(Ptr pb, Ptr lb, uint32_t si, uint32_t
           for (int q = 0; q < D; ++q)
             if (q < b) {
               const float2 u = U[off + q * b + p];
-              cmac_conj(np, u, pv[m + q]);
+              if (WPHI) cmac_conj(np, u, pv[m + q]);
               cmac_conj(nl, u, lv[m + q]);
             }
           const uint32_t o = member_off<D, KIND>(s, lo + p, si, sj);
-          pb[o] = np;
+          if (WPHI) pb[o] = np;
           lb[o] = nl;
         }
       m += b;
@@ -273,7 +274,7 @@ __device__ __forceinline__ void gate2_direct_block(int vb, const float2 *src, fl
   }
 }
 
-template <int D, int KIND>
+template <int D, int KIND, bool WPHI = true>
 __device__ __forceinline__ float adj_direct_block(int vb, float2 *phi, float2 *lam, const float2 *__restrict__ U,
                                                   const float2 *__restrict__ A, const GateLaunch &g) {
   constexpr int NG = direct_groups<D>();
@@ -286,10 +287,10 @@ __device__ __forceinline__ float adj_direct_block(int vb, float2 *phi, float2 *l
     const uint32_t fb = fiber_base(f, g, D);
     float2 *pb = phi + fb, *lb = lam + fb;
     switch (gi) {
-      case 0: gacc = adj_group<D, KIND, NG, 0>(pb, lb, g.si, g.sj, U, A); break;
-      case 1: if constexpr (NG > 1) gacc = adj_group<D, KIND, NG, 1>(pb, lb, g.si, g.sj, U, A); break;
-      case 2: if constexpr (NG > 2) gacc = adj_group<D, KIND, NG, 2>(pb, lb, g.si, g.sj, U, A); break;
-      default: if constexpr (NG > 3) gacc = adj_group<D, KIND, NG, 3>(pb, lb, g.si, g.sj, U, A); break;
+      case 0: gacc = adj_group<D, KIND, NG, 0, WPHI>(pb, lb, g.si, g.sj, U, A); break;
+      case 1: if constexpr (NG > 1) gacc = adj_group<D, KIND, NG, 1, WPHI>(pb, lb, g.si, g.sj, U, A); break;
+      case 2: if constexpr (NG > 2) gacc = adj_group<D, KIND, NG, 2, WPHI>(pb, lb, g.si, g.sj, U, A); break;
+      default: if constexpr (NG > 3) gacc = adj_group<D, KIND, NG, 3, WPHI>(pb, lb, g.si, g.sj, U, A); break;
     }
   }
   return gacc;
@@ -301,13 +302,13 @@ __global__ __launch_bounds__(kBlock) void k_gate2(const float2 *src, float2 *psi
   gate2_direct_block<D, KIND, DAG>(xcd_remap(blockIdx.x, gridDim.x), src, psi, U, g);
 }
 
-template <int D, int KIND>
+template <int D, int KIND, bool WPHI>
 __global__ __launch_bounds__(kBlock) void k_gate2_adj(float2 *__restrict__ phi, float2 *__restrict__ lam,
                                                       const float2 *__restrict__ U, const float2 *__restrict__ A,
                                                       double *__restrict__ partial, GateLaunch g) {
   __shared__ double red[4];
   const int vb = xcd_remap(blockIdx.x, gridDim.x);
-  const float gacc = adj_direct_block<D, KIND>(vb, phi, lam, U, A, g);
+  const float gacc = adj_direct_block<D, KIND, WPHI>(vb, phi, lam, U, A, g);
   const double sg = block_sum_d((double)gacc, red);
   if (threadIdx.x == 0) partial[vb] = sg;
 }
@@ -387,7 +388,7 @@ __device__ __forceinline__ void gate2_m0_block(int vb, const float2 *src, float2
   __syncthreads();
 }
 
-template <int D, int KIND>
+template <int D, int KIND, bool WPHI = true>
 __device__ __forceinline__ float adj_m0_block(int vb, float2 *phi, float2 *lam, const float2 *__restrict__ U,
                                               const float2 *__restrict__ A, const GateLaunch &g, float2 *tp,
                                               float2 *tl, uint32_t *fbase) {
@@ -404,14 +405,14 @@ __device__ __forceinline__ float adj_m0_block(int vb, float2 *phi, float2 *lam, 
   if ((uint32_t)lane < nf && lane < FL) {
     float2 *pb = tp + lane * ST, *lb = tl + lane * ST;
     switch (wave) {
-      case 0: gacc = adj_group<D, KIND, 4, 0>(pb, lb, 1u, (uint32_t)D, U, A); break;
-      case 1: gacc = adj_group<D, KIND, 4, 1>(pb, lb, 1u, (uint32_t)D, U, A); break;
-      case 2: gacc = adj_group<D, KIND, 4, 2>(pb, lb, 1u, (uint32_t)D, U, A); break;
-      default: gacc = adj_group<D, KIND, 4, 3>(pb, lb, 1u, (uint32_t)D, U, A); break;
+      case 0: gacc = adj_group<D, KIND, 4, 0, WPHI>(pb, lb, 1u, (uint32_t)D, U, A); break;
+      case 1: gacc = adj_group<D, KIND, 4, 1, WPHI>(pb, lb, 1u, (uint32_t)D, U, A); break;
+      case 2: gacc = adj_group<D, KIND, 4, 2, WPHI>(pb, lb, 1u, (uint32_t)D, U, A); break;
+      default: gacc = adj_group<D, KIND, 4, 3, WPHI>(pb, lb, 1u, (uint32_t)D, U, A); break;
     }
   }
   __syncthreads();
-  tile_copy<D>(tp, phi, fbase, g.sj, false, nf);
+  if (WPHI) tile_copy<D>(tp, phi, fbase, g.sj, false, nf);
   tile_copy<D>(tl, lam, fbase, g.sj, false, nf);
   __syncthreads();
   return gacc;
@@ -425,7 +426,7 @@ __global__ __launch_bounds__(kBlock) void k_gate2_m0(const float2 *src, float2 *
   gate2_m0_block<D, KIND, DAG>(xcd_remap(blockIdx.x, gridDim.x), src, psi, U, g, tile, fbase);
 }
 
-template <int D, int KIND>
+template <int D, int KIND, bool WPHI>
 __global__ __launch_bounds__(kBlock) void k_gate2_adj_m0(float2 *__restrict__ phi, float2 *__restrict__ lam,
                                                          const float2 *__restrict__ U, const float2 *__restrict__ A,
                                                          double *__restrict__ partial, GateLaunch g) {
@@ -433,7 +434,7 @@ __global__ __launch_bounds__(kBlock) void k_gate2_adj_m0(float2 *__restrict__ ph
   __shared__ uint32_t fbase[lds_fibers<D>()];
   __shared__ double red[4];
   const int vb = xcd_remap(blockIdx.x, gridDim.x);
-  const float gacc = adj_m0_block<D, KIND>(vb, phi, lam, U, A, g, tp, tl, fbase);
+  const float gacc = adj_m0_block<D, KIND, WPHI>(vb, phi, lam, U, A, g, tp, tl, fbase);
   const double sg = block_sum_d((double)gacc, red);
   if (threadIdx.x == 0) partial[vb] = sg;
 }
@@ -471,7 +472,7 @@ __device__ __forceinline__ void diag_block(int vb, const float2 *src, float2 *ps
   __syncthreads();
 }
 
-template <int D>
+template <int D, bool WPHI = true>
 __device__ __forceinline__ float diag_adj_block(int vb, float2 *phi, float2 *lam, const float2 *__restrict__ phg,
                                                 const DiagLaunch &a, float2 *phs) {
   if (threadIdx.x < D) phs[threadIdx.x] = phg[threadIdx.x];
@@ -491,12 +492,12 @@ __device__ __forceinline__ float diag_adj_block(int vb, float2 *phi, float2 *lam
       gacc = fmaf(-f, lv[q].x * pv[q].y - lv[q].y * pv[q].x, gacc);
       const float2 p = phs[lev];
       float2 np = make_float2(0.f, 0.f), nl = make_float2(0.f, 0.f);
-      cmac_conj(np, p, pv[q]);
+      if (WPHI) cmac_conj(np, p, pv[q]);
       cmac_conj(nl, p, lv[q]);
       pv[q] = np;
       lv[q] = nl;
     }
-    store_row<D>(phi + (size_t)row * D, pv);
+    if (WPHI) store_row<D>(phi + (size_t)row * D, pv);
     store_row<D>(lam + (size_t)row * D, lv);
   }
   __syncthreads();
@@ -510,14 +511,14 @@ __global__ __launch_bounds__(kBlock) void k_diag(const float2 *src, float2 *psi,
   diag_block<D, DAG>(xcd_remap(blockIdx.x, gridDim.x), src, psi, phg, a, phs);
 }
 
-template <int D>
+template <int D, bool WPHI>
 __global__ __launch_bounds__(kBlock) void k_diag_adj(float2 *__restrict__ phi, float2 *__restrict__ lam,
                                                      const float2 *__restrict__ phg, double *__restrict__ partial,
                                                      DiagLaunch a) {
   __shared__ float2 phs[kMaxD];
   __shared__ double red[4];
   const int vb = xcd_remap(blockIdx.x, gridDim.x);
-  const float gacc = diag_adj_block<D>(vb, phi, lam, phg, a, phs);
+  const float gacc = diag_adj_block<D, WPHI>(vb, phi, lam, phg, a, phs);
   const double sg = block_sum_d((double)gacc, red);
   if (threadIdx.x == 0) partial[vb] = sg;
 }
@@ -545,13 +546,20 @@ void gate_launch_d(const GateLaunch &gl, int i, int kind, bool dag, const float2
 
 template <int D>
 void adj_launch_d(const GateLaunch &gl, int i, int kind, const float2 *U, const float2 *A, float2 *phi, float2 *lam,
-                  double *partial, int G, hipStream_t s) {
-#define ADJ_K(KN, K) hipLaunchKernelGGL((KN<D, K>), dim3(G), dim3(kBlock), 0, s, phi, lam, U, A, partial, gl)
-  if (i == 0) {
-    if (kind == KIND_SUM) ADJ_K(k_gate2_adj_m0, KIND_SUM); else ADJ_K(k_gate2_adj_m0, KIND_DIFF);
-  } else {
-    if (kind == KIND_SUM) ADJ_K(k_gate2_adj, KIND_SUM); else ADJ_K(k_gate2_adj, KIND_DIFF);
+                  double *partial, int G, bool wphi, hipStream_t s) {
+#define ADJ_K(KN, K, W) hipLaunchKernelGGL((KN<D, K, W>), dim3(G), dim3(kBlock), 0, s, phi, lam, U, A, partial, gl)
+#define ADJ_SEL(KN)                                                      \
+  if (kind == KIND_SUM) {                                                \
+    if (wphi) ADJ_K(KN, KIND_SUM, true); else ADJ_K(KN, KIND_SUM, false);    \
+  } else {                                                               \
+    if (wphi) ADJ_K(KN, KIND_DIFF, true); else ADJ_K(KN, KIND_DIFF, false);  \
   }
+  if (i == 0) {
+    ADJ_SEL(k_gate2_adj_m0);
+  } else {
+    ADJ_SEL(k_gate2_adj);
+  }
+#undef ADJ_SEL
 #undef ADJ_K
 }
 
@@ -560,12 +568,12 @@ void adj_launch_d(const GateLaunch &gl, int i, int kind, const float2 *U, const 
   template void gate_launch_d<D>(const GateLaunch &, int, int, bool, const float2 *, const float2 *,       \
                                  float2 *, int, hipStream_t);                                              \
   template void adj_launch_d<D>(const GateLaunch &, int, int, const float2 *, const float2 *, float2 *,    \
-                                float2 *, double *, int, hipStream_t);
+                                float2 *, double *, int, bool, hipStream_t);
 #define FOCK_GATE_EXTERN(D)                                                                                  \
   extern template int fibers_per_block_d<D>(int);                                                          \
   extern template void gate_launch_d<D>(const GateLaunch &, int, int, bool, const float2 *, const float2 *, \
                                         float2 *, int, hipStream_t);                                       \
   extern template void adj_launch_d<D>(const GateLaunch &, int, int, const float2 *, const float2 *,       \
-                                       float2 *, float2 *, double *, int, hipStream_t);
+                                       float2 *, float2 *, double *, int, bool, hipStream_t);
 
 }  // namespace fock

@@ -33,6 +33,7 @@ struct fock_hva {
   size_t ws_bytes = 0;
   Ctx ctx;
   fock_adapt_report_t init{};
+  void *store_buf = nullptr;  // forward states of gradient evaluations (may be null)
 };
 
 extern "C" {
@@ -77,6 +78,7 @@ int hva_create(const fock_ham_t *ham, const fock_op_t *layer, int n_layer, int m
   st->lam = (float2 *)(b + 2 * sbytes);
   st->ws = b + 3 * sbytes;
   rc = make_ctx(*ham, namp, 0, nmax, st->ws, st->ws_bytes, st->s, &st->ctx);
+  if (!rc) rc = attach_state_store(st->ctx, nmax, &st->store_buf);
   if (!rc) {
     // the caller's psi0 must be complete before this stream copies it
     if (hipStreamSynchronize((hipStream_t)stream) != hipSuccess ||
@@ -93,6 +95,7 @@ int hva_create(const fock_ham_t *ham, const fock_op_t *layer, int n_layer, int m
   if (rc) {
     (void)hipStreamSynchronize(st->s);
     (void)hipFree(st->dbuf);
+    if (st->store_buf) (void)hipFree(st->store_buf);
     delete st;
     return rc;
   }
@@ -162,6 +165,7 @@ int hva_destroy(fock_hva_t *st) {
   if (!st) return FOCK_OK;
   (void)hipStreamSynchronize(st->s);
   if (st->dbuf) (void)hipFree(st->dbuf);
+  if (st->store_buf) (void)hipFree(st->store_buf);
   delete st;
   return FOCK_OK;
 }

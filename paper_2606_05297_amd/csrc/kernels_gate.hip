@@ -153,10 +153,10 @@ int launch_gate(const Geometry &g, int i, int j, int kind, bool dag, const float
 }
 
 int launch_gate_adj(const Geometry &g, int i, int j, int kind, const float2 *U, const float2 *A, float2 *phi,
-                    float2 *lam, double *partial, hipStream_t s) {
+                    float2 *lam, double *partial, hipStream_t s, bool write_phi) {
   const GateLaunch gl = make_gate_launch(g, i, j);
   const int G = gate_blocks_count(g, i);
-  FOCK_D_SWITCH(g.d, adj_launch_d<D>(gl, i, kind, U, A, phi, lam, partial, G, s));
+  FOCK_D_SWITCH(g.d, adj_launch_d<D>(gl, i, kind, U, A, phi, lam, partial, G, write_phi, s));
   FOCK_HIP(hipGetLastError());
   return FOCK_OK;
 }
@@ -193,10 +193,16 @@ int launch_diag(const Geometry &g, int r, int type, bool dag, const float2 *ph, 
 }
 
 int launch_diag_adj(const Geometry &g, int r, int type, const float2 *ph, float2 *phi, float2 *lam,
-                    double *partial, hipStream_t s) {
+                    double *partial, hipStream_t s, bool write_phi) {
   const DiagLaunch a = make_diag_launch(g, r, type);
   const int G = diag_blocks_count(g);
-  FOCK_D_SWITCH(g.d, hipLaunchKernelGGL(k_diag_adj<D>, dim3(G), dim3(kBlock), 0, s, phi, lam, ph, partial, a));
+  if (write_phi) {
+    FOCK_D_SWITCH(g.d, hipLaunchKernelGGL((k_diag_adj<D, true>), dim3(G), dim3(kBlock), 0, s, phi, lam, ph, partial,
+                                          a));
+  } else {
+    FOCK_D_SWITCH(g.d, hipLaunchKernelGGL((k_diag_adj<D, false>), dim3(G), dim3(kBlock), 0, s, phi, lam, ph, partial,
+                                          a));
+  }
   FOCK_HIP(hipGetLastError());
   return FOCK_OK;
 }

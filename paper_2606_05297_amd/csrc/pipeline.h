@@ -20,6 +20,13 @@ struct Ctx {
   hipStream_t s;
   char *ws;
   Layout L;
+  // Optional store of forward states: nstore device buffers of one state each
+  // (stride `sstride` amplitudes).  With a store, a gradient evaluation keeps
+  // phi_k = O_k..O_1 psi0 in buffer k - 1 and the reverse sweep reads it
+  // instead of undoing each gate on phi.
+  float2 *store = nullptr;
+  int nstore = 0;
+  size_t sstride = 0;
 };
 
 int check_geometry(int L, int d, uint32_t *namp);
@@ -29,6 +36,9 @@ int check_ptr(const void *p, const char *name);
 HamArgs make_ham_args(const fock_ham_t &h);
 Layout make_layout(uint32_t namp, int L, int d, int P, int n);
 int make_ctx(const fock_ham_t &ham, uint32_t namp, int P, int n, void *ws, size_t ws_bytes, hipStream_t s, Ctx *c);
+// Attach a store of nmax forward states to c if switched on and the device has
+// room; *owner receives the allocation to free (nullptr: no store).
+int attach_state_store(Ctx &c, int nmax, void **owner);
 int stage_gates(Ctx &c, const fock_op_t *ops, const double *theta, int n, const int *nblk);
 // psi <- O_k src (src == psi: in place)
 int forward_gate(Ctx &c, const fock_op_t &op, int k, bool dag, const float2 *src, float2 *psi);

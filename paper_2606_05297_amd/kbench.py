@@ -33,6 +33,9 @@ def main():
     ap.add_argument("--lib", default=None, help="path of an alternative libfock.so build")
     ap.add_argument("--schedule", type=int, default=None, help="stencil tile schedule (fock_set_stencil_schedule)")
     ap.add_argument("--stencil", type=int, default=None, help="H psi work split (fock_set_stencil_variant)")
+    ap.add_argument("--store-L", type=int, default=None,
+                    help="adapt_store leg: chain length of the Kitaev-Kerr run (default: the workload's L)")
+    ap.add_argument("--store-steps", type=int, default=4, help="adapt_store leg: ADAPT steps per run")
     ap.add_argument("--hot", action="store_true",
                     help="apply H psi to one state and one output buffer every time (input stays cache-resident, "
                          "as inside an ADAPT step) instead of rotating over three")
@@ -143,6 +146,38 @@ def main():
         torch.cuda.synchronize()
         net.close()
         print(f"[kbench] mlp done", file=sys.stderr, flush=True)
+    if "adapt_store" in want:
+        # ADAPT steps with the forward-state store off and on, alternating twice
+        # (Kitaev-Kerr chain of the workload's parameters, nearest-neighbour pool)
+        Ls = args.store_L or L
+        cs = dict(cfg, L=Ls, pool=W.pool(Ls, "nn", False, W.KITAEV_TYPES))
+        hs = lib.ham_from(cs)
+        p0 = torch.zeros(d**Ls, dtype=torch.complex64, device="cuda")
+        p0[0] = 1.0
+        res["adapt_store"] = []
+        lib.prof_enable(False)
+        for mode in (lib.STORE_OFF, lib.STORE_ON, lib.STORE_OFF, lib.STORE_ON):
+            lib.set_state_store(mode)
+            ad = lib.Adapt(hs, cs["pool"], p0, max_iters=60, recycle_hessian=True)
+            lib.prof_reset()
+            lib.prof_enable(True)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            rs = [ad.step() for _ in range(args.store_steps)]
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            lib.prof_enable(False)
+            us = {}
+            for nm, kid in (("gate2", 2), ("gate2_adjoint", 3), ("apply_h", 0)):
+                q = lib.prof_query(kid)
+                us[nm] = 1e3 * q["ms"] / q["launches"] if q["launches"] else None
+            res["adapt_store"].append({"L": Ls, "store": mode, "states_kept": ad.state_store(),
+                                       "steps_per_s": args.store_steps / dt, "E": rs[-1]["E"],
+                                       "bfgs_evals": int(sum(r["bfgs_evals"] for r in rs)), "avg_us": us})
+            ad.close()
+        lib.set_state_store(lib.STORE_AUTO)
+        lib.prof_reset()
+        print(f"[kbench] adapt_store done", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     lib.prof_enable(False)
     for kid, name in NAMES.items():

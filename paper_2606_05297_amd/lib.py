@@ -109,6 +109,8 @@ def load(path: str = LIB_PATH):
                                C.POINTER(vp)]
     L.adapt_step.argtypes = [vp, C.POINTER(AdaptReport)]
     L.adapt_step_select.argtypes = [vp, C.POINTER(AdaptReport)]
+    L.adapt_state_store.argtypes = [vp, ip]
+    L.fock_set_state_store.argtypes = [C.c_int]
     L.adapt_step_finish.argtypes = [vp, C.POINTER(AdaptReport)]
     L.adapt_warm_report.argtypes = [vp, C.POINTER(AdaptReport)]
     L.adapt_get_ansatz.argtypes = [vp, C.POINTER(Op), dp, C.c_int, ip]
@@ -263,6 +265,19 @@ def apply_H_noalloc(h: Ham, psi, hpsi, res=None, stream=None):
             raise FockError(-1, "res must be a contiguous CUDA float64 tensor of at least 2 entries")
     _check(L.fock_apply_H_noalloc(C.byref(h), _ptr(psi), _ptr(hpsi), _ptr(res) if res is not None else None,
                                   _stream(stream)))
+
+
+STORE_OFF, STORE_ON, STORE_AUTO = 0, 1, 2
+
+
+def set_state_store(mode: int):
+    """Forward-state store of drivers created afterwards (fock_set_state_store):
+    STORE_OFF, STORE_ON or STORE_AUTO (the default)."""
+    _check(load().fock_set_state_store(int(mode)))
+
+
+def get_state_store() -> int:
+    return int(load().fock_get_state_store())
 
 
 def stream_probe(kind, a, b, grid=4096, iters=10, stream=None):
@@ -445,6 +460,12 @@ class Adapt:
         r = AdaptReport()
         _check(self._L.adapt_step_finish(self._st, C.byref(r)))
         return r.as_dict()
+
+    def state_store(self) -> int:
+        """Forward states this run keeps for its gradient evaluations (0: none)."""
+        n = C.c_int(0)
+        _check(self._L.adapt_state_store(self._st, C.byref(n)))
+        return n.value
 
     def ansatz(self):
         n = C.c_int(0)

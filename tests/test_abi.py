@@ -323,3 +323,17 @@ def test_stream_probe_rejects_before_device_work():
     assert L.fock_stream_probe(0, C.c_void_p((1 << 20) + 8), b, 1 << 20, 64, 1, C.byref(ms), None) == -1
     assert L.fock_stream_probe(1, a, b, 64, 64, 1, C.byref(ms), None) == -1 and "too small" in lib.last_error()
     assert L.fock_stream_probe(0, a, b, 1 << 20, 64, 1, None, None) == -1
+
+
+def test_state_store_switch():
+    """The forward-state store defaults to AUTO and takes only OFF, ON, AUTO."""
+    L = lib.load()
+    assert lib.get_state_store() == lib.STORE_AUTO
+    assert L.fock_set_state_store(3) == -1 and "AUTO" in lib.last_error()
+    for m in (lib.STORE_OFF, lib.STORE_ON):
+        lib.set_state_store(m)
+        try:
+            assert lib.get_state_store() == m
+        finally:
+            lib.set_state_store(lib.STORE_AUTO)
+    assert lib.get_state_store() == lib.STORE_AUTO

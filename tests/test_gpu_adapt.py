@@ -202,6 +202,39 @@ def test_adapt_select_finish_matches_step_and_takes_late_proposals():
     b.close()
 
 
+def test_state_store_matches_in_place_sweep():
+    """ADAPT with the forward states kept (STORE_ON) and with the in-place
+    reverse sweep (STORE_OFF; AUTO keeps none at this size): the first run
+    holds one state per gate slot, the others none; all select the same
+    operators with the same energies (1e-6 relative), and the stored run's
+    energies replay on the oracle."""
+    L, d = 4, 6
+    c = dict(L=L, d=d, periodic=False, J=1.0, U=0.0, mu=0.0, Delta=0.5, K=0.2)
+    ho, hl = oham(c), lib.ham_from(c)
+    pool = W.pool(L, "nn", False, W.KITAEV_TYPES) + W.site_ops(L, ("KERR",))
+    psi0 = O.fock_state(L, d, [0] * L)
+    say("state store on/off")
+    try:
+        lib.set_state_store(lib.STORE_ON)
+        a = lib.Adapt(hl, pool, dev(psi0), max_iters=6)
+        lib.set_state_store(lib.STORE_OFF)
+        b = lib.Adapt(hl, pool, dev(psi0), max_iters=6)
+    finally:
+        lib.set_state_store(lib.STORE_AUTO)
+    c_auto = lib.Adapt(hl, pool, dev(psi0), max_iters=6)
+    assert a.state_store() == 7 and b.state_store() == 0 and c_auto.state_store() == 0
+    c_auto.close()
+    for _ in range(5):
+        ra, rb = a.step(), b.step()
+        assert ra["k_sel"] == rb["k_sel"]
+        assert abs(ra["E"] - rb["E"]) <= 1e-6 * max(1.0, abs(rb["E"]))
+        ops, th = a.ansatz()
+        Eo = O.energy_of(ho, psi0, ops, th)
+        assert abs(ra["E"] - Eo) <= 1e-5 * max(1.0, abs(Eo))
+    a.close()
+    b.close()
+
+
 def test_adapt_kitaev_kerr_l8_d8_first_steps_replay():
     c = W.config("kk_l8_d8")
     ho, hl = oham(c), lib.ham_from(c)
