@@ -297,6 +297,15 @@ static void plan_gate_groups(const Ctx &c, const fock_op_t *ops, int n, std::vec
     gr.k0 = k;
     gr.k1 = k + 1;
     gr.s = 0;
+    // consecutive single-mode phase gates commute: one diagonal pass
+    const int k1 = diag_run_end(ops, n, k);
+    if (k1 > k) {
+      gr.k1 = k1;
+      gr.diag = true;
+      out->push_back(gr);
+      k = k1;
+      continue;
+    }
     if (on) {
       unsigned mask = 1u;  // modes in the union (mode 0 always)
       auto modes = [&](const fock_op_t &o) { return is_single_mode(o.type) ? (1u << o.i) : ((1u << o.i) | (1u << o.j)); };
@@ -391,7 +400,7 @@ static int stage_circuit(Ctx &c, const fock_op_t *ops, const double *theta, int 
 static bool use_store(const Ctx &c, const fock_op_t *ops, int n, const std::vector<GateGroup> &groups) {
   if (!c.store || n < 1 || n > c.nstore) return false;
   for (const GateGroup &gr : groups)
-    if (gr.s > 0) return false;
+    if (gr.s > 0 || gr.diag) return false;
   for (int k = 0; k < n; ++k)
     if (is_squeeze(ops[k].type)) return false;
   return true;
@@ -433,6 +442,13 @@ static int reverse_sweep(Ctx &c, const fock_op_t *ops, int n, const std::vector<
   const int stride = gate_stride(c.g.d);
   for (int gi = (int)groups.size() - 1; gi >= 0; --gi) {
     const GateGroup &gr = groups[gi];
+    if (gr.diag) {
+      ProfScope ps(FOCK_K_DIAG, c.s, 32.0 * c.g.n_amp);
+      rc = launch_diag_run_adj(c.g, diag_run_params(c.g, ops, gr.k0, gr.k1), utab + (size_t)gr.k0 * stride, phi, lam,
+                               part + (size_t)gr.k0 * c.L.rs, c.L.rs, c.s);
+      if (rc) return rc;
+      continue;
+    }
     if (gr.s > 0 && fuse_rev) {
       ProfScope ps(FOCK_K_ADJ, c.s, 32.0 * c.g.n_amp);
       rc = launch_fuse_adj(c.g.d, make_fuse_args(c, gr, ops), phi, lam, utab, part, c.L.rs, c.s);
@@ -474,7 +490,11 @@ static int forward_circuit(Ctx &c, const fock_op_t *ops, int n, const std::vecto
   for (const GateGroup &gr : groups) {
     const float2 *src = gr.k0 == 0 ? (const float2 *)psi0 : phi;
     int rc;
-    if (gr.s == 0) {
+    if (gr.diag) {
+      ProfScope ps(FOCK_K_DIAG, c.s, 16.0 * c.g.n_amp);
+      rc = launch_diag_run(c.g, diag_run_params(c.g, ops, gr.k0, gr.k1), false,
+                           utab + (size_t)gr.k0 * gate_stride(c.g.d), src, phi, c.s);
+    } else if (gr.s == 0) {
       rc = forward_gate(c, ops[gr.k0], gr.k0, false, src, phi);
     } else {
       ProfScope ps(FOCK_K_GATE, c.s, 16.0 * c.g.n_amp);

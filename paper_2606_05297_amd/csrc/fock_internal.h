@@ -187,6 +187,26 @@ int launch_diag(const Geometry &g, int r, int type, bool dag, const float2 *ph, 
 int launch_diag_adj(const Geometry &g, int r, int type, const float2 *ph, float2 *phi, float2 *lam,
                     double *partial, hipStream_t s, bool write_phi = true);
 int diag_blocks_count(const Geometry &g);
+// A run of consecutive single-mode phase gates ops[k0..k1) (KERR / ROT, at
+// most kMaxDiagRun) applied as one diagonal pass; U = table of gate k0 (the
+// run's tables follow at the gate stride).  The reverse step writes gate g's
+// workgroup sums to partial[g * rs + block] (diag_blocks_count(g) blocks).
+constexpr int kMaxDiagRun = 32;
+struct DiagRun {
+  int nrows, ng, stride;  // rows of d amplitudes; gates; float2 between gate tables
+  int8_t r[kMaxDiagRun];
+  int8_t kerr[kMaxDiagRun];
+  FastDiv dsr[kMaxDiagRun];  // divide a row index by d^(r-1) (r >= 1)
+};
+DiagRun diag_run_params(const Geometry &g, const fock_op_t *ops, int k0, int k1);
+// End (exclusive) of the run of single-mode phase gates (KERR, ROT) that starts
+// at ops[k] when at least two start there (at most kMaxDiagRun), else k.  The
+// single-point drivers and the batched sweep group gates with this one rule.
+int diag_run_end(const fock_op_t *ops, int n, int k);
+int launch_diag_run(const Geometry &g, const DiagRun &a, bool dag, const float2 *U, const float2 *src, float2 *psi,
+                    hipStream_t s);
+int launch_diag_run_adj(const Geometry &g, const DiagRun &a, const float2 *U, float2 *phi, float2 *lam,
+                        double *partial, int rs, hipStream_t s, bool write_phi = true);
 // Squeezer gates (gate1_kernels.hip): U, A are d x d row-major; the reverse
 // step and the pool scoring write one partial per workgroup
 // (diag_blocks_count(g) of them).

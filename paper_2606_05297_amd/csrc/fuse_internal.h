@@ -28,9 +28,13 @@ struct FuseArgs {
 
 // A run of consecutive gates [k0, k1); s = 0 marks a single gate run by the
 // per-gate kernels, otherwise the tile modes m[0..s).
+// Gates k0..k1 of a circuit run together: an LDS tile over the modes m[0..s)
+// (gate fusion, s > 0), a run of single-mode phase gates applied as one
+// diagonal pass (diag), or one gate on its own kernel.
 struct GateGroup {
   int k0, k1, s;
   int m[kMaxFuseModes];
+  bool diag = false;
 };
 
 // Greedy grouping of a circuit (see plan_gate_groups in api.cpp).

@@ -523,6 +523,142 @@ __global__ __launch_bounds__(kBlock) void k_diag_adj(float2 *__restrict__ phi, f
   if (threadIdx.x == 0) partial[vb] = sg;
 }
 
+// ---------------------------------------------------------------- runs of single-mode phase gates
+// Consecutive gates exp(theta_g i f_g(N_{r_g})) (f = n^2 or n) commute and
+// multiply into one diagonal unitary: amplitude n picks up the product of the
+// gates' phase-table entries at n_{r_g}.  One pass applies a whole run.  In the
+// reverse sweep every gate of the run sees the same Im(conj(lam) phi) per
+// amplitude (a diagonal phase leaves conj(lam) phi unchanged), so one pass also
+// yields all of the run's gradient partials: per row, M_k = sum_q q^k m_q with
+// m_q = Im(conj(lam) phi) at n_0 = q; a gate on mode 0 takes -M_2 (Kerr) or -M_1
+// (rotation), a gate on mode r >= 1 takes -f(n_r) M_0.
+// Stage the run's phase tables (conjugated when DAG) in LDS: tb[g * D + n] for
+// the gates on modes r >= 1 and t0[q] = product over the mode-0 gates.
+template <int D, bool DAG>
+__device__ __forceinline__ void diag_run_tables(const float2 *__restrict__ U, const DiagRun &a, float2 *tb,
+                                                float2 *t0) {
+  for (int e = threadIdx.x; e < a.ng * D; e += kBlock) {
+    const float2 v = U[(size_t)(e / D) * a.stride + e % D];
+    tb[e] = DAG ? make_float2(v.x, -v.y) : v;
+  }
+  __syncthreads();
+  if (threadIdx.x < D) {
+    float2 p = make_float2(1.f, 0.f);
+    for (int g = 0; g < a.ng; ++g)
+      if (a.r[g] == 0) {
+        const float2 t = tb[g * D + threadIdx.x];
+        p = make_float2(p.x * t.x - p.y * t.y, p.x * t.y + p.y * t.x);
+      }
+    t0[threadIdx.x] = p;
+  }
+  __syncthreads();
+}
+
+// Product of the row's phases from the gates on modes r >= 1.
+template <int D>
+__device__ __forceinline__ float2 diag_run_row_phase(int row, const DiagRun &a, const float2 *tb) {
+  float2 p = make_float2(1.f, 0.f);
+  for (int g = 0; g < a.ng; ++g)
+    if (a.r[g] > 0) {
+      const int n = (int)(fdiv((uint32_t)row, a.dsr[g]) % D);
+      const float2 t = tb[g * D + n];
+      p = make_float2(p.x * t.x - p.y * t.y, p.x * t.y + p.y * t.x);
+    }
+  return p;
+}
+
+// tb: kMaxDiagRun * kMaxD, t0: kMaxD float2 of LDS.  Contains barriers.
+template <int D, bool DAG>
+__device__ __forceinline__ void diag_run_block(int vb, const float2 *src, float2 *psi, const float2 *__restrict__ U,
+                                               const DiagRun &a, float2 *tb, float2 *t0) {
+  diag_run_tables<D, DAG>(U, a, tb, t0);
+  const int row = vb * kBlock + threadIdx.x;
+  if (row < a.nrows) {
+    float2 v[D];
+    load_row<D>(src + (size_t)row * D, v);
+    const float2 pr = diag_run_row_phase<D>(row, a, tb);
+#pragma unroll
+    for (int q = 0; q < D; ++q) {
+      const float2 t = t0[q];
+      const float2 ph = make_float2(pr.x * t.x - pr.y * t.y, pr.x * t.y + pr.y * t.x);
+      float2 o = make_float2(0.f, 0.f);
+      cmac(o, ph, v[q]);
+      v[q] = o;
+    }
+    store_row<D>(psi + (size_t)row * D, v);
+  }
+  __syncthreads();
+}
+
+// Reverse step of a run: red[w][g] (LDS, 4 x kMaxDiagRun doubles) receives the
+// wavefront sums of each gate's Re<lam|A_g phi>; phi (when WPHI) and lam are
+// multiplied by the conjugate phase.  Contains barriers.
+template <int D, bool WPHI>
+__device__ __forceinline__ void diag_run_adj_block(int vb, float2 *phi, float2 *lam, const float2 *__restrict__ U,
+                                                   const DiagRun &a, float2 *tb, float2 *t0,
+                                                   double (*red)[kMaxDiagRun]) {
+  diag_run_tables<D, true>(U, a, tb, t0);
+  const int row = vb * kBlock + threadIdx.x;
+  float m0 = 0.f, m1 = 0.f, m2 = 0.f;
+  if (row < a.nrows) {
+    float2 pv[D], lv[D];
+    load_row<D>(phi + (size_t)row * D, pv);
+    load_row<D>(lam + (size_t)row * D, lv);
+    const float2 pr = diag_run_row_phase<D>(row, a, tb);
+#pragma unroll
+    for (int q = 0; q < D; ++q) {
+      const float m = lv[q].x * pv[q].y - lv[q].y * pv[q].x;
+      m0 += m;
+      m1 += (float)q * m;
+      m2 += (float)(q * q) * m;
+      const float2 t = t0[q];
+      const float2 ph = make_float2(pr.x * t.x - pr.y * t.y, pr.x * t.y + pr.y * t.x);
+      float2 np = make_float2(0.f, 0.f), nl = make_float2(0.f, 0.f);
+      if (WPHI) cmac(np, ph, pv[q]);
+      cmac(nl, ph, lv[q]);
+      pv[q] = np;
+      lv[q] = nl;
+    }
+    if (WPHI) store_row<D>(phi + (size_t)row * D, pv);
+    store_row<D>(lam + (size_t)row * D, lv);
+  }
+  const bool in = row < a.nrows;
+  for (int g = 0; g < a.ng; ++g) {
+    float v;
+    if (a.r[g] == 0) {
+      v = a.kerr[g] ? -m2 : -m1;
+    } else {
+      const int n = in ? (int)(fdiv((uint32_t)row, a.dsr[g]) % D) : 0;
+      v = -(a.kerr[g] ? (float)(n * n) : (float)n) * m0;
+    }
+    const double sv = wave_sum_d(in ? (double)v : 0.0);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6][g] = sv;
+  }
+  __syncthreads();
+}
+
+template <int D, bool DAG>
+__global__ __launch_bounds__(kBlock) void k_diag_run(const float2 *src, float2 *psi, const float2 *__restrict__ U,
+                                                     DiagRun a) {
+  __shared__ float2 tb[kMaxDiagRun * kMaxD], t0[kMaxD];
+  diag_run_block<D, DAG>(xcd_remap(blockIdx.x, gridDim.x), src, psi, U, a, tb, t0);
+}
+
+// partial[g * rs + vb]: gate g's sum over workgroup vb.
+template <int D, bool WPHI>
+__global__ __launch_bounds__(kBlock) void k_diag_run_adj(float2 *__restrict__ phi, float2 *__restrict__ lam,
+                                                         const float2 *__restrict__ U, double *__restrict__ partial,
+                                                         int rs, DiagRun a) {
+  __shared__ float2 tb[kMaxDiagRun * kMaxD], t0[kMaxD];
+  __shared__ double red[kBlock / 64][kMaxDiagRun];
+  const int vb = xcd_remap(blockIdx.x, gridDim.x);
+  diag_run_adj_block<D, WPHI>(vb, phi, lam, U, a, tb, t0, red);
+  if ((int)threadIdx.x < a.ng) {
+    const int g = threadIdx.x;
+    partial[(size_t)g * rs + vb] = (red[0][g] + red[1][g]) + (red[2][g] + red[3][g]);
+  }
+}
+
 template <int D>
 constexpr int lds_fibers_d() { return lds_fibers<D>(); }
 

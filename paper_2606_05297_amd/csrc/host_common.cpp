@@ -47,6 +47,14 @@ using cd = std::complex<double>;
 bool is_single_mode(int type) { return type == FOCK_KERR || type == FOCK_ROT || type == FOCK_SR || type == FOCK_SI; }
 bool is_squeeze(int type) { return type == FOCK_SR || type == FOCK_SI; }
 bool is_pool_diagonal(int type) { return type == FOCK_KERR || type == FOCK_ROT || type == FOCK_CK; }
+
+int diag_run_end(const fock_op_t *ops, int n, int k) {
+  auto phase = [](const fock_op_t &o) { return o.type == FOCK_KERR || o.type == FOCK_ROT; };
+  if (k + 1 >= n || !phase(ops[k]) || !phase(ops[k + 1])) return k;
+  int k1 = k + 1;
+  while (k1 < n && k1 - k < kMaxDiagRun && phase(ops[k1])) ++k1;
+  return k1;
+}
 int gate_kind(int type) { return (type == FOCK_PR || type == FOCK_PI) ? KIND_DIFF : KIND_SUM; }
 
 // Truncated annihilation operator, a|m> = sqrt(m)|m-1> (Sec. II.A).

@@ -12,6 +12,8 @@
 // lam = lambda_k, accumulate Re <lam| A phi> over the fiber, then apply
 // O_k^+ = exp(-theta A) to both phi and lam.  A is block diagonal with the
 // same blocks, so the gradient term is fiber-local and fused with the update.
+#include <cstring>
+
 #include "gate_kernels.h"
 
 namespace fock {
@@ -202,6 +204,52 @@ int launch_diag_adj(const Geometry &g, int r, int type, const float2 *ph, float2
   } else {
     FOCK_D_SWITCH(g.d, hipLaunchKernelGGL((k_diag_adj<D, false>), dim3(G), dim3(kBlock), 0, s, phi, lam, ph, partial,
                                           a));
+  }
+  FOCK_HIP(hipGetLastError());
+  return FOCK_OK;
+}
+
+DiagRun diag_run_params(const Geometry &g, const fock_op_t *ops, int k0, int k1) {
+  DiagRun a;
+  memset(&a, 0, sizeof(a));
+  a.nrows = (int)(g.n_amp / (uint32_t)g.d);
+  a.ng = k1 - k0;
+  a.stride = gate_stride(g.d);
+  for (int q = 0; q < a.ng; ++q) {
+    const fock_op_t &op = ops[k0 + q];
+    a.r[q] = (int8_t)op.i;
+    a.kerr[q] = (int8_t)(op.type == FOCK_KERR);
+    uint32_t sr = 1;
+    for (int k = 1; k < op.i; ++k) sr *= (uint32_t)g.d;
+    a.dsr[q] = make_fastdiv(sr);
+  }
+  return a;
+}
+
+int launch_diag_run(const Geometry &g, const DiagRun &a, bool dag, const float2 *U, const float2 *src, float2 *psi,
+                    hipStream_t s) {
+  if (a.ng < 1 || a.ng > kMaxDiagRun) return set_error(FOCK_ERR_ARG, "diagonal run of %d gates", a.ng);
+  const int G = diag_blocks_count(g);
+  if (dag) {
+    FOCK_D_SWITCH(g.d, hipLaunchKernelGGL((k_diag_run<D, true>), dim3(G), dim3(kBlock), 0, s, src, psi, U, a));
+  } else {
+    FOCK_D_SWITCH(g.d, hipLaunchKernelGGL((k_diag_run<D, false>), dim3(G), dim3(kBlock), 0, s, src, psi, U, a));
+  }
+  FOCK_HIP(hipGetLastError());
+  return FOCK_OK;
+}
+
+int launch_diag_run_adj(const Geometry &g, const DiagRun &a, const float2 *U, float2 *phi, float2 *lam,
+                        double *partial, int rs, hipStream_t s, bool write_phi) {
+  if (a.ng < 1 || a.ng > kMaxDiagRun) return set_error(FOCK_ERR_ARG, "diagonal run of %d gates", a.ng);
+  const int G = diag_blocks_count(g);
+  if (G > rs) return set_error(FOCK_ERR_SIZE, "diagonal run: %d partials per gate exceed the row stride %d", G, rs);
+  if (write_phi) {
+    FOCK_D_SWITCH(g.d, hipLaunchKernelGGL((k_diag_run_adj<D, true>), dim3(G), dim3(kBlock), 0, s, phi, lam, U,
+                                          partial, rs, a));
+  } else {
+    FOCK_D_SWITCH(g.d, hipLaunchKernelGGL((k_diag_run_adj<D, false>), dim3(G), dim3(kBlock), 0, s, phi, lam, U,
+                                          partial, rs, a));
   }
   FOCK_HIP(hipGetLastError());
   return FOCK_OK;

@@ -83,6 +83,9 @@ struct fock_sweep {
   // item lists (device) for the current ansatz lengths
   void *items_d = nullptr;
   size_t items_cap = 0;
+  // descriptors of the points' runs of phase gates (device), referenced by items
+  DiagRun *runs_d = nullptr;
+  size_t runs_cap = 0;
   struct Launch {
     int kind, d, n;  // kind: 0 gate, 1 H, 2 adj, 3 reduce
     size_t off;
@@ -108,29 +111,70 @@ struct Lists {
   std::vector<SweepRItem> red;
 };
 
-void build_lists(fock_sweep *sw, const std::vector<char> &sel, bool grad, Lists *Ls) {
+// A point's gate groups: [k0, k1) runs of phase gates (diag_run_end) or single gates.
+void point_groups(const std::vector<fock_op_t> &ops, std::vector<std::pair<int, int>> *gr) {
+  gr->clear();
+  const int n = (int)ops.size();
+  for (int k = 0; k < n;) {
+    const int e = diag_run_end(ops.data(), n, k);
+    const int k1 = e > k ? e : k + 1;
+    gr->push_back({k, k1});
+    k = k1;
+  }
+}
+
+// Gate layers are the points' gate groups: layer l holds group l of every
+// point, so a run of phase gates takes one layer and one pass.
+int build_lists(fock_sweep *sw, const std::vector<char> &sel, bool grad, Lists *Ls) {
+  const size_t npt = sw->pts.size();
+  std::vector<std::vector<std::pair<int, int>>> groups(npt);
+  std::vector<DiagRun> runs;
+  std::vector<size_t> run_base(npt, 0);
   int maxn = 0;
-  for (size_t p = 0; p < sw->pts.size(); ++p)
-    if (sel[p]) maxn = std::max(maxn, (int)sw->pts[p].ops.size());
+  for (size_t p = 0; p < npt; ++p) {
+    const SPoint &P = sw->pts[p];
+    point_groups(P.ops, &groups[p]);
+    run_base[p] = runs.size();
+    for (auto &g : groups[p])
+      if (g.second - g.first > 1) runs.push_back(diag_run_params(P.g, P.ops.data(), g.first, g.second));
+    if (sel[p]) maxn = std::max(maxn, (int)groups[p].size());
+  }
+  if (runs.size() > sw->runs_cap) {
+    if (sw->runs_d) FOCK_HIP(hipFree(sw->runs_d));
+    sw->runs_d = nullptr;
+    sw->runs_cap = 0;
+    FOCK_HIP(hipMalloc(&sw->runs_d, sizeof(DiagRun) * runs.size() * 2));
+    sw->runs_cap = runs.size() * 2;
+  }
+  if (!runs.empty())
+    FOCK_HIP(hipMemcpy(sw->runs_d, runs.data(), sizeof(DiagRun) * runs.size(), hipMemcpyHostToDevice));
   const int NG = (int)sw->groups.size();
   Ls->fwd.assign(maxn, std::vector<std::vector<SweepItem>>(2 * NG));
   Ls->rev.assign(maxn, std::vector<std::vector<SweepItem>>(2 * NG));
   Ls->h.assign(NG, {});
   Ls->red.clear();
-  for (size_t pi = 0; pi < sw->pts.size(); ++pi) {
+  for (size_t pi = 0; pi < npt; ++pi) {
     if (!sel[pi]) continue;
     SPoint &P = sw->pts[pi];
     const DGroup &G = sw->groups[P.group];
     const int stride = gate_stride(P.g.d);
     const int n = (int)P.ops.size();
-    for (int k = 0; k < n; ++k) {
+    size_t ri = run_base[pi];
+    for (size_t l = 0; l < groups[pi].size(); ++l) {
+      const int k = groups[pi][l].first, k1 = groups[pi][l].second;
       const fock_op_t &op = P.ops[k];
       SweepItem it;
       memset(&it, 0, sizeof(it));
       it.p = (int)pi;
       it.U = G.utab + (size_t)(P.gate_base + k) * stride;
       int nb;
-      if (is_single_mode(op.type)) {
+      if (k1 - k > 1) {
+        it.variant = 3;
+        it.kind = 0;
+        it.rs = P.rs;
+        it.run = sw->runs_d + ri++;
+        nb = diag_blocks_count(P.g);
+      } else if (is_single_mode(op.type)) {
         it.variant = 2;
         it.kind = 0;
         it.dl = diag_launch_params(P.g, op.i, op.type);
@@ -148,25 +192,29 @@ void build_lists(fock_sweep *sw, const std::vector<char> &sel, bool grad, Lists 
         f.vb = vb;
         f.src = k == 0 ? P.psi0 : P.phi;
         f.dst = P.phi;
-        Ls->fwd[k][li].push_back(f);
+        Ls->fwd[l][li].push_back(f);
         if (grad) {
           SweepItem r = it;
           r.vb = vb;
           r.dst = P.phi;
           r.lam = P.lam;
           r.partial = P.partial + (size_t)k * P.rs;
-          Ls->rev[k][li].push_back(r);
+          Ls->rev[l][li].push_back(r);
         }
       }
-      if (grad) {
-        SweepRItem ri{(int)pi, 1, nb, 0, k, P.rs, P.partial, P.res + 2 + k};
-        Ls->red.push_back(ri);
-      }
     }
+    if (grad)
+      for (int k = 0; k < n; ++k) {
+        const fock_op_t &op = P.ops[k];
+        const int nb = is_single_mode(op.type) ? diag_blocks_count(P.g)
+                                               : sweep_gate_blocks(P.g.d, (int)P.g.n_amp, op.i);
+        Ls->red.push_back(SweepRItem{(int)pi, 1, nb, 0, k, P.rs, P.partial, P.res + 2 + k});
+      }
     const float2 *st = n > 0 ? P.phi : P.psi0;
     for (int vb = 0; vb < P.GH; ++vb) Ls->h[P.group].push_back(SweepHItem{(int)pi, vb, st, P.lam, P.partial});
   }
   // energy / norm reductions run before the reverse sweep reuses the partials
+  return FOCK_OK;
 }
 
 template <class T>
@@ -323,7 +371,10 @@ int destroy_graph(fock_sweep *sw) {
 // and H psi, direct launches); results in P.f, P.n2 (P.rc on failure).
 int eval_forward(fock_sweep *sw, const std::vector<char> &sel) {
   Lists Lf;
-  build_lists(sw, sel, false, &Lf);
+  {
+    const int brc = build_lists(sw, sel, false, &Lf);
+    if (brc) return brc;
+  }
   std::vector<size_t> offf;
   int rc = upload_recs(sw);
   if (rc) return rc;
@@ -349,7 +400,10 @@ int eval_forward(fock_sweep *sw, const std::vector<char> &sel) {
 int bfgs_phase(fock_sweep *sw, const std::vector<char> &sel, const std::vector<double> &gtol,
                std::vector<fock_adapt_report_t> *reps) {
   Lists Ls;
-  build_lists(sw, sel, true, &Ls);
+  {
+    const int brc = build_lists(sw, sel, true, &Ls);
+    if (brc) return brc;
+  }
   std::vector<size_t> offs;
   int rc = stage_lists(sw, Ls, true, &offs);
   if (rc) return rc;
@@ -461,7 +515,10 @@ int bfgs_phase(fock_sweep *sw, const std::vector<char> &sel, const std::vector<d
 // Forward + H psi + pool scoring for the selected points (direct launches).
 int score_phase(fock_sweep *sw, const std::vector<char> &sel, std::vector<std::vector<double>> *grads) {
   Lists Ls;
-  build_lists(sw, sel, false, &Ls);
+  {
+    const int brc = build_lists(sw, sel, false, &Ls);
+    if (brc) return brc;
+  }
   std::vector<size_t> offs;
   // pool items reuse the H tiles of every point
   std::vector<char> blob;
@@ -940,7 +997,10 @@ int fock_sweep_autotune(fock_sweep_t *sw, const char *cache_path, int *best_grid
   std::vector<char> sel(sw->pts.size(), 0);
   for (size_t p = 0; p < sw->pts.size(); ++p) sel[p] = !sw->pts[p].done;
   Lists Ls;
-  build_lists(sw, sel, false, &Ls);
+  {
+    const int brc = build_lists(sw, sel, false, &Ls);
+    if (brc) return brc;
+  }
   std::vector<size_t> offs;
   int rc = upload_recs(sw);
   if (rc) return rc;
@@ -997,6 +1057,7 @@ int fock_sweep_destroy(fock_sweep_t *sw) {
   (void)hipStreamSynchronize(sw->s);
   destroy_graph(sw);
   if (sw->items_d) (void)hipFree(sw->items_d);
+  if (sw->runs_d) (void)hipFree(sw->runs_d);
   if (sw->dbuf) (void)hipFree(sw->dbuf);
   if (sw->pin) (void)hipHostFree(sw->pin);
   if (sw->s) (void)hipStreamDestroy(sw->s);

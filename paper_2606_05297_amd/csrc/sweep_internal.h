@@ -33,19 +33,23 @@ struct CPtr {
 
 // One workgroup's share of one gate (forward) or of its reverse step.
 // variant: 0 = two-mode gate with i >= 1, 1 = two-mode gate on (0, j) (LDS),
-// 2 = single-mode diagonal gate.  Forward: dst <- O src.  Reverse: dst = phi,
-// lam = lambda, partial[vb] <- Re<lam|A phi> of the workgroup.
+// 2 = single-mode diagonal gate, 3 = a run of single-mode phase gates (run,
+// tables from U on at the gate stride).  Forward: dst <- O src.  Reverse:
+// dst = phi, lam = lambda, partial[vb] <- Re<lam|A phi> of the workgroup (a
+// run writes gate g's sum to partial[g * rs + vb]).
 struct SweepItem {
-  int p, vb, variant, kind;
+  int p, vb, variant, kind, rs;
   GateLaunch gl;
   DiagLaunch dl;
   CPtr<const float2> U;
   CPtr<const float2> A;
+  CPtr<const DiagRun> run;
   GPtr<const float2> src;
   GPtr<float2> dst;
   GPtr<float2> lam;
   GPtr<double> partial;
 };
+static_assert(sizeof(DiagRun) % 4 == 0, "run descriptors are copied word by word");
 
 // One tile of H psi or of pool scoring for point p.
 struct SweepHItem {

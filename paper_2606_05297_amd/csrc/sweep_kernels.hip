@@ -9,6 +9,29 @@
 
 namespace fock {
 
+// An item's run descriptor copied to LDS by the whole workgroup (items are
+// uniform per workgroup).  The first barrier keeps the previous item's readers
+// of the descriptor ahead of the copy.
+__device__ __forceinline__ void load_run(const SweepItem &g, DiagRun *dst) {
+  __syncthreads();
+  const __attribute__((address_space(4))) int *src = (const __attribute__((address_space(4))) int *)g.run.p;
+  int *d = (int *)dst;
+  for (int e = threadIdx.x; e < (int)(sizeof(DiagRun) / 4); e += kBlock) d[e] = src[e];
+  __syncthreads();
+}
+
+// Reverse step of a run item: all of its gates' workgroup sums.
+template <int D>
+__device__ __forceinline__ void sweep_run_adj(const SweepItem &g, DiagRun *srun, float2 *tb, float2 *t0,
+                                              double (*dred)[kMaxDiagRun]) {
+  load_run(g, srun);
+  diag_run_adj_block<D, true>(g.vb, g.dst, g.lam, g.U, *srun, tb, t0, dred);
+  if ((int)threadIdx.x < srun->ng) {
+    const int q = threadIdx.x;
+    g.partial[(size_t)q * g.rs + g.vb] = (dred[0][q] + dred[1][q]) + (dred[2][q] + dred[3][q]);
+  }
+}
+
 // Gate and reverse-step items of one gate layer: at d = 8 they come in two
 // classes launched separately, so that each kernel declares only the LDS its
 // items use (64 kB of mode-0 tiles would otherwise cap the occupancy of the
@@ -22,6 +45,8 @@ __global__ __launch_bounds__(kBlock) void k_sweep_gate_all(const SweepItem *__re
   __shared__ float2 tile[m0_tile_elems<D>()];
   __shared__ uint32_t fbase[lds_fibers<D>()];
   __shared__ float2 phs[kMaxD];
+  __shared__ DiagRun srun;
+  __shared__ float2 tb[kMaxDiagRun * D], t0[D];
   for (int it = blockIdx.x; it < n; it += gridDim.x) {
     const SweepItem g = items[it];
     if (!active[g.p]) continue;
@@ -30,6 +55,10 @@ __global__ __launch_bounds__(kBlock) void k_sweep_gate_all(const SweepItem *__re
       case 1: gate2_direct_block<D, KIND_DIFF, false>(g.vb, g.src, g.dst, g.U, g.gl); break;
       case 2: gate2_m0_block<D, KIND_SUM, false>(g.vb, g.src, g.dst, g.U, g.gl, tile, fbase); break;
       case 3: gate2_m0_block<D, KIND_DIFF, false>(g.vb, g.src, g.dst, g.U, g.gl, tile, fbase); break;
+      case 6:
+        load_run(g, &srun);
+        diag_run_block<D, false>(g.vb, g.src, g.dst, g.U, srun, tb, t0);
+        break;
       default: diag_block<D, false>(g.vb, g.src, g.dst, g.U, g.dl, phs); break;
     }
   }
@@ -42,9 +71,16 @@ __global__ __launch_bounds__(kBlock) void k_sweep_adj_all(const SweepItem *__res
   __shared__ uint32_t fbase[lds_fibers<D>()];
   __shared__ float2 phs[kMaxD];
   __shared__ double red[4];
+  __shared__ DiagRun srun;
+  __shared__ float2 tb[kMaxDiagRun * D], t0[D];
+  __shared__ double dred[kBlock / 64][kMaxDiagRun];
   for (int it = blockIdx.x; it < n; it += gridDim.x) {
     const SweepItem g = items[it];
     if (!active[g.p]) continue;
+    if (g.variant == 3) {
+      sweep_run_adj<D>(g, &srun, tb, t0, dred);
+      continue;
+    }
     float gacc = 0.f;
     switch (g.variant * 2 + g.kind) {
       case 0: gacc = adj_direct_block<D, KIND_SUM>(g.vb, g.dst, g.lam, g.U, g.A, g.gl); break;
@@ -62,12 +98,18 @@ template <int D>
 __global__ __launch_bounds__(kBlock) void k_sweep_gate(const SweepItem *__restrict__ items, int n,
                                                        const int *__restrict__ active) {
   __shared__ float2 phs[kMaxD];
+  __shared__ DiagRun srun;
+  __shared__ float2 tb[kMaxDiagRun * D], t0[D];
   for (int it = blockIdx.x; it < n; it += gridDim.x) {
     const SweepItem g = items[it];
     if (!active[g.p]) continue;
     switch (g.variant * 2 + g.kind) {
       case 0: gate2_direct_block<D, KIND_SUM, false>(g.vb, g.src, g.dst, g.U, g.gl); break;
       case 1: gate2_direct_block<D, KIND_DIFF, false>(g.vb, g.src, g.dst, g.U, g.gl); break;
+      case 6:
+        load_run(g, &srun);
+        diag_run_block<D, false>(g.vb, g.src, g.dst, g.U, srun, tb, t0);
+        break;
       default: diag_block<D, false>(g.vb, g.src, g.dst, g.U, g.dl, phs); break;
     }
   }
@@ -91,9 +133,16 @@ __global__ __launch_bounds__(kBlock) void k_sweep_adj(const SweepItem *__restric
                                                       const int *__restrict__ active) {
   __shared__ float2 phs[kMaxD];
   __shared__ double red[4];
+  __shared__ DiagRun srun;
+  __shared__ float2 tb[kMaxDiagRun * D], t0[D];
+  __shared__ double dred[kBlock / 64][kMaxDiagRun];
   for (int it = blockIdx.x; it < n; it += gridDim.x) {
     const SweepItem g = items[it];
     if (!active[g.p]) continue;
+    if (g.variant == 3) {
+      sweep_run_adj<D>(g, &srun, tb, t0, dred);
+      continue;
+    }
     float gacc = 0.f;
     switch (g.variant * 2 + g.kind) {
       case 0: gacc = adj_direct_block<D, KIND_SUM>(g.vb, g.dst, g.lam, g.U, g.A, g.gl); break;

@@ -309,6 +309,41 @@ def test_energy_and_adjoint_parity(case):
     assert E3 == E and np.array_equal(g3, g)
 
 
+DIAG_RUN_CASES = [(3, 5, False, 12), (4, 4, True, 12), (5, 3, False, 12), (4, 3, False, 40)]
+
+
+@pytest.mark.parametrize("case", DIAG_RUN_CASES, ids=lambda c: f"L{c[0]}d{c[1]}n{c[3]}")
+def test_phase_gate_runs_energy_and_adjoint(case):
+    """Runs of consecutive single-mode phase gates (Kerr and rotation on mode 0
+    and on higher modes) go through one diagonal pass forward and one in the
+    reverse sweep; ragged row counts (d^(L-1) not a multiple of the workgroup)
+    and a 40-gate run (split at 32 gates).  Energy, every gradient and the final
+    state against the oracle, which applies the gates one by one."""
+    L, d, per, n = case
+    ho, hl = ham_pair(L, d, per, 1.0, 0.7, 0.2, 0.3, 0.1)
+    rng = np.random.default_rng(L * 10 + d)
+    if n == 12:
+        ops = [("HR", 0, 1), ("KERR", 0, -1), ("ROT", 2, -1), ("KERR", 1, -1), ("ROT", 0, -1),
+               ("KERR", L - 1, -1), ("HI", 1, 2), ("ROT", 1, -1), ("KERR", 2, -1), ("PR", 0, L - 1),
+               ("ROT", 0, -1), ("ROT", 0, -1)]
+    else:
+        ops = [("HR", 0, 1)] + [(("KERR", "ROT")[int(rng.integers(2))], int(rng.integers(L)), -1)
+                                for _ in range(n - 2)] + [("PI", 1, 2)]
+    th = rng.uniform(-0.6, 0.6, len(ops))
+    say("phase-gate runs", case)
+    psi0 = W.random_state(L, d, seed=4, sector=None)
+    x0 = dev(psi0)
+    a, b = torch.empty_like(x0), torch.empty_like(x0)
+    ws = lib.workspace(hl, 0, len(ops))
+    E, n2, g = lib.energy_grad_adjoint(hl, ops, th, x0, a, b, ws)
+    Eref, gref, n2ref = O.energy_and_grad_adjoint(ho, psi0.astype(np.complex128), ops, th)
+    assert abs(E - Eref / n2ref) <= 1e-5 * max(1.0, abs(Eref))
+    assert np.abs(g - gref).max() <= 1e-4 * max(1.0, np.abs(gref).max()), np.abs(g - gref).max()
+    lib.energy_grad_adjoint(hl, ops, th, x0, a, b, ws, grad=False)
+    psi_n = O.ansatz_state(psi0.astype(np.complex128), ops, th, L, d)
+    assert np.abs(host(a) - psi_n).max() <= 1e-5
+
+
 def test_adjoint_matches_gpu_finite_differences():
     """dE/dtheta from the reverse sweep vs central differences (h = 1e-4 in the
     angle, required step) of the GPU energy, Kitaev-Kerr chain."""
