@@ -418,6 +418,169 @@ __device__ __forceinline__ float adj_m0_block(int vb, float2 *phi, float2 *lam, 
   return gacc;
 }
 
+// ---------------------------------------------------------------- pairs (0, j), d = 8: pipelined tiles
+// A workgroup walks kM0Tiles consecutive 64-fibre tiles.  The next tile's
+// global loads go out (into registers) before the current tile is computed in
+// LDS and stored, so memory latency overlaps the compute and store phases
+// instead of separating them.  Loads are issued before the current tile's
+// stores, so waiting for them never waits for those stores.  Used when every
+// workgroup has whole tiles (d = 8 and a fibre count divisible by 64 kM0Tiles).
+constexpr int kM0Tiles = 4;
+
+template <int D>
+__device__ __forceinline__ void m0_bases(uint32_t tile, const GateLaunch &g, uint32_t *fb) {
+  constexpr int FL = lds_fibers<D>();
+  if (threadIdx.x < FL) fb[threadIdx.x] = fiber_base(tile * FL + threadIdx.x, g, D);
+}
+
+// Thread's share of a tile: PER float4 (two n_0 values each), rows b = i.
+template <int D>
+constexpr int m0_per_thread() { return lds_fibers<D>() * D * D / 2 / kBlock; }
+
+template <int D>
+__device__ __forceinline__ void m0_gload(const float2 *src, const uint32_t *fb, uint32_t sj,
+                                         float4 (&buf)[m0_per_thread<D>()]) {
+  constexpr int HALF = lds_fibers<D>() * D / 2;
+#pragma unroll
+  for (int i = 0; i < m0_per_thread<D>(); ++i) {
+    const int e = threadIdx.x + i * kBlock, b = e / HALF, r = e % HALF;
+    const int fl = r / (D / 2), a = 2 * (r % (D / 2));
+    buf[i] = *reinterpret_cast<const float4 *>(src + fb[fl] + (uint32_t)a + (uint32_t)b * sj);
+  }
+}
+
+template <int D>
+__device__ __forceinline__ void m0_lds_put(float2 *tile, const float4 (&buf)[m0_per_thread<D>()]) {
+  constexpr int HALF = lds_fibers<D>() * D / 2, ST = D * D + 1;
+#pragma unroll
+  for (int i = 0; i < m0_per_thread<D>(); ++i) {
+    const int e = threadIdx.x + i * kBlock, b = e / HALF, r = e % HALF;
+    const int fl = r / (D / 2), a = 2 * (r % (D / 2));
+    float2 *tp = tile + fl * ST + b * D + a;
+    tp[0] = make_float2(buf[i].x, buf[i].y);
+    tp[1] = make_float2(buf[i].z, buf[i].w);
+  }
+}
+
+template <int D>
+__device__ __forceinline__ void m0_gstore(float2 *dst, const uint32_t *fb, uint32_t sj, const float2 *tile) {
+  constexpr int HALF = lds_fibers<D>() * D / 2, ST = D * D + 1;
+#pragma unroll
+  for (int i = 0; i < m0_per_thread<D>(); ++i) {
+    const int e = threadIdx.x + i * kBlock, b = e / HALF, r = e % HALF;
+    const int fl = r / (D / 2), a = 2 * (r % (D / 2));
+    const float2 *tp = tile + fl * ST + b * D + a;
+    *reinterpret_cast<float4 *>(dst + fb[fl] + (uint32_t)a + (uint32_t)b * sj) =
+        make_float4(tp[0].x, tp[0].y, tp[1].x, tp[1].y);
+  }
+}
+
+// tile: m0_tile_elems<D>() float2, fbase: 2 x lds_fibers<D>() words of LDS.
+// Contains barriers: every thread of the workgroup must call it.
+template <int D, int KIND, bool DAG>
+__device__ __forceinline__ void gate2_m0p_block(int vb, const float2 *src, float2 *psi, const float2 *__restrict__ U,
+                                                const GateLaunch &g, float2 *tile, uint32_t (*fbase)[lds_fibers<D>()]) {
+  constexpr int ST = D * D + 1;
+  const uint32_t t0 = (uint32_t)vb * kM0Tiles;
+  float4 buf[m0_per_thread<D>()];
+  m0_bases<D>(t0, g, fbase[0]);
+  if (kM0Tiles > 1) m0_bases<D>(t0 + 1, g, fbase[1]);
+  __syncthreads();
+  m0_gload<D>(src, fbase[0], g.sj, buf);
+  m0_lds_put<D>(tile, buf);
+  __syncthreads();
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+#pragma unroll 1
+  for (int t = 0; t < kM0Tiles; ++t) {
+    const bool more = t + 1 < kM0Tiles;
+    if (more) m0_gload<D>(src, fbase[(t + 1) & 1], g.sj, buf);
+    float2 *base = tile + lane * ST;
+    switch (wave) {
+      case 0: gate_group<D, KIND, DAG, 4, 0>(base, base, 1u, (uint32_t)D, U); break;
+      case 1: gate_group<D, KIND, DAG, 4, 1>(base, base, 1u, (uint32_t)D, U); break;
+      case 2: gate_group<D, KIND, DAG, 4, 2>(base, base, 1u, (uint32_t)D, U); break;
+      default: gate_group<D, KIND, DAG, 4, 3>(base, base, 1u, (uint32_t)D, U); break;
+    }
+    __syncthreads();
+    m0_gstore<D>(psi, fbase[t & 1], g.sj, tile);
+    __syncthreads();
+    if (more) {
+      m0_lds_put<D>(tile, buf);
+      if (t + 2 < kM0Tiles) m0_bases<D>(t0 + t + 2, g, fbase[t & 1]);
+      __syncthreads();
+    }
+  }
+}
+
+template <int D, int KIND, bool DAG>
+__global__ __launch_bounds__(kBlock) void k_gate2_m0p(const float2 *src, float2 *psi, const float2 *__restrict__ U,
+                                                      GateLaunch g) {
+  __shared__ float2 tile[m0_tile_elems<D>()];
+  __shared__ uint32_t fbase[2][lds_fibers<D>()];
+  gate2_m0p_block<D, KIND, DAG>(xcd_remap(blockIdx.x, gridDim.x), src, psi, U, g, tile, fbase);
+}
+
+// Reverse step over the workgroup's kM0Tiles tiles; returns the thread's sum of
+// Re<lam|A phi> over all of them.  tp, tl: m0_tile_elems<D>() float2 each,
+// fbase: 2 x lds_fibers<D>() words of LDS.  Contains barriers.
+template <int D, int KIND, bool WPHI = true>
+__device__ __forceinline__ float adj_m0p_block(int vb, float2 *phi, float2 *lam, const float2 *__restrict__ U,
+                                               const float2 *__restrict__ A, const GateLaunch &g, float2 *tp,
+                                               float2 *tl, uint32_t (*fbase)[lds_fibers<D>()]) {
+  constexpr int ST = D * D + 1;
+  const uint32_t t0 = (uint32_t)vb * kM0Tiles;
+  float4 bp[m0_per_thread<D>()], bl[m0_per_thread<D>()];
+  m0_bases<D>(t0, g, fbase[0]);
+  if (kM0Tiles > 1) m0_bases<D>(t0 + 1, g, fbase[1]);
+  __syncthreads();
+  m0_gload<D>(phi, fbase[0], g.sj, bp);
+  m0_gload<D>(lam, fbase[0], g.sj, bl);
+  m0_lds_put<D>(tp, bp);
+  m0_lds_put<D>(tl, bl);
+  __syncthreads();
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  float gacc = 0.f;
+#pragma unroll 1
+  for (int t = 0; t < kM0Tiles; ++t) {
+    const bool more = t + 1 < kM0Tiles;
+    if (more) {
+      m0_gload<D>(phi, fbase[(t + 1) & 1], g.sj, bp);
+      m0_gload<D>(lam, fbase[(t + 1) & 1], g.sj, bl);
+    }
+    float2 *pb = tp + lane * ST, *lb = tl + lane * ST;
+    switch (wave) {
+      case 0: gacc += adj_group<D, KIND, 4, 0, WPHI>(pb, lb, 1u, (uint32_t)D, U, A); break;
+      case 1: gacc += adj_group<D, KIND, 4, 1, WPHI>(pb, lb, 1u, (uint32_t)D, U, A); break;
+      case 2: gacc += adj_group<D, KIND, 4, 2, WPHI>(pb, lb, 1u, (uint32_t)D, U, A); break;
+      default: gacc += adj_group<D, KIND, 4, 3, WPHI>(pb, lb, 1u, (uint32_t)D, U, A); break;
+    }
+    __syncthreads();
+    if (WPHI) m0_gstore<D>(phi, fbase[t & 1], g.sj, tp);
+    m0_gstore<D>(lam, fbase[t & 1], g.sj, tl);
+    __syncthreads();
+    if (more) {
+      m0_lds_put<D>(tp, bp);
+      m0_lds_put<D>(tl, bl);
+      if (t + 2 < kM0Tiles) m0_bases<D>(t0 + t + 2, g, fbase[t & 1]);
+      __syncthreads();
+    }
+  }
+  return gacc;
+}
+
+template <int D, int KIND, bool WPHI>
+__global__ __launch_bounds__(kBlock) void k_gate2_adj_m0p(float2 *__restrict__ phi, float2 *__restrict__ lam,
+                                                          const float2 *__restrict__ U, const float2 *__restrict__ A,
+                                                          double *__restrict__ partial, GateLaunch g) {
+  __shared__ float2 tp[m0_tile_elems<D>()], tl[m0_tile_elems<D>()];
+  __shared__ uint32_t fbase[2][lds_fibers<D>()];
+  __shared__ double red[4];
+  const int vb = xcd_remap(blockIdx.x, gridDim.x);
+  const float gacc = adj_m0p_block<D, KIND, WPHI>(vb, phi, lam, U, A, g, tp, tl, fbase);
+  const double sg = block_sum_d((double)gacc, red);
+  if (threadIdx.x == 0) partial[vb] = sg;
+}
+
 template <int D, int KIND, bool DAG>
 __global__ __launch_bounds__(kBlock) void k_gate2_m0(const float2 *src, float2 *psi, const float2 *__restrict__ U,
                                                      GateLaunch g) {
@@ -665,6 +828,18 @@ constexpr int lds_fibers_d() { return lds_fibers<D>(); }
 template <int D>
 int fibers_per_block_d(int i) { return i == 0 ? lds_fibers<D>() : 64 * (4 / direct_groups<D>()); }
 
+// The pipelined mode-0 kernels: d = 8 and whole tiles for every workgroup.
+template <int D>
+constexpr bool m0p_used(int i, uint32_t nfib) {
+  return D == 8 && i == 0 && nfib % (uint32_t)(lds_fibers<D>() * kM0Tiles) == 0;
+}
+
+// Fibres per workgroup of the kernels gate_launch_d / adj_launch_d launch.
+template <int D>
+int launch_fibers_per_block_d(int i, uint32_t nfib) {
+  return m0p_used<D>(i, nfib) ? lds_fibers<D>() * kM0Tiles : fibers_per_block_d<D>(i);
+}
+
 template <int D>
 void gate_launch_d(const GateLaunch &gl, int i, int kind, bool dag, const float2 *U, const float2 *src, float2 *psi,
                    int G, hipStream_t s) {
@@ -675,7 +850,18 @@ void gate_launch_d(const GateLaunch &gl, int i, int kind, bool dag, const float2
   } else {                                                                   \
     if (dag) GATE_K(KN, KIND_DIFF, true); else GATE_K(KN, KIND_DIFF, false); \
   }
-  if (i == 0) { GATE_SEL(k_gate2_m0); } else { GATE_SEL(k_gate2); }
+  if (i == 0) {
+    bool piped = false;
+    if constexpr (D == 8) {
+      if (m0p_used<D>(i, gl.nfib)) {
+        GATE_SEL(k_gate2_m0p);
+        piped = true;
+      }
+    }
+    if (!piped) GATE_SEL(k_gate2_m0);
+  } else {
+    GATE_SEL(k_gate2);
+  }
 #undef GATE_SEL
 #undef GATE_K
 }
@@ -691,7 +877,14 @@ void adj_launch_d(const GateLaunch &gl, int i, int kind, const float2 *U, const 
     if (wphi) ADJ_K(KN, KIND_DIFF, true); else ADJ_K(KN, KIND_DIFF, false);  \
   }
   if (i == 0) {
-    ADJ_SEL(k_gate2_adj_m0);
+    bool piped = false;
+    if constexpr (D == 8) {
+      if (m0p_used<D>(i, gl.nfib)) {
+        ADJ_SEL(k_gate2_adj_m0p);
+        piped = true;
+      }
+    }
+    if (!piped) ADJ_SEL(k_gate2_adj_m0);
   } else {
     ADJ_SEL(k_gate2_adj);
   }
@@ -701,12 +894,14 @@ void adj_launch_d(const GateLaunch &gl, int i, int kind, const float2 *U, const 
 
 #define FOCK_GATE_INSTANTIATE(D)                                                                             \
   template int fibers_per_block_d<D>(int);                                                                 \
+  template int launch_fibers_per_block_d<D>(int, uint32_t);                                                \
   template void gate_launch_d<D>(const GateLaunch &, int, int, bool, const float2 *, const float2 *,       \
                                  float2 *, int, hipStream_t);                                              \
   template void adj_launch_d<D>(const GateLaunch &, int, int, const float2 *, const float2 *, float2 *,    \
                                 float2 *, double *, int, bool, hipStream_t);
 #define FOCK_GATE_EXTERN(D)                                                                                  \
   extern template int fibers_per_block_d<D>(int);                                                          \
+  extern template int launch_fibers_per_block_d<D>(int, uint32_t);                                         \
   extern template void gate_launch_d<D>(const GateLaunch &, int, int, bool, const float2 *, const float2 *, \
                                         float2 *, int, hipStream_t);                                       \
   extern template void adj_launch_d<D>(const GateLaunch &, int, int, const float2 *, const float2 *,       \

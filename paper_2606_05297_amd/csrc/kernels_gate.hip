@@ -136,7 +136,7 @@ GateLaunch gate_launch_params(const Geometry &g, int i, int j) { return make_gat
 int gate_blocks_count(const Geometry &g, int i) {
   const uint32_t nf = g.n_amp / (uint32_t)(g.d * g.d);
   int fpb = 64;
-  FOCK_D_SWITCH(g.d, fpb = fibers_per_block_d<D>(i));
+  FOCK_D_SWITCH(g.d, fpb = launch_fibers_per_block_d<D>(i, nf));
   return (int)((nf + (uint32_t)fpb - 1) / (uint32_t)fpb);
 }
 

@@ -180,13 +180,14 @@ int build_lists(fock_sweep *sw, const std::vector<char> &sel, bool grad, Lists *
         it.dl = diag_launch_params(P.g, op.i, op.type);
         nb = diag_blocks_count(P.g);
       } else {
-        it.variant = op.i == 0 ? 1 : 0;
+        it.variant = op.i == 0 ? (sweep_m0_piped(P.g.d, (int)P.g.n_amp, 0) ? 4 : 1) : 0;
         it.kind = gate_kind(op.type);
         it.gl = gate_launch_params(P.g, op.i, op.j);
         it.A = G.T.A[table_slot(op.type)];
         nb = sweep_gate_blocks(P.g.d, (int)P.g.n_amp, op.i);
       }
-      const int li = 2 * P.group + (it.variant == 1 && sweep_split_classes(P.g.d) ? 1 : 0);  // item class list
+      const bool m0 = it.variant == 1 || it.variant == 4;
+      const int li = 2 * P.group + (m0 && sweep_split_classes(P.g.d) ? 1 : 0);  // item class list
       for (int vb = 0; vb < nb; ++vb) {
         SweepItem f = it;
         f.vb = vb;

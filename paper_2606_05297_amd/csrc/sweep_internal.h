@@ -34,7 +34,8 @@ struct CPtr {
 // One workgroup's share of one gate (forward) or of its reverse step.
 // variant: 0 = two-mode gate with i >= 1, 1 = two-mode gate on (0, j) (LDS),
 // 2 = single-mode diagonal gate, 3 = a run of single-mode phase gates (run,
-// tables from U on at the gate stride).  Forward: dst <- O src.  Reverse:
+// tables from U on at the gate stride), 4 = two-mode gate on (0, j) at d = 8
+// over several tiles (the single-point pipelined block).  Forward: dst <- O src.  Reverse:
 // dst = phi, lam = lambda, partial[vb] <- Re<lam|A phi> of the workgroup (a
 // run writes gate g's sum to partial[g * rs + vb]).
 struct SweepItem {
@@ -74,6 +75,8 @@ struct SweepPoolArgs {
 
 bool sweep_supports_d(int d);
 int sweep_gate_blocks(int d, int namp, int i);
+// Whether mode-0 items at this size run the pipelined multi-tile block (variant 4).
+bool sweep_m0_piped(int d, int namp, int i);
 // Whether the items of a gate layer at cutoff d are split into two classes
 // (separate lists and launches): 0 = two-mode gates on modes i >= 1 and
 // single-mode phases, 1 = two-mode gates on mode 0 (variant 1 items).  When

@@ -115,16 +115,25 @@ __global__ __launch_bounds__(kBlock) void k_sweep_gate(const SweepItem *__restri
   }
 }
 
+// Mode-0 items at d = 8: variant 4 items run the pipelined multi-tile block of
+// the single-point kernels (same tiles per workgroup, same summation order).
 template <int D>
 __global__ __launch_bounds__(kBlock) void k_sweep_gate_m0(const SweepItem *__restrict__ items, int n,
                                                           const int *__restrict__ active) {
   __shared__ float2 tile[m0_tile_elems<D>()];
-  __shared__ uint32_t fbase[lds_fibers<D>()];
+  __shared__ uint32_t fbase[2][lds_fibers<D>()];
   for (int it = blockIdx.x; it < n; it += gridDim.x) {
     const SweepItem g = items[it];
     if (!active[g.p]) continue;
-    if (g.kind == KIND_SUM) gate2_m0_block<D, KIND_SUM, false>(g.vb, g.src, g.dst, g.U, g.gl, tile, fbase);
-    else gate2_m0_block<D, KIND_DIFF, false>(g.vb, g.src, g.dst, g.U, g.gl, tile, fbase);
+    if (g.variant == 4) {
+      __syncthreads();  // the previous item's readers of fbase are done
+      if (g.kind == KIND_SUM) gate2_m0p_block<D, KIND_SUM, false>(g.vb, g.src, g.dst, g.U, g.gl, tile, fbase);
+      else gate2_m0p_block<D, KIND_DIFF, false>(g.vb, g.src, g.dst, g.U, g.gl, tile, fbase);
+    } else if (g.kind == KIND_SUM) {
+      gate2_m0_block<D, KIND_SUM, false>(g.vb, g.src, g.dst, g.U, g.gl, tile, fbase[0]);
+    } else {
+      gate2_m0_block<D, KIND_DIFF, false>(g.vb, g.src, g.dst, g.U, g.gl, tile, fbase[0]);
+    }
   }
 }
 
@@ -158,14 +167,20 @@ template <int D>
 __global__ __launch_bounds__(kBlock) void k_sweep_adj_m0(const SweepItem *__restrict__ items, int n,
                                                          const int *__restrict__ active) {
   __shared__ float2 tp[m0_tile_elems<D>()], tl[m0_tile_elems<D>()];
-  __shared__ uint32_t fbase[lds_fibers<D>()];
+  __shared__ uint32_t fbase[2][lds_fibers<D>()];
   __shared__ double red[4];
   for (int it = blockIdx.x; it < n; it += gridDim.x) {
     const SweepItem g = items[it];
     if (!active[g.p]) continue;
-    const float gacc = g.kind == KIND_SUM
-                           ? adj_m0_block<D, KIND_SUM>(g.vb, g.dst, g.lam, g.U, g.A, g.gl, tp, tl, fbase)
-                           : adj_m0_block<D, KIND_DIFF>(g.vb, g.dst, g.lam, g.U, g.A, g.gl, tp, tl, fbase);
+    float gacc;
+    if (g.variant == 4) {
+      __syncthreads();  // the previous item's readers of fbase are done
+      gacc = g.kind == KIND_SUM ? adj_m0p_block<D, KIND_SUM>(g.vb, g.dst, g.lam, g.U, g.A, g.gl, tp, tl, fbase)
+                                : adj_m0p_block<D, KIND_DIFF>(g.vb, g.dst, g.lam, g.U, g.A, g.gl, tp, tl, fbase);
+    } else {
+      gacc = g.kind == KIND_SUM ? adj_m0_block<D, KIND_SUM>(g.vb, g.dst, g.lam, g.U, g.A, g.gl, tp, tl, fbase[0])
+                                : adj_m0_block<D, KIND_DIFF>(g.vb, g.dst, g.lam, g.U, g.A, g.gl, tp, tl, fbase[0]);
+    }
     const double sg = block_sum_d((double)gacc, red);
     if (threadIdx.x == 0) g.partial[g.vb] = sg;
   }
@@ -287,9 +302,13 @@ int sweep_launch_reduce(const SweepRItem *items, int n, const int *active, int g
 // The single-point kernels' launch geometry, needed to build item lists.
 int sweep_gate_blocks(int d, int namp, int i) {
   int fpb = 64;
-  SWEEP_D_SWITCH(d, fpb = fibers_per_block_d<D>(i));
   const int nf = namp / (d * d);
+  SWEEP_D_SWITCH(d, fpb = launch_fibers_per_block_d<D>(i, (uint32_t)nf));
   return (nf + fpb - 1) / fpb;
+}
+
+bool sweep_m0_piped(int d, int namp, int i) {
+  return d == 8 && m0p_used<8>(i, (uint32_t)(namp / 64));
 }
 
 }  // namespace fock
