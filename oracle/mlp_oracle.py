@@ -8,8 +8,8 @@ The network maps the features (J, Delta, K, n / 64) of an ADAPT point at step
 n to 64 initial angles (the converged angles of that step, padded): the paper
 observes that the initial parameters matter (Sec. V.B, the discussion of random
 initialisations) and suggests re-using information across runs (Appendix D,
-Hessian recycling); the learned proposal is this build's addition on top of the
-plain {theta_prev, 0} initialisation of Sec. IV.B.
+Hessian recycling); the learned proposal is an addition to the method, on top
+of the plain {theta_prev, 0} initialisation of Sec. IV.B.
 
 Architecture 4 -> 128 -> 128 -> 64, SiLU on both hidden layers, linear output.
 Precision contract shared with the device path (each step below is what the
