@@ -57,11 +57,37 @@ enum {
  *   H = sum_bonds [ -J (a_i^+ a_j + a_j^+ a_i) + Delta (a_i a_j + a_i^+ a_j^+) ]
  *     + sum_r [ (U/2 + K) n_r (n_r - 1) - mu n_r ]
  * Bonds: (r, r+1) for r = 0..L-2, plus (0, L-1) when periodic and L >= 3.
- * Bose-Hubbard: Delta = K = 0.  Kitaev + Kerr: U = 0. */
+ * Bose-Hubbard: Delta = K = 0.  Kitaev + Kerr: U = 0.
+ * layout: how the state buffers of the call hold psi.
+ *   FOCK_LAYOUT_FULL (0): the d^L tensor, index sum_r n_r d^r.
+ *   FOCK_LAYOUT_EVEN (1), FOCK_LAYOUT_ODD (2): a state of total parity
+ *     sigma = 0 resp. 1 (sum_r n_r = sigma mod 2) in the parity-halved layout:
+ *     the top mode stores m = 0..d/2-1 with n_{L-1} = 2 m + ((n_0 + .. + n_{L-2}
+ *     + sigma) mod 2), at index sum_{r < L-1} n_r d^r + m d^(L-1), so a state
+ *     holds d^L / 2 amplitudes (the other half of the tensor is zero).  H and
+ *     every two-mode generator keep the total parity (Sec. II.B, III), so the
+ *     sector is closed under them.  Open chains of L = 8, d = 8 under the slab
+ *     stencil only; taken by fock_workspace_bytes, fock_apply_H, fock_pool_grads
+ *     and fock_score (pools of HR..PI on nearest-neighbour pairs),
+ *     fock_energy_grad_adjoint and fock_adjoint_sweep (HR..PI gates on pairs
+ *     (i, j) with j < L-1, or (L-2, L-1)); FOCK_ERR_UNSUPPORTED elsewhere and
+ *     for other ops.  Every other call takes layout 0 only. */
+enum { FOCK_LAYOUT_FULL = 0, FOCK_LAYOUT_EVEN = 1, FOCK_LAYOUT_ODD = 2 };
 typedef struct {
-  int32_t L, d, periodic, reserved;
+  int32_t L, d, periodic, layout;
   double J, U, mu, Delta, K;
 } fock_ham_t;
+
+/* Conversions between a full d^L state of one total parity and its
+ * parity-halved layout (FOCK_LAYOUT_EVEN / _ODD, see fock_ham_t), d = 8,
+ * 2 <= L <= 10.  pack: half[c] = full[index of c] for the d^L / 2 stored
+ * amplitudes (the other parity part of full is not read); unpack writes every
+ * amplitude of full (zero outside the sector).  Device buffers of d^L resp.
+ * d^L / 2 complex64, 16-byte aligned, not overlapping; stream-ordered on
+ * `stream`, no allocation.  FOCK_ERR_ARG / FOCK_ERR_UNSUPPORTED on bad
+ * arguments. */
+int fock_sector_pack(int L, int d, int layout, const void *full, void *half, fock_stream_t stream);
+int fock_sector_unpack(int L, int d, int layout, const void *half, void *full, fock_stream_t stream);
 
 /* Anti-Hermitian generators A (gate = exp(theta A)), Sec. II.B and Table I:
  *   FOCK_HR   a_i^+ a_j - a_j^+ a_i              (beam splitter, phi = pi)
@@ -222,10 +248,11 @@ typedef struct fock_adapt fock_adapt_t;
  * tie_tau 1e-4, gtol_floor_rel 1e-5, warm_gtol 1e-6, fd_step 1e-3, noise_rel 1e-7. */
 void adapt_default_opts(fock_adapt_opts_t *opts);
 
-/* Create an ADAPT run on `ham` with `pool` (P ops, host, copied) from the
- * device state psi0 (copied).  The object owns its device buffers (three
- * states plus workspace) and uses `stream`.  With a warm-up layer, its angles
- * are BFGS-optimised here (report via adapt_warm_report). */
+/* Create an ADAPT run on `ham` (layout 0) with `pool` (P ops, host, copied)
+ * from the device state psi0 (d^L complex64, copied).  The object owns its
+ * device buffers (three states, in the layout adapt_layout reports, plus
+ * workspace) and uses `stream`.  With a warm-up layer, its angles are
+ * BFGS-optimised here (report via adapt_warm_report). */
 int adapt_create(const fock_ham_t *ham, const fock_op_t *pool, int P, const void *psi0,
                  const fock_adapt_opts_t *opts, fock_stream_t stream, fock_adapt_t **out);
 
@@ -266,6 +293,16 @@ int adapt_last_proposal(fock_adapt_t *st, int *accepted, double *E_prop, double 
 /* Number of forward states the run keeps for its gradient evaluations (0: none;
  * see fock_set_state_store). */
 int adapt_state_store(fock_adapt_t *st, int *nstates);
+
+/* Layout the run keeps its states in (FOCK_LAYOUT_*): with the sector switch
+ * on (fock_set_sector_layout), adapt_create picks FOCK_LAYOUT_EVEN / _ODD when
+ * psi0 has exactly zero amplitude outside one total-parity sector, the chain
+ * is an open L = 8, d = 8 chain under the slab stencil, the pool holds only
+ * HR..PI generators on nearest-neighbour pairs (each at most once) and the
+ * warm-up layer only HR..PI gates on pairs (i, j) with j < L-1 or (L-2, L-1);
+ * otherwise FOCK_LAYOUT_FULL.  Both layouts give the same energies, gradients
+ * and selections to FP32 rounding. */
+int adapt_layout(fock_adapt_t *st, int *layout);
 
 int adapt_destroy(fock_adapt_t *st);
 
@@ -463,6 +500,16 @@ int fock_get_stencil_variant(void);
 enum { FOCK_STORE_OFF = 0, FOCK_STORE_ON = 1, FOCK_STORE_AUTO = 2 };
 int fock_set_state_store(int mode);
 int fock_get_state_store(void);
+
+/* Parity-halved states in the ADAPT driver (see adapt_layout):
+ *   FOCK_SECTOR_OFF  (0) always the full d^L layout;
+ *   FOCK_SECTOR_AUTO (1) the parity-halved layout where adapt_layout says
+ *                    (default): half the state bytes of every kernel.
+ * Applies to drivers created after the call; FOCK_ERR_ARG for other values;
+ * process-wide. */
+enum { FOCK_SECTOR_OFF = 0, FOCK_SECTOR_AUTO = 1 };
+int fock_set_sector_layout(int mode);
+int fock_get_sector_layout(void);
 
 /* ------------------------------------------------------------------ FP64 states */
 

@@ -33,6 +33,8 @@ SOURCES = [
     "kernels_gate_dd.hip",
     "kernels_gate_de.hip",
     "kernels_gate_df.hip",
+    "gate_half.hip",
+    "sector.hip",
     "sweep_kernels.hip",
     "sweep.cpp",
     "host_common.cpp",

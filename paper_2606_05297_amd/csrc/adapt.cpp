@@ -43,6 +43,27 @@ struct fock_adapt {
 
 namespace {
 
+// Total parity of a full d = 8 state: 0 or 1 when one of the two parity parts
+// is exactly zero and the other is not, -1 otherwise.
+int psi_sector(const void *psi, uint32_t namp, hipStream_t s, int *sector) {
+  *sector = -1;
+  const int G = sector_norms_blocks(namp);
+  double *buf = nullptr;
+  if (hipMalloc((void **)&buf, sizeof(double) * (2 * (size_t)G + 2)) != hipSuccess)
+    return set_error(FOCK_ERR_HIP, "hipMalloc of the sector partials failed");
+  double host[2] = {0.0, 0.0};
+  int rc = launch_sector_norms((const float2 *)psi, namp, buf, s);
+  if (!rc) rc = launch_reduce(buf, G, 2, buf + 2 * G, s);
+  if (!rc && (hipMemcpyAsync(host, buf + 2 * G, sizeof(host), hipMemcpyDeviceToHost, s) != hipSuccess ||
+              hipStreamSynchronize(s) != hipSuccess))
+    rc = set_error(FOCK_ERR_HIP, "sector norms of psi0 failed");
+  (void)hipFree(buf);
+  if (rc) return rc;
+  if (host[1] == 0.0 && host[0] > 0.0) *sector = 0;
+  else if (host[0] == 0.0 && host[1] > 0.0) *sector = 1;
+  return FOCK_OK;
+}
+
 int eval_energy(fock_adapt *st, const std::vector<double> &th, double *E, double *n2, std::vector<double> *g) {
   const int n = (int)st->ops.size();
   if (!g) return run_circuit(st->ctx, st->ops.data(), th.data(), n, st->psi0, st->phi, st->lam, false, E, n2, nullptr);
@@ -148,8 +169,22 @@ int adapt_create(const fock_ham_t *ham, const fock_op_t *pool, int P, const void
     return set_error(FOCK_ERR_ARG, "invalid iteration caps (max_iters in 0..4000) or tolerance");
   if (opts->grad_mode == 1 && !(opts->fd_step > 0.0)) return set_error(FOCK_ERR_ARG, "fd_step must be > 0");
 
+  if (ham->layout != FOCK_LAYOUT_FULL)
+    return set_error(FOCK_ERR_ARG, "adapt_create takes a full d^L psi0 (layout 0); the driver picks its own layout");
+  // A parity-definite psi0 under a parity-keeping pool stays in its sector:
+  // the driver then keeps every state in the parity-halved layout.
+  fock_ham_t hc = *ham;
+  if (half_layout_wanted(*ham, pool, P, opts->warm_ops, opts->n_warm)) {
+    int sector = -1;
+    if ((rc = psi_sector(psi0, namp, (hipStream_t)stream, &sector))) return rc;
+    if (sector >= 0) {
+      hc.layout = sector ? FOCK_LAYOUT_ODD : FOCK_LAYOUT_EVEN;
+      namp /= 2;
+    }
+  }
+
   fock_adapt *st = new fock_adapt();
-  st->ham = *ham;
+  st->ham = hc;
   st->namp = namp;
   st->s = (hipStream_t)stream;
   st->opt = *opts;
@@ -161,7 +196,7 @@ int adapt_create(const fock_ham_t *ham, const fock_op_t *pool, int P, const void
     st->theta.push_back(opts->warm_theta0[k]);
   }
   const int nmax = opts->n_warm + opts->max_iters + 1;
-  const Layout L = make_layout(namp, ham->L, ham->d, P, nmax);
+  const Layout L = make_layout(namp, ham->L, ham->d, P, nmax, hc.layout != FOCK_LAYOUT_FULL);
   const size_t sbytes = (sizeof(float2) * (size_t)namp + 255) & ~(size_t)255;
   st->ws_bytes = L.total;
   if (hipMalloc(&st->dbuf, 3 * sbytes + st->ws_bytes) != hipSuccess) {
@@ -173,9 +208,11 @@ int adapt_create(const fock_ham_t *ham, const fock_op_t *pool, int P, const void
   st->phi = (float2 *)(b + sbytes);
   st->lam = (float2 *)(b + 2 * sbytes);
   st->ws = b + 3 * sbytes;
-  rc = make_ctx(*ham, namp, P, nmax, st->ws, st->ws_bytes, st->s, &st->ctx);
+  rc = make_ctx(hc, namp, P, nmax, st->ws, st->ws_bytes, st->s, &st->ctx);
   if (!rc) rc = attach_state_store(st->ctx, nmax, &st->store_buf);
-  if (!rc && hipMemcpyAsync(st->psi0, psi0, sizeof(float2) * namp, hipMemcpyDeviceToDevice, st->s) != hipSuccess)
+  if (!rc && hc.layout != FOCK_LAYOUT_FULL)
+    rc = launch_sector_convert(hc.L, st->ctx.g.sector, true, (const float2 *)psi0, st->psi0, st->s);
+  else if (!rc && hipMemcpyAsync(st->psi0, psi0, sizeof(float2) * namp, hipMemcpyDeviceToDevice, st->s) != hipSuccess)
     rc = set_error(FOCK_ERR_HIP, "copy of psi0 failed");
   if (!rc) {
     st->warm.iter = 0;
@@ -336,6 +373,12 @@ int adapt_last_proposal(fock_adapt_t *st, int *accepted, double *E_prop, double 
   if (accepted) *accepted = st->prop_acc;
   if (E_prop) *E_prop = st->prop_E;
   if (E_plain) *E_plain = st->plain_E;
+  return FOCK_OK;
+}
+
+int adapt_layout(fock_adapt_t *st, int *layout) {
+  if (!st || !layout) return set_error(FOCK_ERR_ARG, "NULL argument");
+  *layout = st->ham.layout;
   return FOCK_OK;
 }
 

@@ -27,13 +27,28 @@ int check_geometry(int L, int d, uint32_t *namp) {
   return FOCK_OK;
 }
 
-int check_ham(const fock_ham_t *h, uint32_t *namp) {
+int check_ham_layout(const fock_ham_t *h, uint32_t *namp) {
   if (!h) return set_error(FOCK_ERR_ARG, "ham is NULL");
   int rc = check_geometry(h->L, h->d, namp);
   if (rc) return rc;
   const double v[5] = {h->J, h->U, h->mu, h->Delta, h->K};
   for (double x : v)
     if (!std::isfinite(x)) return set_error(FOCK_ERR_NONFINITE, "non-finite Hamiltonian parameter");
+  if (h->layout < FOCK_LAYOUT_FULL || h->layout > FOCK_LAYOUT_ODD)
+    return set_error(FOCK_ERR_ARG, "layout %d not in {0, 1, 2}", h->layout);
+  if (h->layout != FOCK_LAYOUT_FULL) {
+    if (h->L != 8 || h->d != 8 || h->periodic)
+      return set_error(FOCK_ERR_UNSUPPORTED, "the parity-halved layout is for open chains of L = 8, d = 8");
+    *namp /= 2;
+  }
+  return FOCK_OK;
+}
+
+int check_ham(const fock_ham_t *h, uint32_t *namp) {
+  int rc = check_ham_layout(h, namp);
+  if (rc) return rc;
+  if (h->layout != FOCK_LAYOUT_FULL)
+    return set_error(FOCK_ERR_UNSUPPORTED, "this call takes full d^L states (layout 0)");
   return FOCK_OK;
 }
 
@@ -109,14 +124,15 @@ static thread_local Pinned tl_in, tl_out;
 // ---------------------------------------------------------------- workspace layout
 static size_t al(size_t x) { return (x + 255) & ~(size_t)255; }
 
-Layout make_layout(uint32_t namp, int Lm, int d, int P, int n) {
+Layout make_layout(uint32_t namp, int Lm, int d, int P, int n, int half) {
   Layout L;
   const uint32_t nrows = namp / (uint32_t)d;
   L.G = (int)((nrows + kBlock - 1) / kBlock);
   L.G = std::max(L.G, (int)(nrows / (uint32_t)apply_h_tile_rows(Lm, d)));
   L.rs = L.G;
   if (Lm >= 2) {
-    const Geometry g{Lm, d, namp};
+    Geometry g{Lm, d, namp};
+    g.half = half;
     L.rs = std::max(L.G, gate_blocks_max(g));
   }
   L.nmax = std::max(n, 1);
@@ -148,6 +164,10 @@ int make_ctx(const fock_ham_t &ham, uint32_t namp, int P, int n, void *ws, size_
                     Ctx *c) {
   c->g = {ham.L, ham.d, namp};
   c->h = make_ham_args(ham);
+  if (ham.layout != FOCK_LAYOUT_FULL) {
+    c->g.half = c->h.half = 1;
+    c->g.sector = c->h.sector = ham.layout == FOCK_LAYOUT_ODD ? 1 : 0;
+  }
   memset(&c->T, 0, sizeof(c->T));  // eigendata loaded below when the call applies gates
   {
     int rc = stencil_order_table(ham.L, ham.d, apply_h_blocks(c->h), &c->h.order);
@@ -158,9 +178,11 @@ int make_ctx(const fock_ham_t &ham, uint32_t namp, int P, int n, void *ws, size_
                   lanes_stencil_ok(ham.L, ham.d, c->h.periodic_wrap)) ? 1 : 0;
     c->h.slab = (stencil_variant() == FOCK_STENCIL_SLAB && c->h.hi_m == 0 && slab_stencil_ok(ham.L, ham.d)) ? 1 : 0;
   }
+  if (c->g.half && !c->h.slab)
+    return set_error(FOCK_ERR_UNSUPPORTED, "the parity-halved layout needs the slab stencil with the one-pass schedule");
   c->s = s;
   c->ws = (char *)ws;
-  c->L = make_layout(namp, ham.L, ham.d, P, n);
+  c->L = make_layout(namp, ham.L, ham.d, P, n, c->g.half);
   if (!ws) return set_error(FOCK_ERR_ARG, "workspace is NULL");
   if (((uintptr_t)ws) & 255) return set_error(FOCK_ERR_ARG, "workspace must be 256-byte aligned");
   if (ws_bytes < c->L.total)
@@ -239,7 +261,7 @@ int gate_variant() { return g_gate_variant.load(); }
 
 int forward_gate(Ctx &c, const fock_op_t &op, int k, bool dag, const float2 *src, float2 *psi) {
   const float2 *U = (const float2 *)(c.ws + c.L.utab) + (size_t)k * gate_stride(c.g.d);
-  if (!is_single_mode(op.type) && gate_variant() == FOCK_GATE_DENSE_MFMA && dense_supported(c.g.d)) {
+  if (!is_single_mode(op.type) && !c.g.half && gate_variant() == FOCK_GATE_DENSE_MFMA && dense_supported(c.g.d)) {
     ProfScope ps(FOCK_K_GATE_DENSE, c.s, 16.0 * c.g.n_amp);
     return launch_gate_dense(c.g, op.i, op.j, gate_kind(op.type), dag, U, src, psi, (float *)(c.ws + c.L.wdense),
                              c.s);
@@ -290,7 +312,7 @@ int fuse_max_modes(int L, int d) {
 static void plan_gate_groups(const Ctx &c, const fock_op_t *ops, int n, std::vector<GateGroup> *out) {
   out->clear();
   const int L = c.g.L, d = c.g.d, smax = fuse_max_modes(L, d);
-  const bool on = g_fuse.load() != FOCK_FUSE_OFF && fuse_supported(d) && smax >= 2;
+  const bool on = !c.g.half && g_fuse.load() != FOCK_FUSE_OFF && fuse_supported(d) && smax >= 2;
   int k = 0;
   while (k < n) {
     GateGroup gr;
@@ -379,8 +401,20 @@ static FuseArgs make_fuse_args(const Ctx &c, const GateGroup &gr, const fock_op_
 
 // Stage the gate tables of a circuit (with the per-gate partial counts of the
 // reverse step, which depend on how the gates are grouped) and plan its groups.
+// Gates the parity-halved layout runs: two-mode HR..PI generators (they keep
+// the total parity) on pairs below the top mode or on the top pair itself.
+bool half_layout_op_ok(const fock_op_t &op, int L) {
+  if (op.type < FOCK_HR || op.type > FOCK_PI || op.j < 0) return false;
+  return op.j < L - 1 || op.i == L - 2;
+}
+
 static int stage_circuit(Ctx &c, const fock_op_t *ops, const double *theta, int n, std::vector<GateGroup> *groups) {
   if (n > c.L.nmax) return set_error(FOCK_ERR_SIZE, "circuit of %d gates exceeds the workspace's %d", n, c.L.nmax);
+  if (c.g.half)
+    for (int k = 0; k < n; ++k)
+      if (!half_layout_op_ok(ops[k], c.g.L))
+        return set_error(FOCK_ERR_UNSUPPORTED, "gate %d (type %d on (%d,%d)) in the parity-halved layout", k,
+                         ops[k].type, ops[k].i, ops[k].j);
   plan_gate_groups(c, ops, n, groups);
   if (n == 0) return FOCK_OK;
   const bool fuse_rev = g_fuse.load() == FOCK_FUSE_ALL;
@@ -582,6 +616,33 @@ int run_reverse(Ctx &c, const fock_op_t *ops, const double *theta, int n, float2
   return FOCK_OK;
 }
 
+// ---------------------------------------------------------------- parity-halved layout (ADAPT driver)
+static std::atomic<int> g_sector_layout{FOCK_SECTOR_AUTO};
+
+int sector_layout_mode() { return g_sector_layout.load(); }
+
+// Whether the ADAPT driver may keep a parity-definite state of this chain in
+// the parity-halved layout: switched on, an open L = 8, d = 8 chain under the
+// slab stencil, a pool that the slab scoring takes whole (HR..PI on
+// nearest-neighbour pairs, no repeats) and gates the layout runs.
+bool half_layout_wanted(const fock_ham_t &h, const fock_op_t *pool, int P, const fock_op_t *ops, int n) {
+  if (g_sector_layout.load() != FOCK_SECTOR_AUTO || h.L != 8 || h.d != 8 || h.periodic) return false;
+  const int wrap = (h.periodic && h.L >= 3) ? 1 : 0;
+  const int hi_m = stencil_schedule() == FOCK_SCHED_TWO_PASS ? apply_h_hi_modes(h.L, h.d, wrap) : 0;
+  if (stencil_variant() != FOCK_STENCIL_SLAB || hi_m != 0 || !slab_stencil_ok(h.L, h.d)) return false;
+  if (P < 1 || P > kMaxSlots) return false;
+  bool seen[8][5] = {};
+  for (int k = 0; k < P; ++k) {
+    const fock_op_t &op = pool[k];
+    if (op.type < FOCK_HR || op.type > FOCK_PI || op.j != op.i + 1 || op.i < 0 || op.i > 6) return false;
+    if (seen[op.i][op.type]) return false;
+    seen[op.i][op.type] = true;
+  }
+  for (int k = 0; k < n; ++k)
+    if (!half_layout_op_ok(ops[k], h.L)) return false;
+  return true;
+}
+
 // The whole pool as one slab-kernel chunk, when every entry is a two-mode
 // generator (HR..PI) on a nearest-neighbour pair (p, p + 1), or on the ring pair
 // (0, L - 1) of a ring, or a diagonal generator (at most kSlabDiag), with no
@@ -594,7 +655,7 @@ static bool slab_pool_of(const Ctx &c, const fock_op_t *pool, int P, SlabPool *s
   for (int k = 0; k < P; ++k) {
     const fock_op_t &op = pool[k];
     if (is_pool_diagonal(op.type)) {
-      if (sp->ndiag >= kSlabDiag) return false;
+      if (c.g.half || sp->ndiag >= kSlabDiag) return false;
       sp->diag[sp->ndiag++] = {(int16_t)op.i, (int16_t)op.type, (int16_t)k, (int16_t)(op.type == FOCK_CK ? op.j : -1)};
       continue;
     }
@@ -616,16 +677,17 @@ int score_dev(Ctx &c, const fock_op_t *pool, int P, const float2 *psi, float2 *h
   SlabPool sp;
   if (slab_pool_of(c, pool, P, &sp)) {
     double *ppart = (double *)(c.ws + c.L.partial);
-    double *hpart = ppart + (size_t)pool_slab_blocks() * P;
+    double *hpart = ppart + (size_t)pool_slab_blocks(c.h) * P;
     {
       ProfScope ps(FOCK_K_SCORE, c.s, 16.0 * c.g.n_amp);
       int rc = launch_score_slab(sp, c.h, psi, hpsi, hpart, ppart, c.s);
       if (rc) return rc;
     }
-    int rc = launch_reduce(hpart, 512, 2, res, c.s);
+    int rc = launch_reduce(hpart, apply_h2_blocks(c.h), 2, res, c.s);
     if (rc) return rc;
-    return launch_reduce(ppart, pool_slab_blocks(), P, res + 2, c.s);
+    return launch_reduce(ppart, pool_slab_blocks(c.h), P, res + 2, c.s);
   }
+  if (c.g.half) return set_error(FOCK_ERR_UNSUPPORTED, "pool outside the slab scoring in the parity-halved layout");
   int rc = apply_h_dev(c, psi, hpsi, res);
   if (rc) return rc;
   return pool_dev(c, pool, P, psi, hpsi, res + 2);
@@ -633,6 +695,19 @@ int score_dev(Ctx &c, const fock_op_t *pool, int P, const float2 *psi, float2 *h
 
 // Pool gradients 2 Re <hpsi|A_k psi> into res[0..P) on the device.
 int pool_dev(Ctx &c, const fock_op_t *pool, int P, const float2 *psi, const float2 *hpsi, double *res) {
+  if (c.g.half) {  // one slab chunk: nearest-neighbour pairs only
+    SlabPool sp;
+    if (!slab_pool_of(c, pool, P, &sp))
+      return set_error(FOCK_ERR_UNSUPPORTED, "pool outside the slab scoring in the parity-halved layout");
+    double *part = (double *)(c.ws + c.L.partial);
+    int G = 0;
+    {
+      ProfScope ps(FOCK_K_POOL, c.s, 16.0 * c.g.n_amp);
+      int rc = launch_pool_slab(sp, c.h, psi, hpsi, part, &G, c.s);
+      if (rc) return rc;
+    }
+    return launch_reduce(part, G, P, res, c.s);
+  }
   PoolArgs a;
   memset(&a, 0, sizeof(a));
   a.L = c.g.L;
@@ -783,19 +858,19 @@ int fock_version(void) { return 1; }
 
 int fock_workspace_bytes(const fock_ham_t *ham, int n_pool, int n_ops, size_t *bytes) {
   uint32_t namp = 0;
-  int rc = check_ham(ham, &namp);
+  int rc = check_ham_layout(ham, &namp);
   if (rc) return rc;
   if (!bytes) return set_error(FOCK_ERR_ARG, "bytes is NULL");
   if (n_pool < 0 || n_pool > 4096 || n_ops < 0 || n_ops > 4096)
     return set_error(FOCK_ERR_ARG, "n_pool/n_ops out of range");
-  *bytes = make_layout(namp, ham->L, ham->d, n_pool, n_ops).total;
+  *bytes = make_layout(namp, ham->L, ham->d, n_pool, n_ops, ham->layout != FOCK_LAYOUT_FULL).total;
   return FOCK_OK;
 }
 
 int fock_apply_H(const fock_ham_t *ham, const void *psi, void *hpsi, double *E, double *norm2, void *ws,
                  size_t ws_bytes, fock_stream_t stream) {
   uint32_t namp = 0;
-  int rc = check_ham(ham, &namp);
+  int rc = check_ham_layout(ham, &namp);
   if (rc) return rc;
   if ((rc = check_ptr(psi, "psi")) || (rc = check_ptr(hpsi, "hpsi"))) return rc;
   if (psi == hpsi) return set_error(FOCK_ERR_ARG, "psi and hpsi must not overlap");
@@ -928,7 +1003,7 @@ int fock_apply_gate2(int L, int d, fock_op_t op, double theta, int adjoint, void
 int fock_pool_grads(const fock_ham_t *ham, const fock_op_t *pool, int P, const void *psi, const void *hpsi,
                     double *grads, void *ws, size_t ws_bytes, fock_stream_t stream) {
   uint32_t namp = 0;
-  int rc = check_ham(ham, &namp);
+  int rc = check_ham_layout(ham, &namp);
   if (rc) return rc;
   if (P < 0 || P > 4096) return set_error(FOCK_ERR_ARG, "P=%d out of range", P);
   if (P == 0) return FOCK_OK;
@@ -948,7 +1023,7 @@ int fock_energy_grad_adjoint(const fock_ham_t *ham, const fock_op_t *ops, const 
                              const void *psi0, void *psi_work, void *lam_work, double *E, double *norm2,
                              double *dEdtheta, void *ws, size_t ws_bytes, fock_stream_t stream) {
   uint32_t namp = 0;
-  int rc = check_ham(ham, &namp);
+  int rc = check_ham_layout(ham, &namp);
   if (rc) return rc;
   if (n < 0 || n > 4096) return set_error(FOCK_ERR_ARG, "n=%d out of range", n);
   if (n > 0 && (!ops || !theta)) return set_error(FOCK_ERR_ARG, "ops/theta is NULL");
@@ -970,7 +1045,7 @@ int fock_energy_grad_adjoint(const fock_ham_t *ham, const fock_op_t *ops, const 
 int fock_score(const fock_ham_t *ham, const fock_op_t *pool, int P, const void *psi, void *hpsi, double *E,
                double *norm2, double *grads, void *ws, size_t ws_bytes, fock_stream_t stream) {
   uint32_t namp = 0;
-  int rc = check_ham(ham, &namp);
+  int rc = check_ham_layout(ham, &namp);
   if (rc) return rc;
   if (P < 1 || P > 4096) return set_error(FOCK_ERR_ARG, "P=%d out of range", P);
   if (!pool || !grads) return set_error(FOCK_ERR_ARG, "pool/grads is NULL");
@@ -1008,11 +1083,39 @@ int fock_set_state_store(int mode) {
 
 int fock_get_state_store(void) { return g_state_store.load(); }
 
+int fock_set_sector_layout(int mode) {
+  if (mode != FOCK_SECTOR_OFF && mode != FOCK_SECTOR_AUTO)
+    return set_error(FOCK_ERR_ARG, "sector layout mode %d is not OFF (0) or AUTO (1)", mode);
+  g_sector_layout.store(mode);
+  return FOCK_OK;
+}
+
+int fock_get_sector_layout(void) { return g_sector_layout.load(); }
+
+static int sector_convert(int L, int d, int layout, const void *src, void *dst, bool to_half, fock_stream_t stream) {
+  if (d != 8) return set_error(FOCK_ERR_UNSUPPORTED, "the parity-halved layout needs d = 8 (d=%d)", d);
+  if (layout != FOCK_LAYOUT_EVEN && layout != FOCK_LAYOUT_ODD)
+    return set_error(FOCK_ERR_ARG, "layout %d is not EVEN (1) or ODD (2)", layout);
+  int rc;
+  if ((rc = check_ptr(src, "src")) || (rc = check_ptr(dst, "dst"))) return rc;
+  if (src == dst) return set_error(FOCK_ERR_ARG, "src and dst must not overlap");
+  return launch_sector_convert(L, layout == FOCK_LAYOUT_ODD ? 1 : 0, to_half, (const float2 *)src, (float2 *)dst,
+                               (hipStream_t)stream);
+}
+
+int fock_sector_pack(int L, int d, int layout, const void *full, void *half, fock_stream_t stream) {
+  return sector_convert(L, d, layout, full, half, true, stream);
+}
+
+int fock_sector_unpack(int L, int d, int layout, const void *half, void *full, fock_stream_t stream) {
+  return sector_convert(L, d, layout, half, full, false, stream);
+}
+
 int fock_adjoint_sweep(const fock_ham_t *ham, const fock_op_t *ops, const double *theta, int n, void *psi_work,
                        void *lam_work, double norm2, double *dEdtheta, void *ws, size_t ws_bytes,
                        fock_stream_t stream) {
   uint32_t namp = 0;
-  int rc = check_ham(ham, &namp);
+  int rc = check_ham_layout(ham, &namp);
   if (rc) return rc;
   if (n < 0 || n > 4096) return set_error(FOCK_ERR_ARG, "n=%d out of range", n);
   if (n > 0 && (!ops || !theta || !dEdtheta)) return set_error(FOCK_ERR_ARG, "ops/theta/dEdtheta is NULL");

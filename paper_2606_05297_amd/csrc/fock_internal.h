@@ -53,6 +53,8 @@ struct HamArgs {
                       // by a first pass that stages those modes in LDS; 0 = single pass
   int lanes;          // 1: lane-split stencil (d = 8, 4 <= L <= 10, open chain, single pass)
   int slab;           // 1: two-pass slab stencil (L = 8, d = 8; stencil2.hip)
+  int half;           // 1: parity-halved layout (the top mode stores m with n_top = 2 m + parity)
+  int sector;         // total parity of the states in the halved layout (0 even, 1 odd)
 };
 
 // ---------------------------------------------------------------- pool gradients
@@ -119,10 +121,21 @@ struct EigTables {
   int d, psize;
 };
 
+// Parity-halved layout (d = 8, open chain, states of one total parity sigma):
+// the top mode L-1 stores m = 0..d/2-1 and n_{L-1} = 2 m + ((n_0 + .. + n_{L-2}
+// + sigma) mod 2), so a state holds d^L / 2 amplitudes at index
+// sum_{r < L-1} n_r d^r + m d^(L-1).  Every generator that keeps the total
+// parity and leaves mode L-1 alone acts on it as on a tensor whose top mode has
+// d/2 levels; the pair (L-2, L-1) and the bonds that touch mode L-1 have
+// kernels of their own.
 struct Geometry {
   int L, d;
   uint32_t n_amp;
+  int half = 0;    // 1: parity-halved layout (n_amp = d^L / 2)
+  int sector = 0;  // its total parity
 };
+// Parity of the base-8 digit sum of x (digits are 3-bit fields; x < 2^30).
+__host__ __device__ inline int octal_digit_parity(uint32_t x) { return __builtin_popcount(x & 0x09249249u) & 1; }
 
 inline int block_lo(int kind, int d, int s) {
   if (kind == KIND_SUM) return s - (d - 1) > 0 ? s - (d - 1) : 0;
@@ -180,6 +193,13 @@ int launch_gate(const Geometry &g, int i, int j, int kind, bool dag, const float
 int launch_gate_adj(const Geometry &g, int i, int j, int kind, const float2 *U, const float2 *A, float2 *phi,
                     float2 *lam, double *partial, hipStream_t s, bool write_phi = true);
 int gate_blocks_count(const Geometry &g, int i);  // workgroups of a gate on (i, j)
+// Top pair (L-2, L-1) of the parity-halved layout (gate_half.hip); the general
+// launchers above route to these.
+int launch_gate_half(const Geometry &g, int i, int j, int kind, bool dag, const float2 *U, const float2 *src,
+                     float2 *psi, hipStream_t s);
+int launch_gate_adj_half(const Geometry &g, int i, int j, int kind, const float2 *U, const float2 *A, float2 *phi,
+                         float2 *lam, double *partial, hipStream_t s, bool write_phi);
+int half_top_blocks(const Geometry &g);
 int gate_blocks_max(const Geometry &g);
 // Single-mode diagonal gate with device phase table ph[d].
 int launch_diag(const Geometry &g, int r, int type, bool dag, const float2 *ph, const float2 *src, float2 *psi,
@@ -241,10 +261,12 @@ bool slab_stencil_ok(int L, int d);
 int launch_apply_h2(const HamArgs &h, const float2 *psi, float2 *hpsi, double *partial, int *nblocks,
                     hipStream_t s);
 // Slab pool scoring (stencil2.hip): one FP64 partial per (workgroup, slot),
-// pool_slab_blocks() workgroups, slot values already doubled.
+// pool_slab_blocks(h) workgroups, slot values already doubled.
 int launch_pool_slab(const SlabPool &sp, const HamArgs &h, const float2 *psi, const float2 *hpsi, double *partial,
                      int *nblocks, hipStream_t s);
-int pool_slab_blocks();
+int pool_slab_blocks(const HamArgs &h);
+// Pencil partials of launch_apply_h2 / launch_score_slab (2 doubles each).
+int apply_h2_blocks(const HamArgs &h);
 // Fused scoring (stencil2.hip): H psi into hpsi with (<psi|H psi>, <psi|psi>)
 // partials per pencil in hpart (apply_h2 layout), and the pool partials of
 // every slot in ppart (launch_pool_slab layout), from one column pass, one row
@@ -252,6 +274,12 @@ int pool_slab_blocks();
 // column-shape pool pass.
 int launch_score_slab(const SlabPool &sp, const HamArgs &h, const float2 *psi, float2 *hpsi, double *hpart,
                       double *ppart, hipStream_t s);
+
+// Parity sectors (sector.hip, d = 8): partial (even, odd) sums of |Re| + |Im|
+// of a full state, sector_norms_blocks(n) pairs; full <-> parity-halved conversion.
+int sector_norms_blocks(uint32_t n);
+int launch_sector_norms(const float2 *psi, uint32_t n, double *partial, hipStream_t s);
+int launch_sector_convert(int L, int sector, bool to_half, const float2 *src, float2 *dst, hipStream_t s);
 
 struct ProfScope {
   int id;

@@ -149,6 +149,7 @@ static int gate1_grid(const Gate1Launch &a) { return (int)((a.nfib + kBlock - 1)
 
 int launch_gate1(const Geometry &g, int r, bool dag, const float2 *U, const float2 *src, float2 *psi,
                  hipStream_t s) {
+  if (g.half) return set_error(FOCK_ERR_UNSUPPORTED, "squeezers in the parity-halved layout");
   const Gate1Launch a = make_gate1_launch(g, r);
   const dim3 grid(gate1_grid(a));
   if (dag) G1_D_SWITCH(g.d, hipLaunchKernelGGL((k_gate1<D, true>), grid, dim3(kBlock), 0, s, src, psi, U, a))
@@ -159,6 +160,7 @@ int launch_gate1(const Geometry &g, int r, bool dag, const float2 *U, const floa
 
 int launch_gate1_adj(const Geometry &g, int r, const float2 *U, const float2 *A, float2 *phi, float2 *lam,
                      double *partial, hipStream_t s) {
+  if (g.half) return set_error(FOCK_ERR_UNSUPPORTED, "squeezers in the parity-halved layout");
   const Gate1Launch a = make_gate1_launch(g, r);
   const dim3 grid(gate1_grid(a));
   G1_D_SWITCH(g.d, hipLaunchKernelGGL(k_gate1_adj<D>, grid, dim3(kBlock), 0, s, phi, lam, U, A, partial, a))
@@ -168,6 +170,7 @@ int launch_gate1_adj(const Geometry &g, int r, const float2 *U, const float2 *A,
 
 int launch_pool1(const Geometry &g, int r, const float2 *A, const float2 *psi, const float2 *hpsi, double *partial,
                  int *nblocks, hipStream_t s) {
+  if (g.half) return set_error(FOCK_ERR_UNSUPPORTED, "squeezers in the parity-halved layout");
   const Gate1Launch a = make_gate1_launch(g, r);
   *nblocks = gate1_grid(a);
   const dim3 grid(*nblocks);

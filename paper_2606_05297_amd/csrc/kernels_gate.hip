@@ -12,6 +12,7 @@
 // lam = lambda_k, accumulate Re <lam| A phi> over the fiber, then apply
 // O_k^+ = exp(-theta A) to both phi and lam.  A is block diagonal with the
 // same blocks, so the gradient term is fiber-local and fused with the update.
+#include <algorithm>
 #include <cstring>
 
 #include "gate_kernels.h"
@@ -134,6 +135,7 @@ static GateLaunch make_gate_launch(const Geometry &g, int i, int j) {
 GateLaunch gate_launch_params(const Geometry &g, int i, int j) { return make_gate_launch(g, i, j); }
 
 int gate_blocks_count(const Geometry &g, int i) {
+  if (g.half && i == g.L - 2) return half_top_blocks(g);
   const uint32_t nf = g.n_amp / (uint32_t)(g.d * g.d);
   int fpb = 64;
   FOCK_D_SWITCH(g.d, fpb = launch_fibers_per_block_d<D>(i, nf));
@@ -142,11 +144,13 @@ int gate_blocks_count(const Geometry &g, int i) {
 
 int gate_blocks_max(const Geometry &g) {
   const int a = gate_blocks_count(g, 0), b = gate_blocks_count(g, 1);
-  return a > b ? a : b;
+  const int c = g.half ? gate_blocks_count(g, g.L - 2) : 0;
+  return std::max(a, std::max(b, c));
 }
 
 int launch_gate(const Geometry &g, int i, int j, int kind, bool dag, const float2 *U, const float2 *src, float2 *psi,
                 hipStream_t s) {
+  if (g.half && j == g.L - 1) return launch_gate_half(g, i, j, kind, dag, U, src, psi, s);
   const GateLaunch gl = make_gate_launch(g, i, j);
   const int G = gate_blocks_count(g, i);
   FOCK_D_SWITCH(g.d, gate_launch_d<D>(gl, i, kind, dag, U, src, psi, G, s));
@@ -156,6 +160,7 @@ int launch_gate(const Geometry &g, int i, int j, int kind, bool dag, const float
 
 int launch_gate_adj(const Geometry &g, int i, int j, int kind, const float2 *U, const float2 *A, float2 *phi,
                     float2 *lam, double *partial, hipStream_t s, bool write_phi) {
+  if (g.half && j == g.L - 1) return launch_gate_adj_half(g, i, j, kind, U, A, phi, lam, partial, s, write_phi);
   const GateLaunch gl = make_gate_launch(g, i, j);
   const int G = gate_blocks_count(g, i);
   FOCK_D_SWITCH(g.d, adj_launch_d<D>(gl, i, kind, U, A, phi, lam, partial, G, write_phi, s));
@@ -183,6 +188,7 @@ DiagLaunch diag_launch_params(const Geometry &g, int r, int type) { return make_
 
 int launch_diag(const Geometry &g, int r, int type, bool dag, const float2 *ph, const float2 *src, float2 *psi,
                 hipStream_t s) {
+  if (g.half) return set_error(FOCK_ERR_UNSUPPORTED, "phase gates in the parity-halved layout");
   const DiagLaunch a = make_diag_launch(g, r, type);
   const int G = diag_blocks_count(g);
   if (dag) {
@@ -196,6 +202,7 @@ int launch_diag(const Geometry &g, int r, int type, bool dag, const float2 *ph, 
 
 int launch_diag_adj(const Geometry &g, int r, int type, const float2 *ph, float2 *phi, float2 *lam,
                     double *partial, hipStream_t s, bool write_phi) {
+  if (g.half) return set_error(FOCK_ERR_UNSUPPORTED, "phase gates in the parity-halved layout");
   const DiagLaunch a = make_diag_launch(g, r, type);
   const int G = diag_blocks_count(g);
   if (write_phi) {
@@ -228,6 +235,7 @@ DiagRun diag_run_params(const Geometry &g, const fock_op_t *ops, int k0, int k1)
 
 int launch_diag_run(const Geometry &g, const DiagRun &a, bool dag, const float2 *U, const float2 *src, float2 *psi,
                     hipStream_t s) {
+  if (g.half) return set_error(FOCK_ERR_UNSUPPORTED, "phase gates in the parity-halved layout");
   if (a.ng < 1 || a.ng > kMaxDiagRun) return set_error(FOCK_ERR_ARG, "diagonal run of %d gates", a.ng);
   const int G = diag_blocks_count(g);
   if (dag) {
@@ -241,6 +249,7 @@ int launch_diag_run(const Geometry &g, const DiagRun &a, bool dag, const float2 
 
 int launch_diag_run_adj(const Geometry &g, const DiagRun &a, const float2 *U, float2 *phi, float2 *lam,
                         double *partial, int rs, hipStream_t s, bool write_phi) {
+  if (g.half) return set_error(FOCK_ERR_UNSUPPORTED, "phase gates in the parity-halved layout");
   if (a.ng < 1 || a.ng > kMaxDiagRun) return set_error(FOCK_ERR_ARG, "diagonal run of %d gates", a.ng);
   const int G = diag_blocks_count(g);
   if (G > rs) return set_error(FOCK_ERR_SIZE, "diagonal run: %d partials per gate exceed the row stride %d", G, rs);

@@ -30,11 +30,19 @@ struct Ctx {
 };
 
 int check_geometry(int L, int d, uint32_t *namp);
+// check_ham takes full d^L states only; check_ham_layout also the parity-halved
+// layout (namp = d^L / 2 then).
 int check_ham(const fock_ham_t *h, uint32_t *namp);
+int check_ham_layout(const fock_ham_t *h, uint32_t *namp);
+bool half_layout_op_ok(const fock_op_t &op, int L);
+// Switch of the ADAPT driver's automatic parity-halved layout (FOCK_SECTOR_*),
+// and whether it applies to this chain, pool and warm-up layer.
+int sector_layout_mode();
+bool half_layout_wanted(const fock_ham_t &h, const fock_op_t *pool, int P, const fock_op_t *ops, int n);
 int check_op(const fock_op_t &op, int L);
 int check_ptr(const void *p, const char *name);
 HamArgs make_ham_args(const fock_ham_t &h);
-Layout make_layout(uint32_t namp, int L, int d, int P, int n);
+Layout make_layout(uint32_t namp, int L, int d, int P, int n, int half = 0);
 int make_ctx(const fock_ham_t &ham, uint32_t namp, int P, int n, void *ws, size_t ws_bytes, hipStream_t s, Ctx *c);
 // Attach a store of nmax forward states to c if switched on and the device has
 // room; *owner receives the allocation to free (nullptr: no store).

@@ -47,6 +47,9 @@ constexpr int kColThreads = 512;
 constexpr int kRowThreads = 512;
 constexpr int kS4 = 4096;        // stride of mode 4 (amplitudes)
 
+// Row-pass pencils: (n5, n6, n7), or (n5, n6, m7) in the parity-halved layout.
+__host__ __device__ inline int slab_pencils(const HamArgs &h) { return h.half ? kPencils / 2 : kPencils; }
+
 __device__ __forceinline__ float dpp_from_left(float v) {  // lane i receives lane i - 1 (0 at a row start)
   return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x111, 0xF, 0xF, true));
 }
@@ -59,6 +62,13 @@ __device__ __forceinline__ void fma4(float4 &a, const float4 &v, float c) {
   a.y = fmaf(c, v.y, a.y);
   a.z = fmaf(c, v.z, a.z);
   a.w = fmaf(c, v.w, a.w);
+}
+// a += v with factor c_lo on the first amplitude (x, y) and c_hi on the second (z, w)
+__device__ __forceinline__ void fma4s(float4 &a, const float4 &v, float c_lo, float c_hi) {
+  a.x = fmaf(c_lo, v.x, a.x);
+  a.y = fmaf(c_lo, v.y, a.y);
+  a.z = fmaf(c_hi, v.z, a.z);
+  a.w = fmaf(c_hi, v.w, a.w);
 }
 __device__ __forceinline__ void fma2(float2 &a, const float2 &v, float c) {
   a.x = fmaf(c, v.x, a.x);
@@ -86,9 +96,20 @@ __device__ __forceinline__ Coef make_coef(const HamArgs &h) {
 // Column pass.  Thread t: l = t & 7 (amplitudes 2l, 2l+1 of the chunk), n4 =
 // (t >> 3) & 7, n5 = t >> 6; registers over n6.  A wavefront reads eight
 // 128-byte segments per load (one per n4).
-template <bool RING>
+//
+// HALF: the parity-halved layout, whose slices are m7 = 0..3 with n7 = 2 m7 + e
+// and e = (n0 + .. + n6 + sigma) mod 2 per amplitude.  Bonds (4,5) and (5,6)
+// keep the parity of n0..n6, so their neighbours sit in the same slice.  Bond
+// (6,7) moves n6 by one, so e flips: an amplitude with e = 0 (n7 = 2 m7) reads
+// its n7 + 1 neighbours in its own slice and its n7 - 1 neighbours in slice
+// m7 - 1; one with e = 1 reads n7 - 1 in its own slice and n7 + 1 in slice
+// m7 + 1.  e is fixed per (thread, register parity, float4 half), so each
+// push carries a per-lane factor that selects the terms of the right parity.
+template <bool RING, bool HALF>
 __global__ __launch_bounds__(kColThreads) void k_h8_col(const float4 *__restrict__ psi, float4 *__restrict__ tout,
                                                          HamArgs h) {
+  static_assert(!(RING && HALF), "the parity-halved layout is for open chains");
+  constexpr int NS = HALF ? 4 : 8;  // streamed slices
   __shared__ float4 sl[4096];  // [n6][n5][n4][l]
   const Coef C = make_coef(h);
   const int b = blockIdx.x;
@@ -111,20 +132,36 @@ __global__ __launch_bounds__(kColThreads) void k_h8_col(const float4 *__restrict
   const float dg45 = C.dg(n4) + C.dg(n5);
   // ring bond (0,7): n0 of the two amplitudes
   const int q0 = 2 * (l & 3), q1 = q0 + 1;
+  // HALF: per-lane factors for q = (register parity) ^ (float4 half): the
+  // amplitude has e = par ^ q.  fJ/fD weigh the in-slice (6,7) reads of n6 - 1
+  // and n6 + 1 (-J and Delta swap roles between e = 0 and e = 1), w1 / w0 keep
+  // only e = 1 (pushed into m7 - 1) resp. e = 0 (pushed into m7 + 1).
+  float fJ[2] = {0.f, 0.f}, fD[2] = {0.f, 0.f}, w0[2] = {0.f, 0.f}, w1[2] = {0.f, 0.f};
+  if constexpr (HALF) {
+    const int par = (octal_digit_parity((uint32_t)(16 * j + 2 * l)) + n4 + n5 + h.sector) & 1;
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const bool odd = (par ^ q) != 0;
+      fJ[q] = odd ? C.Dl : -C.J;
+      fD[q] = odd ? -C.J : C.Dl;
+      w1[q] = odd ? 1.f : 0.f;
+      w0[q] = odd ? 0.f : 1.f;
+    }
+  }
 
   float4 own[8], nxt[8];
   float4 acc[3][8];
 #pragma unroll
   for (int a = 0; a < 8; ++a) own[a] = src[(size_t)a * S6];
 #pragma unroll
-  for (int k = 0; k < 8; ++k) {
+  for (int k = 0; k < NS; ++k) {
     float4(&am)[8] = acc[(k + 2) % 3];  // slice k - 1
     float4(&a0)[8] = acc[k % 3];        // slice k
     float4(&ap)[8] = acc[(k + 1) % 3];  // slice k + 1
     if (k > 0) __syncthreads();
 #pragma unroll
     for (int a = 0; a < 8; ++a) sl[li(n4, n5, a)] = own[a];
-    if (k < 7) {
+    if (k < NS - 1) {
 #pragma unroll
       for (int a = 0; a < 8; ++a) nxt[a] = src[(size_t)a * S6 + (size_t)(k + 1) * S7];
     }
@@ -137,52 +174,91 @@ __global__ __launch_bounds__(kColThreads) void k_h8_col(const float4 *__restrict
     // (its second amplitude, 2l - 1) and l + 1 (its first, 2l + 2) of the same n4
     // bond (6,7) and the ring bond, pushed from slice k into k - 1 ...
     if (k > 0) {
-      const float u = C.up(k - 1);
+      if constexpr (HALF) {
+        // outputs with e = 1 of slice k - 1 (n7 = 2k - 1) read n7 + 1 = 2k here
+        const float u = __builtin_sqrtf((float)(2 * k));
 #pragma unroll
-      for (int a = 0; a < 8; ++a) {
-        if (a > 0) fma4(am[a], own[a - 1], -C.J * C.dn(a) * u);  // a6^+ a7: reads (n6 - 1, n7 + 1)
-        if (a < 7) fma4(am[a], own[a + 1], C.Dl * C.up(a) * u);  // a6 a7:   reads (n6 + 1, n7 + 1)
-        if constexpr (RING) {
-          // a0^+ a7 reads (n0 - 1, n7 + 1); a0 a7 reads (n0 + 1, n7 + 1)
-          const float h0 = -C.J * C.dn(q0) * u, h1 = -C.J * C.dn(q1) * u;
-          const float p0 = C.Dl * C.up(q0) * u, p1 = C.Dl * C.up(q1) * u;
-          const float lz = dpp_from_left(own[a].z), lw = dpp_from_left(own[a].w);
-          const float rx = dpp_from_right(own[a].x), ry = dpp_from_right(own[a].y);
-          am[a].x = fmaf(h0, lz, fmaf(p0, own[a].z, am[a].x));
-          am[a].y = fmaf(h0, lw, fmaf(p0, own[a].w, am[a].y));
-          am[a].z = fmaf(h1, own[a].x, fmaf(p1, rx, am[a].z));
-          am[a].w = fmaf(h1, own[a].y, fmaf(p1, ry, am[a].w));
+        for (int a = 0; a < 8; ++a) {
+          const int q = a & 1;
+          if (a > 0) fma4s(am[a], own[a - 1], -C.J * C.dn(a) * u * w1[q], -C.J * C.dn(a) * u * w1[q ^ 1]);
+          if (a < 7) fma4s(am[a], own[a + 1], C.Dl * C.up(a) * u * w1[q], C.Dl * C.up(a) * u * w1[q ^ 1]);
+        }
+      } else {
+        const float u = C.up(k - 1);
+#pragma unroll
+        for (int a = 0; a < 8; ++a) {
+          if (a > 0) fma4(am[a], own[a - 1], -C.J * C.dn(a) * u);  // a6^+ a7: reads (n6 - 1, n7 + 1)
+          if (a < 7) fma4(am[a], own[a + 1], C.Dl * C.up(a) * u);  // a6 a7:   reads (n6 + 1, n7 + 1)
+          if constexpr (RING) {
+            // a0^+ a7 reads (n0 - 1, n7 + 1); a0 a7 reads (n0 + 1, n7 + 1)
+            const float h0 = -C.J * C.dn(q0) * u, h1 = -C.J * C.dn(q1) * u;
+            const float p0 = C.Dl * C.up(q0) * u, p1 = C.Dl * C.up(q1) * u;
+            const float lz = dpp_from_left(own[a].z), lw = dpp_from_left(own[a].w);
+            const float rx = dpp_from_right(own[a].x), ry = dpp_from_right(own[a].y);
+            am[a].x = fmaf(h0, lz, fmaf(p0, own[a].z, am[a].x));
+            am[a].y = fmaf(h0, lw, fmaf(p0, own[a].w, am[a].y));
+            am[a].z = fmaf(h1, own[a].x, fmaf(p1, rx, am[a].z));
+            am[a].w = fmaf(h1, own[a].y, fmaf(p1, ry, am[a].w));
+          }
         }
       }
 #pragma unroll
       for (int a = 0; a < 8; ++a) dst[(size_t)a * S6 + (size_t)(k - 1) * S7] = am[a];
     }
     // ... and into k + 1
-    if (k < 7) {
-      const float dnx = C.dn(k + 1);
+    if (k < NS - 1) {
+      if constexpr (HALF) {
+        // outputs with e = 0 of slice k + 1 (n7 = 2k + 2) read n7 - 1 = 2k + 1 here
+        const float dnx = __builtin_sqrtf((float)(2 * k + 2));
 #pragma unroll
-      for (int a = 0; a < 8; ++a) {
-        ap[a] = make_float4(0.f, 0.f, 0.f, 0.f);
-        if (a < 7) fma4(ap[a], own[a + 1], -C.J * C.up(a) * dnx);  // a7^+ a6: reads (n6 + 1, n7 - 1)
-        if (a > 0) fma4(ap[a], own[a - 1], C.Dl * C.dn(a) * dnx);  // a6^+ a7^+: reads (n6 - 1, n7 - 1)
-        if constexpr (RING) {
-          // a7^+ a0 reads (n0 + 1, n7 - 1); a0^+ a7^+ reads (n0 - 1, n7 - 1)
-          const float h0 = -C.J * C.up(q0) * dnx, h1 = -C.J * C.up(q1) * dnx;
-          const float p0 = C.Dl * C.dn(q0) * dnx, p1 = C.Dl * C.dn(q1) * dnx;
-          const float lz = dpp_from_left(own[a].z), lw = dpp_from_left(own[a].w);
-          const float rx = dpp_from_right(own[a].x), ry = dpp_from_right(own[a].y);
-          ap[a].x = fmaf(h0, own[a].z, fmaf(p0, lz, ap[a].x));
-          ap[a].y = fmaf(h0, own[a].w, fmaf(p0, lw, ap[a].y));
-          ap[a].z = fmaf(h1, rx, fmaf(p1, own[a].x, ap[a].z));
-          ap[a].w = fmaf(h1, ry, fmaf(p1, own[a].y, ap[a].w));
+        for (int a = 0; a < 8; ++a) {
+          const int q = a & 1;
+          ap[a] = make_float4(0.f, 0.f, 0.f, 0.f);
+          if (a < 7) fma4s(ap[a], own[a + 1], -C.J * C.up(a) * dnx * w0[q], -C.J * C.up(a) * dnx * w0[q ^ 1]);
+          if (a > 0) fma4s(ap[a], own[a - 1], C.Dl * C.dn(a) * dnx * w0[q], C.Dl * C.dn(a) * dnx * w0[q ^ 1]);
+        }
+      } else {
+        const float dnx = C.dn(k + 1);
+#pragma unroll
+        for (int a = 0; a < 8; ++a) {
+          ap[a] = make_float4(0.f, 0.f, 0.f, 0.f);
+          if (a < 7) fma4(ap[a], own[a + 1], -C.J * C.up(a) * dnx);  // a7^+ a6: reads (n6 + 1, n7 - 1)
+          if (a > 0) fma4(ap[a], own[a - 1], C.Dl * C.dn(a) * dnx);  // a6^+ a7^+: reads (n6 - 1, n7 - 1)
+          if constexpr (RING) {
+            // a7^+ a0 reads (n0 + 1, n7 - 1); a0^+ a7^+ reads (n0 - 1, n7 - 1)
+            const float h0 = -C.J * C.up(q0) * dnx, h1 = -C.J * C.up(q1) * dnx;
+            const float p0 = C.Dl * C.dn(q0) * dnx, p1 = C.Dl * C.dn(q1) * dnx;
+            const float lz = dpp_from_left(own[a].z), lw = dpp_from_left(own[a].w);
+            const float rx = dpp_from_right(own[a].x), ry = dpp_from_right(own[a].y);
+            ap[a].x = fmaf(h0, own[a].z, fmaf(p0, lz, ap[a].x));
+            ap[a].y = fmaf(h0, own[a].w, fmaf(p0, lw, ap[a].y));
+            ap[a].z = fmaf(h1, rx, fmaf(p1, own[a].x, ap[a].z));
+            ap[a].w = fmaf(h1, ry, fmaf(p1, own[a].y, ap[a].w));
+          }
         }
       }
     }
-    // in-slice terms of slice k: on-site, bond (4,5), bond (5,6)
-    const float dgk = dg45 + C.dg(k);
+    // in-slice terms of slice k: on-site, bond (4,5), bond (5,6) (and, HALF,
+    // bond (6,7) within the slice: n7 = 2k reads 2k + 1 and n7 = 2k + 1 reads 2k)
+    if constexpr (HALF) {
+      const float r = __builtin_sqrtf((float)(2 * k + 1));
+      const float dge = C.dg(2 * k), dgo = C.dg(2 * k + 1);
+#pragma unroll
+      for (int a = 0; a < 8; ++a) {
+        const int q = a & 1;
+        const float dgl = dg45 + C.dg(a) + w0[q] * dge + w1[q] * dgo;
+        const float dgh = dg45 + C.dg(a) + w0[q ^ 1] * dge + w1[q ^ 1] * dgo;
+        fma4s(a0[a], own[a], dgl, dgh);
+        if (a > 0) fma4s(a0[a], own[a - 1], C.dn(a) * r * fJ[q], C.dn(a) * r * fJ[q ^ 1]);
+        if (a < 7) fma4s(a0[a], own[a + 1], C.up(a) * r * fD[q], C.up(a) * r * fD[q ^ 1]);
+      }
+    } else {
+      const float dgk = dg45 + C.dg(k);
+#pragma unroll
+      for (int a = 0; a < 8; ++a) fma4(a0[a], own[a], dgk + C.dg(a));
+    }
 #pragma unroll
     for (int a = 0; a < 8; ++a) {
-      fma4(a0[a], own[a], dgk + C.dg(a));
       const int o6 = a * 64 * 8;
       fma4(a0[a], sl[oA + o6], cA);
       fma4(a0[a], sl[oB + o6], cB);
@@ -203,10 +279,10 @@ __global__ __launch_bounds__(kColThreads) void k_h8_col(const float4 *__restrict
     }
 #pragma unroll
     for (int a = 0; a < 8; ++a)
-      if (k < 7) own[a] = nxt[a];
+      if (k < NS - 1) own[a] = nxt[a];
   }
 #pragma unroll
-  for (int a = 0; a < 8; ++a) dst[(size_t)a * S6 + (size_t)7 * S7] = acc[7 % 3][a];
+  for (int a = 0; a < 8; ++a) dst[(size_t)a * S6 + (size_t)(NS - 1) * S7] = acc[(NS - 1) % 3][a];
 }
 
 // Row pass.  Thread t: n0 = t & 7, n1 = (t >> 3) & 7, n2 = t >> 6; registers
@@ -217,7 +293,7 @@ __global__ __launch_bounds__(kRowThreads) void k_h8_row(const float2 *__restrict
   __shared__ double red[2 * kRowThreads / 64];
   const Coef C = make_coef(h);
   const int b = blockIdx.x;
-  const int p = (b & 7) * (kPencils / 8) + (b >> 3);  // XCD x takes the pencils with n7 = x
+  const int p = (b & 7) * (gridDim.x / 8) + (b >> 3);  // XCD x takes the pencils with n7 (m7) = x (x/2)
   const int t = threadIdx.x;
   const int n0 = t & 7, n1 = (t >> 3) & 7, n2 = t >> 6;
   const size_t base = (size_t)t + (size_t)p * 8 * kS4;
@@ -474,7 +550,7 @@ __global__ __launch_bounds__(kRowThreads) void k_pool8_row(const float2 *__restr
   for (int e = t; e < (kRowThreads / 64) * kMaxSlots; e += kRowThreads) (&red[0][0])[e] = 0.0;
   const Coef C = make_coef(hcoef);
   const int b = blockIdx.x;
-  const int p = (b & 7) * (kPencils / 8) + (b >> 3);
+  const int p = (b & 7) * (gridDim.x / 8) + (b >> 3);
   const int n0 = t & 7, n1 = (t >> 3) & 7, n2 = t >> 6;
   const int n5 = p & 7, n6 = (p >> 3) & 7, n7 = p >> 6;
   const size_t base = (size_t)t + (size_t)p * 8 * kS4;
@@ -597,7 +673,14 @@ __global__ __launch_bounds__(kRowThreads) void k_pool8_row(const float2 *__restr
 // 2l + 1 of the chunk, registers n6.  The streamed pairs couple slices k and
 // k + 1 through the prefetched slice k + 1 (psi and H psi), so no registers
 // of slice k - 1 are kept.
-template <bool RING>
+//
+// HALF (parity-halved layout, slices m7 with n7 = 2 m7 + e): for pair (6,7)
+// an amplitude with e = 0 finds its n7 + 1 neighbours in its own slice and its
+// n7 - 1 neighbours in slice m7 - 1; one with e = 1 finds n7 - 1 in its own
+// slice and n7 + 1 in slice m7 + 1.  Step k scores the own-slice terms of
+// slice k and the cross terms between slices k and k + 1 (e = 1 amplitudes of
+// slice k, e = 0 amplitudes of slice k + 1); per-lane 0/1 factors pick them.
+template <bool RING, bool HALF>
 __global__ __launch_bounds__(kColThreads) void k_pool8_col(const float4 *__restrict__ psi,
                                                            const float4 *__restrict__ hpsi,
                                                            double *__restrict__ partial, SlabPool sp, HamArgs hcoef) {
@@ -616,6 +699,17 @@ __global__ __launch_bounds__(kColThreads) void k_pool8_col(const float4 *__restr
   const float q0 = (float)(2 * (l & 3)), q1 = q0 + 1.f;  // n0 of the two amplitudes
   const int iq0 = 2 * (l & 3), iq1 = iq0 + 1;
   const float2 z = make_float2(0.f, 0.f);
+  static_assert(!(RING && HALF), "the parity-halved layout is for open chains");
+  constexpr int NS = HALF ? 4 : 8;  // streamed slices
+  float w0[2] = {0.f, 0.f}, w1[2] = {0.f, 0.f};  // HALF: e = par ^ q selects (q = register parity ^ half)
+  if constexpr (HALF) {
+    const int par = (octal_digit_parity((uint32_t)(16 * j + 2 * l)) + n4 + n5 + hcoef.sector) & 1;
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      w1[q] = (par ^ q) ? 1.f : 0.f;
+      w0[q] = 1.f - w1[q];
+    }
+  }
   PairSums S[4];
   float4 own[8], h[8], nxt[8], hn[8];
 #pragma unroll
@@ -625,11 +719,11 @@ __global__ __launch_bounds__(kColThreads) void k_pool8_col(const float4 *__restr
   }
   __syncthreads();
 #pragma unroll 1
-  for (int k = 0; k < 8; ++k) {
+  for (int k = 0; k < NS; ++k) {
     if (k > 0) __syncthreads();
 #pragma unroll
     for (int a = 0; a < 8; ++a) sl[li(n4, n5, a)] = own[a];
-    if (k < 7) {
+    if (k < NS - 1) {
 #pragma unroll
       for (int a = 0; a < 8; ++a) {
         nxt[a] = psi[base + (size_t)a * S6 + (size_t)(k + 1) * S7];
@@ -668,7 +762,44 @@ __global__ __launch_bounds__(kColThreads) void k_pool8_col(const float4 *__restr
                    cmul(cw2, hi2(vmp)), (float)n5, X, Y, Dh);
       }
     }
-    if (on67 && k < 7) {
+    if (HALF && on67) {
+      const bool X = want_x(sp, 6), Y = want_y(sp, 6), Dh = want_d(sp, 6);
+      const float r = __builtin_sqrtf((float)(2 * k + 1)), rx = __builtin_sqrtf((float)(2 * k + 2));
+#pragma unroll
+      for (int a = 0; a < 8; ++a) {
+        const float2 ml = lo2(own[a > 0 ? a - 1 : a]), mh = hi2(own[a > 0 ? a - 1 : a]);  // n6 - 1
+        const float2 pl = lo2(own[a < 7 ? a + 1 : a]), ph = hi2(own[a < 7 ? a + 1 : a]);  // n6 + 1
+        const float dn = C.dn(a), up = C.up(a);
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+          const int q = (a & 1) ^ e;
+          const float2 hv = e ? hi2(h[a]) : lo2(h[a]);
+          const float2 vm = e ? mh : ml, vp = e ? ph : pl;
+          // own slice: e = 0 reads (n6 -+ 1, n7 + 1) (u1, w1), e = 1 reads (n6 +- 1, n7 - 1) (u2, w2)
+          pair_terms(S[2], hv, cmul(w0[q] * dn * r, vm), cmul(w1[q] * up * r, vp), cmul(w0[q] * up * r, vp),
+                     cmul(w1[q] * dn * r, vm), (float)a, X, Y, Dh);
+        }
+      }
+      if (k < NS - 1) {
+#pragma unroll
+        for (int a = 0; a < 8; ++a) {
+          const float dn = C.dn(a), up = C.up(a);
+          const float4 xm = nxt[a > 0 ? a - 1 : a], xp = nxt[a < 7 ? a + 1 : a];
+          const float4 om = own[a > 0 ? a - 1 : a], op = own[a < 7 ? a + 1 : a];
+#pragma unroll
+          for (int e = 0; e < 2; ++e) {
+            const int q = (a & 1) ^ e;
+            // e = 1 of slice k (n7 = 2k + 1) reads slice k + 1 at n7 + 1: a6^+ a7, a6 a7
+            pair_terms(S[2], e ? hi2(h[a]) : lo2(h[a]), cmul(w1[q] * dn * rx, e ? hi2(xm) : lo2(xm)), z,
+                       cmul(w1[q] * up * rx, e ? hi2(xp) : lo2(xp)), z, (float)a, X, Y, Dh);
+            // e = 0 of slice k + 1 (n7 = 2k + 2) reads slice k at n7 - 1: a7^+ a6, a6^+ a7^+
+            pair_terms(S[2], e ? hi2(hn[a]) : lo2(hn[a]), z, cmul(w0[q] * up * rx, e ? hi2(op) : lo2(op)), z,
+                       cmul(w0[q] * dn * rx, e ? hi2(om) : lo2(om)), (float)a, X, Y, Dh);
+          }
+        }
+      }
+    }
+    if (!HALF && on67 && k < 7) {
       const bool X = want_x(sp, 6), Y = want_y(sp, 6), Dh = want_d(sp, 6);
 #pragma unroll
       for (int a = 0; a < 8; ++a) {
@@ -706,7 +837,7 @@ __global__ __launch_bounds__(kColThreads) void k_pool8_col(const float4 *__restr
                    Dh);
       }
     }
-    if (k < 7) {
+    if (k < NS - 1) {
 #pragma unroll
       for (int a = 0; a < 8; ++a) {
         own[a] = nxt[a];
@@ -716,7 +847,7 @@ __global__ __launch_bounds__(kColThreads) void k_pool8_col(const float4 *__restr
   }
 #pragma unroll
   for (int p4 = 0; p4 < 4; ++p4) pair_slots(red, sp, 4 + p4, S[p4]);
-  write_slots<kColThreads>(red, sp.nslots, partial + (size_t)(kPencils + j) * sp.nslots);
+  write_slots<kColThreads>(red, sp.nslots, partial + (size_t)(slab_pencils(hcoef) + j) * sp.nslots);
 }
 
 // Fused scoring, row shape: the row pass of H psi that also scores the pool
@@ -739,7 +870,7 @@ __global__ __launch_bounds__(kRowThreads) void k_h8_row_score(const float2 *__re
   for (int e = t; e < (kRowThreads / 64) * kMaxSlots; e += kRowThreads) (&red[0][0])[e] = 0.0;
   const Coef C = make_coef(h);
   const int b = blockIdx.x;
-  const int p = (b & 7) * (kPencils / 8) + (b >> 3);
+  const int p = (b & 7) * (gridDim.x / 8) + (b >> 3);
   const int n0 = t & 7, n1 = (t >> 3) & 7, n2 = t >> 6;
   const int n5 = p & 7, n6 = (p >> 3) & 7, n7 = p >> 6;
   const size_t base = (size_t)t + (size_t)p * 8 * kS4;
@@ -948,42 +1079,68 @@ __global__ __launch_bounds__(kRowThreads) void k_h8_row_score(const float2 *__re
 
 }  // namespace
 
-bool apply_h2_supported(const HamArgs &h) { return slab_stencil_ok(h.L, h.d); }
+bool apply_h2_supported(const HamArgs &h) {
+  return slab_stencil_ok(h.L, h.d) && (!h.half || (!h.periodic_wrap && (h.sector == 0 || h.sector == 1)));
+}
 
-// Partials written: 2 * kPencils doubles, columns (<psi|H psi>, <psi|psi>) per pencil.
-int apply_h2_blocks() { return kPencils; }
+// Partials written: 2 per pencil, columns (<psi|H psi>, <psi|psi>).
+int apply_h2_blocks(const HamArgs &h) { return slab_pencils(h); }
+
+static void launch_col(const HamArgs &h, const float2 *psi, float2 *hpsi, hipStream_t s) {
+  if (h.half)
+    hipLaunchKernelGGL((k_h8_col<false, true>), dim3(kCols), dim3(kColThreads), 0, s, (const float4 *)psi,
+                       (float4 *)hpsi, h);
+  else if (h.periodic_wrap)
+    hipLaunchKernelGGL((k_h8_col<true, false>), dim3(kCols), dim3(kColThreads), 0, s, (const float4 *)psi,
+                       (float4 *)hpsi, h);
+  else
+    hipLaunchKernelGGL((k_h8_col<false, false>), dim3(kCols), dim3(kColThreads), 0, s, (const float4 *)psi,
+                       (float4 *)hpsi, h);
+}
+
+static void launch_pool_col(const SlabPool &sp, const HamArgs &h, const float2 *psi, const float2 *hpsi,
+                            double *partial, hipStream_t s) {
+  if (h.half)
+    hipLaunchKernelGGL((k_pool8_col<false, true>), dim3(kCols), dim3(kColThreads), 0, s, (const float4 *)psi,
+                       (const float4 *)hpsi, partial, sp, h);
+  else if (h.periodic_wrap)
+    hipLaunchKernelGGL((k_pool8_col<true, false>), dim3(kCols), dim3(kColThreads), 0, s, (const float4 *)psi,
+                       (const float4 *)hpsi, partial, sp, h);
+  else
+    hipLaunchKernelGGL((k_pool8_col<false, false>), dim3(kCols), dim3(kColThreads), 0, s, (const float4 *)psi,
+                       (const float4 *)hpsi, partial, sp, h);
+}
 
 int launch_apply_h2(const HamArgs &h, const float2 *psi, float2 *hpsi, double *partial, int *nblocks,
                     hipStream_t s) {
   if (!apply_h2_supported(h)) return set_error(FOCK_ERR_UNSUPPORTED, "two-pass H psi needs L = 8, d = 8");
-  if (h.periodic_wrap)
-    hipLaunchKernelGGL(k_h8_col<true>, dim3(kCols), dim3(kColThreads), 0, s, (const float4 *)psi, (float4 *)hpsi, h);
-  else
-    hipLaunchKernelGGL(k_h8_col<false>, dim3(kCols), dim3(kColThreads), 0, s, (const float4 *)psi, (float4 *)hpsi, h);
-  hipLaunchKernelGGL(k_h8_row, dim3(kPencils), dim3(kRowThreads), 0, s, psi, hpsi, partial, h);
+  launch_col(h, psi, hpsi, s);
+  hipLaunchKernelGGL(k_h8_row, dim3(slab_pencils(h)), dim3(kRowThreads), 0, s, psi, hpsi, partial, h);
   FOCK_HIP(hipGetLastError());
-  *nblocks = apply_h2_blocks();
+  *nblocks = apply_h2_blocks(h);
   return FOCK_OK;
 }
 
-int pool_slab_blocks() { return kPencils + kCols; }
+int pool_slab_blocks(const HamArgs &h) { return slab_pencils(h) + kCols; }
+
+// The parity-halved layout has no stored n7, which the diagonal entries need.
+static int check_slab_pool(const SlabPool &sp, const HamArgs &h) {
+  if (sp.nslots < 1 || sp.nslots > kMaxSlots || sp.ndiag < 0 || sp.ndiag > kSlabDiag)
+    return set_error(FOCK_ERR_ARG, "slab pool: %d slots, %d diagonal entries", sp.nslots, sp.ndiag);
+  if (h.half && sp.ndiag > 0)
+    return set_error(FOCK_ERR_UNSUPPORTED, "diagonal pool entries in the parity-halved layout");
+  return FOCK_OK;
+}
 
 int launch_score_slab(const SlabPool &sp, const HamArgs &h, const float2 *psi, float2 *hpsi, double *hpart,
                       double *ppart, hipStream_t s) {
   if (!apply_h2_supported(h)) return set_error(FOCK_ERR_UNSUPPORTED, "fused scoring needs L = 8, d = 8");
-  if (sp.nslots < 1 || sp.nslots > kMaxSlots || sp.ndiag < 0 || sp.ndiag > kSlabDiag)
-    return set_error(FOCK_ERR_ARG, "slab pool: %d slots, %d diagonal entries", sp.nslots, sp.ndiag);
-  if (h.periodic_wrap)
-    hipLaunchKernelGGL(k_h8_col<true>, dim3(kCols), dim3(kColThreads), 0, s, (const float4 *)psi, (float4 *)hpsi, h);
-  else
-    hipLaunchKernelGGL(k_h8_col<false>, dim3(kCols), dim3(kColThreads), 0, s, (const float4 *)psi, (float4 *)hpsi, h);
-  hipLaunchKernelGGL(k_h8_row_score, dim3(kPencils), dim3(kRowThreads), 0, s, psi, hpsi, hpart, ppart, sp, h);
-  if (h.periodic_wrap)
-    hipLaunchKernelGGL(k_pool8_col<true>, dim3(kCols), dim3(kColThreads), 0, s, (const float4 *)psi,
-                       (const float4 *)hpsi, ppart, sp, h);
-  else
-    hipLaunchKernelGGL(k_pool8_col<false>, dim3(kCols), dim3(kColThreads), 0, s, (const float4 *)psi,
-                       (const float4 *)hpsi, ppart, sp, h);
+  int rc = check_slab_pool(sp, h);
+  if (rc) return rc;
+  launch_col(h, psi, hpsi, s);
+  hipLaunchKernelGGL(k_h8_row_score, dim3(slab_pencils(h)), dim3(kRowThreads), 0, s, psi, hpsi, hpart, ppart, sp,
+                     h);
+  launch_pool_col(sp, h, psi, hpsi, ppart, s);
   FOCK_HIP(hipGetLastError());
   return FOCK_OK;
 }
@@ -991,17 +1148,12 @@ int launch_score_slab(const SlabPool &sp, const HamArgs &h, const float2 *psi, f
 int launch_pool_slab(const SlabPool &sp, const HamArgs &h, const float2 *psi, const float2 *hpsi, double *partial,
                      int *nblocks, hipStream_t s) {
   if (!apply_h2_supported(h)) return set_error(FOCK_ERR_UNSUPPORTED, "slab pool scoring needs L = 8, d = 8");
-  if (sp.nslots < 1 || sp.nslots > kMaxSlots || sp.ndiag < 0 || sp.ndiag > kSlabDiag)
-    return set_error(FOCK_ERR_ARG, "slab pool: %d slots, %d diagonal entries", sp.nslots, sp.ndiag);
-  hipLaunchKernelGGL(k_pool8_row, dim3(kPencils), dim3(kRowThreads), 0, s, psi, hpsi, partial, sp, h);
-  if (h.periodic_wrap)
-    hipLaunchKernelGGL(k_pool8_col<true>, dim3(kCols), dim3(kColThreads), 0, s, (const float4 *)psi,
-                       (const float4 *)hpsi, partial, sp, h);
-  else
-    hipLaunchKernelGGL(k_pool8_col<false>, dim3(kCols), dim3(kColThreads), 0, s, (const float4 *)psi,
-                       (const float4 *)hpsi, partial, sp, h);
+  int rc = check_slab_pool(sp, h);
+  if (rc) return rc;
+  hipLaunchKernelGGL(k_pool8_row, dim3(slab_pencils(h)), dim3(kRowThreads), 0, s, psi, hpsi, partial, sp, h);
+  launch_pool_col(sp, h, psi, hpsi, partial, s);
   FOCK_HIP(hipGetLastError());
-  *nblocks = pool_slab_blocks();
+  *nblocks = pool_slab_blocks(h);
   return FOCK_OK;
 }
 

@@ -26,7 +26,7 @@ K_SCORE = 9
 
 
 class Ham(C.Structure):
-    _fields_ = [("L", C.c_int32), ("d", C.c_int32), ("periodic", C.c_int32), ("reserved", C.c_int32),
+    _fields_ = [("L", C.c_int32), ("d", C.c_int32), ("periodic", C.c_int32), ("layout", C.c_int32),
                 ("J", C.c_double), ("U", C.c_double), ("mu", C.c_double), ("Delta", C.c_double),
                 ("K", C.c_double)]
 
@@ -111,6 +111,10 @@ def load(path: str = LIB_PATH):
     L.adapt_step_select.argtypes = [vp, C.POINTER(AdaptReport)]
     L.adapt_state_store.argtypes = [vp, ip]
     L.fock_set_state_store.argtypes = [C.c_int]
+    L.fock_set_sector_layout.argtypes = [C.c_int]
+    L.fock_sector_pack.argtypes = [C.c_int, C.c_int, C.c_int, vp, vp, vp]
+    L.fock_sector_unpack.argtypes = [C.c_int, C.c_int, C.c_int, vp, vp, vp]
+    L.adapt_layout.argtypes = [vp, ip]
     L.adapt_step_finish.argtypes = [vp, C.POINTER(AdaptReport)]
     L.adapt_warm_report.argtypes = [vp, C.POINTER(AdaptReport)]
     L.adapt_get_ansatz.argtypes = [vp, C.POINTER(Op), dp, C.c_int, ip]
@@ -159,8 +163,21 @@ def last_error() -> str:
 
 # ---------------------------------------------------------------- marshalling helpers
 
-def ham(L, d, periodic=False, J=1.0, U=0.0, mu=0.0, Delta=0.0, K=0.0) -> Ham:
-    return Ham(int(L), int(d), int(bool(periodic)), 0, float(J), float(U), float(mu), float(Delta), float(K))
+LAYOUT_FULL, LAYOUT_EVEN, LAYOUT_ODD = 0, 1, 2
+
+
+def ham(L, d, periodic=False, J=1.0, U=0.0, mu=0.0, Delta=0.0, K=0.0, layout=LAYOUT_FULL) -> Ham:
+    """Hamiltonian record; layout says how the state buffers of a call hold psi
+    (LAYOUT_FULL: d^L amplitudes; LAYOUT_EVEN / LAYOUT_ODD: the parity-halved
+    layout of a state of that total parity, d^L / 2 amplitudes)."""
+    return Ham(int(L), int(d), int(bool(periodic)), int(layout), float(J), float(U), float(mu), float(Delta),
+               float(K))
+
+
+def n_amplitudes(h: Ham) -> int:
+    """Amplitudes of one state buffer of a call on h."""
+    n = int(h.d) ** int(h.L)
+    return n // 2 if int(h.layout) != LAYOUT_FULL else n
 
 
 def ham_from(cfg: dict) -> Ham:
@@ -201,11 +218,12 @@ def workspace(h: Ham, n_pool: int = 0, n_ops: int = 0, device="cuda"):
     return torch.empty(workspace_bytes(h, n_pool, n_ops), dtype=torch.uint8, device=device)
 
 
-def _state_arg(t, L_, d, name, dtype="c64"):
+def _state_arg(t, L_, d, name, dtype="c64", layout=LAYOUT_FULL):
     """Reject a state tensor the kernels cannot take: not a contiguous complex64
     (complex128 for the FP64 driver) tensor on the current GPU, or not holding
-    exactly d^L amplitudes.  Raised before any launch, so a wrong buffer never
-    reaches a kernel that would read or write past it."""
+    exactly d^L amplitudes (d^L / 2 in the parity-halved layouts).  Raised before
+    any launch, so a wrong buffer never reaches a kernel that would read or
+    write past it."""
     import torch
     want = torch.complex64 if dtype == "c64" else torch.complex128
     if not isinstance(t, torch.Tensor):
@@ -214,6 +232,10 @@ def _state_arg(t, L_, d, name, dtype="c64"):
         raise FockError(-1, f"{name} must be a contiguous {want} tensor (got {t.dtype}, "
                             f"contiguous={t.is_contiguous()})")
     n = int(d) ** int(L_)
+    if int(layout) != LAYOUT_FULL:
+        n //= 2
+        if t.numel() != n:
+            raise FockError(-2, f"{name} must hold d^L / 2 = {n} amplitudes (parity-halved layout), got {t.numel()}")
     if t.numel() != n:
         raise FockError(-2, f"{name} must hold d^L = {d}^{L_} = {n} amplitudes, got {t.numel()}")
     if not t.is_cuda:
@@ -240,8 +262,8 @@ def _disjoint(a, b, na, nb):
 def apply_H(h: Ham, psi, hpsi, ws, energy=True, stream=None):
     """hpsi = H psi; returns (<psi|H|psi>, <psi|psi>) when energy is True."""
     L = load()
-    _state_arg(psi, h.L, h.d, "psi")
-    _state_arg(hpsi, h.L, h.d, "hpsi")
+    _state_arg(psi, h.L, h.d, "psi", layout=h.layout)
+    _state_arg(hpsi, h.L, h.d, "hpsi", layout=h.layout)
     _disjoint(psi, hpsi, "psi", "hpsi")
     _ws_arg(ws)
     E, n2 = C.c_double(0), C.c_double(0)
@@ -255,8 +277,8 @@ def apply_H_noalloc(h: Ham, psi, hpsi, res=None, stream=None):
     CUDA float64 tensor of 2 entries receiving (<psi|H|psi>, <psi|psi>) on the
     device, without a host synchronisation."""
     L = load()
-    _state_arg(psi, h.L, h.d, "psi")
-    _state_arg(hpsi, h.L, h.d, "hpsi")
+    _state_arg(psi, h.L, h.d, "psi", layout=h.layout)
+    _state_arg(hpsi, h.L, h.d, "hpsi", layout=h.layout)
     _disjoint(psi, hpsi, "psi", "hpsi")
     if res is not None:
         import torch
@@ -268,6 +290,40 @@ def apply_H_noalloc(h: Ham, psi, hpsi, res=None, stream=None):
 
 
 STORE_OFF, STORE_ON, STORE_AUTO = 0, 1, 2
+SECTOR_OFF, SECTOR_AUTO = 0, 1
+
+
+def set_sector_layout(mode: int):
+    """Parity-halved states in ADAPT drivers created afterwards
+    (fock_set_sector_layout): SECTOR_OFF or SECTOR_AUTO (the default)."""
+    _check(load().fock_set_sector_layout(int(mode)))
+
+
+def get_sector_layout() -> int:
+    return int(load().fock_get_sector_layout())
+
+
+def _sector_bufs(L_, d, layout, full, half):
+    if int(layout) not in (LAYOUT_EVEN, LAYOUT_ODD):
+        raise FockError(-1, f"layout must be LAYOUT_EVEN or LAYOUT_ODD, got {layout}")
+    _state_arg(full, L_, d, "full")
+    _state_arg(half, L_, d, "half", layout=layout)
+    _disjoint(full, half, "full", "half")
+
+
+def sector_pack(L_, d, layout, full, half, stream=None):
+    """half = the stored amplitudes of the full state in the parity-halved
+    layout (fock_sector_pack)."""
+    _sector_bufs(L_, d, layout, full, half)
+    _check(load().fock_sector_pack(int(L_), int(d), int(layout), _ptr(full), _ptr(half), _stream(stream)))
+
+
+def sector_unpack(L_, d, layout, half, full, stream=None):
+    """full = the d^L state of a parity-halved one, zero outside its sector
+    (fock_sector_unpack)."""
+    _sector_bufs(L_, d, layout, full, half)
+    _check(load().fock_sector_unpack(int(L_), int(d), int(layout), _ptr(half), _ptr(full), _stream(stream)))
+
 
 
 def set_state_store(mode: int):
@@ -308,8 +364,8 @@ def apply_gate2(L_, d, o, theta, psi, ws, adjoint=False, stream=None):
 
 def pool_grads(h: Ham, pool, psi, hpsi, ws, stream=None) -> np.ndarray:
     L = load()
-    _state_arg(psi, h.L, h.d, "psi")
-    _state_arg(hpsi, h.L, h.d, "hpsi")
+    _state_arg(psi, h.L, h.d, "psi", layout=h.layout)
+    _state_arg(hpsi, h.L, h.d, "hpsi", layout=h.layout)
     _ws_arg(ws)
     P = len(pool)
     out = np.zeros(P, dtype=np.float64)
@@ -323,7 +379,7 @@ def energy_grad_adjoint(h: Ham, ops, theta, psi0, psi_work, lam_work, ws, grad=T
     L = load()
     n = len(ops)
     for t, nm in ((psi0, "psi0"), (psi_work, "psi_work"), (lam_work, "lam_work")):
-        _state_arg(t, h.L, h.d, nm)
+        _state_arg(t, h.L, h.d, nm, layout=h.layout)
     _disjoint(psi0, psi_work, "psi0", "psi_work")
     _disjoint(psi0, lam_work, "psi0", "lam_work")
     _disjoint(psi_work, lam_work, "psi_work", "lam_work")
@@ -344,8 +400,8 @@ def score(h: Ham, pool, psi, hpsi, ws, stream=None):
     """hpsi = H psi and the pool gradients in one call (fock_score, fused where
     the pool allows it); returns (grads, <psi|H|psi>, <psi|psi>)."""
     L = load()
-    _state_arg(psi, h.L, h.d, "psi")
-    _state_arg(hpsi, h.L, h.d, "hpsi")
+    _state_arg(psi, h.L, h.d, "psi", layout=h.layout)
+    _state_arg(hpsi, h.L, h.d, "hpsi", layout=h.layout)
     _disjoint(psi, hpsi, "psi", "hpsi")
     _ws_arg(ws)
     P = len(pool)
@@ -362,8 +418,8 @@ def adjoint_sweep(h: Ham, ops, theta, psi_work, lam_work, norm2, ws, stream=None
     ops/theta (both buffers are overwritten); norm2 is that call's <psi|psi>."""
     L = load()
     n = len(ops)
-    _state_arg(psi_work, h.L, h.d, "psi_work")
-    _state_arg(lam_work, h.L, h.d, "lam_work")
+    _state_arg(psi_work, h.L, h.d, "psi_work", layout=h.layout)
+    _state_arg(lam_work, h.L, h.d, "lam_work", layout=h.layout)
     _disjoint(psi_work, lam_work, "psi_work", "lam_work")
     _ws_arg(ws)
     th = np.ascontiguousarray(theta, dtype=np.float64)
@@ -460,6 +516,12 @@ class Adapt:
         r = AdaptReport()
         _check(self._L.adapt_step_finish(self._st, C.byref(r)))
         return r.as_dict()
+
+    def layout(self) -> int:
+        """Layout the run keeps its states in (LAYOUT_FULL, LAYOUT_EVEN or LAYOUT_ODD)."""
+        n = C.c_int(0)
+        _check(self._L.adapt_layout(self._st, C.byref(n)))
+        return n.value
 
     def state_store(self) -> int:
         """Forward states this run keeps for its gradient evaluations (0: none)."""

@@ -337,3 +337,31 @@ def test_state_store_switch():
         finally:
             lib.set_state_store(lib.STORE_AUTO)
     assert lib.get_state_store() == lib.STORE_AUTO
+
+
+def test_sector_layout_switch_and_argument_checks():
+    """The ADAPT sector switch defaults to AUTO and takes only OFF and AUTO; the
+    layout field of the Hamiltonian record and the conversions reject bad
+    values before any device work (null pointers included)."""
+    L = lib.load()
+    assert lib.get_sector_layout() == lib.SECTOR_AUTO
+    assert L.fock_set_sector_layout(2) == -1 and "AUTO" in lib.last_error()
+    lib.set_sector_layout(lib.SECTOR_OFF)
+    try:
+        assert lib.get_sector_layout() == lib.SECTOR_OFF
+    finally:
+        lib.set_sector_layout(lib.SECTOR_AUTO)
+    assert lib.get_sector_layout() == lib.SECTOR_AUTO
+    nb = C.c_size_t(0)
+    # layout outside {0, 1, 2}; halved layout off the supported chains
+    for h in (lib.ham(8, 8, layout=3), lib.ham(8, 6, layout=1), lib.ham(8, 8, periodic=True, layout=2),
+              lib.ham(6, 8, layout=1)):
+        assert L.fock_workspace_bytes(C.byref(h), 0, 0, C.byref(nb)) in (-1, -3)
+    h = lib.ham(8, 8, layout=lib.LAYOUT_EVEN)
+    assert L.fock_workspace_bytes(C.byref(h), 28, 20, C.byref(nb)) == 0 and nb.value > 0
+    # calls that take full states only
+    assert L.fock_apply_H_noalloc(C.byref(h), None, None, None, None) in (-1, -3)
+    # conversions: d, layout and pointers checked first
+    assert L.fock_sector_pack(8, 6, 1, None, None, None) == -3
+    assert L.fock_sector_pack(8, 8, 0, None, None, None) == -1
+    assert L.fock_sector_unpack(8, 8, 1, None, None, None) == -1

@@ -257,15 +257,17 @@ BENCH_STEPS = 20  # bench.py's default --steps: the timed trajectory is this one
 
 def test_adapt_kitaev_kerr_l8_d8_benchmark_trajectory_replay():
     """The benchmark's run (Kitaev-Kerr L=8 d=8 from the vacuum, 20 ADAPT
-    steps, adjoint gradients, inverse Hessian recycled): every step lowers the
-    energy, every step's selection lies in the tie band of the pool gradients
-    the GPU reported, and after steps 5, 10, 15 and 20 the oracle re-evaluates
-    the GPU's own ansatz and angles in FP64 (|dE| <= 1e-5 |E|)."""
+    steps, adjoint gradients, inverse Hessian recycled, parity-halved states):
+    every step lowers the energy, every step's selection lies in the tie band
+    of the pool gradients the GPU reported, and after steps 5, 10, 15 and 20
+    the oracle re-evaluates the GPU's own ansatz and angles in FP64
+    (|dE| <= 1e-5 |E|)."""
     c = W.config("kk_l8_d8")
     ho, hl = oham(c), lib.ham_from(c)
     psi0 = O.fock_state(8, 8, c["occ"])
     say(f"adapt kk_l8_d8 {BENCH_STEPS} steps, Hessian recycling")
     ad = lib.Adapt(hl, c["pool"], dev(psi0), max_iters=c["max_iters"], recycle_hessian=True)
+    assert ad.layout() == lib.LAYOUT_EVEN  # the vacuum is even: the run keeps parity-halved states
     reps, checks = [], {}
     for s in range(1, BENCH_STEPS + 1):
         reps.append(ad.step())
