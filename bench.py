@@ -6,7 +6,11 @@
 A step is one full ADAPT iteration on the device path: pool scoring (H psi and
 all 28 pool gradients), selection, append, and BFGS re-optimisation of all
 angles with energy + adjoint-gradient evaluations (gate build, forward gates,
-H psi, fused reverse sweep).  W warm-up steps run on a separate ADAPT instance;
+H psi, fused reverse sweep).  The vacuum is even and every pool generator keeps
+the total parity, so the driver keeps its states in the parity-halved layout
+(the top mode's level follows from the other modes' parity: 8,388,608 stored
+amplitudes); --full-layout runs the whole benchmark on the full tensor, and
+"variants" also reports the default run in the full layout.  W warm-up steps run on a separate ADAPT instance;
 the K timed steps are steps 1..K of a fresh run from the vacuum.  Per-kernel
 durations come from HIP events recorded on the launch stream inside the timed
 region, around one launch in --prof-sample (default 4) of each kernel family:
@@ -178,6 +182,8 @@ def main():
                     help="start every BFGS from the scaled identity instead of the previous inverse Hessian")
     ap.add_argument("--no-variants", action="store_true", help="skip the FD-gradient and Hessian-recycling lines")
     ap.add_argument("--no-warm-start", action="store_true", help="skip the learned warm-start leg")
+    ap.add_argument("--full-layout", action="store_true",
+                    help="keep the ADAPT states in the full d^L layout (parity-halved layout off)")
     ap.add_argument("--prof-sample", type=int, default=4,
                     help="time one launch in this many per kernel family with HIP events (1: every launch)")
     ap.add_argument("--gate-fusion", type=int, choices=[0, 1, 2], default=None,
@@ -197,6 +203,8 @@ def main():
     torch.cuda.set_device(0)
     if args.gate_fusion is not None:
         lib.set_gate_fusion(args.gate_fusion)
+    if args.full_layout:
+        lib.set_sector_layout(lib.SECTOR_OFF)
     cfg = W.config("kk_l8_d8")
     hl = lib.ham_from(cfg)
     n = cfg["d"] ** cfg["L"]
@@ -211,6 +219,10 @@ def main():
             ad.step()
         ad.close()
     ad = lib.Adapt(hl, cfg["pool"], psi0, max_iters=cfg["max_iters"], grad_mode=gm, recycle_hessian=rh)
+    layout = ad.layout()
+    layout_desc = {lib.LAYOUT_FULL: "full d^L tensor (16,777,216 amplitudes)",
+                   lib.LAYOUT_EVEN: "parity-halved, even sector (8,388,608 stored amplitudes)",
+                   lib.LAYOUT_ODD: "parity-halved, odd sector (8,388,608 stored amplitudes)"}[layout]
     lib.prof_set_sample(args.prof_sample)
     lib.prof_reset()
     lib.prof_enable(True)
@@ -268,9 +280,10 @@ def main():
         "config": {"workload": (f"Kitaev-Kerr open chain L=8 d=8 (16,777,216 amplitudes), J=1 Delta=0.5 K=0.2, "
                                 f"vacuum start, 28-op nearest-neighbour pool, ADAPT steps 1..{args.steps} with "
                                 f"{args.grad_mode} BFGS gradients"
-                                f"{', inverse Hessian recycled across steps' if rh else ''}"),
+                                f"{', inverse Hessian recycled across steps' if rh else ''}; states kept "
+                                f"{layout_desc}"),
                    "L": 8, "d": 8, "pool": len(cfg["pool"]), "grad_mode": args.grad_mode, "hessian_recycling": rh,
-                   "gate_fusion": lib.get_gate_fusion()},
+                   "gate_fusion": lib.get_gate_fusion(), "state_layout": layout_desc},
         "roofline": roof,
         "apply_h": kernel_entry(0),
         "kernels": {KERNEL_NAMES[k]: kernel_entry(k) for k in KERNEL_NAMES if prof[k]["launches"]},
@@ -320,6 +333,12 @@ def main():
             "adjoint_hessian_recycling": main if rh else variant(args.steps, recycle_hessian=True),
             "adjoint_graph_replay": variant_graph(args.steps),
         }
+        if layout != lib.LAYOUT_FULL:
+            lib.set_sector_layout(lib.SECTOR_OFF)
+            try:
+                out["variants"]["adjoint_hessian_recycling_full_layout"] = variant(args.steps, recycle_hessian=rh)
+            finally:
+                lib.set_sector_layout(lib.SECTOR_AUTO)
     if not args.no_variants and args.grad_mode == "adjoint" and not args.no_warm_start:
         print("[bench] warm-start leg: training data from 8 nearby points, network, proposals after selection",
               file=sys.stderr, flush=True)

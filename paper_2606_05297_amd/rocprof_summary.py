@@ -3,7 +3,11 @@ counter passes) as text.
 
     python -m paper_2606_05297_amd.rocprof_summary --trace T.db [--fetch F.db] [--write W.db]
            [--copy-bytes N | --fetch-factor F --write-factor W] [--json out.json]
-           [--traffic-out traffic.json]
+           [--traffic-out traffic.json] [--split]
+
+--split adds the time split of the trace: its span, the time some kernel runs
+(the union of the kernel intervals), the idle time, the median gap between
+consecutive kernels, and the kernel time per stage of the ADAPT step (SPLIT).
 
 Counter scaling: FETCH_SIZE and WRITE_SIZE (KiB per dispatch) are converted to
 bytes with the factor that makes the plain device copy kernel
@@ -41,11 +45,59 @@ FAMILIES = {
     "pool_grads": (((("k_pool8_row",), ("k_pool8_col",)), (("k_pool",),)),
                    ("stencil2.hip", "kernels_pool.hip", "stencil_kernels.h", "device_common.h")),
     "score": (((("k_h8_col",), ("k_h8_row_score",), ("k_pool8_col",)),), ("stencil2.hip", "device_common.h")),
-    "gate2": (((("k_gate2", "k_gate2_m0"),),), ("gate_kernels.h", "kernels_gate.hip", "device_common.h")),
-    "gate2_adjoint": (((("k_gate2_adj", "k_gate2_adj_m0"),),),
-                      ("gate_kernels.h", "kernels_gate.hip", "device_common.h")),
+    "gate2": (((("k_gate2", "k_gate2_m0", "k_gate2_m0p", "k_gate2_half"),),),
+              ("gate_kernels.h", "kernels_gate.hip", "gate_half.hip", "device_common.h")),
+    "gate2_adjoint": (((("k_gate2_adj", "k_gate2_adj_m0", "k_gate2_adj_m0p", "k_gate2_adj_half"),),),
+                      ("gate_kernels.h", "kernels_gate.hip", "gate_half.hip", "device_common.h")),
     "diag_gate": (((("k_diag", "k_diag_adj"),),), ("gate_kernels.h", "kernels_gate.hip", "device_common.h")),
 }
+
+
+# stages of the ADAPT step for --split: (label, kernel base names); the last
+# entry takes every other kernel.
+SPLIT = [
+    ("reverse step, top pair (6,7) of the parity-halved layout", ("k_gate2_adj_half",)),
+    ("reverse step, mode-0 pair (0,1)", ("k_gate2_adj_m0p", "k_gate2_adj_m0")),
+    ("reverse step, other pairs", ("k_gate2_adj",)),
+    ("forward gates, top pair (6,7) of the parity-halved layout", ("k_gate2_half",)),
+    ("forward gates, mode-0 pair (0,1)", ("k_gate2_m0p", "k_gate2_m0")),
+    ("forward gates, other pairs", ("k_gate2",)),
+    ("apply-H row pass", ("k_h8_row",)),
+    ("column pass (apply-H and scoring)", ("k_h8_col",)),
+    ("scoring (fused row pass, column pool pass)", ("k_h8_row_score", "k_pool8_col", "k_pool8_row")),
+    ("other kernels (reductions, copies, gate builds, sector conversion)", None),
+]
+
+
+def split(db):
+    """Span, busy time (union of kernel intervals), idle time, median gap
+    between consecutive kernels, and kernel time per SPLIT stage."""
+    con = sqlite3.connect(db)
+    rows = con.execute("select name, start, end from kernels order by start").fetchall()
+    if not rows:
+        return
+    busy, cur_s, cur_e, gaps = 0, rows[0][1], rows[0][2], []
+    per = defaultdict(float)
+    for n, st, en in rows:
+        if st > cur_e:
+            busy += cur_e - cur_s
+            gaps.append(st - cur_e)
+            cur_s, cur_e = st, en
+        else:
+            cur_e = max(cur_e, en)
+        b = base_of(short(n))
+        lab = next(lab for lab, names in SPLIT if names is None or b in names)
+        per[lab] += en - st
+    busy += cur_e - cur_s
+    span = rows[-1][2] - rows[0][1]
+    gaps.sort()
+    med = gaps[len(gaps) // 2] / 1e3 if gaps else 0.0
+    ktot = sum(per.values())
+    print(f"{len(rows)} kernels over {span / 1e6:.1f} ms: some kernel runs for {busy / 1e6:.1f} ms, idle "
+          f"{(span - busy) / 1e6:.1f} ms, median gap between consecutive kernels {med:.2f} us")
+    for lab, _ in SPLIT:
+        if per.get(lab):
+            print(f"  {lab:66s} {per[lab] / 1e6:9.1f} ms  {100 * per[lab] / ktot:5.1f} %")
 
 
 def source_sha(family: str) -> str:
@@ -117,6 +169,7 @@ def main():
     ap.add_argument("--write-factor", type=float, default=None)
     ap.add_argument("--json")
     ap.add_argument("--traffic-out")
+    ap.add_argument("--split", action="store_true")
     a = ap.parse_args()
     tr = trace(a.trace)
     fe = counter(a.fetch, "FETCH_SIZE") if a.fetch else {}
@@ -142,6 +195,8 @@ def main():
         print(f"{k[:60]:60s} {len(d):6d} {avg:10.2f} {sum(d) / 1e6:10.3f} {fs} {ws}")
     if ffac or wfac:
         print(f"counter scale factors (copy kernel): fetch x{ffac}, write x{wfac}")
+    if a.split:
+        split(a.trace)
     if a.json:
         with open(a.json, "w") as fh:
             json.dump(out, fh, indent=1)
