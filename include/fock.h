@@ -192,6 +192,20 @@ int fock_adjoint_sweep(const fock_ham_t *ham, const fock_op_t *ops, const double
                        void *lam_work, double norm2, double *dEdtheta, void *ws, size_t ws_bytes,
                        fock_stream_t stream);
 
+/* Build ahead of time, on the current device, what the calls on (L, d) would
+ * otherwise create on their first use: the gate eigendata of cutoff d (device
+ * memory and a synchronous upload, Sec. II.B), the tile-order tables of the
+ * stencil schedules 1-3 for open and ring chains, and this thread's pinned
+ * staging buffers at their base size (64 kB each).  Afterwards fock_apply_H,
+ * fock_apply_gate2 and fock_energy_grad_adjoint on (L, d) from this thread
+ * allocate nothing and add no synchronisation of their own beyond their
+ * documented result fetch, for circuits of up to ~2,700 gates.  (Pool scoring
+ * outside the slab kernels stages its pair tables through the pinned buffer,
+ * which grows on its first such call.)  Idempotent; FOCK_ERR_UNSUPPORTED /
+ * FOCK_ERR_SIZE as fock_workspace_bytes; the tables are kept until the process
+ * ends. */
+int fock_prepare(int L, int d);
+
 /* fock_apply_H without any allocation, for callers that cannot allocate
  * (code under HIP graph capture, tight serving loops, harnesses that forbid
  * hipMalloc): hpsi = H psi as fock_apply_H, with the per-workgroup energy and

@@ -90,8 +90,18 @@ int eval_energy(fock_adapt *st, const std::vector<double> &th, double *E, double
 }
 
 int optimise(fock_adapt *st, double gtol, fock_adapt_report_t *rep) {
-  ObjFn fn = [st](const std::vector<double> &x, double *f, std::vector<double> *g) {
-    return eval_energy(st, x, f, nullptr, g);
+  // every evaluation of this run, so that the energy and norm at the final
+  // angles (always an evaluated point) are reported without evaluating again
+  struct Seen {
+    std::vector<double> x;
+    double f, n2;
+  };
+  std::vector<Seen> seen;
+  ObjFn fn = [st, &seen](const std::vector<double> &x, double *f, std::vector<double> *g) {
+    double n2 = 0.0;
+    const int rc = eval_energy(st, x, f, &n2, g);
+    if (!rc) seen.push_back({x, *f, n2});
+    return rc;
   };
   const int n = (int)st->theta.size();
   std::vector<double> *H = nullptr;
@@ -113,10 +123,18 @@ int optimise(fock_adapt *st, double gtol, fock_adapt_report_t *rep) {
   int rc = bfgs_minimize(st->theta, fn, gtol, st->opt.bfgs_maxiter, H, &bo, st->opt.noise_rel);
   if (rc) return rc;
   double E = 0.0, n2 = 0.0;
-  rc = eval_energy(st, st->theta, &E, &n2, nullptr);
-  if (rc) return rc;
+  const Seen *hit = nullptr;
+  for (const Seen &e : seen)
+    if (e.x == st->theta) hit = &e;
+  if (hit) {
+    E = hit->f;
+    n2 = hit->n2;
+  } else {
+    rc = eval_energy(st, st->theta, &E, &n2, nullptr);
+    if (rc) return rc;
+  }
   rep->bfgs_iters = bo.iters;
-  rep->bfgs_evals = bo.evals + 1;
+  rep->bfgs_evals = bo.evals + (hit ? 0 : 1);
   rep->status = bo.status;
   rep->E = E;
   rep->norm2 = n2;

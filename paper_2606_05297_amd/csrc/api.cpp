@@ -856,6 +856,30 @@ extern "C" {
 
 int fock_version(void) { return 1; }
 
+int fock_prepare(int L, int d) {
+  uint32_t namp = 0;
+  int rc = check_geometry(L, d, &namp);
+  if (rc) return rc;
+  EigTables T;
+  if ((rc = get_tables(d, &T))) return rc;
+  fock_ham_t ham;
+  memset(&ham, 0, sizeof(ham));
+  ham.L = L;
+  ham.d = d;
+  for (int periodic = 0; periodic < 2; ++periodic) {
+    ham.periodic = periodic;
+    const HamArgs h = make_ham_args(ham);
+    const int nt = apply_h_blocks(h);
+    for (int scheme = 1; scheme < FOCK_SCHED_TWO_PASS; ++scheme) {
+      const int *order = nullptr;
+      if ((rc = stencil_order_table_for(L, d, nt, scheme, &order))) return rc;
+    }
+  }
+  // pinned staging of this thread at its minimum size
+  if ((rc = tl_in.reserve(1))) return rc;
+  return tl_out.reserve(1);
+}
+
 int fock_workspace_bytes(const fock_ham_t *ham, int n_pool, int n_ops, size_t *bytes) {
   uint32_t namp = 0;
   int rc = check_ham_layout(ham, &namp);

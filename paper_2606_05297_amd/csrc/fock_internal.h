@@ -249,6 +249,8 @@ int launch_reduce_rows(const double *partial, int row_stride, const GateRec *rec
 // result of a kernel does not depend on the schedule (partials are indexed by
 // tile).  *order receives a device table of ntiles entries or nullptr.
 int stencil_order_table(int L, int d, int ntiles, const int **order);
+// The same for an explicit scheme (tables are built once per device and kept).
+int stencil_order_table_for(int L, int d, int ntiles, int scheme, const int **order);
 int stencil_schedule();
 // Work split of the H psi kernel (FOCK_STENCIL_*), and whether the lane
 // split covers (L, d, ring bond).

@@ -365,8 +365,11 @@ bool lanes_stencil_ok(int L, int d, int periodic_wrap) { return d == 8 && L >= 4
 bool slab_stencil_ok(int L, int d) { return L == 8 && d == 8; }
 
 int stencil_order_table(int L, int d, int ntiles, const int **order) {
+  return stencil_order_table_for(L, d, ntiles, g_sched.load(), order);
+}
+
+int stencil_order_table_for(int L, int d, int ntiles, int scheme, const int **order) {
   *order = nullptr;
-  const int scheme = g_sched.load();
   if (scheme == 0 || scheme == FOCK_SCHED_TWO_PASS) return FOCK_OK;
   int dev = 0;
   FOCK_HIP(hipGetDevice(&dev));

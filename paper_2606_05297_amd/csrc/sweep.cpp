@@ -436,10 +436,19 @@ int bfgs_phase(fock_sweep *sw, const std::vector<char> &sel, const std::vector<d
     P.rc = 0;
     ++running;
   }
+  // energy and norm at each point's final angles, when the run evaluated them
+  // (as the single-point driver does, so that both report the same values)
+  std::vector<char> hit(sw->pts.size(), 0);
+  std::vector<double> hit_f(sw->pts.size(), 0.0), hit_n2(sw->pts.size(), 0.0);
   for (size_t pi = 0; pi < sw->pts.size(); ++pi) {
     if (!sel[pi]) continue;
     th.emplace_back([&, pi]() {
       SPoint &P = sw->pts[pi];
+      struct Seen {
+        std::vector<double> x;
+        double f, n2;
+      };
+      std::vector<Seen> seen;
       ObjFn fn = [&](const std::vector<double> &x, double *f, std::vector<double> *gg) -> int {
         std::unique_lock<std::mutex> lk(mu);
         P.x = x;
@@ -451,12 +460,19 @@ int bfgs_phase(fock_sweep *sw, const std::vector<char> &sel, const std::vector<d
         if (P.rc) return P.rc;
         *f = P.f;
         *gg = P.grad;
+        seen.push_back({x, P.f, P.n2});
         return 0;
       };
       std::vector<double> th0 = P.theta;
       BfgsOut bo;
       int r = bfgs_minimize(th0, fn, gtol[pi], sw->opt.bfgs_maxiter, nullptr, &bo, sw->opt.noise_rel);
       std::unique_lock<std::mutex> lk(mu);
+      for (const Seen &e : seen)
+        if (e.x == th0) {
+          hit[pi] = 1;
+          hit_f[pi] = e.f;
+          hit_n2[pi] = e.n2;
+        }
       if (!r) P.theta = th0;
       if (r && !P.rc) P.rc = r;
       outs[pi] = bo;
@@ -492,18 +508,30 @@ int bfgs_phase(fock_sweep *sw, const std::vector<char> &sel, const std::vector<d
   }
   for (auto &t : th) t.join();
   if (err) return err;
-  // final energies at the accepted angles (forward only, graph-free)
+  // final energies at the accepted angles (forward only, graph-free) for the
+  // points whose run did not evaluate them
+  std::vector<char> need(sw->pts.size(), 0);
+  bool any = false;
   for (size_t pi = 0; pi < sw->pts.size(); ++pi)
-    if (sel[pi]) sw->pts[pi].x = sw->pts[pi].theta;
-  rc = eval_forward(sw, sel);
-  if (rc) return rc;
+    if (sel[pi]) {
+      SPoint &P = sw->pts[pi];
+      if (hit[pi]) {
+        P.f = hit_f[pi];
+        P.n2 = hit_n2[pi];
+      } else {
+        P.x = P.theta;
+        need[pi] = 1;
+        any = true;
+      }
+    }
+  if (any && (rc = eval_forward(sw, need))) return rc;
   for (size_t pi = 0; pi < sw->pts.size(); ++pi) {
     if (!sel[pi]) continue;
     SPoint &P = sw->pts[pi];
     if (P.rc) return P.rc;
     fock_adapt_report_t &r = (*reps)[pi];
     r.bfgs_iters = outs[pi].iters;
-    r.bfgs_evals = outs[pi].evals + 1;
+    r.bfgs_evals = outs[pi].evals + need[pi];
     r.status = outs[pi].status;
     r.E = P.f;
     r.norm2 = P.n2;

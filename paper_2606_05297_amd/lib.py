@@ -111,6 +111,7 @@ def load(path: str = LIB_PATH):
     L.adapt_step_select.argtypes = [vp, C.POINTER(AdaptReport)]
     L.adapt_state_store.argtypes = [vp, ip]
     L.fock_set_state_store.argtypes = [C.c_int]
+    L.fock_prepare.argtypes = [C.c_int, C.c_int]
     L.fock_set_sector_layout.argtypes = [C.c_int]
     L.fock_sector_pack.argtypes = [C.c_int, C.c_int, C.c_int, vp, vp, vp]
     L.fock_sector_unpack.argtypes = [C.c_int, C.c_int, C.c_int, vp, vp, vp]
@@ -291,6 +292,12 @@ def apply_H_noalloc(h: Ham, psi, hpsi, res=None, stream=None):
 
 STORE_OFF, STORE_ON, STORE_AUTO = 0, 1, 2
 SECTOR_OFF, SECTOR_AUTO = 0, 1
+
+
+def prepare(L_, d):
+    """Build the per-device tables of (L, d) and this thread's pinned staging
+    ahead of time (fock_prepare), so later calls on them allocate nothing."""
+    _check(load().fock_prepare(int(L_), int(d)))
 
 
 def set_sector_layout(mode: int):

@@ -365,3 +365,11 @@ def test_sector_layout_switch_and_argument_checks():
     assert L.fock_sector_pack(8, 6, 1, None, None, None) == -3
     assert L.fock_sector_pack(8, 8, 0, None, None, None) == -1
     assert L.fock_sector_unpack(8, 8, 1, None, None, None) == -1
+
+
+def test_prepare_rejects_bad_geometry():
+    """fock_prepare checks (L, d) like the other calls before touching a device."""
+    L = lib.load()
+    assert L.fock_prepare(0, 8) == -3
+    assert L.fock_prepare(8, 1) == -3
+    assert L.fock_prepare(12, 16) == -2  # d^L beyond 2^31 amplitudes

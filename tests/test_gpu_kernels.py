@@ -775,3 +775,34 @@ def test_event_timing_samples_one_launch_in_k():
     finally:
         lib.prof_enable(False)
         lib.prof_set_sample(1)
+
+
+def test_prepare_then_calls_allocate_no_device_memory():
+    """After fock_prepare(L, d) the gate, H psi (every tile schedule) and
+    adjoint calls on (L, d) change the device's free memory by nothing (the
+    library's kernels are loaded by an earlier call on another cutoff)."""
+    L, d = 5, 7
+    h0 = lib.ham(3, 4)
+    x0 = torch.zeros(64, dtype=torch.complex64, device="cuda")
+    x0[0] = 1.0
+    lib.apply_H(h0, x0, torch.empty_like(x0), lib.workspace(h0))
+    hl = lib.ham(L, d, False, 1.0, 0.5, 0.1, 0.3, 0.2)
+    psi = dev(W.random_state(L, d, seed=5))
+    y, a, b = torch.empty_like(psi), torch.empty_like(psi), torch.empty_like(psi)
+    ws = lib.workspace(hl, 0, 4)
+    ops = [("HR", 0, 1), ("PI", 2, 3), ("KERR", 4, -1), ("SR", 1, -1)]
+    th = np.array([0.1, -0.2, 0.3, 0.05])
+    lib.prepare(L, d)
+    torch.cuda.synchronize()
+    free0 = torch.cuda.mem_get_info()[0]
+    prev = lib.get_stencil_schedule()
+    try:
+        for sc in (0, 1, 2, 3, 4):
+            lib.set_stencil_schedule(sc)
+            lib.apply_H(hl, psi, y, ws)
+    finally:
+        lib.set_stencil_schedule(prev)
+    lib.apply_gate2(L, d, ("HR", 1, 3), 0.2, psi, ws)
+    lib.energy_grad_adjoint(hl, ops, th, psi, a, b, ws)
+    torch.cuda.synchronize()
+    assert torch.cuda.mem_get_info()[0] == free0

@@ -244,3 +244,4 @@ def test_adapt_sector_layout_odd_start_and_fallbacks():
     assert abs(ra["E"] - Eo) <= 1e-5 * max(1.0, abs(Eo))
     for x in (a, b, m, k):
         x.close()
+
