@@ -9,8 +9,11 @@ angles with energy + adjoint-gradient evaluations (gate build, forward gates,
 H psi, fused reverse sweep).  The vacuum is even and every pool generator keeps
 the total parity, so the driver keeps its states in the parity-halved layout
 (the top mode's level follows from the other modes' parity: 8,388,608 stored
-amplitudes); --full-layout runs the whole benchmark on the full tensor, and
-"variants" also reports the default run in the full layout.  W warm-up steps run on a separate ADAPT instance;
+amplitudes).  Every gate the run selects is HR or PR and the vacuum is real,
+so its evaluations run their gates and reverse steps on real float32
+amplitudes (H psi and scoring on a complex64 copy).  --full-layout and
+--complex-states switch these off; "variants" also reports the default run
+with each of them off and with both off.  W warm-up steps run on a separate ADAPT instance;
 the K timed steps are steps 1..K of a fresh run from the vacuum.  Per-kernel
 durations come from HIP events recorded on the launch stream inside the timed
 region, around one launch in --prof-sample (default 4) of each kernel family:
@@ -45,7 +48,8 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0
 METRIC = "ADAPT steps/s, Kitaev-Kerr L=8 d=8, |ΔE|<1e-5 vs ED; apply-H GB/s vs peak"
-KERNEL_NAMES = {0: "apply_h", 1: "pool_grads", 2: "gate2", 3: "gate2_adjoint", 4: "diag_gate", 9: "score"}
+KERNEL_NAMES = {0: "apply_h", 1: "pool_grads", 2: "gate2", 3: "gate2_adjoint", 4: "diag_gate", 9: "score",
+                10: "gate2_real", 11: "gate2_adjoint_real", 12: "real_convert"}
 
 
 def traffic_for(kid: int):
@@ -184,6 +188,8 @@ def main():
     ap.add_argument("--no-warm-start", action="store_true", help="skip the learned warm-start leg")
     ap.add_argument("--full-layout", action="store_true",
                     help="keep the ADAPT states in the full d^L layout (parity-halved layout off)")
+    ap.add_argument("--complex-states", action="store_true",
+                    help="evaluate every circuit on complex64 states (real states off)")
     ap.add_argument("--prof-sample", type=int, default=4,
                     help="time one launch in this many per kernel family with HIP events (1: every launch)")
     ap.add_argument("--gate-fusion", type=int, choices=[0, 1, 2], default=None,
@@ -205,6 +211,8 @@ def main():
         lib.set_gate_fusion(args.gate_fusion)
     if args.full_layout:
         lib.set_sector_layout(lib.SECTOR_OFF)
+    if args.complex_states:
+        lib.set_real_states(lib.REAL_OFF)
     cfg = W.config("kk_l8_d8")
     hl = lib.ham_from(cfg)
     n = cfg["d"] ** cfg["L"]
@@ -223,6 +231,8 @@ def main():
     layout_desc = {lib.LAYOUT_FULL: "full d^L tensor (16,777,216 amplitudes)",
                    lib.LAYOUT_EVEN: "parity-halved, even sector (8,388,608 stored amplitudes)",
                    lib.LAYOUT_ODD: "parity-halved, odd sector (8,388,608 stored amplitudes)"}[layout]
+    if ad.real():
+        layout_desc += "; real float32 amplitudes for evaluations whose gates are all HR or PR"
     lib.prof_set_sample(args.prof_sample)
     lib.prof_reset()
     lib.prof_enable(True)
@@ -333,12 +343,17 @@ def main():
             "adjoint_hessian_recycling": main if rh else variant(args.steps, recycle_hessian=True),
             "adjoint_graph_replay": variant_graph(args.steps),
         }
-        if layout != lib.LAYOUT_FULL:
-            lib.set_sector_layout(lib.SECTOR_OFF)
+        # the headline's state representations switched off one at a time, then both
+        for name, sector, real in (("full_layout", lib.SECTOR_OFF, lib.REAL_AUTO),
+                                   ("complex_states", lib.SECTOR_AUTO, lib.REAL_OFF),
+                                   ("full_layout_complex_states", lib.SECTOR_OFF, lib.REAL_OFF)):
+            lib.set_sector_layout(sector)
+            lib.set_real_states(real)
             try:
-                out["variants"]["adjoint_hessian_recycling_full_layout"] = variant(args.steps, recycle_hessian=rh)
+                out["variants"]["adjoint_hessian_recycling_" + name] = variant(args.steps, recycle_hessian=rh)
             finally:
                 lib.set_sector_layout(lib.SECTOR_AUTO)
+                lib.set_real_states(lib.REAL_AUTO)
     if not args.no_variants and args.grad_mode == "adjoint" and not args.no_warm_start:
         print("[bench] warm-start leg: training data from 8 nearby points, network, proposals after selection",
               file=sys.stderr, flush=True)

@@ -308,6 +308,17 @@ int adapt_last_proposal(fock_adapt_t *st, int *accepted, double *E_prop, double 
  * see fock_set_state_store). */
 int adapt_state_store(fock_adapt_t *st, int *nstates);
 
+/* Whether the run keeps float32 copies of its states (*real = 1): with the
+ * switch on (fock_set_real_states), d = 8 and psi0 with every imaginary part
+ * exactly zero.  An evaluation whose gates are all HR or PR then runs its
+ * gates and reverse steps on real amplitudes (4 bytes each): H (Sec. III) is
+ * real and these generators are real antisymmetric (Sec. II.B), so psi,
+ * H psi and the reverse sweep's states stay real; H psi and the pool scoring
+ * run on a complex64 copy.  Evaluations with any other gate run in complex64.
+ * Energies, gradients and selections agree with the complex path to FP32
+ * rounding (the gate tables' imaginary parts are rounding noise). */
+int adapt_real(fock_adapt_t *st, int *real);
+
 /* Layout the run keeps its states in (FOCK_LAYOUT_*): with the sector switch
  * on (fock_set_sector_layout), adapt_create picks FOCK_LAYOUT_EVEN / _ODD when
  * psi0 has exactly zero amplitude outside one total-parity sector, the chain
@@ -525,6 +536,13 @@ enum { FOCK_SECTOR_OFF = 0, FOCK_SECTOR_AUTO = 1 };
 int fock_set_sector_layout(int mode);
 int fock_get_sector_layout(void);
 
+/* Real states in the ADAPT driver (see adapt_real): FOCK_REAL_OFF (0) never,
+ * FOCK_REAL_AUTO (1) where adapt_real says (default).  Applies to drivers
+ * created after the call; FOCK_ERR_ARG for other values; process-wide. */
+enum { FOCK_REAL_OFF = 0, FOCK_REAL_AUTO = 1 };
+int fock_set_real_states(int mode);
+int fock_get_real_states(void);
+
 /* ------------------------------------------------------------------ FP64 states */
 
 /* CV-ADAPT-VQE (Sec. IV.B) on complex128 states, for runs that resolve energy
@@ -617,7 +635,9 @@ int fock_stream_probe(int kind, const void *a, void *b, size_t bytes, int grid, 
 /* Kernel ids for per-kernel timing by HIP events recorded on the launch stream. */
 enum { FOCK_K_APPLY_H = 0, FOCK_K_POOL = 1, FOCK_K_GATE = 2, FOCK_K_ADJ = 3, FOCK_K_DIAG = 4,
        FOCK_K_REDUCE = 5, FOCK_K_MLP_FWD = 6, FOCK_K_MLP_TRAIN = 7, FOCK_K_GATE_DENSE = 8,
-       FOCK_K_SCORE = 9 /* fused scoring: H psi and pool partials, fock_score / adapt_step */, FOCK_K_NUM = 10 };
+       FOCK_K_SCORE = 9 /* fused scoring: H psi and pool partials, fock_score / adapt_step */,
+       FOCK_K_RGATE = 10, FOCK_K_RADJ = 11 /* gates and reverse steps on real states (adapt_real) */,
+       FOCK_K_CONVERT = 12 /* real <-> complex64 state conversion around H psi */, FOCK_K_NUM = 13 };
 
 /* Enable/disable event timing of launches (off by default). */
 int fock_prof_enable(int on);

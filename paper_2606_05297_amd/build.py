@@ -34,6 +34,7 @@ SOURCES = [
     "kernels_gate_de.hip",
     "kernels_gate_df.hip",
     "gate_half.hip",
+    "gate_real.hip",
     "sector.hip",
     "sweep_kernels.hip",
     "sweep.cpp",

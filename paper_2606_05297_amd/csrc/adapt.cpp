@@ -39,6 +39,7 @@ struct fock_adapt {
   bool pending = false;
   fock_adapt_report_t pend{};
   void *store_buf = nullptr;  // forward states of gradient evaluations (may be null)
+  void *real_buf = nullptr;   // float32 psi0, phi, lam of real-state evaluations (may be null)
 };
 
 namespace {
@@ -62,6 +63,35 @@ int psi_sector(const void *psi, uint32_t namp, hipStream_t s, int *sector) {
   if (host[1] == 0.0 && host[0] > 0.0) *sector = 0;
   else if (host[0] == 0.0 && host[1] > 0.0) *sector = 1;
   return FOCK_OK;
+}
+
+// Real-state buffers for st when switched on, d = 8 and every imaginary part of
+// its (stored) psi0 is exactly zero; otherwise none.
+int attach_real_states(fock_adapt *st) {
+  if (real_states_mode() != FOCK_REAL_AUTO || st->ham.d != 8 || st->namp % 4 != 0) return FOCK_OK;
+  unsigned int *flag = nullptr;
+  if (hipMalloc((void **)&flag, sizeof(unsigned int)) != hipSuccess)
+    return set_error(FOCK_ERR_HIP, "hipMalloc of the imaginary-part flag failed");
+  unsigned int host = 1u;
+  int rc = FOCK_OK;
+  if (hipMemsetAsync(flag, 0, sizeof(unsigned int), st->s) != hipSuccess) rc = set_error(FOCK_ERR_HIP, "memset failed");
+  if (!rc) rc = launch_imag_any(st->psi0, st->namp, flag, st->s);
+  if (!rc && (hipMemcpyAsync(&host, flag, sizeof(host), hipMemcpyDeviceToHost, st->s) != hipSuccess ||
+              hipStreamSynchronize(st->s) != hipSuccess))
+    rc = set_error(FOCK_ERR_HIP, "imaginary-part check of psi0 failed");
+  (void)hipFree(flag);
+  if (rc || host != 0u) return rc;
+  const size_t rb = (sizeof(float) * (size_t)st->namp + 255) & ~(size_t)255;
+  if (hipMalloc(&st->real_buf, 3 * rb) != hipSuccess) {
+    (void)hipGetLastError();
+    st->real_buf = nullptr;
+    return FOCK_OK;  // no room: complex evaluations only
+  }
+  char *b = (char *)st->real_buf;
+  st->ctx.psi0_r = (float *)b;
+  st->ctx.phi_r = (float *)(b + rb);
+  st->ctx.lam_r = (float *)(b + 2 * rb);
+  return launch_real_convert(st->namp, false, st->psi0, st->ctx.psi0_r, st->s);
 }
 
 int eval_energy(fock_adapt *st, const std::vector<double> &th, double *E, double *n2, std::vector<double> *g) {
@@ -232,6 +262,7 @@ int adapt_create(const fock_ham_t *ham, const fock_op_t *pool, int P, const void
     rc = launch_sector_convert(hc.L, st->ctx.g.sector, true, (const float2 *)psi0, st->psi0, st->s);
   else if (!rc && hipMemcpyAsync(st->psi0, psi0, sizeof(float2) * namp, hipMemcpyDeviceToDevice, st->s) != hipSuccess)
     rc = set_error(FOCK_ERR_HIP, "copy of psi0 failed");
+  if (!rc) rc = attach_real_states(st);
   if (!rc) {
     st->warm.iter = 0;
     st->warm.k_sel = -1;
@@ -251,6 +282,7 @@ int adapt_create(const fock_ham_t *ham, const fock_op_t *pool, int P, const void
     (void)hipStreamSynchronize(st->s);
     (void)hipFree(st->dbuf);
     if (st->store_buf) (void)hipFree(st->store_buf);
+    if (st->real_buf) (void)hipFree(st->real_buf);
     delete st;
     return rc;
   }
@@ -394,6 +426,12 @@ int adapt_last_proposal(fock_adapt_t *st, int *accepted, double *E_prop, double 
   return FOCK_OK;
 }
 
+int adapt_real(fock_adapt_t *st, int *real) {
+  if (!st || !real) return set_error(FOCK_ERR_ARG, "NULL argument");
+  *real = st->ctx.psi0_r != nullptr ? 1 : 0;
+  return FOCK_OK;
+}
+
 int adapt_layout(fock_adapt_t *st, int *layout) {
   if (!st || !layout) return set_error(FOCK_ERR_ARG, "NULL argument");
   *layout = st->ham.layout;
@@ -411,6 +449,7 @@ int adapt_destroy(fock_adapt_t *st) {
   (void)hipStreamSynchronize(st->s);
   if (st->dbuf) (void)hipFree(st->dbuf);
   if (st->store_buf) (void)hipFree(st->store_buf);
+  if (st->real_buf) (void)hipFree(st->real_buf);
   delete st;
   return FOCK_OK;
 }

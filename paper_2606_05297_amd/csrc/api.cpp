@@ -539,14 +539,68 @@ static int forward_circuit(Ctx &c, const fock_op_t *ops, int n, const std::vecto
   return FOCK_OK;
 }
 
+// ---------------------------------------------------------------- real states
+static std::atomic<int> g_real_states{FOCK_REAL_AUTO};
+
+int real_states_mode() { return g_real_states.load(); }
+
+// An evaluation runs on real states when the context keeps them and every gate
+// is HR or PR (real orthogonal) with a real-state kernel for its pair.
+static bool real_eval(const Ctx &c, const fock_op_t *ops, int n) {
+  if (!c.psi0_r) return false;
+  for (int k = 0; k < n; ++k)
+    if ((ops[k].type != FOCK_HR && ops[k].type != FOCK_PR) || !real_gate_supported(c.g, ops[k].i, ops[k].j))
+      return false;
+  return true;
+}
+
+// phi_r = O_n..O_1 psi0_r (staged gates), then phi = phi_r widened to complex64.
+static int forward_real(Ctx &c, const fock_op_t *ops, int n, float2 *phi) {
+  const float2 *utab = (const float2 *)(c.ws + c.L.utab);
+  const int stride = gate_stride(c.g.d);
+  if (n == 0)
+    FOCK_HIP(hipMemcpyAsync(c.phi_r, c.psi0_r, sizeof(float) * (size_t)c.g.n_amp, hipMemcpyDeviceToDevice, c.s));
+  for (int k = 0; k < n; ++k) {
+    ProfScope ps(FOCK_K_RGATE, c.s, 8.0 * c.g.n_amp);
+    const int rc = launch_rgate(c.g, ops[k].i, ops[k].j, gate_kind(ops[k].type), false, utab + (size_t)k * stride,
+                                k == 0 ? c.psi0_r : c.phi_r, c.phi_r, c.s);
+    if (rc) return rc;
+  }
+  ProfScope ps(FOCK_K_CONVERT, c.s, 12.0 * c.g.n_amp);
+  return launch_real_convert(c.g.n_amp, true, c.phi_r, phi, c.s);
+}
+
+// Reverse sweep on real states: lam_r = real part of H psi (lam), then per gate
+// the partial sums of lam . A phi and phi_r, lam_r <- U^T phi_r, U^T lam_r.
+static int reverse_real(Ctx &c, const fock_op_t *ops, int n, const float2 *lam, double *res) {
+  {
+    ProfScope ps(FOCK_K_CONVERT, c.s, 12.0 * c.g.n_amp);
+    const int rc = launch_real_convert(c.g.n_amp, false, lam, c.lam_r, c.s);
+    if (rc) return rc;
+  }
+  const float2 *utab = (const float2 *)(c.ws + c.L.utab);
+  double *part = (double *)(c.ws + c.L.partial);
+  const int stride = gate_stride(c.g.d);
+  for (int k = n - 1; k >= 0; --k) {
+    const fock_op_t &op = ops[k];
+    ProfScope ps(FOCK_K_RADJ, c.s, 16.0 * c.g.n_amp);
+    const int rc = launch_rgate_adj(c.g, op.i, op.j, gate_kind(op.type), utab + (size_t)k * stride,
+                                    c.T.A[table_slot(op.type)], c.phi_r, c.lam_r, part + (size_t)k * c.L.rs, c.s,
+                                    true);
+    if (rc) return rc;
+  }
+  return launch_reduce_rows(part, c.L.rs, (const GateRec *)(c.ws + c.L.recs), n, res, c.s);
+}
+
 // State of a circuit, its energy and the pool gradients there, with the
 // scoring fused where possible; g receives the raw 2 Re <H psi|A_k psi>.
 int run_score(Ctx &c, const fock_op_t *ops, const double *theta, int n, const void *psi0, float2 *phi,
               float2 *lam, const fock_op_t *pool, int P, double *E, double *norm2, double *g) {
   std::vector<GateGroup> groups;
-  int rc = stage_circuit(c, ops, theta, n, &groups);
+  const bool real = real_eval(c, ops, n);
+  int rc = real ? stage_gates(c, ops, theta, n, nullptr) : stage_circuit(c, ops, theta, n, &groups);
   if (rc) return rc;
-  if ((rc = forward_circuit(c, ops, n, groups, psi0, phi))) return rc;
+  if ((rc = real ? forward_real(c, ops, n, phi) : forward_circuit(c, ops, n, groups, psi0, phi))) return rc;
   double *res = (double *)(c.ws + c.L.result);
   if ((rc = score_dev(c, pool, P, phi, lam, res))) return rc;
   std::vector<double> host(2 + P);
@@ -564,10 +618,15 @@ int run_score(Ctx &c, const fock_op_t *ops, const double *theta, int n, const vo
 int run_circuit(Ctx &c, const fock_op_t *ops, const double *theta, int n, const void *psi0, float2 *phi,
                        float2 *lam, bool grad, double *E, double *norm2, double *dE) {
   std::vector<GateGroup> groups;
-  int rc = stage_circuit(c, ops, theta, n, &groups);
+  const bool real = real_eval(c, ops, n);
+  int rc = real ? stage_gates(c, ops, theta, n, nullptr) : stage_circuit(c, ops, theta, n, &groups);
   if (rc) return rc;
   double *res = (double *)(c.ws + c.L.result);
-  if (grad && use_store(c, ops, n, groups)) {
+  if (real) {
+    if ((rc = forward_real(c, ops, n, phi))) return rc;
+    if ((rc = apply_h_dev(c, phi, lam, res))) return rc;
+    if (grad && n > 0 && (rc = reverse_real(c, ops, n, lam, res + 2))) return rc;
+  } else if (grad && use_store(c, ops, n, groups)) {
     // forward states kept: H psi_n reads the last one; phi is not touched
     if ((rc = forward_stored(c, ops, n, psi0))) return rc;
     if ((rc = apply_h_dev(c, stored_state(c, n), lam, res))) return rc;
@@ -1115,6 +1174,15 @@ int fock_set_sector_layout(int mode) {
 }
 
 int fock_get_sector_layout(void) { return g_sector_layout.load(); }
+
+int fock_set_real_states(int mode) {
+  if (mode != FOCK_REAL_OFF && mode != FOCK_REAL_AUTO)
+    return set_error(FOCK_ERR_ARG, "real-state mode %d is not OFF (0) or AUTO (1)", mode);
+  g_real_states.store(mode);
+  return FOCK_OK;
+}
+
+int fock_get_real_states(void) { return g_real_states.load(); }
 
 static int sector_convert(int L, int d, int layout, const void *src, void *dst, bool to_half, fock_stream_t stream) {
   if (d != 8) return set_error(FOCK_ERR_UNSUPPORTED, "the parity-halved layout needs d = 8 (d=%d)", d);

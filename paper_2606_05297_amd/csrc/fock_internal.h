@@ -277,6 +277,22 @@ int apply_h2_blocks(const HamArgs &h);
 int launch_score_slab(const SlabPool &sp, const HamArgs &h, const float2 *psi, float2 *hpsi, double *hpart,
                       double *ppart, hipStream_t s);
 
+// Real states (gate_real.hip, d = 8): gates and reverse steps of the real
+// generators HR and PR on float32 amplitudes (tables: the complex ones, real
+// parts), in the full or the parity-halved geometry; the gate on (i, j) is
+// available when real_gate_supported.  launch_real_convert widens n real
+// amplitudes to complex64 (imaginary parts zero) or keeps the real parts;
+// launch_imag_any raises *flag (atomic max of the bit pattern of |Im|) when
+// any imaginary part of c is non-zero.
+bool real_gate_supported(const Geometry &g, int i, int j);
+int real_gate_blocks(const Geometry &g, int i, int j);
+int launch_rgate(const Geometry &g, int i, int j, int kind, bool dag, const float2 *U, const float *src, float *psi,
+                 hipStream_t s);
+int launch_rgate_adj(const Geometry &g, int i, int j, int kind, const float2 *U, const float2 *A, float *phi,
+                     float *lam, double *partial, hipStream_t s, bool write_phi);
+int launch_real_convert(uint32_t n, bool to_complex, const void *src, void *dst, hipStream_t s);
+int launch_imag_any(const float2 *c, uint32_t n, unsigned int *flag, hipStream_t s);
+
 // Parity sectors (sector.hip, d = 8): partial (even, odd) sums of |Re| + |Im|
 // of a full state, sector_norms_blocks(n) pairs; full <-> parity-halved conversion.
 int sector_norms_blocks(uint32_t n);

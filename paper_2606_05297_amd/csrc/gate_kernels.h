@@ -10,6 +10,8 @@ struct GateLaunch {
   uint32_t nfib, si, sj;
   FastDiv dsi, dm1;
 };
+// Launch parameters of a gate on (i, j) in geometry g (kernels_gate.hip).
+GateLaunch gate_launch_params(const Geometry &g, int i, int j);
 
 __device__ __forceinline__ uint32_t fiber_base(uint32_t f, const GateLaunch &g, int D) {
   const uint32_t t = fdiv(f, g.dsi);

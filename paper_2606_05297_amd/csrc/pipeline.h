@@ -27,6 +27,9 @@ struct Ctx {
   float2 *store = nullptr;
   int nstore = 0;
   size_t sstride = 0;
+  // Real states (d = 8, ADAPT driver): float32 copies of psi0 and the forward
+  // and adjoint states, used by evaluations whose gates are all HR or PR.
+  float *psi0_r = nullptr, *phi_r = nullptr, *lam_r = nullptr;
 };
 
 int check_geometry(int L, int d, uint32_t *namp);
@@ -35,6 +38,8 @@ int check_geometry(int L, int d, uint32_t *namp);
 int check_ham(const fock_ham_t *h, uint32_t *namp);
 int check_ham_layout(const fock_ham_t *h, uint32_t *namp);
 bool half_layout_op_ok(const fock_op_t &op, int L);
+// Switch of the ADAPT driver's real states (FOCK_REAL_*).
+int real_states_mode();
 // Switch of the ADAPT driver's automatic parity-halved layout (FOCK_SECTOR_*),
 // and whether it applies to this chain, pool and warm-up layer.
 int sector_layout_mode();

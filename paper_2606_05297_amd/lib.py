@@ -113,6 +113,8 @@ def load(path: str = LIB_PATH):
     L.fock_set_state_store.argtypes = [C.c_int]
     L.fock_prepare.argtypes = [C.c_int, C.c_int]
     L.fock_set_sector_layout.argtypes = [C.c_int]
+    L.fock_set_real_states.argtypes = [C.c_int]
+    L.adapt_real.argtypes = [vp, ip]
     L.fock_sector_pack.argtypes = [C.c_int, C.c_int, C.c_int, vp, vp, vp]
     L.fock_sector_unpack.argtypes = [C.c_int, C.c_int, C.c_int, vp, vp, vp]
     L.adapt_layout.argtypes = [vp, ip]
@@ -298,6 +300,19 @@ def prepare(L_, d):
     """Build the per-device tables of (L, d) and this thread's pinned staging
     ahead of time (fock_prepare), so later calls on them allocate nothing."""
     _check(load().fock_prepare(int(L_), int(d)))
+
+
+REAL_OFF, REAL_AUTO = 0, 1
+
+
+def set_real_states(mode: int):
+    """Real states in ADAPT drivers created afterwards (fock_set_real_states):
+    REAL_OFF or REAL_AUTO (the default)."""
+    _check(load().fock_set_real_states(int(mode)))
+
+
+def get_real_states() -> int:
+    return int(load().fock_get_real_states())
 
 
 def set_sector_layout(mode: int):
@@ -523,6 +538,12 @@ class Adapt:
         r = AdaptReport()
         _check(self._L.adapt_step_finish(self._st, C.byref(r)))
         return r.as_dict()
+
+    def real(self) -> bool:
+        """Whether the run keeps float32 states for evaluations whose gates are all HR or PR."""
+        n = C.c_int(0)
+        _check(self._L.adapt_real(self._st, C.byref(n)))
+        return bool(n.value)
 
     def layout(self) -> int:
         """Layout the run keeps its states in (LAYOUT_FULL, LAYOUT_EVEN or LAYOUT_ODD)."""

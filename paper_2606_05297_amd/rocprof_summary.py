@@ -50,12 +50,19 @@ FAMILIES = {
     "gate2_adjoint": (((("k_gate2_adj", "k_gate2_adj_m0", "k_gate2_adj_m0p", "k_gate2_adj_half"),),),
                       ("gate_kernels.h", "kernels_gate.hip", "gate_half.hip", "device_common.h")),
     "diag_gate": (((("k_diag", "k_diag_adj"),),), ("gate_kernels.h", "kernels_gate.hip", "device_common.h")),
+    "gate2_real": (((("k_rgate2", "k_rgate2_m0p"),),), ("gate_real.hip", "gate_kernels.h", "device_common.h")),
+    "gate2_adjoint_real": (((("k_rgate2_adj", "k_rgate2_adj_m0p"),),),
+                           ("gate_real.hip", "gate_kernels.h", "device_common.h")),
+    "real_convert": (((("k_real_to_complex", "k_complex_to_real"),),), ("gate_real.hip", "device_common.h")),
 }
 
 
 # stages of the ADAPT step for --split: (label, kernel base names); the last
 # entry takes every other kernel.
 SPLIT = [
+    ("reverse step on real states", ("k_rgate2_adj", "k_rgate2_adj_m0p")),
+    ("forward gates on real states", ("k_rgate2", "k_rgate2_m0p")),
+    ("real <-> complex conversion", ("k_real_to_complex", "k_complex_to_real")),
     ("reverse step, top pair (6,7) of the parity-halved layout", ("k_gate2_adj_half",)),
     ("reverse step, mode-0 pair (0,1)", ("k_gate2_adj_m0p", "k_gate2_adj_m0")),
     ("reverse step, other pairs", ("k_gate2_adj",)),
