@@ -554,7 +554,8 @@ static bool real_eval(const Ctx &c, const fock_op_t *ops, int n) {
   return true;
 }
 
-// phi_r = O_n..O_1 psi0_r (staged gates), then phi = phi_r widened to complex64.
+// phi_r = O_n..O_1 psi0_r (staged gates), then (phi != nullptr) phi = phi_r
+// widened to complex64.
 static int forward_real(Ctx &c, const fock_op_t *ops, int n, float2 *phi) {
   const float2 *utab = (const float2 *)(c.ws + c.L.utab);
   const int stride = gate_stride(c.g.d);
@@ -566,18 +567,25 @@ static int forward_real(Ctx &c, const fock_op_t *ops, int n, float2 *phi) {
                                 k == 0 ? c.psi0_r : c.phi_r, c.phi_r, c.s);
     if (rc) return rc;
   }
+  if (!phi) return FOCK_OK;
   ProfScope ps(FOCK_K_CONVERT, c.s, 12.0 * c.g.n_amp);
   return launch_real_convert(c.g.n_amp, true, c.phi_r, phi, c.s);
 }
 
-// Reverse sweep on real states: lam_r = real part of H psi (lam), then per gate
-// the partial sums of lam . A phi and phi_r, lam_r <- U^T phi_r, U^T lam_r.
-static int reverse_real(Ctx &c, const fock_op_t *ops, int n, const float2 *lam, double *res) {
+// H phi_r into lam_r and (<psi|H psi>, <psi|psi>) into res2, on real states.
+static int apply_h_real(Ctx &c, double *res2) {
+  int G = 0;
   {
-    ProfScope ps(FOCK_K_CONVERT, c.s, 12.0 * c.g.n_amp);
-    const int rc = launch_real_convert(c.g.n_amp, false, lam, c.lam_r, c.s);
+    ProfScope ps(FOCK_K_APPLY_H, c.s, 8.0 * c.g.n_amp);
+    const int rc = launch_apply_h2_real(c.h, c.phi_r, c.lam_r, (double *)(c.ws + c.L.partial), &G, c.s);
     if (rc) return rc;
   }
+  return launch_reduce((const double *)(c.ws + c.L.partial), G, 2, res2, c.s);
+}
+
+// Reverse sweep on real states from phi_r and lam_r = H phi_r: per gate the
+// partial sums of lam . A phi, then phi_r, lam_r <- U^T phi_r, U^T lam_r.
+static int reverse_real(Ctx &c, const fock_op_t *ops, int n, double *res) {
   const float2 *utab = (const float2 *)(c.ws + c.L.utab);
   double *part = (double *)(c.ws + c.L.partial);
   const int stride = gate_stride(c.g.d);
@@ -623,9 +631,20 @@ int run_circuit(Ctx &c, const fock_op_t *ops, const double *theta, int n, const 
   if (rc) return rc;
   double *res = (double *)(c.ws + c.L.result);
   if (real) {
-    if ((rc = forward_real(c, ops, n, phi))) return rc;
-    if ((rc = apply_h_dev(c, phi, lam, res))) return rc;
-    if (grad && n > 0 && (rc = reverse_real(c, ops, n, lam, res + 2))) return rc;
+    // H psi on the real states when the slab passes take them, else on a
+    // complex64 copy whose real part is kept
+    const bool rh = apply_h2_real_supported(c.h) && c.h.slab;
+    if ((rc = forward_real(c, ops, n, rh ? nullptr : phi))) return rc;
+    if (rh) {
+      if ((rc = apply_h_real(c, res))) return rc;
+    } else {
+      if ((rc = apply_h_dev(c, phi, lam, res))) return rc;
+      if (grad && n > 0) {
+        ProfScope ps(FOCK_K_CONVERT, c.s, 12.0 * c.g.n_amp);
+        if ((rc = launch_real_convert(c.g.n_amp, false, lam, c.lam_r, c.s))) return rc;
+      }
+    }
+    if (grad && n > 0 && (rc = reverse_real(c, ops, n, res + 2))) return rc;
   } else if (grad && use_store(c, ops, n, groups)) {
     // forward states kept: H psi_n reads the last one; phi is not touched
     if ((rc = forward_stored(c, ops, n, psi0))) return rc;

@@ -262,6 +262,11 @@ bool slab_stencil_ok(int L, int d);
 // (<psi|H psi>, <psi|psi>) partials.
 int launch_apply_h2(const HamArgs &h, const float2 *psi, float2 *hpsi, double *partial, int *nblocks,
                     hipStream_t s);
+// The same on real states (float32 amplitudes, open chains; H has real
+// matrix elements): 4 bytes per amplitude in each pass.
+bool apply_h2_real_supported(const HamArgs &h);
+int launch_apply_h2_real(const HamArgs &h, const float *psi, float *hpsi, double *partial, int *nblocks,
+                         hipStream_t s);
 // Slab pool scoring (stencil2.hip): one FP64 partial per (workgroup, slot),
 // pool_slab_blocks(h) workgroups, slot values already doubled.
 int launch_pool_slab(const SlabPool &sp, const HamArgs &h, const float2 *psi, const float2 *hpsi, double *partial,

@@ -75,6 +75,38 @@ __device__ __forceinline__ void fma2(float2 &a, const float2 &v, float c) {
   a.y = fmaf(c, v.y, a.y);
 }
 
+// Real states: the column pass holds two real amplitudes per float2 (where the
+// complex pass holds two complex ones per float4), the row pass one per float.
+__device__ __forceinline__ void fma4(float2 &a, const float2 &v, float c) {
+  a.x = fmaf(c, v.x, a.x);
+  a.y = fmaf(c, v.y, a.y);
+}
+__device__ __forceinline__ void fma4s(float2 &a, const float2 &v, float c_lo, float c_hi) {
+  a.x = fmaf(c_lo, v.x, a.x);
+  a.y = fmaf(c_hi, v.y, a.y);
+}
+__device__ __forceinline__ void fma2(float &a, const float &v, float c) { a = fmaf(c, v, a); }
+template <class V>
+__device__ __forceinline__ V vzero();
+template <>
+__device__ __forceinline__ float4 vzero<float4>() { return make_float4(0.f, 0.f, 0.f, 0.f); }
+template <>
+__device__ __forceinline__ float2 vzero<float2>() { return make_float2(0.f, 0.f); }
+template <>
+__device__ __forceinline__ float vzero<float>() { return 0.f; }
+__device__ __forceinline__ float2 vadd(const float2 &a, const float2 &b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ float vadd(float a, float b) { return a + b; }
+__device__ __forceinline__ float vdot(const float2 &a, const float2 &b) { return a.x * b.x + a.y * b.y; }
+__device__ __forceinline__ float vdot(float a, float b) { return a * b; }
+__device__ __forceinline__ float2 vdpp_left(const float2 &u) {
+  return make_float2(dpp_from_left(u.x), dpp_from_left(u.y));
+}
+__device__ __forceinline__ float vdpp_left(float u) { return dpp_from_left(u); }
+__device__ __forceinline__ float2 vdpp_right(const float2 &u) {
+  return make_float2(dpp_from_right(u.x), dpp_from_right(u.y));
+}
+__device__ __forceinline__ float vdpp_right(float u) { return dpp_from_right(u); }
+
 // Ladder factors: folded to constants where m is known at compile time (the
 // unrolled register and stream indices), one square root per thread otherwise.
 struct Coef {
@@ -105,12 +137,14 @@ __device__ __forceinline__ Coef make_coef(const HamArgs &h) {
 // m7 - 1; one with e = 1 reads n7 - 1 in its own slice and n7 + 1 in slice
 // m7 + 1.  e is fixed per (thread, register parity, float4 half), so each
 // push carries a per-lane factor that selects the terms of the right parity.
-template <bool RING, bool HALF>
-__global__ __launch_bounds__(kColThreads) void k_h8_col(const float4 *__restrict__ psi, float4 *__restrict__ tout,
-                                                         HamArgs h) {
+// V = float4 (two complex amplitudes per lane) or float2 (two real ones, real
+// states: same indexing, half the bytes; open chains only).
+template <bool RING, bool HALF, class V = float4>
+__global__ __launch_bounds__(kColThreads) void k_h8_col(const V *__restrict__ psi, V *__restrict__ tout, HamArgs h) {
   static_assert(!(RING && HALF), "the parity-halved layout is for open chains");
+  static_assert(!(RING && sizeof(V) != sizeof(float4)), "real states: open chains");
   constexpr int NS = HALF ? 4 : 8;  // streamed slices
-  __shared__ float4 sl[4096];  // [n6][n5][n4][l]
+  __shared__ V sl[4096];  // [n6][n5][n4][l]
   const Coef C = make_coef(h);
   const int b = blockIdx.x;
   const int j = (b & 7) * (kCols / 8) + (b >> 3);  // XCD x takes chunks 32x .. 32x+31 (contiguous low-mode run)
@@ -118,8 +152,8 @@ __global__ __launch_bounds__(kColThreads) void k_h8_col(const float4 *__restrict
   const int l = t & 7, n4 = (t >> 3) & 7, n5 = t >> 6;
   constexpr int S6 = kS4 / 2 * 64, S7 = kS4 / 2 * 512;  // float4 strides of modes 6, 7
   const size_t base = (size_t)(8 * j + l) + (size_t)(kS4 / 2) * (n4 + 8 * n5);
-  const float4 *src = psi + base;
-  float4 *dst = tout + base;
+  const V *src = psi + base;
+  V *dst = tout + base;
   // bond (4,5) coefficients and LDS offsets (wrapped indices carry weight 0)
   const float cA = -C.J * C.dn(n4) * C.up(n5), cB = -C.J * C.up(n4) * C.dn(n5);
   const float cC = C.Dl * C.up(n4) * C.up(n5), cD = C.Dl * C.dn(n4) * C.dn(n5);
@@ -149,15 +183,15 @@ __global__ __launch_bounds__(kColThreads) void k_h8_col(const float4 *__restrict
     }
   }
 
-  float4 own[8], nxt[8];
-  float4 acc[3][8];
+  V own[8], nxt[8];
+  V acc[3][8];
 #pragma unroll
   for (int a = 0; a < 8; ++a) own[a] = src[(size_t)a * S6];
 #pragma unroll
   for (int k = 0; k < NS; ++k) {
-    float4(&am)[8] = acc[(k + 2) % 3];  // slice k - 1
-    float4(&a0)[8] = acc[k % 3];        // slice k
-    float4(&ap)[8] = acc[(k + 1) % 3];  // slice k + 1
+    V(&am)[8] = acc[(k + 2) % 3];  // slice k - 1
+    V(&a0)[8] = acc[k % 3];        // slice k
+    V(&ap)[8] = acc[(k + 1) % 3];  // slice k + 1
     if (k > 0) __syncthreads();
 #pragma unroll
     for (int a = 0; a < 8; ++a) sl[li(n4, n5, a)] = own[a];
@@ -168,7 +202,7 @@ __global__ __launch_bounds__(kColThreads) void k_h8_col(const float4 *__restrict
     __syncthreads();
     if (k == 0) {
 #pragma unroll
-      for (int a = 0; a < 8; ++a) a0[a] = make_float4(0.f, 0.f, 0.f, 0.f);
+      for (int a = 0; a < 8; ++a) a0[a] = vzero<V>();
     }
     // ring bond: neighbours along n0 inside the chunk come from lanes l - 1
     // (its second amplitude, 2l - 1) and l + 1 (its first, 2l + 2) of the same n4
@@ -213,7 +247,7 @@ __global__ __launch_bounds__(kColThreads) void k_h8_col(const float4 *__restrict
 #pragma unroll
         for (int a = 0; a < 8; ++a) {
           const int q = a & 1;
-          ap[a] = make_float4(0.f, 0.f, 0.f, 0.f);
+          ap[a] = vzero<V>();
           if (a < 7) fma4s(ap[a], own[a + 1], -C.J * C.up(a) * dnx * w0[q], -C.J * C.up(a) * dnx * w0[q ^ 1]);
           if (a > 0) fma4s(ap[a], own[a - 1], C.Dl * C.dn(a) * dnx * w0[q], C.Dl * C.dn(a) * dnx * w0[q ^ 1]);
         }
@@ -221,7 +255,7 @@ __global__ __launch_bounds__(kColThreads) void k_h8_col(const float4 *__restrict
         const float dnx = C.dn(k + 1);
 #pragma unroll
         for (int a = 0; a < 8; ++a) {
-          ap[a] = make_float4(0.f, 0.f, 0.f, 0.f);
+          ap[a] = vzero<V>();
           if (a < 7) fma4(ap[a], own[a + 1], -C.J * C.up(a) * dnx);  // a7^+ a6: reads (n6 + 1, n7 - 1)
           if (a > 0) fma4(ap[a], own[a - 1], C.Dl * C.dn(a) * dnx);  // a6^+ a7^+: reads (n6 - 1, n7 - 1)
           if constexpr (RING) {
@@ -267,7 +301,7 @@ __global__ __launch_bounds__(kColThreads) void k_h8_col(const float4 *__restrict
     }
 #pragma unroll
     for (int a = 0; a < 8; ++a) {
-      const float4 vm = sl[om + a * 512], vp = sl[op + a * 512];
+      const V vm = sl[om + a * 512], vp = sl[op + a * 512];
       if (a > 0) {  // outputs n6 = a - 1 read (n5 -+ 1, n6 + 1)
         fma4(a0[a - 1], vm, hm * C.up(a - 1));
         fma4(a0[a - 1], vp, pp * C.up(a - 1));
@@ -287,9 +321,11 @@ __global__ __launch_bounds__(kColThreads) void k_h8_col(const float4 *__restrict
 
 // Row pass.  Thread t: n0 = t & 7, n1 = (t >> 3) & 7, n2 = t >> 6; registers
 // over n3.  A wavefront reads 512 contiguous bytes per load.
-__global__ __launch_bounds__(kRowThreads) void k_h8_row(const float2 *__restrict__ psi, float2 *__restrict__ hpsi,
+// E = float2 (complex amplitudes) or float (real states).
+template <class E = float2>
+__global__ __launch_bounds__(kRowThreads) void k_h8_row(const E *__restrict__ psi, E *__restrict__ hpsi,
                                                         double *__restrict__ partial, HamArgs h) {
-  __shared__ float2 tile[4096];  // [n3][n2][n1][n0]
+  __shared__ E tile[4096];  // [n3][n2][n1][n0]
   __shared__ double red[2 * kRowThreads / 64];
   const Coef C = make_coef(h);
   const int b = blockIdx.x;
@@ -297,8 +333,8 @@ __global__ __launch_bounds__(kRowThreads) void k_h8_row(const float2 *__restrict
   const int t = threadIdx.x;
   const int n0 = t & 7, n1 = (t >> 3) & 7, n2 = t >> 6;
   const size_t base = (size_t)t + (size_t)p * 8 * kS4;
-  const float2 *src = psi + base;
-  float2 *dst = hpsi + base;
+  const E *src = psi + base;
+  E *dst = hpsi + base;
   auto ti = [&](int a0, int a1, int a2, int a3) { return (a0 & 7) + 8 * (a1 & 7) + 64 * (a2 & 7) + 512 * a3; };
   // bond (0,1): rows n1 +- 1 at n0, shifted along n0 across lanes
   const int r01p = ti(n0, n1 + 1, n2, 0), r01m = ti(n0, n1 - 1, n2, 0);
@@ -317,16 +353,16 @@ __global__ __launch_bounds__(kRowThreads) void k_h8_row(const float2 *__restrict
   const float hp = -C.J * C.up(n2), pp = C.Dl * C.up(n2);
   const float dg012 = C.dg(n0) + C.dg(n1) + C.dg(n2);
 
-  float2 own[8], nxt[8], prev[8], tv[8];
-  float2 acc[3][8];
+  E own[8], nxt[8], prev[8], tv[8];
+  E acc[3][8];
 #pragma unroll
   for (int a = 0; a < 8; ++a) own[a] = src[(size_t)a * 512];
   float e = 0.f, nn = 0.f;
 #pragma unroll
   for (int k = 0; k < 8; ++k) {
-    float2(&am)[8] = acc[(k + 2) % 3];
-    float2(&a0)[8] = acc[k % 3];
-    float2(&ap)[8] = acc[(k + 1) % 3];
+    E(&am)[8] = acc[(k + 2) % 3];
+    E(&a0)[8] = acc[k % 3];
+    E(&ap)[8] = acc[(k + 1) % 3];
     if (k > 0) __syncthreads();
 #pragma unroll
     for (int a = 0; a < 8; ++a) tile[t + 512 * a] = own[a];
@@ -341,7 +377,7 @@ __global__ __launch_bounds__(kRowThreads) void k_h8_row(const float2 *__restrict
     __syncthreads();
     if (k == 0) {
 #pragma unroll
-      for (int a = 0; a < 8; ++a) a0[a] = make_float2(0.f, 0.f);
+      for (int a = 0; a < 8; ++a) a0[a] = vzero<E>();
     }
     if (k > 0) {  // bond (3,4) pushed from slice k into k - 1, then slice k - 1 is complete
       const float u = C.up(k - 1);
@@ -349,9 +385,9 @@ __global__ __launch_bounds__(kRowThreads) void k_h8_row(const float2 *__restrict
       for (int a = 0; a < 8; ++a) {
         if (a > 0) fma2(am[a], own[a - 1], -C.J * C.dn(a) * u);  // a3^+ a4: reads (n3 - 1, n4 + 1)
         if (a < 7) fma2(am[a], own[a + 1], C.Dl * C.up(a) * u);  // a3 a4:   reads (n3 + 1, n4 + 1)
-        const float2 hv = make_float2(am[a].x + tv[a].x, am[a].y + tv[a].y);
-        e += prev[a].x * hv.x + prev[a].y * hv.y;
-        nn += prev[a].x * prev[a].x + prev[a].y * prev[a].y;
+        const E hv = vadd(am[a], tv[a]);
+        e += vdot(prev[a], hv);
+        nn += vdot(prev[a], prev[a]);
         dst[(size_t)a * 512 + (size_t)(k - 1) * kS4] = hv;
       }
     }
@@ -359,7 +395,7 @@ __global__ __launch_bounds__(kRowThreads) void k_h8_row(const float2 *__restrict
       const float dnx = C.dn(k + 1);
 #pragma unroll
       for (int a = 0; a < 8; ++a) {
-        ap[a] = make_float2(0.f, 0.f);
+        ap[a] = vzero<E>();
         if (a < 7) fma2(ap[a], own[a + 1], -C.J * C.up(a) * dnx);  // a4^+ a3: reads (n3 + 1, n4 - 1)
         if (a > 0) fma2(ap[a], own[a - 1], C.Dl * C.dn(a) * dnx);  // a3^+ a4^+: reads (n3 - 1, n4 - 1)
       }
@@ -368,11 +404,8 @@ __global__ __launch_bounds__(kRowThreads) void k_h8_row(const float2 *__restrict
     for (int a = 0; a < 8; ++a) {
       fma2(a0[a], own[a], dg012 + C.dg(a));  // on-site terms of modes 0..3 (mode 4's: column pass)
       // bond (0,1)
-      const float2 u = tile[r01p + 512 * a], v = tile[r01m + 512 * a];
-      const float2 ul = make_float2(dpp_from_left(u.x), dpp_from_left(u.y));
-      const float2 ur = make_float2(dpp_from_right(u.x), dpp_from_right(u.y));
-      const float2 vl = make_float2(dpp_from_left(v.x), dpp_from_left(v.y));
-      const float2 vr = make_float2(dpp_from_right(v.x), dpp_from_right(v.y));
+      const E u = tile[r01p + 512 * a], v = tile[r01m + 512 * a];
+      const E ul = vdpp_left(u), ur = vdpp_right(u), vl = vdpp_left(v), vr = vdpp_right(v);
       fma2(a0[a], ul, c01a);
       fma2(a0[a], vr, c01b);
       fma2(a0[a], ur, c01c);
@@ -385,7 +418,7 @@ __global__ __launch_bounds__(kRowThreads) void k_h8_row(const float2 *__restrict
     }
 #pragma unroll
     for (int a = 0; a < 8; ++a) {  // bond (2,3)
-      const float2 vm = tile[o23m + 512 * a], vp = tile[o23p + 512 * a];
+      const E vm = tile[o23m + 512 * a], vp = tile[o23p + 512 * a];
       if (a > 0) {
         fma2(a0[a - 1], vm, hm * C.up(a - 1));
         fma2(a0[a - 1], vp, pp * C.up(a - 1));
@@ -402,14 +435,14 @@ __global__ __launch_bounds__(kRowThreads) void k_h8_row(const float2 *__restrict
     }
   }
   {
-    float2(&am)[8] = acc[7 % 3];
+    E(&am)[8] = acc[7 % 3];
 #pragma unroll
     for (int a = 0; a < 8; ++a) tv[a] = dst[(size_t)a * 512 + (size_t)7 * kS4];
 #pragma unroll
     for (int a = 0; a < 8; ++a) {
-      const float2 hv = make_float2(am[a].x + tv[a].x, am[a].y + tv[a].y);
-      e += prev[a].x * hv.x + prev[a].y * hv.y;
-      nn += prev[a].x * prev[a].x + prev[a].y * prev[a].y;
+      const E hv = vadd(am[a], tv[a]);
+      e += vdot(prev[a], hv);
+      nn += vdot(prev[a], prev[a]);
       dst[(size_t)a * 512 + (size_t)7 * kS4] = hv;
     }
   }
@@ -1115,7 +1148,25 @@ int launch_apply_h2(const HamArgs &h, const float2 *psi, float2 *hpsi, double *p
                     hipStream_t s) {
   if (!apply_h2_supported(h)) return set_error(FOCK_ERR_UNSUPPORTED, "two-pass H psi needs L = 8, d = 8");
   launch_col(h, psi, hpsi, s);
-  hipLaunchKernelGGL(k_h8_row, dim3(slab_pencils(h)), dim3(kRowThreads), 0, s, psi, hpsi, partial, h);
+  hipLaunchKernelGGL((k_h8_row<float2>), dim3(slab_pencils(h)), dim3(kRowThreads), 0, s, psi, hpsi, partial, h);
+  FOCK_HIP(hipGetLastError());
+  *nblocks = apply_h2_blocks(h);
+  return FOCK_OK;
+}
+
+bool apply_h2_real_supported(const HamArgs &h) { return apply_h2_supported(h) && !h.periodic_wrap; }
+
+int launch_apply_h2_real(const HamArgs &h, const float *psi, float *hpsi, double *partial, int *nblocks,
+                         hipStream_t s) {
+  if (!apply_h2_real_supported(h))
+    return set_error(FOCK_ERR_UNSUPPORTED, "two-pass H psi on real states needs an open L = 8, d = 8 chain");
+  if (h.half)
+    hipLaunchKernelGGL((k_h8_col<false, true, float2>), dim3(kCols), dim3(kColThreads), 0, s, (const float2 *)psi,
+                       (float2 *)hpsi, h);
+  else
+    hipLaunchKernelGGL((k_h8_col<false, false, float2>), dim3(kCols), dim3(kColThreads), 0, s, (const float2 *)psi,
+                       (float2 *)hpsi, h);
+  hipLaunchKernelGGL((k_h8_row<float>), dim3(slab_pencils(h)), dim3(kRowThreads), 0, s, psi, hpsi, partial, h);
   FOCK_HIP(hipGetLastError());
   *nblocks = apply_h2_blocks(h);
   return FOCK_OK;
