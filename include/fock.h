@@ -71,8 +71,15 @@ enum {
  *     and fock_score (pools of HR..PI on nearest-neighbour pairs),
  *     fock_energy_grad_adjoint and fock_adjoint_sweep (HR..PI gates on pairs
  *     (i, j) with j < L-1, or (L-2, L-1)); FOCK_ERR_UNSUPPORTED elsewhere and
- *     for other ops.  Every other call takes layout 0 only. */
-enum { FOCK_LAYOUT_FULL = 0, FOCK_LAYOUT_EVEN = 1, FOCK_LAYOUT_ODD = 2 };
+ *     for other ops.  Every other call takes layout 0 only.
+ * FOCK_LAYOUT_REAL (4), added to any of the three: the state buffers hold
+ *     float32 amplitudes (4 bytes each, same count and order).  H has real
+ *     matrix elements (Sec. III) and HR, PR are real antisymmetric (Sec. II.B),
+ *     so a real state stays real under H and their gates.  Open chains of
+ *     L = 8, d = 8 under the slab stencil; taken by fock_workspace_bytes,
+ *     fock_apply_H and fock_energy_grad_adjoint (HR and PR gates only; psi0,
+ *     psi_work and lam_work are float32); FOCK_ERR_UNSUPPORTED elsewhere. */
+enum { FOCK_LAYOUT_FULL = 0, FOCK_LAYOUT_EVEN = 1, FOCK_LAYOUT_ODD = 2, FOCK_LAYOUT_REAL = 4 };
 typedef struct {
   int32_t L, d, periodic, layout;
   double J, U, mu, Delta, K;

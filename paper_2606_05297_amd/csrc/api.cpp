@@ -27,19 +27,25 @@ int check_geometry(int L, int d, uint32_t *namp) {
   return FOCK_OK;
 }
 
-int check_ham_layout(const fock_ham_t *h, uint32_t *namp) {
+int check_ham_layout(const fock_ham_t *h, uint32_t *namp, bool allow_real) {
   if (!h) return set_error(FOCK_ERR_ARG, "ham is NULL");
   int rc = check_geometry(h->L, h->d, namp);
   if (rc) return rc;
   const double v[5] = {h->J, h->U, h->mu, h->Delta, h->K};
   for (double x : v)
     if (!std::isfinite(x)) return set_error(FOCK_ERR_NONFINITE, "non-finite Hamiltonian parameter");
-  if (h->layout < FOCK_LAYOUT_FULL || h->layout > FOCK_LAYOUT_ODD)
-    return set_error(FOCK_ERR_ARG, "layout %d not in {0, 1, 2}", h->layout);
-  if (h->layout != FOCK_LAYOUT_FULL) {
+  const int sector = h->layout & 3;
+  if (sector > FOCK_LAYOUT_ODD || (h->layout & ~(3 | FOCK_LAYOUT_REAL)) != 0)
+    return set_error(FOCK_ERR_ARG, "layout %d is not 0, 1 or 2, optionally with FOCK_LAYOUT_REAL (4)", h->layout);
+  if (sector != FOCK_LAYOUT_FULL) {
     if (h->L != 8 || h->d != 8 || h->periodic)
       return set_error(FOCK_ERR_UNSUPPORTED, "the parity-halved layout is for open chains of L = 8, d = 8");
     *namp /= 2;
+  }
+  if (h->layout & FOCK_LAYOUT_REAL) {
+    if (!allow_real) return set_error(FOCK_ERR_UNSUPPORTED, "this call takes complex64 states (no FOCK_LAYOUT_REAL)");
+    if (h->L != 8 || h->d != 8 || h->periodic)
+      return set_error(FOCK_ERR_UNSUPPORTED, "real states are taken for open chains of L = 8, d = 8");
   }
   return FOCK_OK;
 }
@@ -164,9 +170,9 @@ int make_ctx(const fock_ham_t &ham, uint32_t namp, int P, int n, void *ws, size_
                     Ctx *c) {
   c->g = {ham.L, ham.d, namp};
   c->h = make_ham_args(ham);
-  if (ham.layout != FOCK_LAYOUT_FULL) {
+  if ((ham.layout & 3) != FOCK_LAYOUT_FULL) {
     c->g.half = c->h.half = 1;
-    c->g.sector = c->h.sector = ham.layout == FOCK_LAYOUT_ODD ? 1 : 0;
+    c->g.sector = c->h.sector = (ham.layout & 3) == FOCK_LAYOUT_ODD ? 1 : 0;
   }
   memset(&c->T, 0, sizeof(c->T));  // eigendata loaded below when the call applies gates
   {
@@ -960,19 +966,19 @@ int fock_prepare(int L, int d) {
 
 int fock_workspace_bytes(const fock_ham_t *ham, int n_pool, int n_ops, size_t *bytes) {
   uint32_t namp = 0;
-  int rc = check_ham_layout(ham, &namp);
+  int rc = check_ham_layout(ham, &namp, true);
   if (rc) return rc;
   if (!bytes) return set_error(FOCK_ERR_ARG, "bytes is NULL");
   if (n_pool < 0 || n_pool > 4096 || n_ops < 0 || n_ops > 4096)
     return set_error(FOCK_ERR_ARG, "n_pool/n_ops out of range");
-  *bytes = make_layout(namp, ham->L, ham->d, n_pool, n_ops, ham->layout != FOCK_LAYOUT_FULL).total;
+  *bytes = make_layout(namp, ham->L, ham->d, n_pool, n_ops, (ham->layout & 3) != FOCK_LAYOUT_FULL).total;
   return FOCK_OK;
 }
 
 int fock_apply_H(const fock_ham_t *ham, const void *psi, void *hpsi, double *E, double *norm2, void *ws,
                  size_t ws_bytes, fock_stream_t stream) {
   uint32_t namp = 0;
-  int rc = check_ham_layout(ham, &namp);
+  int rc = check_ham_layout(ham, &namp, true);
   if (rc) return rc;
   if ((rc = check_ptr(psi, "psi")) || (rc = check_ptr(hpsi, "hpsi"))) return rc;
   if (psi == hpsi) return set_error(FOCK_ERR_ARG, "psi and hpsi must not overlap");
@@ -980,7 +986,13 @@ int fock_apply_H(const fock_ham_t *ham, const void *psi, void *hpsi, double *E, 
   rc = make_ctx(*ham, namp, 0, 0, ws, ws_bytes, (hipStream_t)stream, &c);
   if (rc) return rc;
   double *res = (double *)(c.ws + c.L.result);
-  rc = apply_h_dev(c, (const float2 *)psi, (float2 *)hpsi, res);
+  if (ham->layout & FOCK_LAYOUT_REAL) {
+    c.phi_r = (float *)const_cast<void *>(psi);
+    c.lam_r = (float *)hpsi;
+    rc = apply_h_real(c, res);
+  } else {
+    rc = apply_h_dev(c, (const float2 *)psi, (float2 *)hpsi, res);
+  }
   if (rc) return rc;
   if (E || norm2) {
     double h2[2];
@@ -1125,7 +1137,7 @@ int fock_energy_grad_adjoint(const fock_ham_t *ham, const fock_op_t *ops, const 
                              const void *psi0, void *psi_work, void *lam_work, double *E, double *norm2,
                              double *dEdtheta, void *ws, size_t ws_bytes, fock_stream_t stream) {
   uint32_t namp = 0;
-  int rc = check_ham_layout(ham, &namp);
+  int rc = check_ham_layout(ham, &namp, true);
   if (rc) return rc;
   if (n < 0 || n > 4096) return set_error(FOCK_ERR_ARG, "n=%d out of range", n);
   if (n > 0 && (!ops || !theta)) return set_error(FOCK_ERR_ARG, "ops/theta is NULL");
@@ -1140,6 +1152,16 @@ int fock_energy_grad_adjoint(const fock_ham_t *ham, const fock_op_t *ops, const 
   Ctx c;
   rc = make_ctx(*ham, namp, 0, n, ws, ws_bytes, (hipStream_t)stream, &c);
   if (rc) return rc;
+  if (ham->layout & FOCK_LAYOUT_REAL) {
+    // float32 states: psi0, psi_work and lam_work are the real-state buffers
+    c.psi0_r = (float *)const_cast<void *>(psi0);
+    c.phi_r = (float *)psi_work;
+    c.lam_r = (float *)lam_work;
+    if (!real_eval(c, ops, n))
+      return set_error(FOCK_ERR_UNSUPPORTED, "real states take HR and PR gates only");
+    if (!c.h.slab)  // the real H psi is the slab one; no complex copy fits these buffers
+      return set_error(FOCK_ERR_UNSUPPORTED, "real states need the slab stencil with the one-pass schedule");
+  }
   return run_circuit(c, ops, theta, n, psi0, (float2 *)psi_work, (float2 *)lam_work, dEdtheta != nullptr, E, norm2,
                      dEdtheta);
 }

@@ -34,9 +34,9 @@ struct Ctx {
 
 int check_geometry(int L, int d, uint32_t *namp);
 // check_ham takes full d^L states only; check_ham_layout also the parity-halved
-// layout (namp = d^L / 2 then).
+// layout (namp = d^L / 2 then) and, with allow_real, FOCK_LAYOUT_REAL.
 int check_ham(const fock_ham_t *h, uint32_t *namp);
-int check_ham_layout(const fock_ham_t *h, uint32_t *namp);
+int check_ham_layout(const fock_ham_t *h, uint32_t *namp, bool allow_real = false);
 bool half_layout_op_ok(const fock_op_t &op, int L);
 // Switch of the ADAPT driver's real states (FOCK_REAL_*).
 int real_states_mode();

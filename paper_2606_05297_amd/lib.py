@@ -166,13 +166,14 @@ def last_error() -> str:
 
 # ---------------------------------------------------------------- marshalling helpers
 
-LAYOUT_FULL, LAYOUT_EVEN, LAYOUT_ODD = 0, 1, 2
+LAYOUT_FULL, LAYOUT_EVEN, LAYOUT_ODD, LAYOUT_REAL = 0, 1, 2, 4
 
 
 def ham(L, d, periodic=False, J=1.0, U=0.0, mu=0.0, Delta=0.0, K=0.0, layout=LAYOUT_FULL) -> Ham:
     """Hamiltonian record; layout says how the state buffers of a call hold psi
     (LAYOUT_FULL: d^L amplitudes; LAYOUT_EVEN / LAYOUT_ODD: the parity-halved
-    layout of a state of that total parity, d^L / 2 amplitudes)."""
+    layout of a state of that total parity, d^L / 2 amplitudes; plus
+    LAYOUT_REAL: float32 amplitudes instead of complex64)."""
     return Ham(int(L), int(d), int(bool(periodic)), int(layout), float(J), float(U), float(mu), float(Delta),
                float(K))
 
@@ -180,7 +181,7 @@ def ham(L, d, periodic=False, J=1.0, U=0.0, mu=0.0, Delta=0.0, K=0.0, layout=LAY
 def n_amplitudes(h: Ham) -> int:
     """Amplitudes of one state buffer of a call on h."""
     n = int(h.d) ** int(h.L)
-    return n // 2 if int(h.layout) != LAYOUT_FULL else n
+    return n // 2 if (int(h.layout) & 3) != LAYOUT_FULL else n
 
 
 def ham_from(cfg: dict) -> Ham:
@@ -229,13 +230,15 @@ def _state_arg(t, L_, d, name, dtype="c64", layout=LAYOUT_FULL):
     write past it."""
     import torch
     want = torch.complex64 if dtype == "c64" else torch.complex128
+    if int(layout) & LAYOUT_REAL:
+        want = torch.float32
     if not isinstance(t, torch.Tensor):
         raise FockError(-1, f"{name} must be a torch tensor, got {type(t).__name__}")
     if t.dtype != want or not t.is_contiguous():
         raise FockError(-1, f"{name} must be a contiguous {want} tensor (got {t.dtype}, "
                             f"contiguous={t.is_contiguous()})")
     n = int(d) ** int(L_)
-    if int(layout) != LAYOUT_FULL:
+    if (int(layout) & 3) != LAYOUT_FULL:
         n //= 2
         if t.numel() != n:
             raise FockError(-2, f"{name} must hold d^L / 2 = {n} amplitudes (parity-halved layout), got {t.numel()}")

@@ -134,3 +134,89 @@ def test_real_states_fallbacks():
     a.close()
     b.close()
     del c
+
+
+def stored_index(L, d, sigma):
+    """Full flat index of every stored amplitude of the parity-halved layout
+    (from its definition, as in test_gpu_sector.py)."""
+    nlow = d ** (L - 1)
+    c = np.arange(d**L // 2, dtype=np.int64)
+    low, m = c % nlow, c // nlow
+    s, x = np.zeros_like(low), low.copy()
+    for _ in range(L - 1):
+        s += x % d
+        x //= d
+    return low + (2 * m + (s + sigma) % 2) * nlow
+
+
+def real_state(seed):
+    """A real, normalised, even-parity state of L=8, d=8 (the real part of a
+    seeded sector state)."""
+    psi = W.random_state(8, 8, seed=seed, sector=("parity", 0)).real.astype(np.float64)
+    return psi / np.linalg.norm(psi)
+
+
+HAM = dict(L=8, d=8, periodic=False, J=0.8, U=1.1, mu=0.3, Delta=0.45, K=0.15)
+REAL_LAYOUTS = [lib.LAYOUT_FULL | lib.LAYOUT_REAL, lib.LAYOUT_EVEN | lib.LAYOUT_REAL]
+
+
+def ham_real(layout):
+    c = HAM
+    return (O.Ham(c["L"], c["d"], c["periodic"], c["J"], c["U"], c["mu"], c["Delta"], c["K"]),
+            lib.ham(c["L"], c["d"], c["periodic"], c["J"], c["U"], c["mu"], c["Delta"], c["K"], layout=layout))
+
+
+@pytest.mark.parametrize("layout", REAL_LAYOUTS, ids=["full", "halved"])
+def test_real_apply_H_l8_d8(layout):
+    """H psi on float32 states (FOCK_LAYOUT_REAL) on every stored amplitude,
+    with the energy and norm, against the oracle on the full tensor (open
+    chain with hopping, pairing, U, K and mu)."""
+    ho, hl = ham_real(layout)
+    say("real H psi, layout", layout)
+    psi = real_state(81)
+    idx = stored_index(8, 8, 0) if layout & 3 else np.arange(8**8)
+    x = torch.from_numpy(psi[idx].astype(np.float32)).to("cuda")
+    y = torch.full_like(x, float("nan"))
+    ws = lib.workspace(hl, 0, 0)
+    E, n2 = lib.apply_H(hl, x, y, ws)
+    p128 = psi.astype(np.float32).astype(np.complex128)
+    href = O.apply_H_slices(ho, p128)
+    assert np.abs(href.imag).max() == 0.0
+    got = y.cpu().numpy().astype(np.float64)
+    hs = href.real[idx]
+    assert np.isfinite(got).all()
+    assert np.abs(got - hs).max() <= 2e-5 * np.abs(hs).max()
+    Eref = np.vdot(p128, href).real
+    assert abs(E - Eref) <= 1e-5 * max(1.0, abs(Eref))
+    assert abs(n2 - np.vdot(p128, p128).real) <= 1e-6
+
+
+@pytest.mark.parametrize("layout", REAL_LAYOUTS, ids=["full", "halved"])
+def test_real_energy_and_adjoint_l8_d8(layout):
+    """Energy, final state and every dE/dtheta of an HR / PR circuit on float32
+    states (20 gates over all seven bonds, the mode-0 pair and the top pair
+    included) against the oracle's FP64 reverse sweep on the full tensor."""
+    ho, hl = ham_real(layout)
+    pool = W.pool(8, "nn", False, ("HR", "PR"))
+    ops, th = W.random_circuit(pool, 16, seed=91)
+    ops = ops + [("HR", 0, 1), ("PR", 0, 1), ("HR", 6, 7), ("PR", 6, 7)]
+    th = np.concatenate([th, [0.21, -0.17, 0.33, -0.29]])
+    say("real adjoint, layout", layout, len(ops))
+    psi0 = real_state(93)
+    idx = stored_index(8, 8, 0) if layout & 3 else np.arange(8**8)
+    x0 = torch.from_numpy(psi0[idx].astype(np.float32)).to("cuda")
+    a, b = torch.empty_like(x0), torch.empty_like(x0)
+    ws = lib.workspace(hl, 0, len(ops))
+    p0 = psi0.astype(np.float32).astype(np.complex128)
+    E, n2, g = lib.energy_grad_adjoint(hl, ops, th, x0, a, b, ws, grad=False)
+    psi_n = O.ansatz_state(p0, ops, th, 8, 8)
+    assert np.abs(psi_n.imag).max() < 1e-12
+    assert np.abs(a.cpu().numpy() - psi_n.real[idx]).max() <= 1e-5 * np.abs(psi_n).max() * len(ops) ** 0.5
+    E, n2, g = lib.energy_grad_adjoint(hl, ops, th, x0, a, b, ws)
+    Eref, gref, n2ref = O.energy_and_grad_adjoint(ho, p0, ops, th, apply_h=O.apply_H_slices)
+    assert abs(E - Eref) <= 1e-5 * max(1.0, abs(Eref))
+    assert abs(n2 - n2ref) <= 1e-6 * len(ops)
+    assert np.abs(g - gref).max() <= 1e-4 * max(1.0, np.abs(gref).max()), np.abs(g - gref).max()
+    with pytest.raises(lib.FockError) as e:  # a complex gate on real states
+        lib.energy_grad_adjoint(hl, [("HI", 0, 1)], np.array([0.1]), x0, a, b, ws)
+    assert e.value.code == -3
