@@ -644,7 +644,8 @@ enum { FOCK_K_APPLY_H = 0, FOCK_K_POOL = 1, FOCK_K_GATE = 2, FOCK_K_ADJ = 3, FOC
        FOCK_K_REDUCE = 5, FOCK_K_MLP_FWD = 6, FOCK_K_MLP_TRAIN = 7, FOCK_K_GATE_DENSE = 8,
        FOCK_K_SCORE = 9 /* fused scoring: H psi and pool partials, fock_score / adapt_step */,
        FOCK_K_RGATE = 10, FOCK_K_RADJ = 11 /* gates and reverse steps on real states (adapt_real) */,
-       FOCK_K_CONVERT = 12 /* real <-> complex64 state conversion around H psi */, FOCK_K_NUM = 13 };
+       FOCK_K_CONVERT = 12 /* real <-> complex64 state conversion around H psi */,
+       FOCK_K_APPLY_H_REAL = 13 /* two-pass H psi on real states */, FOCK_K_NUM = 14 };
 
 /* Enable/disable event timing of launches (off by default). */
 int fock_prof_enable(int on);

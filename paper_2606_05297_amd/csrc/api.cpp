@@ -560,6 +560,14 @@ static bool real_eval(const Ctx &c, const fock_op_t *ops, int n) {
   return true;
 }
 
+// Gate tables of a real-state evaluation, with the real kernels' workgroup
+// counts as the reverse step's partial counts.
+static int stage_real(Ctx &c, const fock_op_t *ops, const double *theta, int n) {
+  std::vector<int> nblk(n > 0 ? n : 1);
+  for (int k = 0; k < n; ++k) nblk[k] = real_gate_blocks(c.g, ops[k].i, ops[k].j);
+  return stage_gates(c, ops, theta, n, nblk.data());
+}
+
 // phi_r = O_n..O_1 psi0_r (staged gates), then (phi != nullptr) phi = phi_r
 // widened to complex64.
 static int forward_real(Ctx &c, const fock_op_t *ops, int n, float2 *phi) {
@@ -582,7 +590,7 @@ static int forward_real(Ctx &c, const fock_op_t *ops, int n, float2 *phi) {
 static int apply_h_real(Ctx &c, double *res2) {
   int G = 0;
   {
-    ProfScope ps(FOCK_K_APPLY_H, c.s, 8.0 * c.g.n_amp);
+    ProfScope ps(FOCK_K_APPLY_H_REAL, c.s, 8.0 * c.g.n_amp);
     const int rc = launch_apply_h2_real(c.h, c.phi_r, c.lam_r, (double *)(c.ws + c.L.partial), &G, c.s);
     if (rc) return rc;
   }
@@ -612,7 +620,7 @@ int run_score(Ctx &c, const fock_op_t *ops, const double *theta, int n, const vo
               float2 *lam, const fock_op_t *pool, int P, double *E, double *norm2, double *g) {
   std::vector<GateGroup> groups;
   const bool real = real_eval(c, ops, n);
-  int rc = real ? stage_gates(c, ops, theta, n, nullptr) : stage_circuit(c, ops, theta, n, &groups);
+  int rc = real ? stage_real(c, ops, theta, n) : stage_circuit(c, ops, theta, n, &groups);
   if (rc) return rc;
   if ((rc = real ? forward_real(c, ops, n, phi) : forward_circuit(c, ops, n, groups, psi0, phi))) return rc;
   double *res = (double *)(c.ws + c.L.result);
@@ -633,7 +641,7 @@ int run_circuit(Ctx &c, const fock_op_t *ops, const double *theta, int n, const 
                        float2 *lam, bool grad, double *E, double *norm2, double *dE) {
   std::vector<GateGroup> groups;
   const bool real = real_eval(c, ops, n);
-  int rc = real ? stage_gates(c, ops, theta, n, nullptr) : stage_circuit(c, ops, theta, n, &groups);
+  int rc = real ? stage_real(c, ops, theta, n) : stage_circuit(c, ops, theta, n, &groups);
   if (rc) return rc;
   double *res = (double *)(c.ws + c.L.result);
   if (real) {

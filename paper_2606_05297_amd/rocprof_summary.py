@@ -50,6 +50,7 @@ FAMILIES = {
     "gate2_adjoint": (((("k_gate2_adj", "k_gate2_adj_m0", "k_gate2_adj_m0p", "k_gate2_adj_half"),),),
                       ("gate_kernels.h", "kernels_gate.hip", "gate_half.hip", "device_common.h")),
     "diag_gate": (((("k_diag", "k_diag_adj"),),), ("gate_kernels.h", "kernels_gate.hip", "device_common.h")),
+    "apply_h_real": (((("k_h8_col_r",), ("k_h8_row_r",)),), ("stencil2.hip", "device_common.h")),
     "gate2_real": (((("k_rgate2", "k_rgate2_m0p"),),), ("gate_real.hip", "gate_kernels.h", "device_common.h")),
     "gate2_adjoint_real": (((("k_rgate2_adj", "k_rgate2_adj_m0p"),),),
                            ("gate_real.hip", "gate_kernels.h", "device_common.h")),
@@ -71,6 +72,7 @@ SPLIT = [
     ("forward gates, other pairs", ("k_gate2",)),
     ("apply-H row pass", ("k_h8_row",)),
     ("column pass (apply-H and scoring)", ("k_h8_col",)),
+    ("apply-H on real states (column + row pass)", ("k_h8_col_r", "k_h8_row_r")),
     ("scoring (fused row pass, column pool pass)", ("k_h8_row_score", "k_pool8_col", "k_pool8_row")),
     ("other kernels (reductions, copies, gate builds, sector conversion)", None),
 ]
@@ -116,7 +118,14 @@ def source_sha(family: str) -> str:
 
 
 def base_of(kname: str) -> str:
-    return kname.split("<")[0].split("::")[-1]
+    """Kernel base name; the real-state instantiations of the slab H passes
+    (two reals per float2, one per float) get a name of their own."""
+    b = kname.split("<")[0].split("::")[-1]
+    if b == "k_h8_col" and "float, 2u" in kname:
+        return "k_h8_col_r"
+    if b == "k_h8_row" and re.search(r"k_h8_row<float\s*>", kname):
+        return "k_h8_row_r"
+    return b
 
 
 def family_bytes(fam: str, per_kernel: dict):
