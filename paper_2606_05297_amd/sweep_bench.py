@@ -48,9 +48,11 @@ def main():
     amps = sum(p["d"] ** p["L"] for p in pts)
     print(f"[sweep_bench] {len(pts)} points, {amps} amplitudes, {K} steps", file=sys.stderr, flush=True)
 
-    # (a) point by point, gates one per pass like the batched kernels (bitwise comparable)
+    # (a) point by point, gates one per pass on complex64 states like the batched
+    # kernels (bitwise comparable: fusion and real-state evaluations off)
     fused = lib.get_gate_fusion()
     lib.set_gate_fusion(lib.FUSE_OFF)
+    lib.set_real_states(lib.REAL_OFF)
     singles = [lib.Adapt(e["ham"], e["pool"], e["psi0"], max_iters=40, warm_ops=e["warm_ops"],
                          warm_theta0=e["warm_theta0"]) for e in entries]
     torch.cuda.synchronize()
@@ -70,6 +72,7 @@ def main():
     for a in singles:
         a.close()
     lib.set_gate_fusion(fused)
+    lib.set_real_states(lib.REAL_AUTO)
     print(f"[sweep_bench] sequential {t_seq:.2f} s", file=sys.stderr, flush=True)
 
     # (b) batched

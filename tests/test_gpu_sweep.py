@@ -40,12 +40,15 @@ def entry(p):
 
 @pytest.fixture
 def unfused():
-    """The batched sweep runs gates one per pass; its point-by-point reference
-    must do the same for bitwise equality."""
+    """The batched sweep runs gates one per pass on complex64 states; its
+    point-by-point reference must do the same for bitwise equality (gate
+    fusion and real-state evaluations off)."""
     prev = lib.get_gate_fusion()
     lib.set_gate_fusion(lib.FUSE_OFF)
+    lib.set_real_states(lib.REAL_OFF)
     yield
     lib.set_gate_fusion(prev)
+    lib.set_real_states(lib.REAL_AUTO)
 
 
 def test_sweep_equals_unbatched_and_oracle(tmp_path, unfused):
