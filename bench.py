@@ -49,7 +49,8 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0
 METRIC = "ADAPT steps/s, Kitaev-Kerr L=8 d=8, |ΔE|<1e-5 vs ED; apply-H GB/s vs peak"
 KERNEL_NAMES = {0: "apply_h", 1: "pool_grads", 2: "gate2", 3: "gate2_adjoint", 4: "diag_gate", 9: "score",
-                10: "gate2_real", 11: "gate2_adjoint_real", 12: "real_convert", 13: "apply_h_real"}
+                10: "gate2_real", 11: "gate2_adjoint_real", 12: "real_convert", 13: "apply_h_real",
+                14: "gate2_real_fused", 15: "gate2_adjoint_real_fused"}
 
 
 def traffic_for(kid: int):
@@ -190,6 +191,8 @@ def main():
                     help="keep the ADAPT states in the full d^L layout (parity-halved layout off)")
     ap.add_argument("--complex-states", action="store_true",
                     help="evaluate every circuit on complex64 states (real states off)")
+    ap.add_argument("--no-real-fusion", action="store_true",
+                    help="run real-state gates and reverse steps gate by gate (fused runs off)")
     ap.add_argument("--prof-sample", type=int, default=4,
                     help="time one launch in this many per kernel family with HIP events (1: every launch)")
     ap.add_argument("--gate-fusion", type=int, choices=[0, 1, 2], default=None,
@@ -213,6 +216,8 @@ def main():
         lib.set_sector_layout(lib.SECTOR_OFF)
     if args.complex_states:
         lib.set_real_states(lib.REAL_OFF)
+    if args.no_real_fusion:
+        lib.set_real_fusion(lib.RFUSE_OFF)
     cfg = W.config("kk_l8_d8")
     hl = lib.ham_from(cfg)
     n = cfg["d"] ** cfg["L"]
@@ -345,16 +350,19 @@ def main():
             "adjoint_graph_replay": variant_graph(args.steps),
         }
         # the headline's state representations switched off one at a time, then both
-        for name, sector, real in (("full_layout", lib.SECTOR_OFF, lib.REAL_AUTO),
-                                   ("complex_states", lib.SECTOR_AUTO, lib.REAL_OFF),
-                                   ("full_layout_complex_states", lib.SECTOR_OFF, lib.REAL_OFF)):
+        for name, sector, real, fuse in (("unfused", lib.SECTOR_AUTO, lib.REAL_AUTO, lib.RFUSE_OFF),
+                                         ("full_layout", lib.SECTOR_OFF, lib.REAL_AUTO, lib.RFUSE_ON),
+                                         ("complex_states", lib.SECTOR_AUTO, lib.REAL_OFF, lib.RFUSE_ON),
+                                         ("full_layout_complex_states", lib.SECTOR_OFF, lib.REAL_OFF, lib.RFUSE_ON)):
             lib.set_sector_layout(sector)
             lib.set_real_states(real)
+            lib.set_real_fusion(fuse)
             try:
                 out["variants"]["adjoint_hessian_recycling_" + name] = variant(args.steps, recycle_hessian=rh)
             finally:
                 lib.set_sector_layout(lib.SECTOR_AUTO)
                 lib.set_real_states(lib.REAL_AUTO)
+                lib.set_real_fusion(lib.RFUSE_ON)
     if not args.no_variants and args.grad_mode == "adjoint" and not args.no_warm_start:
         print("[bench] warm-start leg: training data from 8 nearby points, network, proposals after selection",
               file=sys.stderr, flush=True)

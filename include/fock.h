@@ -550,6 +550,20 @@ enum { FOCK_REAL_OFF = 0, FOCK_REAL_AUTO = 1 };
 int fock_set_real_states(int mode);
 int fock_get_real_states(void);
 
+/* Fused runs of real gates.  An evaluation on real states (see adapt_real and
+ * FOCK_LAYOUT_REAL) at d = 8 with >= 2^21 stored amplitudes takes each run of
+ * >= 2 consecutive HR / PR gates whose pairs lie inside three consecutive modes
+ * (a, a+1, a+2; below the top mode in the parity-halved layout) as one pass:
+ * tiles of 32 (forward) or 16 (reverse) sets of the 512 amplitudes over those
+ * modes are staged in LDS, and the run's gates (Sec. II.B), or its reverse steps
+ * with their gradient terms (Sec. IV.B), are applied there in order.  States
+ * are the same bit for bit as gate by gate; gradient partials are summed per
+ * tile, so gradients agree to FP32/FP64 rounding.  At most 8 gates per run.
+ * Process-wide: FOCK_RFUSE_ON (default) or FOCK_RFUSE_OFF (gate by gate). */
+enum { FOCK_RFUSE_OFF = 0, FOCK_RFUSE_ON = 1 };
+int fock_set_real_fusion(int mode);
+int fock_get_real_fusion(void);
+
 /* ------------------------------------------------------------------ FP64 states */
 
 /* CV-ADAPT-VQE (Sec. IV.B) on complex128 states, for runs that resolve energy
@@ -645,7 +659,9 @@ enum { FOCK_K_APPLY_H = 0, FOCK_K_POOL = 1, FOCK_K_GATE = 2, FOCK_K_ADJ = 3, FOC
        FOCK_K_SCORE = 9 /* fused scoring: H psi and pool partials, fock_score / adapt_step */,
        FOCK_K_RGATE = 10, FOCK_K_RADJ = 11 /* gates and reverse steps on real states (adapt_real) */,
        FOCK_K_CONVERT = 12 /* real <-> complex64 state conversion around H psi */,
-       FOCK_K_APPLY_H_REAL = 13 /* two-pass H psi on real states */, FOCK_K_NUM = 14 };
+       FOCK_K_APPLY_H_REAL = 13 /* two-pass H psi on real states */,
+       FOCK_K_RFUSE = 14, FOCK_K_RFUSE_ADJ = 15 /* fused runs of real gates / reverse steps */,
+       FOCK_K_NUM = 16 };
 
 /* Enable/disable event timing of launches (off by default). */
 int fock_prof_enable(int on);

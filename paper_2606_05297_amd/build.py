@@ -34,7 +34,7 @@ SOURCES = [
     "kernels_gate_de.hip",
     "kernels_gate_df.hip",
     "gate_half.hip",
-    "gate_real.hip",
+    "gate_real.hip", "gate_real_fuse.hip",
     "sector.hip",
     "sweep_kernels.hip",
     "sweep.cpp",

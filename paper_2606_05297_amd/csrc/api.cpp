@@ -560,25 +560,88 @@ static bool real_eval(const Ctx &c, const fock_op_t *ops, int n) {
   return true;
 }
 
-// Gate tables of a real-state evaluation, with the real kernels' workgroup
-// counts as the reverse step's partial counts.
-static int stage_real(Ctx &c, const fock_op_t *ops, const double *theta, int n) {
+static std::atomic<int> g_real_fusion{FOCK_RFUSE_ON};
+
+// A run of a real-state evaluation: gates k0..k1-1 fused on modes a..a+2, or
+// (a < 0) gate k0 by itself.
+struct RealRun {
+  int k0, k1, a;
+};
+
+// Greedy runs: extend while every pair of the run lies inside one window of
+// three consecutive modes below the fusion's top mode; runs of one gate use the
+// per-gate kernels.
+static std::vector<RealRun> plan_real_runs(const Ctx &c, const fock_op_t *ops, int n) {
+  std::vector<RealRun> runs;
+  const bool on = g_real_fusion.load() == FOCK_RFUSE_ON && real_fuse_supported(c.g);
+  const int top = on ? real_fuse_top(c.g) : 0;
+  auto fusable = [&](int m) { return on && ops[m].i >= 0 && ops[m].j == ops[m].i + 1 && ops[m].j <= top; };
+  for (int k = 0; k < n;) {
+    int m = k + 1, lo = ops[k].i, hi = ops[k].i;
+    if (fusable(k))
+      for (; m < n && m - k < kRFuseMax && fusable(m); ++m) {
+        const int nlo = std::min(lo, ops[m].i), nhi = std::max(hi, ops[m].i);
+        if (nhi - nlo > 1) break;
+        lo = nlo;
+        hi = nhi;
+      }
+    if (m - k >= 2) {
+      runs.push_back({k, m, std::min(lo, top - 2)});
+    } else {
+      runs.push_back({k, k + 1, -1});
+      m = k + 1;
+    }
+    k = m;
+  }
+  return runs;
+}
+
+// Gate tables of a real-state evaluation, with the workgroup counts of the
+// kernels that take each gate's reverse step as its partial counts.
+static int stage_real(Ctx &c, const fock_op_t *ops, const double *theta, int n, std::vector<RealRun> *runs) {
+  *runs = plan_real_runs(c, ops, n);
   std::vector<int> nblk(n > 0 ? n : 1);
-  for (int k = 0; k < n; ++k) nblk[k] = real_gate_blocks(c.g, ops[k].i, ops[k].j);
+  for (const RealRun &r : *runs)
+    for (int k = r.k0; k < r.k1; ++k)
+      nblk[k] = r.a >= 0 ? real_fuse_blocks(c.g, true) : real_gate_blocks(c.g, ops[k].i, ops[k].j);
   return stage_gates(c, ops, theta, n, nblk.data());
+}
+
+static void real_run_ops(const Ctx &c, const fock_op_t *ops, const RealRun &r, bool reverse, RFuseOp *fo) {
+  const float2 *utab = (const float2 *)(c.ws + c.L.utab);
+  double *part = (double *)(c.ws + c.L.partial);
+  const int stride = gate_stride(c.g.d);
+  for (int k = r.k0; k < r.k1; ++k) {
+    RFuseOp &f = fo[k - r.k0];
+    f.kind = gate_kind(ops[k].type);
+    f.o = ops[k].i - r.a;
+    f.U = utab + (size_t)k * stride;
+    f.A = reverse ? c.T.A[table_slot(ops[k].type)] : nullptr;
+    f.part = reverse ? part + (size_t)k * c.L.rs : nullptr;
+  }
 }
 
 // phi_r = O_n..O_1 psi0_r (staged gates), then (phi != nullptr) phi = phi_r
 // widened to complex64.
-static int forward_real(Ctx &c, const fock_op_t *ops, int n, float2 *phi) {
+static int forward_real(Ctx &c, const fock_op_t *ops, int n, const std::vector<RealRun> &runs, float2 *phi) {
   const float2 *utab = (const float2 *)(c.ws + c.L.utab);
   const int stride = gate_stride(c.g.d);
   if (n == 0)
     FOCK_HIP(hipMemcpyAsync(c.phi_r, c.psi0_r, sizeof(float) * (size_t)c.g.n_amp, hipMemcpyDeviceToDevice, c.s));
-  for (int k = 0; k < n; ++k) {
-    ProfScope ps(FOCK_K_RGATE, c.s, 8.0 * c.g.n_amp);
-    const int rc = launch_rgate(c.g, ops[k].i, ops[k].j, gate_kind(ops[k].type), false, utab + (size_t)k * stride,
-                                k == 0 ? c.psi0_r : c.phi_r, c.phi_r, c.s);
+  for (const RealRun &r : runs) {
+    const float *src = r.k0 == 0 ? c.psi0_r : c.phi_r;
+    int rc;
+    if (r.a >= 0) {
+      RFuseOp fo[kRFuseMax];
+      real_run_ops(c, ops, r, false, fo);
+      ProfScope ps(FOCK_K_RFUSE, c.s, 8.0 * c.g.n_amp);
+      rc = launch_rfuse(c.g, r.a, r.k1 - r.k0, fo, src, c.phi_r, c.s);
+    } else {
+      const int k = r.k0;
+      ProfScope ps(FOCK_K_RGATE, c.s, 8.0 * c.g.n_amp);
+      rc = launch_rgate(c.g, ops[k].i, ops[k].j, gate_kind(ops[k].type), false, utab + (size_t)k * stride, src,
+                        c.phi_r, c.s);
+    }
     if (rc) return rc;
   }
   if (!phi) return FOCK_OK;
@@ -599,16 +662,25 @@ static int apply_h_real(Ctx &c, double *res2) {
 
 // Reverse sweep on real states from phi_r and lam_r = H phi_r: per gate the
 // partial sums of lam . A phi, then phi_r, lam_r <- U^T phi_r, U^T lam_r.
-static int reverse_real(Ctx &c, const fock_op_t *ops, int n, double *res) {
+static int reverse_real(Ctx &c, const fock_op_t *ops, int n, const std::vector<RealRun> &runs, double *res) {
   const float2 *utab = (const float2 *)(c.ws + c.L.utab);
   double *part = (double *)(c.ws + c.L.partial);
   const int stride = gate_stride(c.g.d);
-  for (int k = n - 1; k >= 0; --k) {
-    const fock_op_t &op = ops[k];
-    ProfScope ps(FOCK_K_RADJ, c.s, 16.0 * c.g.n_amp);
-    const int rc = launch_rgate_adj(c.g, op.i, op.j, gate_kind(op.type), utab + (size_t)k * stride,
-                                    c.T.A[table_slot(op.type)], c.phi_r, c.lam_r, part + (size_t)k * c.L.rs, c.s,
-                                    true);
+  for (auto it = runs.rbegin(); it != runs.rend(); ++it) {
+    const RealRun &r = *it;
+    int rc;
+    if (r.a >= 0) {
+      RFuseOp fo[kRFuseMax];
+      real_run_ops(c, ops, r, true, fo);
+      ProfScope ps(FOCK_K_RFUSE_ADJ, c.s, 16.0 * c.g.n_amp);
+      rc = launch_rfuse_adj(c.g, r.a, r.k1 - r.k0, fo, c.phi_r, c.lam_r, c.s);
+    } else {
+      const int k = r.k0;
+      const fock_op_t &op = ops[k];
+      ProfScope ps(FOCK_K_RADJ, c.s, 16.0 * c.g.n_amp);
+      rc = launch_rgate_adj(c.g, op.i, op.j, gate_kind(op.type), utab + (size_t)k * stride,
+                            c.T.A[table_slot(op.type)], c.phi_r, c.lam_r, part + (size_t)k * c.L.rs, c.s, true);
+    }
     if (rc) return rc;
   }
   return launch_reduce_rows(part, c.L.rs, (const GateRec *)(c.ws + c.L.recs), n, res, c.s);
@@ -619,10 +691,11 @@ static int reverse_real(Ctx &c, const fock_op_t *ops, int n, double *res) {
 int run_score(Ctx &c, const fock_op_t *ops, const double *theta, int n, const void *psi0, float2 *phi,
               float2 *lam, const fock_op_t *pool, int P, double *E, double *norm2, double *g) {
   std::vector<GateGroup> groups;
+  std::vector<RealRun> runs;
   const bool real = real_eval(c, ops, n);
-  int rc = real ? stage_real(c, ops, theta, n) : stage_circuit(c, ops, theta, n, &groups);
+  int rc = real ? stage_real(c, ops, theta, n, &runs) : stage_circuit(c, ops, theta, n, &groups);
   if (rc) return rc;
-  if ((rc = real ? forward_real(c, ops, n, phi) : forward_circuit(c, ops, n, groups, psi0, phi))) return rc;
+  if ((rc = real ? forward_real(c, ops, n, runs, phi) : forward_circuit(c, ops, n, groups, psi0, phi))) return rc;
   double *res = (double *)(c.ws + c.L.result);
   if ((rc = score_dev(c, pool, P, phi, lam, res))) return rc;
   std::vector<double> host(2 + P);
@@ -640,15 +713,16 @@ int run_score(Ctx &c, const fock_op_t *ops, const double *theta, int n, const vo
 int run_circuit(Ctx &c, const fock_op_t *ops, const double *theta, int n, const void *psi0, float2 *phi,
                        float2 *lam, bool grad, double *E, double *norm2, double *dE) {
   std::vector<GateGroup> groups;
+  std::vector<RealRun> runs;
   const bool real = real_eval(c, ops, n);
-  int rc = real ? stage_real(c, ops, theta, n) : stage_circuit(c, ops, theta, n, &groups);
+  int rc = real ? stage_real(c, ops, theta, n, &runs) : stage_circuit(c, ops, theta, n, &groups);
   if (rc) return rc;
   double *res = (double *)(c.ws + c.L.result);
   if (real) {
     // H psi on the real states when the slab passes take them, else on a
     // complex64 copy whose real part is kept
     const bool rh = apply_h2_real_supported(c.h) && c.h.slab;
-    if ((rc = forward_real(c, ops, n, rh ? nullptr : phi))) return rc;
+    if ((rc = forward_real(c, ops, n, runs, rh ? nullptr : phi))) return rc;
     if (rh) {
       if ((rc = apply_h_real(c, res))) return rc;
     } else {
@@ -658,7 +732,7 @@ int run_circuit(Ctx &c, const fock_op_t *ops, const double *theta, int n, const 
         if ((rc = launch_real_convert(c.g.n_amp, false, lam, c.lam_r, c.s))) return rc;
       }
     }
-    if (grad && n > 0 && (rc = reverse_real(c, ops, n, res + 2))) return rc;
+    if (grad && n > 0 && (rc = reverse_real(c, ops, n, runs, res + 2))) return rc;
   } else if (grad && use_store(c, ops, n, groups)) {
     // forward states kept: H psi_n reads the last one; phi is not touched
     if ((rc = forward_stored(c, ops, n, psi0))) return rc;
@@ -1232,6 +1306,15 @@ int fock_set_real_states(int mode) {
 }
 
 int fock_get_real_states(void) { return g_real_states.load(); }
+
+int fock_set_real_fusion(int mode) {
+  if (mode != FOCK_RFUSE_OFF && mode != FOCK_RFUSE_ON)
+    return set_error(FOCK_ERR_ARG, "real fusion mode %d is not OFF (0) or ON (1)", mode);
+  g_real_fusion.store(mode);
+  return FOCK_OK;
+}
+
+int fock_get_real_fusion(void) { return g_real_fusion.load(); }
 
 static int sector_convert(int L, int d, int layout, const void *src, void *dst, bool to_half, fock_stream_t stream) {
   if (d != 8) return set_error(FOCK_ERR_UNSUPPORTED, "the parity-halved layout needs d = 8 (d=%d)", d);

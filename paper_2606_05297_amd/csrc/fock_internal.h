@@ -296,6 +296,22 @@ int launch_rgate(const Geometry &g, int i, int j, int kind, bool dag, const floa
 int launch_rgate_adj(const Geometry &g, int i, int j, int kind, const float2 *U, const float2 *A, float *phi,
                      float *lam, double *partial, hipStream_t s, bool write_phi);
 int launch_real_convert(uint32_t n, bool to_complex, const void *src, void *dst, hipStream_t s);
+
+// Fused runs of real gates (gate_real_fuse.hip): ng <= kRFuseMax gates whose
+// pairs are tile modes (o, o+1) of modes a..a+2 (a + 2 <= real_fuse_top), in
+// circuit order; reverse: their reverse steps in reverse order, gate k's tile
+// partials into ops[k].part[0 .. real_fuse_blocks(g, true)).
+constexpr int kRFuseMax = 8;
+struct RFuseOp {
+  int kind, o;
+  const float2 *U, *A;
+  double *part;
+};
+bool real_fuse_supported(const Geometry &g);
+int real_fuse_top(const Geometry &g);
+int real_fuse_blocks(const Geometry &g, bool reverse);
+int launch_rfuse(const Geometry &g, int a, int ng, const RFuseOp *ops, const float *src, float *dst, hipStream_t s);
+int launch_rfuse_adj(const Geometry &g, int a, int ng, const RFuseOp *ops, float *phi, float *lam, hipStream_t s);
 int launch_imag_any(const float2 *c, uint32_t n, unsigned int *flag, hipStream_t s);
 
 // Parity sectors (sector.hip, d = 8): partial (even, odd) sums of |Re| + |Im|

@@ -114,6 +114,7 @@ def load(path: str = LIB_PATH):
     L.fock_prepare.argtypes = [C.c_int, C.c_int]
     L.fock_set_sector_layout.argtypes = [C.c_int]
     L.fock_set_real_states.argtypes = [C.c_int]
+    L.fock_set_real_fusion.argtypes = [C.c_int]
     L.adapt_real.argtypes = [vp, ip]
     L.fock_sector_pack.argtypes = [C.c_int, C.c_int, C.c_int, vp, vp, vp]
     L.fock_sector_unpack.argtypes = [C.c_int, C.c_int, C.c_int, vp, vp, vp]
@@ -316,6 +317,19 @@ def set_real_states(mode: int):
 
 def get_real_states() -> int:
     return int(load().fock_get_real_states())
+
+
+RFUSE_OFF, RFUSE_ON = 0, 1
+
+
+def set_real_fusion(mode: int):
+    """Fused runs of real gates (fock_set_real_fusion): RFUSE_ON (the
+    default) or RFUSE_OFF (gate by gate)."""
+    _check(load().fock_set_real_fusion(int(mode)))
+
+
+def get_real_fusion() -> int:
+    return int(load().fock_get_real_fusion())
 
 
 def set_sector_layout(mode: int):

@@ -367,6 +367,20 @@ def test_sector_layout_switch_and_argument_checks():
     assert L.fock_sector_unpack(8, 8, 1, None, None, None) == -1
 
 
+def test_real_fusion_switch():
+    """Fused runs of real gates default to ON and the switch takes only OFF
+    and ON."""
+    L = lib.load()
+    assert lib.get_real_fusion() == lib.RFUSE_ON
+    assert L.fock_set_real_fusion(2) == -1 and "ON" in lib.last_error()
+    lib.set_real_fusion(lib.RFUSE_OFF)
+    try:
+        assert lib.get_real_fusion() == lib.RFUSE_OFF
+    finally:
+        lib.set_real_fusion(lib.RFUSE_ON)
+    assert lib.get_real_fusion() == lib.RFUSE_ON
+
+
 def test_prepare_rejects_bad_geometry():
     """fock_prepare checks (L, d) like the other calls before touching a device."""
     L = lib.load()

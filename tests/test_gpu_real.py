@@ -220,3 +220,73 @@ def test_real_energy_and_adjoint_l8_d8(layout):
     with pytest.raises(lib.FockError) as e:  # a complex gate on real states
         lib.energy_grad_adjoint(hl, [("HI", 0, 1)], np.array([0.1]), x0, a, b, ws)
     assert e.value.code == -3
+
+
+# Runs chosen to cover every fused tile kind (a = 0, 1, >= 2), gates on both
+# tile pairs, a run from psi0 and one at the end, a run split at 8 gates, the
+# window below the top pair (a = 4) and, in the full layout only, the top
+# window (a = 5); the top pair of the halved layout stays a single gate.
+FUSE_OPS = ([("PR", 0, 1), ("HR", 1, 2), ("HR", 0, 1), ("PR", 6, 7),
+             ("HR", 3, 4), ("PR", 3, 4), ("HR", 2, 3),
+             ("HR", 1, 2), ("PR", 1, 2), ("PR", 2, 3),
+             ("PR", 5, 6), ("HR", 4, 5), ("PR", 5, 6), ("HR", 6, 7)]
+            + [("HR", 3, 4)] * 9
+            + [("PR", 5, 6), ("PR", 6, 7), ("HR", 5, 6), ("PR", 5, 6), ("HR", 0, 1), ("PR", 0, 1)])
+
+
+def fused_pair(hl, ops, th, x0, grad):
+    """The same evaluation with fused runs of real gates and gate by gate."""
+    outs = []
+    ws = lib.workspace(hl, 0, len(ops))
+    for mode in (lib.RFUSE_ON, lib.RFUSE_OFF):
+        lib.set_real_fusion(mode)
+        try:
+            a, b = torch.full_like(x0, float("nan")), torch.full_like(x0, float("nan"))
+            E, n2, g = lib.energy_grad_adjoint(hl, ops, th, x0, a, b, ws, grad=grad)
+            torch.cuda.synchronize()
+            outs.append((E, n2, g, a, b))
+        finally:
+            lib.set_real_fusion(lib.RFUSE_ON)
+    return outs
+
+
+_FUSED_ORACLE = {}
+
+
+def fused_oracle(ho, psi0, th):
+    """The oracle's energy, gradients, norm and final state of FUSE_OPS (the
+    same for both layouts: computed once)."""
+    if not _FUSED_ORACLE:
+        p0 = psi0.astype(np.float32).astype(np.complex128)
+        Eref, gref, n2ref = O.energy_and_grad_adjoint(ho, p0, FUSE_OPS, th, apply_h=O.apply_H_slices)
+        _FUSED_ORACLE["r"] = (Eref, gref, n2ref, O.ansatz_state(p0, FUSE_OPS, th, 8, 8))
+    return _FUSED_ORACLE["r"]
+
+
+@pytest.mark.parametrize("layout", REAL_LAYOUTS, ids=["full", "halved"])
+def test_real_fused_runs_match_gate_by_gate_l8_d8(layout):
+    """Fused runs against the per-gate kernels on the same evaluation: the final
+    state bit for bit (same block arithmetic in LDS), the energy and norm, phi
+    and lambda after the reverse sweep bit for bit, gradients to FP32 rounding
+    of the per-tile partial sums; then the fused evaluation against the
+    oracle's FP64 reverse sweep."""
+    assert lib.get_real_fusion() == lib.RFUSE_ON
+    ho, hl = ham_real(layout)
+    rng = np.random.default_rng(95)
+    th = rng.uniform(-0.4, 0.4, len(FUSE_OPS))
+    psi0 = real_state(97)
+    idx = stored_index(8, 8, 0) if layout & 3 else np.arange(8**8)
+    x0 = torch.from_numpy(psi0[idx].astype(np.float32)).to("cuda")
+    say("fused vs gate by gate, layout", layout, len(FUSE_OPS))
+    (Ef, nf, _, af, _), (Eu, nu, _, au, _) = fused_pair(hl, FUSE_OPS, th, x0, grad=False)
+    assert torch.equal(af, au)
+    assert Ef == Eu and nf == nu
+    (Ef, nf, gf, pf, lf), (Eu, nu, gu, pu, lu) = fused_pair(hl, FUSE_OPS, th, x0, grad=True)
+    assert Ef == Eu and nf == nu
+    assert torch.equal(pf, pu) and torch.equal(lf, lu)
+    assert np.abs(gf - gu).max() <= 2e-5 * max(1.0, np.abs(gu).max()), np.abs(gf - gu).max()
+    Eref, gref, n2ref, psi_n = fused_oracle(ho, psi0, th)
+    assert np.abs(af.cpu().numpy() - psi_n.real[idx]).max() <= 1e-5 * np.abs(psi_n).max() * len(FUSE_OPS) ** 0.5
+    assert abs(Ef - Eref) <= 1e-5 * max(1.0, abs(Eref))
+    assert abs(nf - n2ref) <= 1e-6 * len(FUSE_OPS)
+    assert np.abs(gf - gref).max() <= 1e-4 * max(1.0, np.abs(gref).max()), np.abs(gf - gref).max()
