@@ -51,9 +51,14 @@ FAMILIES = {
                       ("gate_kernels.h", "kernels_gate.hip", "gate_half.hip", "device_common.h")),
     "diag_gate": (((("k_diag", "k_diag_adj"),),), ("gate_kernels.h", "kernels_gate.hip", "device_common.h")),
     "apply_h_real": (((("k_h8_col_r",), ("k_h8_row_r",)),), ("stencil2.hip", "device_common.h")),
-    "gate2_real": (((("k_rgate2", "k_rgate2_m0p"),),), ("gate_real.hip", "gate_kernels.h", "device_common.h")),
+    "gate2_real": (((("k_rgate2", "k_rgate2_m0p"),),),
+                   ("gate_real.hip", "gate_real_groups.h", "gate_kernels.h", "device_common.h")),
     "gate2_adjoint_real": (((("k_rgate2_adj", "k_rgate2_adj_m0p"),),),
-                           ("gate_real.hip", "gate_kernels.h", "device_common.h")),
+                           ("gate_real.hip", "gate_real_groups.h", "gate_kernels.h", "device_common.h")),
+    "gate2_real_fused": (((("k_rfuse",),),),
+                         ("gate_real_fuse.hip", "gate_real_groups.h", "gate_kernels.h", "device_common.h")),
+    "gate2_adjoint_real_fused": (((("k_rfuse_adj",),),),
+                                 ("gate_real_fuse.hip", "gate_real_groups.h", "gate_kernels.h", "device_common.h")),
     "real_convert": (((("k_real_to_complex", "k_complex_to_real"),),), ("gate_real.hip", "device_common.h")),
 }
 
@@ -61,8 +66,10 @@ FAMILIES = {
 # stages of the ADAPT step for --split: (label, kernel base names); the last
 # entry takes every other kernel.
 SPLIT = [
-    ("reverse step on real states", ("k_rgate2_adj", "k_rgate2_adj_m0p")),
-    ("forward gates on real states", ("k_rgate2", "k_rgate2_m0p")),
+    ("fused reverse runs on real states", ("k_rfuse_adj",)),
+    ("fused forward runs on real states", ("k_rfuse",)),
+    ("reverse step on real states (single gates)", ("k_rgate2_adj", "k_rgate2_adj_m0p")),
+    ("forward gates on real states (single gates)", ("k_rgate2", "k_rgate2_m0p")),
     ("real <-> complex conversion", ("k_real_to_complex", "k_complex_to_real")),
     ("reverse step, top pair (6,7) of the parity-halved layout", ("k_gate2_adj_half",)),
     ("reverse step, mode-0 pair (0,1)", ("k_gate2_adj_m0p", "k_gate2_adj_m0")),
