@@ -138,6 +138,33 @@ __device__ __forceinline__ void rf_gstore(float *__restrict__ dst, uint32_t sa, 
   }
 }
 
+// The real parts of a gate's packed tables (U, and A for the reverse step)
+// staged in LDS: the next gate's tables are loaded while the current gate is
+// applied, so a gate phase starts without waiting on table loads.
+constexpr int kTabN = 344;  // sum of b^2 over the conserved blocks at d = 8
+struct LdsTab {
+  const float *p;
+  __device__ __forceinline__ float2 operator[](int i) const { return make_float2(p[i], 0.f); }
+};
+constexpr int kTabPer = (2 * kTabN + kBlock - 1) / kBlock;
+
+// this thread's share of the tables of one gate (nt = 1: U; 2: U then A)
+__device__ __forceinline__ void rf_tab_fetch(const float2 *U, const float2 *A, int nt, float (&r)[kTabPer]) {
+#pragma unroll
+  for (int j = 0; j < kTabPer; ++j) {
+    const int e = threadIdx.x + j * kBlock;
+    r[j] = e < kTabN ? U[e].x : (e < nt * kTabN ? A[e - kTabN].x : 0.f);
+  }
+}
+
+__device__ __forceinline__ void rf_tab_put(float *tab, int nt, const float (&r)[kTabPer]) {
+#pragma unroll
+  for (int j = 0; j < kTabPer; ++j) {
+    const int e = threadIdx.x + j * kBlock;
+    if (e < nt * kTabN) tab[e] = r[j];
+  }
+}
+
 // Fiber geometry of a gate on tile modes (O, O+1): member strides and the
 // stride of the third digit w.
 template <int TK, int R, int O>
@@ -157,26 +184,25 @@ __device__ __forceinline__ int rf_rest_off(int lane) {
 
 // psi <- U psi on group G of every fiber of the tile (64 fibers per round).
 template <int TK, int R, int KIND, int O, int G>
-__device__ __forceinline__ void rf_gate(float *tile, const float2 *__restrict__ U, int lane) {
+__device__ __forceinline__ void rf_gate(float *tile, LdsTab U, int lane) {
   using P = RPhase<TK, R, O>;
   float *rb = tile + rf_rest_off<TK, R>(lane);
 #pragma unroll 1
   for (int rho = 0; rho < R / 8; ++rho) {
     float *b = rb + P::SW * (lane / R + (64 / R) * rho);
-    rgate_group<KIND, false, G, false>(b, b, P::SI, P::SJ, U, 0);
+    rgate_group<KIND, false, G, false, LdsTab>(b, b, P::SI, P::SJ, U, 0);
   }
 }
 
 template <int TK, int R, int KIND, int O, int G>
-__device__ __forceinline__ float rf_adj(float *tp, float *tl, const float2 *__restrict__ U,
-                                        const float2 *__restrict__ A, int lane) {
+__device__ __forceinline__ float rf_adj(float *tp, float *tl, LdsTab U, LdsTab A, int lane) {
   using P = RPhase<TK, R, O>;
   const int rb = rf_rest_off<TK, R>(lane);
   float g = 0.f;
 #pragma unroll 1
   for (int rho = 0; rho < R / 8; ++rho) {
     const int b = rb + P::SW * (lane / R + (64 / R) * rho);
-    g += radj_group<KIND, G, true, false>(tp + b, tl + b, P::SI, P::SJ, U, A, 0);
+    g += radj_group<KIND, G, true, false, LdsTab>(tp + b, tl + b, P::SI, P::SJ, U, A, 0);
   }
   return g;
 }
@@ -190,14 +216,14 @@ __device__ __forceinline__ float rf_adj(float *tp, float *tl, const float2 *__re
   }
 
 template <int TK, int R, int KIND, int O>
-__device__ __forceinline__ void rf_gate_w(int wave, float *tile, const float2 *U, int lane) {
+__device__ __forceinline__ void rf_gate_w(int wave, float *tile, LdsTab U, int lane) {
 #define RFG(G) rf_gate<TK, R, KIND, O, G>(tile, U, lane)
   RF_WAVES(RFG)
 #undef RFG
 }
 
 template <int TK, int R, int KIND, int O>
-__device__ __forceinline__ float rf_adj_w(int wave, float *tp, float *tl, const float2 *U, const float2 *A, int lane) {
+__device__ __forceinline__ float rf_adj_w(int wave, float *tp, float *tl, LdsTab U, LdsTab A, int lane) {
   float g = 0.f;
 #define RFA(G) g = rf_adj<TK, R, KIND, O, G>(tp, tl, U, A, lane)
   RF_WAVES(RFA)
@@ -210,17 +236,23 @@ __global__ __launch_bounds__(kBlock) void k_rfuse(const float *src, float *dst, 
   constexpr int R = kRFuseR;
   using T = RTile<TK, R>;
   __shared__ __align__(16) float tile[T::SIZE];
+  __shared__ float tab[2][kTabN];
   const uint32_t t = (uint32_t)xcd_remap(blockIdx.x, gridDim.x);
   const uint32_t gb = rf_tile_base<TK, R>(t, a);
+  float r[kTabPer];
   {
     float4 v[T::PER];
     rf_gload<TK, R>(src + gb, a.sa, v);
+    rf_tab_fetch(a.U[0], nullptr, 1, r);
     rf_lput<TK, R>(tile, a.sa, v);
+    rf_tab_put(tab[0], 1, r);
   }
   __syncthreads();
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   for (int gi = 0; gi < a.ng; ++gi) {
-    const float2 *U = a.U[gi];
+    const bool more = gi + 1 < a.ng;
+    if (more) rf_tab_fetch(a.U[gi + 1], nullptr, 1, r);
+    const LdsTab U{tab[gi & 1]};
     if (a.kind[gi] == KIND_SUM) {
       if (a.o[gi] == 0) rf_gate_w<TK, R, KIND_SUM, 0>(wave, tile, U, lane);
       else rf_gate_w<TK, R, KIND_SUM, 1>(wave, tile, U, lane);
@@ -228,6 +260,7 @@ __global__ __launch_bounds__(kBlock) void k_rfuse(const float *src, float *dst, 
       if (a.o[gi] == 0) rf_gate_w<TK, R, KIND_DIFF, 0>(wave, tile, U, lane);
       else rf_gate_w<TK, R, KIND_DIFF, 1>(wave, tile, U, lane);
     }
+    if (more) rf_tab_put(tab[(gi + 1) & 1], 1, r);
     __syncthreads();
   }
   rf_gstore<TK, R>(dst + gb, a.sa, tile);
@@ -239,20 +272,25 @@ __global__ __launch_bounds__(kBlock) void k_rfuse_adj(float *__restrict__ phi, f
   using T = RTile<TK, R>;
   __shared__ __align__(16) float tp[T::SIZE];
   __shared__ __align__(16) float tl[T::SIZE];
+  __shared__ float tab[2][2 * kTabN];
   __shared__ double red[4];
   const uint32_t t = (uint32_t)xcd_remap(blockIdx.x, gridDim.x);
   const uint32_t gb = rf_tile_base<TK, R>(t, a);
+  float r[kTabPer];
   {
     float4 vp[T::PER], vl[T::PER];
     rf_gload<TK, R>(phi + gb, a.sa, vp);
     rf_gload<TK, R>(lam + gb, a.sa, vl);
+    rf_tab_fetch(a.U[a.ng - 1], a.A[a.ng - 1], 2, r);
     rf_lput<TK, R>(tp, a.sa, vp);
     rf_lput<TK, R>(tl, a.sa, vl);
+    rf_tab_put(tab[(a.ng - 1) & 1], 2, r);
   }
   __syncthreads();
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   for (int gi = a.ng - 1; gi >= 0; --gi) {
-    const float2 *U = a.U[gi], *A = a.A[gi];
+    if (gi > 0) rf_tab_fetch(a.U[gi - 1], a.A[gi - 1], 2, r);
+    const LdsTab U{tab[gi & 1]}, A{tab[gi & 1] + kTabN};
     float g;
     if (a.kind[gi] == KIND_SUM) {
       g = a.o[gi] == 0 ? rf_adj_w<TK, R, KIND_SUM, 0>(wave, tp, tl, U, A, lane)
@@ -261,6 +299,7 @@ __global__ __launch_bounds__(kBlock) void k_rfuse_adj(float *__restrict__ phi, f
       g = a.o[gi] == 0 ? rf_adj_w<TK, R, KIND_DIFF, 0>(wave, tp, tl, U, A, lane)
                        : rf_adj_w<TK, R, KIND_DIFF, 1>(wave, tp, tl, U, A, lane);
     }
+    if (gi > 0) rf_tab_put(tab[(gi - 1) & 1], 2, r);
     // the reduction's barriers also order this step's LDS writes before the next
     const double sg = block_sum_d((double)g, red);
     if (threadIdx.x == 0) a.part[gi][t] = sg;

@@ -27,10 +27,10 @@ __device__ __forceinline__ uint32_t rmember(int s, int a, uint32_t si, uint32_t 
 }
 
 // psi <- U src (U^T src when DAG) on group G of one fiber; HALF: the top pair
-// of the parity-halved layout, ps = lower modes' parity plus the sector.
-template <int KIND, bool DAG, int G, bool HALF>
-__device__ __forceinline__ void rgate_group(const float *src, float *base, uint32_t si, uint32_t sj,
-                                            const float2 *__restrict__ U, int ps) {
+// of the parity-halved layout, ps = lower modes' parity plus the sector.  UP
+// reads the packed table: a global pointer, or a table staged in LDS.
+template <int KIND, bool DAG, int G, bool HALF, class UP = const float2 *__restrict__>
+__device__ __forceinline__ void rgate_group(const float *src, float *base, uint32_t si, uint32_t sj, UP U, int ps) {
   constexpr int D = kRD;
   constexpr Groups<D, kRNG> P{};
   float v[D * D];
@@ -69,9 +69,8 @@ __device__ __forceinline__ void rgate_group(const float *src, float *base, uint3
 
 // Reverse step on group G: sum lam . (A phi) over the group's members, then
 // phi <- U^T phi (when WPHI) and lam <- U^T lam.
-template <int KIND, int G, bool WPHI, bool HALF>
-__device__ __forceinline__ float radj_group(float *pb, float *lb, uint32_t si, uint32_t sj,
-                                            const float2 *__restrict__ U, const float2 *__restrict__ A, int ps) {
+template <int KIND, int G, bool WPHI, bool HALF, class UP = const float2 *__restrict__>
+__device__ __forceinline__ float radj_group(float *pb, float *lb, uint32_t si, uint32_t sj, UP U, UP A, int ps) {
   constexpr int D = kRD;
   constexpr Groups<D, kRNG> P{};
   float pv[D * D], lv[D * D];
