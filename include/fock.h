@@ -564,6 +564,16 @@ enum { FOCK_RFUSE_OFF = 0, FOCK_RFUSE_ON = 1 };
 int fock_set_real_fusion(int mode);
 int fock_get_real_fusion(void);
 
+/* The runs that an evaluation of ops[0..n) on real states would launch under
+ * the current fusion mode (host only: no device work).  run_k0[r] is the first
+ * gate of run r (runs are consecutive and cover the circuit in order), run_a[r]
+ * the lowest of its three tile modes, or -1 for a gate taken by the per-gate
+ * kernels; *nruns receives the count.  ham->layout selects the geometry (full
+ * or parity-halved; FOCK_LAYOUT_REAL optional).  run_k0 and run_a hold n
+ * entries (caller owned).  Errors: FOCK_ERR_ARG (layout, pairs, NULL arrays),
+ * FOCK_ERR_UNSUPPORTED (a gate other than HR or PR). */
+int fock_real_fusion_plan(const fock_ham_t *ham, const fock_op_t *ops, int n, int *run_k0, int *run_a, int *nruns);
+
 /* ------------------------------------------------------------------ FP64 states */
 
 /* CV-ADAPT-VQE (Sec. IV.B) on complex128 states, for runs that resolve energy

@@ -571,10 +571,10 @@ struct RealRun {
 // Greedy runs: extend while every pair of the run lies inside one window of
 // three consecutive modes below the fusion's top mode; runs of one gate use the
 // per-gate kernels.
-static std::vector<RealRun> plan_real_runs(const Ctx &c, const fock_op_t *ops, int n) {
+static std::vector<RealRun> plan_real_runs(const Geometry &g, const fock_op_t *ops, int n) {
   std::vector<RealRun> runs;
-  const bool on = g_real_fusion.load() == FOCK_RFUSE_ON && real_fuse_supported(c.g);
-  const int top = on ? real_fuse_top(c.g) : 0;
+  const bool on = g_real_fusion.load() == FOCK_RFUSE_ON && real_fuse_supported(g);
+  const int top = on ? real_fuse_top(g) : 0;
   auto fusable = [&](int m) { return on && ops[m].i >= 0 && ops[m].j == ops[m].i + 1 && ops[m].j <= top; };
   for (int k = 0; k < n;) {
     int m = k + 1, lo = ops[k].i, hi = ops[k].i;
@@ -599,7 +599,7 @@ static std::vector<RealRun> plan_real_runs(const Ctx &c, const fock_op_t *ops, i
 // Gate tables of a real-state evaluation, with the workgroup counts of the
 // kernels that take each gate's reverse step as its partial counts.
 static int stage_real(Ctx &c, const fock_op_t *ops, const double *theta, int n, std::vector<RealRun> *runs) {
-  *runs = plan_real_runs(c, ops, n);
+  *runs = plan_real_runs(c.g, ops, n);
   std::vector<int> nblk(n > 0 ? n : 1);
   for (const RealRun &r : *runs)
     for (int k = r.k0; k < r.k1; ++k)
@@ -1246,6 +1246,30 @@ int fock_energy_grad_adjoint(const fock_ham_t *ham, const fock_op_t *ops, const 
   }
   return run_circuit(c, ops, theta, n, psi0, (float2 *)psi_work, (float2 *)lam_work, dEdtheta != nullptr, E, norm2,
                      dEdtheta);
+}
+
+int fock_real_fusion_plan(const fock_ham_t *ham, const fock_op_t *ops, int n, int *run_k0, int *run_a,
+                          int *nruns) {
+  uint32_t namp = 0;
+  int rc = check_ham_layout(ham, &namp, true);
+  if (rc) return rc;
+  if (n < 0 || n > 4096) return set_error(FOCK_ERR_ARG, "n=%d out of range", n);
+  if (n > 0 && (!ops || !run_k0 || !run_a)) return set_error(FOCK_ERR_ARG, "ops/run_k0/run_a is NULL");
+  if (!nruns) return set_error(FOCK_ERR_ARG, "nruns is NULL");
+  for (int k = 0; k < n; ++k) {
+    if ((rc = check_op(ops[k], ham->L))) return rc;
+    if (ops[k].type != FOCK_HR && ops[k].type != FOCK_PR)
+      return set_error(FOCK_ERR_UNSUPPORTED, "real states take HR and PR gates only (gate %d)", k);
+  }
+  Geometry g{ham->L, ham->d, namp};
+  g.half = (ham->layout & 3) != FOCK_LAYOUT_FULL ? 1 : 0;
+  const std::vector<RealRun> runs = plan_real_runs(g, ops, n);
+  for (size_t r = 0; r < runs.size(); ++r) {
+    run_k0[r] = runs[r].k0;
+    run_a[r] = runs[r].a;
+  }
+  *nruns = (int)runs.size();
+  return FOCK_OK;
 }
 
 int fock_score(const fock_ham_t *ham, const fock_op_t *pool, int P, const void *psi, void *hpsi, double *E,

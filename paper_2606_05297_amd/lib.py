@@ -115,6 +115,7 @@ def load(path: str = LIB_PATH):
     L.fock_set_sector_layout.argtypes = [C.c_int]
     L.fock_set_real_states.argtypes = [C.c_int]
     L.fock_set_real_fusion.argtypes = [C.c_int]
+    L.fock_real_fusion_plan.argtypes = [C.POINTER(Ham), C.POINTER(Op), C.c_int, ip, ip, ip]
     L.adapt_real.argtypes = [vp, ip]
     L.fock_sector_pack.argtypes = [C.c_int, C.c_int, C.c_int, vp, vp, vp]
     L.fock_sector_unpack.argtypes = [C.c_int, C.c_int, C.c_int, vp, vp, vp]
@@ -330,6 +331,17 @@ def set_real_fusion(mode: int):
 
 def get_real_fusion() -> int:
     return int(load().fock_get_real_fusion())
+
+
+def real_fusion_plan(h: Ham, ops):
+    """[(first gate, lowest tile mode or -1), ...]: the runs an evaluation of
+    ops on real states launches (fock_real_fusion_plan; host only)."""
+    n = len(ops)
+    k0 = (C.c_int * max(n, 1))()
+    a = (C.c_int * max(n, 1))()
+    nr = C.c_int(0)
+    _check(load().fock_real_fusion_plan(C.byref(h), ops_array(ops), n, k0, a, C.byref(nr)))
+    return [(k0[r], a[r]) for r in range(nr.value)]
 
 
 def set_sector_layout(mode: int):

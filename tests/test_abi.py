@@ -381,6 +381,67 @@ def test_real_fusion_switch():
     assert lib.get_real_fusion() == lib.RFUSE_ON
 
 
+def _runs_from_definition(ops, top, on=True):
+    """Greedy runs written from their definition: extend while every pair of
+    the run lies in one window of three consecutive modes at or below `top`
+    (at most 8 gates); a run of one gate is a single gate (-1)."""
+    runs, k, n = [], 0, len(ops)
+    ok = [on and o[2] == o[1] + 1 and o[2] <= top for o in ops]
+    while k < n:
+        m = k + 1
+        if ok[k]:
+            lo = hi = ops[k][1]
+            while m < n and m - k < 8 and ok[m] and max(hi, ops[m][1]) - min(lo, ops[m][1]) <= 1:
+                lo, hi = min(lo, ops[m][1]), max(hi, ops[m][1])
+                m += 1
+        if m - k >= 2:
+            a = min(lo, top - 2)
+            assert a <= lo and hi + 1 <= a + 2 and a >= 0
+            runs.append((k, a))
+        else:
+            runs.append((k, -1))
+            m = k + 1
+        k = m
+    return runs
+
+
+def test_real_fusion_plan():
+    """The run planner of real-state evaluations (host only): the benchmark's
+    ansatz, the top pair of the parity-halved layout left single, the top
+    window of the full layout, runs split at 8 gates, small states unfused,
+    fusion switched off; every run's pairs inside its tile's three modes."""
+    bench = [("PR", b, b + 1) for b in range(7)] + [("HR", 0, 1), ("PR", 1, 2), ("PR", 0, 1), ("PR", 2, 3),
+                                                     ("HR", 2, 3), ("HR", 1, 2), ("PR", 1, 2), ("PR", 2, 3),
+                                                     ("PR", 3, 4), ("HR", 3, 4), ("PR", 3, 4), ("PR", 4, 5),
+                                                     ("HR", 4, 5)]
+    mixed = [("PR", 5, 6), ("PR", 6, 7), ("HR", 5, 6)] + [("HR", 3, 4)] * 10 + [("PR", 0, 1)]
+    halved, full = lib.ham(8, 8, layout=lib.LAYOUT_EVEN | lib.LAYOUT_REAL), lib.ham(8, 8, layout=lib.LAYOUT_REAL)
+    for h, top in ((halved, 6), (full, 7)):
+        for ops in (bench, mixed, [], [("HR", 2, 3)]):
+            got = lib.real_fusion_plan(h, ops)
+            assert got == _runs_from_definition(ops, top), (top, ops, got)
+            bounds = [r[0] for r in got] + [len(ops)]
+            for (k0, a), k1 in zip(got, bounds[1:]):
+                if a >= 0:
+                    assert k1 - k0 >= 2 and all(a <= o[1] and o[2] <= a + 2 for o in ops[k0:k1])
+    assert lib.real_fusion_plan(halved, bench) == [(0, 0), (2, 2), (4, 4), (6, -1), (7, 0), (10, 1), (15, 3)]
+    # the top pair joins a run only in the full layout
+    assert lib.real_fusion_plan(halved, mixed)[:2] == [(0, -1), (1, -1)]
+    assert lib.real_fusion_plan(full, mixed)[0] == (0, 5)
+    # states below 2^21 stored amplitudes, and fusion off: every gate by itself
+    small = lib.ham(6, 8)
+    assert lib.real_fusion_plan(small, bench[:5]) == [(k, -1) for k in range(5)]
+    lib.set_real_fusion(lib.RFUSE_OFF)
+    try:
+        assert lib.real_fusion_plan(halved, bench) == [(k, -1) for k in range(len(bench))]
+    finally:
+        lib.set_real_fusion(lib.RFUSE_ON)
+    with pytest.raises(lib.FockError):
+        lib.real_fusion_plan(halved, [("HI", 0, 1)])
+    with pytest.raises(lib.FockError):
+        lib.real_fusion_plan(halved, [("HR", 0, 8)])
+
+
 def test_prepare_rejects_bad_geometry():
     """fock_prepare checks (L, d) like the other calls before touching a device."""
     L = lib.load()

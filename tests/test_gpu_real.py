@@ -290,3 +290,38 @@ def test_real_fused_runs_match_gate_by_gate_l8_d8(layout):
     assert abs(Ef - Eref) <= 1e-5 * max(1.0, abs(Eref))
     assert abs(nf - n2ref) <= 1e-6 * len(FUSE_OPS)
     assert np.abs(gf - gref).max() <= 1e-4 * max(1.0, np.abs(gref).max()), np.abs(gf - gref).max()
+
+
+def test_real_fused_adapt_l7_d8():
+    """ADAPT on an L=7 chain (2^21 amplitudes, full layout: the smallest state
+    the fused runs take) with fused runs and gate by gate: the same selections,
+    energies to FP32 rounding, and the oracle replay of the final ansatz."""
+    L = 7
+    cc = dict(L=L, d=8, periodic=False, J=1.0, U=0.0, mu=0.0, Delta=0.5, K=0.2)
+    hl = lib.ham_from(cc)
+    pool = W.pool(L, "nn", False, W.KITAEV_TYPES)
+    psi0 = O.fock_state(L, 8, [0] * L)
+    assert len(lib.real_fusion_plan(hl, [("PR", 0, 1), ("PR", 1, 2)])) == 1
+    say("fused vs gate by gate ADAPT, L", L)
+    a = lib.Adapt(hl, pool, dev(psi0), max_iters=30, recycle_hessian=True)
+    b = lib.Adapt(hl, pool, dev(psi0), max_iters=30, recycle_hessian=True)
+    assert a.real() and b.real()
+    ra = None
+    try:
+        for _ in range(9):
+            ra = a.step()
+            lib.set_real_fusion(lib.RFUSE_OFF)
+            try:
+                rb = b.step()
+            finally:
+                lib.set_real_fusion(lib.RFUSE_ON)
+            assert ra["k_sel"] == rb["k_sel"]
+            assert abs(ra["E"] - rb["E"]) <= 1e-6 * max(1.0, abs(rb["E"]))
+        ops, th = a.ansatz()
+        runs = lib.real_fusion_plan(hl, ops)
+        assert any(r[1] >= 0 for r in runs) and len(runs) < len(ops)
+        Eo = O.energy_of(oham(cc), psi0, ops, th)
+        assert abs(ra["E"] - Eo) <= 1e-5 * max(1.0, abs(Eo))
+    finally:
+        a.close()
+        b.close()
