@@ -202,6 +202,22 @@ int make_ctx(const fock_ham_t &ham, uint32_t namp, int P, int n, void *ws, size_
 
 int stage_gates(Ctx &c, const fock_op_t *ops, const double *theta, int n, const int *nblk) {
   const int stride = gate_stride(c.g.d);
+  if (n <= kArgGates) {  // angles and records ride in the build kernel's arguments
+    GateArgs ga;
+    memset(&ga, 0, sizeof(ga));
+    ga.n = n;
+    const int Gd = diag_blocks_count(c.g);
+    for (int k = 0; k < n; ++k) {
+      if (!std::isfinite(theta[k])) return set_error(FOCK_ERR_NONFINITE, "theta[%d] is not finite", k);
+      ga.theta[k] = theta[k];
+      GateRec &r = ga.rec[k];
+      r.type = ops[k].type;
+      r.u_off = k * stride;
+      r.nblk = nblk && nblk[k] > 0 ? nblk[k] : is_single_mode(ops[k].type) ? Gd : gate_blocks_count(c.g, ops[k].i);
+    }
+    return launch_gate_build_args(ga, c.T, (float2 *)(c.ws + c.L.utab), (double *)(c.ws + c.L.theta),
+                                  (GateRec *)(c.ws + c.L.recs), c.s);
+  }
   const size_t bt = sizeof(double) * n, br = sizeof(GateRec) * n;
   int rc = tl_in.reserve(c.L.recs + br);
   if (rc) return rc;

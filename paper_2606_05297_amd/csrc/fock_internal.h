@@ -121,6 +121,15 @@ struct EigTables {
   int d, psize;
 };
 
+// Angles and gate records of a short circuit, passed to the table build as
+// kernel arguments instead of through a staging copy.
+constexpr int kArgGates = 64;
+struct GateArgs {
+  int n, pad;
+  double theta[kArgGates];
+  GateRec rec[kArgGates];
+};
+
 // Parity-halved layout (d = 8, open chain, states of one total parity sigma):
 // the top mode L-1 stores m = 0..d/2-1 and n_{L-1} = 2 m + ((n_0 + .. + n_{L-2}
 // + sigma) mod 2), so a state holds d^L / 2 amplitudes at index
@@ -183,6 +192,8 @@ int launch_pool(const PoolArgs &a, const PoolPair *pairs, const PoolDiag *diags,
 int pool_blocks(const PoolArgs &a);
 int launch_gate_build(const double *theta, const GateRec *recs, int n, const EigTables &T, float2 *utab,
                       hipStream_t s);
+int launch_gate_build_args(const GateArgs &ga, const EigTables &T, float2 *utab, double *theta_out,
+                           GateRec *recs_out, hipStream_t s);
 // psi <- U src (dag = false) or U^+ src (dag = true) for a two-mode gate on
 // (i, j); src == psi applies it in place.
 int launch_gate(const Geometry &g, int i, int j, int kind, bool dag, const float2 *U, const float2 *src, float2 *psi,

@@ -26,14 +26,9 @@ FOCK_GATE_EXTERN(12) FOCK_GATE_EXTERN(13) FOCK_GATE_EXTERN(14) FOCK_GATE_EXTERN(
 // ---------------------------------------------------------------- device-side gate build
 // U = V diag(exp(i theta lambda)) V^+ per conserved block, from the FP64
 // eigendata of G = -i A (A = i G), computed once per (type, d) on the host.
-__global__ __launch_bounds__(kBlock) void k_gate_build(const double *__restrict__ theta,
-                                                       const GateRec *__restrict__ recs, int n, EigTables T,
-                                                       float2 *__restrict__ utab) {
-  const int k = blockIdx.y;
-  const int e = blockIdx.x * kBlock + threadIdx.x;
-  if (k >= n) return;
-  const GateRec r = recs[k];
-  const double th = theta[k];
+// Entry e of gate table r at angle th.
+__device__ __forceinline__ void gate_build_entry(const GateRec &r, double th, int e, const EigTables &T,
+                                                 float2 *__restrict__ utab) {
   const int d = T.d;
   if (r.type == FOCK_KERR || r.type == FOCK_ROT) {
     if (e < d) {
@@ -87,6 +82,41 @@ __global__ __launch_bounds__(kBlock) void k_gate_build(const double *__restrict_
     ui += ti * qr - tr * qi;
   }
   utab[r.u_off + e] = make_float2((float)ur, (float)ui);
+}
+
+__global__ __launch_bounds__(kBlock) void k_gate_build(const double *__restrict__ theta,
+                                                       const GateRec *__restrict__ recs, int n, EigTables T,
+                                                       float2 *__restrict__ utab) {
+  const int k = blockIdx.y;
+  if (k >= n) return;
+  gate_build_entry(recs[k], theta[k], blockIdx.x * kBlock + threadIdx.x, T, utab);
+}
+
+// The same with the angles and records in the kernel arguments (no staging
+// copy); workgroup (0, k) also stores gate k's record and angle for the
+// kernels that read them later (the reduction of the reverse-step partials).
+__global__ __launch_bounds__(kBlock) void k_gate_build_args(GateArgs ga, EigTables T, float2 *__restrict__ utab,
+                                                            double *__restrict__ theta_out,
+                                                            GateRec *__restrict__ recs_out) {
+  const int k = blockIdx.y;
+  if (k >= ga.n) return;
+  const GateRec r = ga.rec[k];
+  const double th = ga.theta[k];
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    theta_out[k] = th;
+    recs_out[k] = r;
+  }
+  gate_build_entry(r, th, blockIdx.x * kBlock + threadIdx.x, T, utab);
+}
+
+int launch_gate_build_args(const GateArgs &ga, const EigTables &T, float2 *utab, double *theta_out,
+                           GateRec *recs_out, hipStream_t s) {
+  if (ga.n <= 0) return FOCK_OK;
+  if (ga.n > kArgGates) return set_error(FOCK_ERR_SIZE, "%d gates in the kernel arguments (at most %d)", ga.n, kArgGates);
+  const int ex = (T.psize + kBlock - 1) / kBlock;
+  hipLaunchKernelGGL(k_gate_build_args, dim3(ex, ga.n), dim3(kBlock), 0, s, ga, T, utab, theta_out, recs_out);
+  FOCK_HIP(hipGetLastError());
+  return FOCK_OK;
 }
 
 int launch_gate_build(const double *theta, const GateRec *recs, int n, const EigTables &T, float2 *utab,
