@@ -273,7 +273,7 @@ __global__ __launch_bounds__(kBlock) void k_rfuse_adj(float *__restrict__ phi, f
   __shared__ __align__(16) float tp[T::SIZE];
   __shared__ __align__(16) float tl[T::SIZE];
   __shared__ float tab[2][2 * kTabN];
-  __shared__ double red[4];
+  __shared__ double red[kRFuseMax][4];  // per gate and wave: sums of lambda . A phi
   const uint32_t t = (uint32_t)xcd_remap(blockIdx.x, gridDim.x);
   const uint32_t gb = rf_tile_base<TK, R>(t, a);
   float r[kTabPer];
@@ -300,9 +300,13 @@ __global__ __launch_bounds__(kBlock) void k_rfuse_adj(float *__restrict__ phi, f
                        : rf_adj_w<TK, R, KIND_DIFF, 1>(wave, tp, tl, U, A, lane);
     }
     if (gi > 0) rf_tab_put(tab[(gi - 1) & 1], 2, r);
-    // the reduction's barriers also order this step's LDS writes before the next
-    const double sg = block_sum_d((double)g, red);
-    if (threadIdx.x == 0) a.part[gi][t] = sg;
+    const double sw = wave_sum_d((double)g);
+    if (lane == 0) red[gi][wave] = sw;
+    __syncthreads();  // this step's LDS writes before the next step reads them
+  }
+  if (threadIdx.x < a.ng) {
+    const double *w = red[threadIdx.x];
+    a.part[threadIdx.x][t] = (w[0] + w[1]) + (w[2] + w[3]);
   }
   rf_gstore<TK, R>(phi + gb, a.sa, tp);
   rf_gstore<TK, R>(lam + gb, a.sa, tl);
