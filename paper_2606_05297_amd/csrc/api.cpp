@@ -151,7 +151,9 @@ Layout make_layout(uint32_t namp, int Lm, int d, int P, int n, int half) {
   L.utab = o;
   o = al(o + sizeof(float2) * (size_t)gate_stride(d) * L.nmax);
   L.partial = o;
-  const size_t rows = std::max<size_t>({2, (size_t)L.nmax, (size_t)L.pmax});
+  // gate rows, plus two rows after them for the energy partials of a gradient
+  // evaluation on real states (reduced with the gate rows)
+  const size_t rows = std::max<size_t>({2, (size_t)L.nmax + 2, (size_t)L.pmax});
   o = al(o + sizeof(double) * rows * std::max(L.G, L.rs));
   L.result = o;
   o = al(o + sizeof(double) * (2 + std::max(L.nmax, std::max(P, 1))));
@@ -665,20 +667,30 @@ static int forward_real(Ctx &c, const fock_op_t *ops, int n, const std::vector<R
   return launch_real_convert(c.g.n_amp, true, c.phi_r, phi, c.s);
 }
 
-// H phi_r into lam_r and (<psi|H psi>, <psi|psi>) into res2, on real states.
-static int apply_h_real(Ctx &c, double *res2) {
+// H phi_r into lam_r and (<psi|H psi>, <psi|psi>) into res2, on real states;
+// with defer, the energy partials go to the two rows after the n gate rows
+// and *G receives their count, for reverse_real's reduction.
+static int apply_h_real(Ctx &c, double *res2, int n = 0, bool defer = false, int *Gout = nullptr) {
   int G = 0;
+  double *part = (double *)(c.ws + c.L.partial) + (defer ? (size_t)n * c.L.rs : 0);
   {
     ProfScope ps(FOCK_K_APPLY_H_REAL, c.s, 8.0 * c.g.n_amp);
-    const int rc = launch_apply_h2_real(c.h, c.phi_r, c.lam_r, (double *)(c.ws + c.L.partial), &G, c.s);
+    const int rc = launch_apply_h2_real(c.h, c.phi_r, c.lam_r, part, &G, c.s);
     if (rc) return rc;
   }
-  return launch_reduce((const double *)(c.ws + c.L.partial), G, 2, res2, c.s);
+  if (defer) {
+    if (G > std::max(c.L.G, c.L.rs) || n > c.L.nmax)  // rows n, n + 1 hold the 2 G partials
+      return set_error(FOCK_ERR_SIZE, "energy partials beyond the workspace");
+    *Gout = G;
+    return FOCK_OK;
+  }
+  return launch_reduce(part, G, 2, res2, c.s);
 }
 
 // Reverse sweep on real states from phi_r and lam_r = H phi_r: per gate the
 // partial sums of lam . A phi, then phi_r, lam_r <- U^T phi_r, U^T lam_r.
-static int reverse_real(Ctx &c, const fock_op_t *ops, int n, const std::vector<RealRun> &runs, double *res) {
+static int reverse_real(Ctx &c, const fock_op_t *ops, int n, const std::vector<RealRun> &runs, double *res,
+                        int Ge = 0) {
   const float2 *utab = (const float2 *)(c.ws + c.L.utab);
   double *part = (double *)(c.ws + c.L.partial);
   const int stride = gate_stride(c.g.d);
@@ -699,6 +711,9 @@ static int reverse_real(Ctx &c, const fock_op_t *ops, int n, const std::vector<R
     }
     if (rc) return rc;
   }
+  if (Ge > 0)  // with the energy partials of apply_h_real(defer): res[0..1] and res[2..]
+    return launch_reduce_rows_energy(part, c.L.rs, (const GateRec *)(c.ws + c.L.recs), n, part + (size_t)n * c.L.rs,
+                                     Ge, res, c.s);
   return launch_reduce_rows(part, c.L.rs, (const GateRec *)(c.ws + c.L.recs), n, res, c.s);
 }
 
@@ -739,16 +754,22 @@ int run_circuit(Ctx &c, const fock_op_t *ops, const double *theta, int n, const 
     // complex64 copy whose real part is kept
     const bool rh = apply_h2_real_supported(c.h) && c.h.slab;
     if ((rc = forward_real(c, ops, n, runs, rh ? nullptr : phi))) return rc;
-    if (rh) {
-      if ((rc = apply_h_real(c, res))) return rc;
+    if (rh && grad && n > 0) {  // one reduction for the energy, the norm and all gradients
+      int Ge = 0;
+      if ((rc = apply_h_real(c, res, n, true, &Ge))) return rc;
+      if ((rc = reverse_real(c, ops, n, runs, res, Ge))) return rc;
     } else {
-      if ((rc = apply_h_dev(c, phi, lam, res))) return rc;
-      if (grad && n > 0) {
-        ProfScope ps(FOCK_K_CONVERT, c.s, 12.0 * c.g.n_amp);
-        if ((rc = launch_real_convert(c.g.n_amp, false, lam, c.lam_r, c.s))) return rc;
+      if (rh) {
+        if ((rc = apply_h_real(c, res))) return rc;
+      } else {
+        if ((rc = apply_h_dev(c, phi, lam, res))) return rc;
+        if (grad && n > 0) {
+          ProfScope ps(FOCK_K_CONVERT, c.s, 12.0 * c.g.n_amp);
+          if ((rc = launch_real_convert(c.g.n_amp, false, lam, c.lam_r, c.s))) return rc;
+        }
       }
+      if (grad && n > 0 && (rc = reverse_real(c, ops, n, runs, res + 2))) return rc;
     }
-    if (grad && n > 0 && (rc = reverse_real(c, ops, n, runs, res + 2))) return rc;
   } else if (grad && use_store(c, ops, n, groups)) {
     // forward states kept: H psi_n reads the last one; phi is not touched
     if ((rc = forward_stored(c, ops, n, psi0))) return rc;

@@ -252,6 +252,10 @@ int launch_reduce(const double *partial, int nblocks, int ncols, double *out, hi
 // out[k] = sum_{b < recs[k].nblk} partial[k * row_stride + b] for k < n, in a fixed order.
 int launch_reduce_rows(const double *partial, int row_stride, const GateRec *recs, int n, double *out,
                        hipStream_t s);
+// The gate rows (into out[2 + k]) and the energy / norm partials epart (two
+// columns of ne rows, into out[0], out[1]) of a gradient evaluation, one launch.
+int launch_reduce_rows_energy(const double *partial, int row_stride, const GateRec *recs, int n,
+                              const double *epart, int ne, double *out, hipStream_t s);
 
 // ---------------------------------------------------------------- profiling
 // Tile schedule of the stencil kernels (H psi, pool scoring): which tile each

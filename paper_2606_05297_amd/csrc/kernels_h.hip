@@ -81,6 +81,34 @@ __global__ __launch_bounds__(kBlock) void k_reduce_rows(const double *__restrict
   if (threadIdx.x == 0) out[k] = s;
 }
 
+// Rows 0..n-1 as k_reduce_rows into out[2 + k], and (workgroups n, n + 1) the
+// two columns of the energy and norm partials epart[2 b + c], b < ne, into
+// out[c]: the reduction of a whole gradient evaluation in one launch.
+__global__ __launch_bounds__(kBlock) void k_reduce_rows_e(const double *__restrict__ partial, int row_stride,
+                                                          const GateRec *__restrict__ recs, int n,
+                                                          const double *__restrict__ epart, int ne,
+                                                          double *__restrict__ out) {
+  __shared__ double red[4];
+  const int k = blockIdx.x;
+  double s = 0.0;
+  if (k < n) {
+    const int nb = recs[k].nblk;
+    for (int b = threadIdx.x; b < nb; b += kBlock) s += partial[(size_t)k * row_stride + b];
+  } else {
+    for (int b = threadIdx.x; b < ne; b += kBlock) s += epart[(size_t)b * 2 + (k - n)];
+  }
+  s = block_sum_d(s, red);
+  if (threadIdx.x == 0) out[k < n ? 2 + k : k - n] = s;
+}
+
+int launch_reduce_rows_energy(const double *partial, int row_stride, const GateRec *recs, int n,
+                              const double *epart, int ne, double *out, hipStream_t s) {
+  if (n < 0 || ne <= 0) return set_error(FOCK_ERR_ARG, "reduction of %d rows and %d energy partials", n, ne);
+  hipLaunchKernelGGL(k_reduce_rows_e, dim3(n + 2), dim3(kBlock), 0, s, partial, row_stride, recs, n, epart, ne, out);
+  FOCK_HIP(hipGetLastError());
+  return FOCK_OK;
+}
+
 int launch_reduce_rows(const double *partial, int row_stride, const GateRec *recs, int n, double *out,
                        hipStream_t s) {
   if (n <= 0) return FOCK_OK;
