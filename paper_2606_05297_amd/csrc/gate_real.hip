@@ -21,47 +21,112 @@ using namespace rgates;
 
 namespace {
 
-// ---------------------------------------------------------------- pairs (i, j), i >= 1; the top pair (HALF)
+// ---------------------------------------------------------------- pairs (i, j), i >= 1
 // One lane per fiber, 64 consecutive fibers per workgroup, wave = block group.
-template <int KIND, bool DAG, bool HALF>
+template <int KIND, bool DAG>
 __global__ __launch_bounds__(kBlock) void k_rgate2(const float *src, float *psi, const float2 *__restrict__ U,
-                                                   GateLaunch g, int sector) {
+                                                   GateLaunch g) {
   const int vb = xcd_remap(blockIdx.x, gridDim.x);
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const uint32_t f = (uint32_t)vb * 64 + lane;
   if (f >= g.nfib) return;
-  const uint32_t fb = HALF ? f : fiber_base(f, g, kRD);
-  const int ps = HALF ? (octal_digit_parity(f) + sector) & 1 : 0;
+  const uint32_t fb = fiber_base(f, g, kRD);
   const float *sb = src + fb;
   float *base = psi + fb;
   switch (wave) {
-    case 0: rgate_group<KIND, DAG, 0, HALF>(sb, base, g.si, g.sj, U, ps); break;
-    case 1: rgate_group<KIND, DAG, 1, HALF>(sb, base, g.si, g.sj, U, ps); break;
-    case 2: rgate_group<KIND, DAG, 2, HALF>(sb, base, g.si, g.sj, U, ps); break;
-    default: rgate_group<KIND, DAG, 3, HALF>(sb, base, g.si, g.sj, U, ps); break;
+    case 0: rgate_group<KIND, DAG, 0, false>(sb, base, g.si, g.sj, U, 0); break;
+    case 1: rgate_group<KIND, DAG, 1, false>(sb, base, g.si, g.sj, U, 0); break;
+    case 2: rgate_group<KIND, DAG, 2, false>(sb, base, g.si, g.sj, U, 0); break;
+    default: rgate_group<KIND, DAG, 3, false>(sb, base, g.si, g.sj, U, 0); break;
   }
 }
 
-template <int KIND, bool WPHI, bool HALF>
+template <int KIND, bool WPHI>
 __global__ __launch_bounds__(kBlock) void k_rgate2_adj(float *__restrict__ phi, float *__restrict__ lam,
                                                        const float2 *__restrict__ U, const float2 *__restrict__ A,
-                                                       double *__restrict__ partial, GateLaunch g, int sector) {
+                                                       double *__restrict__ partial, GateLaunch g) {
   __shared__ double red[4];
   const int vb = xcd_remap(blockIdx.x, gridDim.x);
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const uint32_t f = (uint32_t)vb * 64 + lane;
   float gacc = 0.f;
   if (f < g.nfib) {
-    const uint32_t fb = HALF ? f : fiber_base(f, g, kRD);
-    const int ps = HALF ? (octal_digit_parity(f) + sector) & 1 : 0;
+    const uint32_t fb = fiber_base(f, g, kRD);
     float *pb = phi + fb, *lb = lam + fb;
     switch (wave) {
-      case 0: gacc = radj_group<KIND, 0, WPHI, HALF>(pb, lb, g.si, g.sj, U, A, ps); break;
-      case 1: gacc = radj_group<KIND, 1, WPHI, HALF>(pb, lb, g.si, g.sj, U, A, ps); break;
-      case 2: gacc = radj_group<KIND, 2, WPHI, HALF>(pb, lb, g.si, g.sj, U, A, ps); break;
-      default: gacc = radj_group<KIND, 3, WPHI, HALF>(pb, lb, g.si, g.sj, U, A, ps); break;
+      case 0: gacc = radj_group<KIND, 0, WPHI, false>(pb, lb, g.si, g.sj, U, A, 0); break;
+      case 1: gacc = radj_group<KIND, 1, WPHI, false>(pb, lb, g.si, g.sj, U, A, 0); break;
+      case 2: gacc = radj_group<KIND, 2, WPHI, false>(pb, lb, g.si, g.sj, U, A, 0); break;
+      default: gacc = radj_group<KIND, 3, WPHI, false>(pb, lb, g.si, g.sj, U, A, 0); break;
     }
   }
+  const double sg = block_sum_d((double)gacc, red);
+  if (threadIdx.x == 0) partial[vb] = sg;
+}
+
+// ---------------------------------------------------------------- the top pair of the parity-halved layout
+// A workgroup takes 128 consecutive lower indices f in two passes, one per
+// value P of the lower modes' parity plus the sector: in pass P lane l takes
+// the one of f0 + 2l, f0 + 2l + 1 (they differ in n_0 by one, so in parity)
+// whose parity is P.  The parity is then uniform and known at compile time in
+// each pass, so only the stored blocks are loaded and computed; a pass's
+// member loads cover every other float of a 512-byte run, the other pass the
+// rest.
+constexpr int kRHalfPer = 128;
+
+__device__ __forceinline__ uint32_t rhalf_f(uint32_t f0, int lane, int P, int sector) {
+  const uint32_t fe = f0 + 2u * (uint32_t)lane;
+  return fe + (uint32_t)(((octal_digit_parity(fe) + sector) & 1) != P);
+}
+
+template <int KIND, bool DAG, int P>
+__device__ __forceinline__ void rhalf_pass(const float *src, float *psi, const float2 *__restrict__ U,
+                                           const GateLaunch &g, int sector, uint32_t f0, int wave, int lane) {
+  const uint32_t f = rhalf_f(f0, lane, P, sector);
+  if (f >= g.nfib) return;
+  switch (wave) {
+    case 0: rgate_group<KIND, DAG, 0, true, const float2 *__restrict__, P>(src + f, psi + f, g.si, g.sj, U, P); break;
+    case 1: rgate_group<KIND, DAG, 1, true, const float2 *__restrict__, P>(src + f, psi + f, g.si, g.sj, U, P); break;
+    case 2: rgate_group<KIND, DAG, 2, true, const float2 *__restrict__, P>(src + f, psi + f, g.si, g.sj, U, P); break;
+    default: rgate_group<KIND, DAG, 3, true, const float2 *__restrict__, P>(src + f, psi + f, g.si, g.sj, U, P); break;
+  }
+}
+
+template <int KIND, bool DAG>
+__global__ __launch_bounds__(kBlock) void k_rgate2_half(const float *src, float *psi, const float2 *__restrict__ U,
+                                                        GateLaunch g, int sector) {
+  const uint32_t f0 = (uint32_t)xcd_remap(blockIdx.x, gridDim.x) * kRHalfPer;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  rhalf_pass<KIND, DAG, 0>(src, psi, U, g, sector, f0, wave, lane);
+  rhalf_pass<KIND, DAG, 1>(src, psi, U, g, sector, f0, wave, lane);
+}
+
+template <int KIND, bool WPHI, int P>
+__device__ __forceinline__ float rhalf_adj_pass(float *phi, float *lam, const float2 *__restrict__ U,
+                                                const float2 *__restrict__ A, const GateLaunch &g, int sector,
+                                                uint32_t f0, int wave, int lane) {
+  const uint32_t f = rhalf_f(f0, lane, P, sector);
+  if (f >= g.nfib) return 0.f;
+  using CP = const float2 *__restrict__;
+  switch (wave) {
+    case 0: return radj_group<KIND, 0, WPHI, true, CP, P>(phi + f, lam + f, g.si, g.sj, U, A, P);
+    case 1: return radj_group<KIND, 1, WPHI, true, CP, P>(phi + f, lam + f, g.si, g.sj, U, A, P);
+    case 2: return radj_group<KIND, 2, WPHI, true, CP, P>(phi + f, lam + f, g.si, g.sj, U, A, P);
+    default: return radj_group<KIND, 3, WPHI, true, CP, P>(phi + f, lam + f, g.si, g.sj, U, A, P);
+  }
+}
+
+template <int KIND, bool WPHI>
+__global__ __launch_bounds__(kBlock) void k_rgate2_adj_half(float *__restrict__ phi, float *__restrict__ lam,
+                                                            const float2 *__restrict__ U,
+                                                            const float2 *__restrict__ A, double *__restrict__ partial,
+                                                            GateLaunch g, int sector) {
+  __shared__ double red[4];
+  const int vb = xcd_remap(blockIdx.x, gridDim.x);
+  const uint32_t f0 = (uint32_t)vb * kRHalfPer;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  float gacc = rhalf_adj_pass<KIND, WPHI, 0>(phi, lam, U, A, g, sector, f0, wave, lane);
+  gacc += rhalf_adj_pass<KIND, WPHI, 1>(phi, lam, U, A, g, sector, f0, wave, lane);
   const double sg = block_sum_d((double)gacc, red);
   if (threadIdx.x == 0) partial[vb] = sg;
 }
@@ -277,7 +342,7 @@ bool real_gate_supported(const Geometry &g, int i, int j) { return real_select(g
 int real_gate_blocks(const Geometry &g, int i, int j) {
   const RealSel r = real_select(g, i, j);
   const GateLaunch gl = rlaunch(g, i, j, r.half_top);
-  const uint32_t per = r.m0p ? (uint32_t)(kRFL * kRTiles) : 64u;
+  const uint32_t per = r.m0p ? (uint32_t)(kRFL * kRTiles) : (r.half_top ? (uint32_t)kRHalfPer : 64u);
   return (int)((gl.nfib + per - 1) / per);
 }
 
@@ -285,8 +350,8 @@ template <int K, bool DG>
 static void rg_launch(const RealSel &r, int G, hipStream_t s, const float *src, float *psi, const float2 *U,
                       const GateLaunch &gl, int sector) {
   if (r.m0p) hipLaunchKernelGGL((k_rgate2_m0p<K, DG>), dim3(G), dim3(kBlock), 0, s, src, psi, U, gl);
-  else if (r.half_top) hipLaunchKernelGGL((k_rgate2<K, DG, true>), dim3(G), dim3(kBlock), 0, s, src, psi, U, gl, sector);
-  else hipLaunchKernelGGL((k_rgate2<K, DG, false>), dim3(G), dim3(kBlock), 0, s, src, psi, U, gl, 0);
+  else if (r.half_top) hipLaunchKernelGGL((k_rgate2_half<K, DG>), dim3(G), dim3(kBlock), 0, s, src, psi, U, gl, sector);
+  else hipLaunchKernelGGL((k_rgate2<K, DG>), dim3(G), dim3(kBlock), 0, s, src, psi, U, gl);
 }
 
 template <int K, bool W>
@@ -295,9 +360,9 @@ static void ra_launch(const RealSel &r, int G, hipStream_t s, float *phi, float 
   if (r.m0p)
     hipLaunchKernelGGL((k_rgate2_adj_m0p<K, W>), dim3(G), dim3(kBlock), 0, s, phi, lam, U, A, partial, gl);
   else if (r.half_top)
-    hipLaunchKernelGGL((k_rgate2_adj<K, W, true>), dim3(G), dim3(kBlock), 0, s, phi, lam, U, A, partial, gl, sector);
+    hipLaunchKernelGGL((k_rgate2_adj_half<K, W>), dim3(G), dim3(kBlock), 0, s, phi, lam, U, A, partial, gl, sector);
   else
-    hipLaunchKernelGGL((k_rgate2_adj<K, W, false>), dim3(G), dim3(kBlock), 0, s, phi, lam, U, A, partial, gl, 0);
+    hipLaunchKernelGGL((k_rgate2_adj<K, W>), dim3(G), dim3(kBlock), 0, s, phi, lam, U, A, partial, gl);
 }
 
 int launch_rgate(const Geometry &g, int i, int j, int kind, bool dag, const float2 *U, const float *src, float *psi,

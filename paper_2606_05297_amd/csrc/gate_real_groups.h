@@ -29,8 +29,9 @@ __device__ __forceinline__ uint32_t rmember(int s, int a, uint32_t si, uint32_t 
 // psi <- U src (U^T src when DAG) on group G of one fiber; HALF: the top pair
 // of the parity-halved layout, ps = lower modes' parity plus the sector.  UP
 // reads the packed table: a global pointer, or a table staged in LDS.
-template <int KIND, bool DAG, int G, bool HALF, class UP = const float2 *__restrict__>
+template <int KIND, bool DAG, int G, bool HALF, class UP = const float2 *__restrict__, int PS = -1>
 __device__ __forceinline__ void rgate_group(const float *src, float *base, uint32_t si, uint32_t sj, UP U, int ps) {
+  if (PS >= 0) ps = PS;  // a compile-time parity drops the absent blocks' code
   constexpr int D = kRD;
   constexpr Groups<D, kRNG> P{};
   float v[D * D];
@@ -69,8 +70,9 @@ __device__ __forceinline__ void rgate_group(const float *src, float *base, uint3
 
 // Reverse step on group G: sum lam . (A phi) over the group's members, then
 // phi <- U^T phi (when WPHI) and lam <- U^T lam.
-template <int KIND, int G, bool WPHI, bool HALF, class UP = const float2 *__restrict__>
+template <int KIND, int G, bool WPHI, bool HALF, class UP = const float2 *__restrict__, int PS = -1>
 __device__ __forceinline__ float radj_group(float *pb, float *lb, uint32_t si, uint32_t sj, UP U, UP A, int ps) {
+  if (PS >= 0) ps = PS;
   constexpr int D = kRD;
   constexpr Groups<D, kRNG> P{};
   float pv[D * D], lv[D * D];

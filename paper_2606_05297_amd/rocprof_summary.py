@@ -51,9 +51,9 @@ FAMILIES = {
                       ("gate_kernels.h", "kernels_gate.hip", "gate_half.hip", "device_common.h")),
     "diag_gate": (((("k_diag", "k_diag_adj"),),), ("gate_kernels.h", "kernels_gate.hip", "device_common.h")),
     "apply_h_real": (((("k_h8_col_r",), ("k_h8_row_r",)),), ("stencil2.hip", "device_common.h")),
-    "gate2_real": (((("k_rgate2", "k_rgate2_m0p"),),),
+    "gate2_real": (((("k_rgate2", "k_rgate2_m0p", "k_rgate2_half"),),),
                    ("gate_real.hip", "gate_real_groups.h", "gate_kernels.h", "device_common.h")),
-    "gate2_adjoint_real": (((("k_rgate2_adj", "k_rgate2_adj_m0p"),),),
+    "gate2_adjoint_real": (((("k_rgate2_adj", "k_rgate2_adj_m0p", "k_rgate2_adj_half"),),),
                            ("gate_real.hip", "gate_real_groups.h", "gate_kernels.h", "device_common.h")),
     "gate2_real_fused": (((("k_rfuse",),),),
                          ("gate_real_fuse.hip", "gate_real_groups.h", "gate_kernels.h", "device_common.h")),
@@ -68,8 +68,8 @@ FAMILIES = {
 SPLIT = [
     ("fused reverse runs on real states", ("k_rfuse_adj",)),
     ("fused forward runs on real states", ("k_rfuse",)),
-    ("reverse step on real states (single gates)", ("k_rgate2_adj", "k_rgate2_adj_m0p")),
-    ("forward gates on real states (single gates)", ("k_rgate2", "k_rgate2_m0p")),
+    ("reverse step on real states (single gates)", ("k_rgate2_adj", "k_rgate2_adj_m0p", "k_rgate2_adj_half")),
+    ("forward gates on real states (single gates)", ("k_rgate2", "k_rgate2_m0p", "k_rgate2_half")),
     ("real <-> complex conversion", ("k_real_to_complex", "k_complex_to_real")),
     ("reverse step, top pair (6,7) of the parity-halved layout", ("k_gate2_adj_half",)),
     ("reverse step, mode-0 pair (0,1)", ("k_gate2_adj_m0p", "k_gate2_adj_m0")),

@@ -149,10 +149,10 @@ def stored_index(L, d, sigma):
     return low + (2 * m + (s + sigma) % 2) * nlow
 
 
-def real_state(seed):
-    """A real, normalised, even-parity state of L=8, d=8 (the real part of a
-    seeded sector state)."""
-    psi = W.random_state(8, 8, seed=seed, sector=("parity", 0)).real.astype(np.float64)
+def real_state(seed, sigma=0):
+    """A real, normalised state of L=8, d=8 and parity sigma (the real part of
+    a seeded sector state)."""
+    psi = W.random_state(8, 8, seed=seed, sector=("parity", sigma)).real.astype(np.float64)
     return psi / np.linalg.norm(psi)
 
 
@@ -191,19 +191,21 @@ def test_real_apply_H_l8_d8(layout):
     assert abs(n2 - np.vdot(p128, p128).real) <= 1e-6
 
 
-@pytest.mark.parametrize("layout", REAL_LAYOUTS, ids=["full", "halved"])
+@pytest.mark.parametrize("layout", REAL_LAYOUTS + [lib.LAYOUT_ODD | lib.LAYOUT_REAL], ids=["full", "halved", "odd"])
 def test_real_energy_and_adjoint_l8_d8(layout):
     """Energy, final state and every dE/dtheta of an HR / PR circuit on float32
     states (20 gates over all seven bonds, the mode-0 pair and the top pair
-    included) against the oracle's FP64 reverse sweep on the full tensor."""
+    included) against the oracle's FP64 reverse sweep on the full tensor; the
+    parity-halved layout in both sectors."""
     ho, hl = ham_real(layout)
     pool = W.pool(8, "nn", False, ("HR", "PR"))
     ops, th = W.random_circuit(pool, 16, seed=91)
     ops = ops + [("HR", 0, 1), ("PR", 0, 1), ("HR", 6, 7), ("PR", 6, 7)]
     th = np.concatenate([th, [0.21, -0.17, 0.33, -0.29]])
     say("real adjoint, layout", layout, len(ops))
-    psi0 = real_state(93)
-    idx = stored_index(8, 8, 0) if layout & 3 else np.arange(8**8)
+    sigma = 1 if (layout & 3) == lib.LAYOUT_ODD else 0
+    psi0 = real_state(93, sigma)
+    idx = stored_index(8, 8, sigma) if layout & 3 else np.arange(8**8)
     x0 = torch.from_numpy(psi0[idx].astype(np.float32)).to("cuda")
     a, b = torch.empty_like(x0), torch.empty_like(x0)
     ws = lib.workspace(hl, 0, len(ops))
