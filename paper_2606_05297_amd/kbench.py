@@ -28,7 +28,7 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--workload", default="kk_l8_d8")
     ap.add_argument("--iters", type=int, default=20)
-    ap.add_argument("--kernels", default="copy,apply_h,pool,score,gate,adjoint,dense,mlp")
+    ap.add_argument("--kernels", default="copy,apply_h,pool,score,gate,adjoint,m4,dense,mlp")
     ap.add_argument("--mlp-batch", type=int, default=16384)
     ap.add_argument("--lib", default=None, help="path of an alternative libfock.so build")
     ap.add_argument("--schedule", type=int, default=None, help="stencil tile schedule (fock_set_stencil_schedule)")
@@ -132,6 +132,53 @@ def main():
         for k in range(max(1, args.iters // 4)):
             lib.energy_grad_adjoint(h, ops, th, states[k % 3], outs[(k + 1) % 3], outs[(k + 2) % 3], ws)
         print(f"[kbench] adjoint done", file=sys.stderr, flush=True)
+    if "m4" in want:
+        # one energy + adjoint-gradient evaluation of a 30-gate circuit (gates drawn
+        # from the pool with default_rng(3), angles U[-0.5, 0.5]) on the complex64
+        # tensor, against the plain method's central-difference gradient (2n energy
+        # evaluations); then a 30-gate HR / PR circuit on real parity-halved states,
+        # gate by gate and with fused runs.  Wall time per call (results on the host).
+        nm4, reps = 30, max(3, args.iters // 4)
+        rng = np.random.default_rng(3)
+        pool = cfg["pool"]
+        ops = [pool[k] for k in rng.integers(0, len(pool), nm4)]
+        th = rng.uniform(-0.5, 0.5, nm4)
+        ws30 = lib.workspace(h, 0, nm4)
+
+        def per_call(fn):
+            fn()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                fn()
+            torch.cuda.synchronize()
+            return (time.perf_counter() - t0) / reps
+
+        t_adj = per_call(lambda: lib.energy_grad_adjoint(h, ops, th, states[0], outs[1], outs[2], ws30))
+        t_en = per_call(lambda: lib.energy_grad_adjoint(h, ops, th, states[0], outs[1], outs[2], ws30, grad=False))
+        m4 = {"n": nm4, "complex_full": {
+            "adjoint_ms": 1e3 * t_adj, "algorithmic_GB": (48 * nm4 + 16) * n / 1e9,
+            "GBs": (48 * nm4 + 16) * n / t_adj / 1e9, "energy_ms": 1e3 * t_en,
+            "fd_gradient_ms": 1e3 * 2 * nm4 * t_en, "adjoint_speedup_vs_fd": 2 * nm4 * t_en / t_adj}}
+        if L == 8 and d == 8 and not cfg["periodic"]:
+            rp = [o for o in pool if o[0] in ("HR", "PR")]
+            ops_r = [rp[k] for k in rng.integers(0, len(rp), nm4)]
+            half = torch.empty(n // 2, dtype=torch.complex64, device="cuda")
+            sr = states[0].real.to(torch.complex64)
+            sr /= torch.linalg.vector_norm(sr)
+            lib.sector_pack(L, d, lib.LAYOUT_EVEN, sr, half)
+            x0 = half.real.contiguous()
+            a, b = torch.empty_like(x0), torch.empty_like(x0)
+            hr = lib.ham_from(cfg, layout=lib.LAYOUT_EVEN | lib.LAYOUT_REAL)
+            wsr = lib.workspace(hr, 0, nm4)
+            for mode, name in ((lib.RFUSE_OFF, "real_halved_gate_by_gate"), (lib.RFUSE_ON, "real_halved_fused")):
+                lib.set_real_fusion(mode)
+                t = per_call(lambda: lib.energy_grad_adjoint(hr, ops_r, th, x0, a, b, wsr))
+                m4[name] = {"adjoint_ms": 1e3 * t, "runs": len(lib.real_fusion_plan(hr, ops_r)),
+                            "algorithmic_GB": (24 * nm4 + 8) * (n // 2) / 1e9}
+            lib.set_real_fusion(lib.RFUSE_ON)
+        res["m4"] = m4
+        print(f"[kbench] m4 done", file=sys.stderr, flush=True)
     if "mlp" in want:
         B = args.mlp_batch
         rng = np.random.default_rng(0)

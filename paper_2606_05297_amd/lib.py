@@ -186,8 +186,9 @@ def n_amplitudes(h: Ham) -> int:
     return n // 2 if (int(h.layout) & 3) != LAYOUT_FULL else n
 
 
-def ham_from(cfg: dict) -> Ham:
-    return ham(cfg["L"], cfg["d"], cfg["periodic"], cfg["J"], cfg["U"], cfg["mu"], cfg["Delta"], cfg["K"])
+def ham_from(cfg: dict, layout: int = 0) -> Ham:
+    return ham(cfg["L"], cfg["d"], cfg["periodic"], cfg["J"], cfg["U"], cfg["mu"], cfg["Delta"], cfg["K"],
+               layout=layout)
 
 
 def op(t, i, j=-1) -> Op:
