@@ -11,9 +11,11 @@ the total parity, so the driver keeps its states in the parity-halved layout
 (the top mode's level follows from the other modes' parity: 8,388,608 stored
 amplitudes).  Every gate the run selects is HR or PR and the vacuum is real,
 so its evaluations run their gates and reverse steps on real float32
-amplitudes (H psi and scoring on a complex64 copy).  --full-layout and
---complex-states switch these off; "variants" also reports the default run
-with each of them off and with both off.  W warm-up steps run on a separate ADAPT instance;
+amplitudes (scoring on a complex64 copy), and runs of consecutive gates inside
+three consecutive modes take one LDS-staged pass.  --full-layout,
+--complex-states and --no-real-fusion switch these off; "variants" also
+reports the default run gate by gate, with the full layout, with complex
+states and with both.  W warm-up steps run on a separate ADAPT instance;
 the K timed steps are steps 1..K of a fresh run from the vacuum.  Per-kernel
 durations come from HIP events recorded on the launch stream inside the timed
 region, around one launch in --prof-sample (default 4) of each kernel family:
@@ -238,6 +240,8 @@ def main():
                    lib.LAYOUT_ODD: "parity-halved, odd sector (8,388,608 stored amplitudes)"}[layout]
     if ad.real():
         layout_desc += "; real float32 amplitudes for evaluations whose gates are all HR or PR"
+        if lib.get_real_fusion() == lib.RFUSE_ON:
+            layout_desc += ", runs of gates inside three consecutive modes fused into one pass"
     lib.prof_set_sample(args.prof_sample)
     lib.prof_reset()
     lib.prof_enable(True)
@@ -298,7 +302,8 @@ def main():
                                 f"{', inverse Hessian recycled across steps' if rh else ''}; states kept "
                                 f"{layout_desc}"),
                    "L": 8, "d": 8, "pool": len(cfg["pool"]), "grad_mode": args.grad_mode, "hessian_recycling": rh,
-                   "gate_fusion": lib.get_gate_fusion(), "state_layout": layout_desc},
+                   "gate_fusion": lib.get_gate_fusion(), "real_fusion": lib.get_real_fusion() == lib.RFUSE_ON,
+                   "state_layout": layout_desc},
         "roofline": roof,
         # H psi of the timed evaluations: on real states when the run uses them
         "apply_h": kernel_entry(13) if prof[13]["launches"] else kernel_entry(0),
