@@ -127,6 +127,24 @@ struct Pinned {
 };
 static thread_local Pinned tl_in, tl_out;
 
+// Results written by a kernel straight into host memory: fine-grained
+// (coherent) pinned memory, so the stream synchronisation that follows the
+// kernel is all the host waits for.  One per thread, grown on demand.
+struct HostResults {
+  double *p = nullptr;
+  size_t cap = 0;
+  int reserve(size_t count) {
+    if (count <= cap) return FOCK_OK;
+    if (p) FOCK_HIP(hipHostFree(p));
+    p = nullptr;
+    const size_t c = std::max<size_t>(count, 4096);
+    FOCK_HIP(hipHostMalloc((void **)&p, sizeof(double) * c, hipHostMallocCoherent | hipHostMallocMapped));
+    cap = c;
+    return FOCK_OK;
+  }
+};
+static thread_local HostResults tl_res;
+
 // ---------------------------------------------------------------- workspace layout
 static size_t al(size_t x) { return (x + 255) & ~(size_t)255; }
 
@@ -754,10 +772,21 @@ int run_circuit(Ctx &c, const fock_op_t *ops, const double *theta, int n, const 
     // complex64 copy whose real part is kept
     const bool rh = apply_h2_real_supported(c.h) && c.h.slab;
     if ((rc = forward_real(c, ops, n, runs, rh ? nullptr : phi))) return rc;
-    if (rh && grad && n > 0) {  // one reduction for the energy, the norm and all gradients
-      int Ge = 0;
+    if (rh && grad && n > 0) {  // one reduction for the energy, the norm and all gradients,
+      int Ge = 0;                 // written straight into host memory
+      if ((rc = tl_res.reserve(2 + (size_t)n))) return rc;
       if ((rc = apply_h_real(c, res, n, true, &Ge))) return rc;
-      if ((rc = reverse_real(c, ops, n, runs, res, Ge))) return rc;
+      if ((rc = reverse_real(c, ops, n, runs, tl_res.p, Ge))) return rc;
+      FOCK_HIP(hipStreamSynchronize(c.s));
+      prof_harvest();
+      const double nrm = tl_res.p[1];
+      if (!std::isfinite(tl_res.p[0]) || !std::isfinite(nrm) || nrm <= 0.0)
+        return set_error(FOCK_ERR_NONFINITE, "non-finite energy or zero norm (E=%g, norm2=%g)", tl_res.p[0], nrm);
+      *E = tl_res.p[0] / nrm;
+      if (norm2) *norm2 = nrm;
+      if (dE)
+        for (int k = 0; k < n; ++k) dE[k] = 2.0 * tl_res.p[2 + k] / nrm;
+      return FOCK_OK;
     } else {
       if (rh) {
         if ((rc = apply_h_real(c, res))) return rc;
