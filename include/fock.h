@@ -203,7 +203,8 @@ int fock_adjoint_sweep(const fock_ham_t *ham, const fock_op_t *ops, const double
  * otherwise create on their first use: the gate eigendata of cutoff d (device
  * memory and a synchronous upload, Sec. II.B), the tile-order tables of the
  * stencil schedules 1-3 for open and ring chains, and this thread's pinned
- * staging buffers at their base size (64 kB each).  Afterwards fock_apply_H,
+ * staging buffers at their base size (64 kB each) with its pinned results
+ * buffer for real-state gradient evaluations (32 kB).  Afterwards fock_apply_H,
  * fock_apply_gate2 and fock_energy_grad_adjoint on (L, d) from this thread
  * allocate nothing and add no synchronisation of their own beyond their
  * documented result fetch, for circuits of up to ~2,700 gates.  (Pool scoring

@@ -129,7 +129,9 @@ static thread_local Pinned tl_in, tl_out;
 
 // Results written by a kernel straight into host memory: fine-grained
 // (coherent) pinned memory, so the stream synchronisation that follows the
-// kernel is all the host waits for.  One per thread, grown on demand.
+// kernel is all the host waits for.  One per thread, sized for the longest
+// circuit (energy, norm and 4096 gradients).
+constexpr size_t kHostResults = 2 + 4096;
 struct HostResults {
   double *p = nullptr;
   size_t cap = 0;
@@ -137,7 +139,7 @@ struct HostResults {
     if (count <= cap) return FOCK_OK;
     if (p) FOCK_HIP(hipHostFree(p));
     p = nullptr;
-    const size_t c = std::max<size_t>(count, 4096);
+    const size_t c = std::max<size_t>(count, kHostResults);
     FOCK_HIP(hipHostMalloc((void **)&p, sizeof(double) * c, hipHostMallocCoherent | hipHostMallocMapped));
     cap = c;
     return FOCK_OK;
@@ -1107,8 +1109,9 @@ int fock_prepare(int L, int d) {
       if ((rc = stencil_order_table_for(L, d, nt, scheme, &order))) return rc;
     }
   }
-  // pinned staging of this thread at its minimum size
+  // pinned staging of this thread at its minimum size, and its results buffer
   if ((rc = tl_in.reserve(1))) return rc;
+  if ((rc = tl_res.reserve(kHostResults))) return rc;
   return tl_out.reserve(1);
 }
 
