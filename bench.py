@@ -21,7 +21,9 @@ durations come from HIP events recorded on the launch stream inside the timed
 region, around one launch in --prof-sample (default 4) of each kernel family:
 two event records per timed launch lengthen the gap to the next kernel, and
 timing every launch costs about 9% of the step rate.  The roofline entry is
-the kernel with the largest total time.  BFGS
+the kernel with the largest total time.  A fused run's algorithmic bytes are
+one pass over its states whatever its gate count; the fused kernels' entries
+add the mean gates per launch and the bandwidth counted per gate.  BFGS
 starts every step from the previous step's inverse Hessian, padded with the
 identity for the new angle (Appendix D); --no-hessian-recycling starts from
 the scaled identity.  After the timed region, "variants" reports the same
@@ -259,6 +261,8 @@ def main():
     t1 = time.perf_counter()
     lib.prof_enable(False)
     prof = {kid: lib.prof_query(kid) for kid in KERNEL_NAMES}
+    ops_final = ad.ansatz()[0]
+    real_run = ad.real()
     ad.close()
     dt = t1 - t0
     value = args.steps / dt
@@ -276,8 +280,36 @@ def main():
                 "avg_us": avg_ms * 1e3, "algorithmic_bytes_per_launch": per_launch_bytes,
                 "total_ms": p["ms"]}
 
+    # Fused runs carry several gates per launch; their algorithmic bytes are
+    # one pass.  Gates per fused launch, from the run planner applied to each
+    # step's ansatz, weighted by the step's evaluations (forward runs also
+    # prepare the step's scoring); "gate_equivalent_GBs" counts every gate's pass.
+    fused_gpl = {}
+    if real_run and lib.get_real_fusion() == lib.RFUSE_ON:
+        hf = lib.ham_from(cfg, layout=layout | lib.LAYOUT_REAL)
+        for kid, extra in ((14, 1), (15, 0)):
+            g_sum = l_sum = 0
+            for r in reps:
+                n_s = r["n_params"]
+                runs = lib.real_fusion_plan(hf, ops_final[:n_s])
+                ends = [k0 for k0, _ in runs[1:]] + [n_s]
+                for (k0, a), k1 in zip(runs, ends):
+                    if a >= 0:
+                        w = r["bfgs_evals"] + extra
+                        g_sum += w * (k1 - k0)
+                        l_sum += w
+            if l_sum:
+                fused_gpl[kid] = g_sum / l_sum
+
+    def with_gates(kid, e):
+        if e is not None and kid in fused_gpl:
+            e["gates_per_launch"] = fused_gpl[kid]
+            e["gate_equivalent_GBs"] = e["achieved"] * fused_gpl[kid]
+            e["gate_equivalent_frac"] = e["gate_equivalent_GBs"] / HBM_PEAK_GBS
+        return e
+
     dom = max((k for k in KERNEL_NAMES if prof[k]["launches"]), key=lambda k: prof[k]["ms"])
-    roof = kernel_entry(dom)
+    roof = with_gates(dom, kernel_entry(dom))
     ed = None
     edp = os.path.join(ROOT, "tests", "golden", "ed_reference.json")
     if os.path.exists(edp):
@@ -307,7 +339,7 @@ def main():
         "roofline": roof,
         # H psi of the timed evaluations: on real states when the run uses them
         "apply_h": kernel_entry(13) if prof[13]["launches"] else kernel_entry(0),
-        "kernels": {KERNEL_NAMES[k]: kernel_entry(k) for k in KERNEL_NAMES if prof[k]["launches"]},
+        "kernels": {KERNEL_NAMES[k]: with_gates(k, kernel_entry(k)) for k in KERNEL_NAMES if prof[k]["launches"]},
         "adapt": {"E_final": reps[-1]["E"], "E0_ed": ed, "dE_vs_ed": (reps[-1]["E"] - ed) if ed is not None else None,
                   "tolerance_reached": (abs(reps[-1]["E"] - ed) <= 1e-5 * abs(ed)) if ed is not None else None,
                   "note": ("the timed steps are the first steps of the run, far from the ground state; the ED gap "
